@@ -1,0 +1,243 @@
+"""ctypes binding of the CPU FP64 reference (test infrastructure only).
+
+Only the test suite, the smoke check and the CPU-baseline leg of the benchmark import this module.
+It marshals a workload description into the plain C structures of oracle.h and calls liboracle.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+MAXD = 12
+
+
+def build(force: bool = True) -> str:
+    """Compiles oracle.c with gcc (plain -O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-fopenmp", "-fPIC", "-shared",
+               os.path.join(_HERE, "oracle.c"), "-o", LIB_PATH + ".tmp", "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class Species(C.Structure):
+    _fields_ = [("stat", C.c_int), ("n_grid", C.c_int), ("q_min", C.c_double), ("q_max", C.c_double),
+                ("mass_kind", C.c_int), ("m0", C.c_double), ("mA", C.c_double), ("mw", C.c_double),
+                ("f", C.POINTER(C.c_double))]
+
+
+class Process(C.Structure):
+    _fields_ = [("n_in", C.c_int), ("n_out", C.c_int), ("sp", C.c_int * 6), ("coupling", C.c_double),
+                ("sigma_E", C.c_double), ("alpha", C.c_double), ("e_cut", C.c_double), ("n_bins", C.c_int),
+                ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int)]
+
+
+class World(C.Structure):
+    _fields_ = [("n_species", C.c_int), ("species", C.POINTER(Species)), ("n_proc", C.c_int),
+                ("procs", C.POINTER(Process)), ("t", C.c_double), ("expansion", C.c_int), ("a0", C.c_double),
+                ("t0", C.c_double)]
+
+
+class Item(C.Structure):
+    _fields_ = [("proc", C.c_int), ("species", C.c_int), ("side", C.c_int), ("term", C.c_int),
+                ("eval_idx", C.c_int), ("mult", C.c_int), ("uid", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.orc_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.orc_sample_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_int, C.c_int64, C.c_int, dp]
+        L.orc_grid_q.argtypes = [C.POINTER(Species), C.c_int]
+        L.orc_grid_q.restype = C.c_double
+        L.orc_mass.argtypes = [C.POINTER(Species), C.c_double]
+        L.orc_mass.restype = C.c_double
+        L.orc_scale_factor.argtypes = [C.POINTER(World), C.c_double]
+        L.orc_scale_factor.restype = C.c_double
+        L.orc_fit.argtypes = [C.POINTER(Species), C.c_double, C.c_double, dp]
+        L.orc_f_at.argtypes = [C.POINTER(Species), dp, C.c_double, C.c_double]
+        L.orc_f_at.restype = C.c_double
+        L.orc_f_batch.argtypes = [C.POINTER(Species), dp, C.c_int64, dp, dp, dp]
+        L.orc_f_batch.restype = None
+        L.orc_stat_factor.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
+        L.orc_stat_factor.restype = C.c_double
+        L.orc_integrand_batch.argtypes = [C.POINTER(World), C.POINTER(Item), C.c_int64, dp, dp]
+        L.orc_side_multiplicity.argtypes = [C.POINTER(Process), C.c_int, C.c_int]
+        L.orc_roles.argtypes = [C.POINTER(Process), C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                C.POINTER(C.c_int)]
+        L.orc_list_items.argtypes = [C.POINTER(World), C.c_int, C.c_int, C.c_int, C.POINTER(Item), C.c_int]
+        L.orc_map_uniform.argtypes = [C.POINTER(World), C.POINTER(Item), dp]
+        L.orc_integrand_at.argtypes = [C.POINTER(World), C.POINTER(Item), dp, dp]
+        L.orc_run_items.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), C.c_int64, C.c_int, C.c_int,
+                                    C.c_uint64, C.c_uint32, C.c_int, dp, dp, dp, dp, dp, C.c_int]
+        L.orc_combine.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), dp, dp, C.c_int, dp, dp]
+        L.orc_combine.restype = None
+        L.orc_collision_all.argtypes = [C.POINTER(World), C.c_int64, C.c_int, C.c_uint64, C.c_uint32, C.c_int, dp,
+                                        dp, dp, C.c_int]
+        L.orc_step.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
+                               C.c_uint64, C.c_uint32, C.c_int, dp, dp, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*ctr)
+    k = (C.c_uint32 * 2)(*key)
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return list(o)
+
+
+def stat_factor(n_in, n, obs_side, term_mode, term, f, eta):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    eta = np.ascontiguousarray(eta, dtype=np.float64)
+    return lib().orc_stat_factor(n_in, n, obs_side, term_mode, term, _dp(f), _dp(eta))
+
+
+def uniforms(seed, uid, epoch, it, n, D):
+    y = np.zeros(D)
+    lib().orc_sample_uniforms(seed, uid, epoch, it, n, D, _dp(y))
+    return y
+
+
+class OracleWorld:
+    """A workload (paper_2603_28848_amd.workloads.Workload) held as oracle structures."""
+
+    def __init__(self, w):
+        self.w = w
+        self.f = [np.ascontiguousarray(s.f, dtype=np.float64).copy() for s in w.species]
+        self.sp = (Species * len(w.species))()
+        for i, s in enumerate(w.species):
+            self.sp[i] = Species(s.stat, s.n_grid, s.q_min, s.q_max, s.mass_kind, s.m0, s.mA, s.mw, _dp(self.f[i]))
+        self.pr = (Process * max(1, len(w.processes)))()
+        for i, p in enumerate(w.processes):
+            sp = (C.c_int * 6)(*(list(p.ins) + list(p.outs) + [0] * (6 - len(p.ins) - len(p.outs))))
+            self.pr[i] = Process(len(p.ins), len(p.outs), sp, p.coupling, p.sigma_E, p.alpha, p.e_cut, p.n_bins,
+                                 p.term_mode, p.side_mask, p.eval_stride)
+        self.world = World(len(w.species), self.sp, len(w.processes), self.pr, w.t, w.expansion, w.a0, w.t0)
+        self._maps = None
+
+    # ---- basic pieces ---------------------------------------------------------------------------
+    @property
+    def t(self):
+        return self.world.t
+
+    def fit(self, species, t=None):
+        t = self.world.t if t is None else t
+        a = lib().orc_scale_factor(C.byref(self.world), t)
+        out = np.zeros(4)
+        rc = lib().orc_fit(C.byref(self.sp[species]), a, t, _dp(out))
+        return rc, out
+
+    def f_at(self, species, fit, q, E):
+        fit = np.ascontiguousarray(fit, dtype=np.float64)
+        return lib().orc_f_at(C.byref(self.sp[species]), _dp(fit), q, E)
+
+    def f_batch(self, species, fit, q, E):
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        fit = np.ascontiguousarray(fit, dtype=np.float64)
+        out = np.zeros_like(q)
+        lib().orc_f_batch(C.byref(self.sp[species]), _dp(fit), q.size, _dp(q), _dp(E), _dp(out))
+        return out
+
+    def integrand_batch(self, item, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        n = x.shape[0]
+        out = np.zeros(n)
+        rc = lib().orc_integrand_batch(C.byref(self.world), C.byref(item), n, _dp(x), _dp(out))
+        assert rc == 0, rc
+        return out
+
+    def grid_q(self, species):
+        return np.array([lib().orc_grid_q(C.byref(self.sp[species]), j) for j in range(self.sp[species].n_grid)])
+
+    def roles(self, proc, species, side):
+        io, ic = C.c_int(), C.c_int()
+        integ = (C.c_int * 6)()
+        rc = lib().orc_roles(C.byref(self.pr[proc]), species, side, C.byref(io), C.byref(ic), integ)
+        n = self.pr[proc].n_in + self.pr[proc].n_out
+        return rc, io.value, ic.value, list(integ)[: n - 2]
+
+    def multiplicity(self, proc, species, side):
+        return lib().orc_side_multiplicity(C.byref(self.pr[proc]), species, side)
+
+    def items(self, proc=-1, species=-1, stride=0):
+        n = lib().orc_list_items(C.byref(self.world), proc, species, stride, None, 0)
+        arr = (Item * max(1, n))()
+        lib().orc_list_items(C.byref(self.world), proc, species, stride, arr, n)
+        return arr, n
+
+    def integrand_at(self, item, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        v = np.zeros(1)
+        rc = lib().orc_integrand_at(C.byref(self.world), C.byref(item), _dp(x), _dp(v))
+        assert rc == 0, rc
+        return v[0]
+
+    def map_uniform(self, item, nb):
+        m = np.zeros(MAXD * (nb + 1))
+        lib().orc_map_uniform(C.byref(self.world), C.byref(item), _dp(m))
+        return m
+
+    # ---- Monte Carlo -----------------------------------------------------------------------------
+    def run_items(self, items, n_items, N, nitn, seed=0, epoch=0, maps=None, threads=0, first_iter=0, adapt=True):
+        nb = self.pr[items[0].proc].n_bins if n_items else 50
+        stride = MAXD * (nb + 1)
+        if maps is None:
+            maps = np.full((n_items, stride), np.nan)
+        I_it = np.zeros((n_items, nitn))
+        V_it = np.zeros((n_items, nitn))
+        Ib = np.zeros(n_items)
+        sg = np.zeros(n_items)
+        rc = lib().orc_run_items(C.byref(self.world), n_items, items, N, first_iter, nitn, seed, epoch, int(adapt),
+                                 _dp(maps), _dp(I_it), _dp(V_it), _dp(Ib), _dp(sg), threads)
+        return rc, dict(I_it=I_it, V_it=V_it, Ibar=Ib, sigma=sg, maps=maps)
+
+    def combine(self, items, n_items, Ibar, sigma, species):
+        n = self.sp[species].n_grid
+        Cv, S = np.zeros(n), np.zeros(n)
+        lib().orc_combine(C.byref(self.world), n_items, items, _dp(np.ascontiguousarray(Ibar)),
+                          _dp(np.ascontiguousarray(sigma)), species, _dp(Cv), _dp(S))
+        return Cv, S
+
+    def _all_maps(self, nb):
+        n = lib().orc_list_items(C.byref(self.world), -1, -1, 0, None, 0)
+        if self._maps is None or self._maps.shape[0] != n:
+            self._maps = np.full((max(1, n), MAXD * (nb + 1)), np.nan)
+        return self._maps
+
+    def collision_all(self, N, nitn, seed=0, epoch=0, threads=0, adapt=True):
+        nb = self.pr[0].n_bins
+        maps = self._all_maps(nb)
+        tot = sum(s.n_grid for s in self.w.species)
+        Cv, S = np.zeros(tot), np.zeros(tot)
+        rc = lib().orc_collision_all(C.byref(self.world), N, nitn, seed, epoch, int(adapt), _dp(maps), _dp(Cv), _dp(S),
+                                     threads)
+        return rc, Cv, S
+
+    def step(self, method, dt, eps, dt_max, N, nitn, seed=0, epoch=0, threads=0, adapt=True):
+        nb = self.pr[0].n_bins
+        maps = self._all_maps(nb)
+        dtu = np.zeros(1)
+        rc = lib().orc_step(C.byref(self.world), method, dt, eps, dt_max, N, nitn, seed, epoch, int(adapt), _dp(maps),
+                            _dp(dtu), threads)
+        return rc, dtu[0]

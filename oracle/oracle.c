@@ -1,0 +1,825 @@
+/*
+ * oracle.c -- plain, slow CPU FP64 reference of the Monte-Carlo collision-integral estimator.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or calls this file; only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark do.  It shares no code, header,
+ * table or constant generator with the HIP implementation.
+ *
+ * What it computes (paper: "Boltzmann Equation Solver for Thermalization", arXiv 2603.28848):
+ *   * the single-position collision integral C^(k)(p) = (1/2E) Int dPi |M|^2 Lambda     (Sec. II.B, Eqs. 3-5)
+ *   * the identical-particle decomposition C_a = n_alpha^a C_{n_alpha} + n_beta^a C_{n_beta}, and the
+ *     self-reverse rule C_a = n_alpha^a C_{n_alpha}                                     (Sec. II.C, Eqs. 7, 12)
+ *   * the Monte-Carlo parametrisation: observed momentum on z, integrated particles in spherical
+ *     coordinates, one momentum fixed by momentum conservation, a Gaussian energy delta, the
+ *     phase-space weight                                         (Sec. II.D, Eqs. 14-16; Appendix A)
+ *   * Vegas adaptive importance sampling (Lepage 1978, 2021), separate gain and loss integrators,
+ *     alpha = 0.5                                                         (Sec. II.D; Appendix C)
+ *   * interpolation of f and its extrapolation log(1/f + eta) = a + b E              (Sec. III.B, Eq. 17)
+ *   * log-space Euler / Heun stepping with the adaptive time step                   (Sec. III.C, Eqs. 18-20)
+ *   * comoving momenta and radiation-domination expansion                            (Sec. III.E)
+ *
+ * Every floating-point quantity is IEEE double; Monte-Carlo sums are accumulated in long double so that
+ * the oracle's sums are (to ~1e-19 relative per term) the exact sums of its per-sample doubles.
+ * Parallelism: OpenMP over work items only; each item's samples are processed serially in index order.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double TWO_PI = 6.283185307179586476925286766559;
+static const double PI_D = 3.141592653589793238462643383279;
+
+/* =====================================================================================================
+ * Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC11, 2011).  One round: two 32x32->64 products of counter words 0 and 2 with the
+ * multipliers 0xD2511F53 and 0xCD9E8D57; the high halves are xored with the other counter words and
+ * the key, the low halves move into the odd slots.  The key is bumped by the Weyl constants
+ * (0x9E3779B9, 0xBB67AE85) between rounds.  Ten rounds.
+ * ===================================================================================================== */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    uint32_t hi0 = (uint32_t)(prod0 >> 32), lo0 = (uint32_t)prod0;
+    uint32_t hi1 = (uint32_t)(prod1 >> 32), lo1 = (uint32_t)prod1;
+    uint32_t n0 = hi1 ^ c1 ^ k0;
+    uint32_t n1 = lo1;
+    uint32_t n2 = hi0 ^ c3 ^ k1;
+    uint32_t n3 = lo0;
+    c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+  }
+  out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* The D uniforms of sample n of iteration `it` of the item with identifier `uid`:
+ *   B = ceil(D/4) blocks per sample; block b uses counter (lo32(n*B+b), hi32(n*B+b), uid, epoch*64+it)
+ *   and key (lo32(seed), hi32(seed)); word w of the sample (w = 4b + slot) becomes y_w = (w + 0.5) 2^-32. */
+void orc_sample_uniforms(uint64_t seed, uint32_t uid, uint32_t epoch, int it, int64_t n, int D, double* y) {
+  const int B = (D + 3) / 4;
+  uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  for (int b = 0; b < B; ++b) {
+    uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
+    uint32_t ctr[4] = {(uint32_t)off, (uint32_t)(off >> 32), uid, epoch * 64u + (uint32_t)it};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    for (int s = 0; s < 4; ++s) {
+      int d = 4 * b + s;
+      if (d < D) y[d] = ((double)w[s] + 0.5) * 2.3283064365386962890625e-10; /* 2^-32 */
+    }
+  }
+}
+
+/* =====================================================================================================
+ * Species: momentum grid, mass, statistics, distribution table.
+ * ===================================================================================================== */
+
+/* Comoving grid node j of a logarithmic grid on [q_min, q_max] with n nodes. */
+double orc_grid_q(const orc_species* s, int j) {
+  double lq0 = log(s->q_min);
+  double h = (log(s->q_max) - lq0) / (double)(s->n_grid - 1);
+  return exp(lq0 + h * (double)j);
+}
+
+/* Mass at time t: constant, or m0 + A sin(w t). */
+double orc_mass(const orc_species* s, double t) {
+  if (s->mass_kind == ORC_MASS_SIN) return s->m0 + s->mA * sin(s->mw * t);
+  return s->m0;
+}
+
+/* Scale factor: 1 without expansion; radiation domination a(t) = a0 (t/t0)^(1/2)  (Sec. III.E). */
+double orc_scale_factor(const orc_world* w, double t) {
+  if (w->expansion == ORC_EXP_RADIATION) return w->a0 * sqrt(t / w->t0);
+  return 1.0;
+}
+
+/* Extrapolation fit (Eq. 17): least-squares line y = a + b E through the points
+ * (E_j, log(1/f_j + eta)), E_j = sqrt((q_j/a)^2 + m^2), over the ORC_NFIT lowest and the ORC_NFIT
+ * highest grid nodes separately.  fit[0..3] = (a_lo, b_lo, a_hi, b_hi).
+ * Returns ORC_ERANGE if a node value is not positive, a Fermi-Dirac value is >= 1, the fit is not
+ * finite, the high-end slope is not positive, or (Bose-Einstein) the fitted exponent is not positive
+ * at an end of the range where it is used. */
+int orc_fit(const orc_species* s, double a, double t, double fit[4]) {
+  const int n = s->n_grid;
+  const double m = orc_mass(s, t);
+  const double eta = (double)s->stat;
+  if (n < 2 * ORC_NFIT) return ORC_EINVAL;
+  for (int side = 0; side < 2; ++side) {
+    int j0 = side == 0 ? 0 : n - ORC_NFIT;
+    double sE = 0, sY = 0;
+    double E[ORC_NFIT], Y[ORC_NFIT];
+    for (int k = 0; k < ORC_NFIT; ++k) {
+      int j = j0 + k;
+      double f = s->f[j];
+      if (!(f > 0.0)) return ORC_ERANGE;
+      if (s->stat == ORC_FERMI && !(f < 1.0)) return ORC_ERANGE;
+      double p = orc_grid_q(s, j) / a;
+      E[k] = sqrt(p * p + m * m);
+      Y[k] = log(1.0 / f + eta);
+      sE += E[k];
+      sY += Y[k];
+    }
+    double mE = sE / ORC_NFIT, mY = sY / ORC_NFIT;
+    double sxy = 0, sxx = 0;
+    for (int k = 0; k < ORC_NFIT; ++k) {
+      sxy += (E[k] - mE) * (Y[k] - mY);
+      sxx += (E[k] - mE) * (E[k] - mE);
+    }
+    double b = sxy / sxx;
+    double aa = mY - b * mE;
+    if (!isfinite(b) || !isfinite(aa)) return ORC_ERANGE;
+    fit[2 * side] = aa;
+    fit[2 * side + 1] = b;
+  }
+  if (!(fit[3] > 0.0)) return ORC_ERANGE;
+  if (s->stat == ORC_BOSE) {
+    double p0 = orc_grid_q(s, 0) / a, pN = orc_grid_q(s, n - 1) / a;
+    double E0 = sqrt(p0 * p0 + m * m), EN = sqrt(pN * pN + m * m);
+    if (!(fit[0] + fit[1] * m > 0.0) || !(fit[0] + fit[1] * E0 > 0.0)) return ORC_ERANGE;
+    if (!(fit[2] + fit[3] * EN > 0.0)) return ORC_ERANGE;
+  }
+  return ORC_OK;
+}
+
+/* f at comoving momentum q with physical energy E (Sec. III.B):
+ *   inside [q_0, q_{N-1}]: linear interpolation in ln q between the bracketing nodes;
+ *   below / above: f = 1 / (exp(a + b E) - eta) with the low / high fit. */
+double orc_f_at(const orc_species* s, const double fit[4], double q, double E) {
+  const int n = s->n_grid;
+  if (q < s->q_min) return 1.0 / (exp(fit[0] + fit[1] * E) - (double)s->stat);
+  if (q > s->q_max) return 1.0 / (exp(fit[2] + fit[3] * E) - (double)s->stat);
+  double lq0 = log(s->q_min);
+  double h = (log(s->q_max) - lq0) / (double)(n - 1);
+  double tpos = (log(q) - lq0) / h;
+  int j = (int)floor(tpos);
+  if (j < 0) j = 0;
+  if (j > n - 2) j = n - 2;
+  double w = tpos - (double)j;
+  return s->f[j] + w * (s->f[j + 1] - s->f[j]);
+}
+
+/* f at n points (q[i], E[i]) -- the same rule as orc_f_at. */
+void orc_f_batch(const orc_species* s, const double fit[4], int64_t n, const double* q, const double* E, double* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_f_at(s, fit, q[i], E[i]);
+}
+
+/* =====================================================================================================
+ * Roles (Sec. II.C; Appendix A "Particle roles").
+ * ===================================================================================================== */
+
+static int is_self_reverse(const orc_process* P) {
+  if (P->n_in != P->n_out) return 0;
+  int a[ORC_MAXN], b[ORC_MAXN];
+  for (int i = 0; i < P->n_in; ++i) a[i] = P->sp[i];
+  for (int i = 0; i < P->n_out; ++i) b[i] = P->sp[P->n_in + i];
+  /* insertion sort both lists */
+  for (int i = 1; i < P->n_in; ++i)
+    for (int k = i; k > 0 && a[k] < a[k - 1]; --k) { int t = a[k]; a[k] = a[k - 1]; a[k - 1] = t; }
+  for (int i = 1; i < P->n_out; ++i)
+    for (int k = i; k > 0 && b[k] < b[k - 1]; --k) { int t = b[k]; b[k] = b[k - 1]; b[k - 1] = t; }
+  for (int i = 0; i < P->n_in; ++i)
+    if (a[i] != b[i]) return 0;
+  return 1;
+}
+
+/* Number of times species a occupies side `side` (0 = initial state, 1 = final state). */
+static int side_count(const orc_process* P, int a, int side) {
+  int lo = side == 0 ? 0 : P->n_in, hi = side == 0 ? P->n_in : P->n_in + P->n_out, c = 0;
+  for (int i = lo; i < hi; ++i) c += (P->sp[i] == a);
+  return c;
+}
+
+/* Multiplicity with which the side-`side` evaluation of species a enters C_a (Eq. 7; Eq. 12 for
+ * self-reverse processes under the automatic side selection).  0 means the side is not evaluated. */
+int orc_side_multiplicity(const orc_process* P, int a, int side) {
+  int n_s = side_count(P, a, side);
+  if (n_s == 0) return 0;
+  int mask = P->side_mask;
+  if (mask == ORC_SIDES_AUTO) {
+    if (is_self_reverse(P) && side == 1) return 0;
+    return n_s;
+  }
+  if (!(mask & (1 << side))) return 0;
+  return n_s;
+}
+
+/* Observed, conserved and integrated particle indices for species a pinned to side `side`. */
+int orc_roles(const orc_process* P, int a, int side, int* i_obs, int* i_cons, int* integ) {
+  const int n_in = P->n_in, n = P->n_in + P->n_out;
+  int lo = side == 0 ? 0 : n_in, hi = side == 0 ? n_in : n;
+  int obs = -1;
+  for (int i = lo; i < hi; ++i)
+    if (P->sp[i] == a) { obs = i; break; }
+  if (obs < 0) return ORC_EINVAL;
+  /* side that receives the conserved particle */
+  int cside;
+  if (P->n_in != P->n_out) cside = P->n_in < P->n_out ? 0 : 1; /* fewer-particle side */
+  else cside = side;                                           /* same side as the observed one */
+  int cons = -1;
+  {
+    int l = cside == 0 ? 0 : n_in, h = cside == 0 ? n_in : n;
+    for (int i = l; i < h; ++i)
+      if (i != obs) { cons = i; break; }
+  }
+  if (cons < 0) { /* fallback: lowest index on the opposite side */
+    int os = 1 - cside;
+    int l = os == 0 ? 0 : n_in, h = os == 0 ? n_in : n;
+    for (int i = l; i < h; ++i)
+      if (i != obs) { cons = i; break; }
+  }
+  if (cons < 0) return ORC_EINVAL;
+  int k = 0;
+  for (int i = 0; i < n; ++i)
+    if (i != obs && i != cons) integ[k++] = i;
+  *i_obs = obs;
+  *i_cons = cons;
+  return ORC_OK;
+}
+
+uint32_t orc_uid(int proc, int species, int side, int term, int eval_idx) {
+  return ((uint32_t)proc << 24) | ((uint32_t)species << 20) | ((uint32_t)side << 19) | ((uint32_t)term << 18) |
+         (uint32_t)eval_idx;
+}
+
+/* Work items for (process selection, species selection), ordered by identifier: process, species,
+ * side, term, evaluation index.  Evaluation indices are {0, s, 2s, ...} below the observed species'
+ * grid size, s = stride_override if > 0 else the process's own stride. */
+int orc_list_items(const orc_world* w, int proc_sel, int species_sel, int stride_override, orc_item* out,
+                   int cap) {
+  int count = 0;
+  for (int p = 0; p < w->n_proc; ++p) {
+    if (proc_sel >= 0 && p != proc_sel) continue;
+    const orc_process* P = &w->procs[p];
+    for (int a = 0; a < w->n_species; ++a) {
+      if (species_sel >= 0 && a != species_sel) continue;
+      for (int side = 0; side < 2; ++side) {
+        int mult = orc_side_multiplicity(P, a, side);
+        if (mult == 0) continue;
+        int n_terms = P->term_mode == ORC_TERMS_NET ? 1 : 2;
+        int stride = stride_override > 0 ? stride_override : (P->eval_stride > 0 ? P->eval_stride : 1);
+        for (int term = 0; term < n_terms; ++term) {
+          for (int i = 0; i < w->species[a].n_grid; i += stride) {
+            if (out && count < cap) {
+              orc_item* it = &out[count];
+              it->proc = p;
+              it->species = a;
+              it->side = side;
+              it->term = term;
+              it->eval_idx = i;
+              it->mult = mult;
+              it->uid = orc_uid(p, a, side, term, i);
+            }
+            ++count;
+          }
+        }
+      }
+    }
+  }
+  return count;
+}
+
+int orc_item_dims(const orc_world* w, const orc_item* it) {
+  const orc_process* P = &w->procs[it->proc];
+  return 3 * (P->n_in + P->n_out - 2);
+}
+
+/* Integration range of dimension d: r in [q_min, q_max] of the integrated particle's species,
+ * theta in [0, pi], phi in [0, 2 pi)  (Appendix A). */
+static void dim_range(const orc_world* w, const orc_process* P, const int* integ, int d, double* lo, double* hi) {
+  int k = d / 3, c = d % 3;
+  if (c == 0) {
+    const orc_species* s = &w->species[P->sp[integ[k]]];
+    *lo = s->q_min;
+    *hi = s->q_max;
+  } else if (c == 1) {
+    *lo = 0.0;
+    *hi = PI_D;
+  } else {
+    *lo = 0.0;
+    *hi = TWO_PI;
+  }
+}
+
+void orc_map_uniform(const orc_world* w, const orc_item* it, double* map) {
+  const orc_process* P = &w->procs[it->proc];
+  int i_obs, i_cons, integ[ORC_MAXN];
+  orc_roles(P, it->species, it->side, &i_obs, &i_cons, integ);
+  const int D = orc_item_dims(w, it), nb = P->n_bins;
+  for (int d = 0; d < D; ++d) {
+    double lo, hi;
+    dim_range(w, P, integ, d, &lo, &hi);
+    for (int j = 0; j <= nb; ++j) map[d * (nb + 1) + j] = lo + (hi - lo) * (double)j / (double)nb;
+  }
+}
+
+/* =====================================================================================================
+ * The integrand of one work item at a point x of the 3(n-2)-dimensional space.
+ * ===================================================================================================== */
+
+/* Statistical factor relative to the observed leg (Eq. 5 and the gain / loss lists of Sec. II.C):
+ *   gain = prod_{opposite side} f_i * prod_{observed side} (1 + eta_i f_i)
+ *   loss = prod_{observed side} f_i * prod_{opposite side} (1 + eta_i f_i)
+ * f[i], eta[i] per position (initial state i < n_in).  SPLIT: term 0 = gain, 1 = loss; NET: gain - loss. */
+double orc_stat_factor(int n_in, int n, int obs_side, int term_mode, int term, const double* f, const double* eta) {
+  double gain = 1.0, loss = 1.0;
+  for (int i = 0; i < n; ++i) {
+    int on_obs_side = ((i < n_in) ? 0 : 1) == obs_side;
+    if (on_obs_side) {
+      gain *= 1.0 + eta[i] * f[i];
+      loss *= f[i];
+    } else {
+      gain *= f[i];
+      loss *= 1.0 + eta[i] * f[i];
+    }
+  }
+  if (term_mode == ORC_TERMS_NET) return gain - loss;
+  return term == 0 ? gain : loss;
+}
+
+typedef struct {
+  const orc_world* w;
+  const orc_process* P;
+  int n, n_in, n_int;
+  int i_obs, i_cons, integ[ORC_MAXN];
+  int obs_side, term;
+  double a;                   /* scale factor */
+  double m[ORC_MAXN];         /* mass of each position */
+  double eta[ORC_MAXN];       /* statistics of each position */
+  const orc_species* sp[ORC_MAXN];
+  const double* fit[ORC_MAXN];
+  double q_obs, f_obs;        /* comoving observed momentum, table value of f there */
+} item_ctx;
+
+static int item_setup(item_ctx* c, const orc_world* w, const orc_item* it, double t, const double* fits) {
+  c->w = w;
+  c->P = &w->procs[it->proc];
+  c->n_in = c->P->n_in;
+  c->n = c->P->n_in + c->P->n_out;
+  c->n_int = c->n - 2;
+  c->obs_side = it->side;
+  c->term = it->term;
+  int rc = orc_roles(c->P, it->species, it->side, &c->i_obs, &c->i_cons, c->integ);
+  if (rc) return rc;
+  c->a = orc_scale_factor(w, t);
+  for (int i = 0; i < c->n; ++i) {
+    const orc_species* s = &w->species[c->P->sp[i]];
+    c->sp[i] = s;
+    c->m[i] = orc_mass(s, t);
+    c->eta[i] = (double)s->stat;
+    c->fit[i] = &fits[4 * c->P->sp[i]];
+  }
+  const orc_species* so = &w->species[it->species];
+  c->q_obs = orc_grid_q(so, it->eval_idx);
+  c->f_obs = so->f[it->eval_idx];
+  return ORC_OK;
+}
+
+/* Weight of the point x, excluding the Vegas Jacobian (Appendix A, Eq. A-weight):
+ *   prod_k r_k^2 sin(theta_k) a^{-3} * |M|^2 * delta_sigma(E_in - E_out)
+ *     / ((2 pi)^{3(n-1)-4} prod_{all i} 2 E_i) * F,
+ * with F = gain or loss (SPLIT) or gain - loss (NET), gain/loss defined relative to the observed leg:
+ *   gain = prod_{opposite side} f * prod_{observed side} (1 + eta f)
+ *   loss = prod_{observed side} f * prod_{opposite side} (1 + eta f)       (Sec. II.C, the C_2 / C_3 lists)
+ * Points with any E_i below the cut get weight 0 (Appendix A). */
+static double item_integrand(const item_ctx* c, const double* x) {
+  const int n = c->n, n_in = c->n_in;
+  const double a = c->a;
+  double px[ORC_MAXN], py[ORC_MAXN], pz[ORC_MAXN], E[ORC_MAXN], f[ORC_MAXN] = {0};
+  double jac = 1.0;
+  /* observed particle on the z axis, physical momentum q/a */
+  px[c->i_obs] = 0.0;
+  py[c->i_obs] = 0.0;
+  pz[c->i_obs] = c->q_obs / a;
+  /* integrated particles: spherical coordinates, comoving r, physical p = r / a */
+  for (int k = 0; k < c->n_int; ++k) {
+    int i = c->integ[k];
+    double r = x[3 * k], th = x[3 * k + 1], ph = x[3 * k + 2];
+    double p = r / a;
+    px[i] = p * sin(th) * cos(ph);
+    py[i] = p * sin(th) * sin(ph);
+    pz[i] = p * cos(th);
+    jac *= r * r * sin(th);
+  }
+  /* conserved particle (Eq. 14 / Appendix A momentum conservation) */
+  {
+    double sx = 0, sy = 0, sz = 0;
+    for (int i = 0; i < n; ++i) {
+      if (i == c->i_cons) continue;
+      double sgn = (i < n_in) ? 1.0 : -1.0; /* sum_in - sum_out */
+      sx += sgn * px[i];
+      sy += sgn * py[i];
+      sz += sgn * pz[i];
+    }
+    if (c->i_cons < n_in) { sx = -sx; sy = -sy; sz = -sz; } /* sum_out - sum_in for an initial-state one */
+    px[c->i_cons] = sx;
+    py[c->i_cons] = sy;
+    pz[c->i_cons] = sz;
+  }
+  /* energies */
+  for (int i = 0; i < n; ++i) {
+    double p2 = px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i];
+    E[i] = sqrt(p2 + c->m[i] * c->m[i]);
+    if (E[i] < c->P->e_cut) return 0.0;
+  }
+  double dE = 0.0;
+  for (int i = 0; i < n; ++i) dE += (i < n_in) ? E[i] : -E[i];
+  const double sig = c->P->sigma_E;
+  double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
+  /* distribution values */
+  for (int i = 0; i < n; ++i) {
+    if (i == c->i_obs) {
+      f[i] = c->f_obs;
+    } else if (i == c->i_cons) {
+      double pabs = sqrt(px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i]);
+      f[i] = orc_f_at(c->sp[i], c->fit[i], a * pabs, E[i]);
+    } else {
+      int k = -1;
+      for (int kk = 0; kk < c->n_int; ++kk)
+        if (c->integ[kk] == i) k = kk;
+      f[i] = orc_f_at(c->sp[i], c->fit[i], x[3 * k], E[i]);
+    }
+  }
+  double F = orc_stat_factor(n_in, n, c->obs_side, c->P->term_mode, c->term, f, c->eta);
+  double prod2E = 1.0;
+  for (int i = 0; i < n; ++i) prod2E *= 2.0 * E[i];
+  double twopi_pow = pow(TWO_PI, (double)(3 * (n - 1) - 4));
+  double a3 = pow(a, -3.0 * (double)c->n_int);
+  double M2 = c->P->coupling * c->P->coupling;
+  return jac * a3 * M2 * delta / (twopi_pow * prod2E) * F;
+}
+
+/* Fit parameters of every species at time t (4 doubles each). */
+int orc_fits_all(const orc_world* w, double t, double* fits) {
+  double a = orc_scale_factor(w, t);
+  for (int s = 0; s < w->n_species; ++s) {
+    int rc = orc_fit(&w->species[s], a, t, &fits[4 * s]);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+int orc_integrand_at(const orc_world* w, const orc_item* it, const double* x, double* value) {
+  double fits[4 * ORC_MAXSPECIES];
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  item_ctx c;
+  rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  *value = item_integrand(&c, x);
+  return ORC_OK;
+}
+
+/* The integrand (without Vegas Jacobian) at n points x[n][D] of one item, OpenMP over points. */
+int orc_integrand_batch(const orc_world* w, const orc_item* it, int64_t n, const double* x, double* value) {
+  double fits[4 * ORC_MAXSPECIES];
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  item_ctx c;
+  rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  const int D = 3 * c.n_int;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) value[i] = item_integrand(&c, &x[i * D]);
+  return ORC_OK;
+}
+
+/* =====================================================================================================
+ * Vegas (Lepage, J. Comput. Phys. 27 (1978) 192; 439 (2021) 110386) for one work item.
+ * ===================================================================================================== */
+
+/* Map adaptation of one dimension from the per-bin sums h_j (of squared weights) and counts c_j:
+ * average d_j = h_j / c_j, (7,1)/(1,6,1)/(1,7) / 8 smoothing, normalisation to unit sum, damping
+ * w_j = ((1 - d_j) / ln(1/d_j))^alpha, then new interior edges at equal cumulative w, placed linearly
+ * inside the old bins.  Dimensions whose smoothed sum is zero keep their edges. */
+static void adapt_dim(double* edges, int nb, const long double* h, const long double* cnt, double alpha) {
+  double d[ORC_MAXBINS], ds[ORC_MAXBINS], wgt[ORC_MAXBINS], old[ORC_MAXBINS + 1];
+  for (int j = 0; j < nb; ++j) d[j] = cnt[j] > 0 ? (double)(h[j] / cnt[j]) : 0.0;
+  if (nb == 1) return;
+  ds[0] = (7.0 * d[0] + d[1]) / 8.0;
+  ds[nb - 1] = (d[nb - 2] + 7.0 * d[nb - 1]) / 8.0;
+  for (int j = 1; j < nb - 1; ++j) ds[j] = (d[j - 1] + 6.0 * d[j] + d[j + 1]) / 8.0;
+  double sum = 0.0;
+  for (int j = 0; j < nb; ++j) sum += ds[j];
+  if (!(sum > 0.0)) return;
+  double wsum = 0.0;
+  for (int j = 0; j < nb; ++j) {
+    double dh = ds[j] / sum;
+    double v;
+    if (dh <= 0.0) v = 0.0;
+    else if (dh >= 1.0) v = 1.0;
+    else {
+      double base = (1.0 - dh) / log(1.0 / dh);
+      v = alpha == 0.5 ? sqrt(base) : pow(base, alpha);
+    }
+    wgt[j] = v;
+    wsum += v;
+  }
+  if (!(wsum > 0.0)) return;
+  for (int j = 0; j <= nb; ++j) old[j] = edges[j];
+  const double per_bin = wsum / (double)nb;
+  int j = 0;           /* current old bin */
+  double acc = 0.0;    /* cumulative weight up to the start of old bin j */
+  for (int k = 1; k < nb; ++k) {
+    double target = per_bin * (double)k;
+    while (j < nb - 1 && acc + wgt[j] < target) {
+      acc += wgt[j];
+      ++j;
+    }
+    double frac = wgt[j] > 0.0 ? (target - acc) / wgt[j] : 0.0;
+    if (frac > 1.0) frac = 1.0;
+    if (frac < 0.0) frac = 0.0;
+    edges[k] = old[j] + frac * (old[j + 1] - old[j]);
+  }
+  edges[0] = old[0];
+  edges[nb] = old[nb];
+}
+
+/* Runs Vegas iterations first_iter .. first_iter + nitn - 1 of N samples for one item.  map: D x (nb+1)
+ * edges (in: current map; out: map adapted after every iteration, or unchanged when adapt == 0).  I_it, V_it: per-iteration estimate and its variance
+ * V = (S2/N - I^2)/(N-1).  Ibar, sigma: inverse-variance weighted combination over the iterations with
+ * V > 0 (plain mean and sigma 0 if there is none). */
+int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int first_iter, int nitn,
+                   uint64_t seed, uint32_t epoch, int adapt, double* map, double* I_it, double* V_it, double* Ibar,
+                   double* sigma) {
+  item_ctx c;
+  int rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  const int D = 3 * c.n_int, nb = c.P->n_bins;
+  long double* h = (long double*)calloc((size_t)D * nb, sizeof(long double));
+  long double* cn = (long double*)calloc((size_t)D * nb, sizeof(long double));
+  if (!h || !cn) { free(h); free(cn); return ORC_ENOMEM; }
+  double y[ORC_MAXD], x[ORC_MAXD];
+  int jb[ORC_MAXD];
+  for (int itn = 0; itn < nitn; ++itn) {
+    long double S1 = 0.0L, S2 = 0.0L;
+    memset(h, 0, sizeof(long double) * (size_t)D * nb);
+    memset(cn, 0, sizeof(long double) * (size_t)D * nb);
+    for (int64_t s = 0; s < N; ++s) {
+      orc_sample_uniforms(seed, it->uid, epoch, first_iter + itn, s, D, y);
+      double J = 1.0;
+      for (int d = 0; d < D; ++d) {
+        double yn = y[d] * (double)nb;
+        int j = (int)floor(yn);
+        if (j > nb - 1) j = nb - 1;
+        double del = yn - (double)j;
+        double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+        x[d] = e0 + (e1 - e0) * del;
+        J *= (double)nb * (e1 - e0);
+        jb[d] = j;
+      }
+      double W = J * item_integrand(&c, x);
+      S1 += (long double)W;
+      S2 += (long double)W * (long double)W;
+      /* training data of the map: W^2, with weights below 2^-400 in magnitude counted as 0 so that every
+       * contribution is a normal double (sub-normal squares carry rounding-order-dependent relative
+       * errors of order one, which the logarithm of the damping step would turn into edge shifts) */
+      double w2 = fabs(W) >= ORC_HIST_WMIN ? W * W : 0.0;
+      for (int d = 0; d < D; ++d) {
+        h[d * nb + jb[d]] += (long double)w2;
+        cn[d * nb + jb[d]] += 1.0L;
+      }
+    }
+    double Id = (double)(S1 / (long double)N);
+    double Vd = (double)(((S2 / (long double)N) - (long double)Id * (long double)Id) / (long double)(N - 1));
+    I_it[itn] = Id;
+    V_it[itn] = Vd;
+    if (adapt)
+      for (int d = 0; d < D; ++d) adapt_dim(&map[d * (nb + 1)], nb, &h[d * nb], &cn[d * nb], c.P->alpha);
+  }
+  free(h);
+  free(cn);
+  double sw = 0.0, swI = 0.0;
+  int npos = 0;
+  for (int itn = 0; itn < nitn; ++itn) {
+    if (V_it[itn] > 0.0) {
+      sw += 1.0 / V_it[itn];
+      swI += I_it[itn] / V_it[itn];
+      ++npos;
+    }
+  }
+  if (npos > 0) {
+    *Ibar = swI / sw;
+    *sigma = 1.0 / sqrt(sw);
+  } else {
+    double m = 0.0;
+    for (int itn = 0; itn < nitn; ++itn) m += I_it[itn];
+    *Ibar = nitn > 0 ? m / nitn : 0.0;
+    *sigma = 0.0;
+  }
+  return ORC_OK;
+}
+
+/* Runs every item of `items` (OpenMP over items).  maps: n_items x ORC_MAP_STRIDE(nb) doubles (in/out;
+ * a row whose first edge is NaN is initialised to the uniform map first).  I_it, V_it: n_items x nitn. */
+int orc_run_items(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
+                  uint64_t seed, uint32_t epoch, int adapt, double* maps, double* I_it, double* V_it, double* Ibar,
+                  double* sigma, int n_threads) {
+  double fits[4 * ORC_MAXSPECIES];
+  if (w->n_species > ORC_MAXSPECIES) return ORC_EINVAL;
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  if (N < 2 || nitn < 1 || first_iter < 0 || first_iter + nitn > 64) return ORC_EINVAL;
+  int err = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_items; ++i) {
+    const orc_process* P = &w->procs[items[i].proc];
+    double* map = &maps[(size_t)i * ORC_MAP_STRIDE(P->n_bins)];
+    if (isnan(map[0])) orc_map_uniform(w, &items[i], map);
+    int r = orc_item_vegas(w, &items[i], fits, N, first_iter, nitn, seed, epoch, adapt, map,
+                           &I_it[(size_t)i * nitn], &V_it[(size_t)i * nitn], &Ibar[i], &sigma[i]);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  return err;
+}
+
+/* Combination of item results into C_a on the evaluation points (Eq. 7, Eq. 12):
+ *   C(q_i) = sum over items at point i of mult * (+Ibar for gain / net, -Ibar for loss),
+ *   sigma(q_i)^2 = sum of mult^2 sigma_item^2.
+ * C and sigma are indexed by grid index (n_grid entries); points that are not evaluated are left 0. */
+void orc_combine(const orc_world* w, int n_items, const orc_item* items, const double* Ibar, const double* sig,
+                 int species, double* C, double* sigma) {
+  int n = w->species[species].n_grid;
+  for (int j = 0; j < n; ++j) { C[j] = 0.0; sigma[j] = 0.0; }
+  for (int i = 0; i < n_items; ++i) {
+    const orc_item* it = &items[i];
+    if (it->species != species) continue;
+    const orc_process* P = &w->procs[it->proc];
+    double sgn = (P->term_mode == ORC_TERMS_SPLIT && it->term == 1) ? -1.0 : 1.0;
+    C[it->eval_idx] += (double)it->mult * sgn * Ibar[i];
+    sigma[it->eval_idx] += (double)it->mult * (double)it->mult * sig[i] * sig[i];
+  }
+  for (int j = 0; j < n; ++j) sigma[j] = sqrt(sigma[j]);
+}
+
+/* Fill rule for a strided evaluation of one process on the grid of species a: between evaluated
+ * neighbours C is linear in ln q; beyond the last evaluated index, C/f of that index is held. */
+static void fill_strided(const orc_species* s, int stride, double* C, double* sg) {
+  const int n = s->n_grid;
+  if (stride <= 1) return;
+  int last = ((n - 1) / stride) * stride;
+  for (int j = 0; j < n; ++j) {
+    if (j % stride == 0) continue;
+    if (j > last) {
+      C[j] = C[last] / s->f[last] * s->f[j];
+      sg[j] = sg[last] / s->f[last] * s->f[j];
+      continue;
+    }
+    int i0 = (j / stride) * stride, i1 = i0 + stride;
+    double l0 = log(orc_grid_q(s, i0)), l1 = log(orc_grid_q(s, i1)), lj = log(orc_grid_q(s, j));
+    double u = (lj - l0) / (l1 - l0);
+    C[j] = C[i0] + u * (C[i1] - C[i0]);
+    sg[j] = sg[i0] + u * (sg[i1] - sg[i0]);
+  }
+}
+
+/* Full-grid collision term of every species from all processes at the world's current time:
+ * per process, its items are run and combined, the strided fill rule is applied, and the processes'
+ * contributions are summed (sigma in quadrature).  C_all / sig_all: concatenation over species of
+ * n_grid entries each.  maps: per item of orc_list_items(w, -1, -1, 0) order (in/out). */
+int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, uint32_t epoch, int adapt,
+                      double* maps, double* C_all, double* sig_all, int n_threads) {
+  int n_items = orc_list_items(w, -1, -1, 0, NULL, 0);
+  orc_item* items = (orc_item*)malloc(sizeof(orc_item) * (size_t)(n_items > 0 ? n_items : 1));
+  double* I_it = (double*)malloc(sizeof(double) * (size_t)(n_items > 0 ? n_items : 1) * (size_t)nitn);
+  double* V_it = (double*)malloc(sizeof(double) * (size_t)(n_items > 0 ? n_items : 1) * (size_t)nitn);
+  double* Ib = (double*)malloc(sizeof(double) * (size_t)(n_items > 0 ? n_items : 1));
+  double* sg = (double*)malloc(sizeof(double) * (size_t)(n_items > 0 ? n_items : 1));
+  if (!items || !I_it || !V_it || !Ib || !sg) {
+    free(items); free(I_it); free(V_it); free(Ib); free(sg);
+    return ORC_ENOMEM;
+  }
+  orc_list_items(w, -1, -1, 0, items, n_items);
+  int rc = orc_run_items(w, n_items, items, N, 0, nitn, seed, epoch, adapt, maps, I_it, V_it, Ib, sg, n_threads);
+  if (rc == ORC_OK) {
+    size_t off = 0;
+    for (int a = 0; a < w->n_species; ++a) {
+      int n = w->species[a].n_grid;
+      for (int j = 0; j < n; ++j) { C_all[off + j] = 0.0; sig_all[off + j] = 0.0; }
+      double* Cp = (double*)malloc(sizeof(double) * (size_t)n);
+      double* Sp = (double*)malloc(sizeof(double) * (size_t)n);
+      for (int p = 0; p < w->n_proc; ++p) {
+        /* items of process p and species a */
+        int first = -1, cnt = 0;
+        for (int i = 0; i < n_items; ++i)
+          if (items[i].proc == p && items[i].species == a) { if (first < 0) first = i; ++cnt; }
+        if (cnt == 0) continue;
+        orc_combine(w, cnt, &items[first], &Ib[first], &sg[first], a, Cp, Sp);
+        int stride = w->procs[p].eval_stride > 0 ? w->procs[p].eval_stride : 1;
+        fill_strided(&w->species[a], stride, Cp, Sp);
+        for (int j = 0; j < n; ++j) {
+          C_all[off + j] += Cp[j];
+          sig_all[off + j] = sqrt(sig_all[off + j] * sig_all[off + j] + Sp[j] * Sp[j]);
+        }
+      }
+      free(Cp);
+      free(Sp);
+      off += (size_t)n;
+    }
+  }
+  free(items); free(I_it); free(V_it); free(Ib); free(sg);
+  return rc;
+}
+
+/* =====================================================================================================
+ * Log-space time stepping (Sec. III.C).
+ * ===================================================================================================== */
+
+/* One Euler or Heun step of every species' f (in place, via the species' f pointers, which must be
+ * writable), advancing w->t.  dt > 0: fixed step; dt <= 0: dt = min(dt_max, eps / max |k1/f|).
+ * Heun: f* = f exp(dt k1/f), k2 = C[f*] at t + dt with epoch + 1,
+ *       log f <- log f + dt/2 (k1/f + k2/f*).
+ * Euler: log f <- log f + dt k1/f.   Maps are reused and updated in place. */
+int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
+             uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads) {
+  size_t tot = 0;
+  for (int a = 0; a < w->n_species; ++a) tot += (size_t)w->species[a].n_grid;
+  double* k1 = (double*)malloc(sizeof(double) * tot);
+  double* k2 = (double*)malloc(sizeof(double) * tot);
+  double* sg = (double*)malloc(sizeof(double) * tot);
+  double* f0 = (double*)malloc(sizeof(double) * tot);
+  double* fs = (double*)malloc(sizeof(double) * tot);
+  if (!k1 || !k2 || !sg || !f0 || !fs) {
+    free(k1); free(k2); free(sg); free(f0); free(fs);
+    return ORC_ENOMEM;
+  }
+  int rc = orc_collision_all(w, N, nitn, seed, epoch, adapt, maps, k1, sg, n_threads);
+  if (rc) goto done;
+  {
+    size_t off = 0;
+    double rmax = 0.0;
+    for (int a = 0; a < w->n_species; ++a) {
+      const orc_species* s = &w->species[a];
+      for (int j = 0; j < s->n_grid; ++j) {
+        f0[off + j] = s->f[j];
+        double r = fabs(k1[off + j] / s->f[j]);
+        if (r > rmax) rmax = r;
+      }
+      off += (size_t)s->n_grid;
+    }
+    double h = dt;
+    if (!(h > 0.0)) {
+      h = rmax > 0.0 ? eps / rmax : dt_max;
+      if (h > dt_max) h = dt_max;
+    }
+    *dt_used = h;
+    if (method == ORC_EULER) {
+      off = 0;
+      for (int a = 0; a < w->n_species; ++a) {
+        double* f = (double*)w->species[a].f;
+        for (int j = 0; j < w->species[a].n_grid; ++j) f[j] = exp(log(f0[off + j]) + h * k1[off + j] / f0[off + j]);
+        off += (size_t)w->species[a].n_grid;
+      }
+      w->t += h;
+    } else {
+      off = 0;
+      for (int a = 0; a < w->n_species; ++a) {
+        double* f = (double*)w->species[a].f;
+        for (int j = 0; j < w->species[a].n_grid; ++j) {
+          fs[off + j] = exp(log(f0[off + j]) + h * k1[off + j] / f0[off + j]);
+          f[j] = fs[off + j];
+        }
+        off += (size_t)w->species[a].n_grid;
+      }
+      double t0 = w->t;
+      w->t = t0 + h;
+      rc = orc_collision_all(w, N, nitn, seed, epoch + 1u, adapt, maps, k2, sg, n_threads);
+      if (rc) {
+        w->t = t0;
+        off = 0;
+        for (int a = 0; a < w->n_species; ++a) {
+          double* f = (double*)w->species[a].f;
+          for (int j = 0; j < w->species[a].n_grid; ++j) f[j] = f0[off + j];
+          off += (size_t)w->species[a].n_grid;
+        }
+        goto done;
+      }
+      off = 0;
+      for (int a = 0; a < w->n_species; ++a) {
+        double* f = (double*)w->species[a].f;
+        for (int j = 0; j < w->species[a].n_grid; ++j)
+          f[j] = exp(log(f0[off + j]) + 0.5 * h * (k1[off + j] / f0[off + j] + k2[off + j] / fs[off + j]));
+        off += (size_t)w->species[a].n_grid;
+      }
+    }
+  }
+done:
+  free(k1); free(k2); free(sg); free(f0); free(fs);
+  return rc;
+}

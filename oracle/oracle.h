@@ -1,0 +1,110 @@
+/*
+ * oracle.h -- declarations of the CPU FP64 reference (test infrastructure only; see oracle.c).
+ * This header is private to oracle/ and the test suite; the product library never includes it.
+ */
+#ifndef BOLTZ_ORACLE_H
+#define BOLTZ_ORACLE_H
+
+#include <stdint.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ESTATE (-2)
+#define ORC_ERANGE (-3)
+#define ORC_ENOMEM (-4)
+
+#define ORC_MAXN 6          /* particles per process */
+#define ORC_MAXD 12         /* 3 (n - 2) */
+#define ORC_MAXBINS 256
+#define ORC_MAXSPECIES 16
+#define ORC_NFIT 5          /* nodes per end in the extrapolation fit */
+#define ORC_HIST_WMIN 0x1p-400 /* smallest |W| whose square enters the Vegas histogram */
+#define ORC_MAP_STRIDE(nb) (ORC_MAXD * ((nb) + 1))
+
+#define ORC_BOSE 1
+#define ORC_FERMI (-1)
+#define ORC_MB 0
+
+#define ORC_MASS_CONST 0
+#define ORC_MASS_SIN 1
+
+#define ORC_EXP_NONE 0
+#define ORC_EXP_RADIATION 1
+
+#define ORC_TERMS_SPLIT 0
+#define ORC_TERMS_NET 1
+
+#define ORC_SIDES_AUTO 0    /* self-reverse -> initial side only; else both sides */
+
+#define ORC_EULER 0
+#define ORC_HEUN 1
+
+typedef struct {
+  int stat;                 /* eta: +1 Bose-Einstein, -1 Fermi-Dirac, 0 Maxwell-Boltzmann */
+  int n_grid;               /* logarithmic grid nodes */
+  double q_min, q_max;      /* comoving momentum range */
+  int mass_kind;            /* ORC_MASS_CONST or ORC_MASS_SIN (m0 + mA sin(mw t)) */
+  double m0, mA, mw;
+  const double* f;          /* n_grid values of f on the grid */
+} orc_species;
+
+typedef struct {
+  int n_in, n_out;
+  int sp[ORC_MAXN];         /* species of positions 0..n-1 (initial state first) */
+  double coupling;          /* |M|^2 = coupling^2 */
+  double sigma_E;           /* absolute Gaussian width */
+  double alpha;             /* Vegas damping exponent */
+  double e_cut;             /* energy cut */
+  int n_bins;               /* Vegas bins per dimension */
+  int term_mode;            /* ORC_TERMS_SPLIT (gain and loss items) or ORC_TERMS_NET */
+  int side_mask;            /* ORC_SIDES_AUTO, or bit 0 = initial side, bit 1 = final side */
+  int eval_stride;          /* evaluate every k-th grid point of the observed species */
+} orc_process;
+
+typedef struct {
+  int n_species;
+  const orc_species* species;
+  int n_proc;
+  const orc_process* procs;
+  double t;
+  int expansion;            /* ORC_EXP_NONE or ORC_EXP_RADIATION */
+  double a0, t0;
+} orc_world;
+
+typedef struct {
+  int proc, species, side, term, eval_idx, mult;
+  uint32_t uid;
+} orc_item;
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void orc_sample_uniforms(uint64_t seed, uint32_t uid, uint32_t epoch, int it, int64_t n, int D, double* y);
+double orc_grid_q(const orc_species* s, int j);
+double orc_mass(const orc_species* s, double t);
+double orc_scale_factor(const orc_world* w, double t);
+int orc_fit(const orc_species* s, double a, double t, double fit[4]);
+double orc_f_at(const orc_species* s, const double fit[4], double q, double E);
+void orc_f_batch(const orc_species* s, const double fit[4], int64_t n, const double* q, const double* E, double* out);
+int orc_side_multiplicity(const orc_process* P, int a, int side);
+int orc_roles(const orc_process* P, int a, int side, int* i_obs, int* i_cons, int* integ);
+uint32_t orc_uid(int proc, int species, int side, int term, int eval_idx);
+int orc_list_items(const orc_world* w, int proc_sel, int species_sel, int stride_override, orc_item* out, int cap);
+int orc_item_dims(const orc_world* w, const orc_item* it);
+void orc_map_uniform(const orc_world* w, const orc_item* it, double* map);
+int orc_fits_all(const orc_world* w, double t, double* fits);
+double orc_stat_factor(int n_in, int n, int obs_side, int term_mode, int term, const double* f, const double* eta);
+int orc_integrand_batch(const orc_world* w, const orc_item* it, int64_t n, const double* x, double* value);
+int orc_integrand_at(const orc_world* w, const orc_item* it, const double* x, double* value);
+int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int first_iter, int nitn,
+                   uint64_t seed, uint32_t epoch, int adapt, double* map, double* I_it, double* V_it, double* Ibar,
+                   double* sigma);
+int orc_run_items(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
+                  uint64_t seed, uint32_t epoch, int adapt, double* maps, double* I_it, double* V_it, double* Ibar,
+                  double* sigma, int n_threads);
+void orc_combine(const orc_world* w, int n_items, const orc_item* items, const double* Ibar, const double* sig,
+                 int species, double* C, double* sigma);
+int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, uint32_t epoch, int adapt,
+                      double* maps, double* C_all, double* sig_all, int n_threads);
+int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
+             uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads);
+
+#endif
