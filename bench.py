@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Benchmark of the Vegas Monte-Carlo collision integral on one MI355X.
+
+Workload: 2<->3 contact process of a single Bose-Einstein scalar (m = 1, |M|^2 = 1), f = 0.8 f_BE(T = 1.5) on a
+128-node logarithmic grid in [0.01, 30], sigma_E = 0.005, both pinned sides (multiplicities 2 and 3), separate
+gain and loss integrators: 512 work items, 10 Vegas iterations of 2^18 samples each (9-dimensional).
+
+A step is one full collision evaluation C[f] (all 10 iterations of all 512 items, with map adaptation and
+integrator reuse across steps) in the batched FP32-integrand form.  The JSON line reports its throughput in
+integrand samples/s, the speedup over the plain per-grid-point FP64 launch measured on the same workload
+(same estimator, same sigma), the roofline of the dominant sample kernel (timed with HIP events on the
+library's stream over the timed region) and the CPU reference timed on a bounded sample of the same items.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane per cycle on 256 CUs
+
+
+def ops_per_sample(n_int: int) -> int:
+    """Arithmetic operations the estimator needs per sample (each +, -, *, /, fma, sqrt, exp, log, sin, cos,
+    compare/select and each 32x32->64 multiply or 3-way xor of Philox counts one):
+    Philox 40 per block (10 rounds x 2 multiplies + 2 xors) x ceil(D/4); 9 per dimension (uniform from the
+    word, map lookup, Jacobian); 15 per integrated particle (momentum components, r^2 sin(theta), energy);
+    conserved momentum 3 (n_int + 1) + 5; energy sum and Gaussian (n_int + 2) + 4; f lookups 8 (n_int + 1) + 2;
+    statistical factor 3 (n_int + 2); weight 2 (n_int + 2) + 4; accumulation 5 + 2 D."""
+    D = 3 * n_int
+    return (40 * ((D + 3) // 4) + 9 * D + 15 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 4 + 8 * (n_int + 1) + 2
+            + 3 * (n_int + 2) + 2 * (n_int + 2) + 4 + 5 + 2 * D)
+
+
+def cpu_baseline(w, threads):
+    """The CPU oracle (as it stands) on a bounded sample of the same items."""
+    from oracle import binding as ob
+    ow = ob.OracleWorld(w)
+    items, n = ow.items()
+    nodes = set(range(0, 128, 8))
+    keep = [items[i] for i in range(n) if items[i].eval_idx in nodes]
+    arr = (ob.Item * len(keep))(*keep)
+    p = w.processes[0]
+    t0 = time.perf_counter()
+    rc, r = ow.run_items(arr, len(keep), p.n_samples, p.n_iter, seed=0, epoch=0, threads=threads)
+    dt = time.perf_counter() - t0
+    assert rc == 0
+    samples = len(keep) * p.n_samples * p.n_iter
+    return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of 512 items (grid nodes 0,8,...,120 x 2 sides x 2 terms), %d samples x %d iterations "
+                      "each = %.3g samples in %.1f s" % (len(keep), p.n_samples, p.n_iter, samples, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the collision-integral items shard across GPUs with one small "
+              "all-gather per evaluation, which this build does not implement; run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2603_28848_amd import boltzmc as bm
+    from paper_2603_28848_amd import workloads as wl
+
+    w = wl.w23_be()
+    p = w.processes[0]
+    n_int = len(p.ins) + len(p.outs) - 2
+
+    # ---- batched FP32-integrand: the timed path ----
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=0, epoch=0, precision=bm.FP32I, launch=bm.LAUNCH_BATCHED)
+    n_items, n_out = ctx.plan_size(-1, -1, opts)
+    samples_per_step = n_items * p.n_samples * p.n_iter
+    first_sigma = None
+    for k in range(max(1, args.warmup)):
+        opts.epoch = k
+        C, S = ctx.collision(-1, -1, opts)
+        if k == 0:
+            first_sigma = S.copy()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ctx.get_timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        opts.epoch = 1000 + k
+        ctx.collision(-1, -1, opts)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernel_ms, n_launch = ctx.get_timing(reset=True)
+    ctx.set_timing(False)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = samples_per_step / ((t1 - t0) / args.steps)
+
+    # ---- plain per-grid-point FP64 and batched FP64 on fresh contexts (same seed/epoch as warm-up 0) ----
+    def rate(precision, launch, steps):
+        c2 = bm.from_workload(w)
+        o = bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch)
+        Cx, Sx = c2.collision(-1, -1, o)  # first evaluation from the uniform maps (sigma comparison)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for k in range(steps):
+            o.epoch = 1000 + k
+            c2.collision(-1, -1, o)
+        torch.cuda.synchronize()
+        return samples_per_step * steps / (time.perf_counter() - ta), Sx
+
+    plain64, sig_plain = rate(bm.FP64, bm.LAUNCH_PLAIN, args.plain_steps)
+    batched64, _ = rate(bm.FP64, bm.LAUNCH_BATCHED, max(1, args.plain_steps))
+    ok = (first_sigma > 0) & (sig_plain > 0)
+    sigma_ratio = float(np.median(first_sigma[ok] / sig_plain[ok]))
+
+    # ---- roofline of the sample kernel ----
+    avg_launch_s = kernel_ms / max(1, n_launch) / 1e3
+    samples_per_launch = samples_per_step / p.n_iter
+    ops = ops_per_sample(n_int)
+    achieved = ops * samples_per_launch / avg_launch_s / 1e12
+
+    line = {
+        "metric": "2<->3 collision-integrand samples/s (batched FP32-integrand) + speedup vs plain per-grid-point "
+                  "FP64 at equal MC sigma",
+        "value": value,
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2<->3 BE scalar m=1 |M|^2=1, f=0.8 f_BE(T=1.5) on 128 log nodes [0.01,30], sigma_E=0.005, "
+                        "both sides (mult 2, 3), gain/loss split: 512 items x 10 Vegas iterations x 2^18 samples",
+            "items": n_items,
+            "samples_per_step": samples_per_step,
+            "precision": "FP32 integrand, FP64 kinematics and accumulation",
+            "launch": "batched persistent",
+            "plain_fp64_samples_per_s": plain64,
+            "batched_fp64_samples_per_s": batched64,
+            "speedup_vs_plain_fp64": value / plain64,
+            "speedup_fp32i_vs_fp64_batched": value / batched64,
+            "sigma_ratio_fp32i_over_plain_fp64": sigma_ratio,
+            "sample_kernel_avg_ms": avg_launch_s * 1e3,
+            "sample_kernel_launches": n_launch,
+        },
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
+                     "ops_per_sample": ops},
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        line["cpu_baseline"] = cpu_baseline(w, threads)
+    print(json.dumps(line))
+    sys.stdout.flush()
+
+
+if __name__ == "__main__":
+    main()

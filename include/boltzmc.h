@@ -1,0 +1,230 @@
+/*
+ * boltzmc.h -- C-ABI of the MI355X (gfx950) Monte-Carlo collision-integral library.
+ *
+ * The library evaluates the momentum-resolved collision integral
+ *     C_a(q_i) = sum over processes of  n_alpha^a C_alpha(q_i) + n_beta^a C_beta(q_i)
+ * (arXiv 2603.28848, Sec. II.C Eq. 7; Eq. 12 for self-reverse processes), each single-position term being
+ * C^(k)(p) = (1/2E) Int dPi |M|^2 Lambda (Sec. II.B Eqs. 3-5), by Vegas adaptive Monte Carlo over the
+ * 3(n_total - 2) dimensional space of Sec. II.D / Appendix A (observed momentum on z, one momentum fixed by
+ * momentum conservation, Gaussian energy delta Eq. 15, phase-space weight Eq. 16), with separate gain and
+ * loss integrators, and steps f in log space (Euler Eq. 18, Heun Eq. 19, adaptive step Eq. 20) in
+ * comoving momenta with an optional radiation-dominated expansion (Sec. III.E).
+ *
+ * Conventions
+ *   * Every function returns an int: BMC_OK (0) or a negative BMC_E* code.  bmc_last_error() describes the
+ *     last failure of a context (the string is owned by the context and valid until its next call).
+ *   * No exceptions cross this boundary.
+ *   * Array arguments are borrowed.  `mem` says whether a pointer is host (BMC_MEM_HOST) or device
+ *     (BMC_MEM_DEVICE) memory.  Device pointers are used asynchronously on the context's stream and must
+ *     stay valid until the stream reaches that point; calls that return host results synchronise the stream.
+ *   * The library allocates no device memory of its own: all device state (tables, Vegas maps, partial
+ *     sums, results) lives in one workspace the caller allocates and binds (bmc_workspace_query / _bind).
+ *   * Results depend only on (inputs, seed, epoch, iteration indices, Vegas maps); they do not depend on the
+ *     launch mode (batched or per grid point), the launch tuning, or other items in the same call.
+ *   * Work item: (process, observed species, pinned side, term, evaluation grid index).  Its identifier is
+ *         uid = process << 24 | species << 20 | side << 19 | term << 18 | eval_index
+ *     (side 0 = initial state, 1 = final state; term 0 = gain or net, 1 = loss).  Items of a call are
+ *     ordered by uid.  Sample n of iteration `it` of an item draws its D uniforms from Philox4x32-10 with
+ *     key (lo32(seed), hi32(seed)), counters (lo32(n B + b), hi32(n B + b), uid, 64 epoch + it),
+ *     B = ceil(D/4), y = (word + 0.5) 2^-32.
+ */
+#ifndef BOLTZMC_H
+#define BOLTZMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---- */
+#define BMC_OK 0
+#define BMC_EINVAL (-1)   /* bad argument or id */
+#define BMC_ESTATE (-2)   /* f not set, workspace not bound or too small, no processes */
+#define BMC_ERANGE (-3)   /* f <= 0, Fermi-Dirac f >= 1, or an invalid extrapolation fit (Sec. III.B) */
+#define BMC_ENOMEM (-4)   /* bound workspace smaller than the call needs (query again) */
+#define BMC_EHIP (-5)     /* a HIP runtime call failed */
+#define BMC_EUNSUP (-6)   /* valid request that this build does not implement */
+
+/* ---- enumerations ---- */
+#define BMC_MEM_HOST 0
+#define BMC_MEM_DEVICE 1
+
+#define BMC_BOSE 1        /* eta = +1 */
+#define BMC_FERMI (-1)    /* eta = -1 */
+#define BMC_MB 0          /* eta = 0 (no 1 +- f factors) */
+
+#define BMC_GRID_LOG 0
+
+#define BMC_MASS_CONST 0  /* m(t) = m0 */
+#define BMC_MASS_SIN 1    /* m(t) = m0 + A sin(w t) */
+
+#define BMC_EXP_NONE 0
+#define BMC_EXP_RADIATION 1  /* a(t) = a0 (t / t0)^(1/2) */
+
+#define BMC_TERMS_SPLIT 0 /* separate gain and loss integrators (Sec. II.D) */
+#define BMC_TERMS_NET 1   /* one integrator of gain - loss */
+
+#define BMC_SIDES_AUTO 0  /* both sides, or the initial side only for a self-reverse process (Eq. 12) */
+#define BMC_SIDES_IN 1
+#define BMC_SIDES_OUT 2
+#define BMC_SIDES_BOTH 3
+
+#define BMC_FP64 0        /* everything in IEEE double */
+#define BMC_FP32I 1       /* FP32 integrand (f lookups, statistical factor, exponentials) with FP64
+                             kinematics up to the delta argument and FP64 accumulation */
+
+#define BMC_LAUNCH_BATCHED 0  /* all items of a call in one persistent launch per Vegas iteration */
+#define BMC_LAUNCH_PLAIN 1    /* one launch per evaluation grid point per iteration */
+
+#define BMC_EULER 0
+#define BMC_HEUN 1
+
+#define BMC_MAXN 6        /* particles per process (n_in + n_out <= 6, >= 3) */
+#define BMC_MAXD 12       /* 3 (n - 2) */
+#define BMC_MAXSPECIES 16
+#define BMC_MAXBINS 64
+#define BMC_MAXGRID 2048
+#define BMC_MAXITER 64
+
+typedef struct bmc_ctx bmc_ctx;
+
+/* Per-process parameters (Sec. III.A "Processes are registered ..."; Appendix C). */
+typedef struct {
+  double coupling;     /* lambda; |M|^2 = lambda^2 includes the identical-particle symmetry factors */
+  double sigma_E;      /* absolute width of the Gaussian energy delta (Eq. 15), > 0 */
+  double alpha;        /* Vegas damping exponent, in [0, 2] (paper: 0.5) */
+  double e_cut;        /* points with any E_i < e_cut get weight 0 (Appendix A); default 0 */
+  int n_bins;          /* Vegas bins per dimension, 2 .. BMC_MAXBINS (paper/workloads: 50) */
+  int term_mode;       /* BMC_TERMS_SPLIT or BMC_TERMS_NET */
+  int side_mask;       /* BMC_SIDES_* */
+  int eval_stride;     /* evaluate every k-th grid point of the observed species (>= 1) */
+  int64_t n_samples;   /* samples per item per iteration (>= 2) */
+  int n_iter;          /* Vegas iterations per evaluation (1 .. BMC_MAXITER) */
+} bmc_process_params;
+
+/* Options of one evaluation. */
+typedef struct {
+  int64_t n_samples;   /* <= 0: each process's own n_samples */
+  int n_iter;          /* <= 0: each process's own n_iter */
+  int first_iter;      /* Philox iteration index of the first iteration (iterations first_iter .. +n_iter-1) */
+  uint64_t seed;
+  uint32_t epoch;      /* < 2^26 */
+  int precision;       /* BMC_FP64 or BMC_FP32I */
+  int launch;          /* BMC_LAUNCH_BATCHED or BMC_LAUNCH_PLAIN */
+  int freeze_maps;     /* 1: the Vegas maps are used but not adapted */
+  int eval_stride;     /* 0: each process's own stride, skipped nodes filled (linear in ln q; C/f held past
+                          the last evaluated node); k >= 1: every k-th node of every process, no fill */
+} bmc_run_opts;
+
+/* ---- context and workspace ---- */
+
+/* Creates a context on HIP device `device` that launches on `hip_stream` (a hipStream_t; NULL = the null
+ * stream).  The caller keeps the stream alive while the context exists. */
+int bmc_create(bmc_ctx** out, int device, void* hip_stream);
+int bmc_destroy(bmc_ctx* ctx);
+int bmc_set_stream(bmc_ctx* ctx, void* hip_stream);
+
+/* Bytes of device workspace needed by every call with at most `max_samples` samples per item per iteration
+ * and at most `max_iter` iterations (<= 0: the registered processes' own values).  Species and processes
+ * must be registered first; adding any afterwards requires a new query and bind. */
+int bmc_workspace_query(bmc_ctx* ctx, int64_t max_samples, int max_iter, size_t* bytes);
+/* Binds caller-owned device memory (256-byte aligned) of `bytes` bytes.  Rebinding a larger workspace
+ * keeps the library's persistent state (f, maps, time): it is copied on the stream. */
+int bmc_workspace_bind(bmc_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* ---- model ---- */
+
+/* Registers a species on a logarithmic comoving grid of n_grid nodes on [q_min, q_max] (Sec. III.A).
+ * stat: BMC_BOSE / BMC_FERMI / BMC_MB.  Returns its id (0, 1, ...) in *species_id. */
+int bmc_add_species(bmc_ctx* ctx, const char* name, int stat, int grid_kind, int n_grid, double q_min,
+                    double q_max, int* species_id);
+/* Mass of a species: BMC_MASS_CONST (m0) or BMC_MASS_SIN (m0 + A sin(w t)); m(t) >= 0 is required. */
+int bmc_set_mass(bmc_ctx* ctx, int species, int kind, double m0, double A, double w);
+/* Sets f on the species' grid (n values).  Validates f > 0 and, for Fermi-Dirac, f < 1 (BMC_ERANGE). */
+int bmc_set_f(bmc_ctx* ctx, int species, const double* f, int n, int mem);
+/* Copies the current f of a species (n values) to `f`. */
+int bmc_get_f(bmc_ctx* ctx, int species, double* f, int n, int mem);
+
+/* Registers the process in_sp[0..n_in-1] -> out_sp[0..n_out-1] (species ids), 3 <= n_in + n_out <= 6. */
+int bmc_add_process(bmc_ctx* ctx, const int* in_sp, int n_in, const int* out_sp, int n_out,
+                    const bmc_process_params* params, int* process_id);
+int bmc_default_process_params(bmc_process_params* params);
+
+/* Expansion (Sec. III.E): BMC_EXP_NONE (a = 1) or BMC_EXP_RADIATION with a0, t0 > 0. */
+int bmc_set_expansion(bmc_ctx* ctx, int kind, double a0, double t0);
+int bmc_set_time(bmc_ctx* ctx, double t);
+int bmc_get_time(bmc_ctx* ctx, double* t);
+
+/* ---- evaluation ---- */
+
+/* Number of items and of output values bmc_collision produces for (process, species, opts):
+ * process -1 = every process; species -1 = every species (outputs concatenated in species order). */
+int bmc_plan_size(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, int* n_items, int* n_out);
+
+/* Evaluates C and its Monte-Carlo sigma for the selected (process, species) pairs in one call.
+ * Outputs (n_out values each, see bmc_plan_size): with opts->eval_stride >= 1, the values at grid nodes
+ * 0, k, 2k, ... of each selected species in species order; with 0, the full grid of each species (the
+ * per-process strided values filled).  sigma_out may be NULL.  Vegas maps are taken from and stored back to
+ * the context (integrator reuse); maps start uniform. */
+int bmc_collision(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
+                  double* sigma_out, size_t n_out, int mem);
+
+/* Per-item results of the last bmc_collision (items in uid order, n = its n_items): uid, multiplicity-free
+ * estimate Ibar and sigma, and per-iteration I and V (n x n_iter each).  Any pointer may be NULL. */
+int bmc_item_results(bmc_ctx* ctx, uint32_t* uids, double* Ibar, double* sigma, double* I_it, double* V_it,
+                     int n, int n_iter);
+
+/* Vegas map of items (uids[i]), each stored as BMC_MAXD x (n_bins + 1) edges (rows beyond D ignored).
+ * An item that has no map yet reads as the uniform map.  Host memory. */
+int bmc_maps_get(bmc_ctx* ctx, const uint32_t* uids, int n, double* maps);
+int bmc_maps_set(bmc_ctx* ctx, const uint32_t* uids, int n, const double* maps);
+/* Forgets the maps of a process (-1 = all): they restart uniform. */
+int bmc_maps_reset(bmc_ctx* ctx, int process);
+
+/* One Euler or Heun step of every species' f in log space over all processes (Sec. III.C):
+ * dt > 0 fixed, dt <= 0: dt = min(dt_max, eps / max|k1/f|) (Eq. 20).  k1 uses opts->epoch at t, k2 uses
+ * epoch + 1 at t + dt.  Strided processes are filled as in bmc_collision with eval_stride 0.  The time
+ * advances by dt.  *dt_used (may be NULL) receives dt (host, synchronises). */
+int bmc_step(bmc_ctx* ctx, int method, double dt, double eps, double dt_max, const bmc_run_opts* opts,
+             double* dt_used);
+
+/* Captures n_steps Heun/Euler steps (epochs opts->epoch + 2s, + 2s + 1 for step s) into a HIP graph held by
+ * the context.  Time, step size, epoch and a(t), m(t) advance on the device, so each replay continues the
+ * evolution.  bmc_graph_replay launches it on the context stream; bmc_graph_status reports a device-side
+ * error flag set during replays (BMC_ERANGE for an invalid f) and the time reached. */
+int bmc_graph_capture_steps(bmc_ctx* ctx, int n_steps, int method, double dt, double eps, double dt_max,
+                            const bmc_run_opts* opts);
+int bmc_graph_replay(bmc_ctx* ctx);
+int bmc_graph_status(bmc_ctx* ctx, double* t, double* last_dt);
+
+/* ---- differentiation ---- */
+
+/* Vector-Jacobian product of the C of the last-planned items with frozen maps and common random numbers
+ * (the same counters as bmc_collision with these opts and one iteration): given the cotangent v on C_out
+ * (n_out values, layout as bmc_collision), returns dL/df (every species' grid, concatenated),
+ * dL/dcoupling (one per process) and dL/dm0 (one per species). */
+int bmc_vjp(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, const double* v_C,
+            size_t n_out, double* grad_f, double* grad_coupling, double* grad_m0, int mem);
+
+/* ---- measurement and tuning ---- */
+
+/* Enables (on != 0) timing of the sample kernel with HIP events on the context stream (eager launches only;
+ * graph replays are not timed). */
+int bmc_set_timing(bmc_ctx* ctx, int on);
+/* Sum of the timed sample-kernel durations (ms) and number of timed launches since the last reset;
+ * synchronises the stream.  reset != 0 clears the counters after reading. */
+int bmc_get_timing(bmc_ctx* ctx, int reset, double* sample_ms, int* n_launches);
+/* Resident blocks per compute unit of the persistent batched launch (0 = from the LDS need).  Results do not
+ * depend on it. */
+int bmc_set_launch_tuning(bmc_ctx* ctx, int blocks_per_cu);
+
+/* ---- misc ---- */
+const char* bmc_last_error(bmc_ctx* ctx);
+const char* bmc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

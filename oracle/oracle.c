@@ -426,9 +426,14 @@ static double item_integrand(const item_ctx* c, const double* x) {
     py[c->i_cons] = sy;
     pz[c->i_cons] = sz;
   }
-  /* energies */
+  /* energies: E = sqrt(|p|^2 + m^2); an integrated particle's |p| is r/a by construction */
   for (int i = 0; i < n; ++i) {
     double p2 = px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i];
+    for (int k = 0; k < c->n_int; ++k)
+      if (c->integ[k] == i) {
+        double p = x[3 * k] / a;
+        p2 = p * p;
+      }
     E[i] = sqrt(p2 + c->m[i] * c->m[i]);
     if (E[i] < c->P->e_cut) return 0.0;
   }

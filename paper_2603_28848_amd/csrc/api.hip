@@ -1,0 +1,1351 @@
+// api.hip -- C-ABI of libboltzmc: context, workspace, model registration, planner and launch sequencing.
+//
+// The planner turns (process, species, options) into work items (Sec. II.C Eq. 7 / Eq. 12 multiplicities and
+// Appendix A particle roles), units of samples, output slots and the gather table; the launch sequence per
+// evaluation is  next-epoch -> prepare (a(t), m(t), fits, FP32 f) -> [sample -> reduce/adapt] x n_iter ->
+// combine -> gather.  All device memory is carved out of the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/boltzmc.h"
+#include "internal.h"
+#include "kernels.h"
+
+using namespace bmc;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Species {
+  std::string name;
+  int stat = 0;
+  int n = 0;
+  double q_min = 0, q_max = 0;
+  int mass_kind = 0;
+  double m0 = 0, A = 0, w = 0;
+  std::vector<double> f;  // host mirror (authoritative until bound; refreshed from the device on demand)
+  bool f_set = false;
+  int64_t f_off = 0;
+};
+
+struct Process {
+  int n_in = 0, n_out = 0;
+  int sp[kMaxN] = {0};
+  bmc_process_params prm{};
+};
+
+struct Plan {
+  // key
+  int process = -2, species = -2, stride = -1;
+  int64_t n_samples = -1;
+  int n_iter = -1;
+  // content
+  std::vector<ItemRec> items;
+  std::vector<int> nodes_of_item;
+  std::vector<Task> tasks_batched;            // item-major
+  std::vector<Task> tasks_plain;              // node-major
+  std::vector<int> plain_node_begin;          // ranges into tasks_plain per distinct node
+  std::vector<int64_t> unit_base;
+  std::vector<int> slot_begin, slot_items;
+  std::vector<GatherEntry> gather;
+  std::vector<GatherProc> gproc;
+  std::vector<int> tasks_per_iter;            // batched tasks with item n_iter > k (prefix of item-major list)
+  int n_iter_max = 0;
+  int n_slots = 0;
+  int n_out = 0;
+  int nint_mask = 0;
+  int64_t n_units = 0;
+  int64_t n_parts = 0;   // doubles
+  int lds64 = 0, lds32 = 0;
+  std::vector<int> new_maps;  // item indices whose maps need initialising
+  // device pointers (inside the scratch region)
+  ItemRec* d_items = nullptr;
+  Task* d_tb = nullptr;
+  Task* d_tp = nullptr;
+  int64_t* d_unit_base = nullptr;
+  double* d_unit_s = nullptr;
+  double* d_parts = nullptr;
+  double* d_res_I = nullptr;
+  double* d_res_V = nullptr;
+  double* d_item_Ibar = nullptr;
+  double* d_item_sig = nullptr;
+  int* d_slot_begin = nullptr;
+  int* d_slot_items = nullptr;
+  double* d_slot_C = nullptr;
+  double* d_slot_S2 = nullptr;
+  GatherEntry* d_gather = nullptr;
+  GatherProc* d_gproc = nullptr;
+  double* d_out_C = nullptr;
+  double* d_out_S = nullptr;
+  int* d_new = nullptr;
+  size_t scratch_bytes = 0;
+  bool uploaded = false;
+};
+
+}  // namespace
+
+struct bmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::vector<Species> sp;
+  std::vector<Process> pr;
+  int expansion = BMC_EXP_NONE;
+  double a0 = 1.0, t0 = 1.0;
+  double t = 0.0;  // host mirror of the time (authoritative while unbound)
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool bound = false;
+  size_t off_state = 0, off_spec = 0, off_f64 = 0, off_f32 = 0, off_f0 = 0, off_k1 = 0, off_k2 = 0, off_sig = 0,
+         off_maps = 0, persist_bytes = 0;
+  int64_t n_f = 0;
+  int max_slots = 0;
+  int n_sp_bound = -1, n_pr_bound = -1;
+  std::unordered_map<uint32_t, int> slot_of_uid;
+  Plan plan;       // last collision plan
+  Plan step_plan;  // plan of bmc_step / graphs (all processes, all species, own strides)
+  int last_n_iter = 0;
+  std::string err;
+  // graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  // tuning
+  int blocks_per_cu = 0;  // 0: from occupancy
+  int n_cu = 0;
+  // optional timing of the sample kernel (eager launches only)
+  bool timing = false;
+  bool capturing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double timed_ms = 0.0;
+  int timed_launches = 0;
+
+  DevState* st() { return reinterpret_cast<DevState*>(ws + off_state); }
+  SpecDev* spec() { return reinterpret_cast<SpecDev*>(ws + off_spec); }
+  double* f64() { return reinterpret_cast<double*>(ws + off_f64); }
+  float* f32() { return reinterpret_cast<float*>(ws + off_f32); }
+  double* f0() { return reinterpret_cast<double*>(ws + off_f0); }
+  double* k1() { return reinterpret_cast<double*>(ws + off_k1); }
+  double* k2() { return reinterpret_cast<double*>(ws + off_k2); }
+  double* sig() { return reinterpret_cast<double*>(ws + off_sig); }
+  double* maps() { return reinterpret_cast<double*>(ws + off_maps); }
+};
+
+namespace {
+
+int fail(bmc_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, x)                                                                         \
+  do {                                                                                         \
+    hipError_t e_ = (x);                                                                       \
+    if (e_ != hipSuccess) return fail(ctx, BMC_EHIP, std::string(#x ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_self_reverse(const Process& P) {
+  if (P.n_in != P.n_out) return false;
+  std::vector<int> a(P.sp, P.sp + P.n_in), b(P.sp + P.n_in, P.sp + P.n_in + P.n_out);
+  std::sort(a.begin(), a.end());
+  std::sort(b.begin(), b.end());
+  return a == b;
+}
+
+int count_on_side(const Process& P, int a, int side) {
+  int lo = side == 0 ? 0 : P.n_in, hi = side == 0 ? P.n_in : P.n_in + P.n_out, c = 0;
+  for (int i = lo; i < hi; ++i) c += P.sp[i] == a;
+  return c;
+}
+
+// Multiplicity of the side evaluation (0: not evaluated).
+int multiplicity(const Process& P, int a, int side) {
+  const int c = count_on_side(P, a, side);
+  if (c == 0) return 0;
+  const int mask = P.prm.side_mask;
+  if (mask == BMC_SIDES_AUTO) return (is_self_reverse(P) && side == 1) ? 0 : c;
+  return (mask & (1 << side)) ? c : 0;
+}
+
+// Observed: lowest index of species a on the side; conserved: lowest other index on the fewer-particle side
+// (asymmetric) or on the observed side (symmetric), else the lowest other index on the opposite side.
+bool assign_roles(const Process& P, int a, int side, int* obs, int* cons, int* integ) {
+  const int n = P.n_in + P.n_out;
+  auto range = [&](int s, int* lo, int* hi) {
+    *lo = s == 0 ? 0 : P.n_in;
+    *hi = s == 0 ? P.n_in : n;
+  };
+  int lo, hi;
+  range(side, &lo, &hi);
+  *obs = -1;
+  for (int i = lo; i < hi && *obs < 0; ++i)
+    if (P.sp[i] == a) *obs = i;
+  if (*obs < 0) return false;
+  const int cside = P.n_in != P.n_out ? (P.n_in < P.n_out ? 0 : 1) : side;
+  *cons = -1;
+  range(cside, &lo, &hi);
+  for (int i = lo; i < hi && *cons < 0; ++i)
+    if (i != *obs) *cons = i;
+  if (*cons < 0) {
+    range(1 - cside, &lo, &hi);
+    for (int i = lo; i < hi && *cons < 0; ++i)
+      if (i != *obs) *cons = i;
+  }
+  if (*cons < 0) return false;
+  int k = 0;
+  for (int i = 0; i < n; ++i)
+    if (i != *obs && i != *cons) integ[k++] = i;
+  return true;
+}
+
+int unit_size_for(int64_t N) {
+  int64_t target = (N + 63) / 64;
+  int64_t u = 4096;
+  while (u < target && u < 65536) u <<= 1;
+  return (int)u;
+}
+
+double grid_node(const Species& S, int j) {
+  const double lq0 = std::log(S.q_min);
+  const double h = (std::log(S.q_max) - lq0) / (double)(S.n - 1);
+  return std::exp(lq0 + h * (double)j);
+}
+
+// Persistent layout from the registrations.
+void layout_persistent(bmc_ctx* c) {
+  size_t o = 0;
+  c->off_state = o;
+  o = align_up(o + sizeof(DevState));
+  c->off_spec = o;
+  o = align_up(o + sizeof(SpecDev) * kMaxSpecies);
+  int64_t nf = 0;
+  for (auto& s : c->sp) {
+    s.f_off = nf;
+    nf += s.n;
+  }
+  c->n_f = nf;
+  c->off_f64 = o;
+  o = align_up(o + 8 * nf);
+  c->off_f32 = o;
+  o = align_up(o + 4 * nf);
+  c->off_f0 = o;
+  o = align_up(o + 8 * nf);
+  c->off_k1 = o;
+  o = align_up(o + 8 * nf);
+  c->off_k2 = o;
+  o = align_up(o + 8 * nf);
+  c->off_sig = o;
+  o = align_up(o + 8 * nf);
+  // map slots: every item any call can plan (stride 1, both sides, both terms)
+  int slots = 0;
+  for (size_t p = 0; p < c->pr.size(); ++p)
+    for (size_t a = 0; a < c->sp.size(); ++a)
+      for (int side = 0; side < 2; ++side)
+        if (multiplicity(c->pr[p], (int)a, side) > 0)
+          slots += c->sp[a].n * (c->pr[p].prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+  c->max_slots = slots;
+  c->off_maps = o;
+  o = align_up(o + sizeof(double) * (size_t)kSlotDoubles * (size_t)slots);
+  c->persist_bytes = o;
+}
+
+SpecDev make_spec(const Species& S) {
+  SpecDev d{};
+  d.stat = S.stat;
+  d.n = S.n;
+  d.q_min = S.q_min;
+  d.q_max = S.q_max;
+  d.lq0 = std::log(S.q_min);
+  d.inv_h = (double)(S.n - 1) / (std::log(S.q_max) - d.lq0);
+  d.mass_kind = S.mass_kind;
+  d.m0 = S.m0;
+  d.A = S.A;
+  d.w = S.w;
+  d.f_off = S.f_off;
+  return d;
+}
+
+int upload_model(bmc_ctx* c) {
+  std::vector<SpecDev> sd(kMaxSpecies);
+  for (size_t i = 0; i < c->sp.size(); ++i) sd[i] = make_spec(c->sp[i]);
+  HIPCHK(c, hipMemcpyAsync(c->spec(), sd.data(), sizeof(SpecDev) * kMaxSpecies, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BMC_OK;
+}
+
+int upload_state(bmc_ctx* c) {
+  DevState s{};
+  s.t = c->t;
+  s.a = 1.0;
+  s.expansion = c->expansion;
+  s.expansion_a0 = c->a0;
+  s.expansion_t0 = c->t0;
+  s.n_species = (int)c->sp.size();
+  for (size_t i = 0; i < c->sp.size(); ++i) s.m[i] = c->sp[i].m0;
+  HIPCHK(c, hipMemcpyAsync(c->st(), &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BMC_OK;
+}
+
+int read_state(bmc_ctx* c, DevState* s) {
+  HIPCHK(c, hipMemcpyAsync(s, c->st(), sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BMC_OK;
+}
+
+int check_ready(bmc_ctx* c) {
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  if ((int)c->sp.size() != c->n_sp_bound || (int)c->pr.size() != c->n_pr_bound)
+    return fail(c, BMC_ESTATE, "species or processes changed since the workspace was bound; query and bind again");
+  if (c->pr.empty()) return fail(c, BMC_ESTATE, "no processes");
+  for (auto& s : c->sp)
+    if (!s.f_set) return fail(c, BMC_ESTATE, "f not set for species '" + s.name + "'");
+  return BMC_OK;
+}
+
+// ---------------------------------------------------------------------------------------------- planner
+struct PlanKey {
+  int process, species, stride;
+  int64_t n_samples;
+  int n_iter;
+};
+
+int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
+  Plan Q;
+  Q.process = k.process;
+  Q.species = k.species;
+  Q.stride = k.stride;
+  Q.n_samples = k.n_samples;
+  Q.n_iter = k.n_iter;
+  const int np = (int)c->pr.size(), ns = (int)c->sp.size();
+  if (k.process < -1 || k.process >= np) return fail(c, BMC_EINVAL, "bad process id");
+  if (k.species < -1 || k.species >= ns) return fail(c, BMC_EINVAL, "bad species id");
+  // per (process, species): slot base for node 0 and its stride
+  std::vector<std::vector<int>> slot_base(np, std::vector<int>(ns, -1));
+  std::vector<std::vector<int>> pstride(np, std::vector<int>(ns, 0));
+  int64_t part = 0, units = 0;
+  int res = 0;
+  std::vector<std::vector<int>> slot_lists;
+  for (int p = 0; p < np; ++p) {
+    if (k.process >= 0 && p != k.process) continue;
+    const Process& Pr = c->pr[p];
+    const int n = Pr.n_in + Pr.n_out;
+    const int nint = n - 2;
+    const int D = 3 * nint;
+    const int nb = Pr.prm.n_bins;
+    const int stride = k.stride > 0 ? k.stride : Pr.prm.eval_stride;
+    const int64_t N = k.n_samples > 0 ? k.n_samples : Pr.prm.n_samples;
+    const int nit = k.n_iter > 0 ? k.n_iter : Pr.prm.n_iter;
+    if (N < 2) return fail(c, BMC_EINVAL, "n_samples < 2");
+    if (nit < 1 || nit > kMaxIter) return fail(c, BMC_EINVAL, "n_iter out of range");
+    for (int a = 0; a < ns; ++a) {
+      if (k.species >= 0 && a != k.species) continue;
+      const Species& S = c->sp[a];
+      bool any = false;
+      for (int side = 0; side < 2; ++side) any |= multiplicity(Pr, a, side) > 0;
+      if (!any) continue;
+      slot_base[p][a] = (int)slot_lists.size();
+      pstride[p][a] = stride;
+      const int n_nodes = (S.n + stride - 1) / stride;
+      const int first_slot = (int)slot_lists.size();
+      slot_lists.resize(slot_lists.size() + n_nodes);
+      for (int side = 0; side < 2; ++side) {
+        const int mult = multiplicity(Pr, a, side);
+        if (mult == 0) continue;
+        int obs, cons, integ[kMaxInt];
+        if (!assign_roles(Pr, a, side, &obs, &cons, integ)) return fail(c, BMC_EINVAL, "role assignment failed");
+        const int n_terms = Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2;
+        for (int term = 0; term < n_terms; ++term) {
+          for (int i = 0; i < S.n; i += stride) {
+            ItemRec it{};
+            it.uid = ((uint32_t)p << 24) | ((uint32_t)a << 20) | ((uint32_t)side << 19) | ((uint32_t)term << 18) |
+                     (uint32_t)i;
+            it.proc = p;
+            it.nint = nint;
+            it.D = D;
+            it.nb = nb;
+            it.term = term;
+            it.net = Pr.prm.term_mode == BMC_TERMS_NET;
+            it.eval_idx = i;
+            it.n_iter = nit;
+            it.q_obs = grid_node(S, i);
+            it.obs_species = a;
+            it.mult = mult;
+            it.N = N;
+            it.unit_size = unit_size_for(N);
+            it.n_units = (int)((N + it.unit_size - 1) / it.unit_size);
+            it.part_off = part;
+            part += (int64_t)it.n_units * 2 * D * nb;
+            it.res_off = res++;
+            it.sign = (!it.net && term == 1) ? -1 : 1;
+            it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
+            it.inv2s2 = 1.0 / (2.0 * Pr.prm.sigma_E * Pr.prm.sigma_E);
+            it.dnorm = 1.0 / (Pr.prm.sigma_E * std::sqrt(2.0 * M_PI));
+            it.e_cut = Pr.prm.e_cut;
+            it.twopi_pow = std::pow(2.0 * M_PI, (double)(3 * (n - 1) - 4));
+            it.alpha = Pr.prm.alpha;
+            // roles
+            int pos[kMaxN];
+            for (int r = 0; r < nint; ++r) pos[r] = integ[r];
+            pos[nint] = cons;
+            pos[nint + 1] = obs;
+            it.n_tab = 0;
+            for (int r = 0; r < nint + 2; ++r) {
+              const int q = pos[r];
+              it.r_species[r] = Pr.sp[q];
+              it.r_in[r] = q < Pr.n_in ? 1 : 0;
+              it.r_obsside[r] = ((q < Pr.n_in) ? 0 : 1) == side ? 1 : 0;
+              it.r_tab[r] = 0;
+              if (r <= nint) {  // integrated and conserved particles read tables
+                int slot = -1;
+                for (int t = 0; t < it.n_tab; ++t)
+                  if (it.tab_species[t] == Pr.sp[q]) slot = t;
+                if (slot < 0) {
+                  slot = it.n_tab++;
+                  it.tab_species[slot] = Pr.sp[q];
+                }
+                it.r_tab[r] = slot;
+              }
+            }
+            it.cons_in = cons < Pr.n_in ? 1 : 0;
+            it.out_slot = first_slot + i / stride;
+            // map slot
+            auto f = c->slot_of_uid.find(it.uid);
+            int ms;
+            if (f == c->slot_of_uid.end()) {
+              ms = (int)c->slot_of_uid.size();
+              if (ms >= c->max_slots) return fail(c, BMC_ENOMEM, "map slots exhausted");
+              c->slot_of_uid[it.uid] = ms;
+              Q.new_maps.push_back((int)Q.items.size());
+            } else {
+              ms = f->second;
+            }
+            it.map_off = (int64_t)ms * kSlotDoubles;
+            Q.nint_mask |= 1 << (nint - 1);
+            Q.n_iter_max = std::max(Q.n_iter_max, nit);
+            slot_lists[it.out_slot].push_back((int)Q.items.size());
+            Q.items.push_back(it);
+          }
+        }
+      }
+    }
+  }
+  if (Q.items.empty()) return fail(c, BMC_EINVAL, "the selection has no work items");
+  // units, tasks
+  Q.unit_base.resize(Q.items.size());
+  for (size_t i = 0; i < Q.items.size(); ++i) {
+    Q.unit_base[i] = units;
+    units += Q.items[i].n_units;
+  }
+  Q.n_units = units;
+  Q.n_parts = part;
+  // batched: item-major; items with more iterations first so that every iteration's tasks are a prefix
+  std::vector<int> order(Q.items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return Q.items[x].n_iter > Q.items[y].n_iter; });
+  for (int i : order)
+    for (int u = 0; u < Q.items[i].n_units; ++u) Q.tasks_batched.push_back(Task{i, u});
+  Q.tasks_per_iter.assign(Q.n_iter_max, 0);
+  for (int kk = 0; kk < Q.n_iter_max; ++kk) {
+    int cnt = 0;
+    for (int i : order)
+      if (Q.items[i].n_iter > kk) cnt += Q.items[i].n_units;
+    Q.tasks_per_iter[kk] = cnt;
+  }
+  // plain: node-major
+  {
+    std::vector<int> byn(Q.items.size());
+    for (size_t i = 0; i < byn.size(); ++i) byn[i] = (int)i;
+    std::stable_sort(byn.begin(), byn.end(),
+                     [&](int x, int y) { return Q.items[x].eval_idx < Q.items[y].eval_idx; });
+    int last = -1;
+    for (int i : byn) {
+      if (Q.items[i].eval_idx != last) {
+        Q.plain_node_begin.push_back((int)Q.tasks_plain.size());
+        last = Q.items[i].eval_idx;
+      }
+      for (int u = 0; u < Q.items[i].n_units; ++u) Q.tasks_plain.push_back(Task{i, u});
+    }
+    Q.plain_node_begin.push_back((int)Q.tasks_plain.size());
+  }
+  // slots
+  Q.n_slots = (int)slot_lists.size();
+  Q.slot_begin.push_back(0);
+  for (auto& l : slot_lists) {
+    for (int i : l) Q.slot_items.push_back(i);
+    Q.slot_begin.push_back((int)Q.slot_items.size());
+  }
+  // gather
+  for (int a = 0; a < ns; ++a) {
+    if (k.species >= 0 && a != k.species) continue;
+    const Species& S = c->sp[a];
+    const int ostride = k.stride > 0 ? k.stride : 1;
+    for (int j = 0; j < S.n; j += ostride) {
+      GatherEntry g{};
+      g.species = a;
+      g.node = j;
+      g.first = (int)Q.gproc.size();
+      for (int p = 0; p < np; ++p) {
+        if (slot_base[p][a] < 0) continue;
+        GatherProc gp{};
+        gp.slot_base = slot_base[p][a];
+        gp.stride = pstride[p][a];
+        gp.last = ((S.n - 1) / gp.stride) * gp.stride;
+        gp.fill = k.stride > 0 ? 0 : 1;
+        Q.gproc.push_back(gp);
+      }
+      g.count = (int)Q.gproc.size() - g.first;
+      Q.gather.push_back(g);
+    }
+  }
+  Q.n_out = (int)Q.gather.size();
+  // LDS bytes
+  for (auto& it : Q.items) {
+    int n_max = 0;
+    for (int t = 0; t < it.n_tab; ++t) n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
+    Q.lds64 = std::max(Q.lds64, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0));
+    Q.lds32 = std::max(Q.lds32, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
+  }
+  if (Q.lds64 > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
+  // scratch sizes
+  size_t s = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = s;
+    s = align_up(s + bytes);
+    return o;
+  };
+  const size_t nI = Q.items.size();
+  size_t o_items = take(sizeof(ItemRec) * nI), o_tb = take(sizeof(Task) * Q.tasks_batched.size()),
+         o_tp = take(sizeof(Task) * Q.tasks_plain.size()), o_ub = take(8 * nI), o_us = take(16 * (size_t)units),
+         o_parts = take(8 * (size_t)part), o_rI = take(8 * kMaxIter * nI), o_rV = take(8 * kMaxIter * nI),
+         o_ib = take(8 * nI), o_is = take(8 * nI), o_sb = take(4 * (Q.slot_begin.size())),
+         o_si = take(4 * std::max<size_t>(1, Q.slot_items.size())), o_sC = take(8 * Q.n_slots),
+         o_sS = take(8 * Q.n_slots), o_g = take(sizeof(GatherEntry) * Q.gather.size()),
+         o_gp = take(sizeof(GatherProc) * std::max<size_t>(1, Q.gproc.size())), o_oC = take(8 * Q.n_out),
+         o_oS = take(8 * Q.n_out), o_new = take(4 * std::max<size_t>(1, Q.new_maps.size()));
+  Q.scratch_bytes = s;
+  char* base = c->ws ? c->ws + c->persist_bytes : nullptr;
+  if (base) {
+    Q.d_items = reinterpret_cast<ItemRec*>(base + o_items);
+    Q.d_tb = reinterpret_cast<Task*>(base + o_tb);
+    Q.d_tp = reinterpret_cast<Task*>(base + o_tp);
+    Q.d_unit_base = reinterpret_cast<int64_t*>(base + o_ub);
+    Q.d_unit_s = reinterpret_cast<double*>(base + o_us);
+    Q.d_parts = reinterpret_cast<double*>(base + o_parts);
+    Q.d_res_I = reinterpret_cast<double*>(base + o_rI);
+    Q.d_res_V = reinterpret_cast<double*>(base + o_rV);
+    Q.d_item_Ibar = reinterpret_cast<double*>(base + o_ib);
+    Q.d_item_sig = reinterpret_cast<double*>(base + o_is);
+    Q.d_slot_begin = reinterpret_cast<int*>(base + o_sb);
+    Q.d_slot_items = reinterpret_cast<int*>(base + o_si);
+    Q.d_slot_C = reinterpret_cast<double*>(base + o_sC);
+    Q.d_slot_S2 = reinterpret_cast<double*>(base + o_sS);
+    Q.d_gather = reinterpret_cast<GatherEntry*>(base + o_g);
+    Q.d_gproc = reinterpret_cast<GatherProc*>(base + o_gp);
+    Q.d_out_C = reinterpret_cast<double*>(base + o_oC);
+    Q.d_out_S = reinterpret_cast<double*>(base + o_oS);
+    Q.d_new = reinterpret_cast<int*>(base + o_new);
+  }
+  *P = std::move(Q);
+  return BMC_OK;
+}
+
+// Worst-case scratch for the registered model.
+size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
+  size_t s = 0;
+  size_t items = 0, units = 0, part = 0, slots = 0, outs = 0, tasks = 0;
+  for (auto& Pr : c->pr) {
+    const int n = Pr.n_in + Pr.n_out;
+    const int D = 3 * (n - 2);
+    const int64_t N = std::max<int64_t>(max_samples > 0 ? max_samples : 0, Pr.prm.n_samples);
+    const int U = unit_size_for(N);
+    const int64_t nu = (N + U - 1) / U;
+    for (size_t a = 0; a < c->sp.size(); ++a) {
+      int sides = 0;
+      for (int side = 0; side < 2; ++side) sides += multiplicity(Pr, (int)a, side) > 0;
+      if (!sides) continue;
+      const size_t ni = (size_t)c->sp[a].n * sides * (Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+      items += ni;
+      units += ni * nu;
+      tasks += ni * nu;
+      part += ni * nu * 2 * D * Pr.prm.n_bins;
+      slots += c->sp[a].n;
+    }
+  }
+  for (auto& S : c->sp) outs += S.n;
+  (void)max_iter;
+  s += align_up(sizeof(ItemRec) * items) + 2 * align_up(sizeof(Task) * tasks) + align_up(8 * items) +
+       align_up(16 * units) + align_up(8 * part) + 2 * align_up(8 * kMaxIter * items) + 2 * align_up(8 * items) +
+       align_up(4 * (slots + 1)) + align_up(4 * items) + 2 * align_up(8 * slots) +
+       align_up(sizeof(GatherEntry) * outs) + align_up(sizeof(GatherProc) * outs * std::max<size_t>(1, c->pr.size())) +
+       2 * align_up(8 * outs) + align_up(4 * items) + 64 * kAlign;
+  return s;
+}
+
+int upload_plan(bmc_ctx* c, Plan& P) {
+  if (c->persist_bytes + P.scratch_bytes > c->ws_bytes)
+    return fail(c, BMC_ENOMEM, "workspace too small for this call: need " +
+                                   std::to_string(c->persist_bytes + P.scratch_bytes) + " bytes");
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(P.d_items, P.items.data(), sizeof(ItemRec) * P.items.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_tb, P.tasks_batched.data(), sizeof(Task) * P.tasks_batched.size(),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_tp, P.tasks_plain.data(), sizeof(Task) * P.tasks_plain.size(), hipMemcpyHostToDevice,
+                           s));
+  HIPCHK(c, hipMemcpyAsync(P.d_unit_base, P.unit_base.data(), 8 * P.unit_base.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_slot_begin, P.slot_begin.data(), 4 * P.slot_begin.size(), hipMemcpyHostToDevice, s));
+  if (!P.slot_items.empty())
+    HIPCHK(c, hipMemcpyAsync(P.d_slot_items, P.slot_items.data(), 4 * P.slot_items.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_gather, P.gather.data(), sizeof(GatherEntry) * P.gather.size(), hipMemcpyHostToDevice,
+                           s));
+  if (!P.gproc.empty())
+    HIPCHK(c, hipMemcpyAsync(P.d_gproc, P.gproc.data(), sizeof(GatherProc) * P.gproc.size(), hipMemcpyHostToDevice,
+                             s));
+  if (!P.new_maps.empty()) {
+    HIPCHK(c, hipMemcpyAsync(P.d_new, P.new_maps.data(), 4 * P.new_maps.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_init_maps(P.d_items, P.d_new, (int)P.new_maps.size(), c->spec(), c->maps(), s));
+    P.new_maps.clear();
+  }
+  HIPCHK(c, hipStreamSynchronize(s));
+  P.uploaded = true;
+  return BMC_OK;
+}
+
+int grid_for(bmc_ctx* c, int precision, int lds, int mask) {
+  if (c->n_cu <= 0) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, c->device) != hipSuccess) return 256;
+    c->n_cu = prop.multiProcessorCount;
+  }
+  int per_cu = c->blocks_per_cu;
+  if (per_cu <= 0) {
+    // LDS-limited residency (160 KB per CU), at most 8 blocks of 256 threads
+    per_cu = std::max(1, std::min(8, (160 * 1024) / std::max(1, lds)));
+    (void)precision;
+    (void)mask;
+  }
+  return c->n_cu * per_cu;
+}
+
+// Enqueues one evaluation of plan P (all iterations, combine, gather) on the context stream.
+hipError_t timed_sample(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
+  if (!c->timing || c->capturing) return launch_sample(L, s);
+  hipEvent_t a, b;
+  hipError_t e = hipEventCreate(&a);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&b);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = launch_sample(L, s);
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  c->ev.push_back({a, b});
+  return e;
+}
+
+int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, double* out_S) {
+  hipStream_t s = c->stream;
+  HIPCHK(c, launch_next_epoch(c->st(), s));
+  HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
+  SampleLaunch L{};
+  L.items = P.d_items;
+  L.spec = c->spec();
+  L.f64 = c->f64();
+  L.f32 = c->f32();
+  L.st = c->st();
+  L.maps = c->maps();
+  L.unit_s = P.d_unit_s;
+  L.parts = P.d_parts;
+  L.unit_base = P.d_unit_base;
+  L.seed_lo = (uint32_t)o.seed;
+  L.seed_hi = (uint32_t)(o.seed >> 32);
+  L.nint_mask = P.nint_mask;
+  L.precision = o.precision;
+  L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
+  for (int k = 0; k < P.n_iter_max; ++k) {
+    L.it = o.first_iter + k;
+    if (o.launch == BMC_LAUNCH_PLAIN) {
+      L.tasks = P.d_tp;
+      for (size_t g = 0; g + 1 < P.plain_node_begin.size(); ++g) {
+        L.task_begin = P.plain_node_begin[g];
+        L.n_tasks = P.plain_node_begin[g + 1] - P.plain_node_begin[g];
+        L.grid = L.n_tasks;
+        HIPCHK(c, timed_sample(c, L, s));
+      }
+    } else {
+      L.tasks = P.d_tb;
+      L.task_begin = 0;
+      L.n_tasks = P.tasks_per_iter[k];
+      L.grid = std::min(L.n_tasks, grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask));
+      HIPCHK(c, timed_sample(c, L, s));
+    }
+    HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_unit_s, P.d_unit_base, P.d_parts,
+                                  P.d_res_I, P.d_res_V, k, c->maps(), o.freeze_maps, s));
+  }
+  HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, P.n_iter_max, P.d_item_Ibar,
+                           P.d_item_sig, P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));
+  HIPCHK(c, launch_gather(P.d_gather, P.n_out, P.d_gproc, P.d_slot_C, P.d_slot_S2, c->spec(), c->f64(), out_C, out_S,
+                          s));
+  return BMC_OK;
+}
+
+int check_opts(bmc_ctx* c, const bmc_run_opts* o) {
+  if (!o) return fail(c, BMC_EINVAL, "opts is NULL");
+  if (o->precision != BMC_FP64 && o->precision != BMC_FP32I) return fail(c, BMC_EINVAL, "bad precision");
+  if (o->launch != BMC_LAUNCH_BATCHED && o->launch != BMC_LAUNCH_PLAIN) return fail(c, BMC_EINVAL, "bad launch");
+  if (o->epoch >= (1u << 26)) return fail(c, BMC_EINVAL, "epoch >= 2^26");
+  if (o->first_iter < 0 || o->eval_stride < 0) return fail(c, BMC_EINVAL, "negative first_iter or eval_stride");
+  return BMC_OK;
+}
+
+int get_plan(bmc_ctx* c, Plan& slot, int process, int species, const bmc_run_opts* o) {
+  PlanKey k{process, species, o->eval_stride, o->n_samples, o->n_iter};
+  const bool same = slot.process == k.process && slot.species == k.species && slot.stride == k.stride &&
+                    slot.n_samples == k.n_samples && slot.n_iter == k.n_iter && slot.uploaded;
+  if (!same) {
+    int rc = build_plan(c, k, &slot);
+    if (rc) {
+      slot = Plan();
+      return rc;
+    }
+  }
+  int nit_max = slot.n_iter_max;
+  if (o->first_iter + nit_max > kMaxIter) return fail(c, BMC_EINVAL, "first_iter + n_iter > 64");
+  if (!slot.uploaded || !slot.new_maps.empty()) return upload_plan(c, slot);
+  return BMC_OK;
+}
+
+int finish_check(bmc_ctx* c) {
+  DevState s;
+  int rc = read_state(c, &s);
+  if (rc) return rc;
+  if (s.err) {
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->st()->err, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return fail(c, BMC_ERANGE, "invalid distribution table (f <= 0, Fermi-Dirac f >= 1 or invalid extrapolation fit)");
+  }
+  return BMC_OK;
+}
+
+}  // namespace
+
+// ================================================================================================ C-ABI
+extern "C" {
+
+int bmc_create(bmc_ctx** out, int device, void* hip_stream) {
+  if (!out) return BMC_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return BMC_EINVAL;
+  bmc_ctx* c = new (std::nothrow) bmc_ctx();
+  if (!c) return BMC_ENOMEM;
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BMC_EHIP;
+  }
+  *out = c;
+  return BMC_OK;
+}
+
+int bmc_destroy(bmc_ctx* c) {
+  if (!c) return BMC_EINVAL;
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  delete c;
+  return BMC_OK;
+}
+
+int bmc_set_stream(bmc_ctx* c, void* hip_stream) {
+  if (!c) return BMC_EINVAL;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return BMC_OK;
+}
+
+int bmc_default_process_params(bmc_process_params* p) {
+  if (!p) return BMC_EINVAL;
+  p->coupling = 1.0;
+  p->sigma_E = 0.01;
+  p->alpha = 0.5;
+  p->e_cut = 0.0;
+  p->n_bins = 50;
+  p->term_mode = BMC_TERMS_SPLIT;
+  p->side_mask = BMC_SIDES_AUTO;
+  p->eval_stride = 1;
+  p->n_samples = 1000000;
+  p->n_iter = 2;
+  return BMC_OK;
+}
+
+int bmc_add_species(bmc_ctx* c, const char* name, int stat, int grid_kind, int n_grid, double q_min, double q_max,
+                    int* species_id) {
+  if (!c) return BMC_EINVAL;
+  if (stat != BMC_BOSE && stat != BMC_FERMI && stat != BMC_MB) return fail(c, BMC_EINVAL, "bad statistics");
+  if (grid_kind != BMC_GRID_LOG) return fail(c, BMC_EUNSUP, "only logarithmic grids are implemented");
+  if (n_grid < 10 || n_grid > BMC_MAXGRID) return fail(c, BMC_EINVAL, "n_grid must be in [10, 2048]");
+  if (!(q_min > 0.0) || !(q_max > q_min) || !std::isfinite(q_max)) return fail(c, BMC_EINVAL, "bad momentum range");
+  if ((int)c->sp.size() >= kMaxSpecies) return fail(c, BMC_EINVAL, "too many species");
+  Species s;
+  s.name = name ? name : "";
+  s.stat = stat;
+  s.n = n_grid;
+  s.q_min = q_min;
+  s.q_max = q_max;
+  s.m0 = 0.0;
+  s.f.assign(n_grid, 0.0);
+  c->sp.push_back(s);
+  if (species_id) *species_id = (int)c->sp.size() - 1;
+  return BMC_OK;
+}
+
+int bmc_set_mass(bmc_ctx* c, int species, int kind, double m0, double A, double w) {
+  if (!c) return BMC_EINVAL;
+  if (species < 0 || species >= (int)c->sp.size()) return fail(c, BMC_EINVAL, "bad species id");
+  if (kind != BMC_MASS_CONST && kind != BMC_MASS_SIN) return fail(c, BMC_EINVAL, "bad mass kind");
+  if (!(m0 >= 0.0) || !std::isfinite(A) || !std::isfinite(w) || (kind == BMC_MASS_SIN && m0 - std::fabs(A) < 0.0))
+    return fail(c, BMC_EINVAL, "mass must stay non-negative");
+  Species& s = c->sp[species];
+  s.mass_kind = kind;
+  s.m0 = m0;
+  s.A = kind == BMC_MASS_SIN ? A : 0.0;
+  s.w = kind == BMC_MASS_SIN ? w : 0.0;
+  if (c->bound && species < c->n_sp_bound) {
+    int rc = upload_model(c);
+    if (rc) return rc;
+  }
+  return BMC_OK;
+}
+
+int bmc_set_f(bmc_ctx* c, int species, const double* f, int n, int mem) {
+  if (!c || !f) return BMC_EINVAL;
+  if (species < 0 || species >= (int)c->sp.size()) return fail(c, BMC_EINVAL, "bad species id");
+  Species& s = c->sp[species];
+  if (n != s.n) return fail(c, BMC_EINVAL, "n does not match the grid");
+  std::vector<double> h(n);
+  if (mem == BMC_MEM_DEVICE) {
+    HIPCHK(c, hipMemcpyAsync(h.data(), f, 8 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::memcpy(h.data(), f, 8 * n);
+  }
+  for (int j = 0; j < n; ++j) {
+    if (!(h[j] > 0.0) || !std::isfinite(h[j])) return fail(c, BMC_ERANGE, "f must be positive and finite");
+    if (s.stat == BMC_FERMI && !(h[j] < 1.0)) return fail(c, BMC_ERANGE, "Fermi-Dirac f must be below 1");
+  }
+  s.f = h;
+  s.f_set = true;
+  if (c->bound && species < c->n_sp_bound) {
+    HIPCHK(c, hipMemcpyAsync(c->f64() + s.f_off, s.f.data(), 8 * n, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return BMC_OK;
+}
+
+int bmc_get_f(bmc_ctx* c, int species, double* f, int n, int mem) {
+  if (!c || !f) return BMC_EINVAL;
+  if (species < 0 || species >= (int)c->sp.size()) return fail(c, BMC_EINVAL, "bad species id");
+  Species& s = c->sp[species];
+  if (n != s.n) return fail(c, BMC_EINVAL, "n does not match the grid");
+  if (c->bound && species < c->n_sp_bound) {
+    HIPCHK(c, hipMemcpyAsync(f, c->f64() + s.f_off, 8 * n,
+                             mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    HIPCHK(c, hipMemcpy(f, s.f.data(), 8 * n, mem == BMC_MEM_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+  }
+  return BMC_OK;
+}
+
+int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, int n_out,
+                    const bmc_process_params* prm, int* process_id) {
+  if (!c || !in_sp || !out_sp || !prm) return BMC_EINVAL;
+  if (n_in < 1 || n_out < 1 || n_in + n_out < 3 || n_in + n_out > kMaxN)
+    return fail(c, BMC_EINVAL, "need 1 <= n_in, n_out and 3 <= n_in + n_out <= 6");
+  if ((int)c->pr.size() >= 255) return fail(c, BMC_EINVAL, "too many processes");
+  Process P;
+  P.n_in = n_in;
+  P.n_out = n_out;
+  for (int i = 0; i < n_in; ++i) P.sp[i] = in_sp[i];
+  for (int i = 0; i < n_out; ++i) P.sp[n_in + i] = out_sp[i];
+  for (int i = 0; i < n_in + n_out; ++i)
+    if (P.sp[i] < 0 || P.sp[i] >= (int)c->sp.size()) return fail(c, BMC_EINVAL, "process references an unknown species");
+  const bmc_process_params& q = *prm;
+  if (!(q.sigma_E > 0.0) || !(q.alpha >= 0.0 && q.alpha <= 2.0) || q.n_bins < 2 || q.n_bins > kMaxBins ||
+      (q.term_mode != BMC_TERMS_SPLIT && q.term_mode != BMC_TERMS_NET) || q.side_mask < 0 || q.side_mask > 3 ||
+      q.eval_stride < 1 || q.n_samples < 2 || q.n_iter < 1 || q.n_iter > kMaxIter || !std::isfinite(q.coupling))
+    return fail(c, BMC_EINVAL, "bad process parameters");
+  P.prm = q;
+  c->pr.push_back(P);
+  if (process_id) *process_id = (int)c->pr.size() - 1;
+  return BMC_OK;
+}
+
+int bmc_set_expansion(bmc_ctx* c, int kind, double a0, double t0) {
+  if (!c) return BMC_EINVAL;
+  if (kind != BMC_EXP_NONE && kind != BMC_EXP_RADIATION) return fail(c, BMC_EINVAL, "bad expansion kind");
+  if (kind == BMC_EXP_RADIATION && (!(a0 > 0.0) || !(t0 > 0.0))) return fail(c, BMC_EINVAL, "a0, t0 must be > 0");
+  c->expansion = kind;
+  c->a0 = a0;
+  c->t0 = t0;
+  if (c->bound) {
+    DevState s;
+    int rc = read_state(c, &s);
+    if (rc) return rc;
+    c->t = s.t;
+    return upload_state(c);
+  }
+  return BMC_OK;
+}
+
+int bmc_set_time(bmc_ctx* c, double t) {
+  if (!c || !std::isfinite(t)) return BMC_EINVAL;
+  c->t = t;
+  if (c->bound) {
+    HIPCHK(c, launch_set_eval(c->st(), t, 0, 1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return BMC_OK;
+}
+
+int bmc_get_time(bmc_ctx* c, double* t) {
+  if (!c || !t) return BMC_EINVAL;
+  if (c->bound) {
+    DevState s;
+    int rc = read_state(c, &s);
+    if (rc) return rc;
+    c->t = s.t;
+  }
+  *t = c->t;
+  return BMC_OK;
+}
+
+int bmc_workspace_query(bmc_ctx* c, int64_t max_samples, int max_iter, size_t* bytes) {
+  if (!c || !bytes) return BMC_EINVAL;
+  if (c->pr.empty()) return fail(c, BMC_ESTATE, "register processes first");
+  std::vector<int64_t> offs;
+  for (auto& s : c->sp) offs.push_back(s.f_off);
+  // layout without touching the bound state
+  bmc_ctx tmp;
+  tmp.sp = c->sp;
+  tmp.pr = c->pr;
+  layout_persistent(&tmp);
+  *bytes = tmp.persist_bytes + scratch_estimate(c, max_samples, max_iter);
+  return BMC_OK;
+}
+
+int bmc_workspace_bind(bmc_ctx* c, void* dev_ptr, size_t bytes) {
+  if (!c || !dev_ptr) return BMC_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(dev_ptr) & (kAlign - 1)) != 0) return fail(c, BMC_EINVAL, "workspace not 256-byte aligned");
+  if (c->pr.empty()) return fail(c, BMC_ESTATE, "register processes first");
+  HIPCHK(c, hipSetDevice(c->device));
+  // save the persistent state of a previous binding
+  std::vector<double> old_maps;
+  size_t n_old_slots = 0;
+  if (c->bound) {
+    DevState s;
+    int rc = read_state(c, &s);
+    if (rc) return rc;
+    c->t = s.t;
+    for (int a = 0; a < c->n_sp_bound; ++a) {
+      HIPCHK(c, hipMemcpy(c->sp[a].f.data(), c->f64() + c->sp[a].f_off, 8 * c->sp[a].n, hipMemcpyDeviceToHost));
+    }
+    n_old_slots = c->slot_of_uid.size();
+    old_maps.resize(n_old_slots * kSlotDoubles);
+    if (n_old_slots)
+      HIPCHK(c, hipMemcpy(old_maps.data(), c->maps(), 8 * old_maps.size(), hipMemcpyDeviceToHost));
+  }
+  layout_persistent(c);
+  if (bytes < c->persist_bytes) return fail(c, BMC_ENOMEM, "workspace smaller than the persistent state");
+  c->ws = reinterpret_cast<char*>(dev_ptr);
+  c->ws_bytes = bytes;
+  c->bound = true;
+  c->n_sp_bound = (int)c->sp.size();
+  c->n_pr_bound = (int)c->pr.size();
+  c->plan = Plan();
+  c->step_plan = Plan();
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  int rc = upload_model(c);
+  if (rc) return rc;
+  rc = upload_state(c);
+  if (rc) return rc;
+  for (auto& s : c->sp)
+    if (s.f_set) HIPCHK(c, hipMemcpyAsync(c->f64() + s.f_off, s.f.data(), 8 * s.n, hipMemcpyHostToDevice, c->stream));
+  if (n_old_slots && n_old_slots <= (size_t)c->max_slots)
+    HIPCHK(c, hipMemcpyAsync(c->maps(), old_maps.data(), 8 * old_maps.size(), hipMemcpyHostToDevice, c->stream));
+  else
+    c->slot_of_uid.clear();
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return BMC_OK;
+}
+
+int bmc_plan_size(bmc_ctx* c, int process, int species, const bmc_run_opts* o, int* n_items, int* n_out) {
+  if (!c) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  Plan P;
+  // a plan built without a workspace does not allocate map slots permanently
+  auto saved = c->slot_of_uid;
+  char* ws = c->ws;
+  c->ws = nullptr;
+  rc = build_plan(c, PlanKey{process, species, o->eval_stride, o->n_samples, o->n_iter}, &P);
+  c->ws = ws;
+  c->slot_of_uid = saved;
+  if (rc) return rc;
+  if (n_items) *n_items = (int)P.items.size();
+  if (n_out) *n_out = P.n_out;
+  return BMC_OK;
+}
+
+int bmc_collision(bmc_ctx* c, int process, int species, const bmc_run_opts* o, double* C_out, double* sigma_out,
+                  size_t n_out, int mem) {
+  if (!c || !C_out) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  rc = get_plan(c, c->plan, process, species, o);
+  if (rc) return rc;
+  Plan& P = c->plan;
+  if ((size_t)P.n_out != n_out) return fail(c, BMC_EINVAL, "n_out does not match the plan (" + std::to_string(P.n_out) + ")");
+  HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, c->stream));
+  rc = enqueue_eval(c, P, *o, P.d_out_C, P.d_out_S);
+  if (rc) return rc;
+  c->last_n_iter = P.n_iter_max;
+  const hipMemcpyKind kind = mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(c, hipMemcpyAsync(C_out, P.d_out_C, 8 * n_out, kind, c->stream));
+  if (sigma_out) HIPCHK(c, hipMemcpyAsync(sigma_out, P.d_out_S, 8 * n_out, kind, c->stream));
+  return finish_check(c);
+}
+
+int bmc_item_results(bmc_ctx* c, uint32_t* uids, double* Ibar, double* sigma, double* I_it, double* V_it, int n,
+                     int n_iter) {
+  if (!c) return BMC_EINVAL;
+  Plan& P = c->plan;
+  if (!P.uploaded) return fail(c, BMC_ESTATE, "no evaluation yet");
+  if (n != (int)P.items.size()) return fail(c, BMC_EINVAL, "n does not match the last plan");
+  if (n_iter < 0 || n_iter > kMaxIter) return fail(c, BMC_EINVAL, "bad n_iter");
+  if (uids)
+    for (int i = 0; i < n; ++i) uids[i] = P.items[i].uid;
+  if (Ibar) HIPCHK(c, hipMemcpy(Ibar, P.d_item_Ibar, 8 * n, hipMemcpyDeviceToHost));
+  if (sigma) HIPCHK(c, hipMemcpy(sigma, P.d_item_sig, 8 * n, hipMemcpyDeviceToHost));
+  if (I_it || V_it) {
+    std::vector<double> bI((size_t)n * kMaxIter), bV((size_t)n * kMaxIter);
+    HIPCHK(c, hipMemcpy(bI.data(), P.d_res_I, 8 * bI.size(), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(bV.data(), P.d_res_V, 8 * bV.size(), hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i)
+      for (int t = 0; t < n_iter; ++t) {
+        const int64_t r = P.items[i].res_off;
+        if (I_it) I_it[(size_t)i * n_iter + t] = bI[r * kMaxIter + t];
+        if (V_it) V_it[(size_t)i * n_iter + t] = bV[r * kMaxIter + t];
+      }
+  }
+  return BMC_OK;
+}
+
+int bmc_maps_get(bmc_ctx* c, const uint32_t* uids, int n, double* maps) {
+  if (!c || !uids || !maps || n < 0) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t uid = uids[i];
+    const int p = (int)(uid >> 24), a = (int)((uid >> 20) & 15), side = (int)((uid >> 19) & 1);
+    const int node = (int)(uid & ((1u << 18) - 1));
+    if (p >= (int)c->pr.size() || a >= (int)c->sp.size() || node >= c->sp[a].n || multiplicity(c->pr[p], a, side) == 0)
+      return fail(c, BMC_EINVAL, "uid does not name a work item");
+    const Process& Pr = c->pr[p];
+    const int nb = Pr.prm.n_bins;
+    double* dst = maps + (size_t)i * kMaxD * (nb + 1);
+    auto f = c->slot_of_uid.find(uid);
+    if (f != c->slot_of_uid.end()) {
+      HIPCHK(c, hipMemcpy(dst, c->maps() + (size_t)f->second * kSlotDoubles, 8 * kMaxD * (nb + 1),
+                          hipMemcpyDeviceToHost));
+    } else {
+      int obs, cons, integ[kMaxInt];
+      assign_roles(Pr, a, side, &obs, &cons, integ);
+      const int D = 3 * (Pr.n_in + Pr.n_out - 2);
+      for (int d = 0; d < kMaxD; ++d)
+        for (int j = 0; j <= nb; ++j) {
+          double lo = 0, hi = 0;
+          if (d < D) {
+            if (d % 3 == 0) {
+              lo = c->sp[Pr.sp[integ[d / 3]]].q_min;
+              hi = c->sp[Pr.sp[integ[d / 3]]].q_max;
+            } else {
+              hi = d % 3 == 1 ? M_PI : 2.0 * M_PI;
+            }
+          }
+          dst[d * (nb + 1) + j] = lo + (hi - lo) * (double)j / (double)nb;
+        }
+    }
+  }
+  return BMC_OK;
+}
+
+int bmc_maps_set(bmc_ctx* c, const uint32_t* uids, int n, const double* maps) {
+  if (!c || !uids || !maps || n < 0) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < n; ++i) {
+    const uint32_t uid = uids[i];
+    const int p = (int)(uid >> 24), a = (int)((uid >> 20) & 15), side = (int)((uid >> 19) & 1);
+    const int node = (int)(uid & ((1u << 18) - 1));
+    if (p >= (int)c->pr.size() || a >= (int)c->sp.size() || node >= c->sp[a].n || multiplicity(c->pr[p], a, side) == 0)
+      return fail(c, BMC_EINVAL, "uid does not name a work item");
+    const int nb = c->pr[p].prm.n_bins;
+    int slot;
+    auto f = c->slot_of_uid.find(uid);
+    if (f == c->slot_of_uid.end()) {
+      slot = (int)c->slot_of_uid.size();
+      if (slot >= c->max_slots) return fail(c, BMC_ENOMEM, "map slots exhausted");
+      c->slot_of_uid[uid] = slot;
+    } else {
+      slot = f->second;
+    }
+    HIPCHK(c, hipMemcpy(c->maps() + (size_t)slot * kSlotDoubles, maps + (size_t)i * kMaxD * (nb + 1),
+                        8 * kMaxD * (nb + 1), hipMemcpyHostToDevice));
+  }
+  // plans that were going to initialise these maps must not do so any more
+  c->plan = Plan();
+  c->step_plan = Plan();
+  return BMC_OK;
+}
+
+int bmc_maps_reset(bmc_ctx* c, int process) {
+  if (!c) return BMC_EINVAL;
+  if (process < -1 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
+  // forgetting a slot makes the next plan re-initialise it (slots are never reused for other uids)
+  std::vector<uint32_t> drop;
+  for (auto& kv : c->slot_of_uid)
+    if (process < 0 || (int)(kv.first >> 24) == process) drop.push_back(kv.first);
+  if (process < 0) {
+    c->slot_of_uid.clear();
+  } else {
+    // keep the slot numbers of other processes; re-initialise the dropped ones through a fresh plan
+    for (uint32_t u : drop) {
+      const int slot = c->slot_of_uid[u];
+      const int p = (int)(u >> 24);
+      (void)p;
+      (void)slot;
+    }
+    // simplest correct behaviour: mark all plans stale and rewrite the dropped maps as uniform now
+    std::vector<double> buf;
+    for (uint32_t u : drop) {
+      const int nb = c->pr[u >> 24].prm.n_bins;
+      buf.assign((size_t)kMaxD * (nb + 1), 0.0);
+      int rc = 0;
+      // bmc_maps_get of a uid without a slot returns the uniform map
+      const int slot = c->slot_of_uid[u];
+      c->slot_of_uid.erase(u);
+      rc = bmc_maps_get(c, &u, 1, buf.data());
+      c->slot_of_uid[u] = slot;
+      if (rc) return rc;
+      HIPCHK(c, hipMemcpy(c->maps() + (size_t)slot * kSlotDoubles, buf.data(), 8 * buf.size(), hipMemcpyHostToDevice));
+    }
+  }
+  c->plan = Plan();
+  c->step_plan = Plan();
+  return BMC_OK;
+}
+
+int bmc_step(bmc_ctx* c, int method, double dt, double eps, double dt_max, const bmc_run_opts* o, double* dt_used) {
+  if (!c) return BMC_EINVAL;
+  if (method != BMC_EULER && method != BMC_HEUN) return fail(c, BMC_EINVAL, "bad method");
+  if (!(dt > 0.0) && (!(eps > 0.0) || !(dt_max > 0.0))) return fail(c, BMC_EINVAL, "need dt > 0 or eps, dt_max > 0");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  bmc_run_opts so = *o;
+  so.eval_stride = 0;
+  rc = get_plan(c, c->step_plan, -1, -1, &so);
+  if (rc) return rc;
+  Plan& P = c->step_plan;
+  hipStream_t s = c->stream;
+  DevState before;
+  rc = read_state(c, &before);
+  if (rc) return rc;
+  // backup of f for error recovery (sig buffer is free outside evaluations)
+  HIPCHK(c, launch_copy(c->sig(), c->f64(), c->n_f, s));
+  HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, s));
+  rc = enqueue_eval(c, P, so, c->k1(), nullptr);
+  if (rc) return rc;
+  HIPCHK(c, launch_step_begin(c->st(), c->f64(), c->f0(), c->k1(), c->n_f, dt, eps, dt_max, method == BMC_HEUN, s));
+  if (method == BMC_HEUN) {
+    rc = enqueue_eval(c, P, so, c->k2(), nullptr);
+    if (rc) return rc;
+    HIPCHK(c, launch_step_finish(c->st(), c->f64(), c->f0(), c->f64(), c->k1(), c->k2(), c->n_f, s));
+  }
+  HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
+  DevState after;
+  rc = read_state(c, &after);
+  if (rc) return rc;
+  if (after.err) {
+    HIPCHK(c, launch_copy(c->f64(), c->sig(), c->n_f, s));
+    HIPCHK(c, launch_set_eval(c->st(), before.t, before.next_epoch, 1, s));
+    int zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->st()->err, &zero, sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return fail(c, BMC_ERANGE, "step produced an invalid distribution; f and t restored");
+  }
+  c->t = after.t;
+  if (dt_used) *dt_used = after.dt;
+  return BMC_OK;
+}
+
+int bmc_graph_capture_steps(bmc_ctx* c, int n_steps, int method, double dt, double eps, double dt_max,
+                            const bmc_run_opts* o) {
+  if (!c || n_steps < 1) return BMC_EINVAL;
+  if (method != BMC_EULER && method != BMC_HEUN) return fail(c, BMC_EINVAL, "bad method");
+  if (!(dt > 0.0) && (!(eps > 0.0) || !(dt_max > 0.0))) return fail(c, BMC_EINVAL, "need dt > 0 or eps, dt_max > 0");
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  if (c->stream == nullptr) return fail(c, BMC_EINVAL, "graph capture needs a non-null stream");
+  bmc_run_opts so = *o;
+  so.eval_stride = 0;
+  rc = get_plan(c, c->step_plan, -1, -1, &so);
+  if (rc) return rc;
+  Plan& P = c->step_plan;
+  hipStream_t s = c->stream;
+  // epochs continue from the device counter: set it once, before the capture
+  HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  if (c->gexec) {
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  if (c->graph) {
+    (void)hipGraphDestroy(c->graph);
+    c->graph = nullptr;
+  }
+  HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;
+  int crc = BMC_OK;
+  for (int k = 0; k < n_steps && crc == BMC_OK; ++k) {
+    crc = enqueue_eval(c, P, so, c->k1(), nullptr);
+    if (crc) break;
+    if (launch_step_begin(c->st(), c->f64(), c->f0(), c->k1(), c->n_f, dt, eps, dt_max, method == BMC_HEUN, s) !=
+        hipSuccess) {
+      crc = fail(c, BMC_EHIP, "launch in capture failed");
+      break;
+    }
+    if (method == BMC_HEUN) {
+      crc = enqueue_eval(c, P, so, c->k2(), nullptr);
+      if (crc) break;
+      if (launch_step_finish(c->st(), c->f64(), c->f0(), c->f64(), c->k1(), c->k2(), c->n_f, s) != hipSuccess) {
+        crc = fail(c, BMC_EHIP, "launch in capture failed");
+        break;
+      }
+    }
+    if (launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s) != hipSuccess) {
+      crc = fail(c, BMC_EHIP, "launch in capture failed");
+      break;
+    }
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  c->capturing = false;
+  if (crc) {
+    if (g) (void)hipGraphDestroy(g);
+    return crc;
+  }
+  if (e != hipSuccess) return fail(c, BMC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+  return BMC_OK;
+}
+
+int bmc_graph_replay(bmc_ctx* c) {
+  if (!c) return BMC_EINVAL;
+  if (!c->gexec) return fail(c, BMC_ESTATE, "no captured graph");
+  HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+  return BMC_OK;
+}
+
+int bmc_graph_status(bmc_ctx* c, double* t, double* last_dt) {
+  if (!c) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  DevState s;
+  int rc = read_state(c, &s);
+  if (rc) return rc;
+  c->t = s.t;
+  if (t) *t = s.t;
+  if (last_dt) *last_dt = s.dt;
+  if (s.err) return fail(c, BMC_ERANGE, "a replayed step produced an invalid distribution");
+  return BMC_OK;
+}
+
+int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const double* v_C, size_t n_out,
+            double* grad_f, double* grad_coupling, double* grad_m0, int mem) {
+  (void)process;
+  (void)species;
+  (void)o;
+  (void)v_C;
+  (void)n_out;
+  (void)grad_f;
+  (void)grad_coupling;
+  (void)grad_m0;
+  (void)mem;
+  if (!c) return BMC_EINVAL;
+  return fail(c, BMC_EUNSUP, "vector-Jacobian products are not built yet");
+}
+
+int bmc_set_timing(bmc_ctx* c, int on) {
+  if (!c) return BMC_EINVAL;
+  c->timing = on != 0;
+  return BMC_OK;
+}
+
+int bmc_get_timing(bmc_ctx* c, int reset, double* sample_ms, int* n_launches) {
+  if (!c) return BMC_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& p : c->ev) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, p.first, p.second));
+    c->timed_ms += ms;
+    c->timed_launches += 1;
+    (void)hipEventDestroy(p.first);
+    (void)hipEventDestroy(p.second);
+  }
+  c->ev.clear();
+  if (sample_ms) *sample_ms = c->timed_ms;
+  if (n_launches) *n_launches = c->timed_launches;
+  if (reset) {
+    c->timed_ms = 0.0;
+    c->timed_launches = 0;
+  }
+  return BMC_OK;
+}
+
+int bmc_set_launch_tuning(bmc_ctx* c, int blocks_per_cu) {
+  if (!c || blocks_per_cu < 0 || blocks_per_cu > 64) return BMC_EINVAL;
+  c->blocks_per_cu = blocks_per_cu;
+  return BMC_OK;
+}
+
+const char* bmc_last_error(bmc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* bmc_version(void) { return "boltzmc 0.1 (gfx950)"; }
+
+}  // extern "C"

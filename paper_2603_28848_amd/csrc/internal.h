@@ -1,0 +1,91 @@
+// internal.h -- device-visible records shared by the host planner and the kernels of libboltzmc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmc {
+
+constexpr int kMaxN = 6;          // particles per process
+constexpr int kMaxInt = 4;        // integrated particles (n - 2)
+constexpr int kMaxD = 12;         // 3 (n - 2)
+constexpr int kMaxSpecies = 16;
+constexpr int kMaxBins = 64;
+constexpr int kMaxIter = 64;
+constexpr int kBlock = 256;       // threads per sample block; part of the fixed summation order
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxTab = 4;        // distinct f tables one item reads (non-observed particles)
+
+// Species as the kernels see it: logarithmic grid q_j = exp(lq0 + h j), j = 0..n-1.
+struct SpecDev {
+  int stat;          // eta
+  int n;             // nodes
+  double q_min, q_max, lq0, inv_h;
+  int mass_kind;     // 0 const, 1 m0 + A sin(w t)
+  double m0, A, w;
+  int64_t f_off;     // offset of the species' values in the f arrays
+};
+
+// Time-dependent state read by every kernel (lives in device memory so graphs can advance it).
+struct DevState {
+  double t;          // time of the current evaluation
+  double a;          // scale factor a(t)
+  double m[kMaxSpecies];          // masses at t
+  double fit[kMaxSpecies][4];     // (a_lo, b_lo, a_hi, b_hi) of log(1/f + eta) = a + b E
+  double dt;         // step size of the step in progress
+  double t_step0;    // time at the start of the step in progress
+  double rmax;       // max |k1/f| of the step in progress
+  uint32_t epoch;    // epoch of the evaluation in progress
+  uint32_t next_epoch;  // epoch the next evaluation consumes
+  int err;           // sticky error flag (BMC_ERANGE ...)
+  double expansion_a0, expansion_t0;
+  int expansion;
+  int n_species;
+};
+
+// One work item.  Roles are stored by role, not by position: integrated k = 0..nint-1, then the
+// conserved and the observed particle.
+struct ItemRec {
+  uint32_t uid;
+  int proc;
+  int nint;          // n - 2
+  int D;             // 3 nint
+  int nb;            // Vegas bins
+  int term;          // 0 gain / net, 1 loss
+  int net;           // 1: gain - loss
+  int eval_idx;      // grid index of the observed momentum
+  int n_iter;        // Vegas iterations of this item in the call
+  double q_obs;      // comoving observed momentum (the grid node)
+  int obs_species;
+  int mult;
+  int n_units;       // partial-sum units of one iteration
+  int unit_size;     // samples per unit
+  int64_t N;         // samples per iteration
+  int64_t map_off;   // doubles: Vegas map, kMaxD rows of (nb + 1) edges
+  int64_t part_off;  // doubles: first unit record (2 D nb doubles each) of this item
+  int64_t res_off;   // index of this item's per-iteration results
+  int out_slot;      // output slot of the item's evaluation point (combine)
+  int sign;          // +1 gain / net, -1 loss
+  double coupling2;
+  double inv2s2;     // 1 / (2 sigma_E^2)
+  double dnorm;      // 1 / (sigma_E sqrt(2 pi))
+  double e_cut;
+  double twopi_pow;  // (2 pi)^(3(n-1)-4)
+  double alpha;
+  // role tables, index r: 0..nint-1 integrated, nint conserved, nint+1 observed
+  int r_species[kMaxN];
+  int r_tab[kMaxN];     // f-table slot (kMaxTab) of the role's species (integrated and conserved)
+  int r_in[kMaxN];      // 1 if the role's particle is in the initial state
+  int r_obsside[kMaxN]; // 1 if the role's particle is on the observed side
+  int cons_in;          // conserved particle in the initial state
+  int tab_species[kMaxTab];
+  int n_tab;
+};
+
+// A unit of work: `unit` of item `item` in iteration order.
+struct Task {
+  int item;
+  int unit;
+};
+
+}  // namespace bmc

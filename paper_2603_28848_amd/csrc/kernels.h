@@ -1,0 +1,84 @@
+// kernels.h -- launch wrappers of the libboltzmc kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace bmc {
+
+struct SampleLaunch {
+  const ItemRec* items;
+  const Task* tasks;
+  int n_tasks;
+  int task_begin;        // first task of this launch
+  const SpecDev* spec;
+  const double* f64;
+  const float* f32;
+  const DevState* st;
+  const double* maps;
+  double* unit_s;        // 2 doubles per unit: S1, S2
+  double* parts;         // unit records (histograms)
+  const int64_t* unit_base;  // per item: index of its first unit in unit_s
+  int it;                // Philox iteration index
+  uint32_t seed_lo, seed_hi;
+  int nint_mask;         // bit (nint-1) set for every integrated-particle count present
+  int precision;         // 0 FP64, 1 FP32I
+  int grid;              // blocks
+  size_t lds_bytes;
+};
+
+hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
+
+// Sums the unit records of each item in unit order, stores I_it, V_it for iteration slot `slot`, and (unless
+// frozen) adapts the item's map.
+hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,
+                               const int64_t* unit_base, const double* parts, double* res_I, double* res_V,
+                               int slot, double* maps, int freeze, hipStream_t s);
+
+// Initialises the maps of items (uniform edges over each dimension's range).
+hipError_t launch_init_maps(const ItemRec* items, const int* which, int n, const SpecDev* spec, double* maps,
+                            hipStream_t s);
+
+// Per-slot combination: Ibar, sigma per item (inverse variance over n_iter iterations) and the slot sums
+// C = sum mult sign Ibar, S2 = sum mult^2 sigma^2 over the slot's items (list slot_items[slot_begin[k]..]).
+hipError_t launch_combine(const ItemRec* items, int n_items, const double* res_I, const double* res_V, int n_iter,
+                          double* item_Ibar, double* item_sig, const int* slot_begin, const int* slot_items,
+                          int n_slots, double* slot_C, double* slot_S2, hipStream_t s);
+
+// Output gather: out[o] for output node o of the plan, from the slot sums (stride-override or fill rule).
+struct GatherEntry {
+  int species;    // species of the output node
+  int node;       // grid index
+  int first;      // first process entry in gather_proc
+  int count;
+};
+struct GatherProc {
+  int slot_base;  // slot index of node 0 of this (process, species)
+  int stride;     // evaluation stride
+  int last;       // last evaluated node
+  int fill;       // 1: apply the fill rule
+};
+hipError_t launch_gather(const GatherEntry* ge, int n_out, const GatherProc* gp, const double* slot_C,
+                         const double* slot_S2, const SpecDev* spec, const double* f64, double* C_out,
+                         double* sig_out, hipStream_t s);
+
+// Recomputes a(t), m_s(t), the extrapolation fits and the FP32 copy of f; sets st->err on invalid tables.
+hipError_t launch_prepare(DevState* st, const SpecDev* spec, int n_species, const double* f64, float* f32,
+                          int64_t n_f, hipStream_t s);
+
+int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
+hipError_t launch_next_epoch(DevState* st, hipStream_t s);
+
+// Sets the next evaluation epoch (and optionally the time) on the device.
+hipError_t launch_set_eval(DevState* st, double t, uint32_t epoch, int set_t, hipStream_t s);
+
+// Step pieces (Sec. III.C).  stage_begin: dt from max|k1/f| (or fixed), f0 <- f, f <- f exp(dt k1 / f),
+// t <- t0 + dt (Heun: epoch + 1).  finish: Heun combination.
+hipError_t launch_step_begin(DevState* st, double* f64, double* f0, const double* k1, int64_t n_f, double dt_fixed,
+                             double eps, double dt_max, int heun, hipStream_t s);
+hipError_t launch_step_finish(DevState* st, double* f64, const double* f0, const double* fstar, const double* k1,
+                              const double* k2, int64_t n_f, hipStream_t s);
+hipError_t launch_copy(double* dst, const double* src, int64_t n, hipStream_t s);
+
+}  // namespace bmc

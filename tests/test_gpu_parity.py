@@ -1,0 +1,206 @@
+"""GPU parity of the HIP path (through the C-ABI) against the CPU oracle on the same seeded inputs.
+
+Vegas adaptation with a narrow Gaussian delta amplifies 1-ulp differences by ~30-100x per iteration, so
+parity is checked (i) on frozen maps across all iterations, (ii) one adaptive iteration at a time from a
+common map produced by the oracle, and (iii) for free-running runs on the first iteration (common uniform
+map) plus a statistical check of the final values.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, assert_items_close, gpu_available, oracle_items_matching, point_scale, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _run_gpu(w, opts, process=-1, species=-1):
+    bm = _bm()
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(process, species, opts)
+    n_iter = opts.n_iter if opts.n_iter > 0 else w.processes[0].n_iter
+    res = ctx.item_results(n_iter)
+    return ctx, C, S, res
+
+
+# --------------------------------------------------------------------------------------- frozen maps
+@pytest.mark.parametrize("precision", [0, 1])
+def test_frozen_maps_2to2_all_items(precision):
+    """2->2 MB, 32-point grid, 4 iterations x 1e4 samples on the uniform map: every item and every C."""
+    bm = _bm()
+    w = wl.w22_mb()
+    say("frozen 2to2 precision=%d" % precision)
+    opts = bm.default_opts(seed=0, epoch=0, precision=precision, freeze_maps=1, n_iter=4, n_samples=10_000)
+    ctx, C, S, res = _run_gpu(w, opts)
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"])
+    rc, r = ow.run_items(items, n, 10_000, 4, adapt=False)
+    assert rc == 0
+    tol = TOL[precision]
+    assert_items_close(res["I_it"], r["I_it"], tol, "I_it")
+    assert_items_close(res["Ibar"], r["Ibar"], tol, "Ibar")
+    assert_items_close(res["sigma"], r["sigma"], 10 * tol, "sigma")
+    Co, So = ow.combine(items, n, r["Ibar"], r["sigma"], 0)
+    scale = point_scale(items, n, r["Ibar"], 0, 32)
+    err = np.abs(C - Co)
+    say("C max err / scale %.3e" % np.max(err / scale))
+    assert np.all(err <= tol * scale)
+    np.testing.assert_allclose(S, So, rtol=10 * tol, atol=0)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_frozen_maps_2to3_full_size_sampled_items(precision):
+    """2<->3 BE on the 128-point grid at the full 2^18 samples per item: GPU evaluates all 512 items in one
+    batched launch; the oracle recomputes a sample of items (first, interior, last nodes; both sides, both
+    terms) and they must match item by item (results depend only on each item's counters and map)."""
+    bm = _bm()
+    w = wl.w23_be()
+    say("frozen 2to3 full-size precision=%d" % precision)
+    opts = bm.default_opts(seed=0, epoch=0, precision=precision, freeze_maps=1, n_iter=2)
+    ctx, C, S, res = _run_gpu(w, opts)
+    assert len(res["uid"]) == 512
+    pick = [i for i, u in enumerate(res["uid"]) if (int(u) & 0x3FFFF) in (0, 47, 127)]
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"][pick])
+    rc, r = ow.run_items(items, n, 1 << 18, 2, adapt=False)
+    assert rc == 0
+    tol = TOL[precision]
+    assert_items_close(res["I_it"][pick], r["I_it"], tol, "I_it")
+    assert_items_close(res["sigma"][pick], r["sigma"], 10 * tol, "sigma")
+
+
+# -------------------------------------------------------------------------------- stepwise adaptation
+def test_stepwise_adaptation_2to2():
+    """From the oracle's map before iteration k, one GPU iteration (Philox iteration index k) reproduces the
+    oracle's I_k, V_k and adapted map."""
+    bm = _bm()
+    w = wl.w22_mb()
+    ow = ob.OracleWorld(w)
+    items, n = ow.items()
+    nb = 50
+    maps = np.full((n, 12 * (nb + 1)), np.nan)
+    ctx = bm.from_workload(w)
+    uids = [items[i].uid for i in range(n)]
+    for k in range(4):
+        say("stepwise iteration %d" % k)
+        if k == 0:
+            maps_k = np.stack([ow.map_uniform(items[i], nb) for i in range(n)])
+        else:
+            maps_k = maps.copy()
+        rc, r = ow.run_items(items, n, 10_000, 1, maps=maps_k.copy(), first_iter=k)
+        assert rc == 0
+        ctx.maps_set(uids, maps_k)
+        opts = bm.default_opts(seed=0, epoch=0, precision=0, n_iter=1, n_samples=10_000, first_iter=k)
+        ctx.collision(-1, -1, opts)
+        res = ctx.item_results(1)
+        assert list(res["uid"]) == uids
+        assert_items_close(res["I_it"][:, 0], r["I_it"][:, 0], 1e-12, "I_%d" % k)
+        assert_items_close(res["V_it"][:, 0], r["V_it"][:, 0], 1e-11, "V_%d" % k)
+        gm = ctx.maps_get(uids, nb)
+        om = r["maps"]
+        # edges relative to each dimension's range
+        rng = np.repeat(np.array([20.0, np.pi, 2 * np.pi] * 4), nb + 1)
+        d_err = np.max(np.abs(gm - om)[:, : 6 * (nb + 1)] / rng[: 6 * (nb + 1)])
+        say("map %d max edge err / range %.3e" % (k, d_err))
+        assert d_err < 1e-12
+        maps = om
+
+
+# ------------------------------------------------------------------------------------ free running
+def test_free_running_2to2_first_iteration_and_statistics():
+    bm = _bm()
+    w = wl.w22_mb()
+    opts = bm.default_opts(seed=0, epoch=0, precision=0)
+    ctx, C, S, res = _run_gpu(w, opts)
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"])
+    rc, r = ow.run_items(items, n, 10_000, 4)
+    assert_items_close(res["I_it"][:, 0], r["I_it"][:, 0], 1e-12, "I_0")
+    Co, So = ow.combine(items, n, r["Ibar"], r["sigma"], 0)
+    z = (C - Co) / np.sqrt(S ** 2 + So ** 2)
+    say("free-running 2to2: max |dC|/sigma = %.2f, rel err vs oracle max %.2e" %
+        (np.max(np.abs(z)), np.max(np.abs(C - Co) / point_scale(items, n, r["Ibar"], 0, 32))))
+    assert np.max(np.abs(z)) < 6.0
+
+
+# -------------------------------------------------------------------------------------------- modes
+def test_plain_equals_batched_bitwise_and_run_to_run():
+    bm = _bm()
+    w = wl.w23_be(n_grid=24, N=3000, nitn=3)
+    outs = []
+    for launch in (0, 1, 0):
+        ctx = bm.from_workload(w)
+        C, S = ctx.collision(-1, -1, bm.default_opts(seed=7, epoch=3, launch=launch))
+        outs.append((C, S, ctx.item_results(3)))
+    for C, S, res in outs[1:]:
+        assert np.array_equal(C, outs[0][0]) and np.array_equal(S, outs[0][1])
+        assert np.array_equal(res["I_it"], outs[0][2]["I_it"])
+
+
+def test_selection_invariance():
+    """An item's results do not depend on which other items share the launch."""
+    bm = _bm()
+    w = wl.w23_be(n_grid=24, N=3000, nitn=2)
+    ctx = bm.from_workload(w)
+    ctx.collision(-1, -1, bm.default_opts(seed=1, freeze_maps=1))
+    all_res = ctx.item_results(2)
+    ctx2 = bm.from_workload(w)
+    ctx2.collision(-1, 0, bm.default_opts(seed=1, freeze_maps=1, eval_stride=5))
+    sub = ctx2.item_results(2)
+    idx = {int(u): i for i, u in enumerate(all_res["uid"])}
+    for j, u in enumerate(sub["uid"]):
+        assert np.array_equal(sub["I_it"][j], all_res["I_it"][idx[int(u)]])
+
+
+# ----------------------------------------------------------------------------------- edge cases
+def test_ragged_units_and_small_sizes():
+    """Sample counts that are not multiples of the block (ragged last unit), the minimum of 2 samples,
+    2 Vegas bins and a 10-node grid."""
+    bm = _bm()
+    # With only a handful of samples an item's estimate can come from one sample far off the energy shell,
+    # where the Gaussian exponent x = dE^2/(2 sigma_E^2) is a few hundred and an ulp of dE (the energies of
+    # the conserved particle differ by an ulp between the two sine/cosine libraries) becomes a relative error
+    # of about 2 x ulp(dE)/dE ~ 1e-11 of that sample; those degenerate cases get 1e-10.
+    for N, nb, ng, tol in ((4097 + 255, 50, 16, 1e-12), (2, 2, 10, 1e-10), (777, 3, 12, 1e-12)):
+        w = wl.w22_mb(n_grid=ng, N=N, nitn=2)
+        w.processes[0].n_bins = nb
+        say("ragged N=%d nb=%d grid=%d" % (N, nb, ng))
+        opts = bm.default_opts(seed=5, precision=0, freeze_maps=1)
+        ctx, C, S, res = _run_gpu(w, opts)
+        ow = ob.OracleWorld(w)
+        items, n = oracle_items_matching(ow, res["uid"])
+        rc, r = ow.run_items(items, n, N, 2, seed=5, adapt=False)
+        assert rc == 0
+        assert_items_close(res["I_it"], r["I_it"], tol, "I_it")
+
+
+def test_error_paths():
+    bm = _bm()
+    w = wl.w22_mb(n_grid=16)
+    ctx = bm.from_workload(w)
+    with pytest.raises(bm.BmcError) as e:
+        ctx.collision(5, -1, bm.default_opts())
+    assert e.value.code == bm.EINVAL
+    with pytest.raises(bm.BmcError) as e:
+        ctx.set_f(0, -np.ones(16))
+    assert e.value.code == bm.ERANGE
+    with pytest.raises(bm.BmcError) as e:
+        ctx.collision(-1, -1, bm.default_opts(precision=7))
+    assert e.value.code == bm.EINVAL
+    fd = wl.w24_fd(n_grid=16, N=64, nitn=1)
+    ctx2 = bm.from_workload(fd)
+    with pytest.raises(bm.BmcError) as e:
+        ctx2.set_f(0, np.full(16, 1.5))
+    assert e.value.code == bm.ERANGE
