@@ -67,6 +67,17 @@ __device__ __forceinline__ double interp64(const double* tab, int n, double lq0,
   return f0 + w * (f1 - f0);
 }
 
+// e^z for the FP32 integrand with the range reduction in FP64: z log2(e) = n + fr, fr in [0, 1), then
+// 2^fr on the hardware exp2 and an exact scaling by 2^n.  Relative error ~1e-7 for any |z| (an FP32
+// argument would lose |z| 2^-24).
+__device__ __forceinline__ float exp_split(double z) {
+  const double y = z * 1.4426950408889634074;
+  double n = floor(y);
+  const float fr = (float)(y - n);
+  n = n > 200.0 ? 200.0 : (n < -200.0 ? -200.0 : n);
+  return ldexpf(__builtin_amdgcn_exp2f(fr), (int)n);
+}
+
 __device__ __forceinline__ float interp32(const float* tab, int n, float lq0, float inv_h, double q) {
   float t = (__logf((float)q) - lq0) * inv_h;
   int j = (int)floorf(t);
@@ -260,7 +271,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
       for (int r = 0; r < NR; ++r) prod2E *= 2.0 * E[r];
       W = J * (jac * a3 * M2 * delta / (it->twopi_pow * prod2E) * F);
     } else {
-      const float delta = __expf((float)(-dE * dE * it->inv2s2)) * (float)it->dnorm;
+      const float delta = exp_split(-dE * dE * it->inv2s2) * (float)it->dnorm;
       float f[NR];
 #pragma unroll
       for (int r = 0; r < NI; ++r) {
@@ -269,9 +280,9 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
         f[r] = interp32(tab, S.n, (float)S.lq0, (float)S.inv_h, x[3 * r]);
       }
       if (q_cons < Sc.q_min) {
-        f[NI] = __builtin_amdgcn_rcpf(__expf((float)(fit_lo_a + fit_lo_b * E[NI])) - (float)eta[NI]);
+        f[NI] = __builtin_amdgcn_rcpf(exp_split(fit_lo_a + fit_lo_b * E[NI]) - (float)eta[NI]);
       } else if (q_cons > Sc.q_max) {
-        f[NI] = __builtin_amdgcn_rcpf(__expf((float)(fit_hi_a + fit_hi_b * E[NI])) - (float)eta[NI]);
+        f[NI] = __builtin_amdgcn_rcpf(exp_split(fit_hi_a + fit_hi_b * E[NI]) - (float)eta[NI]);
       } else {
         const float* tab = reinterpret_cast<const float*>(smem + lay.off_f) + tabslot[NI] * n_max;
         f[NI] = interp32(tab, Sc.n, (float)Sc.lq0, (float)Sc.inv_h, q_cons);

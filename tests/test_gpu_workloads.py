@@ -1,0 +1,160 @@
+"""GPU parity on the other workload shapes: two coupled species with three processes of uneven dimension and
+sample count under radiation-dominated expansion (strided evaluation with fill), and 2->4 Fermi-Dirac with a
+time-dependent mass; plus the log-space Euler/Heun steps and HIP-graph replay."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, assert_items_close, gpu_available, oracle_items_matching, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _first_items_per_side(uids, k):
+    """Indices of the first k items of every (process, species, side, term)."""
+    seen = {}
+    out = []
+    for i, u in enumerate(uids):
+        key = int(u) >> 18
+        seen[key] = seen.get(key, 0) + 1
+        if seen[key] <= k:
+            out.append(i)
+    return out
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_species_expansion_subset(precision):
+    """Species A (BE, m=1) and B (FD, m=0.5), AA->BB, AA->AAA, AA->AABB at strides 4/2/1, a(t) at t = 100:
+    all items in one batched launch; the first 16 items of each process/species/side/term match the oracle."""
+    bm = _bm()
+    w = wl.w_multi(n_grid=64, N=(1 << 12, 1 << 12, 1 << 12), nitn=2)
+    w.t = 150.0  # a = sqrt(1.5)
+    say("multi-species precision=%d" % precision)
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=11, epoch=5, precision=precision, freeze_maps=1)
+    C, S = ctx.collision(-1, -1, opts)
+    res = ctx.item_results(2)
+    pick = _first_items_per_side(res["uid"], 16)
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"][pick])
+    rc, r = ow.run_items(items, n, 1 << 12, 2, seed=11, epoch=5, adapt=False)
+    assert rc == 0
+    assert_items_close(res["I_it"][pick], r["I_it"], TOL[precision] * (10 if precision == 0 else 1), "I_it")
+
+
+def test_multi_species_full_grid_fill_matches_oracle():
+    """C on the full grids with the per-process strided fill, against the oracle's collision_all."""
+    bm = _bm()
+    w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(-1, -1, bm.default_opts(seed=3, freeze_maps=1, eval_stride=0))
+    rc, Co, So = ob.OracleWorld(w).collision_all(1 << 10, 2, seed=3, adapt=False)
+    assert rc == 0
+    scale = np.maximum(np.abs(Co), 1e-300)
+    rel = np.abs(C - Co) / scale
+    say("fill: max rel err %.3e" % rel.max())
+    assert np.all(rel < 1e-9)
+    np.testing.assert_allclose(S, So, rtol=1e-9)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_2to4_fermi_time_dependent_mass_subset(precision):
+    bm = _bm()
+    w = wl.w24_fd(N=1 << 14, nitn=2)
+    say("2to4 precision=%d" % precision)
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(-1, -1, bm.default_opts(seed=0, precision=precision, freeze_maps=1))
+    res = ctx.item_results(2)
+    assert len(res["uid"]) == 2048
+    pick = _first_items_per_side(res["uid"], 16)
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"][pick])
+    rc, r = ow.run_items(items, n, 1 << 14, 2, adapt=False)
+    assert rc == 0
+    assert_items_close(res["I_it"][pick], r["I_it"], TOL[precision] * (10 if precision == 0 else 1), "I_it")
+
+
+# ------------------------------------------------------------------------------------------------ steps
+@pytest.mark.parametrize("method", [0, 1])
+def test_step_matches_oracle_with_frozen_maps(method):
+    bm = _bm()
+    q = wl.log_nodes(0.02, 14.0, 48)
+    w = wl.Workload("st", [wl.Species("phi", wl.BOSE, 48, 0.02, 14.0, wl.f_fermi_step(q), m0=1.0)],
+                    [wl.Process([0, 0], [0, 0], sigma_E=0.02, n_samples=1 << 12, n_iter=2)])
+    ctx = bm.from_workload(w)
+    dt = ctx.step(method, -1.0, 0.1, 1e3, bm.default_opts(seed=2, epoch=4, freeze_maps=1))
+    f_gpu = ctx.get_f(0, 48)
+    ow = ob.OracleWorld(w)
+    rc, dto = ow.step(method, -1.0, 0.1, 1e3, 1 << 12, 2, seed=2, epoch=4, adapt=False)
+    assert rc == 0
+    say("step method=%d dt gpu %.17g oracle %.17g" % (method, dt, dto))
+    assert dt == pytest.approx(dto, rel=1e-10)
+    np.testing.assert_allclose(f_gpu, ow.f[0], rtol=1e-10)
+    assert ctx.get_time() == pytest.approx(ow.t, rel=1e-12)
+
+
+def test_multi_species_heun_step_with_expansion():
+    bm = _bm()
+    w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
+    ctx = bm.from_workload(w)
+    dt = ctx.step(1, -1.0, 0.3, 1.0, bm.default_opts(seed=1, epoch=0, freeze_maps=1))
+    ow = ob.OracleWorld(w)
+    rc, dto = ow.step(1, -1.0, 0.3, 1.0, 1 << 10, 2, seed=1, epoch=0, adapt=False)
+    assert rc == 0
+    assert dt == pytest.approx(dto, rel=1e-9)
+    for a in range(2):
+        np.testing.assert_allclose(ctx.get_f(a, 32), ow.f[a], rtol=1e-9)
+
+
+def test_graph_replay_equals_eager_steps():
+    bm = _bm()
+    w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
+    opts = bm.default_opts(seed=9, epoch=10, precision=1)
+    eager = bm.from_workload(w)
+    for k in range(3):
+        opts.epoch = 10 + 2 * k
+        eager.step(1, -1.0, 0.3, 1.0, opts)
+    g = bm.from_workload(w)
+    opts.epoch = 10
+    g.graph_capture_steps(3, 1, -1.0, 0.3, 1.0, opts)
+    g.graph_replay()
+    t, dt = g.graph_status()
+    assert t == eager.get_time()
+    for a in range(2):
+        assert np.array_equal(g.get_f(a, 32), eager.get_f(a, 32))
+    # a second replay continues the evolution (epochs and time advance on the device)
+    for k in range(3, 6):
+        opts.epoch = 10 + 2 * k
+        eager.step(1, -1.0, 0.3, 1.0, opts)
+    g.graph_replay()
+    t2, _ = g.graph_status()
+    assert t2 == eager.get_time() and t2 > t
+    for a in range(2):
+        assert np.array_equal(g.get_f(a, 32), eager.get_f(a, 32))
+
+
+def test_step_error_restores_state():
+    """A Fermi-Dirac table pushed to f >= 1 by a huge fixed step is rejected and f, t are restored."""
+    bm = _bm()
+    q = wl.log_nodes(0.02, 14.0, 24)
+    f0 = 0.9 / (1 + np.exp(q - 3))
+    w = wl.Workload("fd", [wl.Species("chi", wl.FERMI, 24, 0.02, 14.0, f0, m0=1.0)],
+                    [wl.Process([0, 0], [0, 0], sigma_E=0.05, n_samples=1 << 10, n_iter=1)])
+    ctx = bm.from_workload(w)
+    with pytest.raises(bm.BmcError) as e:
+        ctx.step(0, 1e6, 0.3, 1.0, bm.default_opts(freeze_maps=1))
+    assert e.value.code == bm.ERANGE
+    np.testing.assert_array_equal(ctx.get_f(0, 24), f0)
+    assert ctx.get_time() == 0.0
