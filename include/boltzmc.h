@@ -152,6 +152,9 @@ int bmc_add_process(bmc_ctx* ctx, const int* in_sp, int n_in, const int* out_sp,
                     const bmc_process_params* params, int* process_id);
 int bmc_default_process_params(bmc_process_params* params);
 
+/* Changes the coupling lambda of a process (|M|^2 = lambda^2). */
+int bmc_set_coupling(bmc_ctx* ctx, int process, double coupling);
+
 /* Expansion (Sec. III.E): BMC_EXP_NONE (a = 1) or BMC_EXP_RADIATION with a0, t0 > 0. */
 int bmc_set_expansion(bmc_ctx* ctx, int kind, double a0, double t0);
 int bmc_set_time(bmc_ctx* ctx, double t);

@@ -88,6 +88,8 @@ def lib():
         L.orc_combine.restype = None
         L.orc_collision_all.argtypes = [C.POINTER(World), C.c_int64, C.c_int, C.c_uint64, C.c_uint32, C.c_int, dp,
                                         dp, dp, C.c_int]
+        L.orc_vjp.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), dp, C.c_int64, C.c_int, C.c_uint64,
+                              C.c_uint32, dp, dp, dp, dp, C.c_int]
         L.orc_step.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
                                C.c_uint64, C.c_uint32, C.c_int, dp, dp, C.c_int]
         _lib = L
@@ -233,6 +235,22 @@ class OracleWorld:
         rc = lib().orc_collision_all(C.byref(self.world), N, nitn, seed, epoch, int(adapt), _dp(maps), _dp(Cv), _dp(S),
                                      threads)
         return rc, Cv, S
+
+    def vjp(self, items, n_items, coef, N, iter_=0, seed=0, epoch=0, maps=None, threads=0):
+        """Gradients of sum_i coef_i I_i (frozen maps, one iteration): grad_f (all grids), grad_m, grad_lambda."""
+        nb = self.pr[items[0].proc].n_bins
+        stride = MAXD * (nb + 1)
+        if maps is None:
+            maps = np.full((n_items, stride), np.nan)
+        maps = np.ascontiguousarray(maps, dtype=np.float64)
+        coef = np.ascontiguousarray(coef, dtype=np.float64)
+        tot = sum(s.n_grid for s in self.w.species)
+        gf = np.zeros(tot)
+        gm = np.zeros(len(self.w.species))
+        gl = np.zeros(max(1, len(self.w.processes)))
+        rc = lib().orc_vjp(C.byref(self.world), n_items, items, _dp(coef), N, iter_, seed, epoch, _dp(maps), _dp(gf),
+                           _dp(gm), _dp(gl), threads)
+        return rc, gf, gm, gl[: len(self.w.processes)]
 
     def step(self, method, dt, eps, dt_max, N, nitn, seed=0, epoch=0, threads=0, adapt=True):
         nb = self.pr[0].n_bins

@@ -743,6 +743,288 @@ int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, ui
 }
 
 /* =====================================================================================================
+ * Vector-Jacobian product of the frozen-map estimator (common random numbers).
+ *
+ * With the map frozen, item i's estimate of one iteration is I_i = (1/N) sum_n W_n, and C at an evaluation
+ * point is sum over its items of mult * sign * I_i.  Given coef_i = v_point * mult * sign, this accumulates
+ *   grad_f[s][j] += coef_i/N sum_n dW_n/df_{s,j},   grad_m[s] += coef_i/N sum_n dW_n/dm_s,
+ *   grad_lambda[p] += coef_i/N sum_n 2 W_n / lambda_p.
+ * f enters W through the statistical factor: the observed leg's table value, linear-in-ln-q interpolation
+ * weights of the bracketing nodes, or the extrapolation f = 1/(exp(a + b E) - eta) whose (a, b) are the
+ * least-squares line through (E_k, log(1/f_k + eta)) of the end nodes.  m enters through every energy
+ * E_i = sqrt(p_i^2 + m^2) of a particle of that species (Gaussian delta, 1/(2 E_i), the extrapolated f of
+ * the conserved particle) and through the energies E_k of the fit nodes.
+ * ===================================================================================================== */
+
+/* Derivatives of the end-node fit (a, b) of one side: da/dy_k, db/dy_k, da/dE_k, db/dE_k, the node
+ * energies E_k and values y_k.  side 0 = low end, 1 = high end. */
+static void fit_derivatives(const orc_species* s, double a_scale, double m, int side, double* da_dy, double* db_dy,
+                            double* da_dE, double* db_dE, double* Ek, int* j0_out) {
+  const int n = s->n_grid;
+  const int j0 = side == 0 ? 0 : n - ORC_NFIT;
+  const double eta = (double)s->stat;
+  double E[ORC_NFIT], Y[ORC_NFIT], mE = 0, mY = 0;
+  for (int k = 0; k < ORC_NFIT; ++k) {
+    double p = orc_grid_q(s, j0 + k) / a_scale;
+    E[k] = sqrt(p * p + m * m);
+    Y[k] = log(1.0 / s->f[j0 + k] + eta);
+    mE += E[k] / ORC_NFIT;
+    mY += Y[k] / ORC_NFIT;
+  }
+  double sxx = 0, sxy = 0;
+  for (int k = 0; k < ORC_NFIT; ++k) {
+    sxx += (E[k] - mE) * (E[k] - mE);
+    sxy += (E[k] - mE) * (Y[k] - mY);
+  }
+  const double b = sxy / sxx;
+  for (int k = 0; k < ORC_NFIT; ++k) {
+    db_dy[k] = (E[k] - mE) / sxx;
+    da_dy[k] = 1.0 / ORC_NFIT - mE * db_dy[k];
+    db_dE[k] = ((Y[k] - mY) - 2.0 * b * (E[k] - mE)) / sxx;
+    da_dE[k] = -db_dE[k] * mE - b / ORC_NFIT;
+    Ek[k] = E[k];
+  }
+  *j0_out = j0;
+}
+
+/* One item: accumulates into grad_f (concatenated species grids, offsets f_off), grad_m, grad_lam. */
+int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int iter, uint64_t seed,
+                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_m,
+                 double* grad_lam) {
+  item_ctx c;
+  int rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  const int n = c.n, n_in = c.n_in, D = 3 * c.n_int, nb = c.P->n_bins;
+  const double a = c.a, sig = c.P->sigma_E;
+  const double cN = coef / (double)N;
+  /* per-species accumulators of dW/da, dW/db for the low and high fits */
+  double dfit[ORC_MAXSPECIES][4];
+  memset(dfit, 0, sizeof dfit);
+  double y[ORC_MAXD], x[ORC_MAXD];
+  for (int64_t sidx = 0; sidx < N; ++sidx) {
+    orc_sample_uniforms(seed, it->uid, epoch, iter, sidx, D, y);
+    double J = 1.0;
+    for (int d = 0; d < D; ++d) {
+      double yn = y[d] * (double)nb;
+      int j = (int)floor(yn);
+      if (j > nb - 1) j = nb - 1;
+      double del = yn - (double)j;
+      double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+      x[d] = e0 + (e1 - e0) * del;
+      J *= (double)nb * (e1 - e0);
+    }
+    /* kinematics (as item_integrand) */
+    double px[ORC_MAXN], py[ORC_MAXN], pz[ORC_MAXN], E[ORC_MAXN], f[ORC_MAXN] = {0};
+    double jac = 1.0;
+    px[c.i_obs] = 0.0;
+    py[c.i_obs] = 0.0;
+    pz[c.i_obs] = c.q_obs / a;
+    int kof[ORC_MAXN];
+    for (int i = 0; i < n; ++i) kof[i] = -1;
+    for (int k = 0; k < c.n_int; ++k) {
+      int i = c.integ[k];
+      kof[i] = k;
+      double r = x[3 * k], th = x[3 * k + 1], ph = x[3 * k + 2];
+      double p = r / a;
+      px[i] = p * sin(th) * cos(ph);
+      py[i] = p * sin(th) * sin(ph);
+      pz[i] = p * cos(th);
+      jac *= r * r * sin(th);
+    }
+    {
+      double sx = 0, sy = 0, sz = 0;
+      for (int i = 0; i < n; ++i) {
+        if (i == c.i_cons) continue;
+        double sg = (i < n_in) ? 1.0 : -1.0;
+        sx += sg * px[i];
+        sy += sg * py[i];
+        sz += sg * pz[i];
+      }
+      if (c.i_cons < n_in) { sx = -sx; sy = -sy; sz = -sz; }
+      px[c.i_cons] = sx;
+      py[c.i_cons] = sy;
+      pz[c.i_cons] = sz;
+    }
+    int cut = 0;
+    for (int i = 0; i < n; ++i) {
+      double p2 = px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i];
+      if (kof[i] >= 0) {
+        double p = x[3 * kof[i]] / a;
+        p2 = p * p;
+      }
+      E[i] = sqrt(p2 + c.m[i] * c.m[i]);
+      if (E[i] < c.P->e_cut) cut = 1;
+    }
+    if (cut) continue;
+    double dE = 0.0;
+    for (int i = 0; i < n; ++i) dE += (i < n_in) ? E[i] : -E[i];
+    double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
+    /* f values and where they come from */
+    int src[ORC_MAXN], node[ORC_MAXN], eside[ORC_MAXN];
+    double wgt[ORC_MAXN];
+    for (int i = 0; i < n; ++i) {
+      const orc_species* S = c.sp[i];
+      double q;
+      if (i == c.i_obs) {
+        f[i] = c.f_obs;
+        src[i] = 0;
+        node[i] = it->eval_idx;
+        continue;
+      }
+      if (i == c.i_cons) q = a * sqrt(px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i]);
+      else q = x[3 * kof[i]];
+      f[i] = orc_f_at(S, c.fit[i], q, E[i]);
+      if (q < S->q_min || q > S->q_max) {
+        src[i] = 2;
+        eside[i] = q < S->q_min ? 0 : 1;
+      } else {
+        src[i] = 1;
+        double lq0 = log(S->q_min), h = (log(S->q_max) - lq0) / (double)(S->n_grid - 1);
+        double tpos = (log(q) - lq0) / h;
+        int j = (int)floor(tpos);
+        if (j < 0) j = 0;
+        if (j > S->n_grid - 2) j = S->n_grid - 2;
+        node[i] = j;
+        wgt[i] = tpos - (double)j;
+      }
+    }
+    /* statistical factor and its partials */
+    double g[2][ORC_MAXN], dg[2][ORC_MAXN]; /* [gain/loss][position]: factor value, d factor / d f */
+    for (int i = 0; i < n; ++i) {
+      int on_obs = ((i < n_in) ? 0 : 1) == c.obs_side;
+      double bf = 1.0 + c.eta[i] * f[i];
+      g[0][i] = on_obs ? bf : f[i];
+      dg[0][i] = on_obs ? c.eta[i] : 1.0;
+      g[1][i] = on_obs ? f[i] : bf;
+      dg[1][i] = on_obs ? 1.0 : c.eta[i];
+    }
+    double Fv[2], dF[2][ORC_MAXN];
+    for (int t = 0; t < 2; ++t) {
+      Fv[t] = 1.0;
+      for (int i = 0; i < n; ++i) Fv[t] *= g[t][i];
+      for (int i = 0; i < n; ++i) {
+        double prod = dg[t][i];
+        for (int k = 0; k < n; ++k)
+          if (k != i) prod *= g[t][k];
+        dF[t][i] = prod;
+      }
+    }
+    double F, dFdf[ORC_MAXN];
+    for (int i = 0; i < n; ++i) {
+      if (c.P->term_mode == ORC_TERMS_NET) dFdf[i] = dF[0][i] - dF[1][i];
+      else dFdf[i] = dF[c.term][i];
+    }
+    F = c.P->term_mode == ORC_TERMS_NET ? Fv[0] - Fv[1] : Fv[c.term];
+    double prod2E = 1.0;
+    for (int i = 0; i < n; ++i) prod2E *= 2.0 * E[i];
+    const double twopi_pow = pow(TWO_PI, (double)(3 * (n - 1) - 4));
+    const double a3 = pow(a, -3.0 * (double)c.n_int);
+    const double M2 = c.P->coupling * c.P->coupling;
+    const double Wb = J * (jac * a3 * M2 * delta / (twopi_pow * prod2E));
+    const double W = Wb * F;
+    /* coupling */
+    grad_lam[it->proc] += cN * 2.0 * W / c.P->coupling;
+    /* f */
+    double dWdf[ORC_MAXN];
+    for (int i = 0; i < n; ++i) {
+      dWdf[i] = Wb * dFdf[i];
+      int spc = c.P->sp[i];
+      double gsum = cN * dWdf[i];
+      if (src[i] == 0) {
+        grad_f[f_off[spc] + node[i]] += gsum;
+      } else if (src[i] == 1) {
+        grad_f[f_off[spc] + node[i]] += gsum * (1.0 - wgt[i]);
+        grad_f[f_off[spc] + node[i] + 1] += gsum * wgt[i];
+      } else {
+        double dfdz = -f[i] * (1.0 + c.eta[i] * f[i]);
+        dfit[spc][2 * eside[i]] += gsum * dfdz;
+        dfit[spc][2 * eside[i] + 1] += gsum * dfdz * E[i];
+      }
+    }
+    /* mass: energies of every particle, and the extrapolated f's energy dependence */
+    for (int i = 0; i < n; ++i) {
+      double dWdE = W * (-dE / (sig * sig) * ((i < n_in) ? 1.0 : -1.0) - 1.0 / E[i]);
+      if (src[i] == 2) {
+        double b = c.fit[i][2 * eside[i] + 1];
+        dWdE += dWdf[i] * (-b * f[i] * (1.0 + c.eta[i] * f[i]));
+      }
+      grad_m[c.P->sp[i]] += cN * dWdE * c.m[i] / E[i];
+    }
+  }
+  /* chain of the extrapolation fits */
+  for (int spc = 0; spc < w->n_species; ++spc) {
+    for (int side = 0; side < 2; ++side) {
+      double dWa = dfit[spc][2 * side], dWb = dfit[spc][2 * side + 1];
+      if (dWa == 0.0 && dWb == 0.0) continue;
+      const orc_species* S = &w->species[spc];
+      double m = orc_mass(S, w->t);
+      double da_dy[ORC_NFIT], db_dy[ORC_NFIT], da_dE[ORC_NFIT], db_dE[ORC_NFIT], Ek[ORC_NFIT];
+      int j0;
+      fit_derivatives(S, a, m, side, da_dy, db_dy, da_dE, db_dE, Ek, &j0);
+      const double eta = (double)S->stat;
+      for (int k = 0; k < ORC_NFIT; ++k) {
+        double fk = S->f[j0 + k];
+        double dy_df = -1.0 / (fk * (1.0 + eta * fk));
+        grad_f[f_off[spc] + j0 + k] += (dWa * da_dy[k] + dWb * db_dy[k]) * dy_df;
+        grad_m[spc] += (dWa * da_dE[k] + dWb * db_dE[k]) * m / Ek[k];
+      }
+    }
+  }
+  return ORC_OK;
+}
+
+/* VJP over a list of items with per-item coefficients (v * mult * sign), frozen maps (one map row per item,
+ * ORC_MAP_STRIDE(nb) doubles; NaN first edge = uniform), iteration index `iter`.  grad_f: all species grids
+ * concatenated; grad_m: per species; grad_lam: per process.  Outputs are overwritten. */
+int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
+            uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
+            int n_threads) {
+  double fits[4 * ORC_MAXSPECIES];
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  int64_t f_off[ORC_MAXSPECIES];
+  int64_t tot = 0;
+  for (int s = 0; s < w->n_species; ++s) {
+    f_off[s] = tot;
+    tot += w->species[s].n_grid;
+  }
+  for (int64_t j = 0; j < tot; ++j) grad_f[j] = 0.0;
+  for (int s = 0; s < w->n_species; ++s) grad_m[s] = 0.0;
+  for (int p = 0; p < w->n_proc; ++p) grad_lam[p] = 0.0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+  int err = 0;
+#pragma omp parallel
+  {
+    double* gf = (double*)calloc((size_t)tot, sizeof(double));
+    double gm[ORC_MAXSPECIES] = {0}, gl[256] = {0};
+#pragma omp for schedule(dynamic, 1)
+    for (int i = 0; i < n_items; ++i) {
+      const orc_process* P = &w->procs[items[i].proc];
+      const size_t stride = ORC_MAP_STRIDE(P->n_bins);
+      double* mp = (double*)malloc(sizeof(double) * stride);
+      memcpy(mp, &maps[(size_t)i * stride], sizeof(double) * stride);
+      if (isnan(mp[0])) orc_map_uniform(w, &items[i], mp);
+      int r = orc_item_vjp(w, &items[i], fits, N, iter, seed, epoch, mp, coef[i], f_off, gf, gm, gl);
+      free(mp);
+      if (r) {
+#pragma omp atomic write
+        err = r;
+      }
+    }
+#pragma omp critical
+    {
+      for (int64_t j = 0; j < tot; ++j) grad_f[j] += gf[j];
+      for (int s = 0; s < w->n_species; ++s) grad_m[s] += gm[s];
+      for (int p = 0; p < w->n_proc && p < 256; ++p) grad_lam[p] += gl[p];
+    }
+    free(gf);
+  }
+  return err;
+}
+
+/* =====================================================================================================
  * Log-space time stepping (Sec. III.C).
  * ===================================================================================================== */
 

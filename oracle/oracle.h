@@ -104,6 +104,12 @@ void orc_combine(const orc_world* w, int n_items, const orc_item* items, const d
                  int species, double* C, double* sigma);
 int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, uint32_t epoch, int adapt,
                       double* maps, double* C_all, double* sig_all, int n_threads);
+int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int iter, uint64_t seed,
+                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_m,
+                 double* grad_lam);
+int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
+            uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
+            int n_threads);
 int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
              uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads);
 

@@ -59,6 +59,7 @@ _SIGS = {
     "bmc_add_process": [C.c_void_p, C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int), C.c_int,
                         C.POINTER(ProcessParams), C.POINTER(C.c_int)],
     "bmc_default_process_params": [C.POINTER(ProcessParams)],
+    "bmc_set_coupling": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_expansion": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "bmc_set_time": [C.c_void_p, C.c_double],
     "bmc_get_time": [C.c_void_p, C.POINTER(C.c_double)],
@@ -160,10 +161,25 @@ class Context:
     def add_species(self, name, stat, n_grid, q_min, q_max):
         sid = C.c_int()
         self._check(lib().bmc_add_species(self.h, name.encode(), stat, 0, n_grid, q_min, q_max, C.byref(sid)))
+        self._n_f = getattr(self, "_n_f", 0) + n_grid
+        self._n_species = getattr(self, "_n_species", 0) + 1
+        self.grids = getattr(self, "grids", []) + [n_grid]
+        self.masses = getattr(self, "masses", []) + [(0, 0.0, 0.0, 0.0)]
         return sid.value
 
     def set_mass(self, species, kind, m0, A=0.0, w=0.0):
         self._check(lib().bmc_set_mass(self.h, species, kind, m0, A, w))
+        self.masses[species] = (kind, m0, A, w)
+
+    def set_f_all(self, f):
+        """f of every species, concatenated in species order (host array or device tensor)."""
+        o = 0
+        for s, n in enumerate(self.grids):
+            self.set_f(s, f[o:o + n])
+            o += n
+
+    def get_f_all(self):
+        return np.concatenate([self.get_f(s, n) for s, n in enumerate(self.grids)])
 
     def set_f(self, species, f):
         if hasattr(f, "data_ptr"):
@@ -186,7 +202,11 @@ class Context:
         b = (C.c_int * len(outs))(*outs)
         pid = C.c_int()
         self._check(lib().bmc_add_process(self.h, a, len(ins), b, len(outs), C.byref(p), C.byref(pid)))
+        self._n_proc = getattr(self, "_n_proc", 0) + 1
         return pid.value
+
+    def set_coupling(self, process, coupling):
+        self._check(lib().bmc_set_coupling(self.h, process, coupling))
 
     def set_expansion(self, kind, a0=1.0, t0=1.0):
         self._check(lib().bmc_set_expansion(self.h, kind, a0, t0))
@@ -268,6 +288,20 @@ class Context:
         opts = opts or default_opts()
         self.ensure_workspace(opts.n_samples, opts.n_iter)
         self._check(lib().bmc_graph_capture_steps(self.h, n_steps, method, dt, eps, dt_max, C.byref(opts)))
+
+    def vjp(self, v, process=-1, species=-1, opts: Optional[RunOpts] = None, n_f=None):
+        """dL/df (all grids concatenated), dL/dcoupling (per process), dL/dm0 (per species) of L = v . C with
+        frozen maps and the counters of one iteration (opts.first_iter)."""
+        opts = opts or default_opts()
+        ni, no = self.plan_size(process, species, opts)
+        self.ensure_workspace(opts.n_samples, 1)
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        assert v.size == no
+        n_f = n_f if n_f is not None else self._n_f
+        gf, gl, gm = np.zeros(n_f), np.zeros(self._n_proc), np.zeros(self._n_species)
+        self._check(lib().bmc_vjp(self.h, process, species, C.byref(opts), _ptr(v), no, _ptr(gf), _ptr(gl), _ptr(gm),
+                                  MEM_HOST))
+        return gf, gl, gm
 
     def set_timing(self, on=True):
         self._check(lib().bmc_set_timing(self.h, int(on)))

@@ -108,7 +108,7 @@ struct bmc_ctx {
   size_t ws_bytes = 0;
   bool bound = false;
   size_t off_state = 0, off_spec = 0, off_f64 = 0, off_f32 = 0, off_f0 = 0, off_k1 = 0, off_k2 = 0, off_sig = 0,
-         off_maps = 0, persist_bytes = 0;
+         off_qnode = 0, off_maps = 0, persist_bytes = 0;
   int64_t n_f = 0;
   int max_slots = 0;
   int n_sp_bound = -1, n_pr_bound = -1;
@@ -138,6 +138,7 @@ struct bmc_ctx {
   double* k1() { return reinterpret_cast<double*>(ws + off_k1); }
   double* k2() { return reinterpret_cast<double*>(ws + off_k2); }
   double* sig() { return reinterpret_cast<double*>(ws + off_sig); }
+  double* qnode() { return reinterpret_cast<double*>(ws + off_qnode); }
   double* maps() { return reinterpret_cast<double*>(ws + off_maps); }
 };
 
@@ -246,6 +247,8 @@ void layout_persistent(bmc_ctx* c) {
   o = align_up(o + 8 * nf);
   c->off_sig = o;
   o = align_up(o + 8 * nf);
+  c->off_qnode = o;
+  o = align_up(o + 8 * nf);
   // map slots: every item any call can plan (stride 1, both sides, both terms)
   int slots = 0;
   for (size_t p = 0; p < c->pr.size(); ++p)
@@ -277,8 +280,14 @@ SpecDev make_spec(const Species& S) {
 
 int upload_model(bmc_ctx* c) {
   std::vector<SpecDev> sd(kMaxSpecies);
-  for (size_t i = 0; i < c->sp.size(); ++i) sd[i] = make_spec(c->sp[i]);
+  std::vector<double> qn;
+  for (size_t i = 0; i < c->sp.size(); ++i) {
+    sd[i] = make_spec(c->sp[i]);
+    for (int j = 0; j < c->sp[i].n; ++j) qn.push_back(grid_node(c->sp[i], j));
+  }
   HIPCHK(c, hipMemcpyAsync(c->spec(), sd.data(), sizeof(SpecDev) * kMaxSpecies, hipMemcpyHostToDevice, c->stream));
+  if (!qn.empty())
+    HIPCHK(c, hipMemcpyAsync(c->qnode(), qn.data(), 8 * qn.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BMC_OK;
 }
@@ -584,6 +593,28 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
   }
   for (auto& S : c->sp) outs += S.n;
   (void)max_iter;
+  // adjoint records: per unit n_tab * n_max + 12 doubles (n_tab <= 4 tables of at most the largest grid)
+  size_t gmax = 0, vjp_part = 0;
+  for (auto& S : c->sp) gmax = std::max(gmax, (size_t)S.n);
+  for (auto& Pr : c->pr) {
+    const int64_t N = std::max<int64_t>(max_samples > 0 ? max_samples : 0, Pr.prm.n_samples);
+    const int U = unit_size_for(N);
+    const int64_t nu = (N + U - 1) / U;
+    int ntab = 0;
+    for (size_t a = 0; a < c->sp.size(); ++a) {
+      bool used = false;
+      for (int i = 0; i < Pr.n_in + Pr.n_out; ++i) used |= Pr.sp[i] == (int)a;
+      ntab += used;
+    }
+    for (size_t a = 0; a < c->sp.size(); ++a) {
+      int sides = 0;
+      for (int side = 0; side < 2; ++side) sides += multiplicity(Pr, (int)a, side) > 0;
+      const size_t ni = (size_t)c->sp[a].n * sides * (Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+      vjp_part += ni * nu * (ntab * gmax + 12);
+    }
+  }
+  s += align_up(8 * vjp_part) + align_up((sizeof(ItemRec) + 8 * (4 * gmax + 12) + 24) * items) +
+       align_up(8 * (size_t)c->n_f) + 4 * kAlign + 16 * c->pr.size();
   s += align_up(sizeof(ItemRec) * items) + 2 * align_up(sizeof(Task) * tasks) + align_up(8 * items) +
        align_up(16 * units) + align_up(8 * part) + 2 * align_up(8 * kMaxIter * items) + 2 * align_up(8 * items) +
        align_up(4 * (slots + 1)) + align_up(4 * items) + 2 * align_up(8 * slots) +
@@ -663,6 +694,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.spec = c->spec();
   L.f64 = c->f64();
   L.f32 = c->f32();
+  L.qnode = c->qnode();
   L.st = c->st();
   L.maps = c->maps();
   L.unit_s = P.d_unit_s;
@@ -889,6 +921,16 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
   P.prm = q;
   c->pr.push_back(P);
   if (process_id) *process_id = (int)c->pr.size() - 1;
+  return BMC_OK;
+}
+
+int bmc_set_coupling(bmc_ctx* c, int process, double coupling) {
+  if (!c) return BMC_EINVAL;
+  if (process < 0 || process >= (int)c->pr.size() || !std::isfinite(coupling))
+    return fail(c, BMC_EINVAL, "bad process id or coupling");
+  c->pr[process].prm.coupling = coupling;
+  c->plan = Plan();
+  c->step_plan = Plan();
   return BMC_OK;
 }
 
@@ -1298,17 +1340,119 @@ int bmc_graph_status(bmc_ctx* c, double* t, double* last_dt) {
 
 int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const double* v_C, size_t n_out,
             double* grad_f, double* grad_coupling, double* grad_m0, int mem) {
-  (void)process;
-  (void)species;
-  (void)o;
-  (void)v_C;
-  (void)n_out;
-  (void)grad_f;
-  (void)grad_coupling;
-  (void)grad_m0;
-  (void)mem;
-  if (!c) return BMC_EINVAL;
-  return fail(c, BMC_EUNSUP, "vector-Jacobian products are not built yet");
+  if (!c || !v_C) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (o->precision != BMC_FP64) return fail(c, BMC_EUNSUP, "vector-Jacobian products are FP64 only");
+  rc = check_ready(c);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  bmc_run_opts vo = *o;
+  vo.n_iter = 1;
+  vo.freeze_maps = 1;
+  rc = get_plan(c, c->plan, process, species, &vo);
+  if (rc) return rc;
+  Plan& P = c->plan;
+  if ((size_t)P.n_out != n_out) return fail(c, BMC_EINVAL, "n_out does not match the plan");
+  for (auto& g : P.gproc)
+    if (g.fill && g.stride > 1)
+      return fail(c, BMC_EUNSUP, "strided evaluation with fill is not differentiated; use eval_stride >= 1");
+  // cotangent on the host
+  std::vector<double> v(n_out);
+  if (mem == BMC_MEM_DEVICE) {
+    HIPCHK(c, hipMemcpyAsync(v.data(), v_C, 8 * n_out, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::memcpy(v.data(), v_C, 8 * n_out);
+  }
+  // output index of every item: the gather entry of its (species, node)
+  std::unordered_map<int64_t, int> out_of;
+  for (size_t k = 0; k < P.gather.size(); ++k) out_of[(int64_t)P.gather[k].species * 1000003 + P.gather[k].node] = (int)k;
+  const size_t nI = P.items.size();
+  std::vector<ItemRec> vitems = P.items;
+  std::vector<double> coef(nI);
+  std::vector<int> rec_len(nI), rec_nmax(nI);
+  int64_t part = 0;
+  int rec_stride = 0, lds = 0;
+  for (size_t i = 0; i < nI; ++i) {
+    ItemRec& it = vitems[i];
+    auto f = out_of.find((int64_t)it.obs_species * 1000003 + it.eval_idx);
+    if (f == out_of.end()) return fail(c, BMC_EINVAL, "item without an output");
+    coef[i] = v[f->second] * (double)it.mult * (double)it.sign;
+    int n_max = 0;
+    for (int t = 0; t < it.n_tab; ++t) n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
+    rec_nmax[i] = n_max;
+    rec_len[i] = vjp_record_len(it.n_tab, n_max);
+    rec_stride = std::max(rec_stride, rec_len[i]);
+    it.part_off = part;
+    part += (int64_t)it.n_units * rec_len[i];
+    lds = std::max(lds, vjp_lds_bytes(it.D, it.nb, it.n_tab, n_max));
+  }
+  if (lds > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need of the adjoint above 64 KB");
+  // scratch after the plan's own region
+  size_t off = c->persist_bytes + P.scratch_bytes;
+  auto take = [&](size_t bytes) {
+    size_t o2 = off;
+    off = align_up(off + bytes);
+    return o2;
+  };
+  const size_t o_items = take(sizeof(ItemRec) * nI), o_parts = take(8 * (size_t)part),
+               o_rec = take(8 * (size_t)rec_stride * nI), o_coef = take(8 * nI), o_len = take(4 * nI),
+               o_nmax = take(4 * nI), o_gf = take(8 * (size_t)c->n_f), o_gm = take(8 * kMaxSpecies),
+               o_gl = take(8 * c->pr.size()), o_cp = take(8 * c->pr.size());
+  if (off > c->ws_bytes)
+    return fail(c, BMC_ENOMEM, "workspace too small for the adjoint: need " + std::to_string(off) + " bytes");
+  char* b = c->ws;
+  ItemRec* d_items = reinterpret_cast<ItemRec*>(b + o_items);
+  double* d_parts = reinterpret_cast<double*>(b + o_parts);
+  double* d_rec = reinterpret_cast<double*>(b + o_rec);
+  double* d_coef = reinterpret_cast<double*>(b + o_coef);
+  int* d_len = reinterpret_cast<int*>(b + o_len);
+  int* d_nmax = reinterpret_cast<int*>(b + o_nmax);
+  double* d_gf = reinterpret_cast<double*>(b + o_gf);
+  double* d_gm = reinterpret_cast<double*>(b + o_gm);
+  double* d_gl = reinterpret_cast<double*>(b + o_gl);
+  double* d_cp = reinterpret_cast<double*>(b + o_cp);
+  std::vector<double> cpl(c->pr.size());
+  for (size_t p = 0; p < c->pr.size(); ++p) cpl[p] = c->pr[p].prm.coupling;
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(d_items, vitems.data(), sizeof(ItemRec) * nI, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_coef, coef.data(), 8 * nI, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_len, rec_len.data(), 4 * nI, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_nmax, rec_nmax.data(), 4 * nI, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_cp, cpl.data(), 8 * cpl.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, s));
+  HIPCHK(c, launch_next_epoch(c->st(), s));
+  HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
+  SampleLaunch L{};
+  L.items = d_items;
+  L.tasks = P.d_tb;
+  L.task_begin = 0;
+  L.n_tasks = (int)P.tasks_batched.size();
+  L.spec = c->spec();
+  L.f64 = c->f64();
+  L.f32 = c->f32();
+  L.qnode = c->qnode();
+  L.st = c->st();
+  L.maps = c->maps();
+  L.parts = d_parts;
+  L.unit_base = P.d_unit_base;
+  L.it = o->first_iter;
+  L.seed_lo = (uint32_t)o->seed;
+  L.seed_hi = (uint32_t)(o->seed >> 32);
+  L.nint_mask = P.nint_mask;
+  L.precision = BMC_FP64;
+  L.lds_bytes = lds;
+  L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
+  HIPCHK(c, launch_vjp(L, s));
+  HIPCHK(c, launch_vjp_finish(d_items, (int)nI, d_coef, d_parts, d_len, d_nmax, d_rec, rec_stride, c->spec(),
+                              (int)c->sp.size(), c->f64(), c->qnode(), c->st(), d_gf, c->n_f, d_gm, d_gl, d_cp,
+                              (int)c->pr.size(), s));
+  const hipMemcpyKind kind = mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (grad_f) HIPCHK(c, hipMemcpyAsync(grad_f, d_gf, 8 * (size_t)c->n_f, kind, s));
+  if (grad_m0) HIPCHK(c, hipMemcpyAsync(grad_m0, d_gm, 8 * c->sp.size(), kind, s));
+  if (grad_coupling) HIPCHK(c, hipMemcpyAsync(grad_coupling, d_gl, 8 * c->pr.size(), kind, s));
+  return finish_check(c);
 }
 
 int bmc_set_timing(bmc_ctx* c, int on) {

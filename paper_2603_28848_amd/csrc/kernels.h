@@ -15,6 +15,7 @@ struct SampleLaunch {
   const SpecDev* spec;
   const double* f64;
   const float* f32;
+  const double* qnode;   // comoving grid nodes, same layout as f
   const DevState* st;
   const double* maps;
   double* unit_s;        // 2 doubles per unit: S1, S2
@@ -68,6 +69,17 @@ hipError_t launch_prepare(DevState* st, const SpecDev* spec, int n_species, cons
                           int64_t n_f, hipStream_t s);
 
 int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
+
+// Adjoint (FP64, frozen maps): per-unit records of the sample derivatives, then per item (times coef/N),
+// then per species node, fits, masses and couplings.
+hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s);
+int vjp_lds_bytes(int D, int nb, int n_tab, int n_max);
+int vjp_record_len(int n_tab, int n_max);
+hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* coef, const double* parts,
+                             const int* rec_len, const int* rec_nmax, double* item_rec, int rec_stride,
+                             const SpecDev* spec, int n_species, const double* f64, const double* qnode,
+                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
+                             const double* coupling, int n_proc, hipStream_t s);
 hipError_t launch_next_epoch(DevState* st, hipStream_t s);
 
 // Sets the next evaluation epoch (and optionally the time) on the device.

@@ -14,6 +14,8 @@
 // histograms are accumulated per wave in LDS and summed over waves in order.
 #include <math.h>
 
+#include <type_traits>
+
 #include "kernels.h"
 #include "philox.h"
 
@@ -26,21 +28,26 @@ constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kHistWMin = 0x1p-400;  // |W| below this enters the training histogram as 0
 
 struct Lds {
-  int off_e, off_w, off_f, off_h, off_c, off_red, total;
+  int off_e, off_w, off_sc, off_tab, tab_stride, off_h, off_c, off_red, total;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
+// LDS of one sample block: map edges and widths (D x nb), sin/cos of k pi/16 (33 entries),
+// per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction scratch.
 __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
   Lds L;
-  int DN = D * nb;
+  const int DN = D * nb;
   int o = 0;
   L.off_e = o;
   o = align16(o + DN * 8);
   L.off_w = o;
   o = align16(o + DN * 8);
-  L.off_f = o;
-  o = align16(o + n_tab * n_max * fbytes);
+  L.off_sc = o;
+  o = align16(o + 33 * 16);
+  L.off_tab = o;
+  L.tab_stride = align16(n_max * (16 + fbytes));
+  o = align16(o + n_tab * L.tab_stride);
   L.off_h = o;
   o = align16(o + kWaves * DN * 8);
   L.off_c = o;
@@ -57,16 +64,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// f at a comoving momentum inside the grid: linear in ln q between the bracketing nodes (FP64).
-__device__ __forceinline__ double interp64(const double* tab, int n, double lq0, double inv_h, double q) {
-  double t = (log(q) - lq0) * inv_h;
-  int j = (int)floor(t);
-  j = j < 0 ? 0 : (j > n - 2 ? n - 2 : j);
-  double w = t - (double)j;
-  double f0 = tab[j], f1 = tab[j + 1];
-  return f0 + w * (f1 - f0);
-}
-
 // e^z for the FP32 integrand with the range reduction in FP64: z log2(e) = n + fr, fr in [0, 1), then
 // 2^fr on the hardware exp2 and an exact scaling by 2^n.  Relative error ~1e-7 for any |z| (an FP32
 // argument would lose |z| 2^-24).
@@ -78,12 +75,92 @@ __device__ __forceinline__ float exp_split(double z) {
   return ldexpf(__builtin_amdgcn_exp2f(fr), (int)n);
 }
 
-__device__ __forceinline__ float interp32(const float* tab, int n, float lq0, float inv_h, double q) {
-  float t = (__logf((float)q) - lq0) * inv_h;
-  int j = (int)floorf(t);
-  j = j < 0 ? 0 : (j > n - 2 ? n - 2 : j);
-  float w = t - (float)j;
-  float f0 = tab[j], f1 = tab[j + 1];
+// sin(k pi/16), cos(k pi/16), k = 0..32 (correctly rounded; staged into LDS by every sample block).
+__constant__ double kSinPi16[33] = {0.0, 0.19509032201612828, 0.3826834323650898, 0.5555702330196022, 0.7071067811865476, 0.8314696123025452, 0.9238795325112867, 0.9807852804032304, 1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452, 0.7071067811865476, 0.5555702330196022, 0.3826834323650898, 0.19509032201612828, 0.0, -0.19509032201612828, -0.3826834323650898, -0.5555702330196022, -0.7071067811865476, -0.8314696123025452, -0.9238795325112867, -0.9807852804032304, -1.0, -0.9807852804032304, -0.9238795325112867, -0.8314696123025452, -0.7071067811865476, -0.5555702330196022, -0.3826834323650898, -0.19509032201612828, 0.0};
+__constant__ double kCosPi16[33] = {1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452, 0.7071067811865476, 0.5555702330196022, 0.3826834323650898, 0.19509032201612828, 0.0, -0.19509032201612828, -0.3826834323650898, -0.5555702330196022, -0.7071067811865476, -0.8314696123025452, -0.9238795325112867, -0.9807852804032304, -1.0, -0.9807852804032304, -0.9238795325112867, -0.8314696123025452, -0.7071067811865476, -0.5555702330196022, -0.3826834323650898, -0.19509032201612828, 0.0, 0.19509032201612828, 0.3826834323650898, 0.5555702330196022, 0.7071067811865476, 0.8314696123025452, 0.9238795325112867, 0.9807852804032304, 1.0};
+
+// sin and cos of x in [0, 2 pi]: x = k pi/16 + tau with a two-part Cody-Waite reduction (k pi/16 exact in
+// the first part), |tau| <= pi/32, Taylor series of sin(tau) to tau^11 and cos(tau) to tau^12 (truncation
+// below 1e-22), then the angle-addition formulas with the tabulated sin/cos of k pi/16.
+__device__ __forceinline__ void sincos_red(double x, const double2* __restrict__ tab, double* s, double* c) {
+  const double kf = rint(x * 5.092958178940651);
+  const double tau = fma(-kf, 9.304434350608279e-14, fma(-kf, 0.19634954084926903, x));
+  int k = (int)kf;
+  k = k < 0 ? 0 : (k > 32 ? 32 : k);
+  const double t2 = tau * tau;
+  double ps = -2.505210838544172e-08;
+  ps = fma(ps, t2, 2.7557319223985893e-06);
+  ps = fma(ps, t2, -0.0001984126984126984);
+  ps = fma(ps, t2, 0.008333333333333333);
+  ps = fma(ps, t2, -0.16666666666666666);
+  const double st = fma(tau * t2, ps, tau);
+  double pc = 2.08767569878681e-09;
+  pc = fma(pc, t2, -2.755731922398589e-07);
+  pc = fma(pc, t2, 2.48015873015873e-05);
+  pc = fma(pc, t2, -0.001388888888888889);
+  pc = fma(pc, t2, 0.041666666666666664);
+  pc = fma(pc, t2, -0.5);
+  const double ct = fma(pc, t2, 1.0);
+  const double2 sc = tab[k];
+  *s = fma(sc.x, ct, sc.y * st);
+  *c = fma(sc.y, ct, -(sc.x * st));
+}
+
+// Natural logarithm of q > 0: q = 2^e m with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh((m-1)/(m+1)) by its
+// Taylor series to z^19 (|z| <= 0.1716, truncation below 3e-17), e ln 2 in two parts.
+__device__ __forceinline__ double log_pos(double q) {
+  int e;
+  double m = frexp(q, &e);
+  if (m < 0.7071067811865476) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double z = (m - 1.0) / (m + 1.0);
+  const double z2 = z * z;
+  double p = 0.10526315789473684;  // 2/19
+  p = fma(p, z2, 0.11764705882352941);
+  p = fma(p, z2, 0.13333333333333333);
+  p = fma(p, z2, 0.15384615384615385);
+  p = fma(p, z2, 0.18181818181818182);
+  p = fma(p, z2, 0.2222222222222222);
+  p = fma(p, z2, 0.2857142857142857);
+  p = fma(p, z2, 0.4);
+  p = fma(p, z2, 0.6666666666666666);
+  p = fma(p, z2, 2.0);
+  const double de = (double)e;
+  return fma(de, 0.6931471805592082, fma(de, 7.371002565167799e-13, z * p));
+}
+
+// A table of f on a logarithmic grid in LDS (q_j, 1/q_j, f_j).
+template <typename T>
+struct FTab {
+  const double* q;
+  const double* iq;
+  const T* f;
+  int n;
+  double lq0, inv_h;
+};
+
+// FP64: position t = (ln q - ln q_0)/h on the grid, node j = floor(t), weight t - j.
+__device__ __forceinline__ double interp64(const FTab<double>& t, double q, int* jo, double* wo) {
+  const double tp = (log_pos(q) - t.lq0) * t.inv_h;
+  int j = (int)floor(tp);
+  j = j < 0 ? 0 : (j > t.n - 2 ? t.n - 2 : j);
+  const double w = tp - (double)j;
+  *jo = j;
+  *wo = w;
+  const double f0 = t.f[j], f1 = t.f[j + 1];
+  return f0 + w * (f1 - f0);
+}
+
+// FP32 integrand: the grid position in FP64 (an FP32 logarithm would move the weight by ~1e-6 / h, which the
+// linear interpolation of a steep tail amplifies by f_j / f_{j+1}); interpolation of the FP32 table.
+__device__ __forceinline__ float interp32(const FTab<float>& t, double q) {
+  const double tp = (log_pos(q) - t.lq0) * t.inv_h;
+  int j = (int)floor(tp);
+  j = j < 0 ? 0 : (j > t.n - 2 ? t.n - 2 : j);
+  const float w = (float)(tp - (double)j);
+  const float f0 = t.f[j], f1 = t.f[j + 1];
   return fmaf(w, f1 - f0, f0);
 }
 
@@ -94,6 +171,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   constexpr int D = 3 * NI;
   constexpr int B = (D + 3) / 4;
   constexpr int NR = NI + 2;  // roles: integrated 0..NI-1, conserved NI, observed NI+1
+  using FT = typename std::conditional<PREC == 0, double, float>::type;
   const ItemRec* __restrict__ it = &L.items[task.item];
   const int tid = threadIdx.x;
   const int nb = it->nb;
@@ -101,30 +179,50 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   const int n_tab = it->n_tab;
   int n_max = 0;
   for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
-  const Lds lay = lds_layout(D, nb, n_tab, n_max, PREC == 0 ? 8 : 4);
+  const Lds lay = lds_layout(D, nb, n_tab, n_max, sizeof(FT));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
+  double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
   double* sm_h = reinterpret_cast<double*>(smem + lay.off_h);
   uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
   double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
 
-  // ---- stage the map, the f tables and clear the histograms ----
+  // ---- stage the map, the angle tables, the f tables and clear the histograms ----
   const double* __restrict__ map = L.maps + it->map_off;
   for (int i = tid; i < DN; i += kBlock) {
-    int d = i / nb, j = i - d * nb;
-    double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+    const int d = i / nb, j = i - d * nb;
+    const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+    const double w = e1 - e0;
     sm_e[i] = e0;
-    sm_w[i] = e1 - e0;
+    sm_w[i] = w;
   }
+  if (tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; k < n_tab; ++k) {
     const SpecDev& S = L.spec[it->tab_species[k]];
-    if (PREC == 0) {
-      double* dst = reinterpret_cast<double*>(smem + lay.off_f) + k * n_max;
-      for (int j = tid; j < S.n; j += kBlock) dst[j] = L.f64[S.f_off + j];
-    } else {
-      float* dst = reinterpret_cast<float*>(smem + lay.off_f) + k * n_max;
-      for (int j = tid; j < S.n; j += kBlock) dst[j] = L.f32[S.f_off + j];
+    unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
+    double* q = reinterpret_cast<double*>(base);
+    double* iq = q + n_max;
+    FT* f = reinterpret_cast<FT*>(iq + n_max);
+    for (int j = tid; j < S.n; j += kBlock) {
+      q[j] = L.qnode[S.f_off + j];
+      iq[j] = 1.0 / q[j];
+      if constexpr (PREC == 0) f[j] = L.f64[S.f_off + j];
+      else f[j] = L.f32[S.f_off + j];
     }
+  }
+  // per role (integrated and conserved): its table in LDS
+  FTab<FT> tr[NI + 1];
+#pragma unroll
+  for (int r = 0; r <= NI; ++r) {
+    const int k = it->r_tab[r];
+    const SpecDev& S = L.spec[it->tab_species[k]];
+    const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
+    tr[r].q = reinterpret_cast<const double*>(base);
+    tr[r].iq = tr[r].q + n_max;
+    tr[r].f = reinterpret_cast<const FT*>(tr[r].iq + n_max);
+    tr[r].n = S.n;
+    tr[r].lq0 = S.lq0;
+    tr[r].inv_h = S.inv_h;
   }
   for (int i = tid; i < kWaves * DN; i += kBlock) {
     sm_h[i] = 0.0;
@@ -135,29 +233,25 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   const DevState* __restrict__ st = L.st;
   const double a = st->a;
   const double inv_a = 1.0 / a;
-  double m[NR], eta[NR];
-  int tabslot[NR], obsside[NR], isin[NR];
+  double m2[NR], eta[NR], esg[NR];
+  int obsside[NR];
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
-    m[r] = st->m[it->r_species[r]];
+    const double mr = st->m[it->r_species[r]];
+    m2[r] = mr * mr;
     eta[r] = (double)L.spec[it->r_species[r]].stat;
-    tabslot[r] = it->r_tab[r];
+    esg[r] = it->r_in[r] ? 1.0 : -1.0;
     obsside[r] = it->r_obsside[r];
-    isin[r] = it->r_in[r];
   }
   const SpecDev& So = L.spec[it->obs_species];
-  const double q_obs = it->q_obs;
-  const double p_obs = q_obs * inv_a;
-  const double E_obs = sqrt(p_obs * p_obs + m[NI + 1] * m[NI + 1]);
+  const double p_obs = it->q_obs * inv_a;
+  const double E_obs = sqrt(p_obs * p_obs + m2[NI + 1]);
   const double f_obs = L.f64[So.f_off + it->eval_idx];
-  const double a3 = pow(a, -3.0 * (double)NI);
-  const double M2 = it->coupling2;
+  const double a3M2 = pow(a, -3.0 * (double)NI) * it->coupling2;
   const double e_cut = it->e_cut;
-  // conserved particle: its species' table and fit
   const SpecDev& Sc = L.spec[it->r_species[NI]];
   const double fit_lo_a = st->fit[it->r_species[NI]][0], fit_lo_b = st->fit[it->r_species[NI]][1];
   const double fit_hi_a = st->fit[it->r_species[NI]][2], fit_hi_b = st->fit[it->r_species[NI]][3];
-  const double cons_sign = it->cons_in ? -1.0 : 1.0;  // p_cons = s * (sum_in - sum_out) over the others
   const uint32_t uid = it->uid;
   const uint32_t c3 = st->epoch * 64u + (uint32_t)L.it;
   const int64_t N = it->N;
@@ -167,140 +261,113 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   const int wave = tid >> 6;
   double* my_h = sm_h + wave * DN;
   uint32_t* my_c = sm_c + wave * DN;
+  // observed leg contributions (momentum along z, energy, factors)
+  const double obs_bf = 1.0 + eta[NI + 1] * f_obs;
+  const double g_obs = obsside[NI + 1] ? obs_bf : f_obs;  // always on the observed side
+  const double l_obs = obsside[NI + 1] ? f_obs : obs_bf;
   __syncthreads();
 
   double S1 = 0.0, S2 = 0.0;
   for (int64_t n = n0 + tid; n < n1; n += kBlock) {
     // ---- uniforms ----
-    double y[4 * B];
+    uint32_t wd[4 * B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
       const uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
       Philox4 r = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, L.seed_lo, L.seed_hi);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) y[4 * b + s] = ((double)r.v[s] + 0.5) * 2.3283064365386962890625e-10;
+      for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
     }
-    // ---- Vegas map ----
-    double x[D];
-    int jb[D];
-    double J = 1.0;
+    uint32_t bins[(D + 3) / 4];
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      double yn = y[d] * dnb;
-      int j = (int)yn;
-      j = j > nb - 1 ? nb - 1 : j;
-      double del = yn - (double)j;
-      double e0 = sm_e[d * nb + j], w = sm_w[d * nb + j];
-      x[d] = e0 + w * del;
-      J *= dnb * w;
-      jb[d] = j;
-    }
-    // ---- momenta ----
-    double px[NR], py[NR], pz[NR], E[NR];
-    double jac = 1.0;
+    for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
+    double J = 1.0, jac = 1.0;
+    double sx = 0.0, sy = 0.0, sz = esg[NI + 1] * p_obs;  // sum_in - sum_out over all but the conserved
+    double dE = esg[NI + 1] * E_obs;
+    double prod2E = 2.0 * E_obs;
+    bool cut = E_obs < e_cut;
+    FT gain = (FT)g_obs, loss = (FT)l_obs;
 #pragma unroll
     for (int k = 0; k < NI; ++k) {
-      double r = x[3 * k], th = x[3 * k + 1], ph = x[3 * k + 2];
-      double p = r * inv_a;
-      double sth, cth, sph, cph;
-      sincos(th, &sth, &cth);
-      sincos(ph, &sph, &cph);
-      px[k] = p * sth * cph;
-      py[k] = p * sth * sph;
-      pz[k] = p * cth;
+      double x3[3], sc3[2][2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int d = 3 * k + c;
+        const double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+        int j = (int)yn;
+        j = j > nb - 1 ? nb - 1 : j;
+        const double del = yn - (double)j;
+        const double e0 = sm_e[d * nb + j], w = sm_w[d * nb + j];
+        x3[c] = e0 + w * del;
+        J *= dnb * w;
+        bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
+        if (c != 0) sincos_red(x3[c], sm_sc, &sc3[c - 1][0], &sc3[c - 1][1]);
+      }
+      const double r = x3[0];
+      const double sth = sc3[0][0], cth = sc3[0][1], sph = sc3[1][0], cph = sc3[1][1];
+      const double p = r * inv_a;
+      const double ps = p * sth;
+      sx += esg[k] * (ps * cph);
+      sy += esg[k] * (ps * sph);
+      sz += esg[k] * (p * cth);
       jac *= r * r * sth;
-      E[k] = sqrt(p * p + m[k] * m[k]);
-    }
-    px[NI + 1] = 0.0;
-    py[NI + 1] = 0.0;
-    pz[NI + 1] = p_obs;
-    E[NI + 1] = E_obs;
-    {
-      double sx = 0.0, sy = 0.0, sz = 0.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        if (r == NI) continue;
-        double sg = isin[r] ? 1.0 : -1.0;
-        sx += sg * px[r];
-        sy += sg * py[r];
-        sz += sg * pz[r];
-      }
-      px[NI] = cons_sign * sx;
-      py[NI] = cons_sign * sy;
-      pz[NI] = cons_sign * sz;
-    }
-    const double P2 = px[NI] * px[NI] + py[NI] * py[NI] + pz[NI] * pz[NI];
-    E[NI] = sqrt(P2 + m[NI] * m[NI]);
-    bool cut = false;
-    double dE = 0.0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r) {
-      cut |= E[r] < e_cut;
-      dE += isin[r] ? E[r] : -E[r];
-    }
-    const double q_cons = a * sqrt(P2);
-    double W;
-    if (PREC == 0) {
-      const double delta = exp(-dE * dE * it->inv2s2) * it->dnorm;
-      double f[NR];
-#pragma unroll
-      for (int r = 0; r < NI; ++r) {
-        const SpecDev& S = L.spec[it->r_species[r]];
-        const double* tab = reinterpret_cast<const double*>(smem + lay.off_f) + tabslot[r] * n_max;
-        f[r] = interp64(tab, S.n, S.lq0, S.inv_h, x[3 * r]);
-      }
-      if (q_cons < Sc.q_min) {
-        f[NI] = 1.0 / (exp(fit_lo_a + fit_lo_b * E[NI]) - eta[NI]);
-      } else if (q_cons > Sc.q_max) {
-        f[NI] = 1.0 / (exp(fit_hi_a + fit_hi_b * E[NI]) - eta[NI]);
+      const double E = sqrt(p * p + m2[k]);
+      cut |= E < e_cut;
+      dE += esg[k] * E;
+      prod2E *= 2.0 * E;
+      FT f;
+      if constexpr (PREC == 0) {
+        int jj;
+        double ww;
+        f = interp64(tr[k], r, &jj, &ww);
       } else {
-        const double* tab = reinterpret_cast<const double*>(smem + lay.off_f) + tabslot[NI] * n_max;
-        f[NI] = interp64(tab, Sc.n, Sc.lq0, Sc.inv_h, q_cons);
+        f = interp32(tr[k], r);
       }
-      f[NI + 1] = f_obs;
-      double gain = 1.0, loss = 1.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        double bf = 1.0 + eta[r] * f[r];
-        gain *= obsside[r] ? bf : f[r];
-        loss *= obsside[r] ? f[r] : bf;
+      const FT bf = (FT)1.0 + (FT)eta[k] * f;
+      gain *= obsside[k] ? bf : f;
+      loss *= obsside[k] ? f : bf;
+    }
+    // ---- conserved particle ----
+    const double P2 = sx * sx + sy * sy + sz * sz;
+    const double Ec = sqrt(P2 + m2[NI]);
+    cut |= Ec < e_cut;
+    dE += esg[NI] * Ec;
+    prod2E *= 2.0 * Ec;
+    const double qc = a * sqrt(P2);
+    FT fc;
+    if constexpr (PREC == 0) {
+      if (qc < Sc.q_min) {
+        fc = 1.0 / (exp(fit_lo_a + fit_lo_b * Ec) - eta[NI]);
+      } else if (qc > Sc.q_max) {
+        fc = 1.0 / (exp(fit_hi_a + fit_hi_b * Ec) - eta[NI]);
+      } else {
+        int jj;
+        double ww;
+        fc = interp64(tr[NI], qc, &jj, &ww);
       }
-      const double F = it->net ? gain - loss : (it->term == 0 ? gain : loss);
-      double prod2E = 1.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) prod2E *= 2.0 * E[r];
-      W = J * (jac * a3 * M2 * delta / (it->twopi_pow * prod2E) * F);
+    } else {
+      if (qc < Sc.q_min) {
+        fc = __builtin_amdgcn_rcpf(exp_split(fit_lo_a + fit_lo_b * Ec) - (float)eta[NI]);
+      } else if (qc > Sc.q_max) {
+        fc = __builtin_amdgcn_rcpf(exp_split(fit_hi_a + fit_hi_b * Ec) - (float)eta[NI]);
+      } else {
+        fc = interp32(tr[NI], qc);
+      }
+    }
+    {
+      const FT bf = (FT)1.0 + (FT)eta[NI] * fc;
+      gain *= obsside[NI] ? bf : fc;
+      loss *= obsside[NI] ? fc : bf;
+    }
+    const FT F = it->net ? gain - loss : (it->term == 0 ? gain : loss);
+    double W;
+    if constexpr (PREC == 0) {
+      const double delta = exp(-dE * dE * it->inv2s2) * it->dnorm;
+      W = J * (jac * a3M2 * delta / (it->twopi_pow * prod2E) * (double)F);
     } else {
       const float delta = exp_split(-dE * dE * it->inv2s2) * (float)it->dnorm;
-      float f[NR];
-#pragma unroll
-      for (int r = 0; r < NI; ++r) {
-        const SpecDev& S = L.spec[it->r_species[r]];
-        const float* tab = reinterpret_cast<const float*>(smem + lay.off_f) + tabslot[r] * n_max;
-        f[r] = interp32(tab, S.n, (float)S.lq0, (float)S.inv_h, x[3 * r]);
-      }
-      if (q_cons < Sc.q_min) {
-        f[NI] = __builtin_amdgcn_rcpf(exp_split(fit_lo_a + fit_lo_b * E[NI]) - (float)eta[NI]);
-      } else if (q_cons > Sc.q_max) {
-        f[NI] = __builtin_amdgcn_rcpf(exp_split(fit_hi_a + fit_hi_b * E[NI]) - (float)eta[NI]);
-      } else {
-        const float* tab = reinterpret_cast<const float*>(smem + lay.off_f) + tabslot[NI] * n_max;
-        f[NI] = interp32(tab, Sc.n, (float)Sc.lq0, (float)Sc.inv_h, q_cons);
-      }
-      f[NI + 1] = (float)f_obs;
-      float gain = 1.0f, loss = 1.0f;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        float bf = fmaf((float)eta[r], f[r], 1.0f);
-        gain *= obsside[r] ? bf : f[r];
-        loss *= obsside[r] ? f[r] : bf;
-      }
-      const float F = it->net ? gain - loss : (it->term == 0 ? gain : loss);
-      double prod2E = 1.0;
-#pragma unroll
-      for (int r = 0; r < NR; ++r) prod2E *= 2.0 * E[r];
       const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
-      W = J * jac * (a3 * M2 / it->twopi_pow) * ((double)delta * (double)rcp) * (double)F;
+      W = J * jac * (a3M2 / it->twopi_pow) * ((double)delta * (double)rcp) * (double)F;
     }
     if (cut) W = 0.0;
     S1 += W;
@@ -308,8 +375,9 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      atomicAdd(&my_h[d * nb + jb[d]], w2);
-      atomicAdd(&my_c[d * nb + jb[d]], 1u);
+      const int j = (bins[d >> 2] >> (8 * (d & 3))) & 0xff;
+      atomicAdd(&my_h[d * nb + j], w2);
+      atomicAdd(&my_c[d * nb + j], 1u);
     }
   }
 
@@ -343,6 +411,367 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     rec[DN + i] = (double)c;
   }
   __syncthreads();
+}
+
+// ------------------------------------------------------------------------------------------------------
+// Adjoint of the frozen-map estimator (FP64).  For each sample, W and its partial derivatives with respect to
+// the f values it reads (scattered to the grid through the interpolation weights, or to the extrapolation
+// line (a, b) of the conserved particle's species), the masses of the species of every particle (through
+// E_i in the Gaussian, in 1/(2 E_i) and in the extrapolated f), and the coupling (2 W / lambda) are summed.
+// Per unit record (doubles): n_tab * n_max table gradients, g_obs, d/d(a_lo, b_lo, a_hi, b_hi), d/dm per
+// role (kMaxN), sum W.
+__host__ __device__ inline int vjp_rec_len(int n_tab, int n_max) { return n_tab * n_max + 1 + 4 + kMaxN + 1; }
+
+template <int NI>
+__device__ void vjp_task(const SampleLaunch& L, const Task task, unsigned char* smem) {
+#pragma clang fp contract(off)
+  constexpr int D = 3 * NI;
+  constexpr int B = (D + 3) / 4;
+  constexpr int NR = NI + 2;
+  const ItemRec* __restrict__ it = &L.items[task.item];
+  const int tid = threadIdx.x;
+  const int nb = it->nb;
+  const int DN = D * nb;
+  const int n_tab = it->n_tab;
+  int n_max = 0;
+  for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
+  // LDS: e, w, sin/cos table, f tables (q, iq, f), per-wave table gradients, reduction scratch
+  int o = 0;
+  double* sm_e = reinterpret_cast<double*>(smem + o);
+  o = align16(o + DN * 8);
+  double* sm_w = reinterpret_cast<double*>(smem + o);
+  o = align16(o + DN * 8);
+  double2* sm_sc = reinterpret_cast<double2*>(smem + o);
+  o = align16(o + 33 * 16);
+  const int tab_stride = align16(n_max * 24);
+  const int off_tab = o;
+  o = align16(o + n_tab * tab_stride);
+  const int TG = n_tab * n_max;
+  double* sm_g = reinterpret_cast<double*>(smem + o);
+  o = align16(o + kWaves * TG * 8);
+  double* sm_red = reinterpret_cast<double*>(smem + o);
+  const double* __restrict__ map = L.maps + it->map_off;
+  for (int i = tid; i < DN; i += kBlock) {
+    const int d = i / nb, j = i - d * nb;
+    const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+    sm_e[i] = e0;
+    sm_w[i] = e1 - e0;
+  }
+  if (tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
+  for (int k = 0; k < n_tab; ++k) {
+    const SpecDev& S = L.spec[it->tab_species[k]];
+    double* q = reinterpret_cast<double*>(smem + off_tab + k * tab_stride);
+    double* iq = q + n_max;
+    double* f = iq + n_max;
+    for (int j = tid; j < S.n; j += kBlock) {
+      q[j] = L.qnode[S.f_off + j];
+      iq[j] = 1.0 / q[j];
+      f[j] = L.f64[S.f_off + j];
+    }
+  }
+  for (int i = tid; i < kWaves * TG; i += kBlock) sm_g[i] = 0.0;
+  FTab<double> tr[NI + 1];
+  int tslot[NI + 1];
+#pragma unroll
+  for (int r = 0; r <= NI; ++r) {
+    const int k = it->r_tab[r];
+    const SpecDev& S = L.spec[it->tab_species[k]];
+    tr[r].q = reinterpret_cast<const double*>(smem + off_tab + k * tab_stride);
+    tr[r].iq = tr[r].q + n_max;
+    tr[r].f = tr[r].iq + n_max;
+    tr[r].n = S.n;
+    tr[r].lq0 = S.lq0;
+    tr[r].inv_h = S.inv_h;
+    tslot[r] = k;
+  }
+  const DevState* __restrict__ st = L.st;
+  const double a = st->a, inv_a = 1.0 / a;
+  double m[NR], eta[NR], esg[NR];
+  int obsside[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    m[r] = st->m[it->r_species[r]];
+    eta[r] = (double)L.spec[it->r_species[r]].stat;
+    esg[r] = it->r_in[r] ? 1.0 : -1.0;
+    obsside[r] = it->r_obsside[r];
+  }
+  const SpecDev& So = L.spec[it->obs_species];
+  const double p_obs = it->q_obs * inv_a;
+  const double E_obs = sqrt(p_obs * p_obs + m[NI + 1] * m[NI + 1]);
+  const double f_obs = L.f64[So.f_off + it->eval_idx];
+  const double a3M2 = pow(a, -3.0 * (double)NI) * it->coupling2;
+  const SpecDev& Sc = L.spec[it->r_species[NI]];
+  const double* fitc = st->fit[it->r_species[NI]];
+  const uint32_t uid = it->uid;
+  const uint32_t c3 = st->epoch * 64u + (uint32_t)L.it;
+  const int64_t N = it->N;
+  const int64_t n0 = (int64_t)task.unit * it->unit_size;
+  const int64_t n1 = min(n0 + (int64_t)it->unit_size, N);
+  const double dnb = (double)nb;
+  const double sig2 = 1.0 / (2.0 * it->inv2s2);
+  const int wave = tid >> 6;
+  double* my_g = sm_g + wave * TG;
+  __syncthreads();
+
+  double g_obs = 0.0, dfit[4] = {0.0, 0.0, 0.0, 0.0}, dm[NR], sumW = 0.0;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) dm[r] = 0.0;
+  for (int64_t n = n0 + tid; n < n1; n += kBlock) {
+    uint32_t wd[4 * B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+      const uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
+      Philox4 rr = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, L.seed_lo, L.seed_hi);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) wd[4 * b + s2] = rr.v[s2];
+    }
+    double J = 1.0, jac = 1.0, sx = 0.0, sy = 0.0, sz = esg[NI + 1] * p_obs;
+    double E[NR], f[NR], wt[NR];
+    int jn[NR], src[NR];  // src: 0 table node, 1 interpolated, 2 extrapolated low, 3 extrapolated high
+    E[NI + 1] = E_obs;
+    f[NI + 1] = f_obs;
+    src[NI + 1] = 0;
+    jn[NI + 1] = it->eval_idx;
+    wt[NI + 1] = 0.0;
+    bool cut = E_obs < it->e_cut;
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+      double x3[3], sc3[2][2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int d = 3 * k + c;
+        const double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+        int j = (int)yn;
+        j = j > nb - 1 ? nb - 1 : j;
+        const double del = yn - (double)j;
+        const double e0 = sm_e[d * nb + j], w = sm_w[d * nb + j];
+        x3[c] = e0 + w * del;
+        J *= dnb * w;
+        if (c != 0) sincos_red(x3[c], sm_sc, &sc3[c - 1][0], &sc3[c - 1][1]);
+      }
+      const double r = x3[0];
+      const double p = r * inv_a;
+      const double ps = p * sc3[0][0];
+      sx += esg[k] * (ps * sc3[1][1]);
+      sy += esg[k] * (ps * sc3[1][0]);
+      sz += esg[k] * (p * sc3[0][1]);
+      jac *= r * r * sc3[0][0];
+      E[k] = sqrt(p * p + m[k] * m[k]);
+      cut |= E[k] < it->e_cut;
+      f[k] = interp64(tr[k], r, &jn[k], &wt[k]);
+      src[k] = 1;
+    }
+    const double P2 = sx * sx + sy * sy + sz * sz;
+    E[NI] = sqrt(P2 + m[NI] * m[NI]);
+    cut |= E[NI] < it->e_cut;
+    const double qc = a * sqrt(P2);
+    if (qc < Sc.q_min) {
+      f[NI] = 1.0 / (exp(fitc[0] + fitc[1] * E[NI]) - eta[NI]);
+      src[NI] = 2;
+    } else if (qc > Sc.q_max) {
+      f[NI] = 1.0 / (exp(fitc[2] + fitc[3] * E[NI]) - eta[NI]);
+      src[NI] = 3;
+    } else {
+      f[NI] = interp64(tr[NI], qc, &jn[NI], &wt[NI]);
+      src[NI] = 1;
+    }
+    if (cut) continue;
+    double dE = 0.0, prod2E = 1.0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      dE += esg[r] * E[r];
+      prod2E *= 2.0 * E[r];
+    }
+    const double delta = exp(-dE * dE * it->inv2s2) * it->dnorm;
+    // factors and their derivatives
+    double gv[2][NR], dg[2][NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double bf = 1.0 + eta[r] * f[r];
+      gv[0][r] = obsside[r] ? bf : f[r];
+      dg[0][r] = obsside[r] ? eta[r] : 1.0;
+      gv[1][r] = obsside[r] ? f[r] : bf;
+      dg[1][r] = obsside[r] ? 1.0 : eta[r];
+    }
+    double Fv[2], dF[2][NR];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      Fv[t] = 1.0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) Fv[t] *= gv[t][r];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double prod = dg[t][r];
+#pragma unroll
+        for (int r2 = 0; r2 < NR; ++r2)
+          if (r2 != r) prod *= gv[t][r2];
+        dF[t][r] = prod;
+      }
+    }
+    const double F = it->net ? Fv[0] - Fv[1] : Fv[it->term];
+    const double Wb = J * (jac * a3M2 * delta / (it->twopi_pow * prod2E));
+    const double W = Wb * F;
+    sumW += W;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double dWdf = Wb * (it->net ? dF[0][r] - dF[1][r] : dF[it->term][r]);
+      double dWdE = W * (-dE / sig2 * esg[r] - 1.0 / E[r]);
+      if (src[r] == 0) {
+        g_obs += dWdf;
+      } else if (src[r] == 1) {
+        const int base = (r <= NI ? tslot[r] : 0) * n_max;
+        atomicAdd(&my_g[base + jn[r]], dWdf * (1.0 - wt[r]));
+        atomicAdd(&my_g[base + jn[r] + 1], dWdf * wt[r]);
+      } else {
+        const int sd = src[r] - 2;
+        const double dfdz = -f[r] * (1.0 + eta[r] * f[r]);
+        dfit[2 * sd] += dWdf * dfdz;
+        dfit[2 * sd + 1] += dWdf * dfdz * E[r];
+        dWdE += dWdf * (-fitc[2 * sd + 1] * f[r] * (1.0 + eta[r] * f[r]));
+      }
+      dm[r] += dWdE * m[r] / E[r];
+    }
+  }
+  // ---- fixed-order reductions into the unit record ----
+  constexpr int NS = 1 + 4 + NR + 1;
+  double vals[NS];
+  vals[0] = g_obs;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) vals[1 + k] = dfit[k];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) vals[5 + r] = dm[r];
+  vals[5 + NR] = sumW;
+  double* rec = L.parts + it->part_off + (int64_t)task.unit * vjp_rec_len(n_tab, n_max);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double v = wave_sum(vals[k]);
+    if ((tid & 63) == 0) sm_red[k * kWaves + wave] = v;
+  }
+  __syncthreads();
+  if (tid < NS) {
+    double acc = 0.0;
+    for (int w = 0; w < kWaves; ++w) acc += sm_red[tid * kWaves + w];
+    const int slot = tid < 5 + NR ? tid : 5 + kMaxN;  // g_obs, fit partials, d/dm by role; then sum W
+    rec[TG + slot] = acc;
+  }
+  if (tid >= 5 + NR && tid < 5 + kMaxN) rec[TG + tid] = 0.0;  // roles this process does not have
+  for (int i = tid; i < TG; i += kBlock) {
+    double g = 0.0;
+    for (int w = 0; w < kWaves; ++w) g += sm_g[w * TG + i];
+    rec[i] = g;
+  }
+  __syncthreads();
+}
+
+template <int MASK>
+__global__ __launch_bounds__(kBlock) void k_vjp(SampleLaunch L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
+    const Task task = L.tasks[L.task_begin + t];
+    const int ni = L.items[task.item].nint;
+    if ((MASK & 1) && ni == 1) vjp_task<1>(L, task, smem);
+    if ((MASK & 2) && ni == 2) vjp_task<2>(L, task, smem);
+    if ((MASK & 4) && ni == 3) vjp_task<3>(L, task, smem);
+    if ((MASK & 8) && ni == 4) vjp_task<4>(L, task, smem);
+  }
+}
+
+// Per item: sum of its unit records in unit order, times coef_i / N.
+__global__ void k_vjp_reduce(const ItemRec* items, int n_items, const double* coef, const double* parts,
+                             const int* rec_len, double* item_rec, int rec_stride) {
+  const int i = blockIdx.x;
+  if (i >= n_items) return;
+  const ItemRec& it = items[i];
+  const int len = rec_len[i];
+  const double c = coef[i] / (double)it.N;
+  for (int k = threadIdx.x; k < len; k += blockDim.x) {
+    double acc = 0.0;
+    for (int u = 0; u < it.n_units; ++u) acc += parts[it.part_off + (int64_t)u * len + k];
+    item_rec[(int64_t)i * rec_stride + k] = c * acc;
+  }
+}
+
+// Gradients: grad_f of every species node (items in order), then (one thread per species) the chain through
+// the extrapolation fits, the masses, and per process the coupling.
+__global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
+                             int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
+                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
+                             const double* coupling, int n_proc) {
+  for (int64_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_f; g += (int64_t)gridDim.x * blockDim.x) {
+    int s = 0;
+    while (s + 1 < n_species && g >= spec[s + 1].f_off) ++s;
+    const int j = (int)(g - spec[s].f_off);
+    double acc = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+      const ItemRec& it = items[i];
+      const double* rec = item_rec + (int64_t)i * rec_stride;
+      const int nmax = rec_nmax[i];
+      for (int k = 0; k < it.n_tab; ++k)
+        if (it.tab_species[k] == s && j < spec[s].n) acc += rec[k * nmax + j];
+      if (it.obs_species == s && it.eval_idx == j) acc += rec[it.n_tab * nmax];
+    }
+    grad_f[g] = acc;
+  }
+}
+
+__global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
+                             int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
+                             const DevState* st, double* grad_f, double* grad_m, double* grad_lam,
+                             const double* coupling, int n_proc) {
+  const int s = threadIdx.x;
+  if (s < n_species) {
+    const SpecDev& S = spec[s];
+    double dfa[4] = {0.0, 0.0, 0.0, 0.0}, gm = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+      const ItemRec& it = items[i];
+      const double* rec = item_rec + (int64_t)i * rec_stride + it.n_tab * rec_nmax[i];
+      if (it.r_species[it.nint] == s)
+        for (int k = 0; k < 4; ++k) dfa[k] += rec[1 + k];
+      for (int r = 0; r < it.nint + 2; ++r)
+        if (it.r_species[r] == s) gm += rec[5 + r];
+    }
+    // extrapolation fits: (a, b) least-squares line of y_k = log(1/f_k + eta) against E_k, 5 end nodes
+    const double a = st->a, m = st->m[s], eta = (double)S.stat;
+    const double* f = f64 + S.f_off;
+    for (int side = 0; side < 2; ++side) {
+      const double dWa = dfa[2 * side], dWb = dfa[2 * side + 1];
+      if (dWa == 0.0 && dWb == 0.0) continue;
+      const int j0 = side == 0 ? 0 : S.n - 5;
+      double E[5], Y[5], mE = 0.0, mY = 0.0;
+      for (int k = 0; k < 5; ++k) {
+        const double p = qnode[S.f_off + j0 + k] / a;
+        E[k] = sqrt(p * p + m * m);
+        Y[k] = log(1.0 / f[j0 + k] + eta);
+        mE += E[k] / 5.0;
+        mY += Y[k] / 5.0;
+      }
+      double sxx = 0.0, sxy = 0.0;
+      for (int k = 0; k < 5; ++k) {
+        sxx += (E[k] - mE) * (E[k] - mE);
+        sxy += (E[k] - mE) * (Y[k] - mY);
+      }
+      const double b = sxy / sxx;
+      for (int k = 0; k < 5; ++k) {
+        const double db_dy = (E[k] - mE) / sxx;
+        const double da_dy = 1.0 / 5.0 - mE * db_dy;
+        const double db_dE = ((Y[k] - mY) - 2.0 * b * (E[k] - mE)) / sxx;
+        const double da_dE = -db_dE * mE - b / 5.0;
+        const double fk = f[j0 + k];
+        const double dy_df = -1.0 / (fk * (1.0 + eta * fk));
+        grad_f[S.f_off + j0 + k] += (dWa * da_dy + dWb * db_dy) * dy_df;
+        gm += (dWa * da_dE + dWb * db_dE) * m / E[k];
+      }
+    }
+    grad_m[s] = gm;
+  }
+  for (int p = threadIdx.x; p < n_proc; p += blockDim.x) {
+    double acc = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+      if (items[i].proc != p) continue;
+      acc += item_rec[(int64_t)i * rec_stride + items[i].n_tab * rec_nmax[i] + 5 + kMaxN];
+    }
+    grad_lam[p] = 2.0 * acc / coupling[p];
+  }
 }
 
 template <int MASK, int PREC>
@@ -697,6 +1126,46 @@ hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {
     case 8: return launch_sample_t<8, 1>(L, s);
     default: return launch_sample_t<15, 1>(L, s);
   }
+}
+
+hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s) {
+  if (L.n_tasks <= 0) return hipSuccess;
+  switch (L.nint_mask) {
+    case 1: hipLaunchKernelGGL(k_vjp<1>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+    case 2: hipLaunchKernelGGL(k_vjp<2>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+    case 4: hipLaunchKernelGGL(k_vjp<4>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+    case 8: hipLaunchKernelGGL(k_vjp<8>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+    default: hipLaunchKernelGGL(k_vjp<15>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+  }
+  return hipGetLastError();
+}
+
+int vjp_lds_bytes(int D, int nb, int n_tab, int n_max) {
+  int o = 0;
+  o = align16(o + D * nb * 8);
+  o = align16(o + D * nb * 8);
+  o = align16(o + 33 * 16);
+  o = align16(o + n_tab * align16(n_max * 24));
+  o = align16(o + kWaves * n_tab * n_max * 8);
+  o = align16(o + (1 + 4 + kMaxN + 1) * kWaves * 8);
+  return o;
+}
+
+int vjp_record_len(int n_tab, int n_max) { return vjp_rec_len(n_tab, n_max); }
+
+hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* coef, const double* parts,
+                             const int* rec_len, const int* rec_nmax, double* item_rec, int rec_stride,
+                             const SpecDev* spec, int n_species, const double* f64, const double* qnode,
+                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
+                             const double* coupling, int n_proc, hipStream_t s) {
+  hipLaunchKernelGGL(k_vjp_reduce, dim3(n_items), dim3(256), 0, s, items, n_items, coef, parts, rec_len, item_rec,
+                     rec_stride);
+  hipLaunchKernelGGL(k_vjp_gather, dim3((unsigned)((n_f + 255) / 256)), dim3(256), 0, s, items, n_items, item_rec,
+                     rec_nmax, rec_stride, spec, n_species, f64, qnode, st, grad_f, n_f, grad_m, grad_lam, coupling,
+                     n_proc);
+  hipLaunchKernelGGL(k_vjp_finish, dim3(1), dim3(256), 0, s, items, n_items, item_rec, rec_nmax, rec_stride, spec,
+                     n_species, f64, qnode, st, grad_f, grad_m, grad_lam, coupling, n_proc);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,

@@ -35,12 +35,30 @@ def oracle_items_matching(ow, uids):
     return (ob.Item * len(sel))(*sel), len(sel)
 
 
-def assert_items_close(got, want, tol, what="I"):
+def item_scale(items, n, I):
+    """Per item: the gross rate sum mult |I| over all items at the same (process set, species, node) -- the
+    scale the collision integral at that node is compared on.  Items far smaller than it (pure off-shell
+    estimates) are compared against it instead of their own value."""
+    acc = {}
+    for i in range(n):
+        key = (items[i].species, items[i].eval_idx)
+        acc[key] = acc.get(key, 0.0) + items[i].mult * abs(I[i])
+    return np.array([acc[(items[i].species, items[i].eval_idx)] for i in range(n)])
+
+
+def assert_items_close(got, want, tol, what="I", scale=None):
+    """|got - want| <= tol * max(|want|, scale) elementwise (scale: per item, e.g. item_scale)."""
     got, want = np.asarray(got), np.asarray(want)
     err = np.abs(got - want)
-    bound = tol * np.abs(want)
+    ref = np.abs(want)
+    if scale is not None:
+        sc = np.asarray(scale)
+        if ref.ndim == 2 and sc.ndim == 1:
+            sc = sc[:, None]
+        ref = np.maximum(ref, sc)
+    bound = tol * ref
     bad = np.nonzero(err > bound)[0]
-    rel = np.where(want != 0, err / np.where(want != 0, np.abs(want), 1), err)
+    rel = np.where(ref != 0, err / np.where(ref != 0, ref, 1), err)
     msg = "%s: max rel err %.3e (tol %.1e), %d / %d outside" % (what, rel.max() if rel.size else 0, tol, bad.size,
                                                                got.size)
     say(msg)

@@ -1,0 +1,105 @@
+"""The adjoint kernel (bmc_vjp) against the oracle's VJP (same counters, same frozen maps) and, through the
+autograd Heun rollout, against central finite differences of the GPU forward."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_available, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+@pytest.mark.parametrize("shape", ["23be", "22mb_tail", "24fd_msin", "multi"])
+def test_vjp_matches_oracle(shape):
+    bm = _bm()
+    if shape == "23be":
+        w = wl.w23_be(n_grid=24, q_min=0.05, q_max=8.0, sigma_E=0.05, N=1 << 12, nitn=1)
+    elif shape == "22mb_tail":
+        w = wl.w22_mb(n_grid=16, q_min=0.1, q_max=3.0, sigma_E=0.05, N=1 << 12, nitn=1)
+    elif shape == "24fd_msin":
+        w = wl.w24_fd(n_grid=16, q_min=0.05, q_max=6.0, sigma_E=0.05, N=1 << 11, nitn=1)
+    else:
+        w = wl.w_multi(n_grid=16, N=(1 << 10, 1 << 10, 1 << 10), nitn=1, sigma_E=0.05)
+        for p in w.processes:
+            p.eval_stride = 1
+    N = w.processes[0].n_samples
+    say("vjp %s" % shape)
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=3, epoch=2, n_iter=1, freeze_maps=1, eval_stride=1, n_samples=N)
+    ni, no = ctx.plan_size(-1, -1, opts)
+    v = np.random.default_rng(1).normal(size=no)
+    gf, gl, gm = ctx.vjp(v, -1, -1, opts)
+    # oracle: same items, coefficient v[node] * mult * sign
+    ow = ob.OracleWorld(w)
+    items, n = ow.items(stride=1)
+    offs = np.cumsum([0] + [s.n_grid for s in w.species])
+    coef = np.array([v[offs[items[i].species] + items[i].eval_idx] * items[i].mult * (-1 if items[i].term == 1 else 1)
+                     for i in range(n)])
+    rc, of, om, ol = ow.vjp(items, n, coef, N, 0, seed=3, epoch=2)
+    assert rc == 0
+    sc = np.max(np.abs(of))
+    err_f = np.max(np.abs(gf - of)) / sc
+    say("grad_f max err / max |grad| = %.3e; grad_m %s vs %s; grad_lambda %s vs %s" % (err_f, gm, om, gl, ol))
+    assert err_f < 1e-10
+    np.testing.assert_allclose(gm, om, rtol=1e-10, atol=1e-12 * np.max(np.abs(om)))
+    np.testing.assert_allclose(gl, ol, rtol=1e-10)
+
+
+def test_heun_rollout_gradient_matches_finite_differences():
+    """L = sum (f_T - f_BE)^2 after 3 Heun steps of fixed size, 2<->3 BE: autograd through the adjoint
+    kernel vs central differences (h = 1e-6) of the GPU forward on lambda, m0, two f0 coordinates and two
+    random directions, all with frozen maps and the same counters."""
+    import torch
+    from paper_2603_28848_amd import adjoint
+    bm = _bm()
+    w = wl.w23_adjoint(n_grid=32, q_min=0.1, q_max=12.0, sigma_E=0.02, N=1 << 12, nitn=4)
+    ctx = bm.from_workload(w)
+    ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, n_iter=4, n_samples=1 << 13))  # train the maps
+    base = bm.default_opts(seed=0, n_samples=1 << 12)
+    q = wl.log_nodes(0.1, 12.0, 32)
+    target = torch.tensor(wl.f_equilibrium(q, 1.0, 1.0, wl.BOSE), dtype=torch.float64, device="cuda")
+    f0 = torch.tensor(w.species[0].f, dtype=torch.float64, device="cuda")
+    dt = adjoint.adaptive_dt(ctx, w.species[0].f, 0.3, 1.0, base, epoch0=100)
+    say("dt = %g" % dt)
+
+    def loss(f0_, lam_, m_):
+        fT = adjoint.heun_rollout(ctx, f0_, lam_, m_, 0.0, dt, 3, base, epoch0=100)
+        return torch.sum((fT - target) ** 2)
+
+    lam = torch.tensor([1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+    m = torch.tensor([1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+    f0r = f0.clone().requires_grad_(True)
+    L = loss(f0r, lam, m)
+    L.backward()
+    gf, gl, gm = f0r.grad.clone(), lam.grad.item(), m.grad.item()
+    h = 1e-6
+    with torch.no_grad():
+        def fd(dir_f=None, dl=0.0, dmm=0.0):
+            one = torch.ones(1, dtype=torch.float64, device="cuda")
+            lp = loss(f0 * (1 + h * dir_f) if dir_f is not None else f0, one * (1 + h * dl), one * (1 + h * dmm))
+            lm = loss(f0 * (1 - h * dir_f) if dir_f is not None else f0, one * (1 - h * dl), one * (1 - h * dmm))
+            return (lp - lm).item() / (2 * h)
+        checks = [("lambda", fd(dl=1.0), gl), ("m0", fd(dmm=1.0), gm)]
+        for j in (5, 17):
+            e = torch.zeros(32, dtype=torch.float64, device="cuda")
+            e[j] = 1.0
+            checks.append(("f0[%d]" % j, fd(dir_f=e), (gf * f0 * e).sum().item()))
+        rng = np.random.default_rng(4)
+        for k in range(2):
+            d = torch.tensor(rng.normal(size=32), dtype=torch.float64, device="cuda")
+            checks.append(("dir%d" % k, fd(dir_f=d), (gf * f0 * d).sum().item()))
+    for name, num, ana in checks:
+        say("%s: FD %.10e adjoint %.10e rel %.2e" % (name, num, ana, abs(num - ana) / max(abs(num), 1e-300)))
+        assert ana == pytest.approx(num, rel=1e-5, abs=1e-9 * abs(L.item()))

@@ -4,11 +4,17 @@ time-dependent mass; plus the log-space Euler/Heun steps and HIP-graph replay.""
 import numpy as np
 import pytest
 
-from gpu_util import TOL, assert_items_close, gpu_available, oracle_items_matching, say
+from gpu_util import TOL, assert_items_close, gpu_available, item_scale, oracle_items_matching, say
 from oracle import binding as ob
 from paper_2603_28848_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
+
+# Per-sample relative error of the Gaussian delta from an absolute difference e in dE is ~ (dE/sigma_E)(e/sigma_E);
+# with dE summed from up to six energies of O(10-40), e ~ 1e-14, so at sigma_E = 0.002 one on-shell sample
+# differs by ~5e-12.  Items estimated from a few such samples (reduced sample counts, uniform maps) are
+# checked at 1e-10; well-sampled items meet 1e-12.
+FEW_SAMPLE_TOL = 1e-10
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -51,7 +57,11 @@ def test_multi_species_expansion_subset(precision):
     items, n = oracle_items_matching(ow, res["uid"][pick])
     rc, r = ow.run_items(items, n, 1 << 12, 2, seed=11, epoch=5, adapt=False)
     assert rc == 0
-    assert_items_close(res["I_it"][pick], r["I_it"], TOL[precision] * (10 if precision == 0 else 1), "I_it")
+    scale = item_scale(items, n, r["Ibar"])
+    # 2^12 samples on a uniform map hit the 2->4 energy shell rarely: FP64 items then rest on a handful of
+    # samples, each carrying the ulp-level difference of dE amplified by 1/sigma_E (see FEW_SAMPLE_TOL)
+    tol = TOL[precision] if precision == 1 else FEW_SAMPLE_TOL
+    assert_items_close(res["I_it"][pick], r["I_it"], tol, "I_it", scale=scale)
 
 
 def test_multi_species_full_grid_fill_matches_oracle():
@@ -83,7 +93,25 @@ def test_2to4_fermi_time_dependent_mass_subset(precision):
     items, n = oracle_items_matching(ow, res["uid"][pick])
     rc, r = ow.run_items(items, n, 1 << 14, 2, adapt=False)
     assert rc == 0
-    assert_items_close(res["I_it"][pick], r["I_it"], TOL[precision] * (10 if precision == 0 else 1), "I_it")
+    scale = item_scale(items, n, r["Ibar"])
+    tol = TOL[precision] if precision == 1 else FEW_SAMPLE_TOL
+    assert_items_close(res["I_it"][pick], r["I_it"], tol, "I_it", scale=scale)
+
+
+def test_2to4_full_size_sampled_items_fp64():
+    """2->4 FD at the full 2^22 samples per item and iteration (one iteration on the uniform map, all 2048
+    items in one batched launch): sampled items at the FP64 tolerance."""
+    bm = _bm()
+    w = wl.w24_fd(nitn=1)
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(-1, -1, bm.default_opts(seed=0, precision=0, freeze_maps=1, n_iter=1))
+    res = ctx.item_results(1)
+    pick = [i for i, u in enumerate(res["uid"]) if (int(u) & 0x3FFFF) in (40, 200)]
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"][pick])
+    rc, r = ow.run_items(items, n, 1 << 22, 1, adapt=False)
+    assert rc == 0
+    assert_items_close(res["I_it"][pick], r["I_it"], TOL[0], "I_it", scale=item_scale(items, n, r["Ibar"]))
 
 
 # ------------------------------------------------------------------------------------------------ steps
@@ -119,14 +147,18 @@ def test_multi_species_heun_step_with_expansion():
 
 
 def test_graph_replay_equals_eager_steps():
+    """Three Heun steps captured in a HIP graph (on a side stream of default priority) and replayed twice
+    reproduce six eager steps bitwise; the eager program's own synchronisations sit between the replays."""
+    import torch
     bm = _bm()
     w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
     opts = bm.default_opts(seed=9, epoch=10, precision=1)
+    side = torch.cuda.Stream()
     eager = bm.from_workload(w)
     for k in range(3):
         opts.epoch = 10 + 2 * k
         eager.step(1, -1.0, 0.3, 1.0, opts)
-    g = bm.from_workload(w)
+    g = bm.from_workload(w, stream=side)
     opts.epoch = 10
     g.graph_capture_steps(3, 1, -1.0, 0.3, 1.0, opts)
     g.graph_replay()
