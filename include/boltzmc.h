@@ -219,9 +219,15 @@ int bmc_set_timing(bmc_ctx* ctx, int on);
 /* Sum of the timed sample-kernel durations (ms) and number of timed launches since the last reset;
  * synchronises the stream.  reset != 0 clears the counters after reading. */
 int bmc_get_timing(bmc_ctx* ctx, int reset, double* sample_ms, int* n_launches);
-/* Resident blocks per compute unit of the persistent batched launch (0 = from the LDS need).  Results do not
- * depend on it. */
-int bmc_set_launch_tuning(bmc_ctx* ctx, int blocks_per_cu);
+/* Launch shape of the persistent batched sample kernel: resident blocks per compute unit (0 = from the LDS
+ * need) and the number of consecutive tasks (units of samples) a block takes per visit.  Results do not
+ * depend on either: every unit's partial sums are formed in the same fixed order by whichever block runs it. */
+int bmc_set_launch_tuning(bmc_ctx* ctx, int blocks_per_cu, int chunk);
+/* Times one frozen-map iteration of the (process, species, opts) plan for every launch shape (blocks per CU
+ * 1 .. the LDS limit, chunk 1/2/4/8/16), keeps the fastest in the context and reports it.  No Vegas map,
+ * f or time is changed. */
+int bmc_autotune(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, int* blocks_per_cu, int* chunk,
+                 double* best_ms);
 
 /* ---- misc ---- */
 const char* bmc_last_error(bmc_ctx* ctx);

@@ -81,7 +81,9 @@ _SIGS = {
                 C.c_void_p, C.c_int],
     "bmc_set_timing": [C.c_void_p, C.c_int],
     "bmc_get_timing": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
-    "bmc_set_launch_tuning": [C.c_void_p, C.c_int],
+    "bmc_set_launch_tuning": [C.c_void_p, C.c_int, C.c_int],
+    "bmc_autotune": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                     C.POINTER(C.c_double)],
     "bmc_last_error": [C.c_void_p],
     "bmc_version": [],
 }
@@ -311,8 +313,18 @@ class Context:
         self._check(lib().bmc_get_timing(self.h, int(reset), C.byref(ms), C.byref(n)))
         return ms.value, n.value
 
-    def set_launch_tuning(self, blocks_per_cu):
-        self._check(lib().bmc_set_launch_tuning(self.h, blocks_per_cu))
+    def set_launch_tuning(self, blocks_per_cu, chunk=4):
+        self._check(lib().bmc_set_launch_tuning(self.h, blocks_per_cu, chunk))
+
+    def autotune(self, process=-1, species=-1, opts: Optional[RunOpts] = None):
+        """Picks the fastest persistent launch shape for this plan; returns (blocks_per_cu, chunk, ms)."""
+        opts = opts or default_opts()
+        self.plan_size(process, species, opts)
+        self.ensure_workspace(opts.n_samples, opts.n_iter)
+        b, ch, ms = C.c_int(), C.c_int(), C.c_double()
+        self._check(lib().bmc_autotune(self.h, process, species, C.byref(opts), C.byref(b), C.byref(ch),
+                                       C.byref(ms)))
+        return b.value, ch.value, ms.value
 
     def graph_replay(self):
         self._check(lib().bmc_graph_replay(self.h))

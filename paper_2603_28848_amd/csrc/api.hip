@@ -121,7 +121,8 @@ struct bmc_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   // tuning
-  int blocks_per_cu = 0;  // 0: from occupancy
+  int blocks_per_cu = 0;  // 0: from the LDS need
+  int chunk = 4;          // consecutive tasks per block visit
   int n_cu = 0;
   // optional timing of the sample kernel (eager launches only)
   bool timing = false;
@@ -713,13 +714,15 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         L.task_begin = P.plain_node_begin[g];
         L.n_tasks = P.plain_node_begin[g + 1] - P.plain_node_begin[g];
         L.grid = L.n_tasks;
+        L.chunk = 1;
         HIPCHK(c, timed_sample(c, L, s));
       }
     } else {
       L.tasks = P.d_tb;
       L.task_begin = 0;
       L.n_tasks = P.tasks_per_iter[k];
-      L.grid = std::min(L.n_tasks, grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask));
+      L.chunk = c->chunk;
+      L.grid = std::min((L.n_tasks + L.chunk - 1) / L.chunk, grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask));
       HIPCHK(c, timed_sample(c, L, s));
     }
     HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_unit_s, P.d_unit_base, P.d_parts,
@@ -1443,6 +1446,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   L.nint_mask = P.nint_mask;
   L.precision = BMC_FP64;
   L.lds_bytes = lds;
+  L.chunk = 1;
   L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
   HIPCHK(c, launch_vjp(L, s));
   HIPCHK(c, launch_vjp_finish(d_items, (int)nI, d_coef, d_parts, d_len, d_nmax, d_rec, rec_stride, c->spec(),
@@ -1482,10 +1486,77 @@ int bmc_get_timing(bmc_ctx* c, int reset, double* sample_ms, int* n_launches) {
   return BMC_OK;
 }
 
-int bmc_set_launch_tuning(bmc_ctx* c, int blocks_per_cu) {
-  if (!c || blocks_per_cu < 0 || blocks_per_cu > 64) return BMC_EINVAL;
+int bmc_set_launch_tuning(bmc_ctx* c, int blocks_per_cu, int chunk) {
+  if (!c || blocks_per_cu < 0 || blocks_per_cu > 64 || chunk < 1 || chunk > 64) return BMC_EINVAL;
   c->blocks_per_cu = blocks_per_cu;
+  c->chunk = chunk;
   return BMC_OK;
+}
+
+int bmc_autotune(bmc_ctx* c, int process, int species, const bmc_run_opts* o, int* blocks_per_cu, int* chunk,
+                 double* best_ms) {
+  if (!c) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  // calibration evaluations: one iteration, maps frozen (no state changes), a throw-away epoch
+  bmc_run_opts q = *o;
+  q.n_iter = 1;
+  q.freeze_maps = 1;
+  q.launch = BMC_LAUNCH_BATCHED;
+  rc = get_plan(c, c->plan, process, species, &q);
+  if (rc) return rc;
+  Plan& P = c->plan;
+  const int saved_b = c->blocks_per_cu, saved_c = c->chunk;
+  const bool saved_timing = c->timing;
+  const int lds = q.precision == BMC_FP64 ? P.lds64 : P.lds32;
+  const int max_b = std::max(1, std::min(8, (160 * 1024) / std::max(1, lds)));
+  double best = 1e300;
+  int bb = saved_b, bc = saved_c;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  c->timing = false;
+  for (int b = 1; b <= max_b; ++b) {
+    for (int ch : {1, 2, 4, 8, 16}) {
+      c->blocks_per_cu = b;
+      c->chunk = ch;
+      HIPCHK(c, launch_set_eval(c->st(), 0.0, q.epoch, 0, c->stream));
+      double ms_sum = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(c, hipEventRecord(e0, c->stream));
+        rc = enqueue_eval(c, P, q, P.d_out_C, P.d_out_S);
+        if (rc) break;
+        HIPCHK(c, hipEventRecord(e1, c->stream));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) ms_sum += ms;  // the first run warms the configuration up
+      }
+      if (rc) break;
+      if (ms_sum < best) {
+        best = ms_sum;
+        bb = b;
+        bc = ch;
+      }
+    }
+    if (rc) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->timing = saved_timing;
+  if (rc) {
+    c->blocks_per_cu = saved_b;
+    c->chunk = saved_c;
+    return rc;
+  }
+  c->blocks_per_cu = bb;
+  c->chunk = bc;
+  if (blocks_per_cu) *blocks_per_cu = bb;
+  if (chunk) *chunk = bc;
+  if (best_ms) *best_ms = best;
+  return finish_check(c);
 }
 
 const char* bmc_last_error(bmc_ctx* c) { return c ? c->err.c_str() : "null context"; }

@@ -26,6 +26,7 @@ struct SampleLaunch {
   int nint_mask;         // bit (nint-1) set for every integrated-particle count present
   int precision;         // 0 FP64, 1 FP32I
   int grid;              // blocks
+  int chunk;             // consecutive tasks per block visit
   size_t lds_bytes;
 };
 

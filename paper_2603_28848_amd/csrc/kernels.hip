@@ -165,7 +165,7 @@ __device__ __forceinline__ float interp32(const FTab<float>& t, double q) {
 }
 
 template <int NI, int PREC>
-__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem) {
+__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
   // FP64 expressions are evaluated as written (no fused multiply-add contraction), like the reference
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
@@ -187,17 +187,18 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
   double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
 
-  // ---- stage the map, the angle tables, the f tables and clear the histograms ----
+  // ---- stage the map, the angle tables, the f tables (unless the previous task of this block staged the same
+  // item) and clear the histograms ----
   const double* __restrict__ map = L.maps + it->map_off;
-  for (int i = tid; i < DN; i += kBlock) {
+  for (int i = tid; stage && i < DN; i += kBlock) {
     const int d = i / nb, j = i - d * nb;
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
     const double w = e1 - e0;
     sm_e[i] = e0;
     sm_w[i] = w;
   }
-  if (tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
-  for (int k = 0; k < n_tab; ++k) {
+  if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
+  for (int k = 0; stage && k < n_tab; ++k) {
     const SpecDev& S = L.spec[it->tab_species[k]];
     unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
     double* q = reinterpret_cast<double*>(base);
@@ -774,16 +775,26 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
   }
 }
 
+// Persistent sample kernel: block b takes the chunks b, b + G, b + 2G, ... of `chunk` consecutive tasks (the
+// units of one item are consecutive, so a chunk mostly re-uses the staged map and tables).  Which block runs a
+// task does not change its result.
 template <int MASK, int PREC>
 __global__ __launch_bounds__(kBlock) void k_sample(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
-    const Task task = L.tasks[L.task_begin + t];
-    const int ni = L.items[task.item].nint;
-    if ((MASK & 1) && ni == 1) sample_task<1, PREC>(L, task, smem);
-    if ((MASK & 2) && ni == 2) sample_task<2, PREC>(L, task, smem);
-    if ((MASK & 4) && ni == 3) sample_task<3, PREC>(L, task, smem);
-    if ((MASK & 8) && ni == 4) sample_task<4, PREC>(L, task, smem);
+  const int chunk = L.chunk > 0 ? L.chunk : 1;
+  int prev_item = -1;
+  for (int base = blockIdx.x * chunk; base < L.n_tasks; base += gridDim.x * chunk) {
+    const int end = min(base + chunk, L.n_tasks);
+    for (int t = base; t < end; ++t) {
+      const Task task = L.tasks[L.task_begin + t];
+      const int ni = L.items[task.item].nint;
+      const bool stage = task.item != prev_item;
+      prev_item = task.item;
+      if ((MASK & 1) && ni == 1) sample_task<1, PREC>(L, task, smem, stage);
+      if ((MASK & 2) && ni == 2) sample_task<2, PREC>(L, task, smem, stage);
+      if ((MASK & 4) && ni == 3) sample_task<3, PREC>(L, task, smem, stage);
+      if ((MASK & 8) && ni == 4) sample_task<4, PREC>(L, task, smem, stage);
+    }
   }
 }
 
