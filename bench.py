@@ -85,6 +85,7 @@ def main():
     opts = bm.default_opts(seed=0, epoch=0, precision=bm.FP32I, launch=bm.LAUNCH_BATCHED)
     n_items, n_out = ctx.plan_size(-1, -1, opts)
     samples_per_step = n_items * p.n_samples * p.n_iter
+    tuned = ctx.autotune(-1, -1, opts)  # launch shape only; results do not depend on it
     first_sigma = None
     for k in range(max(1, args.warmup)):
         opts.epoch = k
@@ -110,6 +111,8 @@ def main():
     def rate(precision, launch, steps):
         c2 = bm.from_workload(w)
         o = bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch)
+        if launch == bm.LAUNCH_BATCHED:
+            c2.autotune(-1, -1, o)
         Cx, Sx = c2.collision(-1, -1, o)  # first evaluation from the uniform maps (sigma comparison)
         torch.cuda.synchronize()
         ta = time.perf_counter()
@@ -150,7 +153,7 @@ def main():
             "items": n_items,
             "samples_per_step": samples_per_step,
             "precision": "FP32 integrand, FP64 kinematics and accumulation",
-            "launch": "batched persistent",
+            "launch": "batched persistent (autotuned: %d blocks/CU, chunk %d)" % (tuned[0], tuned[1]),
             "plain_fp64_samples_per_s": plain64,
             "batched_fp64_samples_per_s": batched64,
             "speedup_vs_plain_fp64": value / plain64,

@@ -28,7 +28,7 @@ constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kHistWMin = 0x1p-400;  // |W| below this enters the training histogram as 0
 
 struct Lds {
-  int off_e, off_w, off_sc, off_tab, tab_stride, off_h, off_c, off_red, total;
+  int off_e, off_w, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, total;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
@@ -54,6 +54,8 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + kWaves * DN * 4);
   L.off_red = o;
   o = align16(o + 2 * kWaves * 8);
+  L.off_q = o;  // FP32-integrand screening queue (2 kBlock sample offsets) and per-wave counts
+  o = align16(o + 2 * kBlock * 4 + kWaves * 4);
   L.total = o;
   return L;
 }
@@ -164,13 +166,246 @@ __device__ __forceinline__ float interp32(const FTab<float>& t, double q) {
   return fmaf(w, f1 - f0, f0);
 }
 
-template <int NI, int PREC>
-__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
-  // FP64 expressions are evaluated as written (no fused multiply-add contraction), like the reference
+// Per-item constants of a sample block at the current time (uniform across the block).
+template <int NI, typename FT>
+struct ItemConsts {
+  static constexpr int NR = NI + 2;  // roles: integrated 0..NI-1, conserved NI, observed NI+1
+  const double* e;    // LDS map edges (D x nb)
+  const double* w;    // LDS map widths
+  const double2* sc;  // LDS sin/cos of k pi/16
+  FTab<FT> tr[NI + 1];
+  double a, inv_a, m2[NR], eta[NR], esg[NR];
+  int obsside[NR];
+  double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
+  double fit[4], qc_min, qc_max;
+  double inv2s2, dnorm, twopi_pow;
+  int nb, net, term;
+  uint32_t uid, c3, seed_lo, seed_hi;
+};
+
+template <int NI>
+__device__ __forceinline__ void philox_words(uint32_t* wd, uint64_t n, uint32_t uid, uint32_t c3, uint32_t k0,
+                                             uint32_t k1) {
+  constexpr int B = (3 * NI + 3) / 4;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    const uint64_t off = n * (uint64_t)B + (uint64_t)b;
+    Philox4 r = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, k0, k1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
+  }
+}
+
+// One sample with FP64 kinematics (map, sin/cos, momenta, energies, dE and the Gaussian's argument); the f
+// tables, interpolation and statistical factor in FT.  Returns W and the packed bin indices (8 bits each).
+template <int NI, typename FT>
+__device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, uint32_t* bins) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
-  constexpr int B = (D + 3) / 4;
-  constexpr int NR = NI + 2;  // roles: integrated 0..NI-1, conserved NI, observed NI+1
+  uint32_t wd[4 * ((D + 3) / 4)];
+  philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
+  const int nb = K.nb;
+  const double dnb = (double)nb;
+#pragma unroll
+  for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
+  double J = 1.0, jac = 1.0;
+  double sx = 0.0, sy = 0.0, sz = K.esg[NI + 1] * K.p_obs;  // sum_in - sum_out over all but the conserved
+  double dE = K.esg[NI + 1] * K.E_obs;
+  double prod2E = 2.0 * K.E_obs;
+  bool cut = K.E_obs < K.e_cut;
+  FT gain = (FT)K.g_obs, loss = (FT)K.l_obs;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    double x3[3], sc3[2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int d = 3 * k + c;
+      const double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+      int j = (int)yn;
+      j = j > nb - 1 ? nb - 1 : j;
+      const double del = yn - (double)j;
+      const double e0 = K.e[d * nb + j], w = K.w[d * nb + j];
+      x3[c] = e0 + w * del;
+      J *= dnb * w;
+      bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
+      if (c != 0) sincos_red(x3[c], K.sc, &sc3[c - 1][0], &sc3[c - 1][1]);
+    }
+    const double r = x3[0];
+    const double sth = sc3[0][0], cth = sc3[0][1], sph = sc3[1][0], cph = sc3[1][1];
+    const double p = r * K.inv_a;
+    const double ps = p * sth;
+    sx += K.esg[k] * (ps * cph);
+    sy += K.esg[k] * (ps * sph);
+    sz += K.esg[k] * (p * cth);
+    jac *= r * r * sth;
+    const double E = sqrt(p * p + K.m2[k]);
+    cut |= E < K.e_cut;
+    dE += K.esg[k] * E;
+    prod2E *= 2.0 * E;
+    FT f;
+    if constexpr (std::is_same<FT, double>::value) {
+      int jj;
+      double ww;
+      f = interp64(K.tr[k], r, &jj, &ww);
+    } else {
+      f = interp32(K.tr[k], r);
+    }
+    const FT bf = (FT)1.0 + (FT)K.eta[k] * f;
+    gain *= K.obsside[k] ? bf : f;
+    loss *= K.obsside[k] ? f : bf;
+  }
+  // ---- conserved particle ----
+  const double P2 = sx * sx + sy * sy + sz * sz;
+  const double Ec = sqrt(P2 + K.m2[NI]);
+  cut |= Ec < K.e_cut;
+  dE += K.esg[NI] * Ec;
+  prod2E *= 2.0 * Ec;
+  const double qc = K.a * sqrt(P2);
+  FT fc;
+  if constexpr (std::is_same<FT, double>::value) {
+    if (qc < K.qc_min) {
+      fc = 1.0 / (exp(K.fit[0] + K.fit[1] * Ec) - K.eta[NI]);
+    } else if (qc > K.qc_max) {
+      fc = 1.0 / (exp(K.fit[2] + K.fit[3] * Ec) - K.eta[NI]);
+    } else {
+      int jj;
+      double ww;
+      fc = interp64(K.tr[NI], qc, &jj, &ww);
+    }
+  } else {
+    if (qc < K.qc_min) {
+      fc = __builtin_amdgcn_rcpf(exp_split(K.fit[0] + K.fit[1] * Ec) - (float)K.eta[NI]);
+    } else if (qc > K.qc_max) {
+      fc = __builtin_amdgcn_rcpf(exp_split(K.fit[2] + K.fit[3] * Ec) - (float)K.eta[NI]);
+    } else {
+      fc = interp32(K.tr[NI], qc);
+    }
+  }
+  {
+    const FT bf = (FT)1.0 + (FT)K.eta[NI] * fc;
+    gain *= K.obsside[NI] ? bf : fc;
+    loss *= K.obsside[NI] ? fc : bf;
+  }
+  const FT F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
+  double W;
+  if constexpr (std::is_same<FT, double>::value) {
+    const double delta = exp(-dE * dE * K.inv2s2) * K.dnorm;
+    W = J * (jac * K.a3M2 * delta / (K.twopi_pow * prod2E) * (double)F);
+  } else {
+    const float delta = exp_split(-dE * dE * K.inv2s2) * (float)K.dnorm;
+    const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
+    W = J * jac * (K.a3M2 / K.twopi_pow) * ((double)delta * (double)rcp) * (double)F;
+  }
+  return cut ? 0.0 : W;
+}
+
+// e^z as a double from an FP64 range reduction and the hardware exp2 on the fractional part (relative error
+// ~1e-7; no FP32 underflow).
+__device__ __forceinline__ double exp_split_d(double z) {
+  const double y = z * 1.4426950408889634074;
+  double n = floor(y);
+  const float fr = (float)(y - n);
+  n = n > 1023.0 ? 1023.0 : (n < -1100.0 ? -1100.0 : n);
+  return ldexp((double)__builtin_amdgcn_exp2f(fr), (int)n);
+}
+
+// FP32 screening pass of one sample: FP32 map, hardware sin/cos, momenta, energies and dE.  Returns whether
+// the sample lies within the energy shell |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed energies,
+// far above the FP32 error); for samples outside it also returns W finished in FP32 (their Gaussian factor
+// is below e^-72 relative, so W only matters for the map's training histogram, where ~1% accuracy is ample).
+template <int NI>
+__device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell,
+                                              uint32_t* bins, double* Wout) {
+  constexpr int D = 3 * NI;
+  uint32_t wd[4 * ((D + 3) / 4)];
+  philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
+  const int nb = K.nb;
+  const float fnb = (float)nb;
+  const float inv_a = (float)K.inv_a;
+#pragma unroll
+  for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
+  float J = 1.0f, jac = 1.0f;
+  float sx = 0.0f, sy = 0.0f, sz = (float)(K.esg[NI + 1] * K.p_obs);
+  float dE = (float)(K.esg[NI + 1] * K.E_obs), sumE = (float)K.E_obs, prod2E = 2.0f * (float)K.E_obs;
+  float gain = (float)K.g_obs, loss = (float)K.l_obs;
+  bool cut = K.E_obs < K.e_cut;
+#pragma unroll
+  for (int k = 0; k < NI; ++k) {
+    float x3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int d = 3 * k + c;
+      // bin and offset exactly as the FP64 map: y nb = (2 word + 1) nb / 2^33
+      const uint64_t t = (uint64_t)(2u * (uint64_t)wd[d] + 1u) * (uint64_t)nb;
+      const int j = (int)(t >> 33);
+      const float del = (float)(t & 0x1FFFFFFFFull) * 1.16415321826934814453125e-10f;
+      const float e0 = (float)K.e[d * nb + j], w = (float)K.w[d * nb + j];
+      x3[c] = fmaf(w, del, e0);
+      J *= fnb * w;
+      bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
+    }
+    const float r = x3[0];
+    const float sth = __sinf(x3[1]), cth = __cosf(x3[1]), sph = __sinf(x3[2]), cph = __cosf(x3[2]);
+    const float p = r * inv_a;
+    const float ps = p * sth;
+    const float sg = (float)K.esg[k];
+    sx = fmaf(sg, ps * cph, sx);
+    sy = fmaf(sg, ps * sph, sy);
+    sz = fmaf(sg, p * cth, sz);
+    jac *= r * r * sth;
+    const float E = __fsqrt_rn(fmaf(p, p, (float)K.m2[k]));
+    cut |= E < (float)K.e_cut;
+    dE = fmaf(sg, E, dE);
+    sumE += E;
+    prod2E *= 2.0f * E;
+    const FTab<float>& T = K.tr[k];
+    float tp = (__logf(r) - (float)T.lq0) * (float)T.inv_h;
+    int jj = (int)tp;
+    jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+    const float wgt = tp - (float)jj;
+    const float f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    const float bf = fmaf((float)K.eta[k], f, 1.0f);
+    gain *= K.obsside[k] ? bf : f;
+    loss *= K.obsside[k] ? f : bf;
+  }
+  const float P2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  const float Ec = __fsqrt_rn(P2 + (float)K.m2[NI]);
+  dE = fmaf((float)K.esg[NI], Ec, dE);
+  sumE += Ec;
+  prod2E *= 2.0f * Ec;
+  const bool in = fabsf(dE) < shell + 1e-3f * sumE;
+  if (!in) {
+    const float qc = (float)K.a * __fsqrt_rn(P2);
+    float fc;
+    if (qc < (float)K.qc_min) {
+      fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K.fit[1], Ec, (float)K.fit[0])) - (float)K.eta[NI]);
+    } else if (qc > (float)K.qc_max) {
+      fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K.fit[3], Ec, (float)K.fit[2])) - (float)K.eta[NI]);
+    } else {
+      const FTab<float>& T = K.tr[NI];
+      float tp = (__logf(qc) - (float)T.lq0) * (float)T.inv_h;
+      int jj = (int)tp;
+      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+      fc = fmaf(tp - (float)jj, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    }
+    const float bf = fmaf((float)K.eta[NI], fc, 1.0f);
+    gain *= K.obsside[NI] ? bf : fc;
+    loss *= K.obsside[NI] ? fc : bf;
+    const float F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
+    const double x = (double)dE * (double)dE * K.inv2s2;
+    const double delta = exp_split_d(-x) * K.dnorm;
+    cut |= Ec < (float)K.e_cut;
+    *Wout = cut ? 0.0
+                : (double)J * (double)jac * (K.a3M2 / K.twopi_pow) * delta * (double)__builtin_amdgcn_rcpf(prod2E) *
+                      (double)F;
+  }
+  return in;
+}
+
+template <int NI, int PREC>
+__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
+  constexpr int D = 3 * NI;
+  constexpr int NR = NI + 2;
   using FT = typename std::conditional<PREC == 0, double, float>::type;
   const ItemRec* __restrict__ it = &L.items[task.item];
   const int tid = threadIdx.x;
@@ -186,6 +421,8 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   double* sm_h = reinterpret_cast<double*>(smem + lay.off_h);
   uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
   double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
+  uint32_t* sm_q = reinterpret_cast<uint32_t*>(smem + lay.off_q);
+  int* sm_qn = reinterpret_cast<int*>(smem + lay.off_q + 2 * kBlock * 4);
 
   // ---- stage the map, the angle tables, the f tables (unless the previous task of this block staged the same
   // item) and clear the histograms ----
@@ -193,9 +430,8 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   for (int i = tid; stage && i < DN; i += kBlock) {
     const int d = i / nb, j = i - d * nb;
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
-    const double w = e1 - e0;
     sm_e[i] = e0;
-    sm_w[i] = w;
+    sm_w[i] = e1 - e0;
   }
   if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; stage && k < n_tab; ++k) {
@@ -211,166 +447,75 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
       else f[j] = L.f32[S.f_off + j];
     }
   }
-  // per role (integrated and conserved): its table in LDS
-  FTab<FT> tr[NI + 1];
-#pragma unroll
-  for (int r = 0; r <= NI; ++r) {
-    const int k = it->r_tab[r];
-    const SpecDev& S = L.spec[it->tab_species[k]];
-    const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
-    tr[r].q = reinterpret_cast<const double*>(base);
-    tr[r].iq = tr[r].q + n_max;
-    tr[r].f = reinterpret_cast<const FT*>(tr[r].iq + n_max);
-    tr[r].n = S.n;
-    tr[r].lq0 = S.lq0;
-    tr[r].inv_h = S.inv_h;
-  }
   for (int i = tid; i < kWaves * DN; i += kBlock) {
     sm_h[i] = 0.0;
     sm_c[i] = 0u;
   }
 
   // ---- per-item constants at the current time ----
+  ItemConsts<NI, FT> K;
+  K.e = sm_e;
+  K.w = sm_w;
+  K.sc = sm_sc;
+#pragma unroll
+  for (int r = 0; r <= NI; ++r) {
+    const int k = it->r_tab[r];
+    const SpecDev& S = L.spec[it->tab_species[k]];
+    const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
+    K.tr[r].q = reinterpret_cast<const double*>(base);
+    K.tr[r].iq = K.tr[r].q + n_max;
+    K.tr[r].f = reinterpret_cast<const FT*>(K.tr[r].iq + n_max);
+    K.tr[r].n = S.n;
+    K.tr[r].lq0 = S.lq0;
+    K.tr[r].inv_h = S.inv_h;
+  }
   const DevState* __restrict__ st = L.st;
-  const double a = st->a;
-  const double inv_a = 1.0 / a;
-  double m2[NR], eta[NR], esg[NR];
-  int obsside[NR];
+  K.a = st->a;
+  K.inv_a = 1.0 / K.a;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double mr = st->m[it->r_species[r]];
-    m2[r] = mr * mr;
-    eta[r] = (double)L.spec[it->r_species[r]].stat;
-    esg[r] = it->r_in[r] ? 1.0 : -1.0;
-    obsside[r] = it->r_obsside[r];
+    K.m2[r] = mr * mr;
+    K.eta[r] = (double)L.spec[it->r_species[r]].stat;
+    K.esg[r] = it->r_in[r] ? 1.0 : -1.0;
+    K.obsside[r] = it->r_obsside[r];
   }
   const SpecDev& So = L.spec[it->obs_species];
-  const double p_obs = it->q_obs * inv_a;
-  const double E_obs = sqrt(p_obs * p_obs + m2[NI + 1]);
-  const double f_obs = L.f64[So.f_off + it->eval_idx];
-  const double a3M2 = pow(a, -3.0 * (double)NI) * it->coupling2;
-  const double e_cut = it->e_cut;
+  K.p_obs = it->q_obs * K.inv_a;
+  K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
+  K.f_obs = L.f64[So.f_off + it->eval_idx];
+  {
+    const double obs_bf = 1.0 + K.eta[NI + 1] * K.f_obs;
+    K.g_obs = K.obsside[NI + 1] ? obs_bf : K.f_obs;  // the observed leg is on the observed side
+    K.l_obs = K.obsside[NI + 1] ? K.f_obs : obs_bf;
+  }
+  K.a3M2 = pow(K.a, -3.0 * (double)NI) * it->coupling2;
+  K.e_cut = it->e_cut;
   const SpecDev& Sc = L.spec[it->r_species[NI]];
-  const double fit_lo_a = st->fit[it->r_species[NI]][0], fit_lo_b = st->fit[it->r_species[NI]][1];
-  const double fit_hi_a = st->fit[it->r_species[NI]][2], fit_hi_b = st->fit[it->r_species[NI]][3];
-  const uint32_t uid = it->uid;
-  const uint32_t c3 = st->epoch * 64u + (uint32_t)L.it;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) K.fit[k] = st->fit[it->r_species[NI]][k];
+  K.qc_min = Sc.q_min;
+  K.qc_max = Sc.q_max;
+  K.inv2s2 = it->inv2s2;
+  K.dnorm = it->dnorm;
+  K.twopi_pow = it->twopi_pow;
+  K.nb = nb;
+  K.net = it->net;
+  K.term = it->term;
+  K.uid = it->uid;
+  K.c3 = st->epoch * 64u + (uint32_t)L.it;
+  K.seed_lo = L.seed_lo;
+  K.seed_hi = L.seed_hi;
   const int64_t N = it->N;
   const int64_t n0 = (int64_t)task.unit * it->unit_size;
   const int64_t n1 = min(n0 + (int64_t)it->unit_size, N);
-  const double dnb = (double)nb;
-  const int wave = tid >> 6;
+  const int wave = tid >> 6, lane = tid & 63;
   double* my_h = sm_h + wave * DN;
   uint32_t* my_c = sm_c + wave * DN;
-  // observed leg contributions (momentum along z, energy, factors)
-  const double obs_bf = 1.0 + eta[NI + 1] * f_obs;
-  const double g_obs = obsside[NI + 1] ? obs_bf : f_obs;  // always on the observed side
-  const double l_obs = obsside[NI + 1] ? f_obs : obs_bf;
   __syncthreads();
 
   double S1 = 0.0, S2 = 0.0;
-  for (int64_t n = n0 + tid; n < n1; n += kBlock) {
-    // ---- uniforms ----
-    uint32_t wd[4 * B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
-      Philox4 r = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, L.seed_lo, L.seed_hi);
-#pragma unroll
-      for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
-    }
-    uint32_t bins[(D + 3) / 4];
-#pragma unroll
-    for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
-    double J = 1.0, jac = 1.0;
-    double sx = 0.0, sy = 0.0, sz = esg[NI + 1] * p_obs;  // sum_in - sum_out over all but the conserved
-    double dE = esg[NI + 1] * E_obs;
-    double prod2E = 2.0 * E_obs;
-    bool cut = E_obs < e_cut;
-    FT gain = (FT)g_obs, loss = (FT)l_obs;
-#pragma unroll
-    for (int k = 0; k < NI; ++k) {
-      double x3[3], sc3[2][2];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int d = 3 * k + c;
-        const double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
-        int j = (int)yn;
-        j = j > nb - 1 ? nb - 1 : j;
-        const double del = yn - (double)j;
-        const double e0 = sm_e[d * nb + j], w = sm_w[d * nb + j];
-        x3[c] = e0 + w * del;
-        J *= dnb * w;
-        bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
-        if (c != 0) sincos_red(x3[c], sm_sc, &sc3[c - 1][0], &sc3[c - 1][1]);
-      }
-      const double r = x3[0];
-      const double sth = sc3[0][0], cth = sc3[0][1], sph = sc3[1][0], cph = sc3[1][1];
-      const double p = r * inv_a;
-      const double ps = p * sth;
-      sx += esg[k] * (ps * cph);
-      sy += esg[k] * (ps * sph);
-      sz += esg[k] * (p * cth);
-      jac *= r * r * sth;
-      const double E = sqrt(p * p + m2[k]);
-      cut |= E < e_cut;
-      dE += esg[k] * E;
-      prod2E *= 2.0 * E;
-      FT f;
-      if constexpr (PREC == 0) {
-        int jj;
-        double ww;
-        f = interp64(tr[k], r, &jj, &ww);
-      } else {
-        f = interp32(tr[k], r);
-      }
-      const FT bf = (FT)1.0 + (FT)eta[k] * f;
-      gain *= obsside[k] ? bf : f;
-      loss *= obsside[k] ? f : bf;
-    }
-    // ---- conserved particle ----
-    const double P2 = sx * sx + sy * sy + sz * sz;
-    const double Ec = sqrt(P2 + m2[NI]);
-    cut |= Ec < e_cut;
-    dE += esg[NI] * Ec;
-    prod2E *= 2.0 * Ec;
-    const double qc = a * sqrt(P2);
-    FT fc;
-    if constexpr (PREC == 0) {
-      if (qc < Sc.q_min) {
-        fc = 1.0 / (exp(fit_lo_a + fit_lo_b * Ec) - eta[NI]);
-      } else if (qc > Sc.q_max) {
-        fc = 1.0 / (exp(fit_hi_a + fit_hi_b * Ec) - eta[NI]);
-      } else {
-        int jj;
-        double ww;
-        fc = interp64(tr[NI], qc, &jj, &ww);
-      }
-    } else {
-      if (qc < Sc.q_min) {
-        fc = __builtin_amdgcn_rcpf(exp_split(fit_lo_a + fit_lo_b * Ec) - (float)eta[NI]);
-      } else if (qc > Sc.q_max) {
-        fc = __builtin_amdgcn_rcpf(exp_split(fit_hi_a + fit_hi_b * Ec) - (float)eta[NI]);
-      } else {
-        fc = interp32(tr[NI], qc);
-      }
-    }
-    {
-      const FT bf = (FT)1.0 + (FT)eta[NI] * fc;
-      gain *= obsside[NI] ? bf : fc;
-      loss *= obsside[NI] ? fc : bf;
-    }
-    const FT F = it->net ? gain - loss : (it->term == 0 ? gain : loss);
-    double W;
-    if constexpr (PREC == 0) {
-      const double delta = exp(-dE * dE * it->inv2s2) * it->dnorm;
-      W = J * (jac * a3M2 * delta / (it->twopi_pow * prod2E) * (double)F);
-    } else {
-      const float delta = exp_split(-dE * dE * it->inv2s2) * (float)it->dnorm;
-      const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
-      W = J * jac * (a3M2 / it->twopi_pow) * ((double)delta * (double)rcp) * (double)F;
-    }
-    if (cut) W = 0.0;
+  auto accumulate = [&](double W, const uint32_t* bins) {
     S1 += W;
     S2 += W * W;
     const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
@@ -380,12 +525,56 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
       atomicAdd(&my_h[d * nb + j], w2);
       atomicAdd(&my_c[d * nb + j], 1u);
     }
+  };
+  if constexpr (PREC == 0) {
+    for (int64_t n = n0 + tid; n < n1; n += kBlock) {
+      uint32_t bins[(D + 3) / 4];
+      const double W = eval_sample<NI, double>(K, (uint64_t)n, bins);
+      accumulate(W, bins);
+    }
+  } else {
+    // Rounds of kBlock samples: the FP32 pass finishes off-shell samples; the in-shell ones are appended to an
+    // LDS queue in a fixed order (waves in order, lanes in order) and recomputed with FP64 kinematics whenever
+    // a full block's worth is queued, and at the end of the unit.
+    const float shell = (float)(12.0 * sqrt(1.0 / (2.0 * it->inv2s2)));
+    int qlen = 0;
+    for (int64_t rbase = n0; rbase < n1; rbase += kBlock) {
+      const int64_t n = rbase + tid;
+      bool in = false;
+      if (n < n1) {
+        uint32_t bins[(D + 3) / 4];
+        double W = 0.0;
+        in = screen_sample<NI>(K, (uint64_t)n, shell, bins, &W);
+        if (!in) accumulate(W, bins);
+      }
+      const uint64_t ball = __ballot(in);
+      if (lane == 0) sm_qn[wave] = __popcll(ball);
+      __syncthreads();
+      int off = qlen, tot = qlen;
+      for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) off += sm_qn[w];
+        tot += sm_qn[w];
+      }
+      if (in) sm_q[off + __popcll(ball & ((1ull << lane) - 1ull))] = (uint32_t)(n - n0);
+      qlen = tot;
+      __syncthreads();
+      const bool last = rbase + kBlock >= n1;
+      if (qlen >= kBlock || (last && qlen > 0)) {
+        for (int e = tid; e < qlen; e += kBlock) {
+          uint32_t bins[(D + 3) / 4];
+          const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + sm_q[e]), bins);
+          accumulate(W, bins);
+        }
+        qlen = 0;
+        __syncthreads();
+      }
+    }
   }
 
   // ---- fixed-order reductions ----
   S1 = wave_sum(S1);
   S2 = wave_sum(S2);
-  if ((tid & 63) == 0) {
+  if (lane == 0) {
     sm_red[2 * wave] = S1;
     sm_red[2 * wave + 1] = S2;
   }

@@ -137,17 +137,37 @@ def test_free_running_2to2_first_iteration_and_statistics():
 
 
 # -------------------------------------------------------------------------------------------- modes
-def test_plain_equals_batched_bitwise_and_run_to_run():
+@pytest.mark.parametrize("precision", [0, 1])
+def test_plain_equals_batched_bitwise_and_run_to_run(precision):
     bm = _bm()
     w = wl.w23_be(n_grid=24, N=3000, nitn=3)
     outs = []
     for launch in (0, 1, 0):
         ctx = bm.from_workload(w)
-        C, S = ctx.collision(-1, -1, bm.default_opts(seed=7, epoch=3, launch=launch))
+        C, S = ctx.collision(-1, -1, bm.default_opts(seed=7, epoch=3, launch=launch, precision=precision))
         outs.append((C, S, ctx.item_results(3)))
     for C, S, res in outs[1:]:
         assert np.array_equal(C, outs[0][0]) and np.array_equal(S, outs[0][1])
         assert np.array_equal(res["I_it"], outs[0][2]["I_it"])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_launch_tuning_and_autotuner_do_not_change_results(precision):
+    bm = _bm()
+    w = wl.w23_be(n_grid=24, N=5000, nitn=3)
+    res = []
+    for tuning in ((1, 1), (4, 8), (2, 16), None):
+        ctx = bm.from_workload(w)
+        o = bm.default_opts(seed=4, epoch=1, precision=precision)
+        if tuning is None:
+            b, ch, ms = ctx.autotune(-1, -1, o)
+            say("autotune: %d blocks/CU, chunk %d, %.3f ms" % (b, ch, ms))
+        else:
+            ctx.set_launch_tuning(*tuning)
+        C, S = ctx.collision(-1, -1, o)
+        res.append((C, S, ctx.item_results(3)["I_it"]))
+    for C, S, I in res[1:]:
+        assert np.array_equal(C, res[0][0]) and np.array_equal(S, res[0][1]) and np.array_equal(I, res[0][2])
 
 
 def test_selection_invariance():
