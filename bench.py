@@ -64,6 +64,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the collision-integral items shard across GPUs with one small "
@@ -79,6 +81,13 @@ def main():
     w = wl.w23_be()
     p = w.processes[0]
     n_int = len(p.ins) + len(p.outs) - 2
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- batched FP32-integrand: the timed path ----
     ctx = bm.from_workload(w)

@@ -297,6 +297,8 @@ int upload_state(bmc_ctx* c) {
   DevState s{};
   s.t = c->t;
   s.a = 1.0;
+  s.inv_a = 1.0;
+  for (int n = 0; n < 5; ++n) s.a_m3n[n] = 1.0;
   s.expansion = c->expansion;
   s.expansion_a0 = c->a0;
   s.expansion_t0 = c->t0;
@@ -400,6 +402,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
             it.inv2s2 = 1.0 / (2.0 * Pr.prm.sigma_E * Pr.prm.sigma_E);
+            it.shell = 12.0 * Pr.prm.sigma_E;
             it.dnorm = 1.0 / (Pr.prm.sigma_E * std::sqrt(2.0 * M_PI));
             it.e_cut = Pr.prm.e_cut;
             it.twopi_pow = std::pow(2.0 * M_PI, (double)(3 * (n - 1) - 4));

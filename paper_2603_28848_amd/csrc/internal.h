@@ -30,6 +30,8 @@ struct SpecDev {
 struct DevState {
   double t;          // time of the current evaluation
   double a;          // scale factor a(t)
+  double inv_a;      // 1 / a(t)
+  double a_m3n[5];   // a(t)^(-3 n), n = 0..4 (the a^-3 per integrated particle of the weight)
   double m[kMaxSpecies];          // masses at t
   double fit[kMaxSpecies][4];     // (a_lo, b_lo, a_hi, b_hi) of log(1/f + eta) = a + b E
   double dt;         // step size of the step in progress
@@ -68,6 +70,7 @@ struct ItemRec {
   int sign;          // +1 gain / net, -1 loss
   double coupling2;
   double inv2s2;     // 1 / (2 sigma_E^2)
+  double shell;      // FP32 screening half-width of the energy shell, 12 sigma_E
   double dnorm;      // 1 / (sigma_E sqrt(2 pi))
   double e_cut;
   double twopi_pow;  // (2 pi)^(3(n-1)-4)

@@ -28,12 +28,12 @@ constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kHistWMin = 0x1p-400;  // |W| below this enters the training histogram as 0
 
 struct Lds {
-  int off_e, off_w, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, total;
+  int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, total;
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS of one sample block: map edges and widths (D x nb), sin/cos of k pi/16 (33 entries),
+// LDS of one sample block: map edges and widths (D x nb, FP64, and as FP32 pairs), sin/cos of k pi/16 (33 entries),
 // per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction scratch.
 __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
   Lds L;
@@ -42,6 +42,8 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   L.off_e = o;
   o = align16(o + DN * 8);
   L.off_w = o;
+  o = align16(o + DN * 8);
+  L.off_m32 = o;
   o = align16(o + DN * 8);
   L.off_sc = o;
   o = align16(o + 33 * 16);
@@ -54,8 +56,8 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + kWaves * DN * 4);
   L.off_red = o;
   o = align16(o + 2 * kWaves * 8);
-  L.off_q = o;  // FP32-integrand screening queue (2 kBlock sample offsets) and per-wave counts
-  o = align16(o + 2 * kBlock * 4 + kWaves * 4);
+  L.off_q = o;  // FP32-integrand screening: one ring of 128 sample offsets per wave, ring heads and fill levels
+  o = align16(o + kWaves * 128 * 4 + 2 * kWaves * 4);
   L.total = o;
   return L;
 }
@@ -173,7 +175,9 @@ struct ItemConsts {
   const double* e;    // LDS map edges (D x nb)
   const double* w;    // LDS map widths
   const double2* sc;  // LDS sin/cos of k pi/16
+  const float2* m32;  // LDS map (edge, width) pairs in FP32 (screening pass)
   FTab<FT> tr[NI + 1];
+  float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   double a, inv_a, m2[NR], eta[NR], esg[NR];
   int obsside[NR];
   double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
@@ -197,17 +201,16 @@ __device__ __forceinline__ void philox_words(uint32_t* wd, uint64_t n, uint32_t 
 }
 
 // One sample with FP64 kinematics (map, sin/cos, momenta, energies, dE and the Gaussian's argument); the f
-// tables, interpolation and statistical factor in FT.  Returns W and the packed bin indices (8 bits each).
+// tables, interpolation and statistical factor in FT.  Returns W and, per dimension d, the histogram offset
+// d nb + j of the sample's bin j.
 template <int NI, typename FT>
-__device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, uint32_t* bins) {
+__device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, int* hj) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
   uint32_t wd[4 * ((D + 3) / 4)];
   philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
   const int nb = K.nb;
   const double dnb = (double)nb;
-#pragma unroll
-  for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
   double J = 1.0, jac = 1.0;
   double sx = 0.0, sy = 0.0, sz = K.esg[NI + 1] * K.p_obs;  // sum_in - sum_out over all but the conserved
   double dE = K.esg[NI + 1] * K.E_obs;
@@ -227,7 +230,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
       const double e0 = K.e[d * nb + j], w = K.w[d * nb + j];
       x3[c] = e0 + w * del;
       J *= dnb * w;
-      bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
+      hj[d] = d * nb + j;
       if (c != 0) sincos_red(x3[c], K.sc, &sc3[c - 1][0], &sc3[c - 1][1]);
     }
     const double r = x3[0];
@@ -309,21 +312,22 @@ __device__ __forceinline__ double exp_split_d(double z) {
   return ldexp((double)__builtin_amdgcn_exp2f(fr), (int)n);
 }
 
-// FP32 screening pass of one sample: FP32 map, hardware sin/cos, momenta, energies and dE.  Returns whether
-// the sample lies within the energy shell |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed energies,
-// far above the FP32 error); for samples outside it also returns W finished in FP32 (their Gaussian factor
-// is below e^-72 relative, so W only matters for the map's training histogram, where ~1% accuracy is ample).
+// FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns
+// whether the sample lies within the energy shell |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed
+// energies, far above the FP32 error); for samples outside it also returns W finished in FP32 (their Gaussian
+// factor is below e^-72 relative, so W only matters for the map's training histogram, where ~1e-6 accuracy is
+// ample).  The bin of every dimension is exact (the same as with the FP64 map).
 template <int NI>
-__device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell,
-                                              uint32_t* bins, double* Wout) {
+__device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell, int* hj,
+                                              double* Wout) {
   constexpr int D = 3 * NI;
+  constexpr float kInv2Pi = 0.15915494309189535f;
   uint32_t wd[4 * ((D + 3) / 4)];
   philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
-  const int nb = K.nb;
+  const uint32_t nb = (uint32_t)K.nb;
+  const uint64_t half_nb = nb >> 1;
   const float fnb = (float)nb;
   const float inv_a = (float)K.inv_a;
-#pragma unroll
-  for (int k = 0; k < (D + 3) / 4; ++k) bins[k] = 0u;
   float J = 1.0f, jac = 1.0f;
   float sx = 0.0f, sy = 0.0f, sz = (float)(K.esg[NI + 1] * K.p_obs);
   float dE = (float)(K.esg[NI + 1] * K.E_obs), sumE = (float)K.E_obs, prod2E = 2.0f * (float)K.E_obs;
@@ -335,17 +339,20 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int d = 3 * k + c;
-      // bin and offset exactly as the FP64 map: y nb = (2 word + 1) nb / 2^33
-      const uint64_t t = (uint64_t)(2u * (uint64_t)wd[d] + 1u) * (uint64_t)nb;
-      const int j = (int)(t >> 33);
-      const float del = (float)(t & 0x1FFFFFFFFull) * 1.16415321826934814453125e-10f;
-      const float e0 = (float)K.e[d * nb + j], w = (float)K.w[d * nb + j];
-      x3[c] = fmaf(w, del, e0);
-      J *= fnb * w;
-      bins[d >> 2] |= (uint32_t)j << (8 * (d & 3));
+      // y nb = (word + 1/2) nb / 2^32: the bin is the high word of word nb + floor(nb/2) (exact; an odd nb only
+      // moves the in-bin offset by 2^-33), the offset comes from the low word
+      const uint64_t t = (uint64_t)wd[d] * nb + half_nb;
+      const int j = (int)(t >> 32);
+      const float del = (float)(uint32_t)t * 2.3283064365386963e-10f;
+      const float2 ew = K.m32[d * (int)nb + j];
+      x3[c] = fmaf(ew.y, del, ew.x);
+      J *= fnb * ew.y;
+      hj[d] = d * (int)nb + j;
     }
     const float r = x3[0];
-    const float sth = __sinf(x3[1]), cth = __cosf(x3[1]), sph = __sinf(x3[2]), cph = __cosf(x3[2]);
+    const float th = x3[1] * kInv2Pi, ph = x3[2] * kInv2Pi;  // the hardware sin/cos take revolutions
+    const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
+    const float sph = __builtin_amdgcn_sinf(ph), cph = __builtin_amdgcn_cosf(ph);
     const float p = r * inv_a;
     const float ps = p * sth;
     const float sg = (float)K.esg[k];
@@ -353,13 +360,13 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
     sy = fmaf(sg, ps * sph, sy);
     sz = fmaf(sg, p * cth, sz);
     jac *= r * r * sth;
-    const float E = __fsqrt_rn(fmaf(p, p, (float)K.m2[k]));
+    const float E = __builtin_amdgcn_sqrtf(fmaf(p, p, (float)K.m2[k]));
     cut |= E < (float)K.e_cut;
     dE = fmaf(sg, E, dE);
     sumE += E;
     prod2E *= 2.0f * E;
     const FTab<float>& T = K.tr[k];
-    float tp = (__logf(r) - (float)T.lq0) * (float)T.inv_h;
+    const float tp = fmaf(__builtin_amdgcn_logf(r), K.lg1[k], -K.lg0[k]);
     int jj = (int)tp;
     jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
     const float wgt = tp - (float)jj;
@@ -369,13 +376,13 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
     loss *= K.obsside[k] ? f : bf;
   }
   const float P2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
-  const float Ec = __fsqrt_rn(P2 + (float)K.m2[NI]);
+  const float Ec = __builtin_amdgcn_sqrtf(P2 + (float)K.m2[NI]);
   dE = fmaf((float)K.esg[NI], Ec, dE);
   sumE += Ec;
   prod2E *= 2.0f * Ec;
   const bool in = fabsf(dE) < shell + 1e-3f * sumE;
   if (!in) {
-    const float qc = (float)K.a * __fsqrt_rn(P2);
+    const float qc = (float)K.a * __builtin_amdgcn_sqrtf(P2);
     float fc;
     if (qc < (float)K.qc_min) {
       fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K.fit[1], Ec, (float)K.fit[0])) - (float)K.eta[NI]);
@@ -383,7 +390,7 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
       fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K.fit[3], Ec, (float)K.fit[2])) - (float)K.eta[NI]);
     } else {
       const FTab<float>& T = K.tr[NI];
-      float tp = (__logf(qc) - (float)T.lq0) * (float)T.inv_h;
+      const float tp = fmaf(__builtin_amdgcn_logf(qc), K.lg1[NI], -K.lg0[NI]);
       int jj = (int)tp;
       jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
       fc = fmaf(tp - (float)jj, T.f[jj + 1] - T.f[jj], T.f[jj]);
@@ -417,12 +424,12 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   const Lds lay = lds_layout(D, nb, n_tab, n_max, sizeof(FT));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
+  float2* sm_m32 = reinterpret_cast<float2*>(smem + lay.off_m32);
   double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
   double* sm_h = reinterpret_cast<double*>(smem + lay.off_h);
   uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
   double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
   uint32_t* sm_q = reinterpret_cast<uint32_t*>(smem + lay.off_q);
-  int* sm_qn = reinterpret_cast<int*>(smem + lay.off_q + 2 * kBlock * 4);
 
   // ---- stage the map, the angle tables, the f tables (unless the previous task of this block staged the same
   // item) and clear the histograms ----
@@ -432,6 +439,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
     sm_e[i] = e0;
     sm_w[i] = e1 - e0;
+    sm_m32[i] = make_float2((float)e0, (float)(e1 - e0));
   }
   if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; stage && k < n_tab; ++k) {
@@ -457,6 +465,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   K.e = sm_e;
   K.w = sm_w;
   K.sc = sm_sc;
+  K.m32 = sm_m32;
 #pragma unroll
   for (int r = 0; r <= NI; ++r) {
     const int k = it->r_tab[r];
@@ -468,10 +477,12 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     K.tr[r].n = S.n;
     K.tr[r].lq0 = S.lq0;
     K.tr[r].inv_h = S.inv_h;
+    K.lg1[r] = (float)(0.6931471805599453 * S.inv_h);
+    K.lg0[r] = (float)(S.lq0 * S.inv_h);
   }
   const DevState* __restrict__ st = L.st;
   K.a = st->a;
-  K.inv_a = 1.0 / K.a;
+  K.inv_a = st->inv_a;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const double mr = st->m[it->r_species[r]];
@@ -489,7 +500,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     K.g_obs = K.obsside[NI + 1] ? obs_bf : K.f_obs;  // the observed leg is on the observed side
     K.l_obs = K.obsside[NI + 1] ? K.f_obs : obs_bf;
   }
-  K.a3M2 = pow(K.a, -3.0 * (double)NI) * it->coupling2;
+  K.a3M2 = st->a_m3n[NI] * it->coupling2;
   K.e_cut = it->e_cut;
   const SpecDev& Sc = L.spec[it->r_species[NI]];
 #pragma unroll
@@ -515,59 +526,73 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   __syncthreads();
 
   double S1 = 0.0, S2 = 0.0;
-  auto accumulate = [&](double W, const uint32_t* bins) {
+  auto accumulate = [&](double W, const int* hj) {
     S1 += W;
     S2 += W * W;
     const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
-      const int j = (bins[d >> 2] >> (8 * (d & 3))) & 0xff;
-      atomicAdd(&my_h[d * nb + j], w2);
-      atomicAdd(&my_c[d * nb + j], 1u);
+      atomicAdd(&my_h[hj[d]], w2);
+      atomicAdd(&my_c[hj[d]], 1u);
     }
   };
   if constexpr (PREC == 0) {
     for (int64_t n = n0 + tid; n < n1; n += kBlock) {
-      uint32_t bins[(D + 3) / 4];
-      const double W = eval_sample<NI, double>(K, (uint64_t)n, bins);
-      accumulate(W, bins);
+      int hj[D];
+      const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
+      accumulate(W, hj);
     }
   } else {
-    // Rounds of kBlock samples: the FP32 pass finishes off-shell samples; the in-shell ones are appended to an
-    // LDS queue in a fixed order (waves in order, lanes in order) and recomputed with FP64 kinematics whenever
-    // a full block's worth is queued, and at the end of the unit.
-    const float shell = (float)(12.0 * sqrt(1.0 / (2.0 * it->inv2s2)));
-    int qlen = 0;
-    for (int64_t rbase = n0; rbase < n1; rbase += kBlock) {
-      const int64_t n = rbase + tid;
+    // Each wave takes rounds of 64 samples (wave w, round k: samples n0 + 256 k + 64 w + lane).  The FP32 pass
+    // finishes off-shell samples; the in-shell ones are appended, in lane order, to the wave's ring of sample
+    // offsets in LDS and recomputed with FP64 kinematics 64 at a time (lane l takes the l-th oldest entry).  At
+    // the end of the unit the rings' remainders (wave 0's first) are spread over the whole block.  The order
+    // depends only on the samples, and waves do not wait for each other inside the unit.
+    const float shell = (float)it->shell;
+    uint32_t* ring = sm_q + wave * 128;
+    int* sm_head = reinterpret_cast<int*>(sm_q + kWaves * 128);
+    int* sm_fill = sm_head + kWaves;
+    uint32_t head = 0, tail = 0;  // wave-uniform
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
+      const int64_t n = rbase + lane;
       bool in = false;
       if (n < n1) {
-        uint32_t bins[(D + 3) / 4];
+        int hj[D];
         double W = 0.0;
-        in = screen_sample<NI>(K, (uint64_t)n, shell, bins, &W);
-        if (!in) accumulate(W, bins);
+        in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
+        if (!in) accumulate(W, hj);
       }
       const uint64_t ball = __ballot(in);
-      if (lane == 0) sm_qn[wave] = __popcll(ball);
-      __syncthreads();
-      int off = qlen, tot = qlen;
-      for (int w = 0; w < kWaves; ++w) {
-        if (w < wave) off += sm_qn[w];
-        tot += sm_qn[w];
+      if (in) ring[(tail + (uint32_t)__popcll(ball & below)) & 127u] = (uint32_t)(n - n0);
+      tail += (uint32_t)__popcll(ball);
+      if (tail - head >= 64u) {
+        // the ring entries written above by other lanes of this wave are read below
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        int hj[D];
+        const uint32_t off = ring[(head + (uint32_t)lane) & 127u];
+        const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + off), hj);
+        accumulate(W, hj);
+        head += 64u;
       }
-      if (in) sm_q[off + __popcll(ball & ((1ull << lane) - 1ull))] = (uint32_t)(n - n0);
-      qlen = tot;
-      __syncthreads();
-      const bool last = rbase + kBlock >= n1;
-      if (qlen >= kBlock || (last && qlen > 0)) {
-        for (int e = tid; e < qlen; e += kBlock) {
-          uint32_t bins[(D + 3) / 4];
-          const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + sm_q[e]), bins);
-          accumulate(W, bins);
-        }
-        qlen = 0;
-        __syncthreads();
-      }
+    }
+    if (lane == 0) {
+      sm_head[wave] = (int)(head & 127u);
+      sm_fill[wave] = (int)(tail - head);
+    }
+    __syncthreads();
+    int src = -1, at = tid;
+    for (int w = 0; w < kWaves; ++w) {
+      if (src < 0 && at < sm_fill[w]) src = w;
+      if (src < 0) at -= sm_fill[w];
+    }
+    if (src >= 0) {
+      int hj[D];
+      const uint32_t off = sm_q[src * 128 + ((sm_head[src] + at) & 127)];
+      const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + off), hj);
+      accumulate(W, hj);
     }
   }
 
@@ -854,7 +879,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, unsigned char* 
 }
 
 template <int MASK>
-__global__ __launch_bounds__(kBlock) void k_vjp(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, 2) void k_vjp(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
     const Task task = L.tasks[L.task_begin + t];
@@ -966,9 +991,10 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
 
 // Persistent sample kernel: block b takes the chunks b, b + G, b + 2G, ... of `chunk` consecutive tasks (the
 // units of one item are consecutive, so a chunk mostly re-uses the staged map and tables).  Which block runs a
-// task does not change its result.
+// task does not change its result.  Registers are capped at 256 per lane (two waves per SIMD): beyond that the
+// compiler moves values into accumulation registers and occupancy halves.
 template <int MASK, int PREC>
-__global__ __launch_bounds__(kBlock) void k_sample(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, 2) void k_sample(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int chunk = L.chunk > 0 ? L.chunk : 1;
   int prev_item = -1;
@@ -1185,7 +1211,10 @@ __global__ void k_prepare(DevState* st, const SpecDev* spec, int n_species, cons
                           int64_t n_f) {
   const double t = st->t;
   if (threadIdx.x == 0) {
-    st->a = st->expansion == 1 ? st->expansion_a0 * sqrt(t / st->expansion_t0) : 1.0;
+    const double a = st->expansion == 1 ? st->expansion_a0 * sqrt(t / st->expansion_t0) : 1.0;
+    st->a = a;
+    st->inv_a = 1.0 / a;
+    for (int n = 0; n < 5; ++n) st->a_m3n[n] = pow(a, -3.0 * (double)n);
   }
   __syncthreads();
   const double a = st->a;
