@@ -24,6 +24,12 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
+// FP32 integrand: bytes of in-shell lists one screening launch may fill (larger batches run in slices)
+constexpr size_t kListCapBytes = size_t(1) << 30;
+// FP32 integrand: samples per in-shell record (the in-shell pass takes the units of an item in groups this large)
+constexpr int64_t kShellGroupSamples = 65536;
+
+int shell_units_for(int unit_size) { return (int)std::max<int64_t>(1, kShellGroupSamples / unit_size); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -61,6 +67,17 @@ struct Plan {
   std::vector<GatherEntry> gather;
   std::vector<GatherProc> gproc;
   std::vector<int> tasks_per_iter;            // batched tasks with item n_iter > k (prefix of item-major list)
+  // FP32 integrand: in-shell tasks (one per item) in batched and plain order, slices of the batched launch
+  std::vector<ShellTask> sh_batched, sh_plain;
+  std::vector<int> plain_node_sh_begin;       // ranges into sh_plain per distinct node
+  std::vector<int> sh_per_iter;               // batched in-shell tasks with item n_iter > k
+  struct Slice {
+    int tb, te, sb, se;  // task range and in-shell task range
+  };
+  std::vector<Slice> slices;
+  int64_t list_stride = 0;  // largest unit size
+  int64_t list_pos = 0;     // task positions the in-shell lists hold
+  int64_t n_shell = 0;      // doubles of the in-shell records
   int n_iter_max = 0;
   int n_slots = 0;
   int n_out = 0;
@@ -73,6 +90,11 @@ struct Plan {
   ItemRec* d_items = nullptr;
   Task* d_tb = nullptr;
   Task* d_tp = nullptr;
+  ShellTask* d_shb = nullptr;
+  ShellTask* d_shp = nullptr;
+  uint16_t* d_list = nullptr;
+  uint32_t* d_cnt = nullptr;
+  double* d_shell = nullptr;
   int64_t* d_unit_base = nullptr;
   double* d_unit_s = nullptr;
   double* d_parts = nullptr;
@@ -345,7 +367,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   // per (process, species): slot base for node 0 and its stride
   std::vector<std::vector<int>> slot_base(np, std::vector<int>(ns, -1));
   std::vector<std::vector<int>> pstride(np, std::vector<int>(ns, 0));
-  int64_t part = 0, units = 0;
+  int64_t part = 0, units = 0, shell = 0;
   int res = 0;
   std::vector<std::vector<int>> slot_lists;
   for (int p = 0; p < np; ++p) {
@@ -398,6 +420,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.n_units = (int)((N + it.unit_size - 1) / it.unit_size);
             it.part_off = part;
             part += (int64_t)it.n_units * 2 * D * nb;
+            it.shell_off = shell;
+            it.shell_units = shell_units_for(it.unit_size);
+            shell += (int64_t)((it.n_units + it.shell_units - 1) / it.shell_units) * (2 + 2 * D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
@@ -491,6 +516,61 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     }
     Q.plain_node_begin.push_back((int)Q.tasks_plain.size());
   }
+  // FP32 integrand: in-shell tasks, list sizing and slices of the batched launch
+  {
+    Q.n_shell = shell;
+    std::vector<int> first_b(Q.items.size(), -1), first_p(Q.items.size(), -1);
+    for (size_t t = 0; t < Q.tasks_batched.size(); ++t)
+      if (Q.tasks_batched[t].unit == 0) first_b[Q.tasks_batched[t].item] = (int)t;
+    for (size_t t = 0; t < Q.tasks_plain.size(); ++t)
+      if (Q.tasks_plain[t].unit == 0) first_p[Q.tasks_plain[t].item] = (int)t;
+    // groups of shell_units consecutive units per in-shell task, in the order of the item's tasks
+    auto groups = [&](int i, int first, std::vector<ShellTask>& out) {
+      const ItemRec& it = Q.items[i];
+      const int64_t stride = 2 + 2 * (int64_t)it.D * it.nb;
+      for (int u = 0; u < it.n_units; u += it.shell_units)
+        out.push_back(ShellTask{i, first + u, u, std::min(it.n_units, u + it.shell_units),
+                                it.shell_off + (u / it.shell_units) * stride});
+    };
+    std::vector<int> sh_first(Q.items.size(), 0);
+    for (int i : order) {
+      sh_first[i] = (int)Q.sh_batched.size();
+      groups(i, first_b[i], Q.sh_batched);
+    }
+    Q.sh_per_iter.assign(Q.n_iter_max, 0);
+    for (int kk = 0; kk < Q.n_iter_max; ++kk)
+      for (int i : order)
+        if (Q.items[i].n_iter > kk)
+          Q.sh_per_iter[kk] += (Q.items[i].n_units + Q.items[i].shell_units - 1) / Q.items[i].shell_units;
+    for (size_t g = 0; g + 1 < Q.plain_node_begin.size(); ++g) {
+      Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
+      for (int t = Q.plain_node_begin[g]; t < Q.plain_node_begin[g + 1]; ++t)
+        if (Q.tasks_plain[t].unit == 0) groups(Q.tasks_plain[t].item, t, Q.sh_plain);
+    }
+    Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
+    int64_t umax = 0, pmin = 0;
+    for (auto& it : Q.items) {
+      umax = std::max<int64_t>(umax, it.unit_size);
+      pmin = std::max<int64_t>(pmin, it.n_units);
+    }
+    for (size_t g = 0; g + 1 < Q.plain_node_begin.size(); ++g)
+      pmin = std::max<int64_t>(pmin, Q.plain_node_begin[g + 1] - Q.plain_node_begin[g]);
+    Q.list_stride = umax;
+    Q.list_pos = std::min<int64_t>((int64_t)Q.tasks_batched.size(),
+                                   std::max<int64_t>(pmin, (int64_t)(kListCapBytes / (2 * (size_t)umax))));
+    // slices: whole items in batched order, at most list_pos task positions each
+    int tb = 0, sb = 0;
+    for (size_t k = 0; k < order.size(); ++k) {
+      const int i = order[k];
+      const int te = first_b[i] + Q.items[i].n_units;
+      if (te - tb > Q.list_pos) {
+        Q.slices.push_back(Plan::Slice{tb, first_b[i], sb, sh_first[i]});
+        tb = first_b[i];
+        sb = sh_first[i];
+      }
+    }
+    Q.slices.push_back(Plan::Slice{tb, (int)Q.tasks_batched.size(), sb, (int)Q.sh_batched.size()});
+  }
   // slots
   Q.n_slots = (int)slot_lists.size();
   Q.slot_begin.push_back(0);
@@ -539,7 +619,10 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   };
   const size_t nI = Q.items.size();
   size_t o_items = take(sizeof(ItemRec) * nI), o_tb = take(sizeof(Task) * Q.tasks_batched.size()),
-         o_tp = take(sizeof(Task) * Q.tasks_plain.size()), o_ub = take(8 * nI), o_us = take(16 * (size_t)units),
+         o_tp = take(sizeof(Task) * Q.tasks_plain.size()), o_shb = take(sizeof(ShellTask) * Q.sh_batched.size()),
+         o_shp = take(sizeof(ShellTask) * Q.sh_plain.size()), o_list = take(2 * (size_t)(Q.list_pos * Q.list_stride)),
+         o_cnt = take(4 * kWaves * (size_t)Q.list_pos), o_shell = take(8 * (size_t)Q.n_shell),
+         o_ub = take(8 * nI), o_us = take(16 * (size_t)units),
          o_parts = take(8 * (size_t)part), o_rI = take(8 * kMaxIter * nI), o_rV = take(8 * kMaxIter * nI),
          o_ib = take(8 * nI), o_is = take(8 * nI), o_sb = take(4 * (Q.slot_begin.size())),
          o_si = take(4 * std::max<size_t>(1, Q.slot_items.size())), o_sC = take(8 * Q.n_slots),
@@ -552,6 +635,11 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     Q.d_items = reinterpret_cast<ItemRec*>(base + o_items);
     Q.d_tb = reinterpret_cast<Task*>(base + o_tb);
     Q.d_tp = reinterpret_cast<Task*>(base + o_tp);
+    Q.d_shb = reinterpret_cast<ShellTask*>(base + o_shb);
+    Q.d_shp = reinterpret_cast<ShellTask*>(base + o_shp);
+    Q.d_list = reinterpret_cast<uint16_t*>(base + o_list);
+    Q.d_cnt = reinterpret_cast<uint32_t*>(base + o_cnt);
+    Q.d_shell = reinterpret_cast<double*>(base + o_shell);
     Q.d_unit_base = reinterpret_cast<int64_t*>(base + o_ub);
     Q.d_unit_s = reinterpret_cast<double*>(base + o_us);
     Q.d_parts = reinterpret_cast<double*>(base + o_parts);
@@ -576,25 +664,37 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
 // Worst-case scratch for the registered model.
 size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
   size_t s = 0;
-  size_t items = 0, units = 0, part = 0, slots = 0, outs = 0, tasks = 0;
+  size_t items = 0, units = 0, part = 0, slots = 0, outs = 0, tasks = 0, shell = 0, umax = 0, per_node = 0,
+         per_item = 0;
   for (auto& Pr : c->pr) {
     const int n = Pr.n_in + Pr.n_out;
     const int D = 3 * (n - 2);
     const int64_t N = std::max<int64_t>(max_samples > 0 ? max_samples : 0, Pr.prm.n_samples);
     const int U = unit_size_for(N);
     const int64_t nu = (N + U - 1) / U;
+    umax = std::max<size_t>(umax, (size_t)U);
+    per_item = std::max<size_t>(per_item, (size_t)nu);
     for (size_t a = 0; a < c->sp.size(); ++a) {
       int sides = 0;
       for (int side = 0; side < 2; ++side) sides += multiplicity(Pr, (int)a, side) > 0;
       if (!sides) continue;
-      const size_t ni = (size_t)c->sp[a].n * sides * (Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+      const int terms = Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2;
+      const size_t ni = (size_t)c->sp[a].n * sides * terms;
       items += ni;
       units += ni * nu;
       tasks += ni * nu;
       part += ni * nu * 2 * D * Pr.prm.n_bins;
+      const int64_t G = shell_units_for(U);
+      shell += ni * (size_t)((nu + G - 1) / G) * (2 + 2 * D * Pr.prm.n_bins);
+      per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
     }
   }
+  // in-shell lists of the FP32-integrand screening pass (one slice's task positions)
+  const size_t list_pos =
+      std::min(units, std::max(std::max(per_item, per_node), kListCapBytes / (2 * std::max<size_t>(1, umax))));
+  s += align_up(2 * list_pos * umax) + align_up(4 * kWaves * list_pos) + align_up(8 * shell) +
+       2 * align_up(sizeof(ShellTask) * units);
   for (auto& S : c->sp) outs += S.n;
   (void)max_iter;
   // adjoint records: per unit n_tab * n_max + 12 doubles (n_tab <= 4 tables of at most the largest grid)
@@ -638,6 +738,10 @@ int upload_plan(bmc_ctx* c, Plan& P) {
   HIPCHK(c, hipMemcpyAsync(P.d_tp, P.tasks_plain.data(), sizeof(Task) * P.tasks_plain.size(), hipMemcpyHostToDevice,
                            s));
   HIPCHK(c, hipMemcpyAsync(P.d_unit_base, P.unit_base.data(), 8 * P.unit_base.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_shb, P.sh_batched.data(), sizeof(ShellTask) * P.sh_batched.size(),
+                           hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(P.d_shp, P.sh_plain.data(), sizeof(ShellTask) * P.sh_plain.size(), hipMemcpyHostToDevice,
+                           s));
   HIPCHK(c, hipMemcpyAsync(P.d_slot_begin, P.slot_begin.data(), 4 * P.slot_begin.size(), hipMemcpyHostToDevice, s));
   if (!P.slot_items.empty())
     HIPCHK(c, hipMemcpyAsync(P.d_slot_items, P.slot_items.data(), 4 * P.slot_items.size(), hipMemcpyHostToDevice, s));
@@ -672,23 +776,27 @@ int grid_for(bmc_ctx* c, int precision, int lds, int mask) {
   return c->n_cu * per_cu;
 }
 
-// Enqueues one evaluation of plan P (all iterations, combine, gather) on the context stream.
-hipError_t timed_sample(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
-  if (!c->timing || c->capturing) return launch_sample(L, s);
-  hipEvent_t a, b;
-  hipError_t e = hipEventCreate(&a);
-  if (e != hipSuccess) return e;
-  e = hipEventCreate(&b);
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(a, s);
-  if (e != hipSuccess) return e;
-  e = launch_sample(L, s);
-  if (e != hipSuccess) return e;
-  e = hipEventRecord(b, s);
-  c->ev.push_back({a, b});
+// The sample phase of one launch: the FP64 sample kernel, or the FP32-integrand screening and in-shell passes.
+// With timing on (eager launches only) the phase is bracketed by events on the launch stream.
+hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e;
+  const bool timed = c->timing && !c->capturing;
+  if (timed) {
+    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+    if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
+  }
+  if ((e = launch_sample(L, s)) != hipSuccess) return e;
+  if (L.precision == BMC_FP32I && (e = launch_shell(L, s)) != hipSuccess) return e;
+  if (timed) {
+    e = hipEventRecord(b, s);
+    c->ev.push_back({a, b});
+  }
   return e;
 }
 
+// Enqueues one evaluation of plan P (all iterations, combine, gather) on the context stream.
 int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, double* out_S) {
   hipStream_t s = c->stream;
   HIPCHK(c, launch_next_epoch(c->st(), s));
@@ -709,27 +817,45 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.nint_mask = P.nint_mask;
   L.precision = o.precision;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
+  L.shell_list = P.d_list;
+  L.shell_cnt = P.d_cnt;
+  L.list_stride = P.list_stride;
+  L.shell_rec = P.d_shell;
+  const int max_grid = grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask);
   for (int k = 0; k < P.n_iter_max; ++k) {
     L.it = o.first_iter + k;
     if (o.launch == BMC_LAUNCH_PLAIN) {
       L.tasks = P.d_tp;
+      L.sh_tasks = P.d_shp;
       for (size_t g = 0; g + 1 < P.plain_node_begin.size(); ++g) {
         L.task_begin = P.plain_node_begin[g];
         L.n_tasks = P.plain_node_begin[g + 1] - P.plain_node_begin[g];
         L.grid = L.n_tasks;
         L.chunk = 1;
-        HIPCHK(c, timed_sample(c, L, s));
+        L.sh_begin = P.plain_node_sh_begin[g];
+        L.n_sh = P.plain_node_sh_begin[g + 1] - P.plain_node_sh_begin[g];
+        L.sh_grid = L.n_sh;
+        HIPCHK(c, sample_phase(c, L, s));
       }
     } else {
       L.tasks = P.d_tb;
-      L.task_begin = 0;
-      L.n_tasks = P.tasks_per_iter[k];
+      L.sh_tasks = P.d_shb;
       L.chunk = c->chunk;
-      L.grid = std::min((L.n_tasks + L.chunk - 1) / L.chunk, grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask));
-      HIPCHK(c, timed_sample(c, L, s));
+      for (const Plan::Slice& sl : P.slices) {
+        const int te = std::min(sl.te, P.tasks_per_iter[k]);
+        if (sl.tb >= te) break;
+        L.task_begin = sl.tb;
+        L.n_tasks = te - sl.tb;
+        L.grid = std::min((L.n_tasks + L.chunk - 1) / L.chunk, max_grid);
+        L.sh_begin = sl.sb;
+        L.n_sh = std::min(sl.se, P.sh_per_iter[k]) - sl.sb;
+        L.sh_grid = std::min(L.n_sh, max_grid);
+        HIPCHK(c, sample_phase(c, L, s));
+      }
     }
     HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_unit_s, P.d_unit_base, P.d_parts,
-                                  P.d_res_I, P.d_res_V, k, c->maps(), o.freeze_maps, s));
+                                  o.precision == BMC_FP32I ? P.d_shell : nullptr, P.d_res_I, P.d_res_V, k, c->maps(),
+                                  o.freeze_maps, s));
   }
   HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, P.n_iter_max, P.d_item_Ibar,
                            P.d_item_sig, P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));

@@ -65,6 +65,8 @@ struct ItemRec {
   int64_t N;         // samples per iteration
   int64_t map_off;   // doubles: Vegas map, kMaxD rows of (nb + 1) edges
   int64_t part_off;  // doubles: first unit record (2 D nb doubles each) of this item
+  int64_t shell_off; // doubles: the item's in-shell records (S1, S2, 2 D nb each), FP32 integrand
+  int shell_units;   // units per in-shell record
   int64_t res_off;   // index of this item's per-iteration results
   int out_slot;      // output slot of the item's evaluation point (combine)
   int sign;          // +1 gain / net, -1 loss
@@ -89,6 +91,15 @@ struct ItemRec {
 struct Task {
   int item;
   int unit;
+};
+
+// The in-shell pass over units [unit_begin, unit_end) of one item: `first_task` indexes unit `unit_begin` in the
+// task list of the launch; the sums go to the record at `rec` (doubles into the in-shell records).
+struct ShellTask {
+  int item;
+  int first_task;
+  int unit_begin, unit_end;
+  int64_t rec;
 };
 
 }  // namespace bmc

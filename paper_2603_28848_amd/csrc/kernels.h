@@ -28,15 +28,26 @@ struct SampleLaunch {
   int grid;              // blocks
   int chunk;             // consecutive tasks per block visit
   size_t lds_bytes;
+  // FP32 integrand: in-shell lists of the screening pass and the in-shell pass
+  uint16_t* shell_list;  // list_stride entries per task position of the launch (4 wave lists)
+  uint32_t* shell_cnt;   // 4 counts per task position
+  int64_t list_stride;   // largest unit size of the plan
+  const ShellTask* sh_tasks;
+  int sh_begin, n_sh;    // in-shell tasks (one per item) of this launch
+  int sh_grid;
+  double* shell_rec;     // per item: S1, S2, then 2 D nb histogram doubles
 };
 
+// FP64 sample kernel, or the FP32-integrand screening pass (precision 1).
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
+// FP32-integrand in-shell pass over the items of the preceding screening launch.
+hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
-// Sums the unit records of each item in unit order, stores I_it, V_it for iteration slot `slot`, and (unless
-// frozen) adapts the item's map.
+// Sums the unit records of each item in unit order (then the item's in-shell record when shell_rec is not
+// null), stores I_it, V_it for iteration slot `slot`, and (unless frozen) adapts the item's map.
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,
-                               const int64_t* unit_base, const double* parts, double* res_I, double* res_V,
-                               int slot, double* maps, int freeze, hipStream_t s);
+                               const int64_t* unit_base, const double* parts, const double* shell_rec,
+                               double* res_I, double* res_V, int slot, double* maps, int freeze, hipStream_t s);
 
 // Initialises the maps of items (uniform edges over each dimension's range).
 hipError_t launch_init_maps(const ItemRec* items, const int* which, int n, const SpecDev* spec, double* maps,

@@ -56,8 +56,8 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + kWaves * DN * 4);
   L.off_red = o;
   o = align16(o + 2 * kWaves * 8);
-  L.off_q = o;  // FP32-integrand screening: one ring of 128 sample offsets per wave, ring heads and fill levels
-  o = align16(o + kWaves * 128 * 4 + 2 * kWaves * 4);
+  L.off_q = o;  // FP32-integrand in-shell pass: prefix sums over 256 in-shell lists
+  o = align16(o + (kBlock + 1) * 4);
   L.total = o;
   return L;
 }
@@ -409,12 +409,16 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
   return in;
 }
 
+// Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 pairs), the sin/cos table and
+// the f tables into LDS unless the block's previous task staged the same item, clears the per-wave training
+// histograms, and fills the per-item constants at the current time.  Ends with a block barrier.
 template <int NI, int PREC>
-__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
+__device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec* __restrict__ it,
+                                           unsigned char* smem, bool stage,
+                                           ItemConsts<NI, typename std::conditional<PREC == 0, double, float>::type>& K) {
   constexpr int D = 3 * NI;
   constexpr int NR = NI + 2;
   using FT = typename std::conditional<PREC == 0, double, float>::type;
-  const ItemRec* __restrict__ it = &L.items[task.item];
   const int tid = threadIdx.x;
   const int nb = it->nb;
   const int DN = D * nb;
@@ -428,11 +432,7 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
   double* sm_h = reinterpret_cast<double*>(smem + lay.off_h);
   uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
-  double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
-  uint32_t* sm_q = reinterpret_cast<uint32_t*>(smem + lay.off_q);
 
-  // ---- stage the map, the angle tables, the f tables (unless the previous task of this block staged the same
-  // item) and clear the histograms ----
   const double* __restrict__ map = L.maps + it->map_off;
   for (int i = tid; stage && i < DN; i += kBlock) {
     const int d = i / nb, j = i - d * nb;
@@ -460,8 +460,6 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     sm_c[i] = 0u;
   }
 
-  // ---- per-item constants at the current time ----
-  ItemConsts<NI, FT> K;
   K.e = sm_e;
   K.w = sm_w;
   K.sc = sm_sc;
@@ -517,86 +515,32 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
   K.c3 = st->epoch * 64u + (uint32_t)L.it;
   K.seed_lo = L.seed_lo;
   K.seed_hi = L.seed_hi;
-  const int64_t N = it->N;
-  const int64_t n0 = (int64_t)task.unit * it->unit_size;
-  const int64_t n1 = min(n0 + (int64_t)it->unit_size, N);
-  const int wave = tid >> 6, lane = tid & 63;
-  double* my_h = sm_h + wave * DN;
-  uint32_t* my_c = sm_c + wave * DN;
   __syncthreads();
+  return lay;
+}
 
-  double S1 = 0.0, S2 = 0.0;
-  auto accumulate = [&](double W, const int* hj) {
-    S1 += W;
-    S2 += W * W;
-    const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
+// One sample's contribution: S1 += W, S2 += W^2 (registers), W^2 and a count into the wave's histograms.
+template <int D>
+__device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, double& S2, double* my_h,
+                                           uint32_t* my_c) {
+  S1 += W;
+  S2 += W * W;
+  const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      atomicAdd(&my_h[hj[d]], w2);
-      atomicAdd(&my_c[hj[d]], 1u);
-    }
-  };
-  if constexpr (PREC == 0) {
-    for (int64_t n = n0 + tid; n < n1; n += kBlock) {
-      int hj[D];
-      const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
-      accumulate(W, hj);
-    }
-  } else {
-    // Each wave takes rounds of 64 samples (wave w, round k: samples n0 + 256 k + 64 w + lane).  The FP32 pass
-    // finishes off-shell samples; the in-shell ones are appended, in lane order, to the wave's ring of sample
-    // offsets in LDS and recomputed with FP64 kinematics 64 at a time (lane l takes the l-th oldest entry).  At
-    // the end of the unit the rings' remainders (wave 0's first) are spread over the whole block.  The order
-    // depends only on the samples, and waves do not wait for each other inside the unit.
-    const float shell = (float)it->shell;
-    uint32_t* ring = sm_q + wave * 128;
-    int* sm_head = reinterpret_cast<int*>(sm_q + kWaves * 128);
-    int* sm_fill = sm_head + kWaves;
-    uint32_t head = 0, tail = 0;  // wave-uniform
-    const uint64_t below = (1ull << lane) - 1ull;
-    for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
-      const int64_t n = rbase + lane;
-      bool in = false;
-      if (n < n1) {
-        int hj[D];
-        double W = 0.0;
-        in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
-        if (!in) accumulate(W, hj);
-      }
-      const uint64_t ball = __ballot(in);
-      if (in) ring[(tail + (uint32_t)__popcll(ball & below)) & 127u] = (uint32_t)(n - n0);
-      tail += (uint32_t)__popcll(ball);
-      if (tail - head >= 64u) {
-        // the ring entries written above by other lanes of this wave are read below
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        int hj[D];
-        const uint32_t off = ring[(head + (uint32_t)lane) & 127u];
-        const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + off), hj);
-        accumulate(W, hj);
-        head += 64u;
-      }
-    }
-    if (lane == 0) {
-      sm_head[wave] = (int)(head & 127u);
-      sm_fill[wave] = (int)(tail - head);
-    }
-    __syncthreads();
-    int src = -1, at = tid;
-    for (int w = 0; w < kWaves; ++w) {
-      if (src < 0 && at < sm_fill[w]) src = w;
-      if (src < 0) at -= sm_fill[w];
-    }
-    if (src >= 0) {
-      int hj[D];
-      const uint32_t off = sm_q[src * 128 + ((sm_head[src] + at) & 127)];
-      const double W = eval_sample<NI, float>(K, (uint64_t)(n0 + off), hj);
-      accumulate(W, hj);
-    }
+  for (int d = 0; d < D; ++d) {
+    atomicAdd(&my_h[hj[d]], w2);
+    atomicAdd(&my_c[hj[d]], 1u);
   }
+}
 
-  // ---- fixed-order reductions ----
+// Fixed-order end of a block's pass: butterfly wave sums of S1, S2, the four waves in order into s_out[0..1],
+// and the wave histograms summed in wave order into rec[0 .. 2 DN) (sums of W^2, then counts).
+__device__ __forceinline__ void finish_block(double S1, double S2, const Lds& lay, int DN, unsigned char* smem,
+                                             double* s_out, double* rec) {
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const double* sm_h = reinterpret_cast<const double*>(smem + lay.off_h);
+  const uint32_t* sm_c = reinterpret_cast<const uint32_t*>(smem + lay.off_c);
+  double* sm_red = reinterpret_cast<double*>(smem + lay.off_red);
   S1 = wave_sum(S1);
   S2 = wave_sum(S2);
   if (lane == 0) {
@@ -604,17 +548,15 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     sm_red[2 * wave + 1] = S2;
   }
   __syncthreads();
-  const int64_t gu = L.unit_base[task.item] + task.unit;
   if (tid == 0) {
     double s1 = 0.0, s2 = 0.0;
     for (int w = 0; w < kWaves; ++w) {
       s1 += sm_red[2 * w];
       s2 += sm_red[2 * w + 1];
     }
-    L.unit_s[2 * gu] = s1;
-    L.unit_s[2 * gu + 1] = s2;
+    s_out[0] = s1;
+    s_out[1] = s2;
   }
-  double* rec = L.parts + it->part_off + (int64_t)task.unit * 2 * DN;
   for (int i = tid; i < DN; i += kBlock) {
     double h = 0.0;
     uint32_t c = 0;
@@ -626,6 +568,111 @@ __device__ void sample_task(const SampleLaunch& L, const Task task, unsigned cha
     rec[DN + i] = (double)c;
   }
   __syncthreads();
+}
+
+// FP64: every sample of one unit with FP64 kinematics and integrand.
+template <int NI>
+__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
+  constexpr int D = 3 * NI;
+  const ItemRec* __restrict__ it = &L.items[task.item];
+  ItemConsts<NI, double> K;
+  const Lds lay = setup_block<NI, 0>(L, it, smem, stage, K);
+  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
+  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
+  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
+  const int64_t n0 = (int64_t)task.unit * it->unit_size;
+  const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
+  double S1 = 0.0, S2 = 0.0;
+  for (int64_t n = n0 + tid; n < n1; n += kBlock) {
+    int hj[D];
+    const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
+    accumulate<D>(W, hj, S1, S2, my_h, my_c);
+  }
+  const int64_t gu = L.unit_base[task.item] + task.unit;
+  finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)task.unit * 2 * DN);
+}
+
+// FP32 integrand, screening pass over one unit.  Wave w takes rounds of 64 samples (round k: samples
+// n0 + 256 k + 64 w + lane).  Off-shell samples are finished in FP32 and accumulated; the offsets n - n0 of the
+// in-shell ones are appended, in sample order, to the wave's list of the task position `pos` (list_stride / 4
+// entries per wave) for the in-shell pass, and the wave's count is stored.
+template <int NI>
+__device__ void screen_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem, bool stage) {
+  constexpr int D = 3 * NI;
+  const ItemRec* __restrict__ it = &L.items[task.item];
+  ItemConsts<NI, float> K;
+  const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
+  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
+  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
+  const int64_t n0 = (int64_t)task.unit * it->unit_size;
+  const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
+  const float shell = (float)it->shell;
+  uint16_t* lst = L.shell_list + (int64_t)pos * L.list_stride + (int64_t)wave * (L.list_stride / kWaves);
+  const uint64_t below = (1ull << lane) - 1ull;
+  uint32_t cnt = 0;  // wave-uniform
+  double S1 = 0.0, S2 = 0.0;
+  for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
+    const int64_t n = rbase + lane;
+    bool in = false;
+    if (n < n1) {
+      int hj[D];
+      double W = 0.0;
+      in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
+      if (!in) accumulate<D>(W, hj, S1, S2, my_h, my_c);
+    }
+    const uint64_t ball = __ballot(in);
+    if (in) lst[cnt + (uint32_t)__popcll(ball & below)] = (uint16_t)(n - n0);
+    cnt += (uint32_t)__popcll(ball);
+  }
+  if (lane == 0) L.shell_cnt[(int64_t)pos * kWaves + wave] = cnt;
+  const int64_t gu = L.unit_base[task.item] + task.unit;
+  finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)task.unit * 2 * DN);
+}
+
+// FP32 integrand, in-shell pass over a range of units of one item: the lists of the units (unit order, waves in
+// order within a unit) are read as one sequence whose entry e is evaluated by thread e mod 256 with FP64
+// kinematics; the block's sums go to the range's in-shell record.  Units are taken 64 at a time (256 lists).
+template <int NI>
+__device__ void shell_task(const SampleLaunch& L, const ShellTask sht, unsigned char* smem) {
+  constexpr int D = 3 * NI;
+  constexpr int kLists = kBlock;  // lists per chunk: 64 units x 4 waves
+  const ItemRec* __restrict__ it = &L.items[sht.item];
+  ItemConsts<NI, float> K;
+  const Lds lay = setup_block<NI, 1>(L, it, smem, true, K);
+  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
+  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
+  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
+  int* pre = reinterpret_cast<int*>(smem + lay.off_q);  // kLists + 1 prefix sums
+  const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // task position of unit 0
+  const int64_t wstride = L.list_stride / kWaves;
+  double S1 = 0.0, S2 = 0.0;
+  for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
+    const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
+    if (tid < nl) pre[tid + 1] = (int)L.shell_cnt[(int64_t)(pos0 + u0) * kWaves + tid];
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+    if (tid == 0)
+      for (int l = 1; l <= nl; ++l) pre[l] += pre[l - 1];
+    __syncthreads();
+    const int M = pre[nl];
+    for (int e = tid; e < M; e += kBlock) {
+      int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pre[mid] <= e) lo = mid;
+        else hi = mid;
+      }
+      const int u = u0 + lo / kWaves, w = lo % kWaves;
+      const uint32_t off = L.shell_list[(int64_t)(pos0 + u) * L.list_stride + w * wstride + (e - pre[lo])];
+      int hj[D];
+      const double W = eval_sample<NI, float>(K, (uint64_t)((int64_t)u * it->unit_size + off), hj);
+      accumulate<D>(W, hj, S1, S2, my_h, my_c);
+    }
+    __syncthreads();  // pre is rewritten by the next chunk
+  }
+  double* rec = L.shell_rec + sht.rec;
+  finish_block(S1, S2, lay, DN, smem, rec, rec + 2);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -989,11 +1036,11 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
   }
 }
 
-// Persistent sample kernel: block b takes the chunks b, b + G, b + 2G, ... of `chunk` consecutive tasks (the
+// Persistent sample kernels: block b takes the chunks b, b + G, b + 2G, ... of `chunk` consecutive tasks (the
 // units of one item are consecutive, so a chunk mostly re-uses the staged map and tables).  Which block runs a
-// task does not change its result.  Registers are capped at 256 per lane (two waves per SIMD): beyond that the
-// compiler moves values into accumulation registers and occupancy halves.
-template <int MASK, int PREC>
+// task does not change its result.  Registers are capped per lane so that two (FP64) or three (FP32 screening)
+// waves share a SIMD: above 256 the compiler moves values into accumulation registers and occupancy halves.
+template <int MASK>
 __global__ __launch_bounds__(kBlock, 2) void k_sample(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int chunk = L.chunk > 0 ? L.chunk : 1;
@@ -1005,11 +1052,45 @@ __global__ __launch_bounds__(kBlock, 2) void k_sample(SampleLaunch L) {
       const int ni = L.items[task.item].nint;
       const bool stage = task.item != prev_item;
       prev_item = task.item;
-      if ((MASK & 1) && ni == 1) sample_task<1, PREC>(L, task, smem, stage);
-      if ((MASK & 2) && ni == 2) sample_task<2, PREC>(L, task, smem, stage);
-      if ((MASK & 4) && ni == 3) sample_task<3, PREC>(L, task, smem, stage);
-      if ((MASK & 8) && ni == 4) sample_task<4, PREC>(L, task, smem, stage);
+      if ((MASK & 1) && ni == 1) sample_task<1>(L, task, smem, stage);
+      if ((MASK & 2) && ni == 2) sample_task<2>(L, task, smem, stage);
+      if ((MASK & 4) && ni == 3) sample_task<3>(L, task, smem, stage);
+      if ((MASK & 8) && ni == 4) sample_task<4>(L, task, smem, stage);
     }
+  }
+}
+
+template <int MASK>
+__global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int chunk = L.chunk > 0 ? L.chunk : 1;
+  int prev_item = -1;
+  for (int base = blockIdx.x * chunk; base < L.n_tasks; base += gridDim.x * chunk) {
+    const int end = min(base + chunk, L.n_tasks);
+    for (int t = base; t < end; ++t) {
+      const Task task = L.tasks[L.task_begin + t];
+      const int ni = L.items[task.item].nint;
+      const bool stage = task.item != prev_item;
+      prev_item = task.item;
+      if ((MASK & 1) && ni == 1) screen_task<1>(L, task, t, smem, stage);
+      if ((MASK & 2) && ni == 2) screen_task<2>(L, task, t, smem, stage);
+      if ((MASK & 4) && ni == 3) screen_task<3>(L, task, t, smem, stage);
+      if ((MASK & 8) && ni == 4) screen_task<4>(L, task, t, smem, stage);
+    }
+  }
+}
+
+// In-shell pass: block b takes the items' in-shell work b, b + G, ...
+template <int MASK>
+__global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  for (int k = blockIdx.x; k < L.n_sh; k += gridDim.x) {
+    const ShellTask sht = L.sh_tasks[L.sh_begin + k];
+    const int ni = L.items[sht.item].nint;
+    if ((MASK & 1) && ni == 1) shell_task<1>(L, sht, smem);
+    if ((MASK & 2) && ni == 2) shell_task<2>(L, sht, smem);
+    if ((MASK & 4) && ni == 3) shell_task<3>(L, sht, smem);
+    if ((MASK & 8) && ni == 4) shell_task<4>(L, sht, smem);
   }
 }
 
@@ -1060,8 +1141,9 @@ __device__ void adapt_dimension(double* edges, int nb, const double* h, const do
 }
 
 __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const double* unit_s,
-                                                      const int64_t* unit_base, const double* parts, double* res_I,
-                                                      double* res_V, int slot, double* maps, int freeze) {
+                                                      const int64_t* unit_base, const double* parts,
+                                                      const double* shell_rec, double* res_I, double* res_V,
+                                                      int slot, double* maps, int freeze) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
   __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1];
   const int item = item_begin + blockIdx.x;
@@ -1074,6 +1156,14 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     for (int u = 0; u < it.n_units; ++u) {
       S1 += unit_s[2 * (u0 + u)];
       S2 += unit_s[2 * (u0 + u) + 1];
+    }
+    if (shell_rec) {
+      const int64_t stride = 2 + 2 * (int64_t)it.D * it.nb;
+      for (int u = 0; u < it.n_units; u += it.shell_units) {
+        const int64_t r = it.shell_off + (u / it.shell_units) * stride;
+        S1 += shell_rec[r];
+        S2 += shell_rec[r + 1];
+      }
     }
     const double Nd = (double)it.N;
     const double I = S1 / Nd;
@@ -1088,6 +1178,13 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     for (int u = 0; u < it.n_units; ++u) {
       h += rec[(int64_t)u * 2 * DN + i];
       c += rec[(int64_t)u * 2 * DN + DN + i];
+    }
+    if (shell_rec) {
+      for (int u = 0; u < it.n_units; u += it.shell_units) {
+        const int64_t r = it.shell_off + (u / it.shell_units) * (2 + 2 * (int64_t)DN);
+        h += shell_rec[r + 2 + i];
+        c += shell_rec[r + 2 + DN + i];
+      }
     }
     sh[i] = h;
     sc[i] = c;
@@ -1324,9 +1421,19 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
     dst[i] = src[i];
 }
 
-template <int MASK, int PREC>
+template <int MASK>
 hipError_t launch_sample_t(const SampleLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_sample<MASK, PREC>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+  if (L.precision == 0) {
+    hipLaunchKernelGGL((k_sample<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+  } else {
+    hipLaunchKernelGGL((k_screen<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+  }
+  return hipGetLastError();
+}
+
+template <int MASK>
+hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
+  hipLaunchKernelGGL((k_shell<MASK>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
   return hipGetLastError();
 }
 
@@ -1338,22 +1445,23 @@ int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
 
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {
   if (L.n_tasks <= 0) return hipSuccess;
-  const int m = L.nint_mask;
-  if (L.precision == 0) {
-    switch (m) {
-      case 1: return launch_sample_t<1, 0>(L, s);
-      case 2: return launch_sample_t<2, 0>(L, s);
-      case 4: return launch_sample_t<4, 0>(L, s);
-      case 8: return launch_sample_t<8, 0>(L, s);
-      default: return launch_sample_t<15, 0>(L, s);
-    }
+  switch (L.nint_mask) {
+    case 1: return launch_sample_t<1>(L, s);
+    case 2: return launch_sample_t<2>(L, s);
+    case 4: return launch_sample_t<4>(L, s);
+    case 8: return launch_sample_t<8>(L, s);
+    default: return launch_sample_t<15>(L, s);
   }
-  switch (m) {
-    case 1: return launch_sample_t<1, 1>(L, s);
-    case 2: return launch_sample_t<2, 1>(L, s);
-    case 4: return launch_sample_t<4, 1>(L, s);
-    case 8: return launch_sample_t<8, 1>(L, s);
-    default: return launch_sample_t<15, 1>(L, s);
+}
+
+hipError_t launch_shell(const SampleLaunch& L, hipStream_t s) {
+  if (L.n_sh <= 0) return hipSuccess;
+  switch (L.nint_mask) {
+    case 1: return launch_shell_t<1>(L, s);
+    case 2: return launch_shell_t<2>(L, s);
+    case 4: return launch_shell_t<4>(L, s);
+    case 8: return launch_shell_t<8>(L, s);
+    default: return launch_shell_t<15>(L, s);
   }
 }
 
@@ -1398,11 +1506,11 @@ hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* co
 }
 
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,
-                               const int64_t* unit_base, const double* parts, double* res_I, double* res_V,
-                               int slot, double* maps, int freeze, hipStream_t s) {
+                               const int64_t* unit_base, const double* parts, const double* shell_rec,
+                               double* res_I, double* res_V, int slot, double* maps, int freeze, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(256), 0, s, items, item_begin, unit_s, unit_base, parts,
-                     res_I, res_V, slot, maps, freeze);
+                     shell_rec, res_I, res_V, slot, maps, freeze);
   return hipGetLastError();
 }
 
