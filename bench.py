@@ -23,6 +23,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane per cycle on 256 CUs
+# HBM bytes per sample phase (screening + in-shell kernels) of this workload, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0); None once the kernels change.
+TRAFFIC_BYTES_PER_PHASE = 252.6e6 + 41.9e6
 
 
 def ops_per_sample(n_int: int) -> int:
@@ -168,12 +171,12 @@ def main():
             "speedup_vs_plain_fp64": value / plain64,
             "speedup_fp32i_vs_fp64_batched": value / batched64,
             "sigma_ratio_fp32i_over_plain_fp64": sigma_ratio,
-            "sample_kernel_avg_ms": avg_launch_s * 1e3,
-            "sample_kernel_launches": n_launch,
+            "sample_phase_avg_ms": avg_launch_s * 1e3,
+            "sample_phases": n_launch,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": None,
-                     "ops_per_sample": ops},
+                     "frac": achieved / PEAK_VALU_TOPS, "traffic": TRAFFIC_BYTES_PER_PHASE,
+                     "ops_per_sample": ops, "kernels": "k_screen + k_shell per iteration"},
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
