@@ -178,6 +178,8 @@ struct ItemConsts {
   const float2* m32;  // LDS map (edge, width) pairs in FP32 (screening pass)
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
+  float ylog2;   // log2(e) / (2 sigma_E^2)
+  float wconst;  // a^-3n |M|^2 / ((2 pi)^(3(n-1)-4) sigma_E sqrt(2 pi))
   double a, inv_a, m2[NR], eta[NR], esg[NR];
   int obsside[NR];
   double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
@@ -302,16 +304,6 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   return cut ? 0.0 : W;
 }
 
-// e^z as a double from an FP64 range reduction and the hardware exp2 on the fractional part (relative error
-// ~1e-7; no FP32 underflow).
-__device__ __forceinline__ double exp_split_d(double z) {
-  const double y = z * 1.4426950408889634074;
-  double n = floor(y);
-  const float fr = (float)(y - n);
-  n = n > 1023.0 ? 1023.0 : (n < -1100.0 ? -1100.0 : n);
-  return ldexp((double)__builtin_amdgcn_exp2f(fr), (int)n);
-}
-
 // FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns
 // whether the sample lies within the energy shell |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed
 // energies, far above the FP32 error); for samples outside it also returns W finished in FP32 (their Gaussian
@@ -399,12 +391,15 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
     gain *= K.obsside[NI] ? bf : fc;
     loss *= K.obsside[NI] ? fc : bf;
     const float F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
-    const double x = (double)dE * (double)dE * K.inv2s2;
-    const double delta = exp_split_d(-x) * K.dnorm;
+    // W = m 2^e F: the Gaussian's exponent y = -dE^2 log2(e) / (2 sigma_E^2) = e + (y - e) with e integer, the
+    // weight factors and 2^(y - e) in FP32 (their product stays well inside the FP32 range), the power of two and
+    // F applied in FP64 (W itself can lie far below the FP32 range)
+    // (y is rounded before it is split: a fused y - floor(y) could leave [0, 1) by up to half an ulp of y)
+    const float y = -(dE * dE) * K.ylog2;
+    const float e = floorf(y);
+    const float m = J * jac * K.wconst * __builtin_amdgcn_rcpf(prod2E) * __builtin_amdgcn_exp2f(__builtin_amdgcn_fractf(y));
     cut |= Ec < (float)K.e_cut;
-    *Wout = cut ? 0.0
-                : (double)J * (double)jac * (K.a3M2 / K.twopi_pow) * delta * (double)__builtin_amdgcn_rcpf(prod2E) *
-                      (double)F;
+    *Wout = cut ? 0.0 : ldexp((double)m, (int)fmaxf(e, -1100.0f)) * (double)F;
   }
   return in;
 }
@@ -508,6 +503,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   K.inv2s2 = it->inv2s2;
   K.dnorm = it->dnorm;
   K.twopi_pow = it->twopi_pow;
+  K.ylog2 = (float)(1.4426950408889634 * it->inv2s2);
+  K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
   K.nb = nb;
   K.net = it->net;
   K.term = it->term;
