@@ -404,6 +404,14 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
   return in;
 }
 
+// Clears the per-wave training histograms (W^2 sums and counts, contiguous up to the reduction scratch) with
+// 16-byte stores.
+__device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) {
+  uint4* p = reinterpret_cast<uint4*>(smem + lay.off_h);
+  const int n16 = (lay.off_red - lay.off_h) / 16;
+  for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 pairs), the sin/cos table and
 // the f tables into LDS unless the block's previous task staged the same item, clears the per-wave training
 // histograms, and fills the per-item constants at the current time.  Ends with a block barrier.
@@ -425,8 +433,6 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
   float2* sm_m32 = reinterpret_cast<float2*>(smem + lay.off_m32);
   double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
-  double* sm_h = reinterpret_cast<double*>(smem + lay.off_h);
-  uint32_t* sm_c = reinterpret_cast<uint32_t*>(smem + lay.off_c);
 
   const double* __restrict__ map = L.maps + it->map_off;
   for (int i = tid; stage && i < DN; i += kBlock) {
@@ -450,10 +456,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       else f[j] = L.f32[S.f_off + j];
     }
   }
-  for (int i = tid; i < kWaves * DN; i += kBlock) {
-    sm_h[i] = 0.0;
-    sm_c[i] = 0u;
-  }
+  clear_hist(lay, smem);
 
   K.e = sm_e;
   K.w = sm_w;
@@ -567,64 +570,81 @@ __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& la
   __syncthreads();
 }
 
-// FP64: every sample of one unit with FP64 kinematics and integrand.
+// FP64: every sample of the units of tasks t0 .. t1-1 (all of one item) with FP64 kinematics and integrand.
 template <int NI>
-__device__ void sample_task(const SampleLaunch& L, const Task task, unsigned char* smem, bool stage) {
+__device__ void sample_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
-  const ItemRec* __restrict__ it = &L.items[task.item];
+  const int item = L.tasks[L.task_begin + t0].item;
+  const ItemRec* __restrict__ it = &L.items[item];
   ItemConsts<NI, double> K;
   const Lds lay = setup_block<NI, 0>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
-  const int64_t n0 = (int64_t)task.unit * it->unit_size;
-  const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
-  double S1 = 0.0, S2 = 0.0;
-  for (int64_t n = n0 + tid; n < n1; n += kBlock) {
-    int hj[D];
-    const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
-    accumulate<D>(W, hj, S1, S2, my_h, my_c);
+  for (int t = t0; t < t1; ++t) {
+    const int unit = L.tasks[L.task_begin + t].unit;
+    if (t > t0) {
+      clear_hist(lay, smem);
+      __syncthreads();
+    }
+    const int64_t n0 = (int64_t)unit * it->unit_size;
+    const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
+    double S1 = 0.0, S2 = 0.0;
+    for (int64_t n = n0 + tid; n < n1; n += kBlock) {
+      int hj[D];
+      const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
+      accumulate<D>(W, hj, S1, S2, my_h, my_c);
+    }
+    const int64_t gu = L.unit_base[item] + unit;
+    finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
   }
-  const int64_t gu = L.unit_base[task.item] + task.unit;
-  finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)task.unit * 2 * DN);
 }
 
-// FP32 integrand, screening pass over one unit.  Wave w takes rounds of 64 samples (round k: samples
-// n0 + 256 k + 64 w + lane).  Off-shell samples are finished in FP32 and accumulated; the offsets n - n0 of the
-// in-shell ones are appended, in sample order, to the wave's list of the task position `pos` (list_stride / 4
-// entries per wave) for the in-shell pass, and the wave's count is stored.
+// FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
+// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Off-shell samples are
+// finished in FP32 and accumulated; the offsets n - n0 of the in-shell ones are appended, in sample order, to
+// the wave's list of the task position (list_stride / 4 entries per wave) for the in-shell pass, and the
+// wave's count is stored.
 template <int NI>
-__device__ void screen_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem, bool stage) {
+__device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
-  const ItemRec* __restrict__ it = &L.items[task.item];
+  const int item = L.tasks[L.task_begin + t0].item;
+  const ItemRec* __restrict__ it = &L.items[item];
   ItemConsts<NI, float> K;
   const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
-  const int64_t n0 = (int64_t)task.unit * it->unit_size;
-  const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
   const float shell = (float)it->shell;
-  uint16_t* lst = L.shell_list + (int64_t)pos * L.list_stride + (int64_t)wave * (L.list_stride / kWaves);
   const uint64_t below = (1ull << lane) - 1ull;
-  uint32_t cnt = 0;  // wave-uniform
-  double S1 = 0.0, S2 = 0.0;
-  for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
-    const int64_t n = rbase + lane;
-    bool in = false;
-    if (n < n1) {
-      int hj[D];
-      double W = 0.0;
-      in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
-      if (!in) accumulate<D>(W, hj, S1, S2, my_h, my_c);
+  for (int t = t0; t < t1; ++t) {
+    const int unit = L.tasks[L.task_begin + t].unit;
+    if (t > t0) {
+      clear_hist(lay, smem);
+      __syncthreads();
     }
-    const uint64_t ball = __ballot(in);
-    if (in) lst[cnt + (uint32_t)__popcll(ball & below)] = (uint16_t)(n - n0);
-    cnt += (uint32_t)__popcll(ball);
+    const int64_t n0 = (int64_t)unit * it->unit_size;
+    const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
+    uint16_t* lst = L.shell_list + (int64_t)t * L.list_stride + (int64_t)wave * (L.list_stride / kWaves);
+    uint32_t cnt = 0;  // wave-uniform
+    double S1 = 0.0, S2 = 0.0;
+    for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
+      const int64_t n = rbase + lane;
+      bool in = false;
+      if (n < n1) {
+        int hj[D];
+        double W = 0.0;
+        in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
+        if (!in) accumulate<D>(W, hj, S1, S2, my_h, my_c);
+      }
+      const uint64_t ball = __ballot(in);
+      if (in) lst[cnt + (uint32_t)__popcll(ball & below)] = (uint16_t)(n - n0);
+      cnt += (uint32_t)__popcll(ball);
+    }
+    if (lane == 0) L.shell_cnt[(int64_t)t * kWaves + wave] = cnt;
+    const int64_t gu = L.unit_base[item] + unit;
+    finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
   }
-  if (lane == 0) L.shell_cnt[(int64_t)pos * kWaves + wave] = cnt;
-  const int64_t gu = L.unit_base[task.item] + task.unit;
-  finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)task.unit * 2 * DN);
 }
 
 // FP32 integrand, in-shell pass over a range of units of one item: the lists of the units (unit order, waves in
@@ -1044,15 +1064,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_sample(SampleLaunch L) {
   int prev_item = -1;
   for (int base = blockIdx.x * chunk; base < L.n_tasks; base += gridDim.x * chunk) {
     const int end = min(base + chunk, L.n_tasks);
-    for (int t = base; t < end; ++t) {
-      const Task task = L.tasks[L.task_begin + t];
-      const int ni = L.items[task.item].nint;
-      const bool stage = task.item != prev_item;
-      prev_item = task.item;
-      if ((MASK & 1) && ni == 1) sample_task<1>(L, task, smem, stage);
-      if ((MASK & 2) && ni == 2) sample_task<2>(L, task, smem, stage);
-      if ((MASK & 4) && ni == 3) sample_task<3>(L, task, smem, stage);
-      if ((MASK & 8) && ni == 4) sample_task<4>(L, task, smem, stage);
+    for (int t = base; t < end;) {
+      const int item = L.tasks[L.task_begin + t].item;
+      int t1 = t + 1;
+      while (t1 < end && L.tasks[L.task_begin + t1].item == item) ++t1;
+      const int ni = L.items[item].nint;
+      const bool stage = item != prev_item;
+      prev_item = item;
+      if ((MASK & 1) && ni == 1) sample_run<1>(L, t, t1, smem, stage);
+      if ((MASK & 2) && ni == 2) sample_run<2>(L, t, t1, smem, stage);
+      if ((MASK & 4) && ni == 3) sample_run<3>(L, t, t1, smem, stage);
+      if ((MASK & 8) && ni == 4) sample_run<4>(L, t, t1, smem, stage);
+      t = t1;
     }
   }
 }
@@ -1064,15 +1087,18 @@ __global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
   int prev_item = -1;
   for (int base = blockIdx.x * chunk; base < L.n_tasks; base += gridDim.x * chunk) {
     const int end = min(base + chunk, L.n_tasks);
-    for (int t = base; t < end; ++t) {
-      const Task task = L.tasks[L.task_begin + t];
-      const int ni = L.items[task.item].nint;
-      const bool stage = task.item != prev_item;
-      prev_item = task.item;
-      if ((MASK & 1) && ni == 1) screen_task<1>(L, task, t, smem, stage);
-      if ((MASK & 2) && ni == 2) screen_task<2>(L, task, t, smem, stage);
-      if ((MASK & 4) && ni == 3) screen_task<3>(L, task, t, smem, stage);
-      if ((MASK & 8) && ni == 4) screen_task<4>(L, task, t, smem, stage);
+    for (int t = base; t < end;) {
+      const int item = L.tasks[L.task_begin + t].item;
+      int t1 = t + 1;
+      while (t1 < end && L.tasks[L.task_begin + t1].item == item) ++t1;
+      const int ni = L.items[item].nint;
+      const bool stage = item != prev_item;
+      prev_item = item;
+      if ((MASK & 1) && ni == 1) screen_run<1>(L, t, t1, smem, stage);
+      if ((MASK & 2) && ni == 2) screen_run<2>(L, t, t1, smem, stage);
+      if ((MASK & 4) && ni == 3) screen_run<3>(L, t, t1, smem, stage);
+      if ((MASK & 8) && ni == 4) screen_run<4>(L, t, t1, smem, stage);
+      t = t1;
     }
   }
 }
