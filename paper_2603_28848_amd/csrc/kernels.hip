@@ -519,18 +519,21 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   return lay;
 }
 
-// One sample's contribution: S1 += W, S2 += W^2 (registers), W^2 and a count into the wave's histograms.
+// One sample's contribution: S1 += W, S2 += W^2 (registers), W^2 and a count into the wave's histograms.  A zero
+// W^2 (cut samples, and every |W| below the histogram floor: with sigma_E << E most off-shell samples) leaves the
+// sums unchanged, so its atomics are skipped.
 template <int D>
 __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, double& S2, double* my_h,
                                            uint32_t* my_c) {
   S1 += W;
   S2 += W * W;
-  const double w2 = fabs(W) >= kHistWMin ? W * W : 0.0;
+  if (fabs(W) >= kHistWMin) {
+    const double w2 = W * W;
 #pragma unroll
-  for (int d = 0; d < D; ++d) {
-    atomicAdd(&my_h[hj[d]], w2);
-    atomicAdd(&my_c[hj[d]], 1u);
+    for (int d = 0; d < D; ++d) atomicAdd(&my_h[hj[d]], w2);
   }
+#pragma unroll
+  for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
 }
 
 // Fixed-order end of a block's pass: butterfly wave sums of S1, S2, the four waves in order into s_out[0..1],
