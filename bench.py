@@ -24,8 +24,9 @@ if ROOT not in sys.path:
 
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane per cycle on 256 CUs
 # HBM bytes per sample phase (screening + in-shell kernels) of this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0); None once the kernels change.
-TRAFFIC_BYTES_PER_PHASE = 252.6e6 + 41.9e6
+# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0); None until the current kernels
+# are measured.
+TRAFFIC_BYTES_PER_PHASE = None
 
 
 def ops_per_sample(n_int: int) -> int:

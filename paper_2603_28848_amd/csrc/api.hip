@@ -27,7 +27,7 @@ constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
 // FP32 integrand: bytes of in-shell lists one screening launch may fill (larger batches run in slices)
 constexpr size_t kListCapBytes = size_t(1) << 30;
 // FP32 integrand: samples per in-shell record (the in-shell pass takes the units of an item in groups this large)
-constexpr int64_t kShellGroupSamples = 65536;
+constexpr int64_t kShellGroupSamples = int64_t(1) << 18;
 
 int shell_units_for(int unit_size) { return (int)std::max<int64_t>(1, kShellGroupSamples / unit_size); }
 
