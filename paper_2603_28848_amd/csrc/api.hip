@@ -621,7 +621,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   size_t o_items = take(sizeof(ItemRec) * nI), o_tb = take(sizeof(Task) * Q.tasks_batched.size()),
          o_tp = take(sizeof(Task) * Q.tasks_plain.size()), o_shb = take(sizeof(ShellTask) * Q.sh_batched.size()),
          o_shp = take(sizeof(ShellTask) * Q.sh_plain.size()), o_list = take(2 * (size_t)(Q.list_pos * Q.list_stride)),
-         o_cnt = take(4 * kWaves * (size_t)Q.list_pos), o_shell = take(8 * (size_t)Q.n_shell),
+         o_cnt = take(8 * kWaves * (size_t)Q.list_pos), o_shell = take(8 * (size_t)Q.n_shell),
          o_ub = take(8 * nI), o_us = take(16 * (size_t)units),
          o_parts = take(8 * (size_t)part), o_rI = take(8 * kMaxIter * nI), o_rV = take(8 * kMaxIter * nI),
          o_ib = take(8 * nI), o_is = take(8 * nI), o_sb = take(4 * (Q.slot_begin.size())),
@@ -693,7 +693,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
   // in-shell lists of the FP32-integrand screening pass (one slice's task positions)
   const size_t list_pos =
       std::min(units, std::max(std::max(per_item, per_node), kListCapBytes / (2 * std::max<size_t>(1, umax))));
-  s += align_up(2 * list_pos * umax) + align_up(4 * kWaves * list_pos) + align_up(8 * shell) +
+  s += align_up(2 * list_pos * umax) + align_up(8 * kWaves * list_pos) + align_up(8 * shell) +
        2 * align_up(sizeof(ShellTask) * units);
   for (auto& S : c->sp) outs += S.n;
   (void)max_iter;

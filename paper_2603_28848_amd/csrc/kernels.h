@@ -29,8 +29,9 @@ struct SampleLaunch {
   int chunk;             // consecutive tasks per block visit
   size_t lds_bytes;
   // FP32 integrand: in-shell lists of the screening pass and the in-shell pass
-  uint16_t* shell_list;  // list_stride entries per task position of the launch (4 wave lists)
-  uint32_t* shell_cnt;   // 4 counts per task position
+  uint16_t* shell_list;  // list_stride entries per task position of the launch (4 wave lists: in-shell samples
+                         // from the front, near ones from the back)
+  uint32_t* shell_cnt;   // per task position: 4 in-shell counts, then 4 near counts
   int64_t list_stride;   // largest unit size of the plan
   const ShellTask* sh_tasks;
   int sh_begin, n_sh;    // in-shell tasks (one per item) of this launch

@@ -304,14 +304,20 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   return cut ? 0.0 : W;
 }
 
-// FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns
-// whether the sample lies within the energy shell |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed
-// energies, far above the FP32 error); for samples outside it also returns W finished in FP32 (their Gaussian
-// factor is below e^-72 relative, so W only matters for the map's training histogram, where ~1e-6 accuracy is
-// ample).  The bin of every dimension is exact (the same as with the FP64 map).
-template <int NI>
-__device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell, int* hj,
-                                              double* Wout) {
+// FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns the
+// sample's class:
+//   kInShell  |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed energies, far above the FP32 error): W needs
+//             the FP64 kinematics;
+//   kFar      dE^2 / (2 sigma_E^2) > 760: the Gaussian factor, and so W, is 0 (in FP64 it underflows beyond 745);
+//   kNear     the rest: with FINISH, W is finished in FP32 (its Gaussian factor is below e^-72 relative, so W only
+//             matters for the map's training histogram, where ~1e-6 accuracy is ample).
+// The bin of every dimension is exact (the same as with the FP64 map).
+constexpr int kFar = 0, kNear = 1, kInShell = 2;
+constexpr float kFarExponent = -760.0f * 1.44269504f;  // log2 of e^-760
+
+template <int NI, bool FINISH>
+__device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell, int* hj,
+                                             double* Wout) {
   constexpr int D = 3 * NI;
   constexpr float kInv2Pi = 0.15915494309189535f;
   uint32_t wd[4 * ((D + 3) / 4)];
@@ -372,8 +378,10 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
   dE = fmaf((float)K.esg[NI], Ec, dE);
   sumE += Ec;
   prod2E *= 2.0f * Ec;
-  const bool in = fabsf(dE) < shell + 1e-3f * sumE;
-  if (!in) {
+  if (fabsf(dE) < shell + 1e-3f * sumE) return kInShell;
+  const float y = -(dE * dE) * K.ylog2;
+  if (y < kFarExponent) return kFar;
+  if constexpr (FINISH) {
     const float qc = (float)K.a * __builtin_amdgcn_sqrtf(P2);
     float fc;
     if (qc < (float)K.qc_min) {
@@ -395,13 +403,12 @@ __device__ __forceinline__ bool screen_sample(const ItemConsts<NI, float>& K, ui
     // weight factors and 2^(y - e) in FP32 (their product stays well inside the FP32 range), the power of two and
     // F applied in FP64 (W itself can lie far below the FP32 range)
     // (y is rounded before it is split: a fused y - floor(y) could leave [0, 1) by up to half an ulp of y)
-    const float y = -(dE * dE) * K.ylog2;
     const float e = floorf(y);
     const float m = J * jac * K.wconst * __builtin_amdgcn_rcpf(prod2E) * __builtin_amdgcn_exp2f(__builtin_amdgcn_fractf(y));
     cut |= Ec < (float)K.e_cut;
-    *Wout = cut ? 0.0 : ldexp((double)m, (int)fmaxf(e, -1100.0f)) * (double)F;
+    *Wout = cut ? 0.0 : ldexp((double)m, (int)e) * (double)F;
   }
-  return in;
+  return kNear;
 }
 
 // Clears the per-wave training histograms (W^2 sums and counts, contiguous up to the reduction scratch) with
@@ -536,6 +543,13 @@ __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, 
   for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
 }
 
+// A sample with W = 0: only its count enters the wave's histograms (S1, S2 and the W^2 sums are unchanged).
+template <int D>
+__device__ __forceinline__ void count_only(const int* hj, uint32_t* my_c) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
+}
+
 // Fixed-order end of a block's pass: butterfly wave sums of S1, S2, the four waves in order into s_out[0..1],
 // and the wave histograms summed in wave order into rec[0 .. 2 DN) (sums of W^2, then counts).
 __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& lay, int DN, unsigned char* smem,
@@ -604,10 +618,10 @@ __device__ void sample_run(const SampleLaunch& L, int t0, int t1, unsigned char*
 }
 
 // FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
-// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Off-shell samples are
-// finished in FP32 and accumulated; the offsets n - n0 of the in-shell ones are appended, in sample order, to
-// the wave's list of the task position (list_stride / 4 entries per wave) for the in-shell pass, and the
-// wave's count is stored.
+// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Far samples (W = 0) only add
+// their counts; the offsets n - n0 of in-shell samples are appended, in sample order, to the front of the wave's
+// list of the task position (list_stride / 4 entries per wave), those of near samples to its back, for the
+// in-shell pass; the wave's two counts are stored.
 template <int NI>
 __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
@@ -616,10 +630,10 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   ItemConsts<NI, float> K;
   const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
   const float shell = (float)it->shell;
   const uint64_t below = (1ull << lane) - 1ull;
+  const int64_t wlen = L.list_stride / kWaves;
   for (int t = t0; t < t1; ++t) {
     const int unit = L.tasks[L.task_begin + t].unit;
     if (t > t0) {
@@ -628,31 +642,36 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
     }
     const int64_t n0 = (int64_t)unit * it->unit_size;
     const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
-    uint16_t* lst = L.shell_list + (int64_t)t * L.list_stride + (int64_t)wave * (L.list_stride / kWaves);
-    uint32_t cnt = 0;  // wave-uniform
-    double S1 = 0.0, S2 = 0.0;
+    uint16_t* lst = L.shell_list + (int64_t)t * L.list_stride + (int64_t)wave * wlen;
+    uint32_t cin = 0, cnear = 0;  // wave-uniform
     for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
       const int64_t n = rbase + lane;
-      bool in = false;
+      int cls = kFar;
       if (n < n1) {
         int hj[D];
-        double W = 0.0;
-        in = screen_sample<NI>(K, (uint64_t)n, shell, hj, &W);
-        if (!in) accumulate<D>(W, hj, S1, S2, my_h, my_c);
+        double W;
+        cls = screen_sample<NI, false>(K, (uint64_t)n, shell, hj, &W);
+        if (cls == kFar) count_only<D>(hj, my_c);
       }
-      const uint64_t ball = __ballot(in);
-      if (in) lst[cnt + (uint32_t)__popcll(ball & below)] = (uint16_t)(n - n0);
-      cnt += (uint32_t)__popcll(ball);
+      const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
+      if (cls == kInShell) lst[cin + (uint32_t)__popcll(b_in & below)] = (uint16_t)(n - n0);
+      if (cls == kNear) lst[wlen - 1 - (cnear + (uint32_t)__popcll(b_near & below))] = (uint16_t)(n - n0);
+      cin += (uint32_t)__popcll(b_in);
+      cnear += (uint32_t)__popcll(b_near);
     }
-    if (lane == 0) L.shell_cnt[(int64_t)t * kWaves + wave] = cnt;
+    if (lane == 0) {
+      L.shell_cnt[(int64_t)t * 2 * kWaves + wave] = cin;
+      L.shell_cnt[(int64_t)t * 2 * kWaves + kWaves + wave] = cnear;
+    }
     const int64_t gu = L.unit_base[item] + unit;
-    finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
+    finish_block(0.0, 0.0, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
   }
 }
 
-// FP32 integrand, in-shell pass over a range of units of one item: the lists of the units (unit order, waves in
-// order within a unit) are read as one sequence whose entry e is evaluated by thread e mod 256 with FP64
-// kinematics; the block's sums go to the range's in-shell record.  Units are taken 64 at a time (256 lists).
+// FP32 integrand, second pass over a range of units of one item: first the in-shell lists, then the near lists of
+// the units (unit order, waves in order within a unit), each read as one sequence whose entry e is evaluated by
+// thread e mod 256 -- in-shell samples with FP64 kinematics, near samples with the FP32 finish; the block's sums go
+// to the range's record.  Units are taken 64 at a time (256 lists).
 template <int NI>
 __device__ void shell_task(const SampleLaunch& L, const ShellTask sht, unsigned char* smem) {
   constexpr int D = 3 * NI;
@@ -665,31 +684,41 @@ __device__ void shell_task(const SampleLaunch& L, const ShellTask sht, unsigned 
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
   int* pre = reinterpret_cast<int*>(smem + lay.off_q);  // kLists + 1 prefix sums
   const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // task position of unit 0
-  const int64_t wstride = L.list_stride / kWaves;
+  const int64_t wlen = L.list_stride / kWaves;
+  const float shell = (float)it->shell;
   double S1 = 0.0, S2 = 0.0;
-  for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
-    const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
-    if (tid < nl) pre[tid + 1] = (int)L.shell_cnt[(int64_t)(pos0 + u0) * kWaves + tid];
-    if (tid == 0) pre[0] = 0;
-    __syncthreads();
-    if (tid == 0)
-      for (int l = 1; l <= nl; ++l) pre[l] += pre[l - 1];
-    __syncthreads();
-    const int M = pre[nl];
-    for (int e = tid; e < M; e += kBlock) {
-      int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pre[mid] <= e) lo = mid;
-        else hi = mid;
+  for (int kind = 0; kind < 2; ++kind) {  // 0: in-shell lists, 1: near lists
+    for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
+      const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
+      if (tid < nl) {
+        const int u = u0 + tid / kWaves, w = tid % kWaves;
+        pre[tid + 1] = (int)L.shell_cnt[(int64_t)(pos0 + u) * 2 * kWaves + kind * kWaves + w];
       }
-      const int u = u0 + lo / kWaves, w = lo % kWaves;
-      const uint32_t off = L.shell_list[(int64_t)(pos0 + u) * L.list_stride + w * wstride + (e - pre[lo])];
-      int hj[D];
-      const double W = eval_sample<NI, float>(K, (uint64_t)((int64_t)u * it->unit_size + off), hj);
-      accumulate<D>(W, hj, S1, S2, my_h, my_c);
+      if (tid == 0) pre[0] = 0;
+      __syncthreads();
+      if (tid == 0)
+        for (int l = 1; l <= nl; ++l) pre[l] += pre[l - 1];
+      __syncthreads();
+      const int M = pre[nl];
+      for (int e = tid; e < M; e += kBlock) {
+        int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (pre[mid] <= e) lo = mid;
+          else hi = mid;
+        }
+        const int u = u0 + lo / kWaves, w = lo % kWaves, k = e - pre[lo];
+        const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
+        const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
+        const uint64_t n = (uint64_t)((int64_t)u * it->unit_size + off);
+        int hj[D];
+        double W = 0.0;
+        if (kind == 0) W = eval_sample<NI, float>(K, n, hj);
+        else screen_sample<NI, true>(K, n, shell, hj, &W);
+        accumulate<D>(W, hj, S1, S2, my_h, my_c);
+      }
+      __syncthreads();  // pre is rewritten by the next chunk
     }
-    __syncthreads();  // pre is rewritten by the next chunk
   }
   double* rec = L.shell_rec + sht.rec;
   finish_block(S1, S2, lay, DN, smem, rec, rec + 2);
