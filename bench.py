@@ -29,16 +29,23 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane 
 TRAFFIC_BYTES_PER_PHASE = None
 
 
-def ops_per_sample(n_int: int) -> int:
-    """Arithmetic operations the estimator needs per sample (each +, -, *, /, fma, sqrt, exp, log, sin, cos,
-    compare/select and each 32x32->64 multiply or 3-way xor of Philox counts one):
-    Philox 40 per block (10 rounds x 2 multiplies + 2 xors) x ceil(D/4); 9 per dimension (uniform from the
-    word, map lookup, Jacobian); 15 per integrated particle (momentum components, r^2 sin(theta), energy);
-    conserved momentum 3 (n_int + 1) + 5; energy sum and Gaussian (n_int + 2) + 4; f lookups 8 (n_int + 1) + 2;
-    statistical factor 3 (n_int + 2); weight 2 (n_int + 2) + 4; accumulation 5 + 2 D."""
+def ops_common(n_int: int) -> int:
+    """Arithmetic operations every sample needs (each +, -, *, /, fma, sqrt, exp, log, sin, cos, compare/select and
+    each 32x32->64 multiply or 3-way xor of Philox counts one): Philox 40 per block (10 rounds x 2 multiplies + 2
+    xors) x ceil(D/4); 7 per dimension (uniform from the word, bin, offset, map edge and width, x, its bin count);
+    13 per integrated particle (momentum components, energy); conserved momentum 3 (n_int + 1) + 5; energy sum,
+    Gaussian argument and its test (n_int + 2) + 5."""
     D = 3 * n_int
-    return (40 * ((D + 3) // 4) + 9 * D + 15 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 4 + 8 * (n_int + 1) + 2
-            + 3 * (n_int + 2) + 2 * (n_int + 2) + 4 + 5 + 2 * D)
+    return 40 * ((D + 3) // 4) + 7 * D + 13 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 5
+
+
+def ops_weight(n_int: int) -> int:
+    """Further operations of a sample whose W can be nonzero (in or near the energy shell): Jacobian 2 per
+    dimension and 2 per integrated particle; f lookups 8 (n_int + 1) + 2; statistical factor 3 (n_int + 2); weight
+    2 (n_int + 2) + 4; accumulation of W, W^2 and the W^2 histogram 5 + 2 D.  With ops_common this is the whole
+    estimator for one sample (359 operations at n_int = 3)."""
+    D = 3 * n_int
+    return 2 * D + 2 * n_int + 8 * (n_int + 1) + 2 + 3 * (n_int + 2) + 2 * (n_int + 2) + 4 + 5 + 2 * D
 
 
 def cpu_baseline(w, threads):
@@ -99,15 +106,13 @@ def main():
     n_items, n_out = ctx.plan_size(-1, -1, opts)
     samples_per_step = n_items * p.n_samples * p.n_iter
     tuned = ctx.autotune(-1, -1, opts)  # launch shape only; results do not depend on it
-    first_sigma = None
     for k in range(max(1, args.warmup)):
         opts.epoch = k
-        C, S = ctx.collision(-1, -1, opts)
-        if k == 0:
-            first_sigma = S.copy()
+        ctx.collision(-1, -1, opts)
     torch.cuda.synchronize()
     ctx.set_timing(True)
     ctx.get_timing(reset=True)
+    ctx.get_sample_stats(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -116,35 +121,47 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernel_ms, n_launch = ctx.get_timing(reset=True)
+    n_listed = ctx.get_sample_stats(reset=True)
     ctx.set_timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = samples_per_step / ((t1 - t0) / args.steps)
 
-    # ---- plain per-grid-point FP64 and batched FP64 on fresh contexts (same seed/epoch as warm-up 0) ----
+    # ---- plain per-grid-point FP64 and batched FP64 on fresh contexts (one warm-up evaluation each) ----
     def rate(precision, launch, steps):
         c2 = bm.from_workload(w)
         o = bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch)
         if launch == bm.LAUNCH_BATCHED:
             c2.autotune(-1, -1, o)
-        Cx, Sx = c2.collision(-1, -1, o)  # first evaluation from the uniform maps (sigma comparison)
+        c2.collision(-1, -1, o)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for k in range(steps):
             o.epoch = 1000 + k
             c2.collision(-1, -1, o)
         torch.cuda.synchronize()
-        return samples_per_step * steps / (time.perf_counter() - ta), Sx
+        return samples_per_step * steps / (time.perf_counter() - ta)
 
-    plain64, sig_plain = rate(bm.FP64, bm.LAUNCH_PLAIN, args.plain_steps)
-    batched64, _ = rate(bm.FP64, bm.LAUNCH_BATCHED, max(1, args.plain_steps))
-    ok = (first_sigma > 0) & (sig_plain > 0)
-    sigma_ratio = float(np.median(first_sigma[ok] / sig_plain[ok]))
+    plain64 = rate(bm.FP64, bm.LAUNCH_PLAIN, args.plain_steps)
+    batched64 = rate(bm.FP64, bm.LAUNCH_BATCHED, max(1, args.plain_steps))
 
-    # ---- roofline of the sample kernel ----
+    # ---- the two estimators at equal sample counts: sigma of batched FP32-integrand vs plain FP64, both on the
+    # uniform maps (frozen, so that map adaptation does not enter the comparison) ----
+    def frozen_sigma(precision, launch):
+        c3 = bm.from_workload(w)
+        return c3.collision(-1, -1, bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch,
+                                                     freeze_maps=1))[1]
+
+    sig32 = frozen_sigma(bm.FP32I, bm.LAUNCH_BATCHED)
+    sig64 = frozen_sigma(bm.FP64, bm.LAUNCH_PLAIN)
+    ok = (sig32 > 0) & (sig64 > 0)
+    sigma_ratio = float(np.median(sig32[ok] / sig64[ok]))
+
+    # ---- roofline of the sample phase (screening + second pass) ----
     avg_launch_s = kernel_ms / max(1, n_launch) / 1e3
     samples_per_launch = samples_per_step / p.n_iter
-    ops = ops_per_sample(n_int)
-    achieved = ops * samples_per_launch / avg_launch_s / 1e12
+    listed_per_launch = n_listed / max(1, n_launch)
+    ops_launch = ops_common(n_int) * samples_per_launch + ops_weight(n_int) * listed_per_launch
+    achieved = ops_launch / avg_launch_s / 1e12
 
     line = {
         "metric": "2<->3 collision-integrand samples/s (batched FP32-integrand) + speedup vs plain per-grid-point "
@@ -172,12 +189,15 @@ def main():
             "speedup_vs_plain_fp64": value / plain64,
             "speedup_fp32i_vs_fp64_batched": value / batched64,
             "sigma_ratio_fp32i_over_plain_fp64": sigma_ratio,
+            "sigma_ratio_max_dev": float(np.max(np.abs(sig32[ok] / sig64[ok] - 1.0))),
             "sample_phase_avg_ms": avg_launch_s * 1e3,
             "sample_phases": n_launch,
         },
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
                      "frac": achieved / PEAK_VALU_TOPS, "traffic": TRAFFIC_BYTES_PER_PHASE,
-                     "ops_per_sample": ops, "kernels": "k_screen + k_shell per iteration"},
+                     "ops_per_launch": ops_launch, "ops_per_sample": [ops_common(n_int), ops_weight(n_int)],
+                     "listed_fraction": listed_per_launch / samples_per_launch,
+                     "kernels": "k_screen + k_shell per iteration"},
     }
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -213,12 +213,16 @@ int bmc_vjp(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, co
 
 /* ---- measurement and tuning ---- */
 
-/* Enables (on != 0) timing of the sample kernel with HIP events on the context stream (eager launches only;
- * graph replays are not timed). */
+/* Enables (on != 0) timing of the sample phase (screening and second pass of one iteration's launch) with HIP
+ * events on the context stream (eager launches only; graph replays are not timed). */
 int bmc_set_timing(bmc_ctx* ctx, int on);
-/* Sum of the timed sample-kernel durations (ms) and number of timed launches since the last reset;
+/* Sum of the timed sample-phase durations (ms) and number of timed phases since the last reset;
  * synchronises the stream.  reset != 0 clears the counters after reading. */
 int bmc_get_timing(bmc_ctx* ctx, int reset, double* sample_ms, int* n_launches);
+/* Number of samples the second pass evaluated (those the screening pass found able to carry a nonzero W: in
+ * the energy shell or near it) since the last reset, over all evaluations on the context, graph replays
+ * included; synchronises the stream.  reset != 0 clears the counter after reading. */
+int bmc_get_sample_stats(bmc_ctx* ctx, int reset, int64_t* n_listed);
 /* Launch shape of the persistent batched sample kernel: resident blocks per compute unit (0 = from the LDS
  * need) and the number of consecutive tasks (units of samples) a block takes per visit.  Results do not
  * depend on either: every unit's partial sums are formed in the same fixed order by whichever block runs it. */

@@ -81,6 +81,7 @@ _SIGS = {
                 C.c_void_p, C.c_int],
     "bmc_set_timing": [C.c_void_p, C.c_int],
     "bmc_get_timing": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
+    "bmc_get_sample_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64)],
     "bmc_set_launch_tuning": [C.c_void_p, C.c_int, C.c_int],
     "bmc_autotune": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_double)],
@@ -312,6 +313,12 @@ class Context:
         ms, n = C.c_double(), C.c_int()
         self._check(lib().bmc_get_timing(self.h, int(reset), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def get_sample_stats(self, reset=True):
+        """Samples the second pass evaluated (in or near the energy shell) since the last reset."""
+        n = C.c_int64()
+        self._check(lib().bmc_get_sample_stats(self.h, int(reset), C.byref(n)))
+        return n.value
 
     def set_launch_tuning(self, blocks_per_cu, chunk=4):
         self._check(lib().bmc_set_launch_tuning(self.h, blocks_per_cu, chunk))

@@ -26,10 +26,11 @@ constexpr size_t kAlign = 256;
 constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
 // FP32 integrand: bytes of in-shell lists one screening launch may fill (larger batches run in slices)
 constexpr size_t kListCapBytes = size_t(1) << 30;
-// FP32 integrand: samples per in-shell record (the in-shell pass takes the units of an item in groups this large)
-constexpr int64_t kShellGroupSamples = int64_t(1) << 18;
+// Second pass: an item's units form up to this many groups, each one task of the pass with its own record (enough
+// blocks for a per-grid-point launch, few enough records for a batched one)
+constexpr int kShellGroups = 16;
 
-int shell_units_for(int unit_size) { return (int)std::max<int64_t>(1, kShellGroupSamples / unit_size); }
+int shell_units_for(int64_t n_units) { return (int)((n_units + kShellGroups - 1) / kShellGroups); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -421,13 +422,14 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.part_off = part;
             part += (int64_t)it.n_units * 2 * D * nb;
             it.shell_off = shell;
-            it.shell_units = shell_units_for(it.unit_size);
+            it.shell_units = shell_units_for(it.n_units);
             shell += (int64_t)((it.n_units + it.shell_units - 1) / it.shell_units) * (2 + 2 * D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
             it.inv2s2 = 1.0 / (2.0 * Pr.prm.sigma_E * Pr.prm.sigma_E);
             it.shell = 12.0 * Pr.prm.sigma_E;
+            it.far = std::sqrt(2.0 * 746.0) * Pr.prm.sigma_E;
             it.dnorm = 1.0 / (Pr.prm.sigma_E * std::sqrt(2.0 * M_PI));
             it.e_cut = Pr.prm.e_cut;
             it.twopi_pow = std::pow(2.0 * M_PI, (double)(3 * (n - 1) - 4));
@@ -684,7 +686,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       units += ni * nu;
       tasks += ni * nu;
       part += ni * nu * 2 * D * Pr.prm.n_bins;
-      const int64_t G = shell_units_for(U);
+      const int64_t G = shell_units_for(nu);
       shell += ni * (size_t)((nu + G - 1) / G) * (2 + 2 * D * Pr.prm.n_bins);
       per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
@@ -776,7 +778,7 @@ int grid_for(bmc_ctx* c, int precision, int lds, int mask) {
   return c->n_cu * per_cu;
 }
 
-// The sample phase of one launch: the FP64 sample kernel, or the FP32-integrand screening and in-shell passes.
+// The sample phase of one launch: the screening pass and the second pass (FP64 or FP32 integrand).
 // With timing on (eager launches only) the phase is bracketed by events on the launch stream.
 hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
@@ -788,7 +790,7 @@ hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
     if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
   }
   if ((e = launch_sample(L, s)) != hipSuccess) return e;
-  if (L.precision == BMC_FP32I && (e = launch_shell(L, s)) != hipSuccess) return e;
+  if ((e = launch_shell(L, s)) != hipSuccess) return e;
   if (timed) {
     e = hipEventRecord(b, s);
     c->ev.push_back({a, b});
@@ -821,6 +823,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.shell_cnt = P.d_cnt;
   L.list_stride = P.list_stride;
   L.shell_rec = P.d_shell;
+  L.n_listed = &c->st()->n_listed;
   const int max_grid = grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask);
   for (int k = 0; k < P.n_iter_max; ++k) {
     L.it = o.first_iter + k;
@@ -854,7 +857,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
       }
     }
     HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_unit_s, P.d_unit_base, P.d_parts,
-                                  o.precision == BMC_FP32I ? P.d_shell : nullptr, P.d_res_I, P.d_res_V, k, c->maps(),
+                                  P.d_shell, P.d_res_I, P.d_res_V, k, c->maps(),
                                   o.freeze_maps, s));
   }
   HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, P.n_iter_max, P.d_item_Ibar,
@@ -1591,6 +1594,21 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
 int bmc_set_timing(bmc_ctx* c, int on) {
   if (!c) return BMC_EINVAL;
   c->timing = on != 0;
+  return BMC_OK;
+}
+
+int bmc_get_sample_stats(bmc_ctx* c, int reset, int64_t* n_listed) {
+  if (!c) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  unsigned long long v = 0;
+  HIPCHK(c, hipMemcpyAsync(&v, &c->st()->n_listed, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (n_listed) *n_listed = (int64_t)v;
+  if (reset) {
+    const unsigned long long zero = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->st()->n_listed, &zero, sizeof(zero), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   return BMC_OK;
 }
 

@@ -40,6 +40,7 @@ struct DevState {
   uint32_t epoch;    // epoch of the evaluation in progress
   uint32_t next_epoch;  // epoch the next evaluation consumes
   int err;           // sticky error flag (BMC_ERANGE ...)
+  unsigned long long n_listed;  // samples evaluated by the second pass since the last read-out
   double expansion_a0, expansion_t0;
   int expansion;
   int n_species;
@@ -73,6 +74,7 @@ struct ItemRec {
   double coupling2;
   double inv2s2;     // 1 / (2 sigma_E^2)
   double shell;      // FP32 screening half-width of the energy shell, 12 sigma_E
+  double far;        // FP32 screening: |dE| beyond which the Gaussian factor underflows in FP64 (e^-746)
   double dnorm;      // 1 / (sigma_E sqrt(2 pi))
   double e_cut;
   double twopi_pow;  // (2 pi)^(3(n-1)-4)

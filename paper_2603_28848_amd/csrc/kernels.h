@@ -37,11 +37,12 @@ struct SampleLaunch {
   int sh_begin, n_sh;    // in-shell tasks (one per item) of this launch
   int sh_grid;
   double* shell_rec;     // per item: S1, S2, then 2 D nb histogram doubles
+  unsigned long long* n_listed;  // running count of the samples the second pass evaluates
 };
 
-// FP64 sample kernel, or the FP32-integrand screening pass (precision 1).
+// Screening pass of a sample launch (FP32 kinematics; lists the samples whose W can be nonzero).
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
-// FP32-integrand in-shell pass over the items of the preceding screening launch.
+// Second pass over the listed samples of the preceding screening launch (FP64, or the FP32 integrand).
 hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
 // Sums the unit records of each item in unit order (then the item's in-shell record when shell_rec is not

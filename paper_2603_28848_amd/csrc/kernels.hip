@@ -56,8 +56,8 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + kWaves * DN * 4);
   L.off_red = o;
   o = align16(o + 2 * kWaves * 8);
-  L.off_q = o;  // FP32-integrand in-shell pass: prefix sums over 256 in-shell lists
-  o = align16(o + (kBlock + 1) * 4);
+  L.off_q = o;  // second pass: prefix sums over 256 lists and the four wave totals of the scan
+  o = align16(o + (kBlock + 1 + kWaves) * 4);
   L.total = o;
   return L;
 }
@@ -179,6 +179,7 @@ struct ItemConsts {
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2)
+  float far;     // |dE| of the FP64 underflow of the Gaussian factor
   float wconst;  // a^-3n |M|^2 / ((2 pi)^(3(n-1)-4) sigma_E sqrt(2 pi))
   double a, inv_a, m2[NR], eta[NR], esg[NR];
   int obsside[NR];
@@ -306,14 +307,14 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 
 // FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns the
 // sample's class:
-//   kInShell  |dE| < 12 sigma_E (+ a margin of 1e-3 of the summed energies, far above the FP32 error): W needs
-//             the FP64 kinematics;
-//   kFar      dE^2 / (2 sigma_E^2) > 760: the Gaussian factor, and so W, is 0 (in FP64 it underflows beyond 745);
+//   kInShell  |dE| < 12 sigma_E + m: W needs the FP64 kinematics;
+//   kFar      |dE| > sqrt(2 746) sigma_E + m: the FP64 |dE| exceeds the point where the Gaussian factor
+//             e^(-dE^2 / (2 sigma_E^2)) underflows to 0 in FP64, so W = 0 exactly;
 //   kNear     the rest: with FINISH, W is finished in FP32 (its Gaussian factor is below e^-72 relative, so W only
 //             matters for the map's training histogram, where ~1e-6 accuracy is ample).
-// The bin of every dimension is exact (the same as with the FP64 map).
+// m = 1e-3 of the summed energies bounds the difference of the FP32 and FP64 dE with a wide margin.  The bin of
+// every dimension is exact (the same as with the FP64 map).
 constexpr int kFar = 0, kNear = 1, kInShell = 2;
-constexpr float kFarExponent = -760.0f * 1.44269504f;  // log2 of e^-760
 
 template <int NI, bool FINISH>
 __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell, int* hj,
@@ -378,10 +379,11 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
   dE = fmaf((float)K.esg[NI], Ec, dE);
   sumE += Ec;
   prod2E *= 2.0f * Ec;
-  if (fabsf(dE) < shell + 1e-3f * sumE) return kInShell;
-  const float y = -(dE * dE) * K.ylog2;
-  if (y < kFarExponent) return kFar;
+  const float adE = fabsf(dE), margin = 1e-3f * sumE;
+  if (adE < shell + margin) return kInShell;
+  if (adE > K.far + margin) return kFar;
   if constexpr (FINISH) {
+    const float y = -(dE * dE) * K.ylog2;
     const float qc = (float)K.a * __builtin_amdgcn_sqrtf(P2);
     float fc;
     if (qc < (float)K.qc_min) {
@@ -514,6 +516,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   K.dnorm = it->dnorm;
   K.twopi_pow = it->twopi_pow;
   K.ylog2 = (float)(1.4426950408889634 * it->inv2s2);
+  K.far = (float)it->far;
   K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
   K.nb = nb;
   K.net = it->net;
@@ -587,36 +590,6 @@ __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& la
   __syncthreads();
 }
 
-// FP64: every sample of the units of tasks t0 .. t1-1 (all of one item) with FP64 kinematics and integrand.
-template <int NI>
-__device__ void sample_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
-  constexpr int D = 3 * NI;
-  const int item = L.tasks[L.task_begin + t0].item;
-  const ItemRec* __restrict__ it = &L.items[item];
-  ItemConsts<NI, double> K;
-  const Lds lay = setup_block<NI, 0>(L, it, smem, stage, K);
-  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
-  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
-  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
-  for (int t = t0; t < t1; ++t) {
-    const int unit = L.tasks[L.task_begin + t].unit;
-    if (t > t0) {
-      clear_hist(lay, smem);
-      __syncthreads();
-    }
-    const int64_t n0 = (int64_t)unit * it->unit_size;
-    const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
-    double S1 = 0.0, S2 = 0.0;
-    for (int64_t n = n0 + tid; n < n1; n += kBlock) {
-      int hj[D];
-      const double W = eval_sample<NI, double>(K, (uint64_t)n, hj);
-      accumulate<D>(W, hj, S1, S2, my_h, my_c);
-    }
-    const int64_t gu = L.unit_base[item] + unit;
-    finish_block(S1, S2, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
-  }
-}
-
 // FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
 // Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Far samples (W = 0) only add
 // their counts; the offsets n - n0 of in-shell samples are appended, in sample order, to the front of the wave's
@@ -668,60 +641,84 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   }
 }
 
-// FP32 integrand, second pass over a range of units of one item: first the in-shell lists, then the near lists of
-// the units (unit order, waves in order within a unit), each read as one sequence whose entry e is evaluated by
-// thread e mod 256 -- in-shell samples with FP64 kinematics, near samples with the FP32 finish; the block's sums go
-// to the range's record.  Units are taken 64 at a time (256 lists).
-template <int NI>
-__device__ void shell_task(const SampleLaunch& L, const ShellTask sht, unsigned char* smem) {
+// Second pass over the in-shell tasks k0 .. k1-1 (ranges of units of one item).  Per task: first the in-shell
+// lists, then the near lists of its units (unit order, waves in order within a unit), each read as one sequence
+// whose entry e is evaluated by thread e mod 256.  FP64 (PREC 0): every listed sample with FP64 kinematics and
+// integrand.  FP32 integrand (PREC 1): in-shell samples with FP64 kinematics, near samples with the FP32 finish.
+// The block's sums go to the task's record.  Units are taken 64 at a time (256 lists).
+template <int NI, int PREC>
+__device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
   constexpr int kLists = kBlock;  // lists per chunk: 64 units x 4 waves
-  const ItemRec* __restrict__ it = &L.items[sht.item];
-  ItemConsts<NI, float> K;
-  const Lds lay = setup_block<NI, 1>(L, it, smem, true, K);
+  using FT = typename std::conditional<PREC == 0, double, float>::type;
+  const ItemRec* __restrict__ it = &L.items[L.sh_tasks[L.sh_begin + k0].item];
+  ItemConsts<NI, FT> K;
+  const Lds lay = setup_block<NI, PREC>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
   int* pre = reinterpret_cast<int*>(smem + lay.off_q);  // kLists + 1 prefix sums
-  const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // task position of unit 0
+  int* wtot = pre + kLists + 1;                          // per-wave totals of the scan
+  const int lane = tid & 63;
   const int64_t wlen = L.list_stride / kWaves;
   const float shell = (float)it->shell;
-  double S1 = 0.0, S2 = 0.0;
-  for (int kind = 0; kind < 2; ++kind) {  // 0: in-shell lists, 1: near lists
-    for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
-      const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
-      if (tid < nl) {
-        const int u = u0 + tid / kWaves, w = tid % kWaves;
-        pre[tid + 1] = (int)L.shell_cnt[(int64_t)(pos0 + u) * 2 * kWaves + kind * kWaves + w];
-      }
-      if (tid == 0) pre[0] = 0;
+  for (int k = k0; k < k1; ++k) {
+    const ShellTask sht = L.sh_tasks[L.sh_begin + k];
+    if (k > k0) {
+      clear_hist(lay, smem);
       __syncthreads();
-      if (tid == 0)
-        for (int l = 1; l <= nl; ++l) pre[l] += pre[l - 1];
-      __syncthreads();
-      const int M = pre[nl];
-      for (int e = tid; e < M; e += kBlock) {
-        int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (pre[mid] <= e) lo = mid;
-          else hi = mid;
-        }
-        const int u = u0 + lo / kWaves, w = lo % kWaves, k = e - pre[lo];
-        const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
-        const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
-        const uint64_t n = (uint64_t)((int64_t)u * it->unit_size + off);
-        int hj[D];
-        double W = 0.0;
-        if (kind == 0) W = eval_sample<NI, float>(K, n, hj);
-        else screen_sample<NI, true>(K, n, shell, hj, &W);
-        accumulate<D>(W, hj, S1, S2, my_h, my_c);
-      }
-      __syncthreads();  // pre is rewritten by the next chunk
     }
+    const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // task position of unit 0
+    double S1 = 0.0, S2 = 0.0;
+    for (int kind = 0; kind < 2; ++kind) {  // 0: in-shell lists, 1: near lists
+      for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
+        const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
+        // block-wide inclusive scan of the list lengths: within each wave, then the wave totals in order
+        int v = 0;
+        if (tid < nl) {
+          const int u = u0 + tid / kWaves, w = tid % kWaves;
+          v = (int)L.shell_cnt[(int64_t)(pos0 + u) * 2 * kWaves + kind * kWaves + w];
+        }
+  #pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+          const int t = __shfl_up(v, d, 64);
+          if (lane >= d) v += t;
+        }
+        if (lane == 63) wtot[wave] = v;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) v += wtot[w];
+        pre[tid + 1] = v;
+        if (tid == 0) pre[0] = 0;
+        __syncthreads();
+        const int M = pre[nl];
+        if (tid == 0 && L.n_listed) atomicAdd(L.n_listed, (unsigned long long)M);
+        for (int e = tid; e < M; e += kBlock) {
+          int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= e) lo = mid;
+            else hi = mid;
+          }
+          const int u = u0 + lo / kWaves, w = lo % kWaves, k = e - pre[lo];
+          const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
+          const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
+          const uint64_t n = (uint64_t)((int64_t)u * it->unit_size + off);
+          int hj[D];
+          double W = 0.0;
+          if constexpr (PREC == 0) {
+            W = eval_sample<NI, double>(K, n, hj);
+          } else {
+            if (kind == 0) W = eval_sample<NI, float>(K, n, hj);
+            else screen_sample<NI, true>(K, n, shell, hj, &W);
+          }
+          accumulate<D>(W, hj, S1, S2, my_h, my_c);
+        }
+        __syncthreads();  // pre is rewritten by the next chunk
+      }
+    }
+    double* rec = L.shell_rec + sht.rec;
+    finish_block(S1, S2, lay, DN, smem, rec, rec + 2);
   }
-  double* rec = L.shell_rec + sht.rec;
-  finish_block(S1, S2, lay, DN, smem, rec, rec + 2);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -1085,33 +1082,11 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
   }
 }
 
-// Persistent sample kernels: block b takes the chunks b, b + G, b + 2G, ... of `chunk` consecutive tasks (the
-// units of one item are consecutive, so a chunk mostly re-uses the staged map and tables).  Which block runs a
-// task does not change its result.  Registers are capped per lane so that two (FP64) or three (FP32 screening)
-// waves share a SIMD: above 256 the compiler moves values into accumulation registers and occupancy halves.
-template <int MASK>
-__global__ __launch_bounds__(kBlock, 2) void k_sample(SampleLaunch L) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  const int chunk = L.chunk > 0 ? L.chunk : 1;
-  int prev_item = -1;
-  for (int base = blockIdx.x * chunk; base < L.n_tasks; base += gridDim.x * chunk) {
-    const int end = min(base + chunk, L.n_tasks);
-    for (int t = base; t < end;) {
-      const int item = L.tasks[L.task_begin + t].item;
-      int t1 = t + 1;
-      while (t1 < end && L.tasks[L.task_begin + t1].item == item) ++t1;
-      const int ni = L.items[item].nint;
-      const bool stage = item != prev_item;
-      prev_item = item;
-      if ((MASK & 1) && ni == 1) sample_run<1>(L, t, t1, smem, stage);
-      if ((MASK & 2) && ni == 2) sample_run<2>(L, t, t1, smem, stage);
-      if ((MASK & 4) && ni == 3) sample_run<3>(L, t, t1, smem, stage);
-      if ((MASK & 8) && ni == 4) sample_run<4>(L, t, t1, smem, stage);
-      t = t1;
-    }
-  }
-}
-
+// Persistent screening kernel (both precisions): block b takes the chunks b, b + G, b + 2G, ... of `chunk`
+// consecutive tasks (the units of one item are consecutive, so a chunk mostly re-uses the staged map and tables).
+// Which block runs a task does not change its result.  Registers are capped per lane so that at least three
+// (screening) or two (second pass) waves share a SIMD: above 256 the compiler moves values into accumulation
+// registers and occupancy halves.
 template <int MASK>
 __global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -1135,17 +1110,27 @@ __global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
   }
 }
 
-// In-shell pass: block b takes the items' in-shell work b, b + G, ...
-template <int MASK>
+// Second pass: block b takes the consecutive in-shell tasks [b c, (b + 1) c), c = ceil(n / G) (the tasks of one
+// item are consecutive, so the block re-uses the staged map and tables).  Which block runs a task does not change
+// its result.
+template <int MASK, int PREC>
 __global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int k = blockIdx.x; k < L.n_sh; k += gridDim.x) {
-    const ShellTask sht = L.sh_tasks[L.sh_begin + k];
-    const int ni = L.items[sht.item].nint;
-    if ((MASK & 1) && ni == 1) shell_task<1>(L, sht, smem);
-    if ((MASK & 2) && ni == 2) shell_task<2>(L, sht, smem);
-    if ((MASK & 4) && ni == 3) shell_task<3>(L, sht, smem);
-    if ((MASK & 8) && ni == 4) shell_task<4>(L, sht, smem);
+  const int c = (L.n_sh + gridDim.x - 1) / gridDim.x;
+  const int end = min(L.n_sh, (int)(blockIdx.x + 1) * c);
+  int prev_item = -1;
+  for (int k = blockIdx.x * c; k < end;) {
+    const int item = L.sh_tasks[L.sh_begin + k].item;
+    int k1 = k + 1;
+    while (k1 < end && L.sh_tasks[L.sh_begin + k1].item == item) ++k1;
+    const int ni = L.items[item].nint;
+    const bool stage = item != prev_item;
+    prev_item = item;
+    if ((MASK & 1) && ni == 1) shell_run<1, PREC>(L, k, k1, smem, stage);
+    if ((MASK & 2) && ni == 2) shell_run<2, PREC>(L, k, k1, smem, stage);
+    if ((MASK & 4) && ni == 3) shell_run<3, PREC>(L, k, k1, smem, stage);
+    if ((MASK & 8) && ni == 4) shell_run<4, PREC>(L, k, k1, smem, stage);
+    k = k1;
   }
 }
 
@@ -1478,17 +1463,17 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
 
 template <int MASK>
 hipError_t launch_sample_t(const SampleLaunch& L, hipStream_t s) {
-  if (L.precision == 0) {
-    hipLaunchKernelGGL((k_sample<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
-  } else {
-    hipLaunchKernelGGL((k_screen<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
-  }
+  hipLaunchKernelGGL((k_screen<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
   return hipGetLastError();
 }
 
 template <int MASK>
 hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_shell<MASK>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
+  if (L.precision == 0) {
+    hipLaunchKernelGGL((k_shell<MASK, 0>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
+  } else {
+    hipLaunchKernelGGL((k_shell<MASK, 1>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
+  }
   return hipGetLastError();
 }
 
