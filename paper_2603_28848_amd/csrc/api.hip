@@ -84,7 +84,7 @@ struct Plan {
   int n_out = 0;
   int nint_mask = 0;
   int64_t n_units = 0;
-  int64_t n_parts = 0;   // doubles
+  int64_t n_parts = 0;   // 32-bit bin counts of all units
   int lds64 = 0, lds32 = 0;
   std::vector<int> new_maps;  // item indices whose maps need initialising
   // device pointers (inside the scratch region)
@@ -97,8 +97,7 @@ struct Plan {
   uint32_t* d_cnt = nullptr;
   double* d_shell = nullptr;
   int64_t* d_unit_base = nullptr;
-  double* d_unit_s = nullptr;
-  double* d_parts = nullptr;
+  uint32_t* d_counts = nullptr;
   double* d_res_I = nullptr;
   double* d_res_V = nullptr;
   double* d_item_Ibar = nullptr;
@@ -420,7 +419,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.unit_size = unit_size_for(N);
             it.n_units = (int)((N + it.unit_size - 1) / it.unit_size);
             it.part_off = part;
-            part += (int64_t)it.n_units * 2 * D * nb;
+            part += (int64_t)it.n_units * D * nb;
             it.shell_off = shell;
             it.shell_units = shell_units_for(it.n_units);
             shell += (int64_t)((it.n_units + it.shell_units - 1) / it.shell_units) * (2 + 2 * D * nb);
@@ -624,8 +623,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
          o_tp = take(sizeof(Task) * Q.tasks_plain.size()), o_shb = take(sizeof(ShellTask) * Q.sh_batched.size()),
          o_shp = take(sizeof(ShellTask) * Q.sh_plain.size()), o_list = take(2 * (size_t)(Q.list_pos * Q.list_stride)),
          o_cnt = take(8 * kWaves * (size_t)Q.list_pos), o_shell = take(8 * (size_t)Q.n_shell),
-         o_ub = take(8 * nI), o_us = take(16 * (size_t)units),
-         o_parts = take(8 * (size_t)part), o_rI = take(8 * kMaxIter * nI), o_rV = take(8 * kMaxIter * nI),
+         o_ub = take(8 * nI), o_parts = take(4 * (size_t)part), o_rI = take(8 * kMaxIter * nI), o_rV = take(8 * kMaxIter * nI),
          o_ib = take(8 * nI), o_is = take(8 * nI), o_sb = take(4 * (Q.slot_begin.size())),
          o_si = take(4 * std::max<size_t>(1, Q.slot_items.size())), o_sC = take(8 * Q.n_slots),
          o_sS = take(8 * Q.n_slots), o_g = take(sizeof(GatherEntry) * Q.gather.size()),
@@ -643,8 +641,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     Q.d_cnt = reinterpret_cast<uint32_t*>(base + o_cnt);
     Q.d_shell = reinterpret_cast<double*>(base + o_shell);
     Q.d_unit_base = reinterpret_cast<int64_t*>(base + o_ub);
-    Q.d_unit_s = reinterpret_cast<double*>(base + o_us);
-    Q.d_parts = reinterpret_cast<double*>(base + o_parts);
+    Q.d_counts = reinterpret_cast<uint32_t*>(base + o_parts);
     Q.d_res_I = reinterpret_cast<double*>(base + o_rI);
     Q.d_res_V = reinterpret_cast<double*>(base + o_rV);
     Q.d_item_Ibar = reinterpret_cast<double*>(base + o_ib);
@@ -685,7 +682,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       items += ni;
       units += ni * nu;
       tasks += ni * nu;
-      part += ni * nu * 2 * D * Pr.prm.n_bins;
+      part += ni * nu * D * Pr.prm.n_bins;
       const int64_t G = shell_units_for(nu);
       shell += ni * (size_t)((nu + G - 1) / G) * (2 + 2 * D * Pr.prm.n_bins);
       per_node += (size_t)sides * terms * nu;
@@ -722,7 +719,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
   s += align_up(8 * vjp_part) + align_up((sizeof(ItemRec) + 8 * (4 * gmax + 12) + 24) * items) +
        align_up(8 * (size_t)c->n_f) + 4 * kAlign + 16 * c->pr.size();
   s += align_up(sizeof(ItemRec) * items) + 2 * align_up(sizeof(Task) * tasks) + align_up(8 * items) +
-       align_up(16 * units) + align_up(8 * part) + 2 * align_up(8 * kMaxIter * items) + 2 * align_up(8 * items) +
+       align_up(4 * part) + 2 * align_up(8 * kMaxIter * items) + 2 * align_up(8 * items) +
        align_up(4 * (slots + 1)) + align_up(4 * items) + 2 * align_up(8 * slots) +
        align_up(sizeof(GatherEntry) * outs) + align_up(sizeof(GatherProc) * outs * std::max<size_t>(1, c->pr.size())) +
        2 * align_up(8 * outs) + align_up(4 * items) + 64 * kAlign;
@@ -811,8 +808,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.qnode = c->qnode();
   L.st = c->st();
   L.maps = c->maps();
-  L.unit_s = P.d_unit_s;
-  L.parts = P.d_parts;
+  L.counts = P.d_counts;
   L.unit_base = P.d_unit_base;
   L.seed_lo = (uint32_t)o.seed;
   L.seed_hi = (uint32_t)(o.seed >> 32);
@@ -856,9 +852,8 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         HIPCHK(c, sample_phase(c, L, s));
       }
     }
-    HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_unit_s, P.d_unit_base, P.d_parts,
-                                  P.d_shell, P.d_res_I, P.d_res_V, k, c->maps(),
-                                  o.freeze_maps, s));
+    HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_counts, P.d_shell, P.d_res_I, P.d_res_V, k,
+                                  c->maps(), o.freeze_maps, s));
   }
   HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, P.n_iter_max, P.d_item_Ibar,
                            P.d_item_sig, P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));

@@ -65,7 +65,8 @@ struct ItemRec {
   int unit_size;     // samples per unit
   int64_t N;         // samples per iteration
   int64_t map_off;   // doubles: Vegas map, kMaxD rows of (nb + 1) edges
-  int64_t part_off;  // doubles: first unit record (2 D nb doubles each) of this item
+  int64_t part_off;  // collision: first unit's bin counts (D nb 32-bit counts per unit); adjoint: doubles of the
+                     // first unit record
   int64_t shell_off; // doubles: the item's in-shell records (S1, S2, 2 D nb each), FP32 integrand
   int shell_units;   // units per in-shell record
   int64_t res_off;   // index of this item's per-iteration results

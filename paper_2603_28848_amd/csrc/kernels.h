@@ -18,9 +18,9 @@ struct SampleLaunch {
   const double* qnode;   // comoving grid nodes, same layout as f
   const DevState* st;
   const double* maps;
-  double* unit_s;        // 2 doubles per unit: S1, S2
-  double* parts;         // unit records (histograms)
-  const int64_t* unit_base;  // per item: index of its first unit in unit_s
+  uint32_t* counts;      // per unit: the bin counts of the screening pass (D nb)
+  double* parts;         // adjoint: unit records
+  const int64_t* unit_base;  // per item: index of its first unit
   int it;                // Philox iteration index
   uint32_t seed_lo, seed_hi;
   int nint_mask;         // bit (nint-1) set for every integrated-particle count present
@@ -45,11 +45,12 @@ hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
 // Second pass over the listed samples of the preceding screening launch (FP64, or the FP32 integrand).
 hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
-// Sums the unit records of each item in unit order (then the item's in-shell record when shell_rec is not
-// null), stores I_it, V_it for iteration slot `slot`, and (unless frozen) adapts the item's map.
-hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,
-                               const int64_t* unit_base, const double* parts, const double* shell_rec,
-                               double* res_I, double* res_V, int slot, double* maps, int freeze, hipStream_t s);
+// Per item: S1, S2 and the W^2 histogram from its second-pass records in group order, the bin counts from its
+// units' counts and the second-pass records; stores I_it, V_it for iteration slot `slot` and (unless frozen)
+// adapts the item's map.
+hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
+                               const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
+                               int freeze, hipStream_t s);
 
 // Initialises the maps of items (uniform edges over each dimension's range).
 hipError_t launch_init_maps(const ItemRec* items, const int* which, int n, const SpecDev* spec, double* maps,

@@ -421,6 +421,13 @@ __device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) 
   for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// Clears the per-wave count histograms only.
+__device__ __forceinline__ void clear_counts(const Lds& lay, unsigned char* smem) {
+  uint4* p = reinterpret_cast<uint4*>(smem + lay.off_c);
+  const int n16 = (lay.off_red - lay.off_c) / 16;
+  for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 pairs), the sin/cos table and
 // the f tables into LDS unless the block's previous task staged the same item, clears the per-wave training
 // histograms, and fills the per-item constants at the current time.  Ends with a block barrier.
@@ -553,6 +560,18 @@ __device__ __forceinline__ void count_only(const int* hj, uint32_t* my_c) {
   for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
 }
 
+// End of a screening unit: the wave count histograms summed into the unit's counts.
+__device__ __forceinline__ void finish_counts(const Lds& lay, int DN, unsigned char* smem, uint32_t* out) {
+  const uint32_t* sm_c = reinterpret_cast<const uint32_t*>(smem + lay.off_c);
+  __syncthreads();
+  for (int i = threadIdx.x; i < DN; i += kBlock) {
+    uint32_t c = 0;
+    for (int w = 0; w < kWaves; ++w) c += sm_c[w * DN + i];
+    out[i] = c;
+  }
+  __syncthreads();
+}
+
 // Fixed-order end of a block's pass: butterfly wave sums of S1, S2, the four waves in order into s_out[0..1],
 // and the wave histograms summed in wave order into rec[0 .. 2 DN) (sums of W^2, then counts).
 __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& lay, int DN, unsigned char* smem,
@@ -610,7 +629,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   for (int t = t0; t < t1; ++t) {
     const int unit = L.tasks[L.task_begin + t].unit;
     if (t > t0) {
-      clear_hist(lay, smem);
+      clear_counts(lay, smem);
       __syncthreads();
     }
     const int64_t n0 = (int64_t)unit * it->unit_size;
@@ -636,8 +655,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
       L.shell_cnt[(int64_t)t * 2 * kWaves + wave] = cin;
       L.shell_cnt[(int64_t)t * 2 * kWaves + kWaves + wave] = cnear;
     }
-    const int64_t gu = L.unit_base[item] + unit;
-    finish_block(0.0, 0.0, lay, DN, smem, L.unit_s + 2 * gu, L.parts + it->part_off + (int64_t)unit * 2 * DN);
+    finish_counts(lay, DN, smem, L.counts + it->part_off + (int64_t)unit * DN);
   }
 }
 
@@ -1180,8 +1198,7 @@ __device__ void adapt_dimension(double* edges, int nb, const double* h, const do
   }
 }
 
-__global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const double* unit_s,
-                                                      const int64_t* unit_base, const double* parts,
+__global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
                                                       const double* shell_rec, double* res_I, double* res_V,
                                                       int slot, double* maps, int freeze) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
@@ -1190,20 +1207,13 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   const ItemRec& it = items[item];
   if (slot >= it.n_iter) return;  // the item has finished its iterations
   const int D = it.D, nb = it.nb, DN = D * nb;
-  const int64_t u0 = unit_base[item];
+  const int64_t stride = 2 + 2 * (int64_t)DN;  // second-pass record
   if (threadIdx.x == 0) {
     double S1 = 0.0, S2 = 0.0;
-    for (int u = 0; u < it.n_units; ++u) {
-      S1 += unit_s[2 * (u0 + u)];
-      S2 += unit_s[2 * (u0 + u) + 1];
-    }
-    if (shell_rec) {
-      const int64_t stride = 2 + 2 * (int64_t)it.D * it.nb;
-      for (int u = 0; u < it.n_units; u += it.shell_units) {
-        const int64_t r = it.shell_off + (u / it.shell_units) * stride;
-        S1 += shell_rec[r];
-        S2 += shell_rec[r + 1];
-      }
+    for (int u = 0; u < it.n_units; u += it.shell_units) {
+      const int64_t r = it.shell_off + (u / it.shell_units) * stride;
+      S1 += shell_rec[r];
+      S2 += shell_rec[r + 1];
     }
     const double Nd = (double)it.N;
     const double I = S1 / Nd;
@@ -1212,19 +1222,15 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     res_V[it.res_off * kMaxIter + slot] = V;
   }
   if (freeze) return;
-  const double* rec = parts + it.part_off;
+  const uint32_t* cnt = counts + it.part_off;
   for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    double h = 0.0, c = 0.0;
-    for (int u = 0; u < it.n_units; ++u) {
-      h += rec[(int64_t)u * 2 * DN + i];
-      c += rec[(int64_t)u * 2 * DN + DN + i];
-    }
-    if (shell_rec) {
-      for (int u = 0; u < it.n_units; u += it.shell_units) {
-        const int64_t r = it.shell_off + (u / it.shell_units) * (2 + 2 * (int64_t)DN);
-        h += shell_rec[r + 2 + i];
-        c += shell_rec[r + 2 + DN + i];
-      }
+    uint64_t cu = 0;  // the screening pass's counts (exact integers)
+    for (int u = 0; u < it.n_units; ++u) cu += cnt[(int64_t)u * DN + i];
+    double h = 0.0, c = (double)cu;
+    for (int u = 0; u < it.n_units; u += it.shell_units) {
+      const int64_t r = it.shell_off + (u / it.shell_units) * stride;
+      h += shell_rec[r + 2 + i];
+      c += shell_rec[r + 2 + DN + i];
     }
     sh[i] = h;
     sc[i] = c;
@@ -1545,12 +1551,12 @@ hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* co
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const double* unit_s,
-                               const int64_t* unit_base, const double* parts, const double* shell_rec,
-                               double* res_I, double* res_V, int slot, double* maps, int freeze, hipStream_t s) {
+hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
+                               const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
+                               int freeze, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(256), 0, s, items, item_begin, unit_s, unit_base, parts,
-                     shell_rec, res_I, res_V, slot, maps, freeze);
+  hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(256), 0, s, items, item_begin, counts, shell_rec, res_I,
+                     res_V, slot, maps, freeze);
   return hipGetLastError();
 }
 
