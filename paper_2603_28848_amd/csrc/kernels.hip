@@ -1156,43 +1156,28 @@ __global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
 // Vegas map adaptation of one dimension (Lepage): bin averages d = h/c, (7,1)/(1,6,1)/(1,7)/8 smoothing,
 // normalisation, damping ((1-d)/ln(1/d))^alpha, new edges at equal cumulative damped weight placed linearly
 // inside the old bins; the outer edges stay.
-__device__ void adapt_dimension(double* edges, int nb, const double* h, const double* c, double alpha, double* d,
-                                double* wgt, double* old) {
-  for (int j = 0; j < nb; ++j) d[j] = c[j] > 0.0 ? h[j] / c[j] : 0.0;
-  double sum = 0.0;
-  // smoothed values go into wgt
-  wgt[0] = (7.0 * d[0] + d[1]) / 8.0;
-  wgt[nb - 1] = (d[nb - 2] + 7.0 * d[nb - 1]) / 8.0;
-  for (int j = 1; j < nb - 1; ++j) wgt[j] = (d[j - 1] + 6.0 * d[j] + d[j + 1]) / 8.0;
-  for (int j = 0; j < nb; ++j) sum += wgt[j];
-  if (!(sum > 0.0)) return;
-  double wsum = 0.0;
-  for (int j = 0; j < nb; ++j) {
-    double dh = wgt[j] / sum;
-    double v;
-    if (dh <= 0.0) {
-      v = 0.0;
-    } else if (dh >= 1.0) {
-      v = 1.0;
-    } else {
-      double base = (1.0 - dh) / log(1.0 / dh);
-      v = alpha == 0.5 ? sqrt(base) : pow(base, alpha);
-    }
-    wgt[j] = v;
-    wsum += v;
-  }
-  if (!(wsum > 0.0)) return;
+// Damped weight of a bin whose smoothed, normalised average is dh.
+__device__ __forceinline__ double damped(double dh, double alpha) {
+  if (dh <= 0.0) return 0.0;
+  if (dh >= 1.0) return 1.0;
+  const double base = (1.0 - dh) / log(1.0 / dh);
+  return alpha == 0.5 ? sqrt(base) : pow(base, alpha);
+}
+
+// New edges of one dimension from its damped bin weights v: edge k at cumulative weight k wsum / nb, linear inside
+// the old bins; the outer edges stay.
+__device__ void rebin_dimension(double* edges, int nb, const double* v, double wsum, double* old) {
   for (int j = 0; j <= nb; ++j) old[j] = edges[j];
   const double per = wsum / (double)nb;
   int j = 0;
   double acc = 0.0;
   for (int k = 1; k < nb; ++k) {
     const double target = per * (double)k;
-    while (j < nb - 1 && acc + wgt[j] < target) {
-      acc += wgt[j];
+    while (j < nb - 1 && acc + v[j] < target) {
+      acc += v[j];
       ++j;
     }
-    double frac = wgt[j] > 0.0 ? (target - acc) / wgt[j] : 0.0;
+    double frac = v[j] > 0.0 ? (target - acc) / v[j] : 0.0;
     frac = frac > 1.0 ? 1.0 : (frac < 0.0 ? 0.0 : frac);
     edges[k] = old[j] + frac * (old[j + 1] - old[j]);
   }
@@ -1202,7 +1187,7 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
                                                       const double* shell_rec, double* res_I, double* res_V,
                                                       int slot, double* maps, int freeze) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
-  __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1];
+  __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
   const int item = item_begin + blockIdx.x;
   const ItemRec& it = items[item];
   if (slot >= it.n_iter) return;  // the item has finished its iterations
@@ -1236,10 +1221,39 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     sc[i] = c;
   }
   __syncthreads();
+  // Vegas adaptation, all dimensions at once: per-bin steps over the block, sums and rebinning per dimension in
+  // bin order.  Averages d = h / c:
+  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
+    const int d = i / nb, j = i - d * nb;
+    s_d[d][j] = sc[i] > 0.0 ? sh[i] / sc[i] : 0.0;
+  }
+  __syncthreads();
+  // (7,1)/(1,6,1)/(1,7)/8 smoothing
+  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
+    const int d = i / nb, j = i - d * nb;
+    const double* a = s_d[d];
+    s_w[d][j] = j == 0 ? (7.0 * a[0] + a[1]) / 8.0
+                       : (j == nb - 1 ? (a[nb - 2] + 7.0 * a[nb - 1]) / 8.0 : (a[j - 1] + 6.0 * a[j] + a[j + 1]) / 8.0);
+  }
+  __syncthreads();
   if (threadIdx.x < D) {
+    double sum = 0.0;
+    for (int j = 0; j < nb; ++j) sum += s_w[threadIdx.x][j];
+    s_sum[threadIdx.x] = sum;
+  }
+  __syncthreads();
+  // normalisation and damping
+  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
+    const int d = i / nb, j = i - d * nb;
+    const double sum = s_sum[d];
+    if (sum > 0.0) s_w[d][j] = damped(s_w[d][j] / sum, it.alpha);
+  }
+  __syncthreads();
+  if (threadIdx.x < D && s_sum[threadIdx.x] > 0.0) {  // a dimension without weight keeps its edges
     const int d = threadIdx.x;
-    adapt_dimension(maps + it.map_off + d * (nb + 1), nb, sh + d * nb, sc + d * nb, it.alpha, s_d[d], s_w[d],
-                    s_old[d]);
+    double wsum = 0.0;
+    for (int j = 0; j < nb; ++j) wsum += s_w[d][j];
+    if (wsum > 0.0) rebin_dimension(maps + it.map_off + d * (nb + 1), nb, s_w[d], wsum, s_old[d]);
   }
 }
 
