@@ -24,9 +24,9 @@ if ROOT not in sys.path:
 
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane per cycle on 256 CUs
 # HBM bytes per sample phase (screening + in-shell kernels) of this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0); None until the current kernels
-# are measured.
-TRAFFIC_BYTES_PER_PHASE = None
+# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernels;
+# None once they change.
+TRAFFIC_BYTES_PER_PHASE = 84.7e6 + 99.6e6
 
 
 def ops_common(n_int: int) -> int:
@@ -67,6 +67,104 @@ def cpu_baseline(w, threads):
                       "each = %.3g samples in %.1f s" % (len(keep), p.n_samples, p.n_iter, samples, dt)}
 
 
+def config_line(n, args):
+    """One JSON line for one of the other workloads (not the headline): 1 = 2->2 MB, 3 = two species, three
+    processes under expansion with Heun steps replayed from a HIP graph, 4 = adjoint of the 2<->3 collision
+    integral, 5 = 2->4 FD with a time-dependent mass."""
+    import numpy as np
+    import torch
+    from paper_2603_28848_amd import boltzmc as bm
+    from paper_2603_28848_amd import workloads as wl
+
+    def timed(fn, reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(reps):
+            fn(k)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def samples(ctx, w, opts):
+        tot = 0
+        for p, pr in enumerate(w.processes):
+            ni, _ = ctx.plan_size(p, -1, opts)
+            tot += ni * (opts.n_samples or pr.n_samples) * (opts.n_iter or pr.n_iter)
+        return tot
+
+    def eval_rate(w, precision, launch, reps, freeze=0):
+        ctx = bm.from_workload(w)
+        o = bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch, freeze_maps=freeze)
+        if launch == bm.LAUNCH_BATCHED:
+            ctx.autotune(-1, -1, o)
+        ctx.collision(-1, -1, o)
+
+        def run(k):
+            o.epoch = 1000 + k
+            ctx.collision(-1, -1, o)
+        return samples(ctx, w, o) / timed(run, reps)
+
+    def frozen_sigma(w, precision, launch):
+        ctx = bm.from_workload(w)
+        return ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, precision=precision, launch=launch,
+                                                      freeze_maps=1))[1]
+
+    line = {"n_gpus": 1, "data": "synthetic", "higher_is_better": True}
+    if n in (1, 5):
+        w = wl.w22_mb() if n == 1 else wl.w24_fd()
+        reps = max(1, args.steps)
+        r32 = eval_rate(w, bm.FP32I, bm.LAUNCH_BATCHED, reps)
+        r64 = eval_rate(w, bm.FP64, bm.LAUNCH_BATCHED, reps)
+        p64 = eval_rate(w, bm.FP64, bm.LAUNCH_PLAIN, max(1, args.plain_steps))
+        s32, s64 = frozen_sigma(w, bm.FP32I, bm.LAUNCH_BATCHED), frozen_sigma(w, bm.FP64, bm.LAUNCH_PLAIN)
+        ok = (s32 > 0) & (s64 > 0)
+        line.update({"metric": "collision-integrand samples/s (batched FP32-integrand)", "value": r32,
+                     "unit": "samples/s", "config": {"workload": w.name, "batched_fp64_samples_per_s": r64,
+                                                     "plain_fp64_samples_per_s": p64,
+                                                     "speedup_vs_plain_fp64": r32 / p64,
+                                                     "sigma_ratio_fp32i_over_plain_fp64": float(np.median(
+                                                         s32[ok] / s64[ok])),
+                                                     "sigma_ratio_max_dev": float(np.max(np.abs(
+                                                         s32[ok] / s64[ok] - 1.0)))}})
+    elif n == 3:
+        w = wl.w_multi()
+        side = torch.cuda.Stream()
+        ctx = bm.from_workload(w, stream=side)
+        o = bm.default_opts(seed=0, epoch=0, precision=bm.FP32I)
+        ctx.autotune(-1, -1, o)
+        per_step = 2 * samples(ctx, w, o)
+        n_cap = 10
+        ctx.graph_capture_steps(n_cap, 1, -1.0, 0.3, 1.0, o)
+        ctx.graph_replay()  # first replay: warm-up
+        reps = max(1, args.steps)
+        dt = timed(lambda k: ctx.graph_replay(), reps)
+        t, last_dt = ctx.graph_status()
+        line.update({"metric": "Heun-step samples/s (HIP-graph replay, FP32 integrand)",
+                     "value": per_step * n_cap / dt, "unit": "samples/s",
+                     "config": {"workload": w.name, "samples_per_heun_step": per_step, "steps_per_replay": n_cap,
+                                "replays_timed": reps, "ms_per_heun_step": dt / n_cap * 1e3, "t_end": t,
+                                "last_dt": last_dt}})
+    elif n == 4:
+        w = wl.w23_adjoint()
+        ctx = bm.from_workload(w)
+        o = bm.default_opts(seed=0, epoch=0, precision=bm.FP64, freeze_maps=1, n_iter=1, eval_stride=1)
+        ni, no = ctx.plan_size(-1, -1, o)
+        per_eval = ni * w.processes[0].n_samples
+        ctx.collision(-1, -1, o)
+        fwd = timed(lambda k: ctx.collision(-1, -1, o), max(1, args.steps))
+        v = np.ones(no)
+        ctx.vjp(v, -1, -1, o)
+        bwd = timed(lambda k: ctx.vjp(v, -1, -1, o), max(1, args.steps))
+        line.update({"metric": "adjoint (VJP) samples/s, frozen-map FP64 collision integral",
+                     "value": per_eval / bwd, "unit": "samples/s",
+                     "config": {"workload": w.name, "items": ni, "samples_per_evaluation": per_eval,
+                                "forward_samples_per_s": per_eval / fwd, "vjp_over_forward_time": bwd / fwd}})
+    else:
+        raise SystemExit("--config takes 1, 3, 4 or 5 (2 is the default headline line)")
+    line["steps"] = args.steps
+    print(json.dumps(line))
+    sys.stdout.flush()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -75,6 +173,8 @@ def main():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--config", type=int, default=2,
+                    help="2 (default): the headline 2<->3 line; 1, 3, 4, 5: the other workloads, one line each")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -83,6 +183,10 @@ def main():
               "all-gather per evaluation, which this build does not implement; run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.config != 2:
+        config_line(args.config, args)
+        return
 
     import numpy as np
     import torch
