@@ -1574,8 +1574,25 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   L.precision = BMC_FP64;
   L.lds_bytes = lds;
   L.chunk = 1;
-  L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
-  HIPCHK(c, launch_vjp(L, s));
+  L.shell_list = P.d_list;
+  L.shell_cnt = P.d_cnt;
+  L.list_stride = P.list_stride;
+  // screening launches of the collision plan list the samples whose W can be nonzero; the adjoint pass takes only
+  // those (slice by slice, as the lists of one launch are bounded)
+  SampleLaunch S = L;
+  S.items = P.d_items;
+  S.counts = P.d_counts;
+  S.lds_bytes = P.lds32;
+  S.chunk = c->chunk;
+  S.n_listed = nullptr;
+  for (const Plan::Slice& sl : P.slices) {
+    S.task_begin = L.task_begin = sl.tb;
+    S.n_tasks = L.n_tasks = sl.te - sl.tb;
+    S.grid = std::min((S.n_tasks + S.chunk - 1) / S.chunk, grid_for(c, BMC_FP32I, P.lds32, P.nint_mask));
+    L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
+    HIPCHK(c, launch_sample(S, s));
+    HIPCHK(c, launch_vjp(L, s));
+  }
   HIPCHK(c, launch_vjp_finish(d_items, (int)nI, d_coef, d_parts, d_len, d_nmax, d_rec, rec_stride, c->spec(),
                               (int)c->sp.size(), c->f64(), c->qnode(), c->st(), d_gf, c->n_f, d_gm, d_gl, d_cp,
                               (int)c->pr.size(), s));

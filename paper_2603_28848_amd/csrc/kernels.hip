@@ -749,7 +749,7 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
 __host__ __device__ inline int vjp_rec_len(int n_tab, int n_max) { return n_tab * n_max + 1 + 4 + kMaxN + 1; }
 
 template <int NI>
-__device__ void vjp_task(const SampleLaunch& L, const Task task, unsigned char* smem) {
+__device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
   constexpr int B = (D + 3) / 4;
@@ -842,7 +842,24 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, unsigned char* 
   double g_obs = 0.0, dfit[4] = {0.0, 0.0, 0.0, 0.0}, dm[NR], sumW = 0.0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) dm[r] = 0.0;
-  for (int64_t n = n0 + tid; n < n1; n += kBlock) {
+  // Only the samples the screening pass listed (in or near the energy shell): every other sample has W = 0 and
+  // zero derivatives.  The unit's eight lists (in-shell then near, waves in order) form one sequence whose entry
+  // e is taken by thread e mod 256.
+  const uint32_t* cnt = L.shell_cnt + (int64_t)pos * 2 * kWaves;
+  const uint16_t* lst = L.shell_list + (int64_t)pos * L.list_stride;
+  const int64_t wlen = L.list_stride / kWaves;
+  int M = 0;
+  for (int l = 0; l < 2 * kWaves; ++l) M += (int)cnt[l];
+  (void)n1;
+  for (int e = tid; e < M; e += kBlock) {
+    int l = 0, k = e;
+    while (k >= (int)cnt[l]) {
+      k -= (int)cnt[l];
+      ++l;
+    }
+    const int w = l % kWaves;
+    const uint32_t off = l < kWaves ? lst[w * wlen + k] : lst[w * wlen + wlen - 1 - k];
+    const int64_t n = n0 + off;
     uint32_t wd[4 * B];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -995,10 +1012,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_vjp(SampleLaunch L) {
   for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
     const Task task = L.tasks[L.task_begin + t];
     const int ni = L.items[task.item].nint;
-    if ((MASK & 1) && ni == 1) vjp_task<1>(L, task, smem);
-    if ((MASK & 2) && ni == 2) vjp_task<2>(L, task, smem);
-    if ((MASK & 4) && ni == 3) vjp_task<3>(L, task, smem);
-    if ((MASK & 8) && ni == 4) vjp_task<4>(L, task, smem);
+    if ((MASK & 1) && ni == 1) vjp_task<1>(L, task, t, smem);
+    if ((MASK & 2) && ni == 2) vjp_task<2>(L, task, t, smem);
+    if ((MASK & 4) && ni == 3) vjp_task<3>(L, task, t, smem);
+    if ((MASK & 8) && ni == 4) vjp_task<4>(L, task, t, smem);
   }
 }
 
