@@ -87,6 +87,7 @@ extern "C" {
 #define BMC_MAXBINS 64
 #define BMC_MAXGRID 2048
 #define BMC_MAXITER 64
+#define BMC_MAXEVAL 256    /* evaluation points off the grid per call (bmc_run_opts.eval_q) */
 
 typedef struct bmc_ctx bmc_ctx;
 
@@ -116,6 +117,13 @@ typedef struct {
   int freeze_maps;     /* 1: the Vegas maps are used but not adapted */
   int eval_stride;     /* 0: each process's own stride, skipped nodes filled (linear in ln q; C/f held past
                           the last evaluated node); k >= 1: every k-th node of every process, no fill */
+  const double* eval_q;  /* NULL: the grid (above).  Else n_eval comoving momenta (host, > 0, borrowed for the
+                            call) at which C of the one selected species is evaluated: the observed leg sits at
+                            q, its f interpolated linearly in ln q inside the grid and extrapolated by the fit
+                            outside (the rule of every other particle).  Outputs are C(q_k) in order.  The maps
+                            of these points are kept per index k and species (bmc_maps_reset when the points
+                            change); the adjoint does not take them. */
+  int n_eval;          /* number of eval_q points, 1 .. BMC_MAXEVAL */
 } bmc_run_opts;
 
 /* ---- context and workspace ---- */
@@ -163,7 +171,8 @@ int bmc_get_time(bmc_ctx* ctx, double* t);
 /* ---- evaluation ---- */
 
 /* Number of items and of output values bmc_collision produces for (process, species, opts):
- * process -1 = every process; species -1 = every species (outputs concatenated in species order). */
+ * process -1 = every process; species -1 = every species (outputs concatenated in species order); with
+ * opts->eval_q set, n_out = opts->n_eval (one value per evaluation point). */
 int bmc_plan_size(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, int* n_items, int* n_out);
 
 /* Evaluates C and its Monte-Carlo sigma for the selected (process, species) pairs in one call.
@@ -185,6 +194,18 @@ int bmc_maps_get(bmc_ctx* ctx, const uint32_t* uids, int n, double* maps);
 int bmc_maps_set(bmc_ctx* ctx, const uint32_t* uids, int n, const double* maps);
 /* Forgets the maps of a process (-1 = all): they restart uniform. */
 int bmc_maps_reset(bmc_ctx* ctx, int process);
+
+/* Checkpoint and resume: the state that an evolution carries from one call to the next -- every species' f, the
+ * time and the device epoch counters, and every Vegas map the context holds -- as one host byte blob.
+ * bmc_state_size gives the bytes bmc_state_get writes into the caller's buffer (synchronises the stream).
+ * bmc_state_set restores a blob into a context with the same species grids and processes (checked: a blob of
+ * another model, an invalid f or a map of an unknown work item is rejected with nothing changed); the masses,
+ * couplings and expansion are the context's own.  Layout: a 48-byte header (magic "BMCS", version 1, species
+ * count, map count, number of f values, t, epoch, next epoch, doubles per map), the f values (FP64, species
+ * concatenated), then per map its uid (as a 64-bit word) and its edges (12 x 65 doubles, unused rows zero). */
+int bmc_state_size(bmc_ctx* ctx, size_t* bytes);
+int bmc_state_get(bmc_ctx* ctx, void* blob, size_t bytes);
+int bmc_state_set(bmc_ctx* ctx, const void* blob, size_t bytes);
 
 /* One Euler or Heun step of every species' f in log space over all processes (Sec. III.C):
  * dt > 0 fixed, dt <= 0: dt = min(dt_max, eps / max|k1/f|) (Eq. 20).  k1 uses opts->epoch at t, k2 uses

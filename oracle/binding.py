@@ -47,7 +47,7 @@ class World(C.Structure):
 
 class Item(C.Structure):
     _fields_ = [("proc", C.c_int), ("species", C.c_int), ("side", C.c_int), ("term", C.c_int),
-                ("eval_idx", C.c_int), ("mult", C.c_int), ("uid", C.c_uint32)]
+                ("eval_idx", C.c_int), ("mult", C.c_int), ("uid", C.c_uint32), ("q_obs", C.c_double)]
 
 
 _lib = None
@@ -80,6 +80,8 @@ def lib():
         L.orc_roles.argtypes = [C.POINTER(Process), C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_int)]
         L.orc_list_items.argtypes = [C.POINTER(World), C.c_int, C.c_int, C.c_int, C.POINTER(Item), C.c_int]
+        L.orc_list_items_at.argtypes = [C.POINTER(World), C.c_int, C.c_int, C.POINTER(C.c_double), C.c_int,
+                                        C.POINTER(Item), C.c_int]
         L.orc_map_uniform.argtypes = [C.POINTER(World), C.POINTER(Item), dp]
         L.orc_integrand_at.argtypes = [C.POINTER(World), C.POINTER(Item), dp, dp]
         L.orc_run_items.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), C.c_int64, C.c_int, C.c_int,
@@ -187,6 +189,25 @@ class OracleWorld:
         arr = (Item * max(1, n))()
         lib().orc_list_items(C.byref(self.world), proc, species, stride, arr, n)
         return arr, n
+
+    def items_at(self, q, proc=-1, species=0):
+        """Work items at evaluation momenta q (off the grid) of one species."""
+        q = np.ascontiguousarray(q, dtype=np.float64)
+        n = lib().orc_list_items_at(C.byref(self.world), proc, species, _dp(q), len(q), None, 0)
+        arr = (Item * max(1, n))()
+        lib().orc_list_items_at(C.byref(self.world), proc, species, _dp(q), len(q), arr, n)
+        return arr, n
+
+    def combine_at(self, items, n_items, Ibar, sigma, n_q):
+        """C and sigma at the evaluation points of items_at: C = sum mult sign Ibar, sigma^2 = sum mult^2 sigma^2
+        (Eq. 7; the loss term enters with a minus sign), item by item in order."""
+        Cv, S = np.zeros(n_q), np.zeros(n_q)
+        for i in range(n_items):
+            it = items[i]
+            sgn = -1.0 if (self.pr[it.proc].term_mode == 0 and it.term == 1) else 1.0
+            Cv[it.eval_idx] += it.mult * sgn * Ibar[i]
+            S[it.eval_idx] += it.mult * it.mult * sigma[i] * sigma[i]
+        return Cv, np.sqrt(S)
 
     def integrand_at(self, item, x):
         x = np.ascontiguousarray(x, dtype=np.float64)

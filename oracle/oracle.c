@@ -279,9 +279,44 @@ int orc_list_items(const orc_world* w, int proc_sel, int species_sel, int stride
               it->eval_idx = i;
               it->mult = mult;
               it->uid = orc_uid(p, a, side, term, i);
+              it->q_obs = 0.0;
             }
             ++count;
           }
+        }
+      }
+    }
+  }
+  return count;
+}
+
+/* Evaluation points off the grid: the observed leg sits at the given comoving momentum q[k] and its f follows the
+ * rule of every other particle (orc_f_at: interpolation inside the grid, the extrapolation fit outside). */
+int orc_list_items_at(const orc_world* w, int proc_sel, int species, const double* q, int n_q, orc_item* out,
+                      int cap) {
+  int count = 0;
+  if (species < 0 || species >= w->n_species || n_q < 0 || n_q > ORC_CUSTOM_BASE) return 0;
+  for (int p = 0; p < w->n_proc; ++p) {
+    if (proc_sel >= 0 && p != proc_sel) continue;
+    const orc_process* P = &w->procs[p];
+    for (int side = 0; side < 2; ++side) {
+      int mult = orc_side_multiplicity(P, species, side);
+      if (mult == 0) continue;
+      int n_terms = P->term_mode == ORC_TERMS_NET ? 1 : 2;
+      for (int term = 0; term < n_terms; ++term) {
+        for (int k = 0; k < n_q; ++k) {
+          if (out && count < cap) {
+            orc_item* it = &out[count];
+            it->proc = p;
+            it->species = species;
+            it->side = side;
+            it->term = term;
+            it->eval_idx = k;
+            it->mult = mult;
+            it->uid = orc_uid(p, species, side, term, ORC_CUSTOM_BASE + k);
+            it->q_obs = q[k];
+          }
+          ++count;
         }
       }
     }
@@ -380,8 +415,14 @@ static int item_setup(item_ctx* c, const orc_world* w, const orc_item* it, doubl
     c->fit[i] = &fits[4 * c->P->sp[i]];
   }
   const orc_species* so = &w->species[it->species];
-  c->q_obs = orc_grid_q(so, it->eval_idx);
-  c->f_obs = so->f[it->eval_idx];
+  if (it->q_obs > 0.0) {
+    const double p = it->q_obs / c->a, m = c->m[c->i_obs];
+    c->q_obs = it->q_obs;
+    c->f_obs = orc_f_at(so, c->fit[c->i_obs], it->q_obs, sqrt(p * p + m * m));
+  } else {
+    c->q_obs = orc_grid_q(so, it->eval_idx);
+    c->f_obs = so->f[it->eval_idx];
+  }
   return ORC_OK;
 }
 

@@ -74,7 +74,11 @@ typedef struct {
 typedef struct {
   int proc, species, side, term, eval_idx, mult;
   uint32_t uid;
+  double q_obs;  /* > 0: an evaluation point off the grid (comoving momentum); 0: grid node eval_idx */
 } orc_item;
+
+/* Identifier index of the k-th evaluation point off the grid: above every grid index. */
+#define ORC_CUSTOM_BASE (1 << 17)
 
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 void orc_sample_uniforms(uint64_t seed, uint32_t uid, uint32_t epoch, int it, int64_t n, int D, double* y);
@@ -88,6 +92,10 @@ int orc_side_multiplicity(const orc_process* P, int a, int side);
 int orc_roles(const orc_process* P, int a, int side, int* i_obs, int* i_cons, int* integ);
 uint32_t orc_uid(int proc, int species, int side, int term, int eval_idx);
 int orc_list_items(const orc_world* w, int proc_sel, int species_sel, int stride_override, orc_item* out, int cap);
+/* Work items at n_q evaluation momenta q[k] of one species (eval_idx = k, identifier index ORC_CUSTOM_BASE + k),
+ * in the order of orc_list_items. */
+int orc_list_items_at(const orc_world* w, int proc_sel, int species, const double* q, int n_q, orc_item* out,
+                      int cap);
 int orc_item_dims(const orc_world* w, const orc_item* it);
 void orc_map_uniform(const orc_world* w, const orc_item* it, double* map);
 int orc_fits_all(const orc_world* w, double t, double* fits);

@@ -34,7 +34,7 @@ class ProcessParams(C.Structure):
 class RunOpts(C.Structure):
     _fields_ = [("n_samples", C.c_int64), ("n_iter", C.c_int), ("first_iter", C.c_int), ("seed", C.c_uint64),
                 ("epoch", C.c_uint32), ("precision", C.c_int), ("launch", C.c_int), ("freeze_maps", C.c_int),
-                ("eval_stride", C.c_int)]
+                ("eval_stride", C.c_int), ("eval_q", C.c_void_p), ("n_eval", C.c_int)]
 
 
 class BmcError(RuntimeError):
@@ -82,6 +82,9 @@ _SIGS = {
     "bmc_set_timing": [C.c_void_p, C.c_int],
     "bmc_get_timing": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
     "bmc_get_sample_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64)],
+    "bmc_state_size": [C.c_void_p, C.POINTER(C.c_size_t)],
+    "bmc_state_get": [C.c_void_p, C.c_void_p, C.c_size_t],
+    "bmc_state_set": [C.c_void_p, C.c_void_p, C.c_size_t],
     "bmc_set_launch_tuning": [C.c_void_p, C.c_int, C.c_int],
     "bmc_autotune": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_double)],
@@ -239,9 +242,16 @@ class Context:
         self._check(lib().bmc_plan_size(self.h, process, species, C.byref(opts), C.byref(ni), C.byref(no)))
         return ni.value, no.value
 
-    def collision(self, process=-1, species=-1, opts: Optional[RunOpts] = None, out=None, sigma=None):
-        """C and sigma as host arrays (or into the given device tensors)."""
+    def collision(self, process=-1, species=-1, opts: Optional[RunOpts] = None, out=None, sigma=None, eval_q=None):
+        """C and sigma as host arrays (or into the given device tensors); with eval_q, at those comoving momenta
+        of the one selected species instead of on its grid."""
         opts = opts or default_opts()
+        if eval_q is not None:
+            q = np.ascontiguousarray(eval_q, dtype=np.float64)
+            opts = RunOpts.from_buffer_copy(opts)
+            opts.eval_q = q.ctypes.data
+            opts.n_eval = q.size
+            self._eval_q_keep = q  # the library reads the points during the calls below
         ni, no = self.plan_size(process, species, opts)
         self.ensure_workspace(opts.n_samples, opts.n_iter)
         self._last_items = ni
@@ -313,6 +323,21 @@ class Context:
         ms, n = C.c_double(), C.c_int()
         self._check(lib().bmc_get_timing(self.h, int(reset), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def state_get(self) -> bytes:
+        """Checkpoint: f of every species, the time and epochs, and every Vegas map, as one byte string."""
+        self.ensure_workspace()
+        n = C.c_size_t()
+        self._check(lib().bmc_state_size(self.h, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(lib().bmc_state_get(self.h, buf, n.value))
+        return buf.raw
+
+    def state_set(self, blob: bytes):
+        """Resume from a checkpoint of a context with the same species grids and processes."""
+        self.ensure_workspace()
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(lib().bmc_state_set(self.h, buf, len(blob)))
 
     def get_sample_stats(self, reset=True):
         """Samples the second pass evaluated (in or near the energy shell) since the last reset."""

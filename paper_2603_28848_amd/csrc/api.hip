@@ -29,6 +29,7 @@ constexpr size_t kListCapBytes = size_t(1) << 30;
 // Second pass: an item's units form up to this many groups, each one task of the pass with its own record (enough
 // blocks for a per-grid-point launch, few enough records for a batched one)
 constexpr int kShellGroups = 16;
+constexpr int kMaxEvalPoints = BMC_MAXEVAL;  // map slots are reserved for this many points off the grid
 
 int shell_units_for(int64_t n_units) { return (int)((n_units + kShellGroups - 1) / kShellGroups); }
 
@@ -57,6 +58,7 @@ struct Plan {
   int process = -2, species = -2, stride = -1;
   int64_t n_samples = -1;
   int n_iter = -1;
+  std::vector<double> eval_q;
   // content
   std::vector<ItemRec> items;
   std::vector<int> nodes_of_item;
@@ -272,13 +274,14 @@ void layout_persistent(bmc_ctx* c) {
   o = align_up(o + 8 * nf);
   c->off_qnode = o;
   o = align_up(o + 8 * nf);
-  // map slots: every item any call can plan (stride 1, both sides, both terms)
+  // map slots: every item any call can plan (stride 1, both sides, both terms), at the grid nodes and at
+  // kMaxEvalPoints evaluation points off the grid of every species
   int slots = 0;
   for (size_t p = 0; p < c->pr.size(); ++p)
     for (size_t a = 0; a < c->sp.size(); ++a)
       for (int side = 0; side < 2; ++side)
         if (multiplicity(c->pr[p], (int)a, side) > 0)
-          slots += c->sp[a].n * (c->pr[p].prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+          slots += (c->sp[a].n + kMaxEvalPoints) * (c->pr[p].prm.term_mode == BMC_TERMS_NET ? 1 : 2);
   c->max_slots = slots;
   c->off_maps = o;
   o = align_up(o + sizeof(double) * (size_t)kSlotDoubles * (size_t)slots);
@@ -352,7 +355,10 @@ struct PlanKey {
   int process, species, stride;
   int64_t n_samples;
   int n_iter;
+  std::vector<double> eval_q;  // evaluation points off the grid (empty: the grid)
 };
+
+constexpr uint32_t kCustomBase = 1u << 17;  // identifier index of the first evaluation point off the grid
 
 int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   Plan Q;
@@ -361,9 +367,15 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   Q.stride = k.stride;
   Q.n_samples = k.n_samples;
   Q.n_iter = k.n_iter;
+  Q.eval_q = k.eval_q;
   const int np = (int)c->pr.size(), ns = (int)c->sp.size();
   if (k.process < -1 || k.process >= np) return fail(c, BMC_EINVAL, "bad process id");
   if (k.species < -1 || k.species >= ns) return fail(c, BMC_EINVAL, "bad species id");
+  const bool custom = !k.eval_q.empty();
+  const int n_custom = (int)k.eval_q.size();
+  if (custom && k.species < 0) return fail(c, BMC_EINVAL, "evaluation points need one species");
+  for (double q : k.eval_q)
+    if (!(q > 0.0) || !std::isfinite(q)) return fail(c, BMC_EINVAL, "evaluation points must be positive");
   // per (process, species): slot base for node 0 and its stride
   std::vector<std::vector<int>> slot_base(np, std::vector<int>(ns, -1));
   std::vector<std::vector<int>> pstride(np, std::vector<int>(ns, 0));
@@ -390,7 +402,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
       if (!any) continue;
       slot_base[p][a] = (int)slot_lists.size();
       pstride[p][a] = stride;
-      const int n_nodes = (S.n + stride - 1) / stride;
+      const int n_nodes = custom ? n_custom : (S.n + stride - 1) / stride;
       const int first_slot = (int)slot_lists.size();
       slot_lists.resize(slot_lists.size() + n_nodes);
       for (int side = 0; side < 2; ++side) {
@@ -400,10 +412,11 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
         if (!assign_roles(Pr, a, side, &obs, &cons, integ)) return fail(c, BMC_EINVAL, "role assignment failed");
         const int n_terms = Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2;
         for (int term = 0; term < n_terms; ++term) {
-          for (int i = 0; i < S.n; i += stride) {
+          for (int pt = 0; pt < n_nodes; ++pt) {
+            const int i = custom ? pt : pt * stride;
             ItemRec it{};
             it.uid = ((uint32_t)p << 24) | ((uint32_t)a << 20) | ((uint32_t)side << 19) | ((uint32_t)term << 18) |
-                     (uint32_t)i;
+                     (custom ? kCustomBase + (uint32_t)pt : (uint32_t)i);
             it.proc = p;
             it.nint = nint;
             it.D = D;
@@ -411,8 +424,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.term = term;
             it.net = Pr.prm.term_mode == BMC_TERMS_NET;
             it.eval_idx = i;
+            it.obs_at = custom ? 1 : 0;
             it.n_iter = nit;
-            it.q_obs = grid_node(S, i);
+            it.q_obs = custom ? k.eval_q[pt] : grid_node(S, i);
             it.obs_species = a;
             it.mult = mult;
             it.N = N;
@@ -457,7 +471,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
               }
             }
             it.cons_in = cons < Pr.n_in ? 1 : 0;
-            it.out_slot = first_slot + i / stride;
+            it.out_slot = first_slot + pt;
             // map slot
             auto f = c->slot_of_uid.find(it.uid);
             int ms;
@@ -583,8 +597,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
   for (int a = 0; a < ns; ++a) {
     if (k.species >= 0 && a != k.species) continue;
     const Species& S = c->sp[a];
-    const int ostride = k.stride > 0 ? k.stride : 1;
-    for (int j = 0; j < S.n; j += ostride) {
+    const int ostride = custom ? 1 : (k.stride > 0 ? k.stride : 1);
+    const int n_pts = custom ? n_custom : S.n;
+    for (int j = 0; j < n_pts; j += ostride) {
       GatherEntry g{};
       g.species = a;
       g.node = j;
@@ -593,9 +608,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
         if (slot_base[p][a] < 0) continue;
         GatherProc gp{};
         gp.slot_base = slot_base[p][a];
-        gp.stride = pstride[p][a];
-        gp.last = ((S.n - 1) / gp.stride) * gp.stride;
-        gp.fill = k.stride > 0 ? 0 : 1;
+        gp.stride = custom ? 1 : pstride[p][a];
+        gp.last = custom ? n_custom - 1 : ((S.n - 1) / gp.stride) * gp.stride;
+        gp.fill = (custom || k.stride > 0) ? 0 : 1;
         Q.gproc.push_back(gp);
       }
       g.count = (int)Q.gproc.size() - g.first;
@@ -868,13 +883,22 @@ int check_opts(bmc_ctx* c, const bmc_run_opts* o) {
   if (o->launch != BMC_LAUNCH_BATCHED && o->launch != BMC_LAUNCH_PLAIN) return fail(c, BMC_EINVAL, "bad launch");
   if (o->epoch >= (1u << 26)) return fail(c, BMC_EINVAL, "epoch >= 2^26");
   if (o->first_iter < 0 || o->eval_stride < 0) return fail(c, BMC_EINVAL, "negative first_iter or eval_stride");
+  if (o->eval_q && (o->n_eval < 1 || o->n_eval > kMaxEvalPoints))
+    return fail(c, BMC_EINVAL, "n_eval must be in 1 .. " + std::to_string(kMaxEvalPoints) + " when eval_q is given");
   return BMC_OK;
 }
 
+PlanKey plan_key(int process, int species, const bmc_run_opts* o) {
+  PlanKey k{process, species, o->eval_stride, o->n_samples, o->n_iter, {}};
+  if (o->eval_q) k.eval_q.assign(o->eval_q, o->eval_q + o->n_eval);
+  return k;
+}
+
 int get_plan(bmc_ctx* c, Plan& slot, int process, int species, const bmc_run_opts* o) {
-  PlanKey k{process, species, o->eval_stride, o->n_samples, o->n_iter};
+  const PlanKey k = plan_key(process, species, o);
   const bool same = slot.process == k.process && slot.species == k.species && slot.stride == k.stride &&
-                    slot.n_samples == k.n_samples && slot.n_iter == k.n_iter && slot.uploaded;
+                    slot.n_samples == k.n_samples && slot.n_iter == k.n_iter && slot.eval_q == k.eval_q &&
+                    slot.uploaded;
   if (!same) {
     int rc = build_plan(c, k, &slot);
     if (rc) {
@@ -1178,7 +1202,7 @@ int bmc_plan_size(bmc_ctx* c, int process, int species, const bmc_run_opts* o, i
   auto saved = c->slot_of_uid;
   char* ws = c->ws;
   c->ws = nullptr;
-  rc = build_plan(c, PlanKey{process, species, o->eval_stride, o->n_samples, o->n_iter}, &P);
+  rc = build_plan(c, plan_key(process, species, o), &P);
   c->ws = ws;
   c->slot_of_uid = saved;
   if (rc) return rc;
@@ -1302,6 +1326,120 @@ int bmc_maps_set(bmc_ctx* c, const uint32_t* uids, int n, const double* maps) {
   return BMC_OK;
 }
 
+namespace {
+constexpr uint32_t kStateMagic = 0x53434d42u;  // "BMCS"
+constexpr uint32_t kStateVersion = 1;
+struct StateHeader {
+  uint32_t magic, version, n_species, n_maps;
+  int64_t n_f;
+  double t;
+  uint32_t epoch, next_epoch, slot_doubles, reserved;
+};
+size_t state_bytes(const bmc_ctx* c) {
+  return sizeof(StateHeader) + 8 * (size_t)c->n_f + c->slot_of_uid.size() * (8 + 8 * (size_t)kSlotDoubles);
+}
+}  // namespace
+
+int bmc_state_size(bmc_ctx* c, size_t* bytes) {
+  if (!c || !bytes) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  *bytes = state_bytes(c);
+  return BMC_OK;
+}
+
+int bmc_state_get(bmc_ctx* c, void* blob, size_t bytes) {
+  if (!c || !blob) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  if (bytes < state_bytes(c)) return fail(c, BMC_EINVAL, "state buffer too small");
+  DevState s;
+  int rc = read_state(c, &s);
+  if (rc) return rc;
+  char* p = static_cast<char*>(blob);
+  StateHeader h{kStateMagic, kStateVersion, (uint32_t)c->sp.size(), (uint32_t)c->slot_of_uid.size(), c->n_f, s.t,
+                s.epoch, s.next_epoch, (uint32_t)kSlotDoubles, 0u};
+  std::memcpy(p, &h, sizeof(h));
+  p += sizeof(h);
+  HIPCHK(c, hipMemcpy(p, c->f64(), 8 * (size_t)c->n_f, hipMemcpyDeviceToHost));
+  p += 8 * (size_t)c->n_f;
+  std::vector<std::pair<uint32_t, int>> slots(c->slot_of_uid.begin(), c->slot_of_uid.end());
+  std::sort(slots.begin(), slots.end());
+  for (auto& us : slots) {
+    const uint64_t uid = us.first;
+    std::memcpy(p, &uid, 8);
+    p += 8;
+    HIPCHK(c, hipMemcpy(p, c->maps() + (size_t)us.second * kSlotDoubles, 8 * (size_t)kSlotDoubles,
+                        hipMemcpyDeviceToHost));
+    p += 8 * (size_t)kSlotDoubles;
+  }
+  return BMC_OK;
+}
+
+int bmc_state_set(bmc_ctx* c, const void* blob, size_t bytes) {
+  if (!c || !blob) return BMC_EINVAL;
+  if (!c->bound) return fail(c, BMC_ESTATE, "workspace not bound");
+  if (bytes < sizeof(StateHeader)) return fail(c, BMC_EINVAL, "state blob too short");
+  StateHeader h;
+  std::memcpy(&h, blob, sizeof(h));
+  if (h.magic != kStateMagic || h.version != kStateVersion) return fail(c, BMC_EINVAL, "not a state blob");
+  if (h.n_species != c->sp.size() || h.n_f != c->n_f || h.slot_doubles != (uint32_t)kSlotDoubles)
+    return fail(c, BMC_EINVAL, "the state blob belongs to a different model");
+  if (bytes < sizeof(h) + 8 * (size_t)h.n_f + (size_t)h.n_maps * (8 + 8 * (size_t)kSlotDoubles))
+    return fail(c, BMC_EINVAL, "state blob too short");
+  if (!std::isfinite(h.t)) return fail(c, BMC_EINVAL, "non-finite time in the state blob");
+  const char* p = static_cast<const char*>(blob) + sizeof(h);
+  // validate everything before changing anything
+  std::vector<double> f((size_t)h.n_f);
+  std::memcpy(f.data(), p, 8 * f.size());
+  p += 8 * f.size();
+  for (auto& S : c->sp)
+    for (int j = 0; j < S.n; ++j) {
+      const double v = f[(size_t)S.f_off + j];
+      if (!(v > 0.0) || !std::isfinite(v)) return fail(c, BMC_ERANGE, "f must be positive and finite");
+      if (S.stat == BMC_FERMI && !(v < 1.0)) return fail(c, BMC_ERANGE, "Fermi-Dirac f must be below 1");
+    }
+  std::vector<uint32_t> uids(h.n_maps);
+  const char* pm = p;
+  size_t new_slots = 0;
+  for (uint32_t i = 0; i < h.n_maps; ++i) {
+    uint64_t u;
+    std::memcpy(&u, pm + (size_t)i * (8 + 8 * (size_t)kSlotDoubles), 8);
+    const uint32_t uid = (uint32_t)u;
+    const int pr = (int)(uid >> 24), a = (int)((uid >> 20) & 15), side = (int)((uid >> 19) & 1);
+    const int node = (int)(uid & ((1u << 18) - 1));
+    if (u >> 32 || pr >= (int)c->pr.size() || a >= (int)c->sp.size() || node >= c->sp[a].n ||
+        multiplicity(c->pr[pr], a, side) == 0)
+      return fail(c, BMC_EINVAL, "a map in the state blob does not name a work item of this model");
+    uids[i] = uid;
+    new_slots += c->slot_of_uid.count(uid) ? 0 : 1;
+  }
+  if (c->slot_of_uid.size() + new_slots > (size_t)c->max_slots) return fail(c, BMC_ENOMEM, "map slots exhausted");
+  for (auto& S : c->sp) {
+    S.f.assign(f.begin() + S.f_off, f.begin() + S.f_off + S.n);
+    S.f_set = true;
+  }
+  HIPCHK(c, hipMemcpy(c->f64(), f.data(), 8 * f.size(), hipMemcpyHostToDevice));
+  for (uint32_t i = 0; i < h.n_maps; ++i) {
+    auto it = c->slot_of_uid.find(uids[i]);
+    int slot;
+    if (it == c->slot_of_uid.end()) {
+      slot = (int)c->slot_of_uid.size();
+      c->slot_of_uid[uids[i]] = slot;
+    } else {
+      slot = it->second;
+    }
+    HIPCHK(c, hipMemcpy(c->maps() + (size_t)slot * kSlotDoubles, pm + (size_t)i * (8 + 8 * (size_t)kSlotDoubles) + 8,
+                        8 * (size_t)kSlotDoubles, hipMemcpyHostToDevice));
+  }
+  c->t = h.t;
+  DevState* st = c->st();
+  HIPCHK(c, hipMemcpy(&st->t, &h.t, sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(&st->epoch, &h.epoch, sizeof(uint32_t), hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(&st->next_epoch, &h.next_epoch, sizeof(uint32_t), hipMemcpyHostToDevice));
+  c->plan = Plan();
+  c->step_plan = Plan();
+  return BMC_OK;
+}
+
 int bmc_maps_reset(bmc_ctx* c, int process) {
   if (!c) return BMC_EINVAL;
   if (process < -1 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
@@ -1312,14 +1450,7 @@ int bmc_maps_reset(bmc_ctx* c, int process) {
   if (process < 0) {
     c->slot_of_uid.clear();
   } else {
-    // keep the slot numbers of other processes; re-initialise the dropped ones through a fresh plan
-    for (uint32_t u : drop) {
-      const int slot = c->slot_of_uid[u];
-      const int p = (int)(u >> 24);
-      (void)p;
-      (void)slot;
-    }
-    // simplest correct behaviour: mark all plans stale and rewrite the dropped maps as uniform now
+    // the dropped uids keep their slots (other processes keep theirs); their maps are rewritten as uniform now
     std::vector<double> buf;
     for (uint32_t u : drop) {
       const int nb = c->pr[u >> 24].prm.n_bins;
@@ -1347,6 +1478,7 @@ int bmc_step(bmc_ctx* c, int method, double dt, double eps, double dt_max, const
   if (rc) return rc;
   rc = check_ready(c);
   if (rc) return rc;
+  if (o->eval_q) return fail(c, BMC_EINVAL, "steps evaluate on the grids (eval_q must be NULL)");
   bmc_run_opts so = *o;
   so.eval_stride = 0;
   rc = get_plan(c, c->step_plan, -1, -1, &so);
@@ -1394,6 +1526,7 @@ int bmc_graph_capture_steps(bmc_ctx* c, int n_steps, int method, double dt, doub
   rc = check_ready(c);
   if (rc) return rc;
   if (c->stream == nullptr) return fail(c, BMC_EINVAL, "graph capture needs a non-null stream");
+  if (o->eval_q) return fail(c, BMC_EINVAL, "steps evaluate on the grids (eval_q must be NULL)");
   bmc_run_opts so = *o;
   so.eval_stride = 0;
   rc = get_plan(c, c->step_plan, -1, -1, &so);
@@ -1474,6 +1607,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   int rc = check_opts(c, o);
   if (rc) return rc;
   if (o->precision != BMC_FP64) return fail(c, BMC_EUNSUP, "vector-Jacobian products are FP64 only");
+  if (o->eval_q) return fail(c, BMC_EUNSUP, "vector-Jacobian products are on the grids only (eval_q must be NULL)");
   rc = check_ready(c);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));

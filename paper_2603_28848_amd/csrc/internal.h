@@ -56,7 +56,8 @@ struct ItemRec {
   int nb;            // Vegas bins
   int term;          // 0 gain / net, 1 loss
   int net;           // 1: gain - loss
-  int eval_idx;      // grid index of the observed momentum
+  int eval_idx;      // grid index of the observed momentum, or index k of an evaluation point off the grid
+  int obs_at;        // 1: observed momentum q_obs off the grid, f there from the table's interpolation/fit
   int n_iter;        // Vegas iterations of this item in the call
   double q_obs;      // comoving observed momentum (the grid node)
   int obs_species;

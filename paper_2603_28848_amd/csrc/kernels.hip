@@ -157,6 +157,19 @@ __device__ __forceinline__ double interp64(const FTab<double>& t, double q, int*
   return f0 + w * (f1 - f0);
 }
 
+// f of species S (table f, global memory) at comoving momentum q with energy E by the rule of Sec. III.B: linear
+// in ln q between the bracketing nodes inside [q_0, q_{N-1}], the fit f = 1 / (exp(a + b E) - eta) outside.
+__device__ __forceinline__ double f_at_global(const SpecDev& S, const double* __restrict__ f, const double* fit,
+                                              double q, double E) {
+  if (q < S.q_min) return 1.0 / (exp(fit[0] + fit[1] * E) - (double)S.stat);
+  if (q > S.q_max) return 1.0 / (exp(fit[2] + fit[3] * E) - (double)S.stat);
+  const double tp = (log_pos(q) - S.lq0) * S.inv_h;
+  int j = (int)floor(tp);
+  j = j < 0 ? 0 : (j > S.n - 2 ? S.n - 2 : j);
+  const double w = tp - (double)j;
+  return f[j] + w * (f[j + 1] - f[j]);
+}
+
 // FP32 integrand: the grid position in FP64 (an FP32 logarithm would move the weight by ~1e-6 / h, which the
 // linear interpolation of a steep tail amplifies by f_j / f_{j+1}); interpolation of the FP32 table.
 __device__ __forceinline__ float interp32(const FTab<float>& t, double q) {
@@ -506,7 +519,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   const SpecDev& So = L.spec[it->obs_species];
   K.p_obs = it->q_obs * K.inv_a;
   K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
-  K.f_obs = L.f64[So.f_off + it->eval_idx];
+  K.f_obs = it->obs_at ? f_at_global(So, L.f64 + So.f_off, st->fit[it->obs_species], it->q_obs, K.E_obs)
+                        : L.f64[So.f_off + it->eval_idx];
   {
     const double obs_bf = 1.0 + K.eta[NI + 1] * K.f_obs;
     K.g_obs = K.obsside[NI + 1] ? obs_bf : K.f_obs;  // the observed leg is on the observed side

@@ -225,3 +225,47 @@ def test_error_paths():
     with pytest.raises(bm.BmcError) as e:
         ctx2.set_f(0, np.full(16, 1.5))
     assert e.value.code == bm.ERANGE
+
+
+# ------------------------------------------------------------------------------- points off the grid
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("which", ["2to2", "2to3"])
+def test_points_off_the_grid(precision, which):
+    """Collision integral at momenta between grid nodes, below the grid and above it (observed f interpolated
+    inside the grid, from the fit outside), frozen maps: every item and every point against the oracle."""
+    bm = _bm()
+    if which == "2to2":
+        w, N, nitn = wl.w22_mb(), 10_000, 3
+    else:
+        w, N, nitn = wl.w23_be(n_grid=32, N=1 << 13), 1 << 13, 2
+    sp = w.species[0]
+    qg = wl.log_nodes(sp.q_min, sp.q_max, sp.n_grid)
+    q = np.array([0.5 * sp.q_min, np.sqrt(qg[3] * qg[4]), 0.3 * qg[10] + 0.7 * qg[11], qg[17], 1.3 * sp.q_max])
+    say("off-grid %s precision=%d" % (which, precision))
+    opts = bm.default_opts(seed=3, epoch=0, precision=precision, freeze_maps=1, n_iter=nitn, n_samples=N)
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(-1, 0, opts, eval_q=q)
+    assert C.shape == (len(q),)
+    res = ctx.item_results(nitn)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items_at(q, species=0)
+    by = {items[i].uid: items[i] for i in range(n)}
+    assert sorted(by) == sorted(int(u) for u in res["uid"])
+    sel = [by[int(u)] for u in res["uid"]]
+    items = (ob.Item * len(sel))(*sel)
+    rc, r = ow.run_items(items, n, N, nitn, seed=3, adapt=False)
+    assert rc == 0
+    tol = TOL[precision]
+    assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
+    Co, So = ow.combine_at(items, n, r["Ibar"], r["sigma"], len(q))
+    scale = point_scale(items, n, r["Ibar"], 0, len(q))
+    err = np.abs(C - Co)
+    say("C max err / scale %.3e" % np.max(err / scale))
+    assert np.all(err <= tol * scale)
+    np.testing.assert_allclose(S, So, rtol=10 * tol, atol=1e-300)
+    # the same context still evaluates its grid afterwards, with the grid's own items
+    Cg, _ = ctx.collision(-1, 0, opts)
+    assert Cg.shape == (sp.n_grid,)
+    for bad_q, bad_species in ((np.ones(257), 0), (np.array([1.0, -1.0]), 0), (np.array([1.0]), -1)):
+        with pytest.raises(bm.BmcError):
+            ctx.collision(-1, bad_species, opts, eval_q=bad_q)

@@ -193,3 +193,33 @@ def test_step_error_restores_state():
     assert e.value.code == bm.ERANGE
     np.testing.assert_array_equal(ctx.get_f(0, 24), f0)
     assert ctx.get_time() == 0.0
+
+
+def test_state_checkpoint_resume_continues_bitwise():
+    """A context resumed from bmc_state_get's blob (f, time, epochs, maps) continues an adaptive evolution
+    exactly as the original: two Heun steps after the checkpoint agree bitwise, and the blob round-trips."""
+    bm = _bm()
+    w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
+    opts = bm.default_opts(seed=4, epoch=0, precision=1)
+    a = bm.from_workload(w)
+    for k in range(2):
+        opts.epoch = 2 * k
+        a.step(1, -1.0, 0.3, 1.0, opts)
+    blob = a.state_get()
+    b = bm.from_workload(w)
+    b.state_set(blob)
+    assert b.state_get() == blob
+    assert b.get_time() == a.get_time()
+    for k in range(2, 4):
+        opts.epoch = 2 * k
+        a.step(1, -1.0, 0.3, 1.0, opts)
+        b.step(1, -1.0, 0.3, 1.0, opts)
+    assert a.get_time() == b.get_time()
+    for s in range(2):
+        assert np.array_equal(a.get_f(s, 32), b.get_f(s, 32))
+    assert a.state_get() == b.state_get()
+    # a blob of another model is rejected and leaves the context unchanged
+    other = bm.from_workload(wl.w22_mb(n_grid=16, N=1 << 10, nitn=1))
+    with pytest.raises(bm.BmcError) as e:
+        other.state_set(blob)
+    assert e.value.code == bm.EINVAL

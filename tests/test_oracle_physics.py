@@ -293,3 +293,51 @@ def test_run_is_deterministic():
     a = ob.OracleWorld(w).collision_all(1 << 11, 3)
     b = ob.OracleWorld(w).collision_all(1 << 11, 3)
     assert np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+
+
+def test_points_off_the_grid_reduce_to_grid_items_at_nodes():
+    """An evaluation point placed exactly on grid node j is the grid item of node j: the same integrand at every
+    sampled point x (the observed leg's f by interpolation equals the table value there)."""
+    w = wl.w23_be(n_grid=32, N=1 << 10, nitn=1)
+    ow = ob.OracleWorld(w)
+    q = ow.grid_q(0)
+    nodes = [0, 7, 31]
+    grid_items, ng = ow.items()
+    custom, nc = ow.items_at(q[nodes], species=0)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for i in range(nc):
+        c = custom[i]
+        g = [grid_items[k] for k in range(ng) if grid_items[k].side == c.side and grid_items[k].term == c.term
+             and grid_items[k].eval_idx == nodes[c.eval_idx]][0]
+        D = ow.item_dims(c) if hasattr(ow, "item_dims") else 9
+        for _ in range(20):
+            x = np.concatenate([[rng.uniform(0.01, 30.0), rng.uniform(0, math.pi), rng.uniform(0, 2 * math.pi)]
+                                for _ in range(D // 3)])
+            a, b = ow.integrand_at(c, x), ow.integrand_at(g, x)
+            assert abs(a - b) <= 1e-14 * max(abs(b), 1e-300), (nodes[c.eval_idx], a, b)
+            checked += 1
+    assert checked == nc * 20
+
+
+def test_p4_mb_loss_at_points_off_the_grid():
+    """Loss items at momenta between grid nodes and below the grid agree with the two-body closed form, given
+    the f there (interpolated inside the grid, the Eq. 17 fit below it). Points above the grid are left out:
+    the integrated momenta stay inside [q_min, q_max], which truncates their final states."""
+    m, sig = 1.0, 0.02
+    w = wl.w22_mb(n_grid=64, sigma_E=sig)
+    ow = ob.OracleWorld(w)
+    rc, fit = ow.fit(0)
+    ff = _f_fn(ow, 0, fit)
+    qg = ow.grid_q(0)
+    qs = np.array([math.sqrt(qg[20] * qg[21]), 0.6 * qg[33] + 0.4 * qg[34], 0.005])
+    items, n = ow.items_at(qs, species=0)
+    loss = [items[i] for i in range(n) if items[i].term == 1]
+    arr = (ob.Item * len(loss))(*loss)
+    rc, r = ow.run_items(arr, len(loss), 1 << 16, 6)
+    assert rc == 0
+    for i, it in enumerate(loss):
+        qk = qs[it.eval_idx]
+        f_obs = float(ff(np.array([qk]), np.array([math.hypot(qk, m)]))[0])
+        L = pa.mb_loss_closed_form(qk, f_obs, lambda p: float(ff(np.array([p]), np.array([math.hypot(p, m)]))[0]), m)
+        assert abs(r["Ibar"][i] - L) <= 4 * r["sigma"][i] + 0.15 * sig * L, (qk, r["Ibar"][i], L, r["sigma"][i])
