@@ -71,6 +71,9 @@ extern "C" {
 #define BMC_SIDES_OUT 2
 #define BMC_SIDES_BOTH 3
 
+#define BMC_WIDTH_ABS 0   /* sigma_E is the width of the Gaussian energy delta (an energy) */
+#define BMC_WIDTH_REL 1   /* sigma_E is a fraction w; the width at a point is w (E_in + E_out) / 2 (Appendix C) */
+
 #define BMC_FP64 0        /* everything in IEEE double */
 #define BMC_FP32I 1       /* FP32 integrand (f lookups, statistical factor, exponentials) with FP64
                              kinematics up to the delta argument and FP64 accumulation */
@@ -94,7 +97,9 @@ typedef struct bmc_ctx bmc_ctx;
 /* Per-process parameters (Sec. III.A "Processes are registered ..."; Appendix C). */
 typedef struct {
   double coupling;     /* lambda; |M|^2 = lambda^2 includes the identical-particle symmetry factors */
-  double sigma_E;      /* absolute width of the Gaussian energy delta (Eq. 15), > 0 */
+  double sigma_E;      /* width of the Gaussian energy delta (Eq. 15), > 0: an energy (BMC_WIDTH_ABS) or the
+                          fraction w of (E_in + E_out) / 2 at each point (BMC_WIDTH_REL, w <= 1); the initial value
+                          when the width controller is on */
   double alpha;        /* Vegas damping exponent, in [0, 2] (paper: 0.5) */
   double e_cut;        /* points with any E_i < e_cut get weight 0 (Appendix A); default 0 */
   int n_bins;          /* Vegas bins per dimension, 2 .. BMC_MAXBINS (paper/workloads: 50) */
@@ -103,6 +108,14 @@ typedef struct {
   int eval_stride;     /* evaluate every k-th grid point of the observed species (>= 1) */
   int64_t n_samples;   /* samples per item per iteration (>= 2) */
   int n_iter;          /* Vegas iterations per evaluation (1 .. BMC_MAXITER) */
+  int width_mode;      /* BMC_WIDTH_ABS (default) or BMC_WIDTH_REL */
+  /* Width controller (Appendix C), with width_adapt = 1: after every evaluation the width is divided by
+   * width_factor when the relative Monte Carlo error r of the process's items is below width_lo, multiplied by it
+   * when r exceeds width_hi, and clamped to [width_min, width_max].  r = sum sigma_i / sum |Ibar_i| over the
+   * process's items of that evaluation.  Requires 0 < width_lo < width_hi, width_factor > 1,
+   * 0 < width_min <= width_max (<= 1 for BMC_WIDTH_REL).  Defaults: 1e-3, 1e-2, 1.25, 1e-4, 0.2. */
+  int width_adapt;
+  double width_lo, width_hi, width_factor, width_min, width_max;
 } bmc_process_params;
 
 /* Options of one evaluation. */
@@ -163,6 +176,12 @@ int bmc_default_process_params(bmc_process_params* params);
 /* Changes the coupling lambda of a process (|M|^2 = lambda^2). */
 int bmc_set_coupling(bmc_ctx* ctx, int process, double coupling);
 
+/* The current width parameter of a process (sigma_E, or w for BMC_WIDTH_REL): the registered value until the width
+ * controller changes it on the device.  bmc_set_width replaces it (> 0; <= 1 for a relative width); either call
+ * synchronises the context's stream when a workspace is bound. */
+int bmc_get_width(bmc_ctx* ctx, int process, double* width);
+int bmc_set_width(bmc_ctx* ctx, int process, double width);
+
 /* Expansion (Sec. III.E): BMC_EXP_NONE (a = 1) or BMC_EXP_RADIATION with a0, t0 > 0. */
 int bmc_set_expansion(bmc_ctx* ctx, int kind, double a0, double t0);
 int bmc_set_time(bmc_ctx* ctx, double t);
@@ -200,9 +219,10 @@ int bmc_maps_reset(bmc_ctx* ctx, int process);
  * bmc_state_size gives the bytes bmc_state_get writes into the caller's buffer (synchronises the stream).
  * bmc_state_set restores a blob into a context with the same species grids and processes (checked: a blob of
  * another model, an invalid f or a map of an unknown work item is rejected with nothing changed); the masses,
- * couplings and expansion are the context's own.  Layout: a 48-byte header (magic "BMCS", version 1, species
- * count, map count, number of f values, t, epoch, next epoch, doubles per map), the f values (FP64, species
- * concatenated), then per map its uid (as a 64-bit word) and its edges (12 x 65 doubles, unused rows zero). */
+ * couplings and expansion are the context's own.  Layout: a 48-byte header (magic "BMCS", version 2, species
+ * count, map count, number of f values, t, epoch, next epoch, doubles per map, process count), the f values
+ * (FP64, species concatenated), the current width parameter of every process (FP64), then per map its uid (as a
+ * 64-bit word) and its edges (12 x 65 doubles, unused rows zero). */
 int bmc_state_size(bmc_ctx* ctx, size_t* bytes);
 int bmc_state_get(bmc_ctx* ctx, void* blob, size_t bytes);
 int bmc_state_set(bmc_ctx* ctx, const void* blob, size_t bytes);

@@ -36,7 +36,9 @@ class Species(C.Structure):
 class Process(C.Structure):
     _fields_ = [("n_in", C.c_int), ("n_out", C.c_int), ("sp", C.c_int * 6), ("coupling", C.c_double),
                 ("sigma_E", C.c_double), ("alpha", C.c_double), ("e_cut", C.c_double), ("n_bins", C.c_int),
-                ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int)]
+                ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int), ("width_mode", C.c_int),
+                ("width_adapt", C.c_int), ("width_lo", C.c_double), ("width_hi", C.c_double),
+                ("width_factor", C.c_double), ("width_min", C.c_double), ("width_max", C.c_double)]
 
 
 class World(C.Structure):
@@ -76,6 +78,10 @@ def lib():
         L.orc_stat_factor.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_stat_factor.restype = C.c_double
         L.orc_integrand_batch.argtypes = [C.POINTER(World), C.POINTER(Item), C.c_int64, dp, dp]
+        L.orc_point_width.argtypes = [C.POINTER(Process), C.c_int, dp]
+        L.orc_point_width.restype = C.c_double
+        L.orc_width_control.argtypes = [C.POINTER(Process), C.c_int, dp, dp, C.c_double]
+        L.orc_width_control.restype = C.c_double
         L.orc_side_multiplicity.argtypes = [C.POINTER(Process), C.c_int, C.c_int]
         L.orc_roles.argtypes = [C.POINTER(Process), C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                 C.POINTER(C.c_int)]
@@ -135,7 +141,8 @@ class OracleWorld:
         for i, p in enumerate(w.processes):
             sp = (C.c_int * 6)(*(list(p.ins) + list(p.outs) + [0] * (6 - len(p.ins) - len(p.outs))))
             self.pr[i] = Process(len(p.ins), len(p.outs), sp, p.coupling, p.sigma_E, p.alpha, p.e_cut, p.n_bins,
-                                 p.term_mode, p.side_mask, p.eval_stride)
+                                 p.term_mode, p.side_mask, p.eval_stride, p.width_mode, p.width_adapt, p.width_lo,
+                                 p.width_hi, p.width_factor, p.width_min, p.width_max)
         self.world = World(len(w.species), self.sp, len(w.processes), self.pr, w.t, w.expansion, w.a0, w.t0)
         self._maps = None
 
@@ -197,6 +204,20 @@ class OracleWorld:
         arr = (Item * max(1, n))()
         lib().orc_list_items_at(C.byref(self.world), proc, species, _dp(q), len(q), arr, n)
         return arr, n
+
+    def width_control(self, items, n_items, Ibar, sigma, proc):
+        """The width of process proc after an evaluation with these item results (Appendix C controller); the
+        oracle's process record is updated and the new width returned."""
+        sel = [i for i in range(n_items) if items[i].proc == proc]
+        Ib = np.ascontiguousarray(np.asarray(Ibar, dtype=np.float64)[sel])
+        sg = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64)[sel])
+        w = lib().orc_width_control(C.byref(self.pr[proc]), len(sel), _dp(Ib), _dp(sg), self.pr[proc].sigma_E)
+        self.pr[proc].sigma_E = w
+        return w
+
+    def point_width(self, proc, E):
+        E = np.ascontiguousarray(E, dtype=np.float64)
+        return lib().orc_point_width(C.byref(self.pr[proc]), len(E), _dp(E))
 
     def combine_at(self, items, n_items, Ibar, sigma, n_q):
         """C and sigma at the evaluation points of items_at: C = sum mult sign Ibar, sigma^2 = sum mult^2 sigma^2

@@ -433,10 +433,39 @@ static int item_setup(item_ctx* c, const orc_world* w, const orc_item* it, doubl
  *   gain = prod_{opposite side} f * prod_{observed side} (1 + eta f)
  *   loss = prod_{observed side} f * prod_{opposite side} (1 + eta f)       (Sec. II.C, the C_2 / C_3 lists)
  * Points with any E_i below the cut get weight 0 (Appendix A). */
+/* Width of the Gaussian energy delta at one point (Eq. 15; Appendix C): the given sigma_E, or with a relative
+ * width, sigma_E = w (E_in + E_out) / 2 where E_in and E_out are the summed initial and final energies. */
+double orc_point_width(const orc_process* P, int n, const double* E) {
+  if (P->width_mode != ORC_WIDTH_REL) return P->sigma_E;
+  double sum = 0.0;
+  for (int i = 0; i < n; ++i) sum += E[i];
+  return P->sigma_E * 0.5 * sum;
+}
+
+/* The width controller of Appendix C.  The relative Monte Carlo error of an evaluation is read as
+ * sum_i sigma_i / sum_i |Ibar_i| over the process's items (the error relative to the gross rate, so that the
+ * tiny items at the ends of the grid do not dominate).  Below width_lo the width narrows (w / width_factor),
+ * above width_hi it widens (w width_factor), clamped to [width_min, width_max]. */
+double orc_width_control(const orc_process* P, int n, const double* Ibar, const double* sigma, double w) {
+  if (!P->width_adapt || n <= 0) return w;
+  double se = 0.0, si = 0.0;
+  for (int i = 0; i < n; ++i) {
+    se += sigma[i];
+    si += fabs(Ibar[i]);
+  }
+  if (!(si > 0.0)) return w;
+  const double r = se / si;
+  if (r < P->width_lo) w /= P->width_factor;
+  else if (r > P->width_hi) w *= P->width_factor;
+  if (w < P->width_min) w = P->width_min;
+  if (w > P->width_max) w = P->width_max;
+  return w;
+}
+
 static double item_integrand(const item_ctx* c, const double* x) {
   const int n = c->n, n_in = c->n_in;
   const double a = c->a;
-  double px[ORC_MAXN], py[ORC_MAXN], pz[ORC_MAXN], E[ORC_MAXN], f[ORC_MAXN] = {0};
+  double px[ORC_MAXN], py[ORC_MAXN], pz[ORC_MAXN], E[ORC_MAXN] = {0}, f[ORC_MAXN] = {0};
   double jac = 1.0;
   /* observed particle on the z axis, physical momentum q/a */
   px[c->i_obs] = 0.0;
@@ -480,7 +509,7 @@ static double item_integrand(const item_ctx* c, const double* x) {
   }
   double dE = 0.0;
   for (int i = 0; i < n; ++i) dE += (i < n_in) ? E[i] : -E[i];
-  const double sig = c->P->sigma_E;
+  const double sig = orc_point_width(c->P, n, E);
   double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
   /* distribution values */
   for (int i = 0; i < n; ++i) {
@@ -836,7 +865,7 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
   int rc = item_setup(&c, w, it, w->t, fits);
   if (rc) return rc;
   const int n = c.n, n_in = c.n_in, D = 3 * c.n_int, nb = c.P->n_bins;
-  const double a = c.a, sig = c.P->sigma_E;
+  const double a = c.a;
   const double cN = coef / (double)N;
   /* per-species accumulators of dW/da, dW/db for the low and high fits */
   double dfit[ORC_MAXSPECIES][4];
@@ -899,6 +928,7 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
     if (cut) continue;
     double dE = 0.0;
     for (int i = 0; i < n; ++i) dE += (i < n_in) ? E[i] : -E[i];
+    const double sig = orc_point_width(c.P, n, E);
     double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
     /* f values and where they come from */
     int src[ORC_MAXN], node[ORC_MAXN], eside[ORC_MAXN];
@@ -985,6 +1015,8 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
     /* mass: energies of every particle, and the extrapolated f's energy dependence */
     for (int i = 0; i < n; ++i) {
       double dWdE = W * (-dE / (sig * sig) * ((i < n_in) ? 1.0 : -1.0) - 1.0 / E[i]);
+      /* a relative width grows with every energy: d sigma / d E_i = w / 2 */
+      if (c.P->width_mode == ORC_WIDTH_REL) dWdE += W * (dE * dE / (sig * sig) - 1.0) / sig * (0.5 * c.P->sigma_E);
       if (src[i] == 2) {
         double b = c.fit[i][2 * eside[i] + 1];
         dWdE += dWdf[i] * (-b * f[i] * (1.0 + c.eta[i] * f[i]));

@@ -36,6 +36,9 @@
 
 #define ORC_SIDES_AUTO 0    /* self-reverse -> initial side only; else both sides */
 
+#define ORC_WIDTH_ABS 0     /* sigma_E is the Gaussian's width (an energy) */
+#define ORC_WIDTH_REL 1     /* sigma_E is the fraction w: width w (E_in + E_out) / 2 per point (Appendix C) */
+
 #define ORC_EULER 0
 #define ORC_HEUN 1
 
@@ -52,13 +55,18 @@ typedef struct {
   int n_in, n_out;
   int sp[ORC_MAXN];         /* species of positions 0..n-1 (initial state first) */
   double coupling;          /* |M|^2 = coupling^2 */
-  double sigma_E;           /* absolute Gaussian width */
+  double sigma_E;           /* Gaussian width (ORC_WIDTH_ABS) or its fraction w of (E_in + E_out) / 2 (REL) */
   double alpha;             /* Vegas damping exponent */
   double e_cut;             /* energy cut */
   int n_bins;               /* Vegas bins per dimension */
   int term_mode;            /* ORC_TERMS_SPLIT (gain and loss items) or ORC_TERMS_NET */
   int side_mask;            /* ORC_SIDES_AUTO, or bit 0 = initial side, bit 1 = final side */
   int eval_stride;          /* evaluate every k-th grid point of the observed species */
+  int width_mode;           /* ORC_WIDTH_ABS or ORC_WIDTH_REL */
+  /* width controller (Appendix C): after an evaluation, narrow the width by width_factor when the relative Monte
+   * Carlo error is below width_lo, widen it when above width_hi, within [width_min, width_max] */
+  int width_adapt;
+  double width_lo, width_hi, width_factor, width_min, width_max;
 } orc_process;
 
 typedef struct {
@@ -112,6 +120,11 @@ void orc_combine(const orc_world* w, int n_items, const orc_item* items, const d
                  int species, double* C, double* sigma);
 int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, uint32_t epoch, int adapt,
                       double* maps, double* C_all, double* sig_all, int n_threads);
+/* Gaussian width of one point with energies E[0..n-1]: sigma_E, or w (E_in + E_out) / 2 for ORC_WIDTH_REL. */
+double orc_point_width(const orc_process* P, int n, const double* E);
+/* The width controller: the width after an evaluation whose items of process P had estimates Ibar[i] and Monte
+ * Carlo errors sigma[i] (i < n), starting from width w. */
+double orc_width_control(const orc_process* P, int n, const double* Ibar, const double* sigma, double w);
 int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int iter, uint64_t seed,
                  uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_m,
                  double* grad_lam);

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libboltzmc.so")
 OK, EINVAL, ESTATE, ERANGE, ENOMEM, EHIP, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 FP64, FP32I = 0, 1
+WIDTH_ABS, WIDTH_REL = 0, 1
 LAUNCH_BATCHED, LAUNCH_PLAIN = 0, 1
 EULER, HEUN = 0, 1
 MAXD, MAXITER = 12, 64
@@ -28,7 +29,9 @@ MAXD, MAXITER = 12, 64
 class ProcessParams(C.Structure):
     _fields_ = [("coupling", C.c_double), ("sigma_E", C.c_double), ("alpha", C.c_double), ("e_cut", C.c_double),
                 ("n_bins", C.c_int), ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int),
-                ("n_samples", C.c_int64), ("n_iter", C.c_int)]
+                ("n_samples", C.c_int64), ("n_iter", C.c_int), ("width_mode", C.c_int), ("width_adapt", C.c_int),
+                ("width_lo", C.c_double), ("width_hi", C.c_double), ("width_factor", C.c_double),
+                ("width_min", C.c_double), ("width_max", C.c_double)]
 
 
 class RunOpts(C.Structure):
@@ -60,6 +63,8 @@ _SIGS = {
                         C.POINTER(ProcessParams), C.POINTER(C.c_int)],
     "bmc_default_process_params": [C.POINTER(ProcessParams)],
     "bmc_set_coupling": [C.c_void_p, C.c_int, C.c_double],
+    "bmc_get_width": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
+    "bmc_set_width": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_expansion": [C.c_void_p, C.c_int, C.c_double, C.c_double],
     "bmc_set_time": [C.c_void_p, C.c_double],
     "bmc_get_time": [C.c_void_p, C.POINTER(C.c_double)],
@@ -214,6 +219,14 @@ class Context:
     def set_coupling(self, process, coupling):
         self._check(lib().bmc_set_coupling(self.h, process, coupling))
 
+    def get_width(self, process):
+        w = C.c_double()
+        self._check(lib().bmc_get_width(self.h, process, C.byref(w)))
+        return w.value
+
+    def set_width(self, process, width):
+        self._check(lib().bmc_set_width(self.h, process, width))
+
     def set_expansion(self, kind, a0=1.0, t0=1.0):
         self._check(lib().bmc_set_expansion(self.h, kind, a0, t0))
 
@@ -325,7 +338,8 @@ class Context:
         return ms.value, n.value
 
     def state_get(self) -> bytes:
-        """Checkpoint: f of every species, the time and epochs, and every Vegas map, as one byte string."""
+        """Checkpoint: f of every species, the time and epochs, every process's width and every Vegas map, as one
+        byte string."""
         self.ensure_workspace()
         n = C.c_size_t()
         self._check(lib().bmc_state_size(self.h, C.byref(n)))
@@ -376,7 +390,9 @@ def from_workload(w: wl.Workload, device: int = 0, stream=None) -> Context:
     for p in w.processes:
         ctx.add_process(p.ins, p.outs, coupling=p.coupling, sigma_E=p.sigma_E, alpha=p.alpha, e_cut=p.e_cut,
                         n_bins=p.n_bins, term_mode=p.term_mode, side_mask=p.side_mask, eval_stride=p.eval_stride,
-                        n_samples=p.n_samples, n_iter=p.n_iter)
+                        n_samples=p.n_samples, n_iter=p.n_iter, width_mode=p.width_mode, width_adapt=p.width_adapt,
+                        width_lo=p.width_lo, width_hi=p.width_hi, width_factor=p.width_factor,
+                        width_min=p.width_min, width_max=p.width_max)
     if w.expansion:
         ctx.set_expansion(w.expansion, w.a0, w.t0)
     ctx.ensure_workspace()

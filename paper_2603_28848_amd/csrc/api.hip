@@ -51,6 +51,7 @@ struct Process {
   int n_in = 0, n_out = 0;
   int sp[kMaxN] = {0};
   bmc_process_params prm{};
+  double width = 0.0;  // host mirror of the current width parameter (the device copy is authoritative while bound)
 };
 
 struct Plan {
@@ -132,7 +133,7 @@ struct bmc_ctx {
   size_t ws_bytes = 0;
   bool bound = false;
   size_t off_state = 0, off_spec = 0, off_f64 = 0, off_f32 = 0, off_f0 = 0, off_k1 = 0, off_k2 = 0, off_sig = 0,
-         off_qnode = 0, off_maps = 0, persist_bytes = 0;
+         off_qnode = 0, off_maps = 0, off_wctl = 0, persist_bytes = 0;
   int64_t n_f = 0;
   int max_slots = 0;
   int n_sp_bound = -1, n_pr_bound = -1;
@@ -157,6 +158,7 @@ struct bmc_ctx {
 
   DevState* st() { return reinterpret_cast<DevState*>(ws + off_state); }
   SpecDev* spec() { return reinterpret_cast<SpecDev*>(ws + off_spec); }
+  WidthCtl* wctl() { return reinterpret_cast<WidthCtl*>(ws + off_wctl); }
   double* f64() { return reinterpret_cast<double*>(ws + off_f64); }
   float* f32() { return reinterpret_cast<float*>(ws + off_f32); }
   double* f0() { return reinterpret_cast<double*>(ws + off_f0); }
@@ -254,6 +256,8 @@ void layout_persistent(bmc_ctx* c) {
   o = align_up(o + sizeof(DevState));
   c->off_spec = o;
   o = align_up(o + sizeof(SpecDev) * kMaxSpecies);
+  c->off_wctl = o;
+  o = align_up(o + sizeof(WidthCtl) * std::max<size_t>(1, c->pr.size()));
   int64_t nf = 0;
   for (auto& s : c->sp) {
     s.f_off = nf;
@@ -312,6 +316,12 @@ int upload_model(bmc_ctx* c) {
     for (int j = 0; j < c->sp[i].n; ++j) qn.push_back(grid_node(c->sp[i], j));
   }
   HIPCHK(c, hipMemcpyAsync(c->spec(), sd.data(), sizeof(SpecDev) * kMaxSpecies, hipMemcpyHostToDevice, c->stream));
+  std::vector<WidthCtl> wc(std::max<size_t>(1, c->pr.size()));
+  for (size_t p = 0; p < c->pr.size(); ++p) {
+    const bmc_process_params& q = c->pr[p].prm;
+    wc[p] = WidthCtl{q.width_adapt, q.width_lo, q.width_hi, q.width_factor, q.width_min, q.width_max};
+  }
+  HIPCHK(c, hipMemcpyAsync(c->wctl(), wc.data(), sizeof(WidthCtl) * wc.size(), hipMemcpyHostToDevice, c->stream));
   if (!qn.empty())
     HIPCHK(c, hipMemcpyAsync(c->qnode(), qn.data(), 8 * qn.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -329,6 +339,7 @@ int upload_state(bmc_ctx* c) {
   s.expansion_t0 = c->t0;
   s.n_species = (int)c->sp.size();
   for (size_t i = 0; i < c->sp.size(); ++i) s.m[i] = c->sp[i].m0;
+  for (size_t p = 0; p < c->pr.size(); ++p) s.width[p] = c->pr[p].width;
   HIPCHK(c, hipMemcpyAsync(c->st(), &s, sizeof(s), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BMC_OK;
@@ -338,6 +349,12 @@ int read_state(bmc_ctx* c, DevState* s) {
   HIPCHK(c, hipMemcpyAsync(s, c->st(), sizeof(DevState), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return BMC_OK;
+}
+
+// Host mirrors of the device-side time and widths (before the device state is rebuilt).
+void mirror_state(bmc_ctx* c, const DevState& s) {
+  c->t = s.t;
+  for (int p = 0; p < c->n_pr_bound && p < (int)c->pr.size(); ++p) c->pr[p].width = s.width[p];
 }
 
 int check_ready(bmc_ctx* c) {
@@ -440,10 +457,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
-            it.inv2s2 = 1.0 / (2.0 * Pr.prm.sigma_E * Pr.prm.sigma_E);
-            it.shell = 12.0 * Pr.prm.sigma_E;
-            it.far = std::sqrt(2.0 * 746.0) * Pr.prm.sigma_E;
-            it.dnorm = 1.0 / (Pr.prm.sigma_E * std::sqrt(2.0 * M_PI));
+            it.rel = Pr.prm.width_mode == BMC_WIDTH_REL ? 1 : 0;
             it.e_cut = Pr.prm.e_cut;
             it.twopi_pow = std::pow(2.0 * M_PI, (double)(3 * (n - 1) - 4));
             it.alpha = Pr.prm.alpha;
@@ -874,6 +888,11 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
                            P.d_item_sig, P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));
   HIPCHK(c, launch_gather(P.d_gather, P.n_out, P.d_gproc, P.d_slot_C, P.d_slot_S2, c->spec(), c->f64(), out_C, out_S,
                           s));
+  bool adapt = false;
+  for (auto& pr : c->pr) adapt |= pr.prm.width_adapt != 0;
+  if (adapt)
+    HIPCHK(c, launch_width_control(P.d_items, (int)P.items.size(), P.d_item_Ibar, P.d_item_sig, c->wctl(),
+                                   (int)c->pr.size(), c->st(), s));
   return BMC_OK;
 }
 
@@ -972,6 +991,13 @@ int bmc_default_process_params(bmc_process_params* p) {
   p->eval_stride = 1;
   p->n_samples = 1000000;
   p->n_iter = 2;
+  p->width_mode = BMC_WIDTH_ABS;
+  p->width_adapt = 0;
+  p->width_lo = 1e-3;
+  p->width_hi = 1e-2;
+  p->width_factor = 1.25;
+  p->width_min = 1e-4;
+  p->width_max = 0.2;
   return BMC_OK;
 }
 
@@ -1059,7 +1085,7 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
   if (!c || !in_sp || !out_sp || !prm) return BMC_EINVAL;
   if (n_in < 1 || n_out < 1 || n_in + n_out < 3 || n_in + n_out > kMaxN)
     return fail(c, BMC_EINVAL, "need 1 <= n_in, n_out and 3 <= n_in + n_out <= 6");
-  if ((int)c->pr.size() >= 255) return fail(c, BMC_EINVAL, "too many processes");
+  if ((int)c->pr.size() >= kMaxProc - 1) return fail(c, BMC_EINVAL, "too many processes");
   Process P;
   P.n_in = n_in;
   P.n_out = n_out;
@@ -1072,7 +1098,18 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
       (q.term_mode != BMC_TERMS_SPLIT && q.term_mode != BMC_TERMS_NET) || q.side_mask < 0 || q.side_mask > 3 ||
       q.eval_stride < 1 || q.n_samples < 2 || q.n_iter < 1 || q.n_iter > kMaxIter || !std::isfinite(q.coupling))
     return fail(c, BMC_EINVAL, "bad process parameters");
+  if (q.width_mode != BMC_WIDTH_ABS && q.width_mode != BMC_WIDTH_REL)
+    return fail(c, BMC_EINVAL, "bad width_mode");
+  // a relative width stays <= 1: the screening pass's energy margins assume it
+  if (q.width_mode == BMC_WIDTH_REL && !(q.sigma_E <= 1.0)) return fail(c, BMC_EINVAL, "relative width above 1");
+  if (q.width_adapt != 0 && q.width_adapt != 1) return fail(c, BMC_EINVAL, "width_adapt must be 0 or 1");
+  if (q.width_adapt &&
+      (!(q.width_lo > 0.0) || !(q.width_hi > q.width_lo) || !std::isfinite(q.width_hi) || !(q.width_factor > 1.0) ||
+       !std::isfinite(q.width_factor) || !(q.width_min > 0.0) || !(q.width_max >= q.width_min) ||
+       !std::isfinite(q.width_max) || (q.width_mode == BMC_WIDTH_REL && q.width_max > 1.0)))
+    return fail(c, BMC_EINVAL, "bad width controller parameters");
   P.prm = q;
+  P.width = q.sigma_E;
   c->pr.push_back(P);
   if (process_id) *process_id = (int)c->pr.size() - 1;
   return BMC_OK;
@@ -1088,6 +1125,32 @@ int bmc_set_coupling(bmc_ctx* c, int process, double coupling) {
   return BMC_OK;
 }
 
+int bmc_get_width(bmc_ctx* c, int process, double* width) {
+  if (!c || !width) return BMC_EINVAL;
+  if (process < 0 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
+  if (c->bound && process < c->n_pr_bound) {
+    DevState s;
+    int rc = read_state(c, &s);
+    if (rc) return rc;
+    c->pr[process].width = s.width[process];
+  }
+  *width = c->pr[process].width;
+  return BMC_OK;
+}
+
+int bmc_set_width(bmc_ctx* c, int process, double width) {
+  if (!c) return BMC_EINVAL;
+  if (process < 0 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
+  if (!(width > 0.0) || !std::isfinite(width) || (c->pr[process].prm.width_mode == BMC_WIDTH_REL && width > 1.0))
+    return fail(c, BMC_EINVAL, "width must be > 0 (and <= 1 for a relative width)");
+  c->pr[process].width = width;
+  if (c->bound && process < c->n_pr_bound) {
+    HIPCHK(c, hipMemcpyAsync(&c->st()->width[process], &width, sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return BMC_OK;
+}
+
 int bmc_set_expansion(bmc_ctx* c, int kind, double a0, double t0) {
   if (!c) return BMC_EINVAL;
   if (kind != BMC_EXP_NONE && kind != BMC_EXP_RADIATION) return fail(c, BMC_EINVAL, "bad expansion kind");
@@ -1099,7 +1162,7 @@ int bmc_set_expansion(bmc_ctx* c, int kind, double a0, double t0) {
     DevState s;
     int rc = read_state(c, &s);
     if (rc) return rc;
-    c->t = s.t;
+    mirror_state(c, s);
     return upload_state(c);
   }
   return BMC_OK;
@@ -1153,7 +1216,7 @@ int bmc_workspace_bind(bmc_ctx* c, void* dev_ptr, size_t bytes) {
     DevState s;
     int rc = read_state(c, &s);
     if (rc) return rc;
-    c->t = s.t;
+    mirror_state(c, s);
     for (int a = 0; a < c->n_sp_bound; ++a) {
       HIPCHK(c, hipMemcpy(c->sp[a].f.data(), c->f64() + c->sp[a].f_off, 8 * c->sp[a].n, hipMemcpyDeviceToHost));
     }
@@ -1328,15 +1391,16 @@ int bmc_maps_set(bmc_ctx* c, const uint32_t* uids, int n, const double* maps) {
 
 namespace {
 constexpr uint32_t kStateMagic = 0x53434d42u;  // "BMCS"
-constexpr uint32_t kStateVersion = 1;
+constexpr uint32_t kStateVersion = 2;
 struct StateHeader {
   uint32_t magic, version, n_species, n_maps;
   int64_t n_f;
   double t;
-  uint32_t epoch, next_epoch, slot_doubles, reserved;
+  uint32_t epoch, next_epoch, slot_doubles, n_proc;
 };
 size_t state_bytes(const bmc_ctx* c) {
-  return sizeof(StateHeader) + 8 * (size_t)c->n_f + c->slot_of_uid.size() * (8 + 8 * (size_t)kSlotDoubles);
+  return sizeof(StateHeader) + 8 * (size_t)c->n_f + 8 * c->pr.size() +
+         c->slot_of_uid.size() * (8 + 8 * (size_t)kSlotDoubles);
 }
 }  // namespace
 
@@ -1356,11 +1420,13 @@ int bmc_state_get(bmc_ctx* c, void* blob, size_t bytes) {
   if (rc) return rc;
   char* p = static_cast<char*>(blob);
   StateHeader h{kStateMagic, kStateVersion, (uint32_t)c->sp.size(), (uint32_t)c->slot_of_uid.size(), c->n_f, s.t,
-                s.epoch, s.next_epoch, (uint32_t)kSlotDoubles, 0u};
+                s.epoch, s.next_epoch, (uint32_t)kSlotDoubles, (uint32_t)c->pr.size()};
   std::memcpy(p, &h, sizeof(h));
   p += sizeof(h);
   HIPCHK(c, hipMemcpy(p, c->f64(), 8 * (size_t)c->n_f, hipMemcpyDeviceToHost));
   p += 8 * (size_t)c->n_f;
+  std::memcpy(p, s.width, 8 * c->pr.size());
+  p += 8 * c->pr.size();
   std::vector<std::pair<uint32_t, int>> slots(c->slot_of_uid.begin(), c->slot_of_uid.end());
   std::sort(slots.begin(), slots.end());
   for (auto& us : slots) {
@@ -1381,9 +1447,10 @@ int bmc_state_set(bmc_ctx* c, const void* blob, size_t bytes) {
   StateHeader h;
   std::memcpy(&h, blob, sizeof(h));
   if (h.magic != kStateMagic || h.version != kStateVersion) return fail(c, BMC_EINVAL, "not a state blob");
-  if (h.n_species != c->sp.size() || h.n_f != c->n_f || h.slot_doubles != (uint32_t)kSlotDoubles)
+  if (h.n_species != c->sp.size() || h.n_f != c->n_f || h.slot_doubles != (uint32_t)kSlotDoubles ||
+      h.n_proc != c->pr.size())
     return fail(c, BMC_EINVAL, "the state blob belongs to a different model");
-  if (bytes < sizeof(h) + 8 * (size_t)h.n_f + (size_t)h.n_maps * (8 + 8 * (size_t)kSlotDoubles))
+  if (bytes < sizeof(h) + 8 * (size_t)h.n_f + 8 * (size_t)h.n_proc + (size_t)h.n_maps * (8 + 8 * (size_t)kSlotDoubles))
     return fail(c, BMC_EINVAL, "state blob too short");
   if (!std::isfinite(h.t)) return fail(c, BMC_EINVAL, "non-finite time in the state blob");
   const char* p = static_cast<const char*>(blob) + sizeof(h);
@@ -1397,6 +1464,13 @@ int bmc_state_set(bmc_ctx* c, const void* blob, size_t bytes) {
       if (!(v > 0.0) || !std::isfinite(v)) return fail(c, BMC_ERANGE, "f must be positive and finite");
       if (S.stat == BMC_FERMI && !(v < 1.0)) return fail(c, BMC_ERANGE, "Fermi-Dirac f must be below 1");
     }
+  std::vector<double> widths(h.n_proc);
+  std::memcpy(widths.data(), p, 8 * widths.size());
+  p += 8 * widths.size();
+  for (size_t q = 0; q < widths.size(); ++q)
+    if (!(widths[q] > 0.0) || !std::isfinite(widths[q]) ||
+        (c->pr[q].prm.width_mode == BMC_WIDTH_REL && widths[q] > 1.0))
+      return fail(c, BMC_EINVAL, "invalid width in the state blob");
   std::vector<uint32_t> uids(h.n_maps);
   const char* pm = p;
   size_t new_slots = 0;
@@ -1406,7 +1480,9 @@ int bmc_state_set(bmc_ctx* c, const void* blob, size_t bytes) {
     const uint32_t uid = (uint32_t)u;
     const int pr = (int)(uid >> 24), a = (int)((uid >> 20) & 15), side = (int)((uid >> 19) & 1);
     const int node = (int)(uid & ((1u << 18) - 1));
-    if (u >> 32 || pr >= (int)c->pr.size() || a >= (int)c->sp.size() || node >= c->sp[a].n ||
+    const bool node_ok = node < c->sp[a < (int)c->sp.size() ? a : 0].n ||
+                         (node >= (int)kCustomBase && node < (int)kCustomBase + kMaxEvalPoints);
+    if (u >> 32 || pr >= (int)c->pr.size() || a >= (int)c->sp.size() || !node_ok ||
         multiplicity(c->pr[pr], a, side) == 0)
       return fail(c, BMC_EINVAL, "a map in the state blob does not name a work item of this model");
     uids[i] = uid;
@@ -1432,6 +1508,8 @@ int bmc_state_set(bmc_ctx* c, const void* blob, size_t bytes) {
   }
   c->t = h.t;
   DevState* st = c->st();
+  for (size_t q = 0; q < widths.size(); ++q) c->pr[q].width = widths[q];
+  if (!widths.empty()) HIPCHK(c, hipMemcpy(st->width, widths.data(), 8 * widths.size(), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(&st->t, &h.t, sizeof(double), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(&st->epoch, &h.epoch, sizeof(uint32_t), hipMemcpyHostToDevice));
   HIPCHK(c, hipMemcpy(&st->next_epoch, &h.next_epoch, sizeof(uint32_t), hipMemcpyHostToDevice));

@@ -15,6 +15,7 @@ constexpr int kMaxIter = 64;
 constexpr int kBlock = 256;       // threads per sample block; part of the fixed summation order
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxTab = 4;        // distinct f tables one item reads (non-observed particles)
+constexpr int kMaxProc = 256;     // processes per context (ids 0..254; the identifier keeps 8 bits)
 
 // Species as the kernels see it: logarithmic grid q_j = exp(lq0 + h j), j = 0..n-1.
 struct SpecDev {
@@ -44,6 +45,14 @@ struct DevState {
   double expansion_a0, expansion_t0;
   int expansion;
   int n_species;
+  double width[kMaxProc];  // current width parameter per process: sigma_E, or the fraction w of a relative width
+};
+
+// The width controller of one process (Appendix C): after an evaluation whose relative Monte Carlo error is r,
+// the width is divided by `factor` if r < lo, multiplied by it if r > hi, and clamped to [wmin, wmax].
+struct WidthCtl {
+  int adapt;
+  double lo, hi, factor, wmin, wmax;
 };
 
 // One work item.  Roles are stored by role, not by position: integrated k = 0..nint-1, then the
@@ -74,10 +83,7 @@ struct ItemRec {
   int out_slot;      // output slot of the item's evaluation point (combine)
   int sign;          // +1 gain / net, -1 loss
   double coupling2;
-  double inv2s2;     // 1 / (2 sigma_E^2)
-  double shell;      // FP32 screening half-width of the energy shell, 12 sigma_E
-  double far;        // FP32 screening: |dE| beyond which the Gaussian factor underflows in FP64 (e^-746)
-  double dnorm;      // 1 / (sigma_E sqrt(2 pi))
+  int rel;           // 1: the Gaussian's width at a point is w (E_in + E_out) / 2, w = DevState::width[proc]
   double e_cut;
   double twopi_pow;  // (2 pi)^(3(n-1)-4)
   double alpha;

@@ -62,6 +62,11 @@ hipError_t launch_combine(const ItemRec* items, int n_items, const double* res_I
                           double* item_Ibar, double* item_sig, const int* slot_begin, const int* slot_items,
                           int n_slots, double* slot_C, double* slot_S2, hipStream_t s);
 
+// Width controller after an evaluation (processes with adapt set): r = sum sigma / sum |Ibar| over the process's
+// items in item order; the process's width in st->width is divided or multiplied by the factor and clamped.
+hipError_t launch_width_control(const ItemRec* items, int n_items, const double* item_Ibar, const double* item_sig,
+                                const WidthCtl* ctl, int n_proc, DevState* st, hipStream_t s);
+
 // Output gather: out[o] for output node o of the plan, from the slot sums (stride-override or fill rule).
 struct GatherEntry {
   int species;    // species of the output node

@@ -191,9 +191,14 @@ struct ItemConsts {
   const float2* m32;  // LDS map (edge, width) pairs in FP32 (screening pass)
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
-  float ylog2;   // log2(e) / (2 sigma_E^2)
-  float far;     // |dE| of the FP64 underflow of the Gaussian factor
-  float wconst;  // a^-3n |M|^2 / ((2 pi)^(3(n-1)-4) sigma_E sqrt(2 pi))
+  float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
+  float shell;   // 12 sigma_E (absolute width)
+  float far;     // |dE| of the FP64 underflow of the Gaussian factor, sqrt(2 746) sigma_E (absolute width)
+  float cin, cfar;  // per unit of the summed energies: the FP32 margin, plus 6 w and sqrt(2 746) w / 2 (relative)
+  float wconst;  // a^-3n |M|^2 / ((2 pi)^(3(n-1)-4) sqrt(2 pi)), divided by sigma_E for an absolute width
+  float whalf32;
+  int rel;       // relative width: sigma_E = whalf (sum of the point's energies)
+  double whalf;
   double a, inv_a, m2[NR], eta[NR], esg[NR];
   int obsside[NR];
   double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
@@ -230,7 +235,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   double J = 1.0, jac = 1.0;
   double sx = 0.0, sy = 0.0, sz = K.esg[NI + 1] * K.p_obs;  // sum_in - sum_out over all but the conserved
   double dE = K.esg[NI + 1] * K.E_obs;
-  double prod2E = 2.0 * K.E_obs;
+  double prod2E = 2.0 * K.E_obs, sumE = K.E_obs;
   bool cut = K.E_obs < K.e_cut;
   FT gain = (FT)K.g_obs, loss = (FT)K.l_obs;
 #pragma unroll
@@ -261,6 +266,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     cut |= E < K.e_cut;
     dE += K.esg[k] * E;
     prod2E *= 2.0 * E;
+    sumE += E;
     FT f;
     if constexpr (std::is_same<FT, double>::value) {
       int jj;
@@ -279,6 +285,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   cut |= Ec < K.e_cut;
   dE += K.esg[NI] * Ec;
   prod2E *= 2.0 * Ec;
+  sumE += Ec;
   const double qc = K.a * sqrt(P2);
   FT fc;
   if constexpr (std::is_same<FT, double>::value) {
@@ -306,12 +313,18 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     loss *= K.obsside[NI] ? fc : bf;
   }
   const FT F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
+  double inv2s2 = K.inv2s2, dnorm = K.dnorm;
+  if (K.rel) {
+    const double sg = K.whalf * sumE;
+    inv2s2 = 0.5 / (sg * sg);
+    dnorm = 0.3989422804014327 / sg;
+  }
   double W;
   if constexpr (std::is_same<FT, double>::value) {
-    const double delta = exp(-dE * dE * K.inv2s2) * K.dnorm;
+    const double delta = exp(-dE * dE * inv2s2) * dnorm;
     W = J * (jac * K.a3M2 * delta / (K.twopi_pow * prod2E) * (double)F);
   } else {
-    const float delta = exp_split(-dE * dE * K.inv2s2) * (float)K.dnorm;
+    const float delta = exp_split(-dE * dE * inv2s2) * (float)dnorm;
     const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
     W = J * jac * (K.a3M2 / K.twopi_pow) * ((double)delta * (double)rcp) * (double)F;
   }
@@ -330,8 +343,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 constexpr int kFar = 0, kNear = 1, kInShell = 2;
 
 template <int NI, bool FINISH>
-__device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, float shell, int* hj,
-                                             double* Wout) {
+__device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, int* hj, double* Wout) {
   constexpr int D = 3 * NI;
   constexpr float kInv2Pi = 0.15915494309189535f;
   uint32_t wd[4 * ((D + 3) / 4)];
@@ -392,11 +404,17 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
   dE = fmaf((float)K.esg[NI], Ec, dE);
   sumE += Ec;
   prod2E *= 2.0f * Ec;
-  const float adE = fabsf(dE), margin = 1e-3f * sumE;
-  if (adE < shell + margin) return kInShell;
-  if (adE > K.far + margin) return kFar;
+  const float adE = fabsf(dE);
+  if (adE < fmaf(K.cin, sumE, K.shell)) return kInShell;
+  if (adE > fmaf(K.cfar, sumE, K.far)) return kFar;
   if constexpr (FINISH) {
-    const float y = -(dE * dE) * K.ylog2;
+    float ylog2 = K.ylog2, wconst = K.wconst;
+    if (K.rel) {
+      const float isg = __builtin_amdgcn_rcpf(K.whalf32 * sumE);
+      ylog2 = 0.72134752044448170f * isg * isg;
+      wconst *= isg;
+    }
+    const float y = -(dE * dE) * ylog2;
     const float qc = (float)K.a * __builtin_amdgcn_sqrtf(P2);
     float fc;
     if (qc < (float)K.qc_min) {
@@ -419,7 +437,7 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
     // F applied in FP64 (W itself can lie far below the FP32 range)
     // (y is rounded before it is split: a fused y - floor(y) could leave [0, 1) by up to half an ulp of y)
     const float e = floorf(y);
-    const float m = J * jac * K.wconst * __builtin_amdgcn_rcpf(prod2E) * __builtin_amdgcn_exp2f(__builtin_amdgcn_fractf(y));
+    const float m = J * jac * wconst * __builtin_amdgcn_rcpf(prod2E) * __builtin_amdgcn_exp2f(__builtin_amdgcn_fractf(y));
     cut |= Ec < (float)K.e_cut;
     *Wout = cut ? 0.0 : ldexp((double)m, (int)e) * (double)F;
   }
@@ -533,12 +551,35 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   for (int k = 0; k < 4; ++k) K.fit[k] = st->fit[it->r_species[NI]][k];
   K.qc_min = Sc.q_min;
   K.qc_max = Sc.q_max;
-  K.inv2s2 = it->inv2s2;
-  K.dnorm = it->dnorm;
   K.twopi_pow = it->twopi_pow;
-  K.ylog2 = (float)(1.4426950408889634 * it->inv2s2);
-  K.far = (float)it->far;
-  K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
+  {
+    // the Gaussian energy delta: an absolute width, or w (E_in + E_out) / 2 at each point
+    constexpr double kRs2pi = 0.3989422804014327, kFarK = 38.62641583165593;  // 1/sqrt(2 pi), sqrt(2 746)
+    const double wd = st->width[it->proc];
+    K.rel = it->rel;
+    if (it->rel) {
+      K.whalf = 0.5 * wd;
+      K.inv2s2 = 0.0;
+      K.dnorm = 0.0;
+      K.shell = 0.0f;
+      K.far = 0.0f;
+      K.cin = (float)(1e-3 + 6.0 * wd);
+      K.cfar = (float)(1e-3 + 0.5 * kFarK * wd);
+      K.ylog2 = 0.0f;
+      K.wconst = (float)(K.a3M2 / K.twopi_pow * kRs2pi);
+    } else {
+      K.whalf = 0.0;
+      K.inv2s2 = 1.0 / (2.0 * wd * wd);
+      K.dnorm = kRs2pi / wd;
+      K.shell = (float)(12.0 * wd);
+      K.far = (float)(kFarK * wd);
+      K.cin = 1e-3f;
+      K.cfar = 1e-3f;
+      K.ylog2 = (float)(1.4426950408889634 * K.inv2s2);
+      K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
+    }
+    K.whalf32 = (float)K.whalf;
+  }
   K.nb = nb;
   K.net = it->net;
   K.term = it->term;
@@ -637,7 +678,6 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
-  const float shell = (float)it->shell;
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t wlen = L.list_stride / kWaves;
   for (int t = t0; t < t1; ++t) {
@@ -656,7 +696,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
       if (n < n1) {
         int hj[D];
         double W;
-        cls = screen_sample<NI, false>(K, (uint64_t)n, shell, hj, &W);
+        cls = screen_sample<NI, false>(K, (uint64_t)n, hj, &W);
         if (cls == kFar) count_only<D>(hj, my_c);
       }
       const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
@@ -693,7 +733,6 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
   int* wtot = pre + kLists + 1;                          // per-wave totals of the scan
   const int lane = tid & 63;
   const int64_t wlen = L.list_stride / kWaves;
-  const float shell = (float)it->shell;
   for (int k = k0; k < k1; ++k) {
     const ShellTask sht = L.sh_tasks[L.sh_begin + k];
     if (k > k0) {
@@ -741,7 +780,7 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
             W = eval_sample<NI, double>(K, n, hj);
           } else {
             if (kind == 0) W = eval_sample<NI, float>(K, n, hj);
-            else screen_sample<NI, true>(K, n, shell, hj, &W);
+            else screen_sample<NI, true>(K, n, hj, &W);
           }
           accumulate<D>(W, hj, S1, S2, my_h, my_c);
         }
@@ -848,7 +887,8 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   const int64_t n0 = (int64_t)task.unit * it->unit_size;
   const int64_t n1 = min(n0 + (int64_t)it->unit_size, N);
   const double dnb = (double)nb;
-  const double sig2 = 1.0 / (2.0 * it->inv2s2);
+  const double wpar = st->width[it->proc];
+  const int rel = it->rel;
   const int wave = tid >> 6;
   double* my_g = sm_g + wave * TG;
   __syncthreads();
@@ -933,13 +973,18 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       src[NI] = 1;
     }
     if (cut) continue;
-    double dE = 0.0, prod2E = 1.0;
+    double dE = 0.0, prod2E = 1.0, sumE = 0.0;
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       dE += esg[r] * E[r];
       prod2E *= 2.0 * E[r];
+      sumE += E[r];
     }
-    const double delta = exp(-dE * dE * it->inv2s2) * it->dnorm;
+    // width of the Gaussian at this point; a relative one grows with every energy (d sigma / d E = w / 2)
+    const double sg = rel ? 0.5 * wpar * sumE : wpar;
+    const double sig2 = sg * sg;
+    const double delta = exp(-dE * dE * (0.5 / sig2)) * (0.3989422804014327 / sg);
+    const double dsig = rel ? (dE * dE / sig2 - 1.0) / sg * (0.5 * wpar) : 0.0;
     // factors and their derivatives
     double gv[2][NR], dg[2][NR];
 #pragma unroll
@@ -972,7 +1017,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const double dWdf = Wb * (it->net ? dF[0][r] - dF[1][r] : dF[it->term][r]);
-      double dWdE = W * (-dE / sig2 * esg[r] - 1.0 / E[r]);
+      double dWdE = W * (-dE / sig2 * esg[r] - 1.0 / E[r] + dsig);
       if (src[r] == 0) {
         g_obs += dWdf;
       } else if (src[r] == 1) {
@@ -1354,6 +1399,32 @@ __global__ void k_combine(const ItemRec* items, const double* res_I, const doubl
   slot_S2[k] = S2;
 }
 
+// One thread per process; the sums run over the items in plan order (the same order as the evaluation's item
+// results), so the decision depends on the results alone.
+__global__ void k_width_control(const ItemRec* items, int n_items, const double* item_Ibar, const double* item_sig,
+                                const WidthCtl* ctl, int n_proc, DevState* st) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n_proc) return;
+  const WidthCtl c = ctl[p];
+  if (!c.adapt) return;
+  double se = 0.0, si = 0.0;
+  int n = 0;
+  for (int i = 0; i < n_items; ++i) {
+    if (items[i].proc != p) continue;
+    se += item_sig[i];
+    si += fabs(item_Ibar[i]);
+    ++n;
+  }
+  if (n == 0 || !(si > 0.0)) return;
+  const double r = se / si;
+  double w = st->width[p];
+  if (r < c.lo) w /= c.factor;
+  else if (r > c.hi) w *= c.factor;
+  w = w < c.wmin ? c.wmin : w;
+  w = w > c.wmax ? c.wmax : w;
+  st->width[p] = w;
+}
+
 __global__ void k_gather(const GatherEntry* ge, int n_out, const GatherProc* gp, const double* slot_C,
                          const double* slot_S2, const SpecDev* spec, const double* f64, double* C_out,
                          double* sig_out) {
@@ -1619,6 +1690,14 @@ hipError_t launch_combine(const ItemRec* items, int n_items, const double* res_I
   if (n_slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine, dim3((n_slots + 255) / 256), dim3(256), 0, s, items, res_I, res_V, n_iter, item_Ibar,
                      item_sig, slot_begin, slot_items, n_slots, slot_C, slot_S2);
+  return hipGetLastError();
+}
+
+hipError_t launch_width_control(const ItemRec* items, int n_items, const double* item_Ibar, const double* item_sig,
+                                const WidthCtl* ctl, int n_proc, DevState* st, hipStream_t s) {
+  if (n_proc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_width_control, dim3((n_proc + 63) / 64), dim3(64), 0, s, items, n_items, item_Ibar, item_sig,
+                     ctl, n_proc, st);
   return hipGetLastError();
 }
 

@@ -23,6 +23,7 @@ MASS_CONST, MASS_SIN = 0, 1
 EXP_NONE, EXP_RADIATION = 0, 1
 TERMS_SPLIT, TERMS_NET = 0, 1
 SIDES_AUTO, SIDES_IN, SIDES_OUT, SIDES_BOTH = 0, 1, 2, 3
+WIDTH_ABS, WIDTH_REL = 0, 1
 
 
 @dataclasses.dataclass
@@ -53,6 +54,13 @@ class Process:
     eval_stride: int = 1
     n_samples: int = 10_000
     n_iter: int = 4
+    width_mode: int = WIDTH_ABS  # WIDTH_REL: sigma_E is the fraction w of (E_in + E_out) / 2
+    width_adapt: int = 0
+    width_lo: float = 1e-3
+    width_hi: float = 1e-2
+    width_factor: float = 1.25
+    width_min: float = 1e-4
+    width_max: float = 0.2
 
 
 @dataclasses.dataclass

@@ -21,11 +21,14 @@ def _bm():
     return boltzmc
 
 
-@pytest.mark.parametrize("shape", ["23be", "22mb_tail", "24fd_msin", "multi"])
+@pytest.mark.parametrize("shape", ["23be", "23be_relwidth", "22mb_tail", "24fd_msin", "multi"])
 def test_vjp_matches_oracle(shape):
     bm = _bm()
     if shape == "23be":
         w = wl.w23_be(n_grid=24, q_min=0.05, q_max=8.0, sigma_E=0.05, N=1 << 12, nitn=1)
+    elif shape == "23be_relwidth":  # width w (E_in + E_out) / 2: the mass gradient gains the width's energy terms
+        w = wl.w23_be(n_grid=24, q_min=0.05, q_max=8.0, sigma_E=0.02, N=1 << 12, nitn=1)
+        w.processes[0].width_mode = wl.WIDTH_REL
     elif shape == "22mb_tail":
         w = wl.w22_mb(n_grid=16, q_min=0.1, q_max=3.0, sigma_E=0.05, N=1 << 12, nitn=1)
     elif shape == "24fd_msin":

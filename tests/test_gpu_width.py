@@ -1,0 +1,114 @@
+"""GPU parity of the relative Gaussian width (w (E_in + E_out) / 2 per point) and of the width controller against the
+oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, assert_items_close, gpu_available, item_scale, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _rel(w, frac, **ctl):
+    for p in w.processes:
+        p.width_mode = wl.WIDTH_REL
+        p.sigma_E = frac
+        for k, v in ctl.items():
+            setattr(p, k, v)
+    return w
+
+
+def _oracle_items(ow, uids):
+    items, n = ow.items()
+    by = {items[i].uid: items[i] for i in range(n)}
+    sel = [by[int(u)] for u in uids]
+    return (ob.Item * len(sel))(*sel), len(sel)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("which", ["2to2", "2to3"])
+def test_rel_width_frozen_maps_parity(precision, which):
+    """Every item on frozen uniform maps, relative width: the screening bounds scale with the summed energies and the
+    second pass evaluates the per-point Gaussian."""
+    bm = _bm()
+    if which == "2to2":
+        w, N, nitn = _rel(wl.w22_mb(), 0.004), 10_000, 3
+    else:
+        w, N, nitn = _rel(wl.w23_be(n_grid=32, N=1 << 14), 0.002), 1 << 14, 2
+    say("relative width %s precision=%d" % (which, precision))
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=2, epoch=1, precision=precision, freeze_maps=1, n_iter=nitn, n_samples=N)
+    C, S = ctx.collision(-1, -1, opts)
+    res = ctx.item_results(nitn)
+    ow = ob.OracleWorld(w)
+    items, n = _oracle_items(ow, res["uid"])
+    rc, r = ow.run_items(items, n, N, nitn, seed=2, epoch=1, adapt=False)
+    assert rc == 0
+    tol = TOL[precision]
+    assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
+    Co, So = ow.combine(items, n, r["Ibar"], r["sigma"], 0)
+    scale = np.zeros(len(C))
+    for i in range(n):
+        scale[items[i].eval_idx] += items[i].mult * abs(r["Ibar"][i])
+    err = np.abs(C - Co)
+    say("C max err / scale %.3e" % np.max(err / scale))
+    assert np.all(err <= tol * scale)
+
+
+@pytest.mark.parametrize("direction", ["narrow", "widen", "hold"])
+def test_width_controller_follows_the_oracle(direction):
+    """After each evaluation the device-side controller moves the width as the oracle's controller does from the
+    same item results, and the next evaluation uses the new width (checked item by item against the oracle)."""
+    bm = _bm()
+    lo, hi = {"narrow": (10.0, 20.0), "widen": (1e-9, 2e-9), "hold": (1e-9, 10.0)}[direction]
+    w = _rel(wl.w22_mb(), 0.004, width_adapt=1, width_lo=lo, width_hi=hi, width_factor=1.25, width_min=1e-3,
+             width_max=0.006)
+    N, nitn = 10_000, 2
+    ctx = bm.from_workload(w)
+    ow = ob.OracleWorld(w)
+    widths = []
+    for call in range(3):
+        say("controller %s call %d" % (direction, call))
+        opts = bm.default_opts(seed=4, epoch=call, freeze_maps=1, n_iter=nitn, n_samples=N)
+        ctx.collision(-1, -1, opts)
+        res = ctx.item_results(nitn)
+        items, n = _oracle_items(ow, res["uid"])
+        rc, r = ow.run_items(items, n, N, nitn, seed=4, epoch=call, adapt=False)
+        assert rc == 0
+        assert_items_close(res["I_it"], r["I_it"], TOL[0], "I_it", scale=item_scale(items, n, r["Ibar"]))
+        w_or = ow.width_control(items, n, r["Ibar"], r["sigma"], 0)
+        w_gpu = ctx.get_width(0)
+        assert w_gpu == w_or, (call, w_gpu, w_or)
+        widths.append(w_gpu)
+    expect = {"narrow": [0.004 / 1.25, 0.004 / 1.25 / 1.25, 0.004 / 1.25 / 1.25 / 1.25],
+              "widen": [0.004 * 1.25, 0.006, 0.006], "hold": [0.004] * 3}[direction]
+    np.testing.assert_allclose(widths, expect, rtol=1e-15)
+
+
+def test_width_set_get_and_checkpoint():
+    bm = _bm()
+    w = _rel(wl.w22_mb(), 0.004, width_adapt=1, width_lo=10.0, width_hi=20.0)
+    ctx = bm.from_workload(w)
+    ctx.collision(-1, -1, bm.default_opts(seed=1, freeze_maps=1, n_iter=1, n_samples=2000))
+    w1 = ctx.get_width(0)
+    assert w1 == pytest.approx(0.004 / 1.25, rel=1e-15)
+    blob = ctx.state_get()
+    ctx.set_width(0, 0.01)
+    assert ctx.get_width(0) == 0.01
+    with pytest.raises(bm.BmcError):
+        ctx.set_width(0, 1.5)  # a relative width stays <= 1
+    ctx2 = bm.from_workload(w)
+    ctx2.state_set(blob)
+    assert ctx2.get_width(0) == w1
