@@ -30,7 +30,7 @@ def build(force: bool = True) -> str:
 class Species(C.Structure):
     _fields_ = [("stat", C.c_int), ("n_grid", C.c_int), ("q_min", C.c_double), ("q_max", C.c_double),
                 ("mass_kind", C.c_int), ("m0", C.c_double), ("mA", C.c_double), ("mw", C.c_double),
-                ("f", C.POINTER(C.c_double))]
+                ("f", C.POINTER(C.c_double)), ("interp", C.c_int), ("aux", C.POINTER(C.c_double))]
 
 
 class Process(C.Structure):
@@ -75,6 +75,7 @@ def lib():
         L.orc_f_at.restype = C.c_double
         L.orc_f_batch.argtypes = [C.POINTER(Species), dp, C.c_int64, dp, dp, dp]
         L.orc_f_batch.restype = None
+        L.orc_spline_second_derivatives.argtypes = [C.c_int, dp, dp, dp]
         L.orc_stat_factor.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_stat_factor.restype = C.c_double
         L.orc_integrand_batch.argtypes = [C.POINTER(World), C.POINTER(Item), C.c_int64, dp, dp]
@@ -134,9 +135,11 @@ class OracleWorld:
     def __init__(self, w):
         self.w = w
         self.f = [np.ascontiguousarray(s.f, dtype=np.float64).copy() for s in w.species]
+        self.aux = [np.zeros(s.n_grid) for s in w.species]  # spline second derivatives / node energies
         self.sp = (Species * len(w.species))()
         for i, s in enumerate(w.species):
-            self.sp[i] = Species(s.stat, s.n_grid, s.q_min, s.q_max, s.mass_kind, s.m0, s.mA, s.mw, _dp(self.f[i]))
+            self.sp[i] = Species(s.stat, s.n_grid, s.q_min, s.q_max, s.mass_kind, s.m0, s.mA, s.mw, _dp(self.f[i]),
+                                 s.interp, _dp(self.aux[i]))
         self.pr = (Process * max(1, len(w.processes)))()
         for i, p in enumerate(w.processes):
             sp = (C.c_int * 6)(*(list(p.ins) + list(p.outs) + [0] * (6 - len(p.ins) - len(p.outs))))

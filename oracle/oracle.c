@@ -143,6 +143,22 @@ int orc_fit(const orc_species* s, double a, double t, double fit[4]) {
     fit[2 * side + 1] = b;
   }
   if (!(fit[3] > 0.0)) return ORC_ERANGE;
+  if (s->interp == ORC_INTERP_SPLINE || s->interp == ORC_INTERP_EQEXACT) {
+    if (!s->aux) return ORC_EINVAL;
+    if (s->interp == ORC_INTERP_EQEXACT) {
+      for (int j = 0; j < n; ++j) {
+        double p = orc_grid_q(s, j) / a;
+        s->aux[j] = sqrt(p * p + m * m);
+      }
+    } else {
+      double* q = (double*)malloc(sizeof(double) * (size_t)n);
+      if (!q) return ORC_ENOMEM;
+      for (int j = 0; j < n; ++j) q[j] = orc_grid_q(s, j);
+      int rc = orc_spline_second_derivatives(n, q, s->f, s->aux);
+      free(q);
+      if (rc) return rc;
+    }
+  }
   if (s->stat == ORC_BOSE) {
     double p0 = orc_grid_q(s, 0) / a, pN = orc_grid_q(s, n - 1) / a;
     double E0 = sqrt(p0 * p0 + m * m), EN = sqrt(pN * pN + m * m);
@@ -152,19 +168,92 @@ int orc_fit(const orc_species* s, double a, double t, double fit[4]) {
   return ORC_OK;
 }
 
+/* Second derivatives of the not-a-knot cubic spline through (q_j, f_j), j = 0..n-1, n >= 4 (Sec. III.B: a cubic
+ * spline in linear scale; not-a-knot ends are the usual default).  On [q_j, q_{j+1}], h_j = q_{j+1} - q_j, the
+ * spline is A f_j + B f_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) h_j^2 / 6 with B = (q - q_j) / h_j, A = 1 - B.
+ * Conditions: S' continuous at q_1 .. q_{n-2} (rows 1 .. n-2); the third derivative continuous at q_1 (row 0) and
+ * at q_{n-2} (row n-1).  The n x n system is solved by Gaussian elimination with partial pivoting. */
+int orc_spline_second_derivatives(int n, const double* q, const double* f, double* M) {
+  if (n < 4) return ORC_EINVAL;
+  double* A = (double*)calloc((size_t)n * (size_t)(n + 1), sizeof(double));  /* augmented rows of n + 1 */
+  if (!A) return ORC_ENOMEM;
+#define AE(r, c) A[(size_t)(r) * (size_t)(n + 1) + (size_t)(c)]
+  for (int j = 1; j < n - 1; ++j) {
+    const double hl = q[j] - q[j - 1], hr = q[j + 1] - q[j];
+    AE(j, j - 1) = hl / 6.0;
+    AE(j, j) = (hl + hr) / 3.0;
+    AE(j, j + 1) = hr / 6.0;
+    AE(j, n) = (f[j + 1] - f[j]) / hr - (f[j] - f[j - 1]) / hl;
+  }
+  {
+    const double h0 = q[1] - q[0], h1 = q[2] - q[1];
+    AE(0, 0) = -1.0 / h0;
+    AE(0, 1) = 1.0 / h0 + 1.0 / h1;
+    AE(0, 2) = -1.0 / h1;
+    const double ha = q[n - 2] - q[n - 3], hb = q[n - 1] - q[n - 2];
+    AE(n - 1, n - 3) = -1.0 / ha;
+    AE(n - 1, n - 2) = 1.0 / ha + 1.0 / hb;
+    AE(n - 1, n - 1) = -1.0 / hb;
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (fabs(AE(r, col)) > fabs(AE(piv, col))) piv = r;
+    if (AE(piv, col) == 0.0) {
+      free(A);
+      return ORC_ERANGE;
+    }
+    if (piv != col)
+      for (int c = 0; c <= n; ++c) {
+        double tmp = AE(col, c);
+        AE(col, c) = AE(piv, c);
+        AE(piv, c) = tmp;
+      }
+    for (int r = col + 1; r < n; ++r) {
+      const double fac = AE(r, col) / AE(col, col);
+      if (fac == 0.0) continue;
+      for (int c = col; c <= n; ++c) AE(r, c) -= fac * AE(col, c);
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    double acc = AE(r, n);
+    for (int c = r + 1; c < n; ++c) acc -= AE(r, c) * M[c];
+    M[r] = acc / AE(r, r);
+  }
+#undef AE
+  free(A);
+  return ORC_OK;
+}
+
 /* f at comoving momentum q with physical energy E (Sec. III.B):
- *   inside [q_0, q_{N-1}]: linear interpolation in ln q between the bracketing nodes;
+ *   inside [q_0, q_{N-1}], on the segment [q_j, q_{j+1}] of the logarithmic grid that holds q:
+ *     LINLOG   linear in ln q between f_j and f_{j+1};
+ *     SPLINE   the not-a-knot cubic spline in linear q (second derivatives in s->aux);
+ *     EQEXACT  y = log(1/f + eta) linear in E between (E_j, y_j) and (E_{j+1}, y_{j+1}) (E_j in s->aux),
+ *              f = 1 / (exp(y) - eta);
  *   below / above: f = 1 / (exp(a + b E) - eta) with the low / high fit. */
 double orc_f_at(const orc_species* s, const double fit[4], double q, double E) {
   const int n = s->n_grid;
-  if (q < s->q_min) return 1.0 / (exp(fit[0] + fit[1] * E) - (double)s->stat);
-  if (q > s->q_max) return 1.0 / (exp(fit[2] + fit[3] * E) - (double)s->stat);
+  const double eta = (double)s->stat;
+  if (q < s->q_min) return 1.0 / (exp(fit[0] + fit[1] * E) - eta);
+  if (q > s->q_max) return 1.0 / (exp(fit[2] + fit[3] * E) - eta);
   double lq0 = log(s->q_min);
   double h = (log(s->q_max) - lq0) / (double)(n - 1);
   double tpos = (log(q) - lq0) / h;
   int j = (int)floor(tpos);
   if (j < 0) j = 0;
   if (j > n - 2) j = n - 2;
+  if (s->interp == ORC_INTERP_SPLINE) {
+    const double q0 = orc_grid_q(s, j), q1 = orc_grid_q(s, j + 1), hq = q1 - q0;
+    const double B = (q - q0) / hq, A = 1.0 - B;
+    return A * s->f[j] + B * s->f[j + 1] +
+           ((A * A * A - A) * s->aux[j] + (B * B * B - B) * s->aux[j + 1]) * hq * hq / 6.0;
+  }
+  if (s->interp == ORC_INTERP_EQEXACT) {
+    const double y0 = log(1.0 / s->f[j] + eta), y1 = log(1.0 / s->f[j + 1] + eta);
+    const double w = (E - s->aux[j]) / (s->aux[j + 1] - s->aux[j]);
+    return 1.0 / (exp(y0 + w * (y1 - y0)) - eta);
+  }
   double w = tpos - (double)j;
   return s->f[j] + w * (s->f[j + 1] - s->f[j]);
 }
@@ -426,13 +515,6 @@ static int item_setup(item_ctx* c, const orc_world* w, const orc_item* it, doubl
   return ORC_OK;
 }
 
-/* Weight of the point x, excluding the Vegas Jacobian (Appendix A, Eq. A-weight):
- *   prod_k r_k^2 sin(theta_k) a^{-3} * |M|^2 * delta_sigma(E_in - E_out)
- *     / ((2 pi)^{3(n-1)-4} prod_{all i} 2 E_i) * F,
- * with F = gain or loss (SPLIT) or gain - loss (NET), gain/loss defined relative to the observed leg:
- *   gain = prod_{opposite side} f * prod_{observed side} (1 + eta f)
- *   loss = prod_{observed side} f * prod_{opposite side} (1 + eta f)       (Sec. II.C, the C_2 / C_3 lists)
- * Points with any E_i below the cut get weight 0 (Appendix A). */
 /* Width of the Gaussian energy delta at one point (Eq. 15; Appendix C): the given sigma_E, or with a relative
  * width, sigma_E = w (E_in + E_out) / 2 where E_in and E_out are the summed initial and final energies. */
 double orc_point_width(const orc_process* P, int n, const double* E) {
@@ -462,6 +544,13 @@ double orc_width_control(const orc_process* P, int n, const double* Ibar, const 
   return w;
 }
 
+/* Weight of the point x, excluding the Vegas Jacobian (Appendix A, Eq. A-weight):
+ *   prod_k r_k^2 sin(theta_k) a^{-3} * |M|^2 * delta_sigma(E_in - E_out)
+ *     / ((2 pi)^{3(n-1)-4} prod_{all i} 2 E_i) * F,
+ * with F = gain or loss (SPLIT) or gain - loss (NET), gain/loss defined relative to the observed leg:
+ *   gain = prod_{opposite side} f * prod_{observed side} (1 + eta f)
+ *   loss = prod_{observed side} f * prod_{opposite side} (1 + eta f)       (Sec. II.C, the C_2 / C_3 lists)
+ * Points with any E_i below the cut get weight 0 (Appendix A). */
 static double item_integrand(const item_ctx* c, const double* x) {
   const int n = c->n, n_in = c->n_in;
   const double a = c->a;
@@ -1052,6 +1141,9 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
 int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
             uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
             int n_threads) {
+  /* the gradient's interpolation chain is written for the linear-in-ln q rule */
+  for (int s = 0; s < w->n_species; ++s)
+    if (w->species[s].interp != ORC_INTERP_LINLOG) return ORC_EINVAL;
   double fits[4 * ORC_MAXSPECIES];
   int rc = orc_fits_all(w, w->t, fits);
   if (rc) return rc;

@@ -25,6 +25,10 @@
 #define ORC_FERMI (-1)
 #define ORC_MB 0
 
+#define ORC_INTERP_LINLOG 0  /* f linear in ln q between nodes */
+#define ORC_INTERP_SPLINE 1  /* not-a-knot cubic spline of f in linear q (Sec. III.B) */
+#define ORC_INTERP_EQEXACT 2 /* log(1/f + eta) linear in E between nodes (exact for equilibrium, like Eq. 17) */
+
 #define ORC_MASS_CONST 0
 #define ORC_MASS_SIN 1
 
@@ -49,6 +53,9 @@ typedef struct {
   int mass_kind;            /* ORC_MASS_CONST or ORC_MASS_SIN (m0 + mA sin(mw t)) */
   double m0, mA, mw;
   const double* f;          /* n_grid values of f on the grid */
+  int interp;               /* ORC_INTERP_* */
+  double* aux;              /* n_grid doubles owned by the caller, written by orc_fit: the spline's second
+                               derivatives (SPLINE) or the node energies E_j at the fit's time (EQEXACT) */
 } orc_species;
 
 typedef struct {
@@ -95,6 +102,8 @@ double orc_mass(const orc_species* s, double t);
 double orc_scale_factor(const orc_world* w, double t);
 int orc_fit(const orc_species* s, double a, double t, double fit[4]);
 double orc_f_at(const orc_species* s, const double fit[4], double q, double E);
+/* Second derivatives M[0..n-1] of the not-a-knot cubic spline through (q_j, f_j). */
+int orc_spline_second_derivatives(int n, const double* q, const double* f, double* M);
 void orc_f_batch(const orc_species* s, const double fit[4], int64_t n, const double* q, const double* E, double* out);
 int orc_side_multiplicity(const orc_process* P, int a, int side);
 int orc_roles(const orc_process* P, int a, int side, int* i_obs, int* i_cons, int* integ);

@@ -24,6 +24,7 @@ EXP_NONE, EXP_RADIATION = 0, 1
 TERMS_SPLIT, TERMS_NET = 0, 1
 SIDES_AUTO, SIDES_IN, SIDES_OUT, SIDES_BOTH = 0, 1, 2, 3
 WIDTH_ABS, WIDTH_REL = 0, 1
+INTERP_LINLOG, INTERP_SPLINE, INTERP_EQEXACT = 0, 1, 2
 
 
 @dataclasses.dataclass
@@ -38,6 +39,7 @@ class Species:
     m0: float = 1.0
     mA: float = 0.0
     mw: float = 0.0
+    interp: int = INTERP_LINLOG
 
 
 @dataclasses.dataclass
