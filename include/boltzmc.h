@@ -71,6 +71,10 @@ extern "C" {
 #define BMC_SIDES_OUT 2
 #define BMC_SIDES_BOTH 3
 
+#define BMC_INTERP_LINLOG 0   /* f linear in ln q between grid nodes (default) */
+#define BMC_INTERP_SPLINE 1   /* not-a-knot cubic spline of f in linear q (Sec. III.B) */
+#define BMC_INTERP_EQEXACT 2  /* log(1/f + eta) linear in E between nodes: exact for equilibrium (the form of Eq. 17) */
+
 #define BMC_WIDTH_ABS 0   /* sigma_E is the width of the Gaussian energy delta (an energy) */
 #define BMC_WIDTH_REL 1   /* sigma_E is a fraction w; the width at a point is w (E_in + E_out) / 2 (Appendix C) */
 
@@ -163,6 +167,10 @@ int bmc_add_species(bmc_ctx* ctx, const char* name, int stat, int grid_kind, int
                     double q_max, int* species_id);
 /* Mass of a species: BMC_MASS_CONST (m0) or BMC_MASS_SIN (m0 + A sin(w t)); m(t) >= 0 is required. */
 int bmc_set_mass(bmc_ctx* ctx, int species, int kind, double m0, double A, double w);
+/* Rule for f between grid nodes of a species (Sec. III.B): BMC_INTERP_LINLOG, _SPLINE or _EQEXACT.  Outside the
+ * grid every rule uses the Eq. 17 fit; at the nodes every rule gives the table value.  The spline's second
+ * derivatives are recomputed on the device before every evaluation.  bmc_vjp accepts LINLOG only (BMC_EUNSUP). */
+int bmc_set_interp(bmc_ctx* ctx, int species, int mode);
 /* Sets f on the species' grid (n values).  Validates f > 0 and, for Fermi-Dirac, f < 1 (BMC_ERANGE). */
 int bmc_set_f(bmc_ctx* ctx, int species, const double* f, int n, int mem);
 /* Copies the current f of a species (n values) to `f`. */

@@ -21,6 +21,7 @@ OK, EINVAL, ESTATE, ERANGE, ENOMEM, EHIP, EUNSUP = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 FP64, FP32I = 0, 1
 WIDTH_ABS, WIDTH_REL = 0, 1
+INTERP_LINLOG, INTERP_SPLINE, INTERP_EQEXACT = 0, 1, 2
 LAUNCH_BATCHED, LAUNCH_PLAIN = 0, 1
 EULER, HEUN = 0, 1
 MAXD, MAXITER = 12, 64
@@ -63,6 +64,7 @@ _SIGS = {
                         C.POINTER(ProcessParams), C.POINTER(C.c_int)],
     "bmc_default_process_params": [C.POINTER(ProcessParams)],
     "bmc_set_coupling": [C.c_void_p, C.c_int, C.c_double],
+    "bmc_set_interp": [C.c_void_p, C.c_int, C.c_int],
     "bmc_get_width": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
     "bmc_set_width": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_expansion": [C.c_void_p, C.c_int, C.c_double, C.c_double],
@@ -218,6 +220,9 @@ class Context:
 
     def set_coupling(self, process, coupling):
         self._check(lib().bmc_set_coupling(self.h, process, coupling))
+
+    def set_interp(self, species, mode):
+        self._check(lib().bmc_set_interp(self.h, species, mode))
 
     def get_width(self, process):
         w = C.c_double()
@@ -387,6 +392,8 @@ def from_workload(w: wl.Workload, device: int = 0, stream=None) -> Context:
     for s in w.species:
         sid = ctx.add_species(s.name, s.stat, s.n_grid, s.q_min, s.q_max)
         ctx.set_mass(sid, s.mass_kind, s.m0, s.mA, s.mw)
+        if s.interp != INTERP_LINLOG:
+            ctx.set_interp(sid, s.interp)
     for p in w.processes:
         ctx.add_process(p.ins, p.outs, coupling=p.coupling, sigma_E=p.sigma_E, alpha=p.alpha, e_cut=p.e_cut,
                         n_bins=p.n_bins, term_mode=p.term_mode, side_mask=p.side_mask, eval_stride=p.eval_stride,

@@ -45,6 +45,7 @@ struct Species {
   std::vector<double> f;  // host mirror (authoritative until bound; refreshed from the device on demand)
   bool f_set = false;
   int64_t f_off = 0;
+  int interp = BMC_INTERP_LINLOG;
 };
 
 struct Process {
@@ -133,7 +134,7 @@ struct bmc_ctx {
   size_t ws_bytes = 0;
   bool bound = false;
   size_t off_state = 0, off_spec = 0, off_f64 = 0, off_f32 = 0, off_f0 = 0, off_k1 = 0, off_k2 = 0, off_sig = 0,
-         off_qnode = 0, off_maps = 0, off_wctl = 0, persist_bytes = 0;
+         off_qnode = 0, off_maps = 0, off_wctl = 0, off_aux = 0, persist_bytes = 0;
   int64_t n_f = 0;
   int max_slots = 0;
   int n_sp_bound = -1, n_pr_bound = -1;
@@ -166,6 +167,7 @@ struct bmc_ctx {
   double* k2() { return reinterpret_cast<double*>(ws + off_k2); }
   double* sig() { return reinterpret_cast<double*>(ws + off_sig); }
   double* qnode() { return reinterpret_cast<double*>(ws + off_qnode); }
+  double* aux() { return reinterpret_cast<double*>(ws + off_aux); }  // 2 n_f: spline M, then solve scratch
   double* maps() { return reinterpret_cast<double*>(ws + off_maps); }
 };
 
@@ -278,6 +280,8 @@ void layout_persistent(bmc_ctx* c) {
   o = align_up(o + 8 * nf);
   c->off_qnode = o;
   o = align_up(o + 8 * nf);
+  c->off_aux = o;
+  o = align_up(o + 16 * nf);
   // map slots: every item any call can plan (stride 1, both sides, both terms), at the grid nodes and at
   // kMaxEvalPoints evaluation points off the grid of every species
   int slots = 0;
@@ -292,8 +296,12 @@ void layout_persistent(bmc_ctx* c) {
   c->persist_bytes = o;
 }
 
-SpecDev make_spec(const Species& S) {
+SpecDev make_spec(bmc_ctx* c, const Species& S) {
   SpecDev d{};
+  d.interp = S.interp;
+  d.qn = c->qnode() + S.f_off;
+  d.aux = c->aux() + S.f_off;
+  d.tmp = c->aux() + c->n_f + S.f_off;
   d.stat = S.stat;
   d.n = S.n;
   d.q_min = S.q_min;
@@ -312,7 +320,7 @@ int upload_model(bmc_ctx* c) {
   std::vector<SpecDev> sd(kMaxSpecies);
   std::vector<double> qn;
   for (size_t i = 0; i < c->sp.size(); ++i) {
-    sd[i] = make_spec(c->sp[i]);
+    sd[i] = make_spec(c, c->sp[i]);
     for (int j = 0; j < c->sp[i].n; ++j) qn.push_back(grid_node(c->sp[i], j));
   }
   HIPCHK(c, hipMemcpyAsync(c->spec(), sd.data(), sizeof(SpecDev) * kMaxSpecies, hipMemcpyHostToDevice, c->stream));
@@ -843,6 +851,8 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.seed_hi = (uint32_t)(o.seed >> 32);
   L.nint_mask = P.nint_mask;
   L.precision = o.precision;
+  L.any_interp = 0;
+  for (auto& S : c->sp) L.any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
   L.shell_list = P.d_list;
   L.shell_cnt = P.d_cnt;
@@ -1033,6 +1043,19 @@ int bmc_set_mass(bmc_ctx* c, int species, int kind, double m0, double A, double 
   s.m0 = m0;
   s.A = kind == BMC_MASS_SIN ? A : 0.0;
   s.w = kind == BMC_MASS_SIN ? w : 0.0;
+  if (c->bound && species < c->n_sp_bound) {
+    int rc = upload_model(c);
+    if (rc) return rc;
+  }
+  return BMC_OK;
+}
+
+int bmc_set_interp(bmc_ctx* c, int species, int mode) {
+  if (!c) return BMC_EINVAL;
+  if (species < 0 || species >= (int)c->sp.size()) return fail(c, BMC_EINVAL, "bad species id");
+  if (mode != BMC_INTERP_LINLOG && mode != BMC_INTERP_SPLINE && mode != BMC_INTERP_EQEXACT)
+    return fail(c, BMC_EINVAL, "bad interpolation rule");
+  c->sp[species].interp = mode;
   if (c->bound && species < c->n_sp_bound) {
     int rc = upload_model(c);
     if (rc) return rc;
@@ -1686,6 +1709,9 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   if (rc) return rc;
   if (o->precision != BMC_FP64) return fail(c, BMC_EUNSUP, "vector-Jacobian products are FP64 only");
   if (o->eval_q) return fail(c, BMC_EUNSUP, "vector-Jacobian products are on the grids only (eval_q must be NULL)");
+  for (auto& S : c->sp)
+    if (S.interp != BMC_INTERP_LINLOG)
+      return fail(c, BMC_EUNSUP, "vector-Jacobian products need the linear-in-ln q interpolation");
   rc = check_ready(c);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));
@@ -1784,6 +1810,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   L.seed_hi = (uint32_t)(o->seed >> 32);
   L.nint_mask = P.nint_mask;
   L.precision = BMC_FP64;
+  L.any_interp = 0;  // the adjoint takes the linear rule only
   L.lds_bytes = lds;
   L.chunk = 1;
   L.shell_list = P.d_list;

@@ -25,6 +25,11 @@ struct SpecDev {
   int mass_kind;     // 0 const, 1 m0 + A sin(w t)
   double m0, A, w;
   int64_t f_off;     // offset of the species' values in the f arrays
+  int interp;        // 0 linear in ln q, 1 not-a-knot cubic spline in linear q, 2 log(1/f + eta) linear in E
+  const double* qn;  // n comoving grid nodes
+  double* aux;       // n doubles written by the prepare kernel: the spline's second derivatives, or the node
+                     // energies of the equilibrium-exact rule
+  double* tmp;       // n doubles: scratch of the spline solve, or log(1/f_j + eta) of the equilibrium-exact rule
 };
 
 // Time-dependent state read by every kernel (lives in device memory so graphs can advance it).

@@ -25,6 +25,7 @@ struct SampleLaunch {
   uint32_t seed_lo, seed_hi;
   int nint_mask;         // bit (nint-1) set for every integrated-particle count present
   int precision;         // 0 FP64, 1 FP32I
+  int any_interp;        // 1 if a species of the launch interpolates by the spline or the equilibrium-exact rule
   int grid;              // blocks
   int chunk;             // consecutive tasks per block visit
   size_t lds_bytes;

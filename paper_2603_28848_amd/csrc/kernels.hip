@@ -136,46 +136,82 @@ __device__ __forceinline__ double log_pos(double q) {
 }
 
 // A table of f on a logarithmic grid in LDS (q_j, 1/q_j, f_j).
+// Per node, by rule: linear in ln q -- (unused, unused, f_j); spline -- (q_j, M_j, f_j) with M_j the second
+// derivatives; equilibrium-exact -- (E_j, y_j = log(1/f_j + eta), unused).
 template <typename T>
 struct FTab {
   const double* q;
   const double* iq;
   const T* f;
   int n;
-  double lq0, inv_h;
+  int mode;
+  double lq0, inv_h, eta;
 };
 
+// Value between two nodes by the spline (mode 1: A = q, B = M) or the equilibrium-exact rule (mode 2: A = E,
+// B = log(1/f + eta)); q is the comoving momentum, E the energy.
+__device__ __forceinline__ double interp_alt64(int mode, double eta, double q, double E, double A0, double A1, double B0,
+                                               double B1, double f0, double f1) {
+  if (mode == 1) {
+    const double hq = A1 - A0;
+    const double b = (q - A0) / hq, a = 1.0 - b;
+    return a * f0 + b * f1 + ((a * a * a - a) * B0 + (b * b * b - b) * B1) * (hq * hq / 6.0);
+  }
+  const double w = (E - A0) / (A1 - A0);
+  return 1.0 / (exp(B0 + w * (B1 - B0)) - eta);
+}
+
 // FP64: position t = (ln q - ln q_0)/h on the grid, node j = floor(t), weight t - j.
-__device__ __forceinline__ double interp64(const FTab<double>& t, double q, int* jo, double* wo) {
+// ALT = false: the linear rule only (every table of the launch uses it).
+template <bool ALT>
+__device__ __forceinline__ double interp64(const FTab<double>& t, double q, double E, int* jo, double* wo) {
   const double tp = (log_pos(q) - t.lq0) * t.inv_h;
   int j = (int)floor(tp);
   j = j < 0 ? 0 : (j > t.n - 2 ? t.n - 2 : j);
   const double w = tp - (double)j;
   *jo = j;
   *wo = w;
+  if (ALT && t.mode != 0)
+    return interp_alt64(t.mode, t.eta, q, E, t.q[j], t.q[j + 1], t.iq[j], t.iq[j + 1], t.f[j], t.f[j + 1]);
   const double f0 = t.f[j], f1 = t.f[j + 1];
   return f0 + w * (f1 - f0);
 }
 
 // f of species S (table f, global memory) at comoving momentum q with energy E by the rule of Sec. III.B: linear
 // in ln q between the bracketing nodes inside [q_0, q_{N-1}], the fit f = 1 / (exp(a + b E) - eta) outside.
-__device__ __forceinline__ double f_at_global(const SpecDev& S, const double* __restrict__ f, const double* fit,
-                                              double q, double E) {
+__device__ __forceinline__ double f_at_global(const SpecDev& S, const double* __restrict__ f, const double* qnode,
+                                              const double* fit, double q, double E) {
   if (q < S.q_min) return 1.0 / (exp(fit[0] + fit[1] * E) - (double)S.stat);
   if (q > S.q_max) return 1.0 / (exp(fit[2] + fit[3] * E) - (double)S.stat);
   const double tp = (log_pos(q) - S.lq0) * S.inv_h;
   int j = (int)floor(tp);
   j = j < 0 ? 0 : (j > S.n - 2 ? S.n - 2 : j);
+  if (S.interp == 1)
+    return interp_alt64(1, (double)S.stat, q, E, qnode[j], qnode[j + 1], S.aux[j], S.aux[j + 1], f[j], f[j + 1]);
+  if (S.interp == 2)
+    return interp_alt64(2, (double)S.stat, q, E, S.aux[j], S.aux[j + 1], S.tmp[j], S.tmp[j + 1], f[j], f[j + 1]);
   const double w = tp - (double)j;
   return f[j] + w * (f[j + 1] - f[j]);
 }
 
 // FP32 integrand: the grid position in FP64 (an FP32 logarithm would move the weight by ~1e-6 / h, which the
 // linear interpolation of a steep tail amplifies by f_j / f_{j+1}); interpolation of the FP32 table.
-__device__ __forceinline__ float interp32(const FTab<float>& t, double q) {
+template <bool ALT>
+__device__ __forceinline__ float interp32(const FTab<float>& t, double q, double E) {
   const double tp = (log_pos(q) - t.lq0) * t.inv_h;
   int j = (int)floor(tp);
   j = j < 0 ? 0 : (j > t.n - 2 ? t.n - 2 : j);
+  if (ALT && t.mode == 1) {
+    const double q0 = t.q[j], hq = t.q[j + 1] - q0;
+    const float b = (float)((q - q0) / hq), a = 1.0f - b;
+    const float h26 = (float)(hq * hq / 6.0);
+    return fmaf(a, t.f[j], b * t.f[j + 1]) +
+           ((a * a * a - a) * (float)t.iq[j] + (b * b * b - b) * (float)t.iq[j + 1]) * h26;
+  }
+  if (ALT && t.mode == 2) {
+    const double w = (E - t.q[j]) / (t.q[j + 1] - t.q[j]);
+    return __builtin_amdgcn_rcpf(exp_split(t.iq[j] + w * (t.iq[j + 1] - t.iq[j])) - (float)t.eta);
+  }
   const float w = (float)(tp - (double)j);
   const float f0 = t.f[j], f1 = t.f[j + 1];
   return fmaf(w, f1 - f0, f0);
@@ -224,7 +260,7 @@ __device__ __forceinline__ void philox_words(uint32_t* wd, uint64_t n, uint32_t 
 // One sample with FP64 kinematics (map, sin/cos, momenta, energies, dE and the Gaussian's argument); the f
 // tables, interpolation and statistical factor in FT.  Returns W and, per dimension d, the histogram offset
 // d nb + j of the sample's bin j.
-template <int NI, typename FT>
+template <int NI, typename FT, bool ALT>
 __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, int* hj) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
@@ -271,9 +307,9 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     if constexpr (std::is_same<FT, double>::value) {
       int jj;
       double ww;
-      f = interp64(K.tr[k], r, &jj, &ww);
+      f = interp64<ALT>(K.tr[k], r, E, &jj, &ww);
     } else {
-      f = interp32(K.tr[k], r);
+      f = interp32<ALT>(K.tr[k], r, E);
     }
     const FT bf = (FT)1.0 + (FT)K.eta[k] * f;
     gain *= K.obsside[k] ? bf : f;
@@ -296,7 +332,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     } else {
       int jj;
       double ww;
-      fc = interp64(K.tr[NI], qc, &jj, &ww);
+      fc = interp64<ALT>(K.tr[NI], qc, Ec, &jj, &ww);
     }
   } else {
     if (qc < K.qc_min) {
@@ -304,7 +340,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     } else if (qc > K.qc_max) {
       fc = __builtin_amdgcn_rcpf(exp_split(K.fit[2] + K.fit[3] * Ec) - (float)K.eta[NI]);
     } else {
-      fc = interp32(K.tr[NI], qc);
+      fc = interp32<ALT>(K.tr[NI], qc, Ec);
     }
   }
   {
@@ -342,7 +378,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 // every dimension is exact (the same as with the FP64 map).
 constexpr int kFar = 0, kNear = 1, kInShell = 2;
 
-template <int NI, bool FINISH>
+template <int NI, bool FINISH, bool ALT = false>
 __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, int* hj, double* Wout) {
   constexpr int D = 3 * NI;
   constexpr float kInv2Pi = 0.15915494309189535f;
@@ -390,11 +426,16 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
     sumE += E;
     prod2E *= 2.0f * E;
     const FTab<float>& T = K.tr[k];
-    const float tp = fmaf(__builtin_amdgcn_logf(r), K.lg1[k], -K.lg0[k]);
-    int jj = (int)tp;
-    jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
-    const float wgt = tp - (float)jj;
-    const float f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    float f;
+    if (!ALT || T.mode == 0) {
+      const float tp = fmaf(__builtin_amdgcn_logf(r), K.lg1[k], -K.lg0[k]);
+      int jj = (int)tp;
+      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+      const float wgt = tp - (float)jj;
+      f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    } else {
+      f = interp32<ALT>(T, (double)r, (double)E);
+    }
     const float bf = fmaf((float)K.eta[k], f, 1.0f);
     gain *= K.obsside[k] ? bf : f;
     loss *= K.obsside[k] ? f : bf;
@@ -423,10 +464,14 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
       fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K.fit[3], Ec, (float)K.fit[2])) - (float)K.eta[NI]);
     } else {
       const FTab<float>& T = K.tr[NI];
-      const float tp = fmaf(__builtin_amdgcn_logf(qc), K.lg1[NI], -K.lg0[NI]);
-      int jj = (int)tp;
-      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
-      fc = fmaf(tp - (float)jj, T.f[jj + 1] - T.f[jj], T.f[jj]);
+      if (!ALT || T.mode == 0) {
+        const float tp = fmaf(__builtin_amdgcn_logf(qc), K.lg1[NI], -K.lg0[NI]);
+        int jj = (int)tp;
+        jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+        fc = fmaf(tp - (float)jj, T.f[jj + 1] - T.f[jj], T.f[jj]);
+      } else {
+        fc = interp32<ALT>(T, (double)qc, (double)Ec);
+      }
     }
     const float bf = fmaf((float)K.eta[NI], fc, 1.0f);
     gain *= K.obsside[NI] ? bf : fc;
@@ -496,9 +541,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     double* q = reinterpret_cast<double*>(base);
     double* iq = q + n_max;
     FT* f = reinterpret_cast<FT*>(iq + n_max);
+    const int md = S.interp;
     for (int j = tid; j < S.n; j += kBlock) {
-      q[j] = L.qnode[S.f_off + j];
-      iq[j] = 1.0 / q[j];
+      q[j] = md == 2 ? S.aux[j] : L.qnode[S.f_off + j];  // node energies (EQEXACT) or nodes
+      iq[j] = md == 1 ? S.aux[j] : (md == 2 ? S.tmp[j] : 0.0);  // spline M_j, or log(1/f_j + eta)
       if constexpr (PREC == 0) f[j] = L.f64[S.f_off + j];
       else f[j] = L.f32[S.f_off + j];
     }
@@ -518,6 +564,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     K.tr[r].iq = K.tr[r].q + n_max;
     K.tr[r].f = reinterpret_cast<const FT*>(K.tr[r].iq + n_max);
     K.tr[r].n = S.n;
+    K.tr[r].mode = S.interp;
+    K.tr[r].eta = (double)S.stat;
     K.tr[r].lq0 = S.lq0;
     K.tr[r].inv_h = S.inv_h;
     K.lg1[r] = (float)(0.6931471805599453 * S.inv_h);
@@ -537,7 +585,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   const SpecDev& So = L.spec[it->obs_species];
   K.p_obs = it->q_obs * K.inv_a;
   K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
-  K.f_obs = it->obs_at ? f_at_global(So, L.f64 + So.f_off, st->fit[it->obs_species], it->q_obs, K.E_obs)
+  K.f_obs = it->obs_at ? f_at_global(So, L.f64 + So.f_off, L.qnode + So.f_off, st->fit[it->obs_species], it->q_obs,
+                                     K.E_obs)
                         : L.f64[So.f_off + it->eval_idx];
   {
     const double obs_bf = 1.0 + K.eta[NI + 1] * K.f_obs;
@@ -718,7 +767,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
 // whose entry e is evaluated by thread e mod 256.  FP64 (PREC 0): every listed sample with FP64 kinematics and
 // integrand.  FP32 integrand (PREC 1): in-shell samples with FP64 kinematics, near samples with the FP32 finish.
 // The block's sums go to the task's record.  Units are taken 64 at a time (256 lists).
-template <int NI, int PREC>
+template <int NI, int PREC, bool ALT>
 __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
   constexpr int kLists = kBlock;  // lists per chunk: 64 units x 4 waves
@@ -777,10 +826,10 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
           int hj[D];
           double W = 0.0;
           if constexpr (PREC == 0) {
-            W = eval_sample<NI, double>(K, n, hj);
+            W = eval_sample<NI, double, ALT>(K, n, hj);
           } else {
-            if (kind == 0) W = eval_sample<NI, float>(K, n, hj);
-            else screen_sample<NI, true>(K, n, hj, &W);
+            if (kind == 0) W = eval_sample<NI, float, ALT>(K, n, hj);
+            else screen_sample<NI, true, ALT>(K, n, hj, &W);
           }
           accumulate<D>(W, hj, S1, S2, my_h, my_c);
         }
@@ -859,6 +908,8 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     tr[r].iq = tr[r].q + n_max;
     tr[r].f = tr[r].iq + n_max;
     tr[r].n = S.n;
+    tr[r].mode = 0;
+    tr[r].eta = (double)S.stat;
     tr[r].lq0 = S.lq0;
     tr[r].inv_h = S.inv_h;
     tslot[r] = k;
@@ -955,7 +1006,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       jac *= r * r * sc3[0][0];
       E[k] = sqrt(p * p + m[k] * m[k]);
       cut |= E[k] < it->e_cut;
-      f[k] = interp64(tr[k], r, &jn[k], &wt[k]);
+      f[k] = interp64<false>(tr[k], r, E[k], &jn[k], &wt[k]);
       src[k] = 1;
     }
     const double P2 = sx * sx + sy * sy + sz * sz;
@@ -969,7 +1020,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       f[NI] = 1.0 / (exp(fitc[2] + fitc[3] * E[NI]) - eta[NI]);
       src[NI] = 3;
     } else {
-      f[NI] = interp64(tr[NI], qc, &jn[NI], &wt[NI]);
+      f[NI] = interp64<false>(tr[NI], qc, E[NI], &jn[NI], &wt[NI]);
       src[NI] = 1;
     }
     if (cut) continue;
@@ -1207,7 +1258,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
 // Second pass: block b takes the consecutive in-shell tasks [b c, (b + 1) c), c = ceil(n / G) (the tasks of one
 // item are consecutive, so the block re-uses the staged map and tables).  Which block runs a task does not change
 // its result.
-template <int MASK, int PREC>
+template <int MASK, int PREC, bool ALT>
 __global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int c = (L.n_sh + gridDim.x - 1) / gridDim.x;
@@ -1220,10 +1271,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
     const int ni = L.items[item].nint;
     const bool stage = item != prev_item;
     prev_item = item;
-    if ((MASK & 1) && ni == 1) shell_run<1, PREC>(L, k, k1, smem, stage);
-    if ((MASK & 2) && ni == 2) shell_run<2, PREC>(L, k, k1, smem, stage);
-    if ((MASK & 4) && ni == 3) shell_run<3, PREC>(L, k, k1, smem, stage);
-    if ((MASK & 8) && ni == 4) shell_run<4, PREC>(L, k, k1, smem, stage);
+    if ((MASK & 1) && ni == 1) shell_run<1, PREC, ALT>(L, k, k1, smem, stage);
+    if ((MASK & 2) && ni == 2) shell_run<2, PREC, ALT>(L, k, k1, smem, stage);
+    if ((MASK & 4) && ni == 3) shell_run<3, PREC, ALT>(L, k, k1, smem, stage);
+    if ((MASK & 8) && ni == 4) shell_run<4, PREC, ALT>(L, k, k1, smem, stage);
     k = k1;
   }
 }
@@ -1466,6 +1517,46 @@ __global__ void k_gather(const GatherEntry* ge, int n_out, const GatherProc* gp,
 }
 
 // a(t), masses, extrapolation fits and the FP32 copy of f.  One block.
+// Not-a-knot cubic spline through (q_j, f_j) on the logarithmic grid q_j = exp(lq0 + h j): second derivatives M_j.
+// With h_j = q_{j+1} - q_j, continuity of S' at the interior nodes gives
+//   h_{j-1}/6 M_{j-1} + (h_{j-1} + h_j)/3 M_j + h_j/6 M_{j+1} = (f_{j+1} - f_j)/h_j - (f_j - f_{j-1})/h_{j-1};
+// a continuous third derivative at q_1 and q_{n-2} gives M_0 = (1 + h_0/h_1) M_1 - (h_0/h_1) M_2 and its mirror at
+// the upper end, which fold into the first and last interior rows.  The tridiagonal system in M_1 .. M_{n-2} is
+// diagonally dominant on a grid of growing spacing and is solved by forward elimination and back substitution
+// (one thread; c holds the eliminated upper diagonal).
+__device__ void spline_second_derivatives(int n, const double* qn, const double* f, double* M, double* c) {
+  auto hs = [&](int j) { return qn[j + 1] - qn[j]; };
+  double prev_c = 0.0, prev_d = 0.0;
+  double hl = hs(0), hr = hs(1);
+  for (int j = 1; j <= n - 2; ++j) {
+    double lo = hl / 6.0, di = (hl + hr) / 3.0, up = hr / 6.0;
+    const double rhs = (f[j + 1] - f[j]) / hr - (f[j] - f[j - 1]) / hl;
+    if (j == 1) {  // M_0 folded in
+      const double r0 = hl / hr;
+      di += lo * (1.0 + r0);
+      up -= lo * r0;
+      lo = 0.0;
+    }
+    if (j == n - 2) {  // M_{n-1} folded in
+      const double r1 = hr / hl;
+      di += up * (1.0 + r1);
+      lo -= up * r1;
+      up = 0.0;
+    }
+    const double den = di - lo * prev_c;
+    prev_c = up / den;
+    prev_d = (rhs - lo * prev_d) / den;
+    c[j] = prev_c;
+    M[j] = prev_d;
+    hl = hr;
+    if (j + 2 <= n - 1) hr = hs(j + 1);
+  }
+  for (int j = n - 3; j >= 1; --j) M[j] -= c[j] * M[j + 1];
+  const double h0 = hs(0), h1 = hs(1), ha = hs(n - 3), hb = hs(n - 2);
+  M[0] = (1.0 + h0 / h1) * M[1] - (h0 / h1) * M[2];
+  M[n - 1] = (1.0 + hb / ha) * M[n - 2] - (hb / ha) * M[n - 3];
+}
+
 __global__ void k_prepare(DevState* st, const SpecDev* spec, int n_species, const double* f64, float* f32,
                           int64_t n_f) {
   const double t = st->t;
@@ -1523,6 +1614,19 @@ __global__ void k_prepare(DevState* st, const SpecDev* spec, int n_species, cons
       atomicMax(&st->err, 3);
     } else {
       for (int k = 0; k < 4; ++k) st->fit[s][k] = fit[k];
+    }
+    if (S.interp == 1) spline_second_derivatives(S.n, S.qn, f, S.aux, S.tmp);
+  }
+  __syncthreads();
+  // equilibrium-exact rule: node energies E_j = sqrt((q_j / a)^2 + m^2) and y_j = log(1/f_j + eta)
+  for (int s = 0; s < n_species; ++s) {
+    const SpecDev& S = spec[s];
+    if (S.interp != 2) continue;
+    const double m = st->m[s], eta = (double)S.stat;
+    for (int j = threadIdx.x; j < S.n; j += blockDim.x) {
+      const double p = S.qn[j] / a;
+      S.aux[j] = sqrt(p * p + m * m);
+      S.tmp[j] = log(1.0 / f64[S.f_off + j] + eta);
     }
   }
 }
@@ -1591,10 +1695,13 @@ hipError_t launch_sample_t(const SampleLaunch& L, hipStream_t s) {
 
 template <int MASK>
 hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
-  if (L.precision == 0) {
-    hipLaunchKernelGGL((k_shell<MASK, 0>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
+  const dim3 g(L.sh_grid), b(kBlock);
+  if (L.any_interp) {
+    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, true>), g, b, L.lds_bytes, s, L);
+    else hipLaunchKernelGGL((k_shell<MASK, 1, true>), g, b, L.lds_bytes, s, L);
   } else {
-    hipLaunchKernelGGL((k_shell<MASK, 1>), dim3(L.sh_grid), dim3(kBlock), L.lds_bytes, s, L);
+    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, false>), g, b, L.lds_bytes, s, L);
+    else hipLaunchKernelGGL((k_shell<MASK, 1, false>), g, b, L.lds_bytes, s, L);
   }
   return hipGetLastError();
 }

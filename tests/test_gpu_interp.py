@@ -1,0 +1,112 @@
+"""GPU parity of the interpolation rules of f between grid nodes (Sec. III.B: not-a-knot cubic spline in linear q;
+log(1/f + eta) linear in E) against the oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, assert_items_close, gpu_available, item_scale, point_scale, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _with_interp(w, interp):
+    for s in w.species:
+        s.interp = interp
+    return w
+
+
+def _oracle_items(ow, uids):
+    items, n = ow.items()
+    by = {items[i].uid: items[i] for i in range(n)}
+    sel = [by[int(u)] for u in uids]
+    return (ob.Item * len(sel))(*sel), len(sel)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("interp", [wl.INTERP_SPLINE, wl.INTERP_EQEXACT])
+@pytest.mark.parametrize("which", ["2to2", "2to3"])
+def test_interp_frozen_maps_parity(which, interp, precision):
+    bm = _bm()
+    if which == "2to2":
+        w, N, nitn = wl.w22_mb(), 10_000, 3
+    else:
+        w, N, nitn = wl.w23_be(n_grid=32, N=1 << 14), 1 << 14, 2
+    _with_interp(w, interp)
+    say("interp %s rule=%d precision=%d" % (which, interp, precision))
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=6, epoch=2, precision=precision, freeze_maps=1, n_iter=nitn, n_samples=N)
+    C, S = ctx.collision(-1, -1, opts)
+    res = ctx.item_results(nitn)
+    ow = ob.OracleWorld(w)
+    items, n = _oracle_items(ow, res["uid"])
+    rc, r = ow.run_items(items, n, N, nitn, seed=6, epoch=2, adapt=False)
+    assert rc == 0
+    tol = TOL[precision]
+    if interp == wl.INTERP_SPLINE and precision == 0:
+        # In the tail of a steep f the spline between nodes is a near-cancellation of its curvature terms
+        # ((A^3 - A) M_j h_j^2 / 6 ~ 1e-5 against f ~ 1e-9 on the 2->3 grid), so the ~1e-14 relative rounding
+        # differences of two correct solves of the spline system (tridiagonal elimination here, pivoted dense
+        # elimination in the oracle) reach the interpolated f amplified by that ratio.
+        tol = 1e-10
+    if which == "2to3" and precision == 0:
+        # 2^14 samples on the uniform map leave a few in-shell samples per item, and each carries the Gaussian's
+        # amplification of ulp-level energy differences ((dE / sigma_E^2) x 1e-14 at sigma_E = 0.005): the
+        # few-sample tolerance of the other parity tests applies
+        tol = 1e-10
+    assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
+    Co, So = ow.combine(items, n, r["Ibar"], r["sigma"], 0)
+    scale = point_scale(items, n, r["Ibar"], 0, len(C))
+    say("C max err / scale %.3e" % np.max(np.abs(C - Co) / scale))
+    assert np.all(np.abs(C - Co) <= tol * scale)
+
+
+@pytest.mark.parametrize("interp", [wl.INTERP_SPLINE, wl.INTERP_EQEXACT])
+def test_interp_points_off_the_grid(interp):
+    """The observed leg between nodes takes its f by the same rule (global-memory path of the observed leg)."""
+    bm = _bm()
+    w = _with_interp(wl.w22_mb(), interp)
+    sp = w.species[0]
+    qg = wl.log_nodes(sp.q_min, sp.q_max, sp.n_grid)
+    q = np.array([np.sqrt(qg[5] * qg[6]), 0.3 * qg[14] + 0.7 * qg[15], 0.5 * sp.q_min])
+    N, nitn = 10_000, 2
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=3, freeze_maps=1, n_iter=nitn, n_samples=N)
+    C, S = ctx.collision(-1, 0, opts, eval_q=q)
+    res = ctx.item_results(nitn)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items_at(q, species=0)
+    by = {items[i].uid: items[i] for i in range(n)}
+    sel = [by[int(u)] for u in res["uid"]]
+    items = (ob.Item * len(sel))(*sel)
+    rc, r = ow.run_items(items, n, N, nitn, seed=3, adapt=False)
+    assert rc == 0
+    assert_items_close(res["I_it"], r["I_it"], TOL[0], "I_it", scale=item_scale(items, n, r["Ibar"]))
+
+
+def test_interp_rules_differ_and_vjp_rejects_them():
+    """Negative control: the three rules give different C on the same samples; the adjoint refuses the others."""
+    bm = _bm()
+    Cs = []
+    for interp in (wl.INTERP_LINLOG, wl.INTERP_SPLINE, wl.INTERP_EQEXACT):
+        ctx = bm.from_workload(_with_interp(wl.w22_mb(), interp))
+        C, S = ctx.collision(-1, -1, bm.default_opts(seed=1, freeze_maps=1, n_iter=2, n_samples=10_000))
+        Cs.append(C)
+    assert np.max(np.abs(Cs[1] - Cs[0]) / (np.abs(Cs[0]) + 1e-300)) > 1e-6
+    assert np.max(np.abs(Cs[2] - Cs[0]) / (np.abs(Cs[0]) + 1e-300)) > 1e-6
+    ctx = bm.from_workload(_with_interp(wl.w22_mb(), wl.INTERP_SPLINE))
+    opts = bm.default_opts(seed=3, epoch=2, n_iter=1, freeze_maps=1, eval_stride=1, n_samples=1000)
+    ni, no = ctx.plan_size(-1, -1, opts)
+    with pytest.raises(bm.BmcError):
+        ctx.vjp(np.ones(no), -1, -1, opts)

@@ -118,11 +118,14 @@ def test_2to4_full_size_sampled_items(precision):
 
 
 # ------------------------------------------------------------------------------------------------ steps
-@pytest.mark.parametrize("method", [0, 1])
-def test_step_matches_oracle_with_frozen_maps(method):
+@pytest.mark.parametrize("method,interp", [(0, wl.INTERP_LINLOG), (1, wl.INTERP_LINLOG), (1, wl.INTERP_SPLINE),
+                                           (1, wl.INTERP_EQEXACT)])
+def test_step_matches_oracle_with_frozen_maps(method, interp):
+    """Euler/Heun step against the oracle's step; with the spline and equilibrium-exact rules the Heun stage's f*
+    needs the rule's node data recomputed on the device."""
     bm = _bm()
     q = wl.log_nodes(0.02, 14.0, 48)
-    w = wl.Workload("st", [wl.Species("phi", wl.BOSE, 48, 0.02, 14.0, wl.f_fermi_step(q), m0=1.0)],
+    w = wl.Workload("st", [wl.Species("phi", wl.BOSE, 48, 0.02, 14.0, wl.f_fermi_step(q), m0=1.0, interp=interp)],
                     [wl.Process([0, 0], [0, 0], sigma_E=0.02, n_samples=1 << 12, n_iter=2)])
     ctx = bm.from_workload(w)
     dt = ctx.step(method, -1.0, 0.1, 1e3, bm.default_opts(seed=2, epoch=4, freeze_maps=1))
