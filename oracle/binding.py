@@ -79,6 +79,9 @@ def lib():
         L.orc_stat_factor.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
         L.orc_stat_factor.restype = C.c_double
         L.orc_integrand_batch.argtypes = [C.POINTER(World), C.POINTER(Item), C.c_int64, dp, dp]
+        L.orc_kinematic_F.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
+        L.orc_kinematic_F.restype = C.c_double
+        L.orc_exact22.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), dp]
         L.orc_point_width.argtypes = [C.POINTER(Process), C.c_int, dp]
         L.orc_point_width.restype = C.c_double
         L.orc_width_control.argtypes = [C.POINTER(Process), C.c_int, dp, dp, C.c_double]
@@ -217,6 +220,12 @@ class OracleWorld:
         w = lib().orc_width_control(C.byref(self.pr[proc]), len(sel), _dp(Ib), _dp(sg), self.pr[proc].sigma_E)
         self.pr[proc].sigma_E = w
         return w
+
+    def exact22(self, items, n_items):
+        """Exact-delta estimates of 2->2 items (the semi-analytic reduction); (rc, I)."""
+        I = np.zeros(max(1, n_items))
+        rc = lib().orc_exact22(C.byref(self.world), n_items, items, _dp(I))
+        return rc, I[:n_items]
 
     def point_width(self, proc, E):
         E = np.ascontiguousarray(E, dtype=np.float64)

@@ -1190,6 +1190,108 @@ int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double
 }
 
 /* =====================================================================================================
+ * Exact-delta 2->2 (Sec. IV "semi-analytical" reduction, Eq. 22; Appendix B).
+ * ===================================================================================================== */
+
+/* The angular kinematic function F = int_{-1}^{1} dcos(theta) |M|^2 pi / sqrt(-a) Theta(b^2 - 4ac) of Appendix B, in
+ * closed form.  With eps = p1 p3 cos(theta), kappa = p1^2 + p3^2 and u = 2 eps:
+ *   -a = 4 px^2 (kappa - u), so pi / sqrt(-a) = pi / (2 px sqrt(kappa - u));
+ *   b^2 - 4ac = 16 px^2 p3^2 sin^2(theta) (4 px^2 (kappa - u) - (G + u)^2), G = Q + 2 gamma,
+ * so the allowed u form the interval between the roots of (G + u)^2 = 4 px^2 (kappa - u),
+ *   u = -(G + 2 px^2) -+ 2 px sqrt(G + px^2 + kappa),
+ * cut to [-2 p1 p3, 2 p1 p3], and
+ *   F = |M|^2 pi (sqrt(kappa - u_lo) - sqrt(kappa - u_hi)) / (2 p1 p3 px). */
+double orc_kinematic_F(double p1, double p3, double px, double G, double M2) {
+  const double kappa = p1 * p1 + p3 * p3;
+  const double disc = G + px * px + kappa;
+  if (!(disc >= 0.0)) return 0.0;
+  const double mid = -(G + 2.0 * px * px), half = 2.0 * px * sqrt(disc);
+  const double U = 2.0 * p1 * p3;
+  const double lo = fmax(-U, mid - half), hi = fmin(U, mid + half);
+  if (!(hi > lo)) return 0.0;
+  return M2 * (0.5 * TWO_PI) * (sqrt(kappa - lo) - sqrt(kappa - hi)) / (2.0 * p1 * p3 * px);
+}
+
+/* Trapezoid weight of node j of a species grid for int dp (physical p = q / a): the rule in ln q,
+ * int g dq = int g q dln q, gives h q_j (1/2 at the two ends), and dp = dq / a. */
+static double trap_weight(const orc_species* s, int j, double a) {
+  const double h = (log(s->q_max) - log(s->q_min)) / (double)(s->n_grid - 1);
+  const double t = (j == 0 || j == s->n_grid - 1) ? 0.5 : 1.0;
+  return t * h * orc_grid_q(s, j) / a;
+}
+
+/* One item.  Positions: 1 the observed particle, 2 its partner on the same side (the conserved particle of the
+ * Monte Carlo roles), 3 and 4 the opposite side in index order.
+ *   backward (gain) term: C_BW = 2/(2 pi)^4 1/(2 E1) int dp3 p3^2/(2E3) int dp4 p4^2/(2E4) F f3 f4 (1 + eta1 f1)(1 + eta2 f2)
+ *     with E2 = E3 + E4 - E1 >= m2, Q = m1^2 - m2^2 + m3^2 + m4^2, gamma = E3 E4 - E1 E3 - E1 E4;
+ *   forward (loss) term: C_FW = 2/(2 pi)^4 1/(2 E1) int dp2 p2^2/(2E2) int dp3 p3^2/(2E3) F' f1 f2 (1 + eta3 f3)(1 + eta4 f4)
+ *     with E4 = E1 + E2 - E3 >= m4, Q' = m1^2 + m2^2 + m3^2 - m4^2, gamma' = E1 E2 - E1 E3 - E2 E3 and p2 in the
+ *     place of p4.
+ * The dependent particle's f comes from orc_f_at (interpolation or fit); the integrated momenta run over the grid
+ * nodes of their species. */
+static int exact22_item(const orc_world* w, const orc_item* it, const double* fits, double* out) {
+  const orc_process* P = &w->procs[it->proc];
+  if (P->n_in != 2 || P->n_out != 2) return ORC_EINVAL;
+  item_ctx c;
+  int rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  const int i1 = c.i_obs, i2 = c.i_cons, i3 = c.integ[0], i4 = c.integ[1];
+  const double a = c.a, M2 = P->coupling * P->coupling;
+  const double m1 = c.m[i1], m2 = c.m[i2], m3 = c.m[i3], m4 = c.m[i4];
+  const double e1 = c.eta[i1], e2 = c.eta[i2], e3 = c.eta[i3], e4 = c.eta[i4];
+  const double p1 = c.q_obs / a, E1 = sqrt(p1 * p1 + m1 * m1), f1 = c.f_obs;
+  const orc_species *s2 = c.sp[i2], *s3 = c.sp[i3], *s4 = c.sp[i4];
+  const int want_gain = P->term_mode == ORC_TERMS_NET || it->term == 0;
+  const int want_loss = P->term_mode == ORC_TERMS_NET || it->term == 1;
+  long double gain = 0.0L, loss = 0.0L;
+  if (want_gain)
+    for (int j3 = 0; j3 < s3->n_grid; ++j3) {
+      const double p3 = orc_grid_q(s3, j3) / a, E3 = sqrt(p3 * p3 + m3 * m3), f3 = s3->f[j3];
+      for (int j4 = 0; j4 < s4->n_grid; ++j4) {
+        const double p4 = orc_grid_q(s4, j4) / a, E4 = sqrt(p4 * p4 + m4 * m4), f4 = s4->f[j4];
+        const double E2 = E3 + E4 - E1;
+        if (!(E2 >= m2)) continue;
+        const double p2 = sqrt(E2 * E2 - m2 * m2);
+        const double f2 = orc_f_at(s2, c.fit[i2], a * p2, E2);
+        const double G = m1 * m1 - m2 * m2 + m3 * m3 + m4 * m4 + 2.0 * (E3 * E4 - E1 * E3 - E1 * E4);
+        const double F = orc_kinematic_F(p1, p3, p4, G, M2);
+        gain += (long double)(trap_weight(s3, j3, a) * trap_weight(s4, j4, a) * (p3 * p3 / (2.0 * E3)) *
+                              (p4 * p4 / (2.0 * E4)) * F * (f3 * f4 * (1.0 + e1 * f1) * (1.0 + e2 * f2)));
+      }
+    }
+  if (want_loss)
+    for (int j2 = 0; j2 < s2->n_grid; ++j2) {
+      const double p2 = orc_grid_q(s2, j2) / a, E2 = sqrt(p2 * p2 + m2 * m2), f2 = s2->f[j2];
+      for (int j3 = 0; j3 < s3->n_grid; ++j3) {
+        const double p3 = orc_grid_q(s3, j3) / a, E3 = sqrt(p3 * p3 + m3 * m3), f3 = s3->f[j3];
+        const double E4 = E1 + E2 - E3;
+        if (!(E4 >= m4)) continue;
+        const double p4 = sqrt(E4 * E4 - m4 * m4);
+        const double f4 = orc_f_at(s4, c.fit[i4], a * p4, E4);
+        const double G = m1 * m1 + m2 * m2 + m3 * m3 - m4 * m4 + 2.0 * (E1 * E2 - E1 * E3 - E2 * E3);
+        const double F = orc_kinematic_F(p1, p3, p2, G, M2);
+        loss += (long double)(trap_weight(s2, j2, a) * trap_weight(s3, j3, a) * (p2 * p2 / (2.0 * E2)) *
+                              (p3 * p3 / (2.0 * E3)) * F * (f1 * f2 * (1.0 + e3 * f3) * (1.0 + e4 * f4)));
+      }
+    }
+  const double pref = 2.0 / pow(TWO_PI, 4.0) / (2.0 * E1);
+  if (P->term_mode == ORC_TERMS_NET) *out = pref * (double)(gain - loss);
+  else *out = pref * (double)(it->term == 0 ? gain : loss);
+  return ORC_OK;
+}
+
+int orc_exact22(const orc_world* w, int n_items, const orc_item* items, double* I) {
+  double fits[4 * ORC_MAXSPECIES];
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  for (int i = 0; i < n_items; ++i) {
+    rc = exact22_item(w, &items[i], fits, &I[i]);
+    if (rc) return rc;
+  }
+  return ORC_OK;
+}
+
+/* =====================================================================================================
  * Log-space time stepping (Sec. III.C).
  * ===================================================================================================== */
 

@@ -125,6 +125,14 @@ int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, i
 int orc_run_items(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
                   uint64_t seed, uint32_t epoch, int adapt, double* maps, double* I_it, double* V_it, double* Ibar,
                   double* sigma, int n_threads);
+/* Exact-delta 2->2 (Sec. IV; Appendix B): the angular kinematic function for observed momentum p1, integrated
+ * momentum p3 and the other integrated momentum px (p4 of the backward term, p2 of the forward term), with
+ * G = Q + 2 gamma of that term, and |M|^2 = M2. */
+double orc_kinematic_F(double p1, double p3, double px, double G, double M2);
+/* Per item of a 2->2 process, the exact-delta estimate of the same single-position contribution the Monte Carlo
+ * items estimate: the two-dimensional reduction with the trapezoidal rule in ln q on the grid nodes of the two
+ * integrated species.  I[i] for items[i]; ORC_EINVAL for an item of another process kind. */
+int orc_exact22(const orc_world* w, int n_items, const orc_item* items, double* I);
 void orc_combine(const orc_world* w, int n_items, const orc_item* items, const double* Ibar, const double* sig,
                  int species, double* C, double* sigma);
 int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, uint32_t epoch, int adapt,
