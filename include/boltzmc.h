@@ -210,6 +210,17 @@ int bmc_plan_size(bmc_ctx* ctx, int process, int species, const bmc_run_opts* op
 int bmc_collision(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
                   double* sigma_out, size_t n_out, int mem);
 
+/* Exact-delta 2->2 path (Sec. IV's two-dimensional reduction; Appendix B): the same outputs as bmc_collision for
+ * the same selection and options, computed without Monte Carlo and without the Gaussian: per item, the integral
+ * over two momentum magnitudes with energy conservation exact and the angular kinematic function in closed form,
+ * by the trapezoidal rule in ln q on the grid nodes of the integrated species (the gain term over the opposite
+ * side's momenta, the loss term over the partner's and one opposite momentum).  sigma_out is 0.  Every selected
+ * process must be 2->2 with constant |M|^2 (BMC_EUNSUP otherwise).  Sampling options (n_samples, n_iter, seed,
+ * epoch, precision, launch, freeze_maps) are ignored; Vegas maps and epochs are untouched.  bmc_item_results then
+ * reports the per-item values with one iteration. */
+int bmc_collision_exact22(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
+                          double* sigma_out, size_t n_out, int mem);
+
 /* Per-item results of the last bmc_collision (items in uid order, n = its n_items): uid, multiplicity-free
  * estimate Ibar and sigma, and per-iteration I and V (n x n_iter each).  Any pointer may be NULL. */
 int bmc_item_results(bmc_ctx* ctx, uint32_t* uids, double* Ibar, double* sigma, double* I_it, double* V_it,

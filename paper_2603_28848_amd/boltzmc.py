@@ -65,6 +65,8 @@ _SIGS = {
     "bmc_default_process_params": [C.POINTER(ProcessParams)],
     "bmc_set_coupling": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_interp": [C.c_void_p, C.c_int, C.c_int],
+    "bmc_collision_exact22": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.c_int],
     "bmc_get_width": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
     "bmc_set_width": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_expansion": [C.c_void_p, C.c_int, C.c_double, C.c_double],
@@ -279,6 +281,23 @@ class Context:
             return out, sigma
         Cv, S = np.zeros(no), np.zeros(no)
         self._check(lib().bmc_collision(self.h, process, species, C.byref(opts), _ptr(Cv), _ptr(S), no, MEM_HOST))
+        return Cv, S
+
+    def collision_exact22(self, process=-1, species=-1, opts: Optional[RunOpts] = None, eval_q=None):
+        """C of 2->2 processes by the exact-delta reduction (host arrays; sigma is 0)."""
+        opts = opts or default_opts()
+        if eval_q is not None:
+            q = np.ascontiguousarray(eval_q, dtype=np.float64)
+            opts = RunOpts.from_buffer_copy(opts)
+            opts.eval_q = q.ctypes.data
+            opts.n_eval = q.size
+            self._eval_q_keep = q
+        ni, no = self.plan_size(process, species, opts)
+        self.ensure_workspace(opts.n_samples, opts.n_iter)
+        self._last_items = ni
+        Cv, S = np.zeros(no), np.zeros(no)
+        self._check(lib().bmc_collision_exact22(self.h, process, species, C.byref(opts), _ptr(Cv), _ptr(S), no,
+                                                MEM_HOST))
         return Cv, S
 
     def item_results(self, n_iter):

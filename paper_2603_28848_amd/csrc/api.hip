@@ -1319,6 +1319,37 @@ int bmc_collision(bmc_ctx* c, int process, int species, const bmc_run_opts* o, d
   return finish_check(c);
 }
 
+int bmc_collision_exact22(bmc_ctx* c, int process, int species, const bmc_run_opts* o, double* C_out,
+                          double* sigma_out, size_t n_out, int mem) {
+  if (!c || !C_out) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  if (process < -1 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
+  for (int p = 0; p < (int)c->pr.size(); ++p)
+    if ((process < 0 || p == process) && !(c->pr[p].n_in == 2 && c->pr[p].n_out == 2))
+      return fail(c, BMC_EUNSUP, "the exact-delta path takes 2->2 processes only");
+  HIPCHK(c, hipSetDevice(c->device));
+  rc = get_plan(c, c->plan, process, species, o);
+  if (rc) return rc;
+  Plan& P = c->plan;
+  if ((size_t)P.n_out != n_out) return fail(c, BMC_EINVAL, "n_out does not match the plan");
+  hipStream_t s = c->stream;
+  HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
+  HIPCHK(c, launch_exact22(P.d_items, (int)P.items.size(), c->spec(), c->f64(), c->qnode(), c->st(), P.d_res_I,
+                           P.d_res_V, s));
+  HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, 1, P.d_item_Ibar, P.d_item_sig,
+                           P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));
+  HIPCHK(c, launch_gather(P.d_gather, P.n_out, P.d_gproc, P.d_slot_C, P.d_slot_S2, c->spec(), c->f64(), P.d_out_C,
+                          P.d_out_S, s));
+  c->last_n_iter = 1;
+  const hipMemcpyKind kind = mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(c, hipMemcpyAsync(C_out, P.d_out_C, 8 * n_out, kind, s));
+  if (sigma_out) HIPCHK(c, hipMemcpyAsync(sigma_out, P.d_out_S, 8 * n_out, kind, s));
+  return finish_check(c);
+}
+
 int bmc_item_results(bmc_ctx* c, uint32_t* uids, double* Ibar, double* sigma, double* I_it, double* V_it, int n,
                      int n_iter) {
   if (!c) return BMC_EINVAL;

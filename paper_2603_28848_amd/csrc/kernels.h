@@ -63,6 +63,10 @@ hipError_t launch_combine(const ItemRec* items, int n_items, const double* res_I
                           double* item_Ibar, double* item_sig, const int* slot_begin, const int* slot_items,
                           int n_slots, double* slot_C, double* slot_S2, hipStream_t s);
 
+// Exact-delta 2->2: one block per item (2->2 items only), the estimate into iteration 0 of res_I with V = 0.
+hipError_t launch_exact22(const ItemRec* items, int n_items, const SpecDev* spec, const double* f64,
+                          const double* qnode, const DevState* st, double* res_I, double* res_V, hipStream_t s);
+
 // Width controller after an evaluation (processes with adapt set): r = sum sigma / sum |Ibar| over the process's
 // items in item order; the process's width in st->width is divided or multiplied by the factor and clamped.
 hipError_t launch_width_control(const ItemRec* items, int n_items, const double* item_Ibar, const double* item_sig,

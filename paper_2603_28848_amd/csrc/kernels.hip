@@ -1450,6 +1450,112 @@ __global__ void k_combine(const ItemRec* items, const double* res_I, const doubl
   slot_S2[k] = S2;
 }
 
+// ------------------------------------------------------------------------------------------------------
+// Exact-delta 2->2 (the two-dimensional reduction of the 2->2 collision integral with energy conservation exact).
+// Angular kinematic function in closed form: with kappa = p1^2 + p3^2 and G = Q + 2 gamma of the term, the allowed
+// u = 2 p1 p3 cos(theta) lie between -(G + 2 px^2) -+ 2 px sqrt(G + px^2 + kappa), cut to [-2 p1 p3, 2 p1 p3], and
+// F = |M|^2 pi (sqrt(kappa - u_lo) - sqrt(kappa - u_hi)) / (2 p1 p3 px).
+__device__ __forceinline__ double kinematic_F(double p1, double p3, double px, double G, double M2) {
+  const double kappa = p1 * p1 + p3 * p3;
+  const double disc = G + px * px + kappa;
+  if (!(disc >= 0.0)) return 0.0;
+  const double mid = -(G + 2.0 * px * px), half = 2.0 * px * sqrt(disc);
+  const double U = 2.0 * p1 * p3;
+  const double lo = fmax(-U, mid - half), hi = fmin(U, mid + half);
+  if (!(hi > lo)) return 0.0;
+  return M2 * 3.141592653589793 * (sqrt(kappa - lo) - sqrt(kappa - hi)) / (U * px);
+}
+
+// One block per item.  Roles of a 2->2 item: integrated 0 and 1 (the opposite side, "3" and "4"), conserved 2 (the
+// observed leg's partner, "2"), observed 3 ("1").  The gain term integrates over p3, p4 on the grid nodes of their
+// species (E2 = E3 + E4 - E1 fixed), the loss term over p2, p3 (E4 = E1 + E2 - E3 fixed); the trapezoidal rule in
+// ln q, h q_j / a per node (half at the ends).  The dependent particle's f comes by the species' interpolation rule
+// or the fit.  Pairs are taken by thread index mod 256, then summed by the fixed wave tree; the estimate goes to
+// iteration 0 of the item's results with V = 0.
+__global__ __launch_bounds__(kBlock) void k_exact22(const ItemRec* items, const SpecDev* spec, const double* f64,
+                                                    const double* qnode, const DevState* st, double* res_I,
+                                                    double* res_V) {
+  __shared__ double red[2 * kWaves];
+  const ItemRec& it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const double a = st->a, inv_a = st->inv_a, M2 = it.coupling2;
+  int sp[4];
+  double m[4], eta[4];
+  for (int r = 0; r < 4; ++r) {
+    sp[r] = it.r_species[r];
+    m[r] = st->m[sp[r]];
+    eta[r] = (double)spec[sp[r]].stat;
+  }
+  // positions 1..4 of the reduction -> roles 3, 2, 0, 1
+  const SpecDev &S1 = spec[sp[3]], &S2 = spec[sp[2]], &S3 = spec[sp[0]], &S4 = spec[sp[1]];
+  const double m1 = m[3], m2 = m[2], m3 = m[0], m4 = m[1];
+  const double e1 = eta[3], e2 = eta[2], e3 = eta[0], e4 = eta[1];
+  const double p1 = it.q_obs * inv_a, E1 = sqrt(p1 * p1 + m1 * m1);
+  const double f1 = it.obs_at ? f_at_global(S1, f64 + S1.f_off, qnode + S1.f_off, st->fit[sp[3]], it.q_obs, E1)
+                              : f64[S1.f_off + it.eval_idx];
+  const bool want_gain = it.net || it.term == 0, want_loss = it.net || it.term == 1;
+  double gain = 0.0, loss = 0.0;
+  if (want_gain) {
+    const int n3 = S3.n, n4 = S4.n;
+    const double w3h = 1.0 / S3.inv_h * inv_a, w4h = 1.0 / S4.inv_h * inv_a;
+    for (int idx = tid; idx < n3 * n4; idx += kBlock) {
+      const int j3 = idx / n4, j4 = idx - j3 * n4;
+      const double q3 = qnode[S3.f_off + j3], q4 = qnode[S4.f_off + j4];
+      const double p3 = q3 * inv_a, p4 = q4 * inv_a;
+      const double E3 = sqrt(p3 * p3 + m3 * m3), E4 = sqrt(p4 * p4 + m4 * m4);
+      const double E2 = E3 + E4 - E1;
+      if (!(E2 >= m2)) continue;
+      const double p2 = sqrt(E2 * E2 - m2 * m2);
+      const double f2 = f_at_global(S2, f64 + S2.f_off, qnode + S2.f_off, st->fit[sp[2]], a * p2, E2);
+      const double G = m1 * m1 - m2 * m2 + m3 * m3 + m4 * m4 + 2.0 * (E3 * E4 - E1 * E3 - E1 * E4);
+      const double F = kinematic_F(p1, p3, p4, G, M2);
+      const double t3 = (j3 == 0 || j3 == n3 - 1) ? 0.5 : 1.0, t4 = (j4 == 0 || j4 == n4 - 1) ? 0.5 : 1.0;
+      const double f3 = f64[S3.f_off + j3], f4 = f64[S4.f_off + j4];
+      gain += (t3 * w3h * q3) * (t4 * w4h * q4) * (p3 * p3 / (2.0 * E3)) * (p4 * p4 / (2.0 * E4)) * F *
+              (f3 * f4 * (1.0 + e1 * f1) * (1.0 + e2 * f2));
+    }
+  }
+  if (want_loss) {
+    const int n2 = S2.n, n3 = S3.n;
+    const double w2h = 1.0 / S2.inv_h * inv_a, w3h = 1.0 / S3.inv_h * inv_a;
+    for (int idx = tid; idx < n2 * n3; idx += kBlock) {
+      const int j2 = idx / n3, j3 = idx - j2 * n3;
+      const double q2 = qnode[S2.f_off + j2], q3 = qnode[S3.f_off + j3];
+      const double p2 = q2 * inv_a, p3 = q3 * inv_a;
+      const double E2 = sqrt(p2 * p2 + m2 * m2), E3 = sqrt(p3 * p3 + m3 * m3);
+      const double E4 = E1 + E2 - E3;
+      if (!(E4 >= m4)) continue;
+      const double p4 = sqrt(E4 * E4 - m4 * m4);
+      const double f4 = f_at_global(S4, f64 + S4.f_off, qnode + S4.f_off, st->fit[sp[1]], a * p4, E4);
+      const double G = m1 * m1 + m2 * m2 + m3 * m3 - m4 * m4 + 2.0 * (E1 * E2 - E1 * E3 - E2 * E3);
+      const double F = kinematic_F(p1, p3, p2, G, M2);
+      const double t2 = (j2 == 0 || j2 == n2 - 1) ? 0.5 : 1.0, t3 = (j3 == 0 || j3 == n3 - 1) ? 0.5 : 1.0;
+      const double f2 = f64[S2.f_off + j2], f3 = f64[S3.f_off + j3];
+      loss += (t2 * w2h * q2) * (t3 * w3h * q3) * (p2 * p2 / (2.0 * E2)) * (p3 * p3 / (2.0 * E3)) * F *
+              (f1 * f2 * (1.0 + e3 * f3) * (1.0 + e4 * f4));
+    }
+  }
+  gain = wave_sum(gain);
+  loss = wave_sum(loss);
+  const int wave = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[wave] = gain;
+    red[kWaves + wave] = loss;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double g = 0.0, l = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      g += red[w];
+      l += red[kWaves + w];
+    }
+    const double pref = 2.0 / (1558.5454565440386 * 2.0 * E1);  // 2 / ((2 pi)^4 2 E1)
+    const double I = pref * (it.net ? g - l : (it.term == 0 ? g : l));
+    res_I[it.res_off * kMaxIter] = I;
+    res_V[it.res_off * kMaxIter] = 0.0;
+  }
+}
+
 // One thread per process; the sums run over the items in plan order (the same order as the evaluation's item
 // results), so the decision depends on the results alone.
 __global__ void k_width_control(const ItemRec* items, int n_items, const double* item_Ibar, const double* item_sig,
@@ -1797,6 +1903,13 @@ hipError_t launch_combine(const ItemRec* items, int n_items, const double* res_I
   if (n_slots <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_combine, dim3((n_slots + 255) / 256), dim3(256), 0, s, items, res_I, res_V, n_iter, item_Ibar,
                      item_sig, slot_begin, slot_items, n_slots, slot_C, slot_S2);
+  return hipGetLastError();
+}
+
+hipError_t launch_exact22(const ItemRec* items, int n_items, const SpecDev* spec, const double* f64,
+                          const double* qnode, const DevState* st, double* res_I, double* res_V, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_exact22, dim3(n_items), dim3(kBlock), 0, s, items, spec, f64, qnode, st, res_I, res_V);
   return hipGetLastError();
 }
 

@@ -1,0 +1,140 @@
+"""Thermalisation runs on the GPU path (Sec. V): a single scalar (m = 1, |M|^2 = lambda^2, H = 0) starts from the
+non-thermal f0 = 1 / (1 + e^{(q - p0)/w}) on a logarithmic grid and evolves under phi phi -> phi phi or
+phi phi <-> phi phi phi with log-space Heun steps of adaptive size; particle number and energy are recorded along
+the way, and the end state is compared with the Bose-Einstein distribution fixed by the conserved quantities.
+
+The moments are diagnostics on the host: N ~ int q^2 f dq and E ~ int q^2 E f dq by the trapezoidal rule in ln q
+on the grid (their common factor 4 pi / (2 pi)^3 cancels in N/N0 and E/E0).
+
+    python -m paper_2603_28848_amd.thermalize --process 2to2 --steps 400
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from typing import Dict, List
+
+import numpy as np
+
+from . import workloads as wl
+
+
+def moments(q: np.ndarray, f: np.ndarray, m: float, a: float = 1.0):
+    """(N, E) ~ (int p^2 f dp, int p^2 E f dp) by the trapezoidal rule in ln q, p = q / a."""
+    lq = np.log(q)
+    h = lq[1] - lq[0]
+    wt = np.full(len(q), h)
+    wt[0] = wt[-1] = 0.5 * h
+    p = q / a
+    E = np.sqrt(p * p + m * m)
+    w = wt * p ** 3  # dp = p dln q
+    return float(np.sum(w * f)), float(np.sum(w * E * f))
+
+
+def equilibrium_for(q: np.ndarray, N: float, E: float, m: float, mu_zero: bool = False):
+    """(T, mu) of the Bose-Einstein distribution with the same N and E on the same grid and rule (mu = 0 fixes T by
+    E alone: the number-changing process drives mu to 0)."""
+    from scipy import optimize
+
+    def mom(T, mu):
+        return moments(q, wl.f_equilibrium(q, m, T, wl.BOSE, mu), m)
+
+    if mu_zero:
+        T = optimize.brentq(lambda T: mom(T, 0.0)[1] - E, 0.05, 50.0)
+        return T, 0.0
+
+    def res(x):
+        T, mu = x[0], min(x[1], m - 1e-9)
+        n, e = mom(T, mu)
+        return [math.log(n / N), math.log(e / E)]
+
+    sol = optimize.fsolve(res, [1.5, 0.0], full_output=True)
+    T, mu = float(sol[0][0]), float(min(sol[0][1], m - 1e-9))
+    return T, mu
+
+
+def fit_T_mu(q: np.ndarray, f: np.ndarray, m: float, lo: float = 0.5, hi: float = 8.0):
+    """Least-squares line log(1/f + 1) = (E - mu) / T over lo <= q <= hi (Bose-Einstein form)."""
+    sel = (q >= lo) & (q <= hi)
+    E = np.sqrt(q[sel] ** 2 + m * m)
+    y = np.log(1.0 / f[sel] + 1.0)
+    b, a0 = np.polyfit(E, y, 1)
+    T = 1.0 / b
+    return T, -a0 * T
+
+
+def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: float = 50.0, m: float = 1.0,
+        coupling: float = 1.0, sigma_E: float = 0.01, n_samples: int = 1 << 16, n_iter: int = 2, steps: int = 200,
+        eps: float = 0.1, dt_max: float = 1e6, t_end: float = math.inf, side_mask: int = wl.SIDES_AUTO,
+        precision: int = 1, seed: int = 0, record_every: int = 10, width_mode: int = wl.WIDTH_ABS,
+        interp: int = wl.INTERP_LINLOG, log=None) -> Dict:
+    """Heun steps (adaptive dt = min(dt_max, eps / max|C/f|)) until `steps` or t_end; histories of t, N/N0, E/E0."""
+    from . import boltzmc as bm
+
+    q = wl.log_nodes(q_min, q_max, n_grid)
+    f0 = wl.f_fermi_step(q)
+    outs = [0, 0] if process == "2to2" else [0, 0, 0]
+    sp = wl.Species("phi", wl.BOSE, n_grid, q_min, q_max, f0, m0=m, interp=interp)
+    pr = wl.Process([0, 0], outs, coupling=coupling, sigma_E=sigma_E, n_samples=n_samples, n_iter=n_iter,
+                    side_mask=side_mask, width_mode=width_mode)
+    ctx = bm.from_workload(wl.Workload("thermalize_" + process, [sp], [pr]))
+    N0, E0 = moments(q, f0, m)
+    hist: Dict[str, List[float]] = {"step": [0], "t": [0.0], "N": [1.0], "E": [1.0], "dt": [0.0]}
+    t0 = time.perf_counter()
+    t = 0.0
+    for s in range(1, steps + 1):
+        opts = bm.default_opts(seed=seed, epoch=2 * s, precision=precision)
+        dt = ctx.step(bm.HEUN, -1.0, eps, dt_max, opts)
+        t += dt
+        if s % record_every == 0 or s == steps or t >= t_end:
+            f = ctx.get_f(0, n_grid)
+            Nn, En = moments(q, f, m)
+            for k, v in (("step", s), ("t", t), ("N", Nn / N0), ("E", En / E0), ("dt", dt)):
+                hist[k].append(v)
+            if log:
+                log("step %d t %.4g dt %.3g N/N0 %.5f E/E0 %.5f" % (s, t, dt, Nn / N0, En / E0))
+        if t >= t_end:
+            break
+    f = ctx.get_f(0, n_grid)
+    Nn, En = moments(q, f, m)
+    T_eq, mu_eq = equilibrium_for(q, Nn, En, m, mu_zero=(process != "2to2"))
+    f_eq = wl.f_equilibrium(q, m, T_eq, wl.BOSE, mu_eq)
+    mid = (q >= 0.3) & (q <= 10.0)
+    T_fit, mu_fit = fit_T_mu(q, f, m)
+    d0 = float(np.max(np.abs(np.log(f0[mid] / wl.f_equilibrium(q[mid], m, *equilibrium_for(
+        q, N0, E0, m, mu_zero=(process != "2to2")), wl.BOSE)))))
+    return {
+        "process": process, "n_grid": n_grid, "steps": hist["step"][-1], "t": t, "wall_s": time.perf_counter() - t0,
+        "N_over_N0": Nn / N0, "E_over_E0": En / E0, "T_eq": T_eq, "mu_eq": mu_eq, "T_fit": T_fit, "mu_fit": mu_fit,
+        "max_log_dev_from_eq": float(np.max(np.abs(np.log(f[mid] / f_eq[mid])))), "initial_max_log_dev": d0,
+        "history": hist, "f": f.tolist(), "q": q.tolist(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--process", choices=["2to2", "2to3"], default="2to2")
+    ap.add_argument("--n-grid", type=int, default=272)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--samples", type=int, default=1 << 16)
+    ap.add_argument("--iters", type=int, default=2)
+    ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--sigma-e", type=float, default=0.01)
+    ap.add_argument("--c3-only", action="store_true", help="2<->3: the final side alone (3 C_3), the incorrect sum")
+    ap.add_argument("--record-every", type=int, default=10)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    res = run(a.process, n_grid=a.n_grid, n_samples=a.samples, n_iter=a.iters, steps=a.steps, eps=a.eps,
+              sigma_E=a.sigma_e, side_mask=wl.SIDES_OUT if a.c3_only else wl.SIDES_AUTO,
+              record_every=a.record_every, log=lambda s: print(s, flush=True))
+    summary = {k: v for k, v in res.items() if k not in ("history", "f", "q")}
+    print(json.dumps(summary), flush=True)
+    if a.out:
+        with open(a.out, "w") as fh:
+            json.dump(res, fh)
+
+
+if __name__ == "__main__":
+    main()

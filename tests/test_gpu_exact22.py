@@ -1,0 +1,116 @@
+"""GPU parity of the exact-delta 2->2 path (Sec. IV two-dimensional reduction, Appendix B) against the oracle, through
+the C-ABI."""
+import numpy as np
+import pytest
+
+from gpu_util import gpu_available, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12  # both sides sum the same terms in FP64, in different orders
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _two_species(n=48):
+    q_min, q_max = 0.02, 20.0
+    q = wl.log_nodes(q_min, q_max, n)
+    fA = wl.f_equilibrium(q, 1.0, 1.2, wl.BOSE) * (1.0 + 0.4 * np.exp(-q))
+    fB = wl.f_equilibrium(q, 0.4, 0.9, wl.FERMI)
+    sp = [wl.Species("A", wl.BOSE, n, q_min, q_max, fA, m0=1.0), wl.Species("B", wl.FERMI, n, q_min, q_max, fB, m0=0.4)]
+    # A A -> B B, A B -> A B (unequal masses on both sides)
+    return wl.Workload("ab", sp, [wl.Process([0, 0], [1, 1], coupling=0.7), wl.Process([0, 1], [0, 1])])
+
+
+CASES = {
+    "mb": lambda: wl.w22_mb(),
+    "be_spline": lambda: wl.Workload("bs", [wl.Species("phi", wl.BOSE, 40, 0.01, 25.0,
+                                                        0.8 * wl.f_equilibrium(wl.log_nodes(0.01, 25.0, 40), 1.0, 1.5,
+                                                                               wl.BOSE), m0=1.0,
+                                                        interp=wl.INTERP_SPLINE)],
+                                     [wl.Process([0, 0], [0, 0])]),
+    "two_species": _two_species,
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_exact22_matches_oracle(case):
+    bm = _bm()
+    w = CASES[case]()
+    if case == "mb":  # with expansion: physical momenta q / a, a = 1.5
+        w.expansion, w.a0, w.t0, w.t = wl.EXP_RADIATION, 1.0, 1.0, 2.25
+    say("exact22 %s" % case)
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(n_iter=1, n_samples=1000)
+    C, S = ctx.collision_exact22(-1, -1, opts)
+    assert np.all(S == 0.0)
+    res = ctx.item_results(1)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items()
+    by = {items[i].uid: items[i] for i in range(n)}
+    sel = [by[int(u)] for u in res["uid"]]
+    arr = (ob.Item * len(sel))(*sel)
+    rc, I = ow.exact22(arr, len(sel))
+    assert rc == 0
+    scale = {}
+    for k, it in enumerate(sel):
+        key = (it.species, it.eval_idx)
+        scale[key] = scale.get(key, 0.0) + it.mult * abs(I[k])
+    err = np.array([abs(res["Ibar"][k] - I[k]) / max(scale[(it.species, it.eval_idx)], 1e-300)
+                    for k, it in enumerate(sel)])
+    say("item max err / gross %.3e over %d items" % (err.max(), len(sel)))
+    assert err.max() <= TOL
+    off = 0
+    for a, s in enumerate(w.species):
+        Co, So = ow.combine(arr, len(sel), I, np.zeros(len(sel)), a)
+        g = np.zeros(s.n_grid)
+        for k, it in enumerate(sel):
+            if it.species == a:
+                g[it.eval_idx] += it.mult * abs(I[k])
+        assert np.all(np.abs(C[off:off + s.n_grid] - Co) <= TOL * np.maximum(g, 1e-300))
+        off += s.n_grid
+
+
+def test_exact22_points_off_the_grid_and_state_untouched():
+    """Off-grid observed momenta take their f by the table rule; the exact path consumes no epoch and leaves the maps
+    alone, so a Monte Carlo evaluation after it is bitwise the one without it."""
+    bm = _bm()
+    w = wl.w22_mb()
+    q = np.array([0.37, 1.9, 0.5 * w.species[0].q_min])
+    ctx = bm.from_workload(w)
+    C, _ = ctx.collision_exact22(-1, 0, bm.default_opts(), eval_q=q)
+    res = ctx.item_results(1)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items_at(q, species=0)
+    by = {items[i].uid: items[i] for i in range(n)}
+    sel = [by[int(u)] for u in res["uid"]]
+    arr = (ob.Item * len(sel))(*sel)
+    rc, I = ow.exact22(arr, len(sel))
+    assert rc == 0
+    np.testing.assert_allclose(res["Ibar"], I, rtol=TOL, atol=0)
+    opts = bm.default_opts(seed=5, n_iter=2, n_samples=4000)
+    ref = bm.from_workload(w)
+    C1, _ = ref.collision(-1, -1, opts)
+    C1b, _ = ref.collision(-1, -1, bm.default_opts(seed=5, n_iter=2, n_samples=4000))
+    ctx2 = bm.from_workload(w)
+    ctx2.collision(-1, -1, opts)
+    ctx2.collision_exact22(-1, -1, bm.default_opts())
+    C2b, _ = ctx2.collision(-1, -1, bm.default_opts(seed=5, n_iter=2, n_samples=4000))
+    assert np.array_equal(C1b, C2b)
+
+
+def test_exact22_rejects_other_processes():
+    bm = _bm()
+    ctx = bm.from_workload(wl.w23_be(n_grid=16, N=1024, nitn=1))
+    with pytest.raises(bm.BmcError):
+        ctx.collision_exact22(-1, -1, bm.default_opts())
