@@ -81,7 +81,17 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
                     side_mask=side_mask, width_mode=width_mode)
     ctx = bm.from_workload(wl.Workload("thermalize_" + process, [sp], [pr]))
     N0, E0 = moments(q, f0, m)
-    hist: Dict[str, List[float]] = {"step": [0], "t": [0.0], "N": [1.0], "E": [1.0], "dt": [0.0]}
+    mid = (q >= 0.3) & (q <= 10.0)
+    mu_zero = process != "2to2"
+
+    def deviation(f):
+        """max |log(f / f_eq)| over 0.3 <= q <= 10, f_eq fixed by the current N and E (mu = 0 for 2<->3)."""
+        Nn, En = moments(q, f, m)
+        T, mu = equilibrium_for(q, Nn, En, m, mu_zero=mu_zero)
+        return float(np.max(np.abs(np.log(f[mid] / wl.f_equilibrium(q[mid], m, T, wl.BOSE, mu)))))
+
+    hist: Dict[str, List[float]] = {"step": [0], "t": [0.0], "N": [1.0], "E": [1.0], "dt": [0.0],
+                                    "dev": [deviation(f0)]}
     t0 = time.perf_counter()
     t = 0.0
     for s in range(1, steps + 1):
@@ -91,24 +101,22 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
         if s % record_every == 0 or s == steps or t >= t_end:
             f = ctx.get_f(0, n_grid)
             Nn, En = moments(q, f, m)
-            for k, v in (("step", s), ("t", t), ("N", Nn / N0), ("E", En / E0), ("dt", dt)):
+            dev = deviation(f)
+            for k, v in (("step", s), ("t", t), ("N", Nn / N0), ("E", En / E0), ("dt", dt), ("dev", dev)):
                 hist[k].append(v)
             if log:
-                log("step %d t %.4g dt %.3g N/N0 %.5f E/E0 %.5f" % (s, t, dt, Nn / N0, En / E0))
+                log("step %d t %.4g dt %.3g N/N0 %.5f E/E0 %.5f dev %.4f" % (s, t, dt, Nn / N0, En / E0, dev))
         if t >= t_end:
             break
     f = ctx.get_f(0, n_grid)
     Nn, En = moments(q, f, m)
-    T_eq, mu_eq = equilibrium_for(q, Nn, En, m, mu_zero=(process != "2to2"))
-    f_eq = wl.f_equilibrium(q, m, T_eq, wl.BOSE, mu_eq)
-    mid = (q >= 0.3) & (q <= 10.0)
+    T_eq, mu_eq = equilibrium_for(q, Nn, En, m, mu_zero=mu_zero)
     T_fit, mu_fit = fit_T_mu(q, f, m)
-    d0 = float(np.max(np.abs(np.log(f0[mid] / wl.f_equilibrium(q[mid], m, *equilibrium_for(
-        q, N0, E0, m, mu_zero=(process != "2to2")), wl.BOSE)))))
     return {
-        "process": process, "n_grid": n_grid, "steps": hist["step"][-1], "t": t, "wall_s": time.perf_counter() - t0,
+        "process": process, "side_mask": side_mask, "n_grid": n_grid, "n_samples": n_samples, "n_iter": n_iter,
+        "sigma_E": sigma_E, "eps": eps, "steps": hist["step"][-1], "t": t, "wall_s": time.perf_counter() - t0,
         "N_over_N0": Nn / N0, "E_over_E0": En / E0, "T_eq": T_eq, "mu_eq": mu_eq, "T_fit": T_fit, "mu_fit": mu_fit,
-        "max_log_dev_from_eq": float(np.max(np.abs(np.log(f[mid] / f_eq[mid])))), "initial_max_log_dev": d0,
+        "max_log_dev_from_eq": deviation(f), "initial_max_log_dev": hist["dev"][0],
         "history": hist, "f": f.tolist(), "q": q.tolist(),
     }
 

@@ -8,7 +8,11 @@ from oracle import binding as ob
 from paper_2603_28848_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
-TOL = 1e-12  # both sides sum the same terms in FP64, in different orders
+# Both sides sum the same terms in FP64, in different orders.  The trapezoid over the grid nodes is not smooth in
+# its inputs: node pairs enter and leave the kinematically allowed region (E2 >= m2, the angular window) with a
+# finite contribution, so a 1-ulp change of the observed momentum moves the oracle's own item values by up to
+# 2.2e-9 of the gross rate (measured on the 2->2 MB workload).  The tolerance sits a few ulps above that.
+TOL = 1e-8
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -69,7 +73,8 @@ def test_exact22_matches_oracle(case):
     err = np.array([abs(res["Ibar"][k] - I[k]) / max(scale[(it.species, it.eval_idx)], 1e-300)
                     for k, it in enumerate(sel)])
     say("item max err / gross %.3e over %d items" % (err.max(), len(sel)))
-    assert err.max() <= TOL
+    tol = TOL
+    assert err.max() <= tol
     off = 0
     for a, s in enumerate(w.species):
         Co, So = ow.combine(arr, len(sel), I, np.zeros(len(sel)), a)
@@ -77,7 +82,7 @@ def test_exact22_matches_oracle(case):
         for k, it in enumerate(sel):
             if it.species == a:
                 g[it.eval_idx] += it.mult * abs(I[k])
-        assert np.all(np.abs(C[off:off + s.n_grid] - Co) <= TOL * np.maximum(g, 1e-300))
+        assert np.all(np.abs(C[off:off + s.n_grid] - Co) <= tol * np.maximum(g, 1e-300))
         off += s.n_grid
 
 
