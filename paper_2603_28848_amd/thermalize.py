@@ -69,7 +69,7 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
         coupling: float = 1.0, sigma_E: float = 0.01, n_samples: int = 1 << 16, n_iter: int = 2, steps: int = 200,
         eps: float = 0.3, dt_max: float = 1e6, t_end: float = math.inf, side_mask: int = wl.SIDES_AUTO,
         precision: int = 1, seed: int = 0, record_every: int = 10, width_mode: int = wl.WIDTH_ABS,
-        interp: int = wl.INTERP_LINLOG, log=None) -> Dict:
+        interp: int = wl.INTERP_LINLOG, term_mode: int = wl.TERMS_SPLIT, log=None) -> Dict:
     """Heun steps (adaptive dt = min(dt_max, eps / max|C/f|)) until `steps` or t_end; histories of t, N/N0, E/E0."""
     from . import boltzmc as bm
 
@@ -78,7 +78,8 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
     outs = [0, 0] if process == "2to2" else [0, 0, 0]
     sp = wl.Species("phi", wl.BOSE, n_grid, q_min, q_max, f0, m0=m, interp=interp)
     pr = wl.Process([0, 0], outs, coupling=coupling, sigma_E=sigma_E, n_samples=n_samples, n_iter=n_iter,
-                    side_mask=side_mask, width_mode=width_mode, width_adapt=int(width_mode == wl.WIDTH_REL))
+                    side_mask=side_mask, width_mode=width_mode, width_adapt=int(width_mode == wl.WIDTH_REL),
+                    term_mode=term_mode)
     ctx = bm.from_workload(wl.Workload("thermalize_" + process, [sp], [pr]))
     N0, E0 = moments(q, f0, m)
     mid = (q >= 0.3) & (q <= 10.0)
@@ -95,15 +96,29 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
     t0 = time.perf_counter()
     t = 0.0
     stopped = ""
+    retries = 0
+    last_dt = 0.0
     for s in range(1, steps + 1):
         opts = bm.default_opts(seed=seed, epoch=2 * s, precision=precision)
         try:
             dt = ctx.step(bm.HEUN, -1.0, eps, dt_max, opts)
-        except bm.BmcError as e:  # the library restored f and t; report how far the run got
-            stopped = "step %d: %s" % (s, e)
-            if log:
-                log("stopped at " + stopped)
-            break
+        except bm.BmcError as e:
+            # the library restored f and t: the corrector left the valid range (a Monte Carlo outlier of k2 / f* in
+            # the tail, which the k1-based step bound does not see); retry with fixed steps of half the last size
+            dt, tries = 0.5 * last_dt, 0
+            while dt > 0.0 and tries < 4:
+                try:
+                    ctx.step(bm.HEUN, dt, eps, dt_max, opts)
+                    break
+                except bm.BmcError:
+                    dt, tries = 0.5 * dt, tries + 1
+            else:
+                stopped = "step %d: %s" % (s, e)
+                if log:
+                    log("stopped at " + stopped)
+                break
+            retries += 1
+        last_dt = dt
         t += dt
         if s % record_every == 0 or s == steps or t >= t_end:
             f = ctx.get_f(0, n_grid)
@@ -120,7 +135,7 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
     T_eq, mu_eq = equilibrium_for(q, Nn, En, m, mu_zero=mu_zero)
     T_fit, mu_fit = fit_T_mu(q, f, m)
     return {
-        "process": process, "stopped": stopped, "side_mask": side_mask, "n_grid": n_grid, "n_samples": n_samples,
+        "process": process, "stopped": stopped, "retried_steps": retries, "side_mask": side_mask, "term_mode": term_mode, "interp": interp, "n_grid": n_grid, "n_samples": n_samples,
         "n_iter": n_iter,
         "sigma_E": sigma_E, "eps": eps, "steps": hist["step"][-1], "t": t, "wall_s": time.perf_counter() - t0,
         "N_over_N0": Nn / N0, "E_over_E0": En / E0, "T_eq": T_eq, "mu_eq": mu_eq, "T_fit": T_fit, "mu_fit": mu_fit,
@@ -138,6 +153,9 @@ def main():
     ap.add_argument("--iters", type=int, default=2)
     ap.add_argument("--eps", type=float, default=0.3)
     ap.add_argument("--t-end", type=float, default=math.inf)
+    ap.add_argument("--dt-max", type=float, default=1e6)
+    ap.add_argument("--net", action="store_true", help="gain - loss with one integrator per point (TERMS_NET)")
+    ap.add_argument("--interp", choices=["linlog", "spline", "eqexact"], default="linlog")
     ap.add_argument("--sigma-e", type=float, default=0.01)
     ap.add_argument("--c3-only", action="store_true", help="2<->3: the final side alone (3 C_3), the incorrect sum")
     ap.add_argument("--rel-width", action="store_true", help="relative width w (E_in + E_out)/2 with its controller")
@@ -147,7 +165,9 @@ def main():
     a = ap.parse_args()
     res = run(a.process, n_grid=a.n_grid, n_samples=a.samples, n_iter=a.iters, steps=a.steps, eps=a.eps,
               sigma_E=a.sigma_e, side_mask=wl.SIDES_OUT if a.c3_only else wl.SIDES_AUTO,
-              record_every=a.record_every, precision=a.precision, t_end=a.t_end,
+              record_every=a.record_every, precision=a.precision, t_end=a.t_end, dt_max=a.dt_max,
+              term_mode=wl.TERMS_NET if a.net else wl.TERMS_SPLIT,
+              interp={"linlog": wl.INTERP_LINLOG, "spline": wl.INTERP_SPLINE, "eqexact": wl.INTERP_EQEXACT}[a.interp],
               width_mode=wl.WIDTH_REL if a.rel_width else wl.WIDTH_ABS, log=lambda s: print(s, flush=True))
     summary = {k: v for k, v in res.items() if k not in ("history", "f", "q")}
     print(json.dumps(summary), flush=True)

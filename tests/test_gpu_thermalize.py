@@ -1,0 +1,42 @@
+"""Thermalisation on the GPU path (Sec. V), shortened: the paper's f0 on its 272-node grid in [0.1, 50], m = 1,
+lambda = 1, H = 0, the paper's cubic spline and eps = 0.3.  2->2 conserves N and E and approaches the Bose-Einstein
+distribution those fix; 2<->3 with the full decomposition 2 C_2 + 3 C_3 conserves E and lowers N, while the final
+side alone (3 C_3) loses energy (the paper's negative example)."""
+import pytest
+
+from gpu_util import gpu_available, say
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _run(**kw):
+    from paper_2603_28848_amd import thermalize as th
+    res = th.run(interp=wl.INTERP_SPLINE, eps=0.3, log=say, **kw)
+    say("%s side_mask=%d: t %.4g steps %d N/N0 %.5f E/E0 %.5f dev %.4f -> %.4f (T %.4f vs %.4f, mu %.4f vs %.4f)" % (
+        res["process"], res["side_mask"], res["t"], res["steps"], res["N_over_N0"], res["E_over_E0"],
+        res["initial_max_log_dev"], res["max_log_dev_from_eq"], res["T_fit"], res["T_eq"], res["mu_fit"],
+        res["mu_eq"]))
+    assert res["stopped"] == ""
+    return res
+
+
+def test_2to2_conserves_number_and_energy_and_thermalizes():
+    r = _run(process="2to2", n_samples=1 << 18, term_mode=wl.TERMS_NET, dt_max=50.0, steps=120, record_every=40)
+    assert abs(r["N_over_N0"] - 1.0) < 0.01 and abs(r["E_over_E0"] - 1.0) < 0.01
+    assert r["max_log_dev_from_eq"] < 0.3 < r["initial_max_log_dev"]
+
+
+def test_2to3_needs_the_full_decomposition():
+    full = _run(process="2to3", n_samples=1 << 20, dt_max=200.0, steps=30, record_every=10)
+    c3 = _run(process="2to3", n_samples=1 << 20, dt_max=200.0, steps=30, record_every=10, side_mask=wl.SIDES_OUT)
+    # the energy drift of the full sum is Monte Carlo noise (0.3 % at 2^22 samples over 300 steps, ~1 % here)
+    assert abs(full["E_over_E0"] - 1.0) < 0.02
+    assert full["N_over_N0"] < 0.97  # 3 -> 2 is favoured from this initial condition
+    assert c3["E_over_E0"] < 0.85
