@@ -38,7 +38,8 @@ class Process(C.Structure):
                 ("sigma_E", C.c_double), ("alpha", C.c_double), ("e_cut", C.c_double), ("n_bins", C.c_int),
                 ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int), ("width_mode", C.c_int),
                 ("width_adapt", C.c_int), ("width_lo", C.c_double), ("width_hi", C.c_double),
-                ("width_factor", C.c_double), ("width_min", C.c_double), ("width_max", C.c_double)]
+                ("width_factor", C.c_double), ("width_min", C.c_double), ("width_max", C.c_double),
+                ("m2_kind", C.c_int), ("m2_c", C.c_double * 6)]
 
 
 class World(C.Structure):
@@ -148,7 +149,8 @@ class OracleWorld:
             sp = (C.c_int * 6)(*(list(p.ins) + list(p.outs) + [0] * (6 - len(p.ins) - len(p.outs))))
             self.pr[i] = Process(len(p.ins), len(p.outs), sp, p.coupling, p.sigma_E, p.alpha, p.e_cut, p.n_bins,
                                  p.term_mode, p.side_mask, p.eval_stride, p.width_mode, p.width_adapt, p.width_lo,
-                                 p.width_hi, p.width_factor, p.width_min, p.width_max)
+                                 p.width_hi, p.width_factor, p.width_min, p.width_max, p.m2_kind,
+                                 (C.c_double * 6)(*p.m2_coef))
         self.world = World(len(w.species), self.sp, len(w.processes), self.pr, w.t, w.expansion, w.a0, w.t0)
         self._maps = None
 

@@ -524,6 +524,24 @@ double orc_point_width(const orc_process* P, int n, const double* E) {
   return P->sigma_E * 0.5 * sum;
 }
 
+/* Matrix-element factor (the paper registers |M|^2 as a function of the momenta; here a quadratic polynomial in
+ * the Mandelstam invariants s and t of the process's positions): 1 for a constant |M|^2, else P(s, t). */
+double orc_m2_factor(const orc_process* P, const double* E, const double* px, const double* py, const double* pz) {
+  if (P->m2_kind != ORC_M2_POLY) return 1.0;
+  double s;
+  if (P->n_in >= 2) {
+    const double e = E[0] + E[1], x = px[0] + px[1], y = py[0] + py[1], z = pz[0] + pz[1];
+    s = e * e - (x * x + y * y + z * z);
+  } else {
+    s = E[0] * E[0] - (px[0] * px[0] + py[0] * py[0] + pz[0] * pz[0]);
+  }
+  const int j = P->n_in;
+  const double e = E[0] - E[j], x = px[0] - px[j], y = py[0] - py[j], z = pz[0] - pz[j];
+  const double t = e * e - (x * x + y * y + z * z);
+  const double* c = P->m2_c;
+  return c[0] + c[1] * s + c[2] * t + c[3] * s * s + c[4] * s * t + c[5] * t * t;
+}
+
 /* The width controller of Appendix C.  The relative Monte Carlo error of an evaluation is read as
  * sum_i sigma_i / sum_i |Ibar_i| over the process's items (the error relative to the gross rate, so that the
  * tiny items at the ends of the grid do not dominate).  Below width_lo the width narrows (w / width_factor),
@@ -619,7 +637,7 @@ static double item_integrand(const item_ctx* c, const double* x) {
   for (int i = 0; i < n; ++i) prod2E *= 2.0 * E[i];
   double twopi_pow = pow(TWO_PI, (double)(3 * (n - 1) - 4));
   double a3 = pow(a, -3.0 * (double)c->n_int);
-  double M2 = c->P->coupling * c->P->coupling;
+  double M2 = c->P->coupling * c->P->coupling * orc_m2_factor(c->P, E, px, py, pz);
   return jac * a3 * M2 * delta / (twopi_pow * prod2E) * F;
 }
 
@@ -1141,9 +1159,11 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
 int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
             uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
             int n_threads) {
-  /* the gradient's interpolation chain is written for the linear-in-ln q rule */
+  /* the gradient's interpolation chain is written for the linear-in-ln q rule and a constant |M|^2 */
   for (int s = 0; s < w->n_species; ++s)
     if (w->species[s].interp != ORC_INTERP_LINLOG) return ORC_EINVAL;
+  for (int p = 0; p < w->n_proc; ++p)
+    if (w->procs[p].m2_kind != ORC_M2_CONST) return ORC_EINVAL;
   double fits[4 * ORC_MAXSPECIES];
   int rc = orc_fits_all(w, w->t, fits);
   if (rc) return rc;
@@ -1231,7 +1251,7 @@ static double trap_weight(const orc_species* s, int j, double a) {
  * nodes of their species. */
 static int exact22_item(const orc_world* w, const orc_item* it, const double* fits, double* out) {
   const orc_process* P = &w->procs[it->proc];
-  if (P->n_in != 2 || P->n_out != 2) return ORC_EINVAL;
+  if (P->n_in != 2 || P->n_out != 2 || P->m2_kind != ORC_M2_CONST) return ORC_EINVAL;
   item_ctx c;
   int rc = item_setup(&c, w, it, w->t, fits);
   if (rc) return rc;

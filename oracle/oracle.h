@@ -43,6 +43,9 @@
 #define ORC_WIDTH_ABS 0     /* sigma_E is the Gaussian's width (an energy) */
 #define ORC_WIDTH_REL 1     /* sigma_E is the fraction w: width w (E_in + E_out) / 2 per point (Appendix C) */
 
+#define ORC_M2_CONST 0      /* |M|^2 = coupling^2 */
+#define ORC_M2_POLY 1       /* |M|^2 = coupling^2 P(s, t), P a quadratic polynomial in the Mandelstam invariants */
+
 #define ORC_EULER 0
 #define ORC_HEUN 1
 
@@ -74,6 +77,11 @@ typedef struct {
    * Carlo error is below width_lo, widen it when above width_hi, within [width_min, width_max] */
   int width_adapt;
   double width_lo, width_hi, width_factor, width_min, width_max;
+  int m2_kind;              /* ORC_M2_CONST or ORC_M2_POLY */
+  /* P(s, t) = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2 with s = (P_0 + P_1)^2 (the first two initial
+   * positions; m_0^2 for one initial particle) and t = (P_0 - P_{n_in})^2 (the first initial and the first final
+   * position), four-momenta physical */
+  double m2_c[6];
 } orc_process;
 
 typedef struct {
@@ -139,6 +147,8 @@ int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, ui
                       double* maps, double* C_all, double* sig_all, int n_threads);
 /* Gaussian width of one point with energies E[0..n-1]: sigma_E, or w (E_in + E_out) / 2 for ORC_WIDTH_REL. */
 double orc_point_width(const orc_process* P, int n, const double* E);
+/* |M|^2 / coupling^2 at one point with position four-momenta (E, px, py, pz): 1, or P(s, t). */
+double orc_m2_factor(const orc_process* P, const double* E, const double* px, const double* py, const double* pz);
 /* The width controller: the width after an evaluation whose items of process P had estimates Ibar[i] and Monte
  * Carlo errors sigma[i] (i < n), starting from width w. */
 double orc_width_control(const orc_process* P, int n, const double* Ibar, const double* sigma, double w);

@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -25,6 +25,7 @@ TERMS_SPLIT, TERMS_NET = 0, 1
 SIDES_AUTO, SIDES_IN, SIDES_OUT, SIDES_BOTH = 0, 1, 2, 3
 WIDTH_ABS, WIDTH_REL = 0, 1
 INTERP_LINLOG, INTERP_SPLINE, INTERP_EQEXACT = 0, 1, 2
+M2_CONST, M2_POLY = 0, 1
 
 
 @dataclasses.dataclass
@@ -63,6 +64,8 @@ class Process:
     width_factor: float = 1.25
     width_min: float = 1e-4
     width_max: float = 0.2
+    m2_kind: int = M2_CONST      # M2_POLY: |M|^2 = coupling^2 P(s, t) with the coefficients below
+    m2_coef: Tuple[float, ...] = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2
 
 
 @dataclasses.dataclass

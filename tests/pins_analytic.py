@@ -105,3 +105,29 @@ def semi_analytic_gain(p1, f_fn, eta, m=1.0, lam=1.0, q_lo=0.01, q_hi=20.0, n_pa
     f2 = f_fn(p2, np.where(allowed, E2, m))
     integrand = p3 * p3 / (2 * E3) * p4 * p4 / (2 * E4) * F * f3 * f4 * (1 + eta * f1) * (1 + eta * f2)
     return 2.0 / (2.0 * math.pi) ** 4 / (2.0 * E1) * float(np.sum(W * integrand))
+
+
+def mb_loss_poly_closed_form(p1, f1, f2_fn, m=1.0, lam=1.0, coef=(1.0, 0, 0, 0, 0, 0), p2_max=60.0):
+    """The MB loss term with |M|^2 = lam^2 P(s, t), P = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2, equal masses.
+    The final-state phase space is the two-body one, Phi_2(s) = sqrt(1 - 4 m^2 / s) / (8 pi), over which t is
+    uniform in the centre-of-mass angle: t = A + B cos(theta*), A = 2 m^2 - s/2, B = s/2 - 2 m^2, so
+    <t> = A and <t^2> = A^2 + B^2 / 3.  The (p2, c) integral is done numerically."""
+    c0, c1, c2, c3, c4, c5 = coef
+    E1 = math.hypot(p1, m)
+
+    def G(s):
+        A, B = 2 * m * m - 0.5 * s, 0.5 * s - 2 * m * m
+        return c0 + c1 * s + c2 * A + c3 * s * s + c4 * s * A + c5 * (A * A + B * B / 3.0)
+
+    def inner(p2):
+        E2 = math.hypot(p2, m)
+
+        def h(c):
+            s = 2 * m * m + 2 * (E1 * E2 - p1 * p2 * c)
+            return math.sqrt(max(0.0, 1.0 - 4 * m * m / s)) * G(s)
+
+        v, _ = integrate.quad(h, -1.0, 1.0, epsabs=0.0, epsrel=1e-11)
+        return p2 * p2 / E2 * f2_fn(p2) * v
+
+    val, _ = integrate.quad(inner, 0.0, p2_max, limit=400, epsabs=0.0, epsrel=1e-9)
+    return f1 * lam * lam / (128.0 * math.pi ** 3 * E1) * val
