@@ -75,6 +75,9 @@ extern "C" {
 #define BMC_INTERP_SPLINE 1   /* not-a-knot cubic spline of f in linear q (Sec. III.B) */
 #define BMC_INTERP_EQEXACT 2  /* log(1/f + eta) linear in E between nodes: exact for equilibrium (the form of Eq. 17) */
 
+#define BMC_M2_CONST 0    /* |M|^2 = coupling^2 */
+#define BMC_M2_POLY 1     /* |M|^2 = coupling^2 P(s, t), P quadratic in the Mandelstam invariants (m2_coef) */
+
 #define BMC_WIDTH_ABS 0   /* sigma_E is the width of the Gaussian energy delta (an energy) */
 #define BMC_WIDTH_REL 1   /* sigma_E is a fraction w; the width at a point is w (E_in + E_out) / 2 (Appendix C) */
 
@@ -120,6 +123,13 @@ typedef struct {
    * 0 < width_min <= width_max (<= 1 for BMC_WIDTH_REL).  Defaults: 1e-3, 1e-2, 1.25, 1e-4, 0.2. */
   int width_adapt;
   double width_lo, width_hi, width_factor, width_min, width_max;
+  /* Matrix element (Sec. III.A registers |M|^2 as a function of the momenta): BMC_M2_CONST (default), or
+   * BMC_M2_POLY with |M|^2 = coupling^2 (c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2), c = m2_coef, where
+   * s = (P_0 + P_1)^2 over the first two initial positions (m_0^2 with one initial particle) and
+   * t = (P_0 - P_{n_in})^2 between the first initial and the first final position, from the physical
+   * four-momenta of each sampled point.  Neither bmc_vjp nor bmc_collision_exact22 takes BMC_M2_POLY. */
+  int m2_kind;
+  double m2_coef[6];
 } bmc_process_params;
 
 /* Options of one evaluation. */

@@ -466,6 +466,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
             it.rel = Pr.prm.width_mode == BMC_WIDTH_REL ? 1 : 0;
+            it.m2poly = Pr.prm.m2_kind == BMC_M2_POLY ? 1 : 0;
+            for (int k2 = 0; k2 < 6; ++k2) it.m2c[k2] = Pr.prm.m2_coef[k2];
             it.e_cut = Pr.prm.e_cut;
             it.twopi_pow = std::pow(2.0 * M_PI, (double)(3 * (n - 1) - 4));
             it.alpha = Pr.prm.alpha;
@@ -480,6 +482,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
               it.r_species[r] = Pr.sp[q];
               it.r_in[r] = q < Pr.n_in ? 1 : 0;
               it.r_obsside[r] = ((q < Pr.n_in) ? 0 : 1) == side ? 1 : 0;
+              it.r_cs[r] = (q == 0 || (q == 1 && Pr.n_in >= 2)) ? 1 : 0;
+              it.r_ct[r] = q == 0 ? 1 : (q == Pr.n_in ? -1 : 0);
               it.r_tab[r] = 0;
               if (r <= nint) {  // integrated and conserved particles read tables
                 int slot = -1;
@@ -853,6 +857,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.precision = o.precision;
   L.any_interp = 0;
   for (auto& S : c->sp) L.any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
+  for (auto& Pr : c->pr) L.any_interp |= Pr.prm.m2_kind != BMC_M2_CONST ? 1 : 0;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
   L.shell_list = P.d_list;
   L.shell_cnt = P.d_cnt;
@@ -1008,6 +1013,9 @@ int bmc_default_process_params(bmc_process_params* p) {
   p->width_factor = 1.25;
   p->width_min = 1e-4;
   p->width_max = 0.2;
+  p->m2_kind = BMC_M2_CONST;
+  p->m2_coef[0] = 1.0;
+  for (int k = 1; k < 6; ++k) p->m2_coef[k] = 0.0;
   return BMC_OK;
 }
 
@@ -1126,6 +1134,9 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
   // a relative width stays <= 1: the screening pass's energy margins assume it
   if (q.width_mode == BMC_WIDTH_REL && !(q.sigma_E <= 1.0)) return fail(c, BMC_EINVAL, "relative width above 1");
   if (q.width_adapt != 0 && q.width_adapt != 1) return fail(c, BMC_EINVAL, "width_adapt must be 0 or 1");
+  if (q.m2_kind != BMC_M2_CONST && q.m2_kind != BMC_M2_POLY) return fail(c, BMC_EINVAL, "bad m2_kind");
+  for (int k = 0; k < 6; ++k)
+    if (!std::isfinite(q.m2_coef[k])) return fail(c, BMC_EINVAL, "non-finite |M|^2 coefficient");
   if (q.width_adapt &&
       (!(q.width_lo > 0.0) || !(q.width_hi > q.width_lo) || !std::isfinite(q.width_hi) || !(q.width_factor > 1.0) ||
        !std::isfinite(q.width_factor) || !(q.width_min > 0.0) || !(q.width_max >= q.width_min) ||
@@ -1328,8 +1339,9 @@ int bmc_collision_exact22(bmc_ctx* c, int process, int species, const bmc_run_op
   if (rc) return rc;
   if (process < -1 || process >= (int)c->pr.size()) return fail(c, BMC_EINVAL, "bad process id");
   for (int p = 0; p < (int)c->pr.size(); ++p)
-    if ((process < 0 || p == process) && !(c->pr[p].n_in == 2 && c->pr[p].n_out == 2))
-      return fail(c, BMC_EUNSUP, "the exact-delta path takes 2->2 processes only");
+    if ((process < 0 || p == process) &&
+        !(c->pr[p].n_in == 2 && c->pr[p].n_out == 2 && c->pr[p].prm.m2_kind == BMC_M2_CONST))
+      return fail(c, BMC_EUNSUP, "the exact-delta path takes 2->2 processes with a constant |M|^2 only");
   HIPCHK(c, hipSetDevice(c->device));
   rc = get_plan(c, c->plan, process, species, o);
   if (rc) return rc;
@@ -1743,6 +1755,9 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   for (auto& S : c->sp)
     if (S.interp != BMC_INTERP_LINLOG)
       return fail(c, BMC_EUNSUP, "vector-Jacobian products need the linear-in-ln q interpolation");
+  for (auto& Pr : c->pr)
+    if (Pr.prm.m2_kind != BMC_M2_CONST)
+      return fail(c, BMC_EUNSUP, "vector-Jacobian products need a constant |M|^2");
   rc = check_ready(c);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));

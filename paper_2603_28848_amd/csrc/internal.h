@@ -98,6 +98,12 @@ struct ItemRec {
   int r_in[kMaxN];      // 1 if the role's particle is in the initial state
   int r_obsside[kMaxN]; // 1 if the role's particle is on the observed side
   int cons_in;          // conserved particle in the initial state
+  // |M|^2 = coupling2 P(s, t) when m2poly: P = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2, s = (sum_r cs_r P_r)^2,
+  // t = (sum_r ct_r P_r)^2 over the roles' four-momenta (cs: the first two initial positions; ct: +1 the first
+  // initial, -1 the first final position)
+  int m2poly;
+  double m2c[6];
+  int r_cs[kMaxN], r_ct[kMaxN];
   int tab_species[kMaxTab];
   int n_tab;
 };

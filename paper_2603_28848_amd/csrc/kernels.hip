@@ -235,6 +235,8 @@ struct ItemConsts {
   float whalf32;
   int rel;       // relative width: sigma_E = whalf (sum of the point's energies)
   double whalf;
+  int m2poly;    // |M|^2 = coupling^2 P(s, t)
+  double m2c[6], cs[NR], ct[NR];
   double a, inv_a, m2[NR], eta[NR], esg[NR];
   int obsside[NR];
   double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
@@ -260,6 +262,23 @@ __device__ __forceinline__ void philox_words(uint32_t* wd, uint64_t n, uint32_t 
 // One sample with FP64 kinematics (map, sin/cos, momenta, energies, dE and the Gaussian's argument); the f
 // tables, interpolation and statistical factor in FT.  Returns W and, per dimension d, the histogram offset
 // d nb + j of the sample's bin j.
+// P(s, t) = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2 from the four-momentum sums Ps and Pt (E, x, y, z).
+template <typename T>
+__device__ __forceinline__ T m2_poly(const double* c, const T* Ps, const T* Pt) {
+  const T s = Ps[0] * Ps[0] - (Ps[1] * Ps[1] + Ps[2] * Ps[2] + Ps[3] * Ps[3]);
+  const T t = Pt[0] * Pt[0] - (Pt[1] * Pt[1] + Pt[2] * Pt[2] + Pt[3] * Pt[3]);
+  return (T)c[0] + (T)c[1] * s + (T)c[2] * t + (T)c[3] * s * s + (T)c[4] * s * t + (T)c[5] * t * t;
+}
+
+// Adds coefficient c times the four-momentum (E, x, y, z) to the sum P.
+template <typename T>
+__device__ __forceinline__ void add4(T* P, T c, T E, T x, T y, T z) {
+  P[0] += c * E;
+  P[1] += c * x;
+  P[2] += c * y;
+  P[3] += c * z;
+}
+
 template <int NI, typename FT, bool ALT>
 __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, int* hj) {
 #pragma clang fp contract(off)
@@ -274,6 +293,13 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   double prod2E = 2.0 * K.E_obs, sumE = K.E_obs;
   bool cut = K.E_obs < K.e_cut;
   FT gain = (FT)K.g_obs, loss = (FT)K.l_obs;
+  double Ps[4] = {0.0, 0.0, 0.0, 0.0}, Pt[4] = {0.0, 0.0, 0.0, 0.0};  // Mandelstam sums (polynomial |M|^2)
+  if constexpr (ALT) {
+    if (K.m2poly) {
+      add4(Ps, K.cs[NI + 1], K.E_obs, 0.0, 0.0, K.p_obs);
+      add4(Pt, K.ct[NI + 1], K.E_obs, 0.0, 0.0, K.p_obs);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
     double x3[3], sc3[2][2];
@@ -303,6 +329,12 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     dE += K.esg[k] * E;
     prod2E *= 2.0 * E;
     sumE += E;
+    if constexpr (ALT) {
+      if (K.m2poly) {
+        add4(Ps, K.cs[k], E, ps * cph, ps * sph, p * cth);
+        add4(Pt, K.ct[k], E, ps * cph, ps * sph, p * cth);
+      }
+    }
     FT f;
     if constexpr (std::is_same<FT, double>::value) {
       int jj;
@@ -322,6 +354,16 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   dE += K.esg[NI] * Ec;
   prod2E *= 2.0 * Ec;
   sumE += Ec;
+  double m2f = 1.0;
+  if constexpr (ALT) {
+    if (K.m2poly) {
+      // the conserved particle's momentum: sum_in - sum_out of the others, negated for an initial-state one
+      const double sc = -K.esg[NI];
+      add4(Ps, K.cs[NI], Ec, sc * sx, sc * sy, sc * sz);
+      add4(Pt, K.ct[NI], Ec, sc * sx, sc * sy, sc * sz);
+      m2f = m2_poly(K.m2c, Ps, Pt);
+    }
+  }
   const double qc = K.a * sqrt(P2);
   FT fc;
   if constexpr (std::is_same<FT, double>::value) {
@@ -364,6 +406,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
     const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
     W = J * jac * (K.a3M2 / K.twopi_pow) * ((double)delta * (double)rcp) * (double)F;
   }
+  if constexpr (ALT) W *= m2f;
   return cut ? 0.0 : W;
 }
 
@@ -393,6 +436,14 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
   float dE = (float)(K.esg[NI + 1] * K.E_obs), sumE = (float)K.E_obs, prod2E = 2.0f * (float)K.E_obs;
   float gain = (float)K.g_obs, loss = (float)K.l_obs;
   bool cut = K.E_obs < K.e_cut;
+  float Ps[4] = {0.0f, 0.0f, 0.0f, 0.0f}, Pt[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // Mandelstam sums (FINISH)
+  constexpr bool kPoly = FINISH && ALT;
+  if constexpr (kPoly) {
+    if (K.m2poly) {
+      add4(Ps, (float)K.cs[NI + 1], (float)K.E_obs, 0.0f, 0.0f, (float)K.p_obs);
+      add4(Pt, (float)K.ct[NI + 1], (float)K.E_obs, 0.0f, 0.0f, (float)K.p_obs);
+    }
+  }
 #pragma unroll
   for (int k = 0; k < NI; ++k) {
     float x3[3];
@@ -425,6 +476,12 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
     dE = fmaf(sg, E, dE);
     sumE += E;
     prod2E *= 2.0f * E;
+    if constexpr (kPoly) {
+      if (K.m2poly) {
+        add4(Ps, (float)K.cs[k], E, ps * cph, ps * sph, p * cth);
+        add4(Pt, (float)K.ct[k], E, ps * cph, ps * sph, p * cth);
+      }
+    }
     const FTab<float>& T = K.tr[k];
     float f;
     if (!ALT || T.mode == 0) {
@@ -476,7 +533,15 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
     const float bf = fmaf((float)K.eta[NI], fc, 1.0f);
     gain *= K.obsside[NI] ? bf : fc;
     loss *= K.obsside[NI] ? fc : bf;
-    const float F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
+    float F = K.net ? gain - loss : (K.term == 0 ? gain : loss);
+    if constexpr (kPoly) {
+      if (K.m2poly) {
+        const float sc = -(float)K.esg[NI];
+        add4(Ps, (float)K.cs[NI], Ec, sc * sx, sc * sy, sc * sz);
+        add4(Pt, (float)K.ct[NI], Ec, sc * sx, sc * sy, sc * sz);
+        F *= m2_poly(K.m2c, Ps, Pt);
+      }
+    }
     // W = m 2^e F: the Gaussian's exponent y = -dE^2 log2(e) / (2 sigma_E^2) = e + (y - e) with e integer, the
     // weight factors and 2^(y - e) in FP32 (their product stays well inside the FP32 range), the power of two and
     // F applied in FP64 (W itself can lie far below the FP32 range)
@@ -581,7 +646,12 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     K.eta[r] = (double)L.spec[it->r_species[r]].stat;
     K.esg[r] = it->r_in[r] ? 1.0 : -1.0;
     K.obsside[r] = it->r_obsside[r];
+    K.cs[r] = (double)it->r_cs[r];
+    K.ct[r] = (double)it->r_ct[r];
   }
+  K.m2poly = it->m2poly;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) K.m2c[k] = it->m2c[k];
   const SpecDev& So = L.spec[it->obs_species];
   K.p_obs = it->q_obs * K.inv_a;
   K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
