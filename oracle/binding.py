@@ -39,7 +39,7 @@ class Process(C.Structure):
                 ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int), ("width_mode", C.c_int),
                 ("width_adapt", C.c_int), ("width_lo", C.c_double), ("width_hi", C.c_double),
                 ("width_factor", C.c_double), ("width_min", C.c_double), ("width_max", C.c_double),
-                ("m2_kind", C.c_int), ("m2_c", C.c_double * 6)]
+                ("vegas_plus", C.c_int), ("beta", C.c_double), ("m2_kind", C.c_int), ("m2_c", C.c_double * 6)]
 
 
 class World(C.Structure):
@@ -83,6 +83,7 @@ def lib():
         L.orc_kinematic_F.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_double]
         L.orc_kinematic_F.restype = C.c_double
         L.orc_exact22.argtypes = [C.POINTER(World), C.c_int, C.POINTER(Item), dp]
+        L.orc_vplus_strata.argtypes = [C.c_int64, C.c_int]
         L.orc_point_width.argtypes = [C.POINTER(Process), C.c_int, dp]
         L.orc_point_width.restype = C.c_double
         L.orc_width_control.argtypes = [C.POINTER(Process), C.c_int, dp, dp, C.c_double]
@@ -149,7 +150,8 @@ class OracleWorld:
             sp = (C.c_int * 6)(*(list(p.ins) + list(p.outs) + [0] * (6 - len(p.ins) - len(p.outs))))
             self.pr[i] = Process(len(p.ins), len(p.outs), sp, p.coupling, p.sigma_E, p.alpha, p.e_cut, p.n_bins,
                                  p.term_mode, p.side_mask, p.eval_stride, p.width_mode, p.width_adapt, p.width_lo,
-                                 p.width_hi, p.width_factor, p.width_min, p.width_max, p.m2_kind,
+                                 p.width_hi, p.width_factor, p.width_min, p.width_max, p.vegas_plus, p.beta,
+                                 p.m2_kind,
                                  (C.c_double * 6)(*p.m2_coef))
         self.world = World(len(w.species), self.sp, len(w.processes), self.pr, w.t, w.expansion, w.a0, w.t0)
         self._maps = None

@@ -727,6 +727,113 @@ static void adapt_dim(double* edges, int nb, const long double* h, const long do
   edges[nb] = old[nb];
 }
 
+/* VEGAS+ (Lepage, J. Comput. Phys. 439 (2021) 110386): adaptive stratified sampling on top of the Vegas map.
+ * y-space is cut into M = k^D hypercubes, k = orc_vplus_strata(N, D) per dimension, each of volume 1/M; hypercube
+ * h = sum_d h_d k^d (dimension 0 fastest).  An iteration draws n_h samples in hypercube h, sample s = off_h + i
+ * (off_h = sum of n over the hypercubes before h) with y_d = (h_d + u_d) / k from the sample's uniforms u.
+ *   estimate   I = sum_h (1/M) S1_h / n_h,  variance V = sum_h (S2_h - S1_h^2 / n_h) / (n_h (n_h - 1)) / M^2;
+ *   map training data: per sample (W N_it / (M n_h))^2, the squared weight of the sample in the plain-Vegas
+ *   normalisation (N_it = sum_h n_h), and a count;
+ *   allocation: the first iteration of a call takes n_h = N / M (integer division); after an adapted iteration,
+ *   sigma_h^2 = max(0, (S2_h - S1_h^2 / n_h) / (n_h - 1)) / M^2, d_h = (sigma_h^2)^(beta/2), and
+ *   n_h = 2 + floor((N - 2 M) d_h / sum d) (every hypercube keeps two samples; the uniform allocation again if
+ *   sum d = 0).  Frozen runs (adapt = 0) keep the uniform allocation. */
+int orc_vplus_strata(int64_t N, int D) {
+  int k = 1;
+  for (;;) {
+    int64_t p = 1;
+    for (int d = 0; d < D && p <= N / 2; ++d) p *= (int64_t)(k + 1);
+    if (p > N / 2) return k;
+    ++k;
+  }
+}
+
+static int item_vegas_plus(const item_ctx* c, const orc_item* it, int64_t N, int first_iter, int nitn, uint64_t seed,
+                           uint32_t epoch, int adapt, double* map, double* I_it, double* V_it) {
+  const int D = 3 * c->n_int, nb = c->P->n_bins;
+  const int k = orc_vplus_strata(N, D);
+  int64_t M = 1;
+  for (int d = 0; d < D; ++d) M *= k;
+  int64_t* nh = (int64_t*)malloc(sizeof(int64_t) * (size_t)M);
+  double* S1 = (double*)malloc(sizeof(double) * (size_t)M);
+  double* S2 = (double*)malloc(sizeof(double) * (size_t)M);
+  long double* h = (long double*)calloc((size_t)D * nb, sizeof(long double));
+  long double* cn = (long double*)calloc((size_t)D * nb, sizeof(long double));
+  if (!nh || !S1 || !S2 || !h || !cn) {
+    free(nh); free(S1); free(S2); free(h); free(cn);
+    return ORC_ENOMEM;
+  }
+  for (int64_t q = 0; q < M; ++q) nh[q] = N / M;
+  double y[ORC_MAXD], x[ORC_MAXD];
+  int jb[ORC_MAXD];
+  for (int itn = 0; itn < nitn; ++itn) {
+    int64_t Nit = 0;
+    for (int64_t q = 0; q < M; ++q) Nit += nh[q];
+    memset(h, 0, sizeof(long double) * (size_t)D * nb);
+    memset(cn, 0, sizeof(long double) * (size_t)D * nb);
+    int64_t off = 0;
+    for (int64_t q = 0; q < M; ++q) {
+      int dig[ORC_MAXD];
+      int64_t rem = q;
+      for (int d = 0; d < D; ++d) {
+        dig[d] = (int)(rem % k);
+        rem /= k;
+      }
+      const double wt = (double)Nit / ((double)M * (double)nh[q]);
+      double s1 = 0.0, s2 = 0.0;
+      for (int64_t i = 0; i < nh[q]; ++i) {
+        orc_sample_uniforms(seed, it->uid, epoch, first_iter + itn, off + i, D, y);
+        double J = 1.0;
+        for (int d = 0; d < D; ++d) {
+          double yn = ((double)dig[d] + y[d]) / (double)k * (double)nb;
+          int j = (int)floor(yn);
+          if (j > nb - 1) j = nb - 1;
+          double del = yn - (double)j;
+          double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+          x[d] = e0 + (e1 - e0) * del;
+          J *= (double)nb * (e1 - e0);
+          jb[d] = j;
+        }
+        double W = J * item_integrand(c, x);
+        s1 += W;
+        s2 += W * W;
+        double Wt = W * wt;
+        double w2 = fabs(Wt) >= ORC_HIST_WMIN ? Wt * Wt : 0.0;
+        for (int d = 0; d < D; ++d) {
+          h[d * nb + jb[d]] += (long double)w2;
+          cn[d * nb + jb[d]] += 1.0L;
+        }
+      }
+      S1[q] = s1;
+      S2[q] = s2;
+      off += nh[q];
+    }
+    long double I = 0.0L, V = 0.0L;
+    for (int64_t q = 0; q < M; ++q) {
+      const double n = (double)nh[q];
+      I += (long double)(S1[q] / n);
+      V += (long double)((S2[q] - S1[q] * S1[q] / n) / (n * (n - 1.0)));
+    }
+    I_it[itn] = (double)(I / (long double)M);
+    V_it[itn] = (double)(V / ((long double)M * (long double)M));
+    if (adapt) {
+      for (int d = 0; d < D; ++d) adapt_dim(&map[d * (nb + 1)], nb, &h[d * nb], &cn[d * nb], c->P->alpha);
+      double sumd = 0.0;
+      for (int64_t q = 0; q < M; ++q) {
+        const double n = (double)nh[q];
+        double s2 = (S2[q] - S1[q] * S1[q] / n) / (n - 1.0) / ((double)M * (double)M);
+        s2 = s2 > 0.0 ? s2 : 0.0;
+        S1[q] = pow(s2, 0.5 * c->P->beta);  /* d_h, reusing the array */
+        sumd += S1[q];
+      }
+      for (int64_t q = 0; q < M; ++q)
+        nh[q] = sumd > 0.0 ? 2 + (int64_t)floor((double)(N - 2 * M) * S1[q] / sumd) : N / M;
+    }
+  }
+  free(nh); free(S1); free(S2); free(h); free(cn);
+  return ORC_OK;
+}
+
 /* Runs Vegas iterations first_iter .. first_iter + nitn - 1 of N samples for one item.  map: D x (nb+1)
  * edges (in: current map; out: map adapted after every iteration, or unchanged when adapt == 0).  I_it, V_it: per-iteration estimate and its variance
  * V = (S2/N - I^2)/(N-1).  Ibar, sigma: inverse-variance weighted combination over the iterations with
@@ -738,6 +845,11 @@ int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, i
   int rc = item_setup(&c, w, it, w->t, fits);
   if (rc) return rc;
   const int D = 3 * c.n_int, nb = c.P->n_bins;
+  if (c.P->vegas_plus) {
+    rc = item_vegas_plus(&c, it, N, first_iter, nitn, seed, epoch, adapt, map, I_it, V_it);
+    if (rc) return rc;
+    nitn = -nitn;  /* iterations done: skip the plain loop below */
+  }
   long double* h = (long double*)calloc((size_t)D * nb, sizeof(long double));
   long double* cn = (long double*)calloc((size_t)D * nb, sizeof(long double));
   if (!h || !cn) { free(h); free(cn); return ORC_ENOMEM; }
@@ -781,6 +893,7 @@ int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, i
   }
   free(h);
   free(cn);
+  if (nitn < 0) nitn = -nitn;
   double sw = 0.0, swI = 0.0;
   int npos = 0;
   for (int itn = 0; itn < nitn; ++itn) {

@@ -77,6 +77,8 @@ typedef struct {
    * Carlo error is below width_lo, widen it when above width_hi, within [width_min, width_max] */
   int width_adapt;
   double width_lo, width_hi, width_factor, width_min, width_max;
+  int vegas_plus;           /* 1: adaptive stratified sampling (VEGAS+) on top of the map */
+  double beta;              /* VEGAS+ allocation exponent: n_h ~ sigma_h^beta */
   int m2_kind;              /* ORC_M2_CONST or ORC_M2_POLY */
   /* P(s, t) = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2 with s = (P_0 + P_1)^2 (the first two initial
    * positions; m_0^2 for one initial particle) and t = (P_0 - P_{n_in})^2 (the first initial and the first final
@@ -127,6 +129,8 @@ int orc_fits_all(const orc_world* w, double t, double* fits);
 double orc_stat_factor(int n_in, int n, int obs_side, int term_mode, int term, const double* f, const double* eta);
 int orc_integrand_batch(const orc_world* w, const orc_item* it, int64_t n, const double* x, double* value);
 int orc_integrand_at(const orc_world* w, const orc_item* it, const double* x, double* value);
+/* Strata per dimension of VEGAS+ for N samples in D dimensions: the largest k >= 1 with k^D <= N / 2. */
+int orc_vplus_strata(int64_t N, int D);
 int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int first_iter, int nitn,
                    uint64_t seed, uint32_t epoch, int adapt, double* map, double* I_it, double* V_it, double* Ibar,
                    double* sigma);

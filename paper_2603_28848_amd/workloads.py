@@ -64,6 +64,8 @@ class Process:
     width_factor: float = 1.25
     width_min: float = 1e-4
     width_max: float = 0.2
+    vegas_plus: int = 0          # 1: adaptive stratified sampling (VEGAS+) on top of the map
+    beta: float = 0.75           # VEGAS+ allocation exponent
     m2_kind: int = M2_CONST      # M2_POLY: |M|^2 = coupling^2 P(s, t) with the coefficients below
     m2_coef: Tuple[float, ...] = (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)  # c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2
 
