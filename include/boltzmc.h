@@ -123,6 +123,15 @@ typedef struct {
    * 0 < width_min <= width_max (<= 1 for BMC_WIDTH_REL).  Defaults: 1e-3, 1e-2, 1.25, 1e-4, 0.2. */
   int width_adapt;
   double width_lo, width_hi, width_factor, width_min, width_max;
+  /* VEGAS+ (Lepage 2021), with vegas_plus = 1: adaptive stratified sampling on top of the Vegas map.  y-space is
+   * cut into M = k^D hypercubes, k the largest integer with k^D <= N / 2; an iteration draws n_h samples in
+   * hypercube h (the first iteration of a call N / M each), estimates I = sum_h S1_h / (M n_h) with variance
+   * sum_h (S2_h - S1_h^2 / n_h) / (n_h (n_h - 1) M^2), trains the map on (W N_it / (M n_h))^2, and (unless frozen)
+   * reallocates n_h = 2 + floor((N - 2 M) sigma_h^beta / sum) with sigma_h the hypercube's standard deviation of
+   * W / M.  Every sample is evaluated in full (no screening pass).  bmc_vjp does not take it.  beta in [0, 2]
+   * (default 0.75). */
+  int vegas_plus;
+  double beta;
   /* Matrix element (Sec. III.A registers |M|^2 as a function of the momenta): BMC_M2_CONST (default), or
    * BMC_M2_POLY with |M|^2 = coupling^2 (c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2), c = m2_coef, where
    * s = (P_0 + P_1)^2 over the first two initial positions (m_0^2 with one initial particle) and

@@ -32,7 +32,8 @@ class ProcessParams(C.Structure):
                 ("n_bins", C.c_int), ("term_mode", C.c_int), ("side_mask", C.c_int), ("eval_stride", C.c_int),
                 ("n_samples", C.c_int64), ("n_iter", C.c_int), ("width_mode", C.c_int), ("width_adapt", C.c_int),
                 ("width_lo", C.c_double), ("width_hi", C.c_double), ("width_factor", C.c_double),
-                ("width_min", C.c_double), ("width_max", C.c_double), ("m2_kind", C.c_int),
+                ("width_min", C.c_double), ("width_max", C.c_double), ("vegas_plus", C.c_int), ("beta", C.c_double),
+                ("m2_kind", C.c_int),
                 ("m2_coef", C.c_double * 6)]
 
 
@@ -419,7 +420,8 @@ def from_workload(w: wl.Workload, device: int = 0, stream=None) -> Context:
                         n_bins=p.n_bins, term_mode=p.term_mode, side_mask=p.side_mask, eval_stride=p.eval_stride,
                         n_samples=p.n_samples, n_iter=p.n_iter, width_mode=p.width_mode, width_adapt=p.width_adapt,
                         width_lo=p.width_lo, width_hi=p.width_hi, width_factor=p.width_factor,
-                        width_min=p.width_min, width_max=p.width_max, m2_kind=p.m2_kind,
+                        width_min=p.width_min, width_max=p.width_max, vegas_plus=p.vegas_plus, beta=p.beta,
+                        m2_kind=p.m2_kind,
                         m2_coef=(C.c_double * 6)(*p.m2_coef))
     if w.expansion:
         ctx.set_expansion(w.expansion, w.a0, w.t0)

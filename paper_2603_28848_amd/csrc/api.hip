@@ -31,6 +31,17 @@ constexpr size_t kListCapBytes = size_t(1) << 30;
 constexpr int kShellGroups = 16;
 constexpr int kMaxEvalPoints = BMC_MAXEVAL;  // map slots are reserved for this many points off the grid
 
+// VEGAS+ strata per dimension: the largest k >= 1 with k^D <= N / 2.
+int vplus_strata(int64_t N, int D) {
+  int k = 1;
+  for (;;) {
+    int64_t p = 1;
+    for (int d = 0; d < D && p <= N / 2; ++d) p *= (int64_t)(k + 1);
+    if (p > N / 2) return k;
+    ++k;
+  }
+}
+
 int shell_units_for(int64_t n_units) { return (int)((n_units + kShellGroups - 1) / kShellGroups); }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -91,6 +102,15 @@ struct Plan {
   int64_t n_parts = 0;   // 32-bit bin counts of all units
   int lds64 = 0, lds32 = 0;
   std::vector<int> new_maps;  // item indices whose maps need initialising
+  // VEGAS+ items: sample blocks (items with more iterations first), blocks per iteration, the items themselves
+  std::vector<VpTask> vp_tasks;
+  std::vector<int> vp_per_iter, vp_items;
+  int64_t vp_hc = 0, vp_hoffs = 0, vp_recd = 0;  // hypercubes, offset entries, record doubles
+  VpTask* d_vpt = nullptr;
+  int* d_vpi = nullptr;
+  int* d_nh = nullptr;
+  int64_t* d_hoff = nullptr;
+  double *d_vS1 = nullptr, *d_vS2 = nullptr, *d_vrec = nullptr;
   // device pointers (inside the scratch region)
   ItemRec* d_items = nullptr;
   Task* d_tb = nullptr;
@@ -456,16 +476,25 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.mult = mult;
             it.N = N;
             it.unit_size = unit_size_for(N);
-            it.n_units = (int)((N + it.unit_size - 1) / it.unit_size);
+            it.n_units = Pr.prm.vegas_plus ? 0 : (int)((N + it.unit_size - 1) / it.unit_size);
             it.part_off = part;
             part += (int64_t)it.n_units * D * nb;
             it.shell_off = shell;
-            it.shell_units = shell_units_for(it.n_units);
+            it.shell_units = std::max(1, shell_units_for(it.n_units));
             shell += (int64_t)((it.n_units + it.shell_units - 1) / it.shell_units) * (2 + 2 * D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
             it.rel = Pr.prm.width_mode == BMC_WIDTH_REL ? 1 : 0;
+            it.vplus = Pr.prm.vegas_plus;
+            it.beta = Pr.prm.beta;
+            if (it.vplus) {
+              it.vp_k = vplus_strata(N, D);
+              int64_t M = 1;
+              for (int d = 0; d < D; ++d) M *= it.vp_k;
+              it.vp_M = (int)M;
+              it.vp_blocks = (int)((M + kBlock - 1) / kBlock);
+            }
             it.m2poly = Pr.prm.m2_kind == BMC_M2_POLY ? 1 : 0;
             for (int k2 = 0; k2 < 6; ++k2) it.m2c[k2] = Pr.prm.m2_coef[k2];
             it.e_cut = Pr.prm.e_cut;
@@ -541,6 +570,24 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
       if (Q.items[i].n_iter > kk) cnt += Q.items[i].n_units;
     Q.tasks_per_iter[kk] = cnt;
   }
+  // VEGAS+: hypercube arrays and sample blocks, items with more iterations first
+  for (int i : order) {
+    ItemRec& it = Q.items[i];
+    if (!it.vplus) continue;
+    it.vp_off = Q.vp_hc;
+    it.vp_hb = Q.vp_hc + (int64_t)Q.vp_items.size();
+    it.vp_rec = Q.vp_recd;
+    Q.vp_hc += it.vp_M;
+    Q.vp_recd += (int64_t)it.vp_blocks * (2 + 2 * (int64_t)it.D * it.nb);
+    Q.vp_items.push_back(i);
+    for (int b = 0; b < it.vp_blocks; ++b) Q.vp_tasks.push_back(VpTask{i, b});
+  }
+  // offsets: M + 1 entries per item, at vp_off + (the item's rank among the VEGAS+ items)
+  Q.vp_hoffs = Q.vp_hc + (int64_t)Q.vp_items.size();
+  Q.vp_per_iter.assign(Q.n_iter_max, 0);
+  for (int kk = 0; kk < Q.n_iter_max; ++kk)
+    for (int i : Q.vp_items)
+      if (Q.items[i].n_iter > kk) Q.vp_per_iter[kk] += Q.items[i].vp_blocks;
   // plain: node-major
   {
     std::vector<int> byn(Q.items.size());
@@ -670,6 +717,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
          o_sS = take(8 * Q.n_slots), o_g = take(sizeof(GatherEntry) * Q.gather.size()),
          o_gp = take(sizeof(GatherProc) * std::max<size_t>(1, Q.gproc.size())), o_oC = take(8 * Q.n_out),
          o_oS = take(8 * Q.n_out), o_new = take(4 * std::max<size_t>(1, Q.new_maps.size()));
+  const size_t o_vpt = take(sizeof(VpTask) * Q.vp_tasks.size()), o_vpi = take(4 * Q.vp_items.size()),
+               o_nh = take(4 * (size_t)Q.vp_hc), o_hoff = take(8 * (size_t)Q.vp_hoffs),
+               o_vS1 = take(8 * (size_t)Q.vp_hc), o_vS2 = take(8 * (size_t)Q.vp_hc), o_vrec = take(8 * (size_t)Q.vp_recd);
   Q.scratch_bytes = s;
   char* base = c->ws ? c->ws + c->persist_bytes : nullptr;
   if (base) {
@@ -696,6 +746,13 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     Q.d_out_C = reinterpret_cast<double*>(base + o_oC);
     Q.d_out_S = reinterpret_cast<double*>(base + o_oS);
     Q.d_new = reinterpret_cast<int*>(base + o_new);
+    Q.d_vpt = reinterpret_cast<VpTask*>(base + o_vpt);
+    Q.d_vpi = reinterpret_cast<int*>(base + o_vpi);
+    Q.d_nh = reinterpret_cast<int*>(base + o_nh);
+    Q.d_hoff = reinterpret_cast<int64_t*>(base + o_hoff);
+    Q.d_vS1 = reinterpret_cast<double*>(base + o_vS1);
+    Q.d_vS2 = reinterpret_cast<double*>(base + o_vS2);
+    Q.d_vrec = reinterpret_cast<double*>(base + o_vrec);
   }
   *P = std::move(Q);
   return BMC_OK;
@@ -729,6 +786,21 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
     }
+  }
+  // VEGAS+ hypercube arrays (at most N / 2 hypercubes per item) and block records
+  for (auto& Pr : c->pr) {
+    if (!Pr.prm.vegas_plus) continue;
+    const int D = 3 * (Pr.n_in + Pr.n_out - 2);
+    const int64_t N = std::max<int64_t>(max_samples > 0 ? max_samples : 0, Pr.prm.n_samples);
+    size_t ni = 0;
+    for (size_t a = 0; a < c->sp.size(); ++a) {
+      int sides = 0;
+      for (int side = 0; side < 2; ++side) sides += multiplicity(Pr, (int)a, side) > 0;
+      ni += (size_t)c->sp[a].n * sides * (Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2);
+    }
+    const size_t M = (size_t)(N / 2), blocks = (M + kBlock - 1) / kBlock;
+    s += ni * (align_up(4 * M) + align_up(8 * (M + 1)) + 2 * align_up(8 * M) +
+               align_up(8 * blocks * (2 + 2 * (size_t)D * Pr.prm.n_bins)) + sizeof(VpTask) * blocks + 4);
   }
   // in-shell lists of the FP32-integrand screening pass (one slice's task positions)
   const size_t list_pos =
@@ -783,6 +855,10 @@ int upload_plan(bmc_ctx* c, Plan& P) {
   HIPCHK(c, hipMemcpyAsync(P.d_shp, P.sh_plain.data(), sizeof(ShellTask) * P.sh_plain.size(), hipMemcpyHostToDevice,
                            s));
   HIPCHK(c, hipMemcpyAsync(P.d_slot_begin, P.slot_begin.data(), 4 * P.slot_begin.size(), hipMemcpyHostToDevice, s));
+  if (!P.vp_tasks.empty()) {
+    HIPCHK(c, hipMemcpyAsync(P.d_vpt, P.vp_tasks.data(), sizeof(VpTask) * P.vp_tasks.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(P.d_vpi, P.vp_items.data(), 4 * P.vp_items.size(), hipMemcpyHostToDevice, s));
+  }
   if (!P.slot_items.empty())
     HIPCHK(c, hipMemcpyAsync(P.d_slot_items, P.slot_items.data(), 4 * P.slot_items.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(P.d_gather, P.gather.data(), sizeof(GatherEntry) * P.gather.size(), hipMemcpyHostToDevice,
@@ -864,6 +940,14 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.list_stride = P.list_stride;
   L.shell_rec = P.d_shell;
   L.n_listed = &c->st()->n_listed;
+  L.vp_tasks = P.d_vpt;
+  L.vp_nh = P.d_nh;
+  L.vp_hoff = P.d_hoff;
+  L.vp_S1 = P.d_vS1;
+  L.vp_S2 = P.d_vS2;
+  L.vp_rec = P.d_vrec;
+  const int n_vpi = (int)P.vp_items.size();
+  if (n_vpi) HIPCHK(c, launch_vplus_init(P.d_items, P.d_vpi, n_vpi, P.d_nh, P.d_hoff, s));
   const int max_grid = grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask);
   for (int k = 0; k < P.n_iter_max; ++k) {
     L.it = o.first_iter + k;
@@ -895,6 +979,12 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         L.sh_grid = std::min(L.n_sh, max_grid);
         HIPCHK(c, sample_phase(c, L, s));
       }
+    }
+    if (n_vpi && P.vp_per_iter[k] > 0) {  // VEGAS+ items: their own sample blocks and reduction
+      L.n_vp = P.vp_per_iter[k];
+      HIPCHK(c, launch_vplus(L, s));
+      HIPCHK(c, launch_vplus_reduce(P.d_items, P.d_vpi, n_vpi, P.d_nh, P.d_hoff, P.d_vS1, P.d_vS2, P.d_vrec, P.d_res_I,
+                                    P.d_res_V, k, c->maps(), o.freeze_maps, s));
     }
     HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_counts, P.d_shell, P.d_res_I, P.d_res_V, k,
                                   c->maps(), o.freeze_maps, s));
@@ -1013,6 +1103,8 @@ int bmc_default_process_params(bmc_process_params* p) {
   p->width_factor = 1.25;
   p->width_min = 1e-4;
   p->width_max = 0.2;
+  p->vegas_plus = 0;
+  p->beta = 0.75;
   p->m2_kind = BMC_M2_CONST;
   p->m2_coef[0] = 1.0;
   for (int k = 1; k < 6; ++k) p->m2_coef[k] = 0.0;
@@ -1135,6 +1227,8 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
   if (q.width_mode == BMC_WIDTH_REL && !(q.sigma_E <= 1.0)) return fail(c, BMC_EINVAL, "relative width above 1");
   if (q.width_adapt != 0 && q.width_adapt != 1) return fail(c, BMC_EINVAL, "width_adapt must be 0 or 1");
   if (q.m2_kind != BMC_M2_CONST && q.m2_kind != BMC_M2_POLY) return fail(c, BMC_EINVAL, "bad m2_kind");
+  if ((q.vegas_plus != 0 && q.vegas_plus != 1) || !(q.beta >= 0.0 && q.beta <= 2.0))
+    return fail(c, BMC_EINVAL, "vegas_plus must be 0 or 1 and beta in [0, 2]");
   for (int k = 0; k < 6; ++k)
     if (!std::isfinite(q.m2_coef[k])) return fail(c, BMC_EINVAL, "non-finite |M|^2 coefficient");
   if (q.width_adapt &&
@@ -1756,8 +1850,8 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
     if (S.interp != BMC_INTERP_LINLOG)
       return fail(c, BMC_EUNSUP, "vector-Jacobian products need the linear-in-ln q interpolation");
   for (auto& Pr : c->pr)
-    if (Pr.prm.m2_kind != BMC_M2_CONST)
-      return fail(c, BMC_EUNSUP, "vector-Jacobian products need a constant |M|^2");
+    if (Pr.prm.m2_kind != BMC_M2_CONST || Pr.prm.vegas_plus)
+      return fail(c, BMC_EUNSUP, "vector-Jacobian products need a constant |M|^2 and plain Vegas sampling");
   rc = check_ready(c);
   if (rc) return rc;
   HIPCHK(c, hipSetDevice(c->device));

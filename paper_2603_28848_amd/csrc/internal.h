@@ -101,11 +101,22 @@ struct ItemRec {
   // |M|^2 = coupling2 P(s, t) when m2poly: P = c0 + c1 s + c2 t + c3 s^2 + c4 s t + c5 t^2, s = (sum_r cs_r P_r)^2,
   // t = (sum_r ct_r P_r)^2 over the roles' four-momenta (cs: the first two initial positions; ct: +1 the first
   // initial, -1 the first final position)
+  // VEGAS+ (adaptive stratified sampling): vp_k strata per dimension, vp_M = vp_k^D hypercubes starting at index
+  // vp_off of the plan's hypercube arrays, vp_blocks sample blocks whose records start at vp_rec (doubles)
+  int vplus, vp_k, vp_M, vp_blocks;
+  int64_t vp_off, vp_hb, vp_rec;  // hypercube base, offset-array base (M + 1 entries), record base
+  double beta;
   int m2poly;
   double m2c[6];
   int r_cs[kMaxN], r_ct[kMaxN];
   int tab_species[kMaxTab];
   int n_tab;
+};
+
+// A VEGAS+ sample block: hypercubes [256 b, 256 (b + 1)) of item `item`.
+struct VpTask {
+  int item;
+  int b;
 };
 
 // A unit of work: `unit` of item `item` in iteration order.

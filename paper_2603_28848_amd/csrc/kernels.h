@@ -39,7 +39,26 @@ struct SampleLaunch {
   int sh_grid;
   double* shell_rec;     // per item: S1, S2, then 2 D nb histogram doubles
   unsigned long long* n_listed;  // running count of the samples the second pass evaluates
+  // VEGAS+ items: sample blocks of this iteration, per-hypercube allocation (n_h), offsets (sum of n before h),
+  // sums of W and W^2, and per-block training records (S1, S2, 2 D nb doubles)
+  const VpTask* vp_tasks;
+  int n_vp;
+  const int* vp_nh;
+  const int64_t* vp_hoff;
+  double* vp_S1;
+  double* vp_S2;
+  double* vp_rec;
 };
+
+// VEGAS+ sample blocks (every sample of the item evaluated in full, FP64 or FP32 integrand).
+hipError_t launch_vplus(const SampleLaunch& L, hipStream_t s);
+// VEGAS+: the uniform allocation n_h = N / M of the first iteration of a call, for the listed items.
+hipError_t launch_vplus_init(const ItemRec* items, const int* which, int n, int* nh, int64_t* hoff, hipStream_t s);
+// VEGAS+ per item: I and V of iteration `slot` from the hypercube sums; unless frozen, the map adapted from the
+// blocks' training records and the next allocation n_h = 2 + floor((N - 2 M) sigma_h^beta / sum).
+hipError_t launch_vplus_reduce(const ItemRec* items, const int* which, int n, int* nh, int64_t* hoff,
+                               const double* S1, const double* S2, const double* rec, double* res_I, double* res_V,
+                               int slot, double* maps, int freeze, hipStream_t s);
 
 // Screening pass of a sample launch (FP32 kinematics; lists the samples whose W can be nonzero).
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);

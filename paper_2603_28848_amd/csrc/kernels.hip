@@ -279,8 +279,10 @@ __device__ __forceinline__ void add4(T* P, T c, T E, T x, T y, T z) {
   P[3] += c * z;
 }
 
-template <int NI, typename FT, bool ALT>
-__device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, int* hj) {
+// STRAT (VEGAS+): y_d = (dig_d + u_d) / kst, the sample inside hypercube dig of kst^D.
+template <int NI, typename FT, bool ALT, bool STRAT = false>
+__device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint64_t n, int* hj,
+                                              const int* dig = nullptr, int kst = 1) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
   uint32_t wd[4 * ((D + 3) / 4)];
@@ -306,7 +308,8 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int d = 3 * k + c;
-      const double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+      double yn = (((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+      if constexpr (STRAT) yn = (((double)dig[d] + ((double)wd[d] + 0.5) * 2.3283064365386962890625e-10) / (double)kst) * dnb;
       int j = (int)yn;
       j = j > nb - 1 ? nb - 1 : j;
       const double del = yn - (double)j;
@@ -1380,6 +1383,9 @@ __device__ void rebin_dimension(double* edges, int nb, const double* v, double w
   }
 }
 
+__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double (*s_d)[kMaxBins],
+                               double (*s_w)[kMaxBins], double (*s_old)[kMaxBins + 1], double* s_sum, double* maps);
+
 __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
                                                       const double* shell_rec, double* res_I, double* res_V,
                                                       int slot, double* maps, int freeze) {
@@ -1387,7 +1393,7 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
   const int item = item_begin + blockIdx.x;
   const ItemRec& it = items[item];
-  if (slot >= it.n_iter) return;  // the item has finished its iterations
+  if (slot >= it.n_iter || it.vplus) return;  // finished, or a VEGAS+ item (its own reduction)
   const int D = it.D, nb = it.nb, DN = D * nb;
   const int64_t stride = 2 + 2 * (int64_t)DN;  // second-pass record
   if (threadIdx.x == 0) {
@@ -1418,8 +1424,15 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     sc[i] = c;
   }
   __syncthreads();
-  // Vegas adaptation, all dimensions at once: per-bin steps over the block, sums and rebinning per dimension in
-  // bin order.  Averages d = h / c:
+  adapt_item_map(it, sh, sc, s_d, s_w, s_old, s_sum, maps);
+}
+
+// Vegas adaptation of an item's map from its training sums sh (W^2) and sc (counts), D x nb in LDS, all dimensions
+// at once: per-bin steps over the block, sums and rebinning per dimension in bin order.
+__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double (*s_d)[kMaxBins],
+                               double (*s_w)[kMaxBins], double (*s_old)[kMaxBins + 1], double* s_sum, double* maps) {
+  const int D = it.D, nb = it.nb, DN = D * nb;
+  // averages d = h / c
   for (int i = threadIdx.x; i < DN; i += blockDim.x) {
     const int d = i / nb, j = i - d * nb;
     s_d[d][j] = sc[i] > 0.0 ? sh[i] / sc[i] : 0.0;
@@ -1451,6 +1464,170 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     double wsum = 0.0;
     for (int j = 0; j < nb; ++j) wsum += s_w[d][j];
     if (wsum > 0.0) rebin_dimension(maps + it.map_off + d * (nb + 1), nb, s_w[d], wsum, s_old[d]);
+  }
+}
+
+// ------------------------------------------------------------------------------------------------------
+// VEGAS+ (adaptive stratified sampling on top of the map).  y-space is cut into M = k^D hypercubes, hypercube
+// h = sum_d h_d k^d (dimension 0 fastest); iteration samples s = off_h + i, i < n_h, lie in hypercube h with
+// y_d = (h_d + u_d) / k.  One thread per hypercube evaluates its samples in order (every sample in full: the
+// allocation puts samples where W is not zero), keeping S1_h, S2_h in registers; the training histograms take
+// (W N_it / (M n_h))^2 per sample in the per-wave LDS histograms, summed per block into the block's record.
+template <int NI, int PREC, bool ALT>
+__device__ void vplus_run(const SampleLaunch& L, const VpTask task, unsigned char* smem) {
+  constexpr int D = 3 * NI;
+  using FT = typename std::conditional<PREC == 0, double, float>::type;
+  const ItemRec* __restrict__ it = &L.items[task.item];
+  ItemConsts<NI, FT> K;
+  const Lds lay = setup_block<NI, PREC>(L, it, smem, true, K);
+  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
+  double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
+  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
+  const int h = task.b * kBlock + tid;
+  double t1 = 0.0, t2 = 0.0;  // weighted sums (the record's S1, S2 fields; not used by the estimate)
+  if (h < it->vp_M) {
+    const int64_t hg = it->vp_off + h;
+    const int nh = L.vp_nh[hg];
+    const int64_t off = L.vp_hoff[it->vp_hb + h];
+    const int64_t n_it = L.vp_hoff[it->vp_hb + it->vp_M];
+    const double wt = (double)n_it / ((double)it->vp_M * (double)nh);
+    int dig[D];
+    int rem = h;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      dig[d] = rem % it->vp_k;
+      rem /= it->vp_k;
+    }
+    double s1 = 0.0, s2 = 0.0;
+    for (int i = 0; i < nh; ++i) {
+      int hj[D];
+      const double W = eval_sample<NI, FT, ALT, true>(K, (uint64_t)(off + i), hj, dig, it->vp_k);
+      s1 += W;
+      s2 += W * W;
+      accumulate<D>(W * wt, hj, t1, t2, my_h, my_c);
+    }
+    L.vp_S1[hg] = s1;
+    L.vp_S2[hg] = s2;
+  }
+  double* rec = L.vp_rec + it->vp_rec + (int64_t)task.b * (2 + 2 * (int64_t)DN);
+  finish_block(t1, t2, lay, DN, smem, rec, rec + 2);
+}
+
+template <int MASK, int PREC, bool ALT>
+__global__ __launch_bounds__(kBlock, 2) void k_vplus(SampleLaunch L) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const VpTask task = L.vp_tasks[blockIdx.x];
+  const int ni = L.items[task.item].nint;
+  if ((MASK & 1) && ni == 1) vplus_run<1, PREC, ALT>(L, task, smem);
+  if ((MASK & 2) && ni == 2) vplus_run<2, PREC, ALT>(L, task, smem);
+  if ((MASK & 4) && ni == 3) vplus_run<3, PREC, ALT>(L, task, smem);
+  if ((MASK & 8) && ni == 4) vplus_run<4, PREC, ALT>(L, task, smem);
+}
+
+// First iteration of a call: n_h = N / M, offsets h N / M.
+__global__ void k_vplus_init(const ItemRec* items, const int* which, int* nh, int64_t* hoff) {
+  const ItemRec& it = items[which[blockIdx.x]];
+  const int64_t n0 = it.N / it.vp_M;
+  for (int h = threadIdx.x; h <= it.vp_M; h += blockDim.x) {
+    if (h < it.vp_M) nh[it.vp_off + h] = (int)n0;
+    hoff[it.vp_hb + h] = (int64_t)h * n0;
+  }
+}
+
+// Per item: I = (1/M) sum_h S1_h / n_h and V = sum_h (S2_h - S1_h^2 / n_h) / (n_h (n_h - 1)) / M^2 (thread-strided
+// partial sums, then the fixed wave tree); unless frozen, the map adapted from the blocks' records (block order)
+// and the next allocation: d_h = (max(0, (S2_h - S1_h^2 / n_h) / (n_h - 1)) / M^2)^(beta / 2),
+// n_h = 2 + floor((N - 2 M) d_h / sum d) (N / M if sum d = 0), offsets by a block scan over contiguous chunks.
+__global__ __launch_bounds__(256) void k_vplus_reduce(const ItemRec* items, const int* which, int* nh,
+                                                      int64_t* hoff, double* S1, const double* S2, const double* rec,
+                                                      double* res_I, double* res_V, int slot, double* maps,
+                                                      int freeze) {
+  __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
+  __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
+  __shared__ double red[2 * kWaves];
+  __shared__ int64_t scan[256];
+  const ItemRec& it = items[which[blockIdx.x]];
+  if (slot >= it.n_iter) return;
+  const int tid = threadIdx.x, M = it.vp_M, wave = tid >> 6;
+  const double Md = (double)M;
+  double pI = 0.0, pV = 0.0;
+  for (int h = tid; h < M; h += 256) {
+    const double n = (double)nh[it.vp_off + h], s1 = S1[it.vp_off + h], s2 = S2[it.vp_off + h];
+    pI += s1 / n;
+    pV += (s2 - s1 * s1 / n) / (n * (n - 1.0));
+  }
+  pI = wave_sum(pI);
+  pV = wave_sum(pV);
+  if ((tid & 63) == 0) {
+    red[wave] = pI;
+    red[kWaves + wave] = pV;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double I = 0.0, V = 0.0;
+    for (int w = 0; w < kWaves; ++w) {
+      I += red[w];
+      V += red[kWaves + w];
+    }
+    res_I[it.res_off * kMaxIter + slot] = I / Md;
+    res_V[it.res_off * kMaxIter + slot] = V / (Md * Md);
+  }
+  if (freeze) return;
+  // training sums over the blocks' records, in block order
+  const int DN = it.D * it.nb;
+  const int64_t stride = 2 + 2 * (int64_t)DN;
+  for (int i = tid; i < DN; i += 256) {
+    double hs = 0.0, cs = 0.0;
+    for (int b = 0; b < it.vp_blocks; ++b) {
+      hs += rec[it.vp_rec + b * stride + 2 + i];
+      cs += rec[it.vp_rec + b * stride + 2 + DN + i];
+    }
+    sh[i] = hs;
+    sc[i] = cs;
+  }
+  __syncthreads();
+  adapt_item_map(it, sh, sc, s_d, s_w, s_old, s_sum, maps);
+  // allocation: d_h into S1 (each h by the thread that read it above), then the sum of d
+  double pd = 0.0;
+  for (int h = tid; h < M; h += 256) {
+    const double n = (double)nh[it.vp_off + h], s1 = S1[it.vp_off + h], s2 = S2[it.vp_off + h];
+    double v = (s2 - s1 * s1 / n) / (n - 1.0) / (Md * Md);
+    v = v > 0.0 ? v : 0.0;
+    const double d = pow(v, 0.5 * it.beta);
+    S1[it.vp_off + h] = d;
+    pd += d;
+  }
+  pd = wave_sum(pd);
+  __syncthreads();
+  if ((tid & 63) == 0) red[wave] = pd;
+  __syncthreads();
+  double sumd = 0.0;
+  for (int w = 0; w < kWaves; ++w) sumd += red[w];
+  // new n_h over contiguous chunks, then the exclusive scan of the chunk totals
+  const int chunk = (M + 255) / 256, h0 = tid * chunk, h1 = min(M, h0 + chunk);
+  const int64_t spare = it.N - 2 * (int64_t)M, n0 = it.N / M;
+  int64_t tot = 0;
+  for (int h = h0; h < h1; ++h) {
+    const int64_t n = sumd > 0.0 ? 2 + (int64_t)floor((double)spare * S1[it.vp_off + h] / sumd) : n0;
+    nh[it.vp_off + h] = (int)n;
+    tot += n;
+  }
+  scan[tid] = tot;
+  __syncthreads();
+  if (tid == 0) {
+    int64_t acc = 0;
+    for (int t = 0; t < 256; ++t) {
+      const int64_t v = scan[t];
+      scan[t] = acc;
+      acc += v;
+    }
+    hoff[it.vp_hb + M] = acc;
+  }
+  __syncthreads();
+  int64_t acc = scan[tid];
+  for (int h = h0; h < h1; ++h) {
+    hoff[it.vp_hb + h] = acc;
+    acc += nh[it.vp_off + h];
   }
 }
 
@@ -1882,6 +2059,19 @@ hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int MASK>
+hipError_t launch_vplus_t(const SampleLaunch& L, hipStream_t s) {
+  const dim3 g(L.n_vp), b(kBlock);
+  if (L.any_interp) {
+    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, true>), g, b, L.lds_bytes, s, L);
+    else hipLaunchKernelGGL((k_vplus<MASK, 1, true>), g, b, L.lds_bytes, s, L);
+  } else {
+    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, false>), g, b, L.lds_bytes, s, L);
+    else hipLaunchKernelGGL((k_vplus<MASK, 1, false>), g, b, L.lds_bytes, s, L);
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
@@ -1896,6 +2086,17 @@ hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {
     case 4: return launch_sample_t<4>(L, s);
     case 8: return launch_sample_t<8>(L, s);
     default: return launch_sample_t<15>(L, s);
+  }
+}
+
+hipError_t launch_vplus(const SampleLaunch& L, hipStream_t s) {
+  if (L.n_vp <= 0) return hipSuccess;
+  switch (L.nint_mask) {
+    case 1: return launch_vplus_t<1>(L, s);
+    case 2: return launch_vplus_t<2>(L, s);
+    case 4: return launch_vplus_t<4>(L, s);
+    case 8: return launch_vplus_t<8>(L, s);
+    default: return launch_vplus_t<15>(L, s);
   }
 }
 
@@ -1980,6 +2181,21 @@ hipError_t launch_exact22(const ItemRec* items, int n_items, const SpecDev* spec
                           const double* qnode, const DevState* st, double* res_I, double* res_V, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_exact22, dim3(n_items), dim3(kBlock), 0, s, items, spec, f64, qnode, st, res_I, res_V);
+  return hipGetLastError();
+}
+
+hipError_t launch_vplus_init(const ItemRec* items, const int* which, int n, int* nh, int64_t* hoff, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vplus_init, dim3(n), dim3(256), 0, s, items, which, nh, hoff);
+  return hipGetLastError();
+}
+
+hipError_t launch_vplus_reduce(const ItemRec* items, const int* which, int n, int* nh, int64_t* hoff,
+                               const double* S1, const double* S2, const double* rec, double* res_I, double* res_V,
+                               int slot, double* maps, int freeze, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_vplus_reduce, dim3(n), dim3(256), 0, s, items, which, nh, hoff, const_cast<double*>(S1), S2,
+                     rec, res_I, res_V, slot, maps, freeze);
   return hipGetLastError();
 }
 
