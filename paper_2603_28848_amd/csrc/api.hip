@@ -29,7 +29,8 @@ constexpr size_t kListCapBytes = size_t(1) << 30;
 // Second pass: an item's units form up to this many groups, each one task of the pass with its own record (enough
 // blocks for a per-grid-point launch, few enough records for a batched one)
 constexpr int kShellGroups = 16;
-constexpr int kMaxEvalPoints = BMC_MAXEVAL;  // map slots are reserved for this many points off the grid
+constexpr int kMaxEvalPoints = BMC_MAXEVAL;
+constexpr int kVplusLdsExtra = 257 * 8 + 256 * 8;  // the VEGAS+ pass's hypercube offsets and chunk of W  // map slots are reserved for this many points off the grid
 
 // VEGAS+ strata per dimension: the largest k >= 1 with k^D <= N / 2.
 int vplus_strata(int64_t N, int D) {
@@ -699,6 +700,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     Q.lds32 = std::max(Q.lds32, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
   }
   if (Q.lds64 > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
+  if (!Q.vp_items.empty() && ((Q.lds64 + 15) & ~15) + kVplusLdsExtra > 65536)
+    return fail(c, BMC_EUNSUP, "per-block LDS of the VEGAS+ pass above 64 KB (grid or bins too large)");
   // scratch sizes
   size_t s = 0;
   auto take = [&](size_t bytes) {

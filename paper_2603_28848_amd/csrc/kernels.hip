@@ -1470,9 +1470,13 @@ __device__ void adapt_item_map(const ItemRec& it, const double* sh, const double
 // ------------------------------------------------------------------------------------------------------
 // VEGAS+ (adaptive stratified sampling on top of the map).  y-space is cut into M = k^D hypercubes, hypercube
 // h = sum_d h_d k^d (dimension 0 fastest); iteration samples s = off_h + i, i < n_h, lie in hypercube h with
-// y_d = (h_d + u_d) / k.  One thread per hypercube evaluates its samples in order (every sample in full: the
-// allocation puts samples where W is not zero), keeping S1_h, S2_h in registers; the training histograms take
+// y_d = (h_d + u_d) / k.  A block takes 256 consecutive hypercubes and walks their samples in chunks of 256, one
+// sample per thread (every sample in full: the allocation puts samples where W is not zero); after each chunk the
+// thread that owns a hypercube adds the chunk's W of that hypercube in sample order, so S1_h and S2_h are summed
+// exactly as a sequential loop over i would, whatever the allocation.  The training histograms take
 // (W N_it / (M n_h))^2 per sample in the per-wave LDS histograms, summed per block into the block's record.
+constexpr int kVpLds = (kBlock + 1) * 8 + kBlock * 8;  // LDS beyond the sample layout: offsets and a chunk of W
+
 template <int NI, int PREC, bool ALT>
 __device__ void vplus_run(const SampleLaunch& L, const VpTask task, unsigned char* smem) {
   constexpr int D = 3 * NI;
@@ -1483,31 +1487,52 @@ __device__ void vplus_run(const SampleLaunch& L, const VpTask task, unsigned cha
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
-  const int h = task.b * kBlock + tid;
+  int64_t* s_off = reinterpret_cast<int64_t*>(smem + align16(lay.total));  // kBlock + 1 offsets
+  double* s_W = reinterpret_cast<double*>(s_off + kBlock + 1);
+  const int h0 = task.b * kBlock, nhc = min(kBlock, it->vp_M - h0);
+  for (int i = tid; i <= nhc; i += kBlock) s_off[i] = L.vp_hoff[it->vp_hb + h0 + i];
+  __syncthreads();
+  const int64_t n_it = L.vp_hoff[it->vp_hb + it->vp_M];
+  const double Mw = (double)it->vp_M;
+  const int64_t s_begin = s_off[0], s_end = s_off[nhc];
   double t1 = 0.0, t2 = 0.0;  // weighted sums (the record's S1, S2 fields; not used by the estimate)
-  if (h < it->vp_M) {
-    const int64_t hg = it->vp_off + h;
-    const int nh = L.vp_nh[hg];
-    const int64_t off = L.vp_hoff[it->vp_hb + h];
-    const int64_t n_it = L.vp_hoff[it->vp_hb + it->vp_M];
-    const double wt = (double)n_it / ((double)it->vp_M * (double)nh);
-    int dig[D];
-    int rem = h;
+  double s1 = 0.0, s2 = 0.0;  // the owned hypercube's sums
+  for (int64_t cs = s_begin; cs < s_end; cs += kBlock) {
+    const int64_t smp = cs + tid;
+    if (smp < s_end) {
+      int lo = 0, hi = nhc;  // the local hypercube: s_off[lo] <= smp < s_off[lo + 1]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= smp) lo = mid;
+        else hi = mid;
+      }
+      int dig[D];
+      int rem = h0 + lo;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      dig[d] = rem % it->vp_k;
-      rem /= it->vp_k;
-    }
-    double s1 = 0.0, s2 = 0.0;
-    for (int i = 0; i < nh; ++i) {
+      for (int d = 0; d < D; ++d) {
+        dig[d] = rem % it->vp_k;
+        rem /= it->vp_k;
+      }
+      const double wt = (double)n_it / (Mw * (double)(s_off[lo + 1] - s_off[lo]));
       int hj[D];
-      const double W = eval_sample<NI, FT, ALT, true>(K, (uint64_t)(off + i), hj, dig, it->vp_k);
-      s1 += W;
-      s2 += W * W;
+      const double W = eval_sample<NI, FT, ALT, true>(K, (uint64_t)smp, hj, dig, it->vp_k);
       accumulate<D>(W * wt, hj, t1, t2, my_h, my_c);
+      s_W[tid] = W;
     }
-    L.vp_S1[hg] = s1;
-    L.vp_S2[hg] = s2;
+    __syncthreads();
+    if (tid < nhc) {
+      const int64_t a = max(s_off[tid], cs), e = min(s_off[tid + 1], cs + kBlock);
+      for (int64_t i = a; i < e; ++i) {
+        const double w = s_W[i - cs];
+        s1 += w;
+        s2 += w * w;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < nhc) {
+    L.vp_S1[it->vp_off + h0 + tid] = s1;
+    L.vp_S2[it->vp_off + h0 + tid] = s2;
   }
   double* rec = L.vp_rec + it->vp_rec + (int64_t)task.b * (2 + 2 * (int64_t)DN);
   finish_block(t1, t2, lay, DN, smem, rec, rec + 2);
@@ -2062,12 +2087,13 @@ hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
 template <int MASK>
 hipError_t launch_vplus_t(const SampleLaunch& L, hipStream_t s) {
   const dim3 g(L.n_vp), b(kBlock);
+  const size_t lds = align16((int)L.lds_bytes) + kVpLds;
   if (L.any_interp) {
-    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, true>), g, b, L.lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_vplus<MASK, 1, true>), g, b, L.lds_bytes, s, L);
+    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, true>), g, b, lds, s, L);
+    else hipLaunchKernelGGL((k_vplus<MASK, 1, true>), g, b, lds, s, L);
   } else {
-    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, false>), g, b, L.lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_vplus<MASK, 1, false>), g, b, L.lds_bytes, s, L);
+    if (L.precision == 0) hipLaunchKernelGGL((k_vplus<MASK, 0, false>), g, b, lds, s, L);
+    else hipLaunchKernelGGL((k_vplus<MASK, 1, false>), g, b, lds, s, L);
   }
   return hipGetLastError();
 }
