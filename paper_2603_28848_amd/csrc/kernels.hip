@@ -224,7 +224,7 @@ struct ItemConsts {
   const double* e;    // LDS map edges (D x nb)
   const double* w;    // LDS map widths
   const double2* sc;  // LDS sin/cos of k pi/16
-  const float2* m32;  // LDS map (edge, width) pairs in FP32 (screening pass)
+  const float2* m32;  // LDS map pairs in FP32 (screening pass): (edge, width 2^-32), angles in revolutions
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
@@ -427,12 +427,11 @@ constexpr int kFar = 0, kNear = 1, kInShell = 2;
 template <int NI, bool FINISH, bool ALT = false>
 __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, int* hj, double* Wout) {
   constexpr int D = 3 * NI;
-  constexpr float kInv2Pi = 0.15915494309189535f;
   uint32_t wd[4 * ((D + 3) / 4)];
   philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
   const uint32_t nb = (uint32_t)K.nb;
   const uint64_t half_nb = nb >> 1;
-  const float fnb = (float)nb;
+  const float fnb32 = (float)nb * 4294967296.0f, fnb32rev = fnb32 * 6.2831853071795865f;  // per-dim Jacobian
   const float inv_a = (float)K.inv_a;
   float J = 1.0f, jac = 1.0f;
   float sx = 0.0f, sy = 0.0f, sz = (float)(K.esg[NI + 1] * K.p_obs);
@@ -454,17 +453,17 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
     for (int c = 0; c < 3; ++c) {
       const int d = 3 * k + c;
       // y nb = (word + 1/2) nb / 2^32: the bin is the high word of word nb + floor(nb/2) (exact; an odd nb only
-      // moves the in-bin offset by 2^-33), the offset comes from the low word
-      const uint64_t t = (uint64_t)wd[d] * nb + half_nb;
-      const int j = (int)(t >> 32);
-      const float del = (float)(uint32_t)t * 2.3283064365386963e-10f;
-      const float2 ew = K.m32[d * (int)nb + j];
-      x3[c] = fmaf(ew.y, del, ew.x);
-      J *= fnb * ew.y;
-      hj[d] = d * (int)nb + j;
+      // moves the in-bin offset by 2^-33), the offset comes from the low word; d nb added to the high word makes it
+      // the histogram index d nb + j directly
+      const uint64_t t = (uint64_t)wd[d] * nb + (half_nb + ((uint64_t)(d * nb) << 32));
+      const int jd = (int)(t >> 32);
+      const float2 ew = K.m32[jd];
+      x3[c] = fmaf(ew.y, (float)(uint32_t)t, ew.x);
+      J *= (c == 0 ? fnb32 : fnb32rev) * ew.y;
+      hj[d] = jd;
     }
     const float r = x3[0];
-    const float th = x3[1] * kInv2Pi, ph = x3[2] * kInv2Pi;  // the hardware sin/cos take revolutions
+    const float th = x3[1], ph = x3[2];  // revolutions
     const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
     const float sph = __builtin_amdgcn_sinf(ph), cph = __builtin_amdgcn_cosf(ph);
     const float p = r * inv_a;
@@ -600,7 +599,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
     sm_e[i] = e0;
     sm_w[i] = e1 - e0;
-    sm_m32[i] = make_float2((float)e0, (float)(e1 - e0));
+    // screening pairs: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions
+    // (the hardware sine takes them), so a coordinate is one fma of the low word
+    const double sc = (d % 3 == 0) ? 1.0 : 0.15915494309189535;
+    sm_m32[i] = make_float2((float)(e0 * sc), (float)((e1 - e0) * sc * 2.3283064365386962890625e-10));
   }
   if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; stage && k < n_tab; ++k) {

@@ -1,0 +1,51 @@
+"""Parameter validation of the newer C-ABI options: every bad value is rejected with an error and nothing changes."""
+import pytest
+
+from gpu_util import gpu_available
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+@pytest.mark.parametrize("bad", [
+    dict(width_mode=2), dict(width_mode=wl.WIDTH_REL, sigma_E=1.5), dict(width_adapt=2),
+    dict(width_adapt=1, width_lo=0.0), dict(width_adapt=1, width_lo=0.02, width_hi=0.01),
+    dict(width_adapt=1, width_factor=1.0), dict(width_adapt=1, width_min=0.0),
+    dict(width_adapt=1, width_min=0.3, width_max=0.2), dict(m2_kind=3), dict(vegas_plus=2), dict(beta=2.5),
+])
+def test_bad_process_parameters_are_rejected(bad):
+    bm = _bm()
+    ctx = bm.Context()
+    sid = ctx.add_species("phi", wl.BOSE, 32, 0.01, 20.0)
+    with pytest.raises(bm.BmcError):
+        ctx.add_process([sid, sid], [sid, sid], **bad)
+
+
+def test_bad_width_and_interp_calls_are_rejected():
+    bm = _bm()
+    w = wl.w22_mb()
+    w.processes[0].width_mode = wl.WIDTH_REL
+    w.processes[0].sigma_E = 0.01
+    ctx = bm.from_workload(w)
+    for v in (0.0, -1.0, 1.5, float("nan")):
+        with pytest.raises(bm.BmcError):
+            ctx.set_width(0, v)
+    assert ctx.get_width(0) == 0.01
+    with pytest.raises(bm.BmcError):
+        ctx.set_width(3, 0.01)
+    for mode in (-1, 3):
+        with pytest.raises(bm.BmcError):
+            ctx.set_interp(0, mode)
+    with pytest.raises(bm.BmcError):
+        ctx.set_interp(5, wl.INTERP_SPLINE)
