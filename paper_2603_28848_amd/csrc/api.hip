@@ -26,9 +26,12 @@ constexpr size_t kAlign = 256;
 constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
 // FP32 integrand: bytes of in-shell lists one screening launch may fill (larger batches run in slices)
 constexpr size_t kListCapBytes = size_t(1) << 30;
-// Second pass: an item's units form up to this many groups, each one task of the pass with its own record (enough
-// blocks for a per-grid-point launch, few enough records for a batched one)
-constexpr int kShellGroups = 16;
+// Second pass: an item's units form groups, each one task of the pass with its own record.  A batched launch has
+// many items and gives each few groups (every group pays for its barriers, histogram clear and record); a
+// per-grid-point launch has a handful of items and needs many groups to fill the device.  Both depend on the item
+// alone, so an item's results do not depend on the other items of its plan.
+constexpr int kShellGroupsBatched = 4;
+constexpr int kShellGroupsPlain = 32;
 constexpr int kMaxEvalPoints = BMC_MAXEVAL;
 constexpr int kVplusLdsExtra = 257 * 8 + 256 * 8;  // the VEGAS+ pass's hypercube offsets and chunk of W  // map slots are reserved for this many points off the grid
 
@@ -43,7 +46,14 @@ int vplus_strata(int64_t N, int D) {
   }
 }
 
-int shell_units_for(int64_t n_units) { return (int)((n_units + kShellGroups - 1) / kShellGroups); }
+// Units per group for at most `groups` groups, and the number of groups that makes.
+int shell_units_for(int64_t n_units, int groups) { return std::max(1, (int)((n_units + groups - 1) / groups)); }
+int64_t shell_groups(int64_t n_units, int su) { return (n_units + su - 1) / su; }
+// Records an item reserves: enough for either launch's grouping.
+int64_t shell_records(int64_t n_units) {
+  return std::max(shell_groups(n_units, shell_units_for(n_units, kShellGroupsBatched)),
+                  shell_groups(n_units, shell_units_for(n_units, kShellGroupsPlain)));
+}
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -481,8 +491,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.part_off = part;
             part += (int64_t)it.n_units * D * nb;
             it.shell_off = shell;
-            it.shell_units = std::max(1, shell_units_for(it.n_units));
-            shell += (int64_t)((it.n_units + it.shell_units - 1) / it.shell_units) * (2 + 2 * D * nb);
+            it.shell_units = shell_units_for(it.n_units, kShellGroupsBatched);
+            it.shell_units_p = shell_units_for(it.n_units, kShellGroupsPlain);
+            shell += shell_records(it.n_units) * (2 + 2 * D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
@@ -613,28 +624,28 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
       if (Q.tasks_batched[t].unit == 0) first_b[Q.tasks_batched[t].item] = (int)t;
     for (size_t t = 0; t < Q.tasks_plain.size(); ++t)
       if (Q.tasks_plain[t].unit == 0) first_p[Q.tasks_plain[t].item] = (int)t;
-    // groups of shell_units consecutive units per in-shell task, in the order of the item's tasks
-    auto groups = [&](int i, int first, std::vector<ShellTask>& out) {
+    // groups of su consecutive units per second-pass task, in the order of the item's tasks
+    auto groups = [&](int i, int first, int su, std::vector<ShellTask>& out) {
       const ItemRec& it = Q.items[i];
       const int64_t stride = 2 + 2 * (int64_t)it.D * it.nb;
-      for (int u = 0; u < it.n_units; u += it.shell_units)
-        out.push_back(ShellTask{i, first + u, u, std::min(it.n_units, u + it.shell_units),
-                                it.shell_off + (u / it.shell_units) * stride});
+      for (int u = 0; u < it.n_units; u += su)
+        out.push_back(ShellTask{i, first + u, u, std::min(it.n_units, u + su), it.shell_off + (u / su) * stride});
     };
     std::vector<int> sh_first(Q.items.size(), 0);
     for (int i : order) {
       sh_first[i] = (int)Q.sh_batched.size();
-      groups(i, first_b[i], Q.sh_batched);
+      groups(i, first_b[i], Q.items[i].shell_units, Q.sh_batched);
     }
     Q.sh_per_iter.assign(Q.n_iter_max, 0);
     for (int kk = 0; kk < Q.n_iter_max; ++kk)
       for (int i : order)
         if (Q.items[i].n_iter > kk)
-          Q.sh_per_iter[kk] += (Q.items[i].n_units + Q.items[i].shell_units - 1) / Q.items[i].shell_units;
+          Q.sh_per_iter[kk] += (int)shell_groups(Q.items[i].n_units, Q.items[i].shell_units);
     for (size_t g = 0; g + 1 < Q.plain_node_begin.size(); ++g) {
       Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
       for (int t = Q.plain_node_begin[g]; t < Q.plain_node_begin[g + 1]; ++t)
-        if (Q.tasks_plain[t].unit == 0) groups(Q.tasks_plain[t].item, t, Q.sh_plain);
+        if (Q.tasks_plain[t].unit == 0)
+          groups(Q.tasks_plain[t].item, t, Q.items[Q.tasks_plain[t].item].shell_units_p, Q.sh_plain);
     }
     Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
     int64_t umax = 0, pmin = 0;
@@ -784,8 +795,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       units += ni * nu;
       tasks += ni * nu;
       part += ni * nu * D * Pr.prm.n_bins;
-      const int64_t G = shell_units_for(nu);
-      shell += ni * (size_t)((nu + G - 1) / G) * (2 + 2 * D * Pr.prm.n_bins);
+      shell += ni * (size_t)shell_records(nu) * (2 + 2 * D * Pr.prm.n_bins);
       per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
     }
@@ -990,7 +1000,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
                                     P.d_res_V, k, c->maps(), o.freeze_maps, s));
     }
     HIPCHK(c, launch_reduce_adapt(P.d_items, 0, (int)P.items.size(), P.d_counts, P.d_shell, P.d_res_I, P.d_res_V, k,
-                                  c->maps(), o.freeze_maps, s));
+                                  c->maps(), o.freeze_maps, o.launch == BMC_LAUNCH_PLAIN ? 1 : 0, s));
   }
   HIPCHK(c, launch_combine(P.d_items, (int)P.items.size(), P.d_res_I, P.d_res_V, P.n_iter_max, P.d_item_Ibar,
                            P.d_item_sig, P.d_slot_begin, P.d_slot_items, P.n_slots, P.d_slot_C, P.d_slot_S2, s));

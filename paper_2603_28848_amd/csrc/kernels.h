@@ -67,10 +67,10 @@ hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
 // Per item: S1, S2 and the W^2 histogram from its second-pass records in group order, the bin counts from its
 // units' counts and the second-pass records; stores I_it, V_it for iteration slot `slot` and (unless frozen)
-// adapts the item's map.
+// adapts the item's map.  `plain` names the grouping the records were written with (per-grid-point launch).
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
-                               int freeze, hipStream_t s);
+                               int freeze, int plain, hipStream_t s);
 
 // Initialises the maps of items (uniform edges over each dimension's range).
 hipError_t launch_init_maps(const ItemRec* items, const int* which, int n, const SpecDev* spec, double* maps,

@@ -1390,7 +1390,7 @@ __device__ void adapt_item_map(const ItemRec& it, const double* sh, const double
 
 __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
                                                       const double* shell_rec, double* res_I, double* res_V,
-                                                      int slot, double* maps, int freeze) {
+                                                      int slot, double* maps, int freeze, int plain) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
   __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
   const int item = item_begin + blockIdx.x;
@@ -1398,10 +1398,11 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   if (slot >= it.n_iter || it.vplus) return;  // finished, or a VEGAS+ item (its own reduction)
   const int D = it.D, nb = it.nb, DN = D * nb;
   const int64_t stride = 2 + 2 * (int64_t)DN;  // second-pass record
+  const int su = plain ? it.shell_units_p : it.shell_units;  // units per record of this launch's grouping
   if (threadIdx.x == 0) {
     double S1 = 0.0, S2 = 0.0;
-    for (int u = 0; u < it.n_units; u += it.shell_units) {
-      const int64_t r = it.shell_off + (u / it.shell_units) * stride;
+    for (int u = 0; u < it.n_units; u += su) {
+      const int64_t r = it.shell_off + (u / su) * stride;
       S1 += shell_rec[r];
       S2 += shell_rec[r + 1];
     }
@@ -1417,8 +1418,8 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     uint64_t cu = 0;  // the screening pass's counts (exact integers)
     for (int u = 0; u < it.n_units; ++u) cu += cnt[(int64_t)u * DN + i];
     double h = 0.0, c = (double)cu;
-    for (int u = 0; u < it.n_units; u += it.shell_units) {
-      const int64_t r = it.shell_off + (u / it.shell_units) * stride;
+    for (int u = 0; u < it.n_units; u += su) {
+      const int64_t r = it.shell_off + (u / su) * stride;
       h += shell_rec[r + 2 + i];
       c += shell_rec[r + 2 + DN + i];
     }
@@ -2181,10 +2182,10 @@ hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* co
 
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
-                               int freeze, hipStream_t s) {
+                               int freeze, int plain, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(256), 0, s, items, item_begin, counts, shell_rec, res_I,
-                     res_V, slot, maps, freeze);
+                     res_V, slot, maps, freeze, plain);
   return hipGetLastError();
 }
 

@@ -152,6 +152,30 @@ def test_plain_equals_batched_bitwise_and_run_to_run(precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_plain_and_batched_groupings_agree_to_rounding(precision):
+    """At 2^17 samples an item has 32 units: a batched launch sums its second pass in 4 records of 8 units, a
+    per-grid-point launch in 32 records of one unit.  On frozen maps the two differ only in the order of the FP64
+    sums, and each launch mode repeats itself bitwise."""
+    bm = _bm()
+    w = wl.w23_be(n_grid=16, N=1 << 17, nitn=2)
+    outs = {0: [], 1: []}
+    for launch in (0, 1, 0, 1):
+        ctx = bm.from_workload(w)
+        C, S = ctx.collision(-1, -1, bm.default_opts(seed=7, epoch=3, launch=launch, precision=precision,
+                                                     freeze_maps=1))
+        outs[launch].append((C, S))
+    for launch in (0, 1):
+        (C0, S0), (C1, S1) = outs[launch]
+        assert np.array_equal(C0, C1) and np.array_equal(S0, S1), launch
+    (Cb, Sb), (Cp, Sp) = outs[0][0], outs[1][0]
+    assert np.all(Sb > 0)
+    dC = np.max(np.abs(Cb - Cp) / Sb)
+    dS = np.max(np.abs(Sb - Sp) / Sb)
+    say("groupings: max |C_batched - C_plain| / sigma = %.2e, max rel dsigma = %.2e" % (dC, dS))
+    assert dC < 1e-9 and dS < 1e-9
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_launch_tuning_and_autotuner_do_not_change_results(precision):
     bm = _bm()
     w = wl.w23_be(n_grid=24, N=5000, nitn=3)
