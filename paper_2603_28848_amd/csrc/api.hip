@@ -493,7 +493,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.shell_off = shell;
             it.shell_units = shell_units_for(it.n_units, kShellGroupsBatched);
             it.shell_units_p = shell_units_for(it.n_units, kShellGroupsPlain);
-            shell += shell_records(it.n_units) * (2 + 2 * D * nb);
+            shell += shell_records(it.n_units) * (2 + D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
@@ -627,7 +627,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     // groups of su consecutive units per second-pass task, in the order of the item's tasks
     auto groups = [&](int i, int first, int su, std::vector<ShellTask>& out) {
       const ItemRec& it = Q.items[i];
-      const int64_t stride = 2 + 2 * (int64_t)it.D * it.nb;
+      const int64_t stride = 2 + (int64_t)it.D * it.nb;
       for (int u = 0; u < it.n_units; u += su)
         out.push_back(ShellTask{i, first + u, u, std::min(it.n_units, u + su), it.shell_off + (u / su) * stride});
     };
@@ -795,7 +795,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       units += ni * nu;
       tasks += ni * nu;
       part += ni * nu * D * Pr.prm.n_bins;
-      shell += ni * (size_t)shell_records(nu) * (2 + 2 * D * Pr.prm.n_bins);
+      shell += ni * (size_t)shell_records(nu) * (2 + D * Pr.prm.n_bins);
       per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
     }

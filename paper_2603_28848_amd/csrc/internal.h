@@ -82,7 +82,7 @@ struct ItemRec {
   int64_t map_off;   // doubles: Vegas map, kMaxD rows of (nb + 1) edges
   int64_t part_off;  // collision: first unit's bin counts (D nb 32-bit counts per unit); adjoint: doubles of the
                      // first unit record
-  int64_t shell_off; // doubles: the item's in-shell records (S1, S2, 2 D nb each), FP32 integrand
+  int64_t shell_off; // doubles: the item's second-pass records (S1, S2 and D nb W^2 sums each)
   int shell_units;   // units per second-pass record in a batched launch
   int shell_units_p; // units per second-pass record in a per-grid-point launch
   int64_t res_off;   // index of this item's per-iteration results

@@ -37,7 +37,7 @@ struct SampleLaunch {
   const ShellTask* sh_tasks;
   int sh_begin, n_sh;    // in-shell tasks (one per item) of this launch
   int sh_grid;
-  double* shell_rec;     // per item: S1, S2, then 2 D nb histogram doubles
+  double* shell_rec;     // per second-pass group: S1, S2, then the D nb W^2 sums
   unsigned long long* n_listed;  // running count of the samples the second pass evaluates
   // VEGAS+ items: sample blocks of this iteration, per-hypercube allocation (n_h), offsets (sum of n before h),
   // sums of W and W^2, and per-block training records (S1, S2, 2 D nb doubles)
@@ -66,7 +66,7 @@ hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
 hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
 // Per item: S1, S2 and the W^2 histogram from its second-pass records in group order, the bin counts from its
-// units' counts and the second-pass records; stores I_it, V_it for iteration slot `slot` and (unless frozen)
+// units' counts (the screening pass counts every sample); stores I_it, V_it for iteration slot `slot` and (unless frozen)
 // adapts the item's map.  `plain` names the grouping the records were written with (per-grid-point launch).
 hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,

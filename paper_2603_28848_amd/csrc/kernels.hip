@@ -33,8 +33,8 @@ struct Lds {
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS of one sample block: map edges and widths (D x nb, FP64, and as FP32 pairs), sin/cos of k pi/16 (33 entries),
-// per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction scratch.
+// LDS of one sample block: map edges and widths (D x nb, FP64, and as 16-byte FP32 slots), sin/cos of k pi/16 (33
+// entries), per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction scratch.
 __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
   Lds L;
   const int DN = D * nb;
@@ -44,7 +44,7 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   L.off_w = o;
   o = align16(o + DN * 8);
   L.off_m32 = o;
-  o = align16(o + DN * 8);
+  o = align16(o + DN * 16);
   L.off_sc = o;
   o = align16(o + 33 * 16);
   L.off_tab = o;
@@ -224,7 +224,8 @@ struct ItemConsts {
   const double* e;    // LDS map edges (D x nb)
   const double* w;    // LDS map widths
   const double2* sc;  // LDS sin/cos of k pi/16
-  const float2* m32;  // LDS map pairs in FP32 (screening pass): (edge, width 2^-32), angles in revolutions
+  float4* m32;        // LDS map slots in FP32 (screening pass): edge, width 2^-32 (angles in revolutions), the
+                      // unit's count of samples in the bin (as bits), padding
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
@@ -421,16 +422,20 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 //   kNear     the rest: with FINISH, W is finished in FP32 (its Gaussian factor is below e^-72 relative, so W only
 //             matters for the map's training histogram, where ~1e-6 accuracy is ample).
 // m = 1e-3 of the summed energies bounds the difference of the FP32 and FP64 dE with a wide margin.  The bin of
-// every dimension is exact (the same as with the FP64 map).
+// every dimension is exact (the same as with the FP64 map).  With COUNT the sample is added to the count of its bin
+// in every dimension (the count word of the bin's map slot).
 constexpr int kFar = 0, kNear = 1, kInShell = 2;
 
-template <int NI, bool FINISH, bool ALT = false>
+template <int NI, bool FINISH, bool ALT = false, bool COUNT = false>
 __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, int* hj, double* Wout) {
   constexpr int D = 3 * NI;
   uint32_t wd[4 * ((D + 3) / 4)];
   philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
   const uint32_t nb = (uint32_t)K.nb;
   const uint64_t half_nb = nb >> 1;
+  // nb as a vector operand, so that the 64-bit multiply-add below can take its uniform addend from scalar registers
+  uint32_t vnb;
+  asm("v_mov_b32 %0, %1" : "=v"(vnb) : "s"(nb));
   const float fnb32 = (float)nb * 4294967296.0f, fnb32rev = fnb32 * 6.2831853071795865f;  // per-dim Jacobian
   const float inv_a = (float)K.inv_a;
   float J = 1.0f, jac = 1.0f;
@@ -455,9 +460,10 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
       // y nb = (word + 1/2) nb / 2^32: the bin is the high word of word nb + floor(nb/2) (exact; an odd nb only
       // moves the in-bin offset by 2^-33), the offset comes from the low word; d nb added to the high word makes it
       // the histogram index d nb + j directly
-      const uint64_t t = (uint64_t)wd[d] * nb + (half_nb + ((uint64_t)(d * nb) << 32));
+      const uint64_t t = (uint64_t)wd[d] * vnb + (half_nb + ((uint64_t)(d * nb) << 32));
       const int jd = (int)(t >> 32);
-      const float2 ew = K.m32[jd];
+      const float2 ew = *reinterpret_cast<const float2*>(K.m32 + jd);
+      if constexpr (COUNT) atomicAdd(reinterpret_cast<uint32_t*>(K.m32 + jd) + 2, 1u);  // the bin's count
       x3[c] = fmaf(ew.y, (float)(uint32_t)t, ew.x);
       J *= (c == 0 ? fnb32 : fnb32rev) * ew.y;
       hj[d] = jd;
@@ -564,13 +570,6 @@ __device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) 
   for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Clears the per-wave count histograms only.
-__device__ __forceinline__ void clear_counts(const Lds& lay, unsigned char* smem) {
-  uint4* p = reinterpret_cast<uint4*>(smem + lay.off_c);
-  const int n16 = (lay.off_red - lay.off_c) / 16;
-  for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
-}
-
 // Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 pairs), the sin/cos table and
 // the f tables into LDS unless the block's previous task staged the same item, clears the per-wave training
 // histograms, and fills the per-item constants at the current time.  Ends with a block barrier.
@@ -590,7 +589,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   const Lds lay = lds_layout(D, nb, n_tab, n_max, sizeof(FT));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
-  float2* sm_m32 = reinterpret_cast<float2*>(smem + lay.off_m32);
+  float4* sm_m32 = reinterpret_cast<float4*>(smem + lay.off_m32);
   double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
 
   const double* __restrict__ map = L.maps + it->map_off;
@@ -599,10 +598,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
     sm_e[i] = e0;
     sm_w[i] = e1 - e0;
-    // screening pairs: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions
-    // (the hardware sine takes them), so a coordinate is one fma of the low word
+    // screening slots: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions
+    // (the hardware sine takes them), so a coordinate is one fma of the low word; the bin's count starts at 0
     const double sc = (d % 3 == 0) ? 1.0 : 0.15915494309189535;
-    sm_m32[i] = make_float2((float)(e0 * sc), (float)((e1 - e0) * sc * 2.3283064365386962890625e-10));
+    sm_m32[i] = make_float4((float)(e0 * sc), (float)((e1 - e0) * sc * 2.3283064365386962890625e-10), 0.0f, 0.0f);
   }
   if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; stage && k < n_tab; ++k) {
@@ -715,10 +714,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   return lay;
 }
 
-// One sample's contribution: S1 += W, S2 += W^2 (registers), W^2 and a count into the wave's histograms.  A zero
-// W^2 (cut samples, and every |W| below the histogram floor: with sigma_E << E most off-shell samples) leaves the
-// sums unchanged, so its atomics are skipped.
-template <int D>
+// One sample's contribution: S1 += W, S2 += W^2 (registers), W^2 and (with COUNT) a count into the wave's
+// histograms.  A zero W^2 (cut samples, and every |W| below the histogram floor: with sigma_E << E most off-shell
+// samples) leaves the sums unchanged, so its atomics are skipped.
+template <int D, bool COUNT = true>
 __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, double& S2, double* my_h,
                                            uint32_t* my_c) {
   S1 += W;
@@ -728,31 +727,27 @@ __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, 
 #pragma unroll
     for (int d = 0; d < D; ++d) atomicAdd(&my_h[hj[d]], w2);
   }
+  if constexpr (COUNT) {
 #pragma unroll
-  for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
+    for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
+  }
 }
 
-// A sample with W = 0: only its count enters the wave's histograms (S1, S2 and the W^2 sums are unchanged).
-template <int D>
-__device__ __forceinline__ void count_only(const int* hj, uint32_t* my_c) {
-#pragma unroll
-  for (int d = 0; d < D; ++d) atomicAdd(&my_c[hj[d]], 1u);
-}
-
-// End of a screening unit: the wave count histograms summed into the unit's counts.
-__device__ __forceinline__ void finish_counts(const Lds& lay, int DN, unsigned char* smem, uint32_t* out) {
-  const uint32_t* sm_c = reinterpret_cast<const uint32_t*>(smem + lay.off_c);
+// End of a screening unit: the counts of the map slots (word 2 of each 16-byte slot) stored as the unit's counts and
+// cleared for the next unit.
+__device__ __forceinline__ void finish_counts(uint32_t* slot_cnt, int DN, uint32_t* out) {
   __syncthreads();
   for (int i = threadIdx.x; i < DN; i += kBlock) {
-    uint32_t c = 0;
-    for (int w = 0; w < kWaves; ++w) c += sm_c[w * DN + i];
-    out[i] = c;
+    out[i] = slot_cnt[4 * i];
+    slot_cnt[4 * i] = 0u;
   }
   __syncthreads();
 }
 
 // Fixed-order end of a block's pass: butterfly wave sums of S1, S2, the four waves in order into s_out[0..1],
-// and the wave histograms summed in wave order into rec[0 .. 2 DN) (sums of W^2, then counts).
+// and the wave histograms summed in wave order into rec[0 .. DN) (sums of W^2) and, with COUNTS, rec[DN .. 2 DN)
+// (counts).
+template <bool COUNTS>
 __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& lay, int DN, unsigned char* smem,
                                              double* s_out, double* rec) {
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -780,17 +775,18 @@ __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& la
     uint32_t c = 0;
     for (int w = 0; w < kWaves; ++w) {
       h += sm_h[w * DN + i];
-      c += sm_c[w * DN + i];
+      if constexpr (COUNTS) c += sm_c[w * DN + i];
     }
     rec[i] = h;
-    rec[DN + i] = (double)c;
+    if constexpr (COUNTS) rec[DN + i] = (double)c;
   }
   __syncthreads();
 }
 
 // FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
-// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Far samples (W = 0) only add
-// their counts; the offsets n - n0 of in-shell samples are appended, in sample order, to the front of the wave's
+// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Every sample adds to the counts
+// of its bins (the unit's counts); far samples (W = 0) do nothing else; the offsets n - n0 of in-shell samples are
+// appended, in sample order, to the front of the wave's
 // list of the task position (list_stride / 4 entries per wave), those of near samples to its back, for the
 // in-shell pass; the wave's two counts are stored.
 template <int NI>
@@ -801,15 +797,13 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   ItemConsts<NI, float> K;
   const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
+  // bin counts of the current unit, in the map slots (all four waves add into them; zero when a unit starts: staged
+  // as zero, and cleared by the previous unit's finish)
+  uint32_t* slot_cnt = reinterpret_cast<uint32_t*>(smem + lay.off_m32) + 2;
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t wlen = L.list_stride / kWaves;
   for (int t = t0; t < t1; ++t) {
     const int unit = L.tasks[L.task_begin + t].unit;
-    if (t > t0) {
-      clear_counts(lay, smem);
-      __syncthreads();
-    }
     const int64_t n0 = (int64_t)unit * it->unit_size;
     const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
     uint16_t* lst = L.shell_list + (int64_t)t * L.list_stride + (int64_t)wave * wlen;
@@ -820,8 +814,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
       if (n < n1) {
         int hj[D];
         double W;
-        cls = screen_sample<NI, false>(K, (uint64_t)n, hj, &W);
-        if (cls == kFar) count_only<D>(hj, my_c);
+        cls = screen_sample<NI, false, false, true>(K, (uint64_t)n, hj, &W);
       }
       const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
       if (cls == kInShell) lst[cin + (uint32_t)__popcll(b_in & below)] = (uint16_t)(n - n0);
@@ -833,7 +826,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
       L.shell_cnt[(int64_t)t * 2 * kWaves + wave] = cin;
       L.shell_cnt[(int64_t)t * 2 * kWaves + kWaves + wave] = cnear;
     }
-    finish_counts(lay, DN, smem, L.counts + it->part_off + (int64_t)unit * DN);
+    finish_counts(slot_cnt, DN, L.counts + it->part_off + (int64_t)unit * DN);
   }
 }
 
@@ -852,7 +845,6 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
   const Lds lay = setup_block<NI, PREC>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
-  uint32_t* my_c = reinterpret_cast<uint32_t*>(smem + lay.off_c) + wave * DN;
   int* pre = reinterpret_cast<int*>(smem + lay.off_q);  // kLists + 1 prefix sums
   int* wtot = pre + kLists + 1;                          // per-wave totals of the scan
   const int lane = tid & 63;
@@ -906,13 +898,13 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
             if (kind == 0) W = eval_sample<NI, float, ALT>(K, n, hj);
             else screen_sample<NI, true, ALT>(K, n, hj, &W);
           }
-          accumulate<D>(W, hj, S1, S2, my_h, my_c);
+          accumulate<D, false>(W, hj, S1, S2, my_h, nullptr);  // the screening pass counted every sample
         }
         __syncthreads();  // pre is rewritten by the next chunk
       }
     }
     double* rec = L.shell_rec + sht.rec;
-    finish_block(S1, S2, lay, DN, smem, rec, rec + 2);
+    finish_block<false>(S1, S2, lay, DN, smem, rec, rec + 2);
   }
 }
 
@@ -1397,7 +1389,7 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   const ItemRec& it = items[item];
   if (slot >= it.n_iter || it.vplus) return;  // finished, or a VEGAS+ item (its own reduction)
   const int D = it.D, nb = it.nb, DN = D * nb;
-  const int64_t stride = 2 + 2 * (int64_t)DN;  // second-pass record
+  const int64_t stride = 2 + (int64_t)DN;  // second-pass record: S1, S2, the W^2 sums
   const int su = plain ? it.shell_units_p : it.shell_units;  // units per record of this launch's grouping
   if (threadIdx.x == 0) {
     double S1 = 0.0, S2 = 0.0;
@@ -1415,14 +1407,11 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   if (freeze) return;
   const uint32_t* cnt = counts + it.part_off;
   for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    uint64_t cu = 0;  // the screening pass's counts (exact integers)
+    uint64_t cu = 0;  // the screening pass's counts of every sample (exact integers)
     for (int u = 0; u < it.n_units; ++u) cu += cnt[(int64_t)u * DN + i];
-    double h = 0.0, c = (double)cu;
-    for (int u = 0; u < it.n_units; u += su) {
-      const int64_t r = it.shell_off + (u / su) * stride;
-      h += shell_rec[r + 2 + i];
-      c += shell_rec[r + 2 + DN + i];
-    }
+    double h = 0.0;
+    for (int u = 0; u < it.n_units; u += su) h += shell_rec[it.shell_off + (u / su) * stride + 2 + i];
+    const double c = (double)cu;
     sh[i] = h;
     sc[i] = c;
   }
@@ -1538,7 +1527,7 @@ __device__ void vplus_run(const SampleLaunch& L, const VpTask task, unsigned cha
     L.vp_S2[it->vp_off + h0 + tid] = s2;
   }
   double* rec = L.vp_rec + it->vp_rec + (int64_t)task.b * (2 + 2 * (int64_t)DN);
-  finish_block(t1, t2, lay, DN, smem, rec, rec + 2);
+  finish_block<true>(t1, t2, lay, DN, smem, rec, rec + 2);
 }
 
 template <int MASK, int PREC, bool ALT>
