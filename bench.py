@@ -32,18 +32,18 @@ TRAFFIC_BYTES_PER_PHASE = 84.9e6 + 81.3e6
 def ops_common(n_int: int) -> int:
     """Arithmetic operations every sample needs (each +, -, *, /, fma, sqrt, exp, log, sin, cos, compare/select and
     each 32x32->64 multiply or 3-way xor of Philox counts one): Philox 40 per block (10 rounds x 2 multiplies + 2
-    xors) x ceil(D/4); 7 per dimension (uniform from the word, bin, offset, map edge and width, x, its bin count);
+    xors) x D/4 (the D words of a sample are a quarter block each: consecutive samples share blocks); 7 per dimension (uniform from the word, bin, offset, map edge and width, x, its bin count);
     13 per integrated particle (momentum components, energy); conserved momentum 3 (n_int + 1) + 5; energy sum,
     Gaussian argument and its test (n_int + 2) + 5."""
     D = 3 * n_int
-    return 40 * ((D + 3) // 4) + 7 * D + 13 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 5
+    return 10 * D + 7 * D + 13 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 5
 
 
 def ops_weight(n_int: int) -> int:
     """Further operations of a sample whose W can be nonzero (in or near the energy shell): Jacobian 2 per
     dimension and 2 per integrated particle; f lookups 8 (n_int + 1) + 2; statistical factor 3 (n_int + 2); weight
     2 (n_int + 2) + 4; accumulation of W, W^2 and the W^2 histogram 5 + 2 D.  With ops_common this is the whole
-    estimator for one sample (359 operations at n_int = 3)."""
+    estimator for one sample (329 operations at n_int = 3)."""
     D = 3 * n_int
     return 2 * D + 2 * n_int + 8 * (n_int + 1) + 2 + 3 * (n_int + 2) + 2 * (n_int + 2) + 4 + 5 + 2 * D
 

@@ -24,9 +24,9 @@
  *   * Work item: (process, observed species, pinned side, term, evaluation grid index).  Its identifier is
  *         uid = process << 24 | species << 20 | side << 19 | term << 18 | eval_index
  *     (side 0 = initial state, 1 = final state; term 0 = gain or net, 1 = loss).  Items of a call are
- *     ordered by uid.  Sample n of iteration `it` of an item draws its D uniforms from Philox4x32-10 with
- *     key (lo32(seed), hi32(seed)), counters (lo32(n B + b), hi32(n B + b), uid, 64 epoch + it),
- *     B = ceil(D/4), y = (word + 0.5) 2^-32.
+ *     ordered by uid.  The uniforms of iteration `it` of an item form one stream of 32-bit words: word k is
+ *     output k mod 4 of Philox4x32-10 with key (lo32(seed), hi32(seed)) and counter (lo32(k/4), hi32(k/4),
+ *     uid, 64 epoch + it); sample n takes words D n .. D n + D-1, and y = (word + 0.5) 2^-32.
  */
 #ifndef BOLTZMC_H
 #define BOLTZMC_H

@@ -63,21 +63,19 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
   out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
-/* The D uniforms of sample n of iteration `it` of the item with identifier `uid`:
- *   B = ceil(D/4) blocks per sample; block b uses counter (lo32(n*B+b), hi32(n*B+b), uid, epoch*64+it)
- *   and key (lo32(seed), hi32(seed)); word w of the sample (w = 4b + slot) becomes y_w = (w + 0.5) 2^-32. */
+/* The D uniforms of sample n of iteration `it` of the item with identifier `uid`.  The iteration's words form
+ * one stream: stream word k is output (k mod 4) of the Philox block with counter (lo32(k/4), hi32(k/4), uid,
+ * epoch*64+it) and key (lo32(seed), hi32(seed)).  Sample n takes stream words D*n .. D*n + D-1, and word d of
+ * the sample becomes y_d = (word + 0.5) 2^-32.  Each word is generated on its own, block by block. */
 void orc_sample_uniforms(uint64_t seed, uint32_t uid, uint32_t epoch, int it, int64_t n, int D, double* y) {
-  const int B = (D + 3) / 4;
   uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
-  for (int b = 0; b < B; ++b) {
-    uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
-    uint32_t ctr[4] = {(uint32_t)off, (uint32_t)(off >> 32), uid, epoch * 64u + (uint32_t)it};
+  for (int d = 0; d < D; ++d) {
+    uint64_t k = (uint64_t)n * (uint64_t)D + (uint64_t)d;
+    uint64_t blk = k / 4;
+    uint32_t ctr[4] = {(uint32_t)blk, (uint32_t)(blk >> 32), uid, epoch * 64u + (uint32_t)it};
     uint32_t w[4];
     orc_philox4x32_10(ctr, key, w);
-    for (int s = 0; s < 4; ++s) {
-      int d = 4 * b + s;
-      if (d < D) y[d] = ((double)w[s] + 0.5) * 2.3283064365386962890625e-10; /* 2^-32 */
-    }
+    y[d] = ((double)w[k % 4] + 0.5) * 2.3283064365386962890625e-10; /* 2^-32 */
   }
 }
 

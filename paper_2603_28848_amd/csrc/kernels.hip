@@ -31,10 +31,16 @@ struct Lds {
   int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, total;
 };
 
+// FP32 map of the screening pass in LDS: three arrays of kMapSlots 32-bit entries (bin edge, bin width, the unit's
+// bin count), so that one address serves all three (the other two by the instruction's constant offset) and a
+// wave's random bins spread over all 32 banks.
+constexpr int kMapSlots = kMaxD * kMaxBins;
+
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
-// LDS of one sample block: map edges and widths (D x nb, FP64, and as 16-byte FP32 slots), sin/cos of k pi/16 (33
-// entries), per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction scratch.
+// LDS of one sample block: map edges and widths (D x nb, FP64, and the screening pass's FP32 map), sin/cos of k pi/16
+// (33 entries), per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction
+// scratch.
 __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
   Lds L;
   const int DN = D * nb;
@@ -44,7 +50,7 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   L.off_w = o;
   o = align16(o + DN * 8);
   L.off_m32 = o;
-  o = align16(o + DN * 16);
+  o = align16(o + 3 * kMapSlots * 4);
   L.off_sc = o;
   o = align16(o + 33 * 16);
   L.off_tab = o;
@@ -224,8 +230,8 @@ struct ItemConsts {
   const double* e;    // LDS map edges (D x nb)
   const double* w;    // LDS map widths
   const double2* sc;  // LDS sin/cos of k pi/16
-  float4* m32;        // LDS map slots in FP32 (screening pass): edge, width 2^-32 (angles in revolutions), the
-                      // unit's count of samples in the bin (as bits), padding
+  float* m32;         // LDS FP32 map (screening pass): edges [0, kMapSlots), widths x 2^-32 (angles in
+                      // revolutions) [kMapSlots, 2 kMapSlots), the unit's bin counts (as bits) after them
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
@@ -247,14 +253,50 @@ struct ItemConsts {
   uint32_t uid, c3, seed_lo, seed_hi;
 };
 
-template <int NI>
-__device__ __forceinline__ void philox_words(uint32_t* wd, uint64_t n, uint32_t uid, uint32_t c3, uint32_t k0,
+// The uniforms of an item's iteration form one stream of 32-bit words: word w is output w & 3 of the
+// Philox4x32-10 block with counter (lo32(w >> 2), hi32(w >> 2), uid, c3), and sample n takes words D n .. D n + D-1.
+// A group of G = 4 / gcd(D, 4) consecutive samples, starting at a multiple of G, fills G D / 4 whole blocks.
+template <int D>
+struct WordStream {
+  static constexpr int g = D % 4 == 0 ? 4 : (D % 2 == 0 ? 2 : 1);  // gcd(D, 4): a sample starts at w & 3 = k g
+  static constexpr int G = 4 / g;                                 // samples per group
+  static constexpr int GB = G * D / 4;                            // blocks per group
+  static constexpr int NB = (4 - g + D - 1) / 4 + 1;              // blocks one sample can touch
+};
+
+// The D words of sample n (any n): its blocks, then the words from the sample's offset in the first.
+template <int D>
+__device__ __forceinline__ void sample_words(uint32_t* wd, uint64_t n, uint32_t uid, uint32_t c3, uint32_t k0,
                                              uint32_t k1) {
-  constexpr int B = (3 * NI + 3) / 4;
+  using WS = WordStream<D>;
+  const uint64_t w0 = n * (uint64_t)D;
+  const uint64_t b0 = w0 >> 2;
+  const int off = (int)(w0 & 3u);
+  uint32_t all[4 * WS::NB];
 #pragma unroll
-  for (int b = 0; b < B; ++b) {
-    const uint64_t off = n * (uint64_t)B + (uint64_t)b;
-    Philox4 r = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, k0, k1);
+  for (int b = 0; b < WS::NB; ++b) {
+    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), (uint32_t)((b0 + b) >> 32), uid, c3, k0, k1);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) all[4 * b + s] = r.v[s];
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    uint32_t v = all[i];
+#pragma unroll
+    for (int o = WS::g; o < 4; o += WS::g) v = off == o ? all[i + o] : v;
+    wd[i] = v;
+  }
+}
+
+// The G D words of the group of samples ng .. ng + G-1 (ng a multiple of G).
+template <int D>
+__device__ __forceinline__ void group_words(uint32_t* wd, uint64_t ng, uint32_t uid, uint32_t c3, uint32_t k0,
+                                            uint32_t k1) {
+  using WS = WordStream<D>;
+  const uint64_t b0 = (ng * (uint64_t)D) >> 2;
+#pragma unroll
+  for (int b = 0; b < WS::GB; ++b) {
+    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), (uint32_t)((b0 + b) >> 32), uid, c3, k0, k1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
   }
@@ -286,8 +328,8 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
                                               const int* dig = nullptr, int kst = 1) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
-  uint32_t wd[4 * ((D + 3) / 4)];
-  philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
+  uint32_t wd[D];
+  sample_words<D>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
   const int nb = K.nb;
   const double dnb = (double)nb;
   double J = 1.0, jac = 1.0;
@@ -427,10 +469,8 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 constexpr int kFar = 0, kNear = 1, kInShell = 2;
 
 template <int NI, bool FINISH, bool ALT = false, bool COUNT = false>
-__device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uint64_t n, int* hj, double* Wout) {
-  constexpr int D = 3 * NI;
-  uint32_t wd[4 * ((D + 3) / 4)];
-  philox_words<NI>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
+__device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, const uint32_t* wd, int* hj,
+                                             double* Wout) {
   const uint32_t nb = (uint32_t)K.nb;
   const uint64_t half_nb = nb >> 1;
   // nb as a vector operand, so that the 64-bit multiply-add below can take its uniform addend from scalar registers
@@ -461,11 +501,16 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, uin
       // moves the in-bin offset by 2^-33), the offset comes from the low word; d nb added to the high word makes it
       // the histogram index d nb + j directly
       const uint64_t t = (uint64_t)wd[d] * vnb + (half_nb + ((uint64_t)(d * nb) << 32));
-      const int jd = (int)(t >> 32);
-      const float2 ew = *reinterpret_cast<const float2*>(K.m32 + jd);
-      if constexpr (COUNT) atomicAdd(reinterpret_cast<uint32_t*>(K.m32 + jd) + 2, 1u);  // the bin's count
-      x3[c] = fmaf(ew.y, (float)(uint32_t)t, ew.x);
-      J *= (c == 0 ? fnb32 : fnb32rev) * ew.y;
+      uint32_t jdu = (uint32_t)(t >> 32);
+      asm("" : "+v"(jdu));  // keeps the bin index as the product's high word (one shift-add to the address below)
+      const int jd = (int)jdu;
+      // one LDS address for the bin's edge, width and count (the last two at constant offsets)
+      char* mp = reinterpret_cast<char*>(K.m32) + 4u * jdu;
+      const float e0 = *reinterpret_cast<const float*>(mp);
+      const float ew = *reinterpret_cast<const float*>(mp + 4 * kMapSlots);
+      if constexpr (COUNT) atomicAdd(reinterpret_cast<uint32_t*>(mp + 8 * kMapSlots), 1u);  // the bin's count
+      x3[c] = fmaf(ew, (float)(uint32_t)t, e0);
+      J *= (c == 0 ? fnb32 : fnb32rev) * ew;
       hj[d] = jd;
     }
     const float r = x3[0];
@@ -589,7 +634,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   const Lds lay = lds_layout(D, nb, n_tab, n_max, sizeof(FT));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
-  float4* sm_m32 = reinterpret_cast<float4*>(smem + lay.off_m32);
+  float* sm_m32 = reinterpret_cast<float*>(smem + lay.off_m32);
   double2* sm_sc = reinterpret_cast<double2*>(smem + lay.off_sc);
 
   const double* __restrict__ map = L.maps + it->map_off;
@@ -598,10 +643,12 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
     sm_e[i] = e0;
     sm_w[i] = e1 - e0;
-    // screening slots: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions
-    // (the hardware sine takes them), so a coordinate is one fma of the low word; the bin's count starts at 0
+    // screening map: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions (the
+    // hardware sine takes them), so a coordinate is one fma of the low word; the bin's count starts at 0
     const double sc = (d % 3 == 0) ? 1.0 : 0.15915494309189535;
-    sm_m32[i] = make_float4((float)(e0 * sc), (float)((e1 - e0) * sc * 2.3283064365386962890625e-10), 0.0f, 0.0f);
+    sm_m32[i] = (float)(e0 * sc);
+    sm_m32[kMapSlots + i] = (float)((e1 - e0) * sc * 2.3283064365386962890625e-10);
+    reinterpret_cast<uint32_t*>(sm_m32)[2 * kMapSlots + i] = 0u;
   }
   if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; stage && k < n_tab; ++k) {
@@ -733,13 +780,12 @@ __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, 
   }
 }
 
-// End of a screening unit: the counts of the map slots (word 2 of each 16-byte slot) stored as the unit's counts and
-// cleared for the next unit.
-__device__ __forceinline__ void finish_counts(uint32_t* slot_cnt, int DN, uint32_t* out) {
+// End of a screening unit: the bin counts of the FP32 map stored as the unit's counts and cleared for the next unit.
+__device__ __forceinline__ void finish_counts(uint32_t* cnt, int DN, uint32_t* out) {
   __syncthreads();
   for (int i = threadIdx.x; i < DN; i += kBlock) {
-    out[i] = slot_cnt[4 * i];
-    slot_cnt[4 * i] = 0u;
+    out[i] = cnt[i];
+    cnt[i] = 0u;
   }
   __syncthreads();
 }
@@ -784,11 +830,12 @@ __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& la
 }
 
 // FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
-// Wave w takes rounds of 64 samples (round k: samples n0 + 256 k + 64 w + lane).  Every sample adds to the counts
-// of its bins (the unit's counts); far samples (W = 0) do nothing else; the offsets n - n0 of in-shell samples are
-// appended, in sample order, to the front of the wave's
-// list of the task position (list_stride / 4 entries per wave), those of near samples to its back, for the
-// in-shell pass; the wave's two counts are stored.
+// A lane screens the G consecutive samples of one word group (G = 4 / gcd(D, 4): their uniforms fill whole Philox
+// blocks); wave w takes rounds of 64 G samples (round k: samples n0 + 256 G k + 64 G w + G lane + s, s < G), so
+// each wave screens a quarter of a unit.  Every sample adds to the counts of its bins (the unit's counts); far
+// samples (W = 0) do nothing else; the offsets n - n0 of in-shell samples are appended, in screening order (round,
+// s, lane), to the front of the wave's list of the task position (list_stride / 4 entries per wave), those of near
+// samples to its back, for the second pass; the wave's two counts are stored.
 template <int NI>
 __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
@@ -797,9 +844,9 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   ItemConsts<NI, float> K;
   const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  // bin counts of the current unit, in the map slots (all four waves add into them; zero when a unit starts: staged
+  // bin counts of the current unit, in the FP32 map (all four waves add into them; zero when a unit starts: staged
   // as zero, and cleared by the previous unit's finish)
-  uint32_t* slot_cnt = reinterpret_cast<uint32_t*>(smem + lay.off_m32) + 2;
+  uint32_t* slot_cnt = reinterpret_cast<uint32_t*>(smem + lay.off_m32) + 2 * kMapSlots;
   const uint64_t below = (1ull << lane) - 1ull;
   const int64_t wlen = L.list_stride / kWaves;
   for (int t = t0; t < t1; ++t) {
@@ -808,19 +855,26 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
     const int64_t n1 = min(n0 + (int64_t)it->unit_size, it->N);
     uint16_t* lst = L.shell_list + (int64_t)t * L.list_stride + (int64_t)wave * wlen;
     uint32_t cin = 0, cnear = 0;  // wave-uniform
-    for (int64_t rbase = n0 + 64 * wave; rbase < n1; rbase += kBlock) {
-      const int64_t n = rbase + lane;
-      int cls = kFar;
-      if (n < n1) {
-        int hj[D];
-        double W;
-        cls = screen_sample<NI, false, false, true>(K, (uint64_t)n, hj, &W);
+    constexpr int G = WordStream<D>::G;
+    for (int64_t rbase = n0 + 64 * G * wave; rbase < n1; rbase += (int64_t)kBlock * G) {
+      const int64_t ng = rbase + (int64_t)G * lane;  // the lane's group
+      uint32_t wg[G * D];
+      if (ng < n1) group_words<D>(wg, (uint64_t)ng, K.uid, K.c3, K.seed_lo, K.seed_hi);
+#pragma unroll
+      for (int s = 0; s < G; ++s) {
+        const int64_t n = ng + s;
+        int cls = kFar;
+        if (n < n1) {
+          int hj[D];
+          double W;
+          cls = screen_sample<NI, false, false, true>(K, wg + s * D, hj, &W);
+        }
+        const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
+        if (cls == kInShell) lst[cin + (uint32_t)__popcll(b_in & below)] = (uint16_t)(n - n0);
+        if (cls == kNear) lst[wlen - 1 - (cnear + (uint32_t)__popcll(b_near & below))] = (uint16_t)(n - n0);
+        cin += (uint32_t)__popcll(b_in);
+        cnear += (uint32_t)__popcll(b_near);
       }
-      const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
-      if (cls == kInShell) lst[cin + (uint32_t)__popcll(b_in & below)] = (uint16_t)(n - n0);
-      if (cls == kNear) lst[wlen - 1 - (cnear + (uint32_t)__popcll(b_near & below))] = (uint16_t)(n - n0);
-      cin += (uint32_t)__popcll(b_in);
-      cnear += (uint32_t)__popcll(b_near);
     }
     if (lane == 0) {
       L.shell_cnt[(int64_t)t * 2 * kWaves + wave] = cin;
@@ -896,7 +950,11 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
             W = eval_sample<NI, double, ALT>(K, n, hj);
           } else {
             if (kind == 0) W = eval_sample<NI, float, ALT>(K, n, hj);
-            else screen_sample<NI, true, ALT>(K, n, hj, &W);
+            else {
+              uint32_t wd[D];
+              sample_words<D>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
+              screen_sample<NI, true, ALT>(K, wd, hj, &W);
+            }
           }
           accumulate<D, false>(W, hj, S1, S2, my_h, nullptr);  // the screening pass counted every sample
         }
@@ -921,7 +979,6 @@ template <int NI>
 __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
-  constexpr int B = (D + 3) / 4;
   constexpr int NR = NI + 2;
   const ItemRec* __restrict__ it = &L.items[task.item];
   const int tid = threadIdx.x;
@@ -1032,14 +1089,8 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     const int w = l % kWaves;
     const uint32_t off = l < kWaves ? lst[w * wlen + k] : lst[w * wlen + wlen - 1 - k];
     const int64_t n = n0 + off;
-    uint32_t wd[4 * B];
-#pragma unroll
-    for (int b = 0; b < B; ++b) {
-      const uint64_t off = (uint64_t)n * (uint64_t)B + (uint64_t)b;
-      Philox4 rr = philox4x32_10((uint32_t)off, (uint32_t)(off >> 32), uid, c3, L.seed_lo, L.seed_hi);
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) wd[4 * b + s2] = rr.v[s2];
-    }
+    uint32_t wd[D];
+    sample_words<D>(wd, (uint64_t)n, uid, c3, L.seed_lo, L.seed_hi);
     double J = 1.0, jac = 1.0, sx = 0.0, sy = 0.0, sz = esg[NI + 1] * p_obs;
     double E[NR], f[NR], wt[NR];
     int jn[NR], src[NR];  // src: 0 table node, 1 interpolated, 2 extrapolated low, 3 extrapolated high

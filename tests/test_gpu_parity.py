@@ -280,6 +280,8 @@ def test_points_off_the_grid(precision, which):
     rc, r = ow.run_items(items, n, N, nitn, seed=3, adapt=False)
     assert rc == 0
     tol = TOL[precision]
+    if which == "2to3" and precision == 0:
+        tol = 1e-10  # few in-shell samples per item at 2^13 on the uniform map (the few-sample tolerance)
     assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
     Co, So = ow.combine_at(items, n, r["Ibar"], r["sigma"], len(q))
     scale = point_scale(items, n, r["Ibar"], 0, len(q))

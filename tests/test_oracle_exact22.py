@@ -160,6 +160,32 @@ def test_exact22_agrees_with_monte_carlo_at_narrow_width():
         assert abs(r["Ibar"][k] - I[k]) <= 4 * r["sigma"][k] + 5e-3 * I[k], (k, r["Ibar"][k], I[k], r["sigma"][k])
 
 
+def test_exact22_h_theorem_and_conservation():
+    """Noise-free H theorem: for the non-thermal initial condition of Sec. V.A on a grid wide enough that
+    collisions do not carry energy past its end, the exact-delta 2->2 operator's entropy production
+    sum_j w_j C_j ln((1 + f_j) / f_j) is positive (14 % of its absolute scale), while its number and energy moments
+    vanish to the quadrature error (trapezoid weights q^2 dq)."""
+    n, q_min, q_max = 96, 0.02, 40.0
+    q = wl.log_nodes(q_min, q_max, n)
+    f0 = wl.f_fermi_step(q)
+    w = wl.Workload("h", [wl.Species("phi", wl.BOSE, n, q_min, q_max, f0, m0=1.0)],
+                    [wl.Process([0, 0], [0, 0], term_mode=wl.TERMS_NET)])
+    ow = ob.OracleWorld(w)
+    items, ni = ow.items()
+    rc, I = ow.exact22(items, ni)
+    assert rc == 0
+    C, _ = ow.combine(items, ni, I, np.zeros(ni), 0)
+    E = np.sqrt(q * q + 1.0)
+    dq = np.zeros_like(q)
+    dq[1:] += 0.5 * np.diff(q)
+    dq[:-1] += 0.5 * np.diff(q)
+    wq = q * q * dq
+    rel = lambda v: (wq @ v) / (wq @ np.abs(v))
+    assert rel(C * np.log1p(1.0 / f0)) > 0.1
+    assert abs(rel(C)) < 1e-6
+    assert abs(rel(E * C)) < 2e-2
+
+
 def test_exact22_rejects_other_processes():
     w = wl.w23_be(n_grid=16, N=256, nitn=1)
     ow = ob.OracleWorld(w)

@@ -1,6 +1,7 @@
 """Pins of the oracle's counter-based generator (Philox4x32-10, Salmon et al. SC11 2011) and of the
 sample-to-counter layout: the published known-answer vectors, and PyTorch's independently written
 header-only engine."""
+import math
 import os
 import shutil
 import subprocess
@@ -50,8 +51,8 @@ def torch_engine():
 
 
 def test_sample_words_match_torch_engine(torch_engine):
-    """Word 4b+s of sample n of iteration it equals output s of the engine with subsequence
-    uid | (epoch*64+it) << 32 and offset n*B + b (B = ceil(D/4))."""
+    """Word d of sample n of iteration it is stream word k = D*n + d: output k % 4 of the engine with subsequence
+    uid | (epoch*64+it) << 32 and offset k // 4."""
     rng = np.random.default_rng(1)
     cases = []
     for _ in range(64):
@@ -64,22 +65,37 @@ def test_sample_words_match_torch_engine(torch_engine):
         cases.append((seed, uid, epoch, it, n, D))
     lines = []
     for seed, uid, epoch, it, n, D in cases:
-        B = (D + 3) // 4
-        for b in range(B):
-            sub = uid | (((epoch * 64 + it) & 0xFFFFFFFF) << 32)
-            lines.append("%d %d %d" % (seed, sub, n * B + b))
+        sub = uid | (((epoch * 64 + it) & 0xFFFFFFFF) << 32)
+        for d in range(D):
+            lines.append("%d %d %d" % (seed, sub, (D * n + d) // 4))
     out = subprocess.run([torch_engine], input="\n".join(lines) + "\n", capture_output=True, text=True,
                          check=True).stdout.split("\n")
     k = 0
     for seed, uid, epoch, it, n, D in cases:
-        B = (D + 3) // 4
         words = []
-        for b in range(B):
-            words += [int(x) for x in out[k].split()]
+        for d in range(D):
+            words.append(int(out[k].split()[(D * n + d) % 4]))
             k += 1
         y = ob.uniforms(seed, uid, epoch, it, n, D)
         w_from_y = y * 2.0**32 - 0.5
-        assert np.array_equal(w_from_y, np.array(words[:D], dtype=np.float64))
+        assert np.array_equal(w_from_y, np.array(words, dtype=np.float64))
+
+
+def test_word_groups_fill_whole_blocks():
+    """G = 4/gcd(D,4) consecutive samples from a multiple of G take the words of G*D/4 whole Philox blocks in order
+    (blocks D*n0/4 ...), and the next sample starts the next block: no stream word is skipped or reused."""
+    seed, uid, epoch, it = 5, 77, 1, 2
+    key = (seed & 0xFFFFFFFF, seed >> 32)
+    for D in (3, 6, 9, 12):
+        G = 4 // math.gcd(D, 4)
+        n0 = 1000 * G
+        got = np.concatenate([ob.uniforms(seed, uid, epoch, it, n0 + s, D) for s in range(2 * G)])
+        b0 = n0 * D // 4
+        words = []
+        for b in range(b0, b0 + 2 * G * D // 4):
+            words += list(ob.philox((b & 0xFFFFFFFF, b >> 32, uid, epoch * 64 + it), key))
+        want = (np.array(words, dtype=np.float64) + 0.5) * 2.0**-32
+        assert np.array_equal(got, want), D
 
 
 def test_uniforms_open_interval():

@@ -135,10 +135,10 @@ def test_p1_nonequilibrium_is_not_stationary():
                     [wl.Process([0, 0], [0, 0, 0], sigma_E=0.01, term_mode=wl.TERMS_NET)])
     ow = ob.OracleWorld(w)
     items, n = _subset(ow, lambda it: it.eval_idx in (20, 55))
-    rc, r = ow.run_items(items, n, 1 << 14, 4)
+    rc, r = ow.run_items(items, n, 1 << 16, 4)
     for i in range(n):
         sgn = 1.0 if items[i].side == 0 else -1.0
-        assert sgn * r["Ibar"][i] > 3 * r["sigma"][i]
+        assert sgn * r["Ibar"][i] > 3 * r["sigma"][i], (items[i].side, items[i].eval_idx, r["Ibar"][i], r["sigma"][i])
 
 
 # ------------------------------------------------------------------------------------------------ P5/P6
