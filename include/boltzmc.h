@@ -113,7 +113,7 @@ typedef struct {
   int term_mode;       /* BMC_TERMS_SPLIT or BMC_TERMS_NET */
   int side_mask;       /* BMC_SIDES_* */
   int eval_stride;     /* evaluate every k-th grid point of the observed species (>= 1) */
-  int64_t n_samples;   /* samples per item per iteration (>= 2) */
+  int64_t n_samples;   /* samples per item per iteration (>= 2, and D n_samples < 2^34) */
   int n_iter;          /* Vegas iterations per evaluation (1 .. BMC_MAXITER) */
   int width_mode;      /* BMC_WIDTH_ABS (default) or BMC_WIDTH_REL */
   /* Width controller (Appendix C), with width_adapt = 1: after every evaluation the width is divided by

@@ -449,6 +449,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     const int64_t N = k.n_samples > 0 ? k.n_samples : Pr.prm.n_samples;
     const int nit = k.n_iter > 0 ? k.n_iter : Pr.prm.n_iter;
     if (N < 2) return fail(c, BMC_EINVAL, "n_samples < 2");
+    // the word stream's block index D N / 4 stays below 2^32 (the device passes 0 as the counter's high word)
+    if ((uint64_t)N * (uint64_t)D >= (1ull << 34)) return fail(c, BMC_EINVAL, "n_samples * D >= 2^34");
     if (nit < 1 || nit > kMaxIter) return fail(c, BMC_EINVAL, "n_iter out of range");
     for (int a = 0; a < ns; ++a) {
       if (k.species >= 0 && a != k.species) continue;
@@ -1234,6 +1236,8 @@ int bmc_add_process(bmc_ctx* c, const int* in_sp, int n_in, const int* out_sp, i
       (q.term_mode != BMC_TERMS_SPLIT && q.term_mode != BMC_TERMS_NET) || q.side_mask < 0 || q.side_mask > 3 ||
       q.eval_stride < 1 || q.n_samples < 2 || q.n_iter < 1 || q.n_iter > kMaxIter || !std::isfinite(q.coupling))
     return fail(c, BMC_EINVAL, "bad process parameters");
+  if ((uint64_t)q.n_samples * (uint64_t)(3 * (n_in + n_out - 2)) >= (1ull << 34))
+    return fail(c, BMC_EINVAL, "n_samples * D >= 2^34");
   if (q.width_mode != BMC_WIDTH_ABS && q.width_mode != BMC_WIDTH_REL)
     return fail(c, BMC_EINVAL, "bad width_mode");
   // a relative width stays <= 1: the screening pass's energy margins assume it

@@ -255,7 +255,9 @@ struct ItemConsts {
 
 // The uniforms of an item's iteration form one stream of 32-bit words: word w is output w & 3 of the
 // Philox4x32-10 block with counter (lo32(w >> 2), hi32(w >> 2), uid, c3), and sample n takes words D n .. D n + D-1.
-// A group of G = 4 / gcd(D, 4) consecutive samples, starting at a multiple of G, fills G D / 4 whole blocks.
+// A group of G = 4 / gcd(D, 4) consecutive samples, starting at a multiple of G, fills G D / 4 whole blocks.  The
+// host keeps D N below 2^34, so the block index fits 32 bits and the counter's second word is 0 (which also makes
+// the first round's second product, and the second round's first, the same for every lane).
 template <int D>
 struct WordStream {
   static constexpr int g = D % 4 == 0 ? 4 : (D % 2 == 0 ? 2 : 1);  // gcd(D, 4): a sample starts at w & 3 = k g
@@ -275,7 +277,7 @@ __device__ __forceinline__ void sample_words(uint32_t* wd, uint64_t n, uint32_t 
   uint32_t all[4 * WS::NB];
 #pragma unroll
   for (int b = 0; b < WS::NB; ++b) {
-    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), (uint32_t)((b0 + b) >> 32), uid, c3, k0, k1);
+    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), 0u, uid, c3, k0, k1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) all[4 * b + s] = r.v[s];
   }
@@ -296,7 +298,7 @@ __device__ __forceinline__ void group_words(uint32_t* wd, uint64_t ng, uint32_t 
   const uint64_t b0 = (ng * (uint64_t)D) >> 2;
 #pragma unroll
   for (int b = 0; b < WS::GB; ++b) {
-    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), (uint32_t)((b0 + b) >> 32), uid, c3, k0, k1);
+    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), 0u, uid, c3, k0, k1);
 #pragma unroll
     for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
   }

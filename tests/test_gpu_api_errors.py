@@ -23,6 +23,7 @@ def _bm():
     dict(width_adapt=1, width_lo=0.0), dict(width_adapt=1, width_lo=0.02, width_hi=0.01),
     dict(width_adapt=1, width_factor=1.0), dict(width_adapt=1, width_min=0.0),
     dict(width_adapt=1, width_min=0.3, width_max=0.2), dict(m2_kind=3), dict(vegas_plus=2), dict(beta=2.5),
+    dict(n_samples=1 << 32),  # D n_samples >= 2^34: the word stream's block index would pass 32 bits
 ])
 def test_bad_process_parameters_are_rejected(bad):
     bm = _bm()
@@ -49,3 +50,12 @@ def test_bad_width_and_interp_calls_are_rejected():
             ctx.set_interp(0, mode)
     with pytest.raises(bm.BmcError):
         ctx.set_interp(5, wl.INTERP_SPLINE)
+
+
+def test_sample_count_beyond_the_word_stream_is_rejected():
+    """A call whose samples per item would take the word stream's block index past 32 bits (D N >= 2^34) fails with
+    an error before anything runs."""
+    bm = _bm()
+    ctx = bm.from_workload(wl.w22_mb())
+    with pytest.raises(bm.BmcError):
+        ctx.collision(-1, -1, bm.default_opts(n_samples=1 << 32, n_iter=1))
