@@ -963,7 +963,9 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.vp_rec = P.d_vrec;
   const int n_vpi = (int)P.vp_items.size();
   if (n_vpi) HIPCHK(c, launch_vplus_init(P.d_items, P.d_vpi, n_vpi, P.d_nh, P.d_hoff, s));
-  const int max_grid = grid_for(c, o.precision, (int)L.lds_bytes, P.nint_mask);
+  // persistent grid of the screening pass (its blocks hold the FP32 map only); the second pass's task grid is capped
+  // by the same count
+  const int max_grid = grid_for(c, o.precision, screen_lds_bytes(), P.nint_mask);
   for (int k = 0; k < P.n_iter_max; ++k) {
     L.it = o.first_iter + k;
     if (o.launch == BMC_LAUNCH_PLAIN) {
@@ -1984,7 +1986,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   for (const Plan::Slice& sl : P.slices) {
     S.task_begin = L.task_begin = sl.tb;
     S.n_tasks = L.n_tasks = sl.te - sl.tb;
-    S.grid = std::min((S.n_tasks + S.chunk - 1) / S.chunk, grid_for(c, BMC_FP32I, P.lds32, P.nint_mask));
+    S.grid = std::min((S.n_tasks + S.chunk - 1) / S.chunk, grid_for(c, BMC_FP32I, screen_lds_bytes(), P.nint_mask));
     L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
     HIPCHK(c, launch_sample(S, s));
     HIPCHK(c, launch_vjp(L, s));
@@ -2065,8 +2067,7 @@ int bmc_autotune(bmc_ctx* c, int process, int species, const bmc_run_opts* o, in
   Plan& P = c->plan;
   const int saved_b = c->blocks_per_cu, saved_c = c->chunk;
   const bool saved_timing = c->timing;
-  const int lds = q.precision == BMC_FP64 ? P.lds64 : P.lds32;
-  const int max_b = std::max(1, std::min(8, (160 * 1024) / std::max(1, lds)));
+  const int max_b = std::max(1, std::min(8, (160 * 1024) / std::max(1, screen_lds_bytes())));
   double best = 1e300;
   int bb = saved_b, bc = saved_c;
   hipEvent_t e0, e1;

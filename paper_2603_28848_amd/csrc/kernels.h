@@ -113,6 +113,8 @@ hipError_t launch_prepare(DevState* st, const SpecDev* spec, int n_species, cons
                           int64_t n_f, hipStream_t s);
 
 int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
+// LDS bytes of a screening block (the FP32 map only).
+int screen_lds_bytes();
 
 // Adjoint (FP64, frozen maps): per-unit records of the sample derivatives, then per item (times coef/N),
 // then per species node, fits, masses and couplings.

@@ -38,6 +38,14 @@ constexpr int kMapSlots = kMaxD * kMaxBins;
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 
+// LDS of a screening block: the FP32 map only (nothing else of the sample layout is read without the finish).
+__host__ __device__ inline Lds screen_layout() {
+  Lds L{};
+  L.off_m32 = 0;
+  L.total = align16(3 * kMapSlots * 4);
+  return L;
+}
+
 // LDS of one sample block: map edges and widths (D x nb, FP64, and the screening pass's FP32 map), sin/cos of k pi/16
 // (33 entries), per f table q_j, 1/q_j and f_j, per-wave training histograms (sum of W^2, counts), reduction
 // scratch.
@@ -290,17 +298,20 @@ __device__ __forceinline__ void sample_words(uint32_t* wd, uint64_t n, uint32_t 
   }
 }
 
-// The G D words of the group of samples ng .. ng + G-1 (ng a multiple of G).
+// Of the G D words of the group of samples ng .. ng + G-1 (ng a multiple of G), the blocks whose first word belongs
+// to sample s of the group (block b starts in sample 4 b / D): called for s = 0 .. G-1 in turn, just before sample
+// s is used, it fills every word of the group once, with few of them live at a time.
 template <int D>
-__device__ __forceinline__ void group_words(uint32_t* wd, uint64_t ng, uint32_t uid, uint32_t c3, uint32_t k0,
-                                            uint32_t k1) {
+__device__ __forceinline__ void group_blocks_for(uint32_t* wd, int s, uint64_t ng, uint32_t uid, uint32_t c3,
+                                                 uint32_t k0, uint32_t k1) {
   using WS = WordStream<D>;
-  const uint64_t b0 = (ng * (uint64_t)D) >> 2;
+  const uint32_t b0 = (uint32_t)((ng * (uint64_t)D) >> 2);
 #pragma unroll
   for (int b = 0; b < WS::GB; ++b) {
-    const Philox4 r = philox4x32_10((uint32_t)(b0 + b), 0u, uid, c3, k0, k1);
+    if ((4 * b) / D != s) continue;
+    const Philox4 r = philox4x32_10(b0 + (uint32_t)b, 0u, uid, c3, k0, k1);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) wd[4 * b + s] = r.v[s];
+    for (int q = 0; q < 4; ++q) wd[4 * b + q] = r.v[q];
   }
 }
 
@@ -537,20 +548,22 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, con
         add4(Pt, (float)K.ct[k], E, ps * cph, ps * sph, p * cth);
       }
     }
-    const FTab<float>& T = K.tr[k];
-    float f;
-    if (!ALT || T.mode == 0) {
-      const float tp = fmaf(__builtin_amdgcn_logf(r), K.lg1[k], -K.lg0[k]);
-      int jj = (int)tp;
-      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
-      const float wgt = tp - (float)jj;
-      f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
-    } else {
-      f = interp32<ALT>(T, (double)r, (double)E);
+    if constexpr (FINISH) {  // the f tables are in LDS only for the finish (the screening layout has the map alone)
+      const FTab<float>& T = K.tr[k];
+      float f;
+      if (!ALT || T.mode == 0) {
+        const float tp = fmaf(__builtin_amdgcn_logf(r), K.lg1[k], -K.lg0[k]);
+        int jj = (int)tp;
+        jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+        const float wgt = tp - (float)jj;
+        f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
+      } else {
+        f = interp32<ALT>(T, (double)r, (double)E);
+      }
+      const float bf = fmaf((float)K.eta[k], f, 1.0f);
+      gain *= K.obsside[k] ? bf : f;
+      loss *= K.obsside[k] ? f : bf;
     }
-    const float bf = fmaf((float)K.eta[k], f, 1.0f);
-    gain *= K.obsside[k] ? bf : f;
-    loss *= K.obsside[k] ? f : bf;
   }
   const float P2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
   const float Ec = __builtin_amdgcn_sqrtf(P2 + (float)K.m2[NI]);
@@ -617,10 +630,11 @@ __device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) 
   for (int i = threadIdx.x; i < n16; i += kBlock) p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 pairs), the sin/cos table and
-// the f tables into LDS unless the block's previous task staged the same item, clears the per-wave training
-// histograms, and fills the per-item constants at the current time.  Ends with a block barrier.
-template <int NI, int PREC>
+// Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 map), the sin/cos table and the f
+// tables into LDS unless the block's previous task staged the same item, clears the per-wave training histograms,
+// and fills the per-item constants at the current time.  SCREEN: the screening pass's layout, the FP32 map only.
+// Ends with a block barrier.
+template <int NI, int PREC, bool SCREEN = false>
 __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec* __restrict__ it,
                                            unsigned char* smem, bool stage,
                                            ItemConsts<NI, typename std::conditional<PREC == 0, double, float>::type>& K) {
@@ -633,7 +647,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   const int n_tab = it->n_tab;
   int n_max = 0;
   for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
-  const Lds lay = lds_layout(D, nb, n_tab, n_max, sizeof(FT));
+  const Lds lay = SCREEN ? screen_layout() : lds_layout(D, nb, n_tab, n_max, sizeof(FT));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
   float* sm_m32 = reinterpret_cast<float*>(smem + lay.off_m32);
@@ -643,8 +657,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   for (int i = tid; stage && i < DN; i += kBlock) {
     const int d = i / nb, j = i - d * nb;
     const double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
-    sm_e[i] = e0;
-    sm_w[i] = e1 - e0;
+    if constexpr (!SCREEN) {
+      sm_e[i] = e0;
+      sm_w[i] = e1 - e0;
+    }
     // screening map: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions (the
     // hardware sine takes them), so a coordinate is one fma of the low word; the bin's count starts at 0
     const double sc = (d % 3 == 0) ? 1.0 : 0.15915494309189535;
@@ -652,8 +668,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     sm_m32[kMapSlots + i] = (float)((e1 - e0) * sc * 2.3283064365386962890625e-10);
     reinterpret_cast<uint32_t*>(sm_m32)[2 * kMapSlots + i] = 0u;
   }
-  if (stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
-  for (int k = 0; stage && k < n_tab; ++k) {
+  if (!SCREEN && stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
+  for (int k = 0; !SCREEN && stage && k < n_tab; ++k) {
     const SpecDev& S = L.spec[it->tab_species[k]];
     unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
     double* q = reinterpret_cast<double*>(base);
@@ -667,7 +683,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       else f[j] = L.f32[S.f_off + j];
     }
   }
-  clear_hist(lay, smem);
+  if constexpr (!SCREEN) clear_hist(lay, smem);
 
   K.e = sm_e;
   K.w = sm_w;
@@ -844,7 +860,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   const int item = L.tasks[L.task_begin + t0].item;
   const ItemRec* __restrict__ it = &L.items[item];
   ItemConsts<NI, float> K;
-  const Lds lay = setup_block<NI, 1>(L, it, smem, stage, K);
+  const Lds lay = setup_block<NI, 1, true>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // bin counts of the current unit, in the FP32 map (all four waves add into them; zero when a unit starts: staged
   // as zero, and cleared by the previous unit's finish)
@@ -861,9 +877,9 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
     for (int64_t rbase = n0 + 64 * G * wave; rbase < n1; rbase += (int64_t)kBlock * G) {
       const int64_t ng = rbase + (int64_t)G * lane;  // the lane's group
       uint32_t wg[G * D];
-      if (ng < n1) group_words<D>(wg, (uint64_t)ng, K.uid, K.c3, K.seed_lo, K.seed_hi);
 #pragma unroll
       for (int s = 0; s < G; ++s) {
+        group_blocks_for<D>(wg, s, (uint64_t)ng, K.uid, K.c3, K.seed_lo, K.seed_hi);
         const int64_t n = ng + s;
         int cls = kFar;
         if (n < n1) {
@@ -1353,7 +1369,7 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
 // (screening) or two (second pass) waves share a SIMD: above 256 the compiler moves values into accumulation
 // registers and occupancy halves.
 template <int MASK>
-__global__ __launch_bounds__(kBlock, 3) void k_screen(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int chunk = L.chunk > 0 ? L.chunk : 1;
   int prev_item = -1;
@@ -2112,7 +2128,7 @@ __global__ void k_copy(double* dst, const double* src, int64_t n) {
 
 template <int MASK>
 hipError_t launch_sample_t(const SampleLaunch& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_screen<MASK>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+  hipLaunchKernelGGL((k_screen<MASK>), dim3(L.grid), dim3(kBlock), screen_layout().total, s, L);
   return hipGetLastError();
 }
 
@@ -2148,6 +2164,8 @@ hipError_t launch_vplus_t(const SampleLaunch& L, hipStream_t s) {
 int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
   return lds_layout(D, nb, n_tab, n_max, precision == 0 ? 8 : 4).total;
 }
+
+int screen_lds_bytes() { return screen_layout().total; }
 
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {
   if (L.n_tasks <= 0) return hipSuccess;
