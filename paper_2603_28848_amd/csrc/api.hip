@@ -1035,11 +1035,15 @@ PlanKey plan_key(int process, int species, const bmc_run_opts* o) {
   return k;
 }
 
+// The context's plan in `slot` is built for key k and uploaded (the calls that change the model reset it).
+bool plan_matches(const Plan& slot, const PlanKey& k) {
+  return slot.process == k.process && slot.species == k.species && slot.stride == k.stride &&
+         slot.n_samples == k.n_samples && slot.n_iter == k.n_iter && slot.eval_q == k.eval_q && slot.uploaded;
+}
+
 int get_plan(bmc_ctx* c, Plan& slot, int process, int species, const bmc_run_opts* o) {
   const PlanKey k = plan_key(process, species, o);
-  const bool same = slot.process == k.process && slot.species == k.species && slot.stride == k.stride &&
-                    slot.n_samples == k.n_samples && slot.n_iter == k.n_iter && slot.eval_q == k.eval_q &&
-                    slot.uploaded;
+  const bool same = plan_matches(slot, k);
   if (!same) {
     int rc = build_plan(c, k, &slot);
     if (rc) {
@@ -1407,6 +1411,11 @@ int bmc_plan_size(bmc_ctx* c, int process, int species, const bmc_run_opts* o, i
   if (!c) return BMC_EINVAL;
   int rc = check_opts(c, o);
   if (rc) return rc;
+  if (plan_matches(c->plan, plan_key(process, species, o))) {  // the plan of the last call: its sizes
+    if (n_items) *n_items = (int)c->plan.items.size();
+    if (n_out) *n_out = c->plan.n_out;
+    return BMC_OK;
+  }
   Plan P;
   // a plan built without a workspace does not allocate map slots permanently
   auto saved = c->slot_of_uid;

@@ -1427,33 +1427,19 @@ __device__ __forceinline__ double damped(double dh, double alpha) {
   return alpha == 0.5 ? sqrt(base) : pow(base, alpha);
 }
 
-// New edges of one dimension from its damped bin weights v: edge k at cumulative weight k wsum / nb, linear inside
-// the old bins; the outer edges stay.
-__device__ void rebin_dimension(double* edges, int nb, const double* v, double wsum, double* old) {
-  for (int j = 0; j <= nb; ++j) old[j] = edges[j];
-  const double per = wsum / (double)nb;
-  int j = 0;
-  double acc = 0.0;
-  for (int k = 1; k < nb; ++k) {
-    const double target = per * (double)k;
-    while (j < nb - 1 && acc + v[j] < target) {
-      acc += v[j];
-      ++j;
-    }
-    double frac = v[j] > 0.0 ? (target - acc) / v[j] : 0.0;
-    frac = frac > 1.0 ? 1.0 : (frac < 0.0 ? 0.0 : frac);
-    edges[k] = old[j] + frac * (old[j + 1] - old[j]);
-  }
+// Lane l's value of v (l the same for every lane).
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
 }
 
-__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double (*s_d)[kMaxBins],
-                               double (*s_w)[kMaxBins], double (*s_old)[kMaxBins + 1], double* s_sum, double* maps);
+__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double* maps);
 
-__global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
+__global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
                                                       const double* shell_rec, double* res_I, double* res_V,
                                                       int slot, double* maps, int freeze, int plain) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
-  __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
   const int item = item_begin + blockIdx.x;
   const ItemRec& it = items[item];
   if (slot >= it.n_iter || it.vplus) return;  // finished, or a VEGAS+ item (its own reduction)
@@ -1476,7 +1462,8 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
   if (freeze) return;
   const uint32_t* cnt = counts + it.part_off;
   for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    uint64_t cu = 0;  // the screening pass's counts of every sample (exact integers)
+    uint64_t cu = 0;  // the screening pass's counts of every sample (exact integers: any order)
+#pragma unroll 16
     for (int u = 0; u < it.n_units; ++u) cu += cnt[(int64_t)u * DN + i];
     double h = 0.0;
     for (int u = 0; u < it.n_units; u += su) h += shell_rec[it.shell_off + (u / su) * stride + 2 + i];
@@ -1485,46 +1472,57 @@ __global__ __launch_bounds__(256) void k_reduce_adapt(const ItemRec* items, int 
     sc[i] = c;
   }
   __syncthreads();
-  adapt_item_map(it, sh, sc, s_d, s_w, s_old, s_sum, maps);
+  adapt_item_map(it, sh, sc, maps);
 }
 
-// Vegas adaptation of an item's map from its training sums sh (W^2) and sc (counts), D x nb in LDS, all dimensions
-// at once: per-bin steps over the block, sums and rebinning per dimension in bin order.
-__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double (*s_d)[kMaxBins],
-                               double (*s_w)[kMaxBins], double (*s_old)[kMaxBins + 1], double* s_sum, double* maps) {
-  const int D = it.D, nb = it.nb, DN = D * nb;
-  // averages d = h / c
-  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    const int d = i / nb, j = i - d * nb;
-    s_d[d][j] = sc[i] > 0.0 ? sh[i] / sc[i] : 0.0;
-  }
-  __syncthreads();
-  // (7,1)/(1,6,1)/(1,7)/8 smoothing
-  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    const int d = i / nb, j = i - d * nb;
-    const double* a = s_d[d];
-    s_w[d][j] = j == 0 ? (7.0 * a[0] + a[1]) / 8.0
-                       : (j == nb - 1 ? (a[nb - 2] + 7.0 * a[nb - 1]) / 8.0 : (a[j - 1] + 6.0 * a[j] + a[j + 1]) / 8.0);
-  }
-  __syncthreads();
-  if (threadIdx.x < D) {
+// Vegas adaptation of an item's map from its training sums sh (W^2) and sc (counts), D x nb in LDS.  One wave per
+// dimension, lane j holding bin j (nb <= 64): averages, smoothing from the neighbours' lanes, the sums over the
+// bins in bin order (lane by lane, the order of a sequential loop), damping, the running sums in bin order, and
+// new edge k (lane k) in the first bin whose running sum reaches k wsum / nb, found by a binary search over the
+// lanes' running sums.  Every value is the one a sequential pass over the bins computes.  No block barrier: the
+// waves take dimensions d = wave, wave + 4, ...
+__device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double* maps) {
+  const int D = it.D, nb = it.nb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  for (int d = wave; d < D; d += nw) {
+    const int j = lane < nb ? lane : nb - 1;  // lanes past the last bin repeat it and write nothing
+    const int i = d * nb + j;
+    const double a = sc[i] > 0.0 ? sh[i] / sc[i] : 0.0;  // bin average h / c
+    const double am = __shfl(a, j > 0 ? j - 1 : 0), ap = __shfl(a, j < nb - 1 ? j + 1 : nb - 1);
+    // (7,1)/(1,6,1)/(1,7)/8 smoothing
+    const double w0 = j == 0 ? (7.0 * a + ap) / 8.0 : (j == nb - 1 ? (am + 7.0 * a) / 8.0 : (am + 6.0 * a + ap) / 8.0);
     double sum = 0.0;
-    for (int j = 0; j < nb; ++j) sum += s_w[threadIdx.x][j];
-    s_sum[threadIdx.x] = sum;
-  }
-  __syncthreads();
-  // normalisation and damping
-  for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    const int d = i / nb, j = i - d * nb;
-    const double sum = s_sum[d];
-    if (sum > 0.0) s_w[d][j] = damped(s_w[d][j] / sum, it.alpha);
-  }
-  __syncthreads();
-  if (threadIdx.x < D && s_sum[threadIdx.x] > 0.0) {  // a dimension without weight keeps its edges
-    const int d = threadIdx.x;
+    for (int k = 0; k < nb; ++k) sum += lane_value(w0, k);
+    if (!(sum > 0.0)) continue;  // a dimension without weight keeps its edges
+    // normalisation and damping
+    const double w = damped(w0 / sum, it.alpha);
     double wsum = 0.0;
-    for (int j = 0; j < nb; ++j) wsum += s_w[d][j];
-    if (wsum > 0.0) rebin_dimension(maps + it.map_off + d * (nb + 1), nb, s_w[d], wsum, s_old[d]);
+    for (int k = 0; k < nb; ++k) wsum += lane_value(w, k);
+    if (!(wsum > 0.0)) continue;
+    // running sums: lane j gets w_0 + ... + w_{j-1} (pre_lo) and that plus w_j (pre_hi)
+    double acc = 0.0, pre_lo = 0.0, pre_hi = 0.0;
+    for (int k = 0; k < nb; ++k) {
+      if (lane == k) pre_lo = acc;
+      acc += lane_value(w, k);
+      if (lane == k) pre_hi = acc;
+    }
+    double* edges = maps + it.map_off + d * (nb + 1);
+    const double old_lo = edges[j], old_hi = edges[j + 1];  // read by every lane before any lane writes
+    // edge k = lane: its bin is the number of bins j <= nb-2 whose running sum pre_hi stays below the target
+    const double per = wsum / (double)nb;
+    const double target = per * (double)lane;
+    int pos = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1) {
+      const int cand = pos + step;
+      const double v = __shfl(pre_hi, cand - 1 < 63 ? cand - 1 : 63);
+      if (cand <= nb - 1 && v < target) pos = cand;
+    }
+    const double vj = __shfl(w, pos), acc_j = __shfl(pre_lo, pos);
+    const double e0 = __shfl(old_lo, pos), e1 = __shfl(old_hi, pos);
+    double frac = vj > 0.0 ? (target - acc_j) / vj : 0.0;
+    frac = frac > 1.0 ? 1.0 : (frac < 0.0 ? 0.0 : frac);
+    if (lane >= 1 && lane < nb) edges[lane] = e0 + frac * (e1 - e0);  // the outer edges stay
   }
 }
 
@@ -1629,7 +1627,6 @@ __global__ __launch_bounds__(256) void k_vplus_reduce(const ItemRec* items, cons
                                                       double* res_I, double* res_V, int slot, double* maps,
                                                       int freeze) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
-  __shared__ double s_d[kMaxD][kMaxBins], s_w[kMaxD][kMaxBins], s_old[kMaxD][kMaxBins + 1], s_sum[kMaxD];
   __shared__ double red[2 * kWaves];
   __shared__ int64_t scan[256];
   const ItemRec& it = items[which[blockIdx.x]];
@@ -1672,7 +1669,7 @@ __global__ __launch_bounds__(256) void k_vplus_reduce(const ItemRec* items, cons
     sc[i] = cs;
   }
   __syncthreads();
-  adapt_item_map(it, sh, sc, s_d, s_w, s_old, s_sum, maps);
+  adapt_item_map(it, sh, sc, maps);
   // allocation: d_h into S1 (each h by the thread that read it above), then the sum of d
   double pd = 0.0;
   for (int h = tid; h < M; h += 256) {
@@ -2244,7 +2241,7 @@ hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
                                int freeze, int plain, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(256), 0, s, items, item_begin, counts, shell_rec, res_I,
+  hipLaunchKernelGGL(k_reduce_adapt, dim3(n_items), dim3(512), 0, s, items, item_begin, counts, shell_rec, res_I,
                      res_V, slot, maps, freeze, plain);
   return hipGetLastError();
 }
