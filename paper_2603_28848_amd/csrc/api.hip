@@ -133,6 +133,7 @@ struct Plan {
   double* d_shell = nullptr;
   int64_t* d_unit_base = nullptr;
   uint32_t* d_counts = nullptr;
+  int64_t n_counts = 0;  // 32-bit bin counts (D nb per item)
   double* d_res_I = nullptr;
   double* d_res_V = nullptr;
   double* d_item_Ibar = nullptr;
@@ -491,7 +492,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.unit_size = unit_size_for(N);
             it.n_units = Pr.prm.vegas_plus ? 0 : (int)((N + it.unit_size - 1) / it.unit_size);
             it.part_off = part;
-            part += (int64_t)it.n_units * D * nb;
+            part += (int64_t)D * nb;  // the item's bin counts of the current iteration
             it.shell_off = shell;
             it.shell_units = shell_units_for(it.n_units, kShellGroupsBatched);
             it.shell_units_p = shell_units_for(it.n_units, kShellGroupsPlain);
@@ -749,6 +750,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
     Q.d_shell = reinterpret_cast<double*>(base + o_shell);
     Q.d_unit_base = reinterpret_cast<int64_t*>(base + o_ub);
     Q.d_counts = reinterpret_cast<uint32_t*>(base + o_parts);
+    Q.n_counts = part;
     Q.d_res_I = reinterpret_cast<double*>(base + o_rI);
     Q.d_res_V = reinterpret_cast<double*>(base + o_rV);
     Q.d_item_Ibar = reinterpret_cast<double*>(base + o_ib);
@@ -796,7 +798,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
       items += ni;
       units += ni * nu;
       tasks += ni * nu;
-      part += ni * nu * D * Pr.prm.n_bins;
+      part += ni * D * Pr.prm.n_bins;
       shell += ni * (size_t)shell_records(nu) * (2 + D * Pr.prm.n_bins);
       per_node += (size_t)sides * terms * nu;
       slots += c->sp[a].n;
@@ -886,6 +888,8 @@ int upload_plan(bmc_ctx* c, Plan& P) {
     HIPCHK(c, launch_init_maps(P.d_items, P.d_new, (int)P.new_maps.size(), c->spec(), c->maps(), s));
     P.new_maps.clear();
   }
+  // the items' bin counts start at zero (each iteration's reduction reads and clears them)
+  if (P.d_counts) HIPCHK(c, hipMemsetAsync(P.d_counts, 0, 4 * (size_t)P.n_counts, s));
   HIPCHK(c, hipStreamSynchronize(s));
   P.uploaded = true;
   return BMC_OK;
@@ -1988,7 +1992,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   // those (slice by slice, as the lists of one launch are bounded)
   SampleLaunch S = L;
   S.items = P.d_items;
-  S.counts = P.d_counts;
+  S.counts = nullptr;  // the collision's bin counts are not touched (no reduction follows)
   S.lds_bytes = P.lds32;
   S.chunk = c->chunk;
   S.n_listed = nullptr;

@@ -80,7 +80,7 @@ struct ItemRec {
   int unit_size;     // samples per unit
   int64_t N;         // samples per iteration
   int64_t map_off;   // doubles: Vegas map, kMaxD rows of (nb + 1) edges
-  int64_t part_off;  // collision: first unit's bin counts (D nb 32-bit counts per unit); adjoint: doubles of the
+  int64_t part_off;  // collision: the item's bin counts (D nb 32-bit counts); adjoint: doubles of the
                      // first unit record
   int64_t shell_off; // doubles: the item's second-pass records (S1, S2 and D nb W^2 sums each)
   int shell_units;   // units per second-pass record in a batched launch

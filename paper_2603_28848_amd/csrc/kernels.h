@@ -18,7 +18,8 @@ struct SampleLaunch {
   const double* qnode;   // comoving grid nodes, same layout as f
   const DevState* st;
   const double* maps;
-  uint32_t* counts;      // per unit: the bin counts of the screening pass (D nb)
+  uint32_t* counts;      // per item: the bin counts of the screening pass (D nb), added by the screening blocks;
+                         // nullptr: not kept
   double* parts;         // adjoint: unit records
   const int64_t* unit_base;  // per item: index of its first unit
   int it;                // Philox iteration index
@@ -65,10 +66,11 @@ hipError_t launch_sample(const SampleLaunch& L, hipStream_t s);
 // Second pass over the listed samples of the preceding screening launch (FP64, or the FP32 integrand).
 hipError_t launch_shell(const SampleLaunch& L, hipStream_t s);
 
-// Per item: S1, S2 and the W^2 histogram from its second-pass records in group order, the bin counts from its
-// units' counts (the screening pass counts every sample); stores I_it, V_it for iteration slot `slot` and (unless frozen)
-// adapts the item's map.  `plain` names the grouping the records were written with (per-grid-point launch).
-hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
+// Per item: S1, S2 and the W^2 histogram from its second-pass records in group order, the bin counts from the
+// item's counts (the screening pass counts every sample; they are cleared here, frozen or not); stores I_it, V_it for
+// iteration slot `slot` and (unless frozen) adapts the item's map.  `plain` names the grouping the records were
+// written with (per-grid-point launch).
+hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, uint32_t* counts,
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
                                int freeze, int plain, hipStream_t s);
 

@@ -798,12 +798,14 @@ __device__ __forceinline__ void accumulate(double W, const int* hj, double& S1, 
   }
 }
 
-// End of a screening unit: the bin counts of the FP32 map stored as the unit's counts and cleared for the next unit.
+// End of a screening block's run of units of one item: the bin counts of the FP32 map added to the item's counts in
+// global memory (integer atomics: any order gives the same sums; out = nullptr drops them) and cleared.
 __device__ __forceinline__ void finish_counts(uint32_t* cnt, int DN, uint32_t* out) {
   __syncthreads();
   for (int i = threadIdx.x; i < DN; i += kBlock) {
-    out[i] = cnt[i];
+    const uint32_t c = cnt[i];
     cnt[i] = 0u;
+    if (out && c) atomicAdd(&out[i], c);
   }
   __syncthreads();
 }
@@ -898,8 +900,9 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
       L.shell_cnt[(int64_t)t * 2 * kWaves + wave] = cin;
       L.shell_cnt[(int64_t)t * 2 * kWaves + kWaves + wave] = cnear;
     }
-    finish_counts(slot_cnt, DN, L.counts + it->part_off + (int64_t)unit * DN);
   }
+  // the run's bin counts (all its units) into the item's counts
+  finish_counts(slot_cnt, DN, L.counts ? L.counts + it->part_off : nullptr);
 }
 
 // Second pass over the in-shell tasks k0 .. k1-1 (ranges of units of one item).  Per task: first the in-shell
@@ -1436,7 +1439,7 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 
 __device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double* maps);
 
-__global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int item_begin, const uint32_t* counts,
+__global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int item_begin, uint32_t* counts,
                                                       const double* shell_rec, double* res_I, double* res_V,
                                                       int slot, double* maps, int freeze, int plain) {
   __shared__ double sh[kMaxD * kMaxBins], sc[kMaxD * kMaxBins];
@@ -1459,12 +1462,15 @@ __global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int 
     res_I[it.res_off * kMaxIter + slot] = I;
     res_V[it.res_off * kMaxIter + slot] = V;
   }
-  if (freeze) return;
-  const uint32_t* cnt = counts + it.part_off;
+  // the item's bin counts of this iteration (every sample, from the screening pass), cleared for the next one
+  uint32_t* cnt = counts + it.part_off;
+  if (freeze) {
+    for (int i = threadIdx.x; i < DN; i += blockDim.x) cnt[i] = 0u;
+    return;
+  }
   for (int i = threadIdx.x; i < DN; i += blockDim.x) {
-    uint64_t cu = 0;  // the screening pass's counts of every sample (exact integers: any order)
-#pragma unroll 16
-    for (int u = 0; u < it.n_units; ++u) cu += cnt[(int64_t)u * DN + i];
+    const uint32_t cu = cnt[i];
+    cnt[i] = 0u;
     double h = 0.0;
     for (int u = 0; u < it.n_units; u += su) h += shell_rec[it.shell_off + (u / su) * stride + 2 + i];
     const double c = (double)cu;
@@ -2237,7 +2243,7 @@ hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* co
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, const uint32_t* counts,
+hipError_t launch_reduce_adapt(const ItemRec* items, int item_begin, int n_items, uint32_t* counts,
                                const double* shell_rec, double* res_I, double* res_V, int slot, double* maps,
                                int freeze, int plain, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
