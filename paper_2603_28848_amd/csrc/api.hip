@@ -997,7 +997,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         L.grid = std::min((L.n_tasks + L.chunk - 1) / L.chunk, max_grid);
         L.sh_begin = sl.sb;
         L.n_sh = std::min(sl.se, P.sh_per_iter[k]) - sl.sb;
-        L.sh_grid = std::min(L.n_sh, max_grid);
+        L.sh_grid = L.n_sh;  // one group per block: the hardware's block dispatch balances the groups' lengths
         HIPCHK(c, sample_phase(c, L, s));
       }
     }
