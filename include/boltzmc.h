@@ -292,8 +292,9 @@ int bmc_vjp(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, co
 
 /* ---- measurement and tuning ---- */
 
-/* Enables (on != 0) timing of the sample phase (screening and second pass of one iteration's launch) with HIP
- * events on the context stream (eager launches only; graph replays are not timed). */
+/* Timing of the sample phase (screening and second pass of one iteration's launch) with HIP events on the context
+ * stream (eager launches only; graph replays are not timed): on = 0 off, on = k >= 1 every k-th sample phase
+ * (k = 1: all; each timed phase puts two event records between kernels).  BMC_EINVAL for on < 0. */
 int bmc_set_timing(bmc_ctx* ctx, int on);
 /* Sum of the timed sample-phase durations (ms) and number of timed phases since the last reset;
  * synchronises the stream.  reset != 0 clears the counters after reading. */

@@ -355,8 +355,9 @@ class Context:
                                   MEM_HOST))
         return gf, gl, gm
 
-    def set_timing(self, on=True):
-        self._check(lib().bmc_set_timing(self.h, int(on)))
+    def set_timing(self, on=True, every=1):
+        """Times the sample phases with HIP events: every `every`-th one while on (off: on=False)."""
+        self._check(lib().bmc_set_timing(self.h, int(every) if on else 0))
 
     def get_timing(self, reset=True):
         ms, n = C.c_double(), C.c_int()

@@ -184,6 +184,8 @@ struct bmc_ctx {
   int n_cu = 0;
   // optional timing of the sample kernel (eager launches only)
   bool timing = false;
+  int timing_every = 1;    // time every k-th sample phase
+  int64_t phase_count = 0;  // sample phases launched while timing is on
   bool capturing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
   double timed_ms = 0.0;
@@ -916,7 +918,7 @@ int grid_for(bmc_ctx* c, int precision, int lds, int mask) {
 hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
   hipEvent_t a = nullptr, b = nullptr;
   hipError_t e;
-  const bool timed = c->timing && !c->capturing;
+  const bool timed = c->timing && !c->capturing && (c->phase_count++ % c->timing_every) == 0;
   if (timed) {
     if ((e = hipEventCreate(&a)) != hipSuccess) return e;
     if ((e = hipEventCreate(&b)) != hipSuccess) return e;
@@ -2015,8 +2017,10 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
 }
 
 int bmc_set_timing(bmc_ctx* c, int on) {
-  if (!c) return BMC_EINVAL;
+  if (!c || on < 0) return BMC_EINVAL;
   c->timing = on != 0;
+  c->timing_every = on > 0 ? on : 1;
+  c->phase_count = 0;
   return BMC_OK;
 }
 

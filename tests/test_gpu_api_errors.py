@@ -59,3 +59,23 @@ def test_sample_count_beyond_the_word_stream_is_rejected():
     ctx = bm.from_workload(wl.w22_mb())
     with pytest.raises(bm.BmcError):
         ctx.collision(-1, -1, bm.default_opts(n_samples=1 << 32, n_iter=1))
+
+
+def test_timing_every_kth_sample_phase():
+    """set_timing(every=k) times phases 0, k, 2k, ... of the calls that follow; every < 0 is rejected."""
+    bm = _bm()
+    ctx = bm.from_workload(wl.w22_mb())
+    o = bm.default_opts(seed=1, n_iter=4)
+    ctx.collision(-1, -1, o)  # plan and maps
+    for every, calls, want in ((1, 1, 4), (3, 1, 2), (3, 2, 3), (5, 2, 2)):
+        ctx.set_timing(True, every=every)
+        ctx.get_timing(reset=True)
+        for _ in range(calls):
+            ctx.collision(-1, -1, o)
+        ms, n = ctx.get_timing(reset=True)
+        assert n == want and ms > 0.0, (every, calls, n, ms)
+    ctx.set_timing(False)
+    ctx.collision(-1, -1, o)
+    assert ctx.get_timing(reset=True)[1] == 0
+    with pytest.raises(bm.BmcError):
+        ctx.set_timing(True, every=-1)
