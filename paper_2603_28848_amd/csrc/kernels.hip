@@ -243,9 +243,9 @@ struct ItemConsts {
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
-  float shell;   // 12 sigma_E (absolute width)
+  float shell;   // 7 sigma_E (absolute width)
   float far;     // |dE| of the FP64 underflow of the Gaussian factor, sqrt(2 746) sigma_E (absolute width)
-  float cin, cfar;  // per unit of the summed energies: the FP32 margin, plus 6 w and sqrt(2 746) w / 2 (relative)
+  float cin, cfar;  // per unit of the summed energies: the FP32 margin, plus 3.5 w and sqrt(2 746) w / 2 (relative)
   float wconst;  // a^-3n |M|^2 / ((2 pi)^(3(n-1)-4) sqrt(2 pi)), divided by sigma_E for an absolute width
   float whalf32;
   int rel;       // relative width: sigma_E = whalf (sum of the point's energies)
@@ -471,11 +471,13 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 
 // FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns the
 // sample's class:
-//   kInShell  |dE| < 12 sigma_E + m: W needs the FP64 kinematics;
+//   kInShell  |dE| < 7 sigma_E + m: W needs the FP64 kinematics;
 //   kFar      |dE| > sqrt(2 746) sigma_E + m: the FP64 |dE| exceeds the point where the Gaussian factor
 //             e^(-dE^2 / (2 sigma_E^2)) underflows to 0 in FP64, so W = 0 exactly;
-//   kNear     the rest: with FINISH, W is finished in FP32 (its Gaussian factor is below e^-72 relative, so W only
-//             matters for the map's training histogram, where ~1e-6 accuracy is ample).
+//   kNear     the rest: with FINISH, W is finished in FP32.  Its Gaussian factor is below e^-24.5 = 2.3e-11 of the
+//             peak, and the FP32 dE moves the factor by at most a few per cent there (|dE| eps_32 sum(E) / sigma_E^2
+//             for sums of energies up to 100 and sigma_E = 0.005), so such a sample shifts the integral by ~1e-12 of
+//             its size at most; W matters for the map's training histogram, where that accuracy is ample.
 // m = 1e-3 of the summed energies bounds the difference of the FP32 and FP64 dE with a wide margin.  The bin of
 // every dimension is exact (the same as with the FP64 map).  With COUNT the sample is added to the count of its bin
 // in every dimension (the count word of the bin's map slot).
@@ -751,7 +753,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       K.dnorm = 0.0;
       K.shell = 0.0f;
       K.far = 0.0f;
-      K.cin = (float)(1e-3 + 6.0 * wd);
+      K.cin = (float)(1e-3 + 3.5 * wd);  // 7 sigma_E with sigma_E = w sum(E) / 2
       K.cfar = (float)(1e-3 + 0.5 * kFarK * wd);
       K.ylog2 = 0.0f;
       K.wconst = (float)(K.a3M2 / K.twopi_pow * kRs2pi);
@@ -759,7 +761,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       K.whalf = 0.0;
       K.inv2s2 = 1.0 / (2.0 * wd * wd);
       K.dnorm = kRs2pi / wd;
-      K.shell = (float)(12.0 * wd);
+      K.shell = (float)(7.0 * wd);
       K.far = (float)(kFarK * wd);
       K.cin = 1e-3f;
       K.cfar = 1e-3f;
