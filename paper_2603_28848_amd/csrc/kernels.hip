@@ -238,8 +238,9 @@ struct ItemConsts {
   const double* e;    // LDS map edges (D x nb)
   const double* w;    // LDS map widths
   const double2* sc;  // LDS sin/cos of k pi/16
-  float* m32;         // LDS FP32 map (screening pass): edges [0, kMapSlots), widths x 2^-32 (angles in
-                      // revolutions) [kMapSlots, 2 kMapSlots), the unit's bin counts (as bits) after them
+  float* m32;         // LDS FP32 map (screening pass): edges [0, kMapSlots), widths x 2^-32 [kMapSlots,
+                      // 2 kMapSlots) (radial values divided by a, angles in revolutions), the unit's bin counts
+                      // (as bits) after them
   FTab<FT> tr[NI + 1];
   float lg1[NI + 1], lg0[NI + 1];  // grid position from log2: t = log2(q) ln2/h - ln(q_0)/h
   float ylog2;   // log2(e) / (2 sigma_E^2) (absolute width)
@@ -491,8 +492,9 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, con
   // nb as a vector operand, so that the 64-bit multiply-add below can take its uniform addend from scalar registers
   uint32_t vnb;
   asm("v_mov_b32 %0, %1" : "=v"(vnb) : "s"(nb));
-  const float fnb32 = (float)nb * 4294967296.0f, fnb32rev = fnb32 * 6.2831853071795865f;  // per-dim Jacobian
-  const float inv_a = (float)K.inv_a;
+  const float a32 = (float)K.a;
+  // per-dimension Jacobian factors (the radial widths carry 1/a, the angular ones 1/(2 pi))
+  const float fnb32 = (float)nb * 4294967296.0f, fnb32r = fnb32 * a32, fnb32rev = fnb32 * 6.2831853071795865f;
   float J = 1.0f, jac = 1.0f;
   float sx = 0.0f, sy = 0.0f, sz = (float)(K.esg[NI + 1] * K.p_obs);
   float dE = (float)(K.esg[NI + 1] * K.E_obs), sumE = (float)K.E_obs, prod2E = 2.0f * (float)K.E_obs;
@@ -525,14 +527,14 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, con
       const float ew = *reinterpret_cast<const float*>(mp + 4 * kMapSlots);
       if constexpr (COUNT) atomicAdd(reinterpret_cast<uint32_t*>(mp + 8 * kMapSlots), 1u);  // the bin's count
       x3[c] = fmaf(ew, (float)(uint32_t)t, e0);
-      J *= (c == 0 ? fnb32 : fnb32rev) * ew;
+      J *= (c == 0 ? fnb32r : fnb32rev) * ew;
       hj[d] = jd;
     }
-    const float r = x3[0];
+    const float p = x3[0];  // physical momentum: the radial map values carry 1/a
+    const float r = p * a32;  // comoving momentum (the finish's Jacobian and f lookup)
     const float th = x3[1], ph = x3[2];  // revolutions
     const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
     const float sph = __builtin_amdgcn_sinf(ph), cph = __builtin_amdgcn_cosf(ph);
-    const float p = r * inv_a;
     const float ps = p * sth;
     const float sg = (float)K.esg[k];
     sx = fmaf(sg, ps * cph, sx);
@@ -663,9 +665,10 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       sm_e[i] = e0;
       sm_w[i] = e1 - e0;
     }
-    // screening map: the width carries the 2^-32 of the uniform's low word, and the angles are in revolutions (the
-    // hardware sine takes them), so a coordinate is one fma of the low word; the bin's count starts at 0
-    const double sc = (d % 3 == 0) ? 1.0 : 0.15915494309189535;
+    // screening map: the width carries the 2^-32 of the uniform's low word, the radial values are physical momenta
+    // (comoving / a) and the angles are in revolutions (the hardware sine takes them), so a momentum or an angle is
+    // one fma of the low word; the bin's count starts at 0
+    const double sc = (d % 3 == 0) ? L.st->inv_a : 0.15915494309189535;
     sm_m32[i] = (float)(e0 * sc);
     sm_m32[kMapSlots + i] = (float)((e1 - e0) * sc * 2.3283064365386962890625e-10);
     reinterpret_cast<uint32_t*>(sm_m32)[2 * kMapSlots + i] = 0u;
