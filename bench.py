@@ -26,7 +26,7 @@ PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane 
 # HBM bytes per sample phase (screening + in-shell kernels) of this workload, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernels;
 # None once they change.
-TRAFFIC_BYTES_PER_PHASE = 29.2e6 + 77.8e6
+TRAFFIC_BYTES_PER_PHASE = 33.3e6 + 81.8e6
 TIMING_EVERY = 7
 
 
