@@ -8,10 +8,13 @@
 //     W = J(y) prod_k r_k^2 sin(theta_k) a^-3 |M|^2 delta(E_in - E_out) / ((2 pi)^{3(n-1)-4} prod_i 2 E_i) * F
 // with F the gain or loss product relative to the observed leg (Eq. 5 and the C_2 / C_3 lists of Sec. II.C).
 //
-// One block of 256 threads processes one unit (a contiguous range of sample indices) of one item.  Sums are
-// formed in a fixed order that depends only on the unit size: per thread in sample order, a butterfly over
-// the wave, the four waves in order, then the units in order (reduce kernel).  The Vegas training
-// histograms are accumulated per wave in LDS and summed over waves in order.
+// An iteration's sample phase is two kernels.  The screening pass (blocks of 256 threads over runs of units, a unit
+// being a contiguous range of sample indices of one item) evaluates every sample's kinematics in FP32, adds every
+// sample to its bins' counts (integers, so any order gives the same sums) and lists the samples whose W can be
+// nonzero.  The second pass (one block per group of an item's units) evaluates the listed samples; its sums are
+// formed in a fixed order that depends only on the item: per thread in list order, a butterfly over the wave, the
+// four waves in order, then the groups in order (reduce kernel).  The Vegas training histograms of W^2 are
+// accumulated per wave in LDS and summed over waves in order.
 #include <math.h>
 
 #include <type_traits>
