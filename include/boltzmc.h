@@ -19,8 +19,10 @@
  *     stay valid until the stream reaches that point; calls that return host results synchronise the stream.
  *   * The library allocates no device memory of its own: all device state (tables, Vegas maps, partial
  *     sums, results) lives in one workspace the caller allocates and binds (bmc_workspace_query / _bind).
- *   * Results depend only on (inputs, seed, epoch, iteration indices, Vegas maps); they do not depend on the
- *     launch mode (batched or per grid point), the launch tuning, or other items in the same call.
+ *   * Results depend only on (inputs, seed, epoch, iteration indices, Vegas maps) and the launch mode; they do not
+ *     depend on the launch tuning or on other items in the same call.  The batched and per-grid-point launch modes
+ *     group the second pass's sums differently (4 and 32 groups per item), so for the same maps their results
+ *     agree to rounding; each mode repeats itself bitwise.
  *   * Work item: (process, observed species, pinned side, term, evaluation grid index).  Its identifier is
  *         uid = process << 24 | species << 20 | side << 19 | term << 18 | eval_index
  *     (side 0 = initial state, 1 = final state; term 0 = gain or net, 1 = loss).  Items of a call are
