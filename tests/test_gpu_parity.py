@@ -194,6 +194,27 @@ def test_launch_tuning_and_autotuner_do_not_change_results(precision):
         assert np.array_equal(C, res[0][0]) and np.array_equal(S, res[0][1]) and np.array_equal(I, res[0][2])
 
 
+def test_frozen_and_adjoint_calls_leave_no_bin_counts_behind():
+    """The screening pass adds every sample to its item's bin counts and each iteration's reduction reads and clears
+    them. A frozen-map collision (which adapts nothing) or an adjoint call (whose screening keeps no counts) must
+    leave them clear: the adapting collision after either equals, bitwise, the same collision on a fresh context."""
+    bm = _bm()
+    w = wl.w23_be(n_grid=16, N=1 << 14, nitn=3)
+    o = bm.default_opts(seed=5, epoch=2)
+    ref = bm.from_workload(w)
+    C0, S0 = ref.collision(-1, -1, o)
+    a = bm.from_workload(w)
+    a.collision(-1, -1, bm.default_opts(seed=9, epoch=7, freeze_maps=1))
+    C1, S1 = a.collision(-1, -1, o)
+    assert np.array_equal(C1, C0) and np.array_equal(S1, S0)
+    b = bm.from_workload(w)
+    ni, no = b.plan_size(-1, -1, o)
+    b.collision(-1, -1, bm.default_opts(seed=9, epoch=7, freeze_maps=1))  # the plan and the adjoint's screening lists
+    b.vjp(np.ones(no), -1, -1, bm.default_opts(seed=9, epoch=7, precision=0))
+    C2, S2 = b.collision(-1, -1, o)
+    assert np.array_equal(C2, C0) and np.array_equal(S2, S0)
+
+
 def test_selection_invariance():
     """An item's results do not depend on which other items share the launch."""
     bm = _bm()
