@@ -106,6 +106,10 @@ def lib():
                               C.c_uint32, dp, dp, dp, dp, C.c_int]
         L.orc_step.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
                                C.c_uint64, C.c_uint32, C.c_int, dp, dp, C.c_int]
+        L.orc_adapt_dim.argtypes = [dp, C.c_int, dp, dp, C.c_double]
+        L.orc_adapt_dim.restype = None
+        L.orc_collision_exact22_all.argtypes = [C.POINTER(World), dp, dp]
+        L.orc_step_exact22.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, dp]
         _lib = L
     return _lib
 
@@ -126,6 +130,17 @@ def stat_factor(n_in, n, obs_side, term_mode, term, f, eta):
     f = np.ascontiguousarray(f, dtype=np.float64)
     eta = np.ascontiguousarray(eta, dtype=np.float64)
     return lib().orc_stat_factor(n_in, n, obs_side, term_mode, term, _dp(f), _dp(eta))
+
+
+def adapt_dim(edges, h, cnt, alpha):
+    """The oracle's Vegas adaptation of one dimension: new edges from old edges (nb + 1), per-bin training sums h
+    and counts cnt (nb each)."""
+    e = np.ascontiguousarray(edges, dtype=np.float64).copy()
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    c = np.ascontiguousarray(cnt, dtype=np.float64)
+    assert e.size == h.size + 1 == c.size + 1
+    lib().orc_adapt_dim(_dp(e), h.size, _dp(h), _dp(c), alpha)
+    return e
 
 
 def uniforms(seed, uid, epoch, it, n, D):
@@ -309,6 +324,19 @@ class OracleWorld:
         rc = lib().orc_vjp(C.byref(self.world), n_items, items, _dp(coef), N, iter_, seed, epoch, _dp(maps), _dp(gf),
                            _dp(gm), _dp(gl), threads)
         return rc, gf, gm, gl[: len(self.w.processes)]
+
+    def collision_exact22_all(self):
+        """(rc, C) of every species' grid by the exact-delta 2->2 operator."""
+        tot = sum(s.n_grid for s in self.w.species)
+        Cv, S = np.zeros(tot), np.zeros(tot)
+        rc = lib().orc_collision_exact22_all(C.byref(self.world), _dp(Cv), _dp(S))
+        return rc, Cv
+
+    def step_exact22(self, method, dt, eps=0.3, dt_max=1e30):
+        """One Euler (0) or Heun (1) step with the exact-delta 2->2 operator; (rc, dt used)."""
+        dtu = np.zeros(1)
+        rc = lib().orc_step_exact22(C.byref(self.world), method, dt, eps, dt_max, _dp(dtu))
+        return rc, dtu[0]
 
     def step(self, method, dt, eps, dt_max, N, nitn, seed=0, epoch=0, threads=0, adapt=True):
         nb = self.pr[0].n_bins

@@ -725,6 +725,18 @@ static void adapt_dim(double* edges, int nb, const long double* h, const long do
   edges[nb] = old[nb];
 }
 
+/* The adaptation of one dimension from per-bin sums h[0..nb-1] and counts cnt[0..nb-1] given as doubles (edges:
+ * nb + 1 values, in/out). */
+void orc_adapt_dim(double* edges, int nb, const double* h, const double* cnt, double alpha) {
+  long double hl[ORC_MAXBINS], cl[ORC_MAXBINS];
+  if (nb < 1 || nb > ORC_MAXBINS) return;
+  for (int j = 0; j < nb; ++j) {
+    hl[j] = (long double)h[j];
+    cl[j] = (long double)cnt[j];
+  }
+  adapt_dim(edges, nb, hl, cl, alpha);
+}
+
 /* VEGAS+ (Lepage, J. Comput. Phys. 439 (2021) 110386): adaptive stratified sampling on top of the Vegas map.
  * y-space is cut into M = k^D hypercubes, k = orc_vplus_strata(N, D) per dimension, each of volume 1/M; hypercube
  * h = sum_d h_d k^d (dimension 0 fastest).  An iteration draws n_h samples in hypercube h, sample s = off_h + i
@@ -1422,17 +1434,73 @@ int orc_exact22(const orc_world* w, int n_items, const orc_item* items, double* 
   return ORC_OK;
 }
 
+/* Full-grid exact-delta collision term of every species from all processes (each 2->2 with a constant |M|^2): the
+ * items of orc_list_items, their exact-delta estimates combined per process as in orc_collision_all (strided fill
+ * included); sig_all is 0. */
+int orc_collision_exact22_all(const orc_world* w, double* C_all, double* sig_all) {
+  int n_items = orc_list_items(w, -1, -1, 0, NULL, 0);
+  orc_item* items = (orc_item*)malloc(sizeof(orc_item) * (size_t)(n_items > 0 ? n_items : 1));
+  double* I = (double*)malloc(sizeof(double) * (size_t)(n_items > 0 ? n_items : 1));
+  double* z = (double*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(double));
+  if (!items || !I || !z) {
+    free(items); free(I); free(z);
+    return ORC_ENOMEM;
+  }
+  orc_list_items(w, -1, -1, 0, items, n_items);
+  int rc = orc_exact22(w, n_items, items, I);
+  if (rc == ORC_OK) {
+    size_t off = 0;
+    for (int a = 0; a < w->n_species; ++a) {
+      int n = w->species[a].n_grid;
+      for (int j = 0; j < n; ++j) { C_all[off + j] = 0.0; sig_all[off + j] = 0.0; }
+      double* Cp = (double*)malloc(sizeof(double) * (size_t)n);
+      double* Sp = (double*)malloc(sizeof(double) * (size_t)n);
+      for (int p = 0; p < w->n_proc; ++p) {
+        int first = -1, cnt = 0;
+        for (int i = 0; i < n_items; ++i)
+          if (items[i].proc == p && items[i].species == a) { if (first < 0) first = i; ++cnt; }
+        if (cnt == 0) continue;
+        orc_combine(w, cnt, &items[first], &I[first], &z[first], a, Cp, Sp);
+        int stride = w->procs[p].eval_stride > 0 ? w->procs[p].eval_stride : 1;
+        fill_strided(&w->species[a], stride, Cp, Sp);
+        for (int j = 0; j < n; ++j) C_all[off + j] += Cp[j];
+      }
+      free(Cp);
+      free(Sp);
+      off += (size_t)n;
+    }
+  }
+  free(items); free(I); free(z);
+  return rc;
+}
+
 /* =====================================================================================================
  * Log-space time stepping (Sec. III.C).
  * ===================================================================================================== */
 
-/* One Euler or Heun step of every species' f (in place, via the species' f pointers, which must be
- * writable), advancing w->t.  dt > 0: fixed step; dt <= 0: dt = min(dt_max, eps / max |k1/f|).
- * Heun: f* = f exp(dt k1/f), k2 = C[f*] at t + dt with epoch + 1,
- *       log f <- log f + dt/2 (k1/f + k2/f*).
- * Euler: log f <- log f + dt k1/f.   Maps are reused and updated in place. */
-int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
-             uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads) {
+/* One evaluation of the collision operator on every species' full grid (C_all, sigma in sig_all).  The Monte Carlo
+ * operator of orc_collision_all, or the exact-delta 2->2 reduction of orc_collision_exact22_all. */
+typedef struct {
+  int exact;
+  int64_t N;
+  int nitn, adapt, n_threads;
+  uint64_t seed;
+  double* maps;
+} step_op;
+
+static int apply_op(const step_op* op, const orc_world* w, uint32_t epoch, double* C_all, double* sig_all) {
+  if (op->exact) return orc_collision_exact22_all(w, C_all, sig_all);
+  return orc_collision_all(w, op->N, op->nitn, op->seed, epoch, op->adapt, op->maps, C_all, sig_all, op->n_threads);
+}
+
+/* One Euler or Heun step of every species' f (in place, via the species' f pointers, which must be writable),
+ * advancing w->t (Sec. III.C).  k1 = C[f] at t; dt > 0: a fixed step; dt <= 0: dt = min(dt_max, eps / max |k1/f|)
+ * (Eq. 20).
+ *   Euler (Eq. 18):  log f <- log f + dt k1/f;
+ *   Heun (Eq. 19):   the predictor f* = f exp(dt k1/f), k2 = C[f*] at t + dt (epoch + 1 for the Monte Carlo
+ *                    operator), then log f <- log f + dt/2 (k1/f + k2/f*). */
+static int step_core(orc_world* w, int method, double dt, double eps, double dt_max, uint32_t epoch,
+                     const step_op* op, double* dt_used) {
   size_t tot = 0;
   for (int a = 0; a < w->n_species; ++a) tot += (size_t)w->species[a].n_grid;
   double* k1 = (double*)malloc(sizeof(double) * tot);
@@ -1444,7 +1512,7 @@ int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int
     free(k1); free(k2); free(sg); free(f0); free(fs);
     return ORC_ENOMEM;
   }
-  int rc = orc_collision_all(w, N, nitn, seed, epoch, adapt, maps, k1, sg, n_threads);
+  int rc = apply_op(op, w, epoch, k1, sg);
   if (rc) goto done;
   {
     size_t off = 0;
@@ -1484,7 +1552,7 @@ int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int
       }
       double t0 = w->t;
       w->t = t0 + h;
-      rc = orc_collision_all(w, N, nitn, seed, epoch + 1u, adapt, maps, k2, sg, n_threads);
+      rc = apply_op(op, w, epoch + 1u, k2, sg);
       if (rc) {
         w->t = t0;
         off = 0;
@@ -1507,4 +1575,17 @@ int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int
 done:
   free(k1); free(k2); free(sg); free(f0); free(fs);
   return rc;
+}
+
+/* The Monte Carlo step: k1 with `epoch`, k2 with epoch + 1; maps are reused and updated in place. */
+int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
+             uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads) {
+  step_op op = {0, N, nitn, adapt, n_threads, seed, maps};
+  return step_core(w, method, dt, eps, dt_max, epoch, &op, dt_used);
+}
+
+/* The same step with the deterministic exact-delta 2->2 operator (every process 2->2 with a constant |M|^2). */
+int orc_step_exact22(orc_world* w, int method, double dt, double eps, double dt_max, double* dt_used) {
+  step_op op = {1, 0, 0, 0, 0, 0, NULL};
+  return step_core(w, method, dt, eps, dt_max, 0u, &op, dt_used);
 }

@@ -162,6 +162,13 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
 int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
             uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
             int n_threads);
+/* Vegas map adaptation of one dimension (smoothing, normalisation, damping, rebinning; Appendix C alpha) from
+ * per-bin training sums h and counts cnt; edges[0..nb] in/out. */
+void orc_adapt_dim(double* edges, int nb, const double* h, const double* cnt, double alpha);
+/* Full-grid collision term of every species by the exact-delta 2->2 reduction (sigma 0). */
+int orc_collision_exact22_all(const orc_world* w, double* C_all, double* sig_all);
+/* One Euler or Heun step (Sec. III.C) with the exact-delta 2->2 operator in place of the Monte Carlo one. */
+int orc_step_exact22(orc_world* w, int method, double dt, double eps, double dt_max, double* dt_used);
 int orc_step(orc_world* w, int method, double dt, double eps, double dt_max, int64_t N, int nitn, uint64_t seed,
              uint32_t epoch, int adapt, double* maps, double* dt_used, int n_threads);
 
