@@ -106,6 +106,7 @@ def lib():
                               C.c_uint32, dp, dp, dp, dp, C.c_int]
         L.orc_step.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
                                C.c_uint64, C.c_uint32, C.c_int, dp, dp, C.c_int]
+        L.orc_item_dims.argtypes = [C.POINTER(World), C.POINTER(Item)]
         L.orc_adapt_dim.argtypes = [dp, C.c_int, dp, dp, C.c_double]
         L.orc_adapt_dim.restype = None
         L.orc_collision_exact22_all.argtypes = [C.POINTER(World), dp, dp]
@@ -267,6 +268,9 @@ class OracleWorld:
         rc = lib().orc_integrand_at(C.byref(self.world), C.byref(item), _dp(x), _dp(v))
         assert rc == 0, rc
         return v[0]
+
+    def item_dims(self, item):
+        return lib().orc_item_dims(C.byref(self.world), C.byref(item))
 
     def map_uniform(self, item, nb):
         m = np.zeros(MAXD * (nb + 1))

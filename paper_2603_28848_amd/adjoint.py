@@ -48,12 +48,12 @@ class CollisionFn(torch.autograd.Function):
         f, coupling, mass = ctx.saved_tensors
         bctx = ctx.bctx
         _apply_params(bctx, coupling, mass)
-        bctx.set_f_all(f.contiguous())
+        bctx.set_f_all(f.to(device="cuda:%d" % bctx.device, dtype=torch.float64).contiguous())
         bctx.set_time(ctx.t)
-        gf, gl, gm = bctx.vjp(gC.detach().cpu().numpy(), -1, -1, _opts(ctx.base, ctx.epoch))
-        dev = f.device
-        return (torch.from_numpy(gf).to(dev), torch.from_numpy(gl).to(dev), torch.from_numpy(gm).to(dev), None, None,
-                None, None)
+        gf, gl, gm = bctx.vjp(gC.detach().to(torch.float64).cpu().numpy(), -1, -1, _opts(ctx.base, ctx.epoch))
+        return (torch.from_numpy(gf).to(device=f.device, dtype=f.dtype),
+                torch.from_numpy(gl).to(device=coupling.device, dtype=coupling.dtype),
+                torch.from_numpy(gm).to(device=mass.device, dtype=mass.dtype), None, None, None, None)
 
 
 def heun_step(bctx, f, coupling, mass, t, dt, base_opts, epoch):

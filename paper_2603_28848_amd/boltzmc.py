@@ -199,7 +199,14 @@ class Context:
         return np.concatenate([self.get_f(s, n) for s, n in enumerate(self.grids)])
 
     def set_f(self, species, f):
+        """f of one species from a host array or a torch tensor.  The library reads FP64 device memory: a tensor of
+        another dtype, on the host or another device, or not contiguous is first copied to a contiguous FP64 tensor
+        on the context's device (bmc_set_f is synchronous, so the copy lives long enough)."""
         if hasattr(f, "data_ptr"):
+            t = self.torch
+            if (f.dtype != t.float64 or f.device.type != "cuda" or f.device.index != self.device
+                    or not f.is_contiguous()):
+                f = f.detach().to(device="cuda:%d" % self.device, dtype=t.float64).contiguous()
             self._check(lib().bmc_set_f(self.h, species, _ptr(f), f.numel(), MEM_DEVICE))
         else:
             f = np.ascontiguousarray(f, dtype=np.float64)

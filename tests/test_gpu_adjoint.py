@@ -106,3 +106,139 @@ def test_heun_rollout_gradient_matches_finite_differences():
     for name, num, ana in checks:
         say("%s: FD %.10e adjoint %.10e rel %.2e" % (name, num, ana, abs(num - ana) / max(abs(num), 1e-300)))
         assert ana == pytest.approx(num, rel=1e-5, abs=1e-9 * abs(L.item()))
+
+
+def _config4_context():
+    """The 2<->3 adjoint workload at full size: 256 nodes on [0.1, 50], the paper's non-thermal f0, 2^20 samples per
+    item; the maps trained by 4 adaptive iterations of 2^18 samples at t = 0, then frozen."""
+    bm = _bm()
+    w = wl.w23_adjoint()
+    ctx = bm.from_workload(w)
+    ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, n_iter=4, n_samples=1 << 18))
+    return bm, w, ctx
+
+
+def test_config4_full_size_rollout_gradient():
+    """L = sum (f(t_20) - f_BE(T=1))^2 after 20 Heun steps (dt from the epsilon rule at step 0, then fixed) at 2^20
+    samples per item and C: autograd through the adjoint kernel against central differences (h = 1e-6) of the same
+    GPU forward on lambda, m0, two f0 coordinates and two random directions."""
+    import torch
+    from paper_2603_28848_amd import adjoint
+    bm, w, ctx = _config4_context()
+    n = 256
+    base = bm.default_opts(seed=0, n_samples=1 << 20)
+    q = wl.log_nodes(0.1, 50.0, n)
+    target = torch.tensor(wl.f_equilibrium(q, 1.0, 1.0, wl.BOSE), dtype=torch.float64, device="cuda")
+    f0 = torch.tensor(w.species[0].f, dtype=torch.float64, device="cuda")
+    dt = adjoint.adaptive_dt(ctx, w.species[0].f, 0.3, 1.0, base, epoch0=1000)
+    say("config-4 rollout: dt = %g" % dt)
+
+    def loss(f0_, lam_, m_):
+        fT = adjoint.heun_rollout(ctx, f0_, lam_, m_, 0.0, dt, 20, base, epoch0=1000)
+        return torch.sum((fT - target) ** 2)
+
+    lam = torch.tensor([1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+    m = torch.tensor([1.0], dtype=torch.float64, device="cuda", requires_grad=True)
+    f0r = f0.clone().requires_grad_(True)
+    L = loss(f0r, lam, m)
+    L.backward()
+    gf, gl, gm = f0r.grad.clone(), lam.grad.item(), m.grad.item()
+    h = 1e-6
+    with torch.no_grad():
+        one = torch.ones(1, dtype=torch.float64, device="cuda")
+
+        def fd(dir_f=None, dl=0.0, dmm=0.0):
+            lp = loss(f0 * (1 + h * dir_f) if dir_f is not None else f0, one * (1 + h * dl), one * (1 + h * dmm))
+            lm = loss(f0 * (1 - h * dir_f) if dir_f is not None else f0, one * (1 - h * dl), one * (1 - h * dmm))
+            return (lp - lm).item() / (2 * h)
+        checks = [("lambda", fd(dl=1.0), gl), ("m0", fd(dmm=1.0), gm)]
+        for j in (40, 150):
+            e = torch.zeros(n, dtype=torch.float64, device="cuda")
+            e[j] = 1.0
+            checks.append(("f0[%d]" % j, fd(dir_f=e), (gf * f0 * e).sum().item()))
+        rng = np.random.default_rng(7)
+        for k in range(2):
+            d = torch.tensor(rng.normal(size=n), dtype=torch.float64, device="cuda")
+            checks.append(("dir%d" % k, fd(dir_f=d), (gf * f0 * d).sum().item()))
+    for name, num, ana in checks:
+        say("config-4 %s: FD %.10e adjoint %.10e rel %.2e" % (name, num, ana, abs(num - ana) / max(abs(num), 1e-300)))
+        assert ana == pytest.approx(num, rel=1e-5, abs=1e-9 * abs(L.item()))
+
+
+def test_config4_vjp_matches_oracle_at_2_14():
+    """One C's VJP on the full 256-node config-4 workload with its trained (frozen) maps, at 2^14 samples per item:
+    GPU against the oracle's VJP on the same maps and counters."""
+    bm, w, ctx = _config4_context()
+    N = 1 << 14
+    opts = bm.default_opts(seed=2, epoch=9, n_iter=1, freeze_maps=1, eval_stride=1, n_samples=N)
+    ni, no = ctx.plan_size(-1, -1, opts)
+    v = np.random.default_rng(3).normal(size=no)
+    gf, gl, gm = ctx.vjp(v, -1, -1, opts)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items(stride=1)
+    assert n == ni == 1024
+    maps = ctx.maps_get([items[i].uid for i in range(n)], 50)
+    coef = np.array([v[items[i].eval_idx] * items[i].mult * (-1 if items[i].term == 1 else 1) for i in range(n)])
+    rc, of, om, ol = ow.vjp(items, n, coef, N, 0, seed=2, epoch=9, maps=maps)
+    assert rc == 0
+    err_f = np.max(np.abs(gf - of)) / np.max(np.abs(of))
+    say("config-4 vjp: grad_f max err / max |grad| = %.3e; grad_m %s vs %s; grad_lambda %s vs %s" %
+        (err_f, gm, om, gl, ol))
+    assert err_f < 1e-10
+    np.testing.assert_allclose(gm, om, rtol=1e-10)
+    np.testing.assert_allclose(gl, ol, rtol=1e-10)
+
+
+def test_heun_rollout_forward_equals_library_step():
+    """The autograd rollout's forward (Eq. 19 composed in torch from two collision calls) against the library's own
+    Heun step (bmc_step) with the same fixed dt, epochs and frozen maps: equal to 1e-12."""
+    import torch
+    from paper_2603_28848_amd import adjoint
+    bm = _bm()
+    w = wl.w23_adjoint(n_grid=32, q_min=0.1, q_max=12.0, sigma_E=0.02, N=1 << 12, nitn=1)
+    a, b = bm.from_workload(w), bm.from_workload(w)
+    train = bm.default_opts(seed=0, epoch=0, n_iter=3, n_samples=1 << 13)
+    a.collision(-1, -1, train)
+    b.collision(-1, -1, train)
+    base = bm.default_opts(seed=0, n_samples=1 << 12)
+    dt = 0.5 * adjoint.adaptive_dt(a, w.species[0].f, 0.3, 1.0, base, epoch0=100)
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    f0 = torch.tensor(w.species[0].f, dtype=torch.float64, device="cuda")
+    with torch.no_grad():
+        f_roll = adjoint.heun_rollout(a, f0, one, one, 0.0, dt, 3, base, epoch0=100).cpu().numpy()
+    for s in range(3):
+        used = b.step(bm.HEUN, dt, 0.3, 1e30, bm.default_opts(seed=0, n_samples=1 << 12, n_iter=1, epoch=100 + 2 * s,
+                                                              freeze_maps=1, eval_stride=1))
+        assert used == dt
+    f_lib = b.get_f(0, 32)
+    rel = np.max(np.abs(f_roll - f_lib) / f_lib)
+    say("rollout forward vs bmc_step: max rel diff %.3e (max |log change| %.3f)" %
+        (rel, np.max(np.abs(np.log(f_lib / w.species[0].f)))))
+    assert rel < 1e-12
+    assert b.get_time() == pytest.approx(3 * dt, rel=1e-15)
+
+
+def test_collision_fn_takes_float32_input():
+    """A float32 f is converted to FP64 on the way in (forward and backward): the result and gradient equal those of
+    the same values given as float64, and the gradient comes back in float32."""
+    import torch
+    from paper_2603_28848_amd import adjoint
+    bm = _bm()
+    w = wl.w23_be(n_grid=24, q_min=0.05, q_max=8.0, sigma_E=0.05, N=1 << 12, nitn=1)
+    ctx = bm.from_workload(w)
+    base = bm.default_opts(seed=1, n_samples=1 << 12)
+    f32 = torch.tensor(w.species[0].f, dtype=torch.float32, device="cuda")
+    f64 = f32.to(torch.float64)
+    one = torch.ones(1, dtype=torch.float64, device="cuda")
+    out = {}
+    for name, f in (("f32", f32), ("f64", f64)):
+        fr = f.clone().requires_grad_(True)
+        C = adjoint.CollisionFn.apply(fr, one, one, ctx, 0.0, base, 3)
+        (C * torch.linspace(-1, 1, C.numel(), dtype=torch.float64, device="cuda")).sum().backward()
+        out[name] = (C.detach().cpu().numpy(), fr.grad)
+    assert np.array_equal(out["f32"][0], out["f64"][0])
+    assert out["f32"][1].dtype == torch.float32
+    assert torch.equal(out["f32"][1], out["f64"][1].to(torch.float32))
+    # a host tensor is also accepted
+    ctx.set_f(0, f64.cpu())
+    np.testing.assert_array_equal(ctx.get_f(0, 24), f64.cpu().numpy())

@@ -117,6 +117,72 @@ def test_2to4_full_size_sampled_items(precision):
     assert_items_close(res["I_it"][pick], r["I_it"], TOL[precision], "I_it", scale=item_scale(items, n, r["Ibar"]))
 
 
+_MULTI_FULL = {}
+
+
+def _multi_full_oracle(uids_pick):
+    """The oracle's results for the picked items of the full-size two-species workload (cached: both precisions
+    compare against the same FP64 numbers).  Each process's items run at that process's sample count."""
+    key = tuple(int(u) for u in uids_pick)
+    if key not in _MULTI_FULL:
+        w = wl.w_multi(nitn=2)
+        ow = ob.OracleWorld(w)
+        I = np.zeros((len(key), 2))
+        scale = np.zeros(len(key))
+        for p, N in enumerate(w.processes[i].n_samples for i in range(3)):
+            sel = [k for k, u in enumerate(key) if (u >> 24) == p]
+            items, n = oracle_items_matching(ow, [key[k] for k in sel])
+            say("multi full size: oracle process %d, %d items at N = %d" % (p, n, N))
+            rc, r = ow.run_items(items, n, N, 2, adapt=False)
+            assert rc == 0
+            I[sel] = r["I_it"]
+            scale[sel] = item_scale(items, n, r["Ibar"])
+        _MULTI_FULL[key] = (I, scale)
+    return _MULTI_FULL[key]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_multi_species_full_size_subset(precision):
+    """The two-species workload at its stated size: 256 nodes per species, AA->BB / AA->AAA / AA->AABB at strides
+    4 / 2 / 1 with N = 2^16 / 2^18 / 2^20 (2304 items, one batched launch per iteration, two iterations on the uniform
+    maps); the first 16 items of each process/species/side/term against the oracle at the full sample counts."""
+    bm = _bm()
+    w = wl.w_multi(nitn=2)
+    say("multi-species full size precision=%d" % precision)
+    ctx = bm.from_workload(w)
+    C, S = ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, precision=precision, freeze_maps=1))
+    res = ctx.item_results(2)
+    assert len(res["uid"]) == 2304
+    pick = _first_items_per_side(res["uid"], 16)
+    I, scale = _multi_full_oracle(res["uid"][pick])
+    rel_own = np.max(np.abs(res["I_it"][pick] - I) / np.where(I != 0, np.abs(I), 1.0))
+    say("multi full size precision=%d: max error relative to each item's own |I| %.3e" % (precision, rel_own))
+    assert_items_close(res["I_it"][pick], I, TOL[precision], "I_it", scale=scale)
+
+
+def test_graph_100_steps_equals_eager():
+    """One hundred Heun steps of the two-species workload (reduced N) captured in a HIP graph equal one hundred eager
+    steps bitwise (f of both species, the time)."""
+    import torch
+    bm = _bm()
+    w = wl.w_multi(n_grid=32, N=(1 << 10, 1 << 10, 1 << 10), nitn=2)
+    opts = bm.default_opts(seed=21, epoch=0, precision=1)
+    eager = bm.from_workload(w)
+    for k in range(100):
+        opts.epoch = 2 * k
+        eager.step(1, -1.0, 0.3, 1.0, opts)
+    side = torch.cuda.Stream()
+    g = bm.from_workload(w, stream=side)
+    opts.epoch = 0
+    g.graph_capture_steps(100, 1, -1.0, 0.3, 1.0, opts)
+    g.graph_replay()
+    t, _ = g.graph_status()
+    say("100 captured steps: t = %.6g (eager %.6g)" % (t, eager.get_time()))
+    assert t == eager.get_time()
+    for a in range(2):
+        assert np.array_equal(g.get_f(a, 32), eager.get_f(a, 32))
+
+
 # ------------------------------------------------------------------------------------------------ steps
 @pytest.mark.parametrize("method,interp", [(0, wl.INTERP_LINLOG), (1, wl.INTERP_LINLOG), (1, wl.INTERP_SPLINE),
                                            (1, wl.INTERP_EQEXACT)])
