@@ -107,6 +107,8 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(World), C.c_int, C.c_double, C.c_double, C.c_double, C.c_int64, C.c_int,
                                C.c_uint64, C.c_uint32, C.c_int, dp, dp, C.c_int]
         L.orc_item_dims.argtypes = [C.POINTER(World), C.POINTER(Item)]
+        L.orc_items_sensitivity.argtypes = [C.c_void_p, C.c_int, C.POINTER(Item), C.c_int64, C.c_int, C.c_int,
+                                            C.c_uint64, C.c_uint32, dp, dp, dp, C.c_int]
         L.orc_adapt_dim.argtypes = [dp, C.c_int, dp, dp, C.c_double]
         L.orc_adapt_dim.restype = None
         L.orc_collision_exact22_all.argtypes = [C.POINTER(World), dp, dp]
@@ -290,6 +292,19 @@ class OracleWorld:
         rc = lib().orc_run_items(C.byref(self.world), n_items, items, N, first_iter, nitn, seed, epoch, int(adapt),
                                  _dp(maps), _dp(I_it), _dp(V_it), _dp(Ib), _dp(sg), threads)
         return rc, dict(I_it=I_it, V_it=V_it, Ibar=Ib, sigma=sg, maps=maps)
+
+    def sensitivity(self, items, n_items, N, nitn, seed=0, epoch=0, maps=None, first_iter=0, threads=0):
+        """Per item and iteration on fixed maps (uniform if None): (B1, B2), the first-order bounds of another correct
+        FP64 evaluation's difference in I and V per unit of relative rounding of the energies."""
+        if maps is None:
+            maps = np.stack([self.map_uniform(items[i], self.pr[items[i].proc].n_bins) for i in range(n_items)])
+        maps = np.ascontiguousarray(maps, dtype=np.float64)
+        B1 = np.zeros((n_items, nitn))
+        B2 = np.zeros((n_items, nitn))
+        rc = lib().orc_items_sensitivity(C.byref(self.world), n_items, items, N, first_iter, nitn, seed, epoch,
+                                         _dp(maps), _dp(B1), _dp(B2), threads)
+        assert rc == 0, rc
+        return B1, B2
 
     def combine(self, items, n_items, Ibar, sigma, species):
         n = self.sp[species].n_grid

@@ -567,11 +567,20 @@ double orc_width_control(const orc_process* P, int n, const double* Ibar, const 
  *   gain = prod_{opposite side} f * prod_{observed side} (1 + eta f)
  *   loss = prod_{observed side} f * prod_{opposite side} (1 + eta f)       (Sec. II.C, the C_2 / C_3 lists)
  * Points with any E_i below the cut get weight 0 (Appendix A). */
-static double item_integrand(const item_ctx* c, const double* x) {
+static double item_point(const item_ctx* c, const double* x, double* sens);
+
+static double item_integrand(const item_ctx* c, const double* x) { return item_point(c, x, NULL); }
+
+/* The same weight; with sens != NULL also the point's sensitivity to rounding in the energies,
+ * (|E_in - E_out| / sigma_E) (sum_i E_i / sigma_E): an absolute change e of E_in - E_out moves the Gaussian factor
+ * by a relative (|E_in - E_out| / sigma_E^2) e, and two correct FP64 evaluations of the energies differ by e of a
+ * few ulps of sum_i E_i. */
+static double item_point(const item_ctx* c, const double* x, double* sens) {
   const int n = c->n, n_in = c->n_in;
   const double a = c->a;
   double px[ORC_MAXN], py[ORC_MAXN], pz[ORC_MAXN], E[ORC_MAXN] = {0}, f[ORC_MAXN] = {0};
   double jac = 1.0;
+  if (sens) *sens = 0.0;
   /* observed particle on the z axis, physical momentum q/a */
   px[c->i_obs] = 0.0;
   py[c->i_obs] = 0.0;
@@ -616,6 +625,11 @@ static double item_integrand(const item_ctx* c, const double* x) {
   for (int i = 0; i < n; ++i) dE += (i < n_in) ? E[i] : -E[i];
   const double sig = orc_point_width(c->P, n, E);
   double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
+  if (sens) {
+    double sumE = 0.0;
+    for (int i = 0; i < n; ++i) sumE += E[i];
+    *sens = (fabs(dE) / sig) * (sumE / sig);
+  }
   /* distribution values */
   for (int i = 0; i < n; ++i) {
     if (i == c->i_obs) {
@@ -923,6 +937,70 @@ int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, i
     *sigma = 0.0;
   }
   return ORC_OK;
+}
+
+/* Rounding sensitivity of the plain-Vegas estimate of one item over iterations first_iter .. + nitn - 1 on a fixed
+ * map (no adaptation), from the same samples as orc_item_vegas: per iteration
+ *   B1 = (1/N) sum_n |W_n| s_n,   B2 = (2 / (N (N - 1))) sum_n W_n^2 s_n,
+ * with s_n the point's sensitivity (item_point).  If another correct FP64 evaluation moves each sample's
+ * E_in - E_out by at most c eps sum_i E_i, its I differs by at most c eps B1 (first order) and its V by about
+ * c eps B2.  Test infrastructure for the tolerance of GPU parity; not part of the estimator. */
+int orc_item_sensitivity(const orc_world* w, const orc_item* it, int64_t N, int first_iter, int nitn, uint64_t seed,
+                         uint32_t epoch, const double* map, double* B1, double* B2) {
+  double fits[4 * ORC_MAXSPECIES];
+  int rc = orc_fits_all(w, w->t, fits);
+  if (rc) return rc;
+  item_ctx c;
+  rc = item_setup(&c, w, it, w->t, fits);
+  if (rc) return rc;
+  if (c.P->vegas_plus) return ORC_EINVAL;
+  const int D = 3 * c.n_int, nb = c.P->n_bins;
+  double y[ORC_MAXD], x[ORC_MAXD];
+  for (int itn = 0; itn < nitn; ++itn) {
+    long double b1 = 0.0L, b2 = 0.0L;
+    for (int64_t s = 0; s < N; ++s) {
+      orc_sample_uniforms(seed, it->uid, epoch, first_iter + itn, s, D, y);
+      double J = 1.0;
+      for (int d = 0; d < D; ++d) {
+        double yn = y[d] * (double)nb;
+        int j = (int)floor(yn);
+        if (j > nb - 1) j = nb - 1;
+        double del = yn - (double)j;
+        double e0 = map[d * (nb + 1) + j], e1 = map[d * (nb + 1) + j + 1];
+        x[d] = e0 + (e1 - e0) * del;
+        J *= (double)nb * (e1 - e0);
+      }
+      double sn = 0.0;
+      const double W = J * item_point(&c, x, &sn);
+      b1 += (long double)(fabs(W) * sn);
+      b2 += (long double)(W * W * sn);
+    }
+    B1[itn] = (double)(b1 / (long double)N);
+    B2[itn] = (double)(2.0L * b2 / ((long double)N * (long double)(N - 1)));
+  }
+  return ORC_OK;
+}
+
+/* orc_item_sensitivity for n_items items (OpenMP over items); maps: n_items x ORC_MAP_STRIDE(nb), B1, B2:
+ * n_items x nitn. */
+int orc_items_sensitivity(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
+                          uint64_t seed, uint32_t epoch, const double* maps, double* B1, double* B2, int n_threads) {
+  int err = 0;
+#ifdef _OPENMP
+  if (n_threads > 0) omp_set_num_threads(n_threads);
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int i = 0; i < n_items; ++i) {
+    const orc_process* P = &w->procs[items[i].proc];
+    int r = orc_item_sensitivity(w, &items[i], N, first_iter, nitn, seed, epoch,
+                                 &maps[(size_t)i * ORC_MAP_STRIDE(P->n_bins)], &B1[(size_t)i * nitn],
+                                 &B2[(size_t)i * nitn]);
+    if (r) {
+#pragma omp atomic write
+      err = r;
+    }
+  }
+  return err;
 }
 
 /* Runs every item of `items` (OpenMP over items).  maps: n_items x ORC_MAP_STRIDE(nb) doubles (in/out;

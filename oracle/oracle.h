@@ -134,6 +134,13 @@ int orc_vplus_strata(int64_t N, int D);
 int orc_item_vegas(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int first_iter, int nitn,
                    uint64_t seed, uint32_t epoch, int adapt, double* map, double* I_it, double* V_it, double* Ibar,
                    double* sigma);
+/* Per iteration on a fixed map: B1 = (1/N) sum |W_n| s_n and B2 = (2/(N(N-1))) sum W_n^2 s_n, s_n = (|dE|/sigma_E)
+ * (sum E / sigma_E) the sample's sensitivity to rounding in the energies (bounds of another FP64 evaluation's
+ * difference in I and V per unit of relative energy rounding). */
+int orc_item_sensitivity(const orc_world* w, const orc_item* it, int64_t N, int first_iter, int nitn, uint64_t seed,
+                         uint32_t epoch, const double* map, double* B1, double* B2);
+int orc_items_sensitivity(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
+                          uint64_t seed, uint32_t epoch, const double* maps, double* B1, double* B2, int n_threads);
 int orc_run_items(const orc_world* w, int n_items, const orc_item* items, int64_t N, int first_iter, int nitn,
                   uint64_t seed, uint32_t epoch, int adapt, double* maps, double* I_it, double* V_it, double* Ibar,
                   double* sigma, int n_threads);

@@ -3,7 +3,7 @@ oracle, through the C-ABI."""
 import numpy as np
 import pytest
 
-from gpu_util import TOL, assert_items_close, gpu_available, item_scale, say
+from gpu_util import TOL, assert_items_close, check_fp64_items, gpu_available, item_scale, say
 from oracle import binding as ob
 from paper_2603_28848_amd import workloads as wl
 
@@ -57,7 +57,10 @@ def test_rel_width_frozen_maps_parity(precision, which):
     rc, r = ow.run_items(items, n, N, nitn, seed=2, epoch=1, adapt=False)
     assert rc == 0
     tol = TOL[precision]
-    assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
+    if precision == 0:
+        check_fp64_items(ow, items, n, res, r, N, nitn, seed=2, epoch=1)
+    else:
+        assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
     Co, So = ow.combine(items, n, r["Ibar"], r["sigma"], 0)
     scale = np.zeros(len(C))
     for i in range(n):
@@ -87,7 +90,7 @@ def test_width_controller_follows_the_oracle(direction):
         items, n = _oracle_items(ow, res["uid"])
         rc, r = ow.run_items(items, n, N, nitn, seed=4, epoch=call, adapt=False)
         assert rc == 0
-        assert_items_close(res["I_it"], r["I_it"], TOL[0], "I_it", scale=item_scale(items, n, r["Ibar"]))
+        check_fp64_items(ow, items, n, res, r, N, nitn, seed=4, epoch=call)
         w_or = ow.width_control(items, n, r["Ibar"], r["sigma"], 0)
         w_gpu = ctx.get_width(0)
         assert w_gpu == w_or, (call, w_gpu, w_or)
