@@ -18,7 +18,8 @@
  *     (BMC_MEM_DEVICE) memory.  Device pointers are used asynchronously on the context's stream and must
  *     stay valid until the stream reaches that point; calls that return host results synchronise the stream.
  *   * The library allocates no device memory of its own: all device state (tables, Vegas maps, partial
- *     sums, results) lives in one workspace the caller allocates and binds (bmc_workspace_query / _bind).
+ *     sums, results) lives in one workspace the caller allocates and binds (bmc_workspace_query / _bind).  The one
+ *     exception is a static 64 MiB array per GPU that only bmc_collision_noalloc uses for its per-call scratch.
  *   * Results depend only on (inputs, seed, epoch, iteration indices, Vegas maps) and the launch mode; they do not
  *     depend on the launch tuning or on other items in the same call.  The batched and per-grid-point launch modes
  *     group the second pass's sums differently (4 and 32 groups per item), so for the same maps their results
@@ -230,6 +231,19 @@ int bmc_plan_size(bmc_ctx* ctx, int process, int species, const bmc_run_opts* op
  * the context (integrator reuse); maps start uniform. */
 int bmc_collision(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
                   double* sigma_out, size_t n_out, int mem);
+
+/* For callers that cannot allocate device memory at call time (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same evaluation, outputs and results as bmc_collision with the same
+ * context state and options, but its per-call scratch (item records, task lists, screening lists, bin counts,
+ * second-pass records, per-iteration estimates, slot sums, gather tables, output staging) lives in a static device
+ * array of 64 MiB that the library holds on each GPU until the process ends, not in the bound workspace (which
+ * still holds the persistent state: f, maps, time).  Calls no hipMalloc.  A call whose scratch exceeds 64 MiB
+ * returns BMC_ENOMEM (the batched 2<->3 workload of 128 nodes x 2^18 samples fits; per-grid-point launches reserve
+ * 8x more second-pass records).  Every call on one GPU shares the array, and the call synchronises the context's
+ * stream before returning, so calls must not overlap on one GPU (concurrent calls from several threads or
+ * contexts on the same GPU race).  bmc_item_results keeps reporting the last bmc_collision, not this call. */
+int bmc_collision_noalloc(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
+                          double* sigma_out, size_t n_out, int mem);
 
 /* Exact-delta 2->2 path (Sec. IV's two-dimensional reduction; Appendix B): the same outputs as bmc_collision for
  * the same selection and options, computed without Monte Carlo and without the Gaussian: per item, the integral

@@ -67,6 +67,8 @@ _SIGS = {
     "bmc_default_process_params": [C.POINTER(ProcessParams)],
     "bmc_set_coupling": [C.c_void_p, C.c_int, C.c_double],
     "bmc_set_interp": [C.c_void_p, C.c_int, C.c_int],
+    "bmc_collision_noalloc": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.c_void_p, C.c_void_p, C.c_size_t,
+                              C.c_int],
     "bmc_collision_exact22": [C.c_void_p, C.c_int, C.c_int, C.POINTER(RunOpts), C.c_void_p, C.c_void_p, C.c_size_t,
                               C.c_int],
     "bmc_get_width": [C.c_void_p, C.c_int, C.POINTER(C.c_double)],
@@ -290,6 +292,17 @@ class Context:
             return out, sigma
         Cv, S = np.zeros(no), np.zeros(no)
         self._check(lib().bmc_collision(self.h, process, species, C.byref(opts), _ptr(Cv), _ptr(S), no, MEM_HOST))
+        return Cv, S
+
+    def collision_noalloc(self, process=-1, species=-1, opts: Optional[RunOpts] = None):
+        """C and sigma (host arrays) from the allocation-free entry point: per-call scratch in the library's static
+        device array; the bound workspace holds only the persistent state."""
+        opts = opts or default_opts()
+        ni, no = self.plan_size(process, species, opts)
+        self.ensure_workspace(opts.n_samples, opts.n_iter)
+        Cv, S = np.zeros(no), np.zeros(no)
+        self._check(lib().bmc_collision_noalloc(self.h, process, species, C.byref(opts), _ptr(Cv), _ptr(S), no,
+                                                MEM_HOST))
         return Cv, S
 
     def collision_exact22(self, process=-1, species=-1, opts: Optional[RunOpts] = None, eval_q=None):

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -20,12 +21,37 @@
 
 using namespace bmc;
 
+// The allocation-free evaluation (bmc_collision_noalloc) takes its per-call scratch from a static device array of
+// kStaticScratchBytes, one per GPU, held until the process ends.  In host code the array's name is not a device
+// address: the address of each GPU's copy comes from hipGetSymbolAddress (g_scratch_ptr below), resolved once per
+// device when a context is created there.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Device address of `scratch` on `device` (the current device), resolved on the first call for that device.
+hipError_t resolve_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = p;
+  return hipSuccess;
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kSlotDoubles = kMaxD * (kMaxBins + 1);
 // FP32 integrand: bytes of in-shell lists one screening launch may fill (larger batches run in slices)
 constexpr size_t kListCapBytes = size_t(1) << 30;
+// Screening lists of one launch of the allocation-free evaluation: capped lower so that its launches are sliced to fit
+// the static scratch.
+constexpr size_t kStaticListCapBytes = size_t(16) << 20;
 // Second pass: an item's units form groups, each one task of the pass with its own record.  A batched launch has
 // many items and gives each few groups (every group pays for its barriers, histogram clear and record); a
 // per-grid-point launch has a handful of items and needs many groups to fill the device.  Both depend on the item
@@ -49,10 +75,11 @@ int vplus_strata(int64_t N, int D) {
 // Units per group for at most `groups` groups, and the number of groups that makes.
 int shell_units_for(int64_t n_units, int groups) { return std::max(1, (int)((n_units + groups - 1) / groups)); }
 int64_t shell_groups(int64_t n_units, int su) { return (n_units + su - 1) / su; }
-// Records an item reserves: enough for either launch's grouping.
-int64_t shell_records(int64_t n_units) {
-  return std::max(shell_groups(n_units, shell_units_for(n_units, kShellGroupsBatched)),
-                  shell_groups(n_units, shell_units_for(n_units, kShellGroupsPlain)));
+// Records an item reserves: enough for either launch's grouping, or (launch >= 0) for that launch mode's only.
+int64_t shell_records(int64_t n_units, int launch = -1) {
+  const int64_t b = shell_groups(n_units, shell_units_for(n_units, kShellGroupsBatched));
+  const int64_t p = shell_groups(n_units, shell_units_for(n_units, kShellGroupsPlain));
+  return launch == BMC_LAUNCH_BATCHED ? b : (launch == BMC_LAUNCH_PLAIN ? p : std::max(b, p));
 }
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
@@ -149,6 +176,7 @@ struct Plan {
   int* d_new = nullptr;
   size_t scratch_bytes = 0;
   bool uploaded = false;
+  bool in_static = false;  // scratch in the library's static device array (bmc_collision_noalloc)
 };
 
 }  // namespace
@@ -419,7 +447,11 @@ struct PlanKey {
 
 constexpr uint32_t kCustomBase = 1u << 17;  // identifier index of the first evaluation point off the grid
 
-int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
+// scratch_base: where the plan's per-call scratch starts (nullptr: after the persistent part of the bound workspace);
+// list_cap: bytes of screening lists one launch may fill; launch: the launch mode the second-pass records are
+// reserved for (-1: either).
+int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullptr,
+               size_t list_cap = kListCapBytes, int launch = -1) {
   Plan Q;
   Q.process = k.process;
   Q.species = k.species;
@@ -498,7 +530,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
             it.shell_off = shell;
             it.shell_units = shell_units_for(it.n_units, kShellGroupsBatched);
             it.shell_units_p = shell_units_for(it.n_units, kShellGroupsPlain);
-            shell += shell_records(it.n_units) * (2 + D * nb);
+            shell += shell_records(it.n_units, launch) * (2 + D * nb);
             it.res_off = res++;
             it.sign = (!it.net && term == 1) ? -1 : 1;
             it.coupling2 = Pr.prm.coupling * Pr.prm.coupling;
@@ -662,7 +694,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
       pmin = std::max<int64_t>(pmin, Q.plain_node_begin[g + 1] - Q.plain_node_begin[g]);
     Q.list_stride = umax;
     Q.list_pos = std::min<int64_t>((int64_t)Q.tasks_batched.size(),
-                                   std::max<int64_t>(pmin, (int64_t)(kListCapBytes / (2 * (size_t)umax))));
+                                   std::max<int64_t>(pmin, (int64_t)(list_cap / (2 * (size_t)umax))));
     // slices: whole items in batched order, at most list_pos task positions each
     int tb = 0, sb = 0;
     for (size_t k = 0; k < order.size(); ++k) {
@@ -740,7 +772,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P) {
                o_nh = take(4 * (size_t)Q.vp_hc), o_hoff = take(8 * (size_t)Q.vp_hoffs),
                o_vS1 = take(8 * (size_t)Q.vp_hc), o_vS2 = take(8 * (size_t)Q.vp_hc), o_vrec = take(8 * (size_t)Q.vp_recd);
   Q.scratch_bytes = s;
-  char* base = c->ws ? c->ws + c->persist_bytes : nullptr;
+  char* base = scratch_base ? scratch_base : (c->ws ? c->ws + c->persist_bytes : nullptr);
+  Q.in_static = scratch_base != nullptr;
   if (base) {
     Q.d_items = reinterpret_cast<ItemRec*>(base + o_items);
     Q.d_tb = reinterpret_cast<Task*>(base + o_tb);
@@ -859,7 +892,7 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
 }
 
 int upload_plan(bmc_ctx* c, Plan& P) {
-  if (c->persist_bytes + P.scratch_bytes > c->ws_bytes)
+  if (!P.in_static && c->persist_bytes + P.scratch_bytes > c->ws_bytes)
     return fail(c, BMC_ENOMEM, "workspace too small for this call: need " +
                                    std::to_string(c->persist_bytes + P.scratch_bytes) + " bytes");
   hipStream_t s = c->stream;
@@ -1090,6 +1123,10 @@ int bmc_create(bmc_ctx** out, int device, void* hip_stream) {
   c->device = device;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
   if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    return BMC_EHIP;
+  }
+  if (device >= kMaxDevices || resolve_scratch(device) != hipSuccess) {
     delete c;
     return BMC_EHIP;
   }
@@ -1456,6 +1493,37 @@ int bmc_collision(bmc_ctx* c, int process, int species, const bmc_run_opts* o, d
   HIPCHK(c, hipMemcpyAsync(C_out, P.d_out_C, 8 * n_out, kind, c->stream));
   if (sigma_out) HIPCHK(c, hipMemcpyAsync(sigma_out, P.d_out_S, 8 * n_out, kind, c->stream));
   return finish_check(c);
+}
+
+int bmc_collision_noalloc(bmc_ctx* c, int process, int species, const bmc_run_opts* o, double* C_out,
+                          double* sigma_out, size_t n_out, int mem) {
+  if (!c || !C_out) return BMC_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  rc = check_ready(c);
+  if (rc) return rc;
+  HIPCHK(c, hipSetDevice(c->device));
+  char* base = static_cast<char*>(g_scratch_ptr[c->device]);
+  if (!base) return fail(c, BMC_ESTATE, "static scratch not resolved for this device");
+  // the array is shared by every call on this GPU: the plan is built and uploaded afresh each time
+  Plan P;
+  rc = build_plan(c, plan_key(process, species, o), &P, base, kStaticListCapBytes, o->launch);
+  if (rc) return rc;
+  if (P.scratch_bytes > kStaticScratchBytes)
+    return fail(c, BMC_ENOMEM, "the call needs " + std::to_string(P.scratch_bytes) +
+                                   " bytes of scratch; the allocation-free evaluation holds " +
+                                   std::to_string(kStaticScratchBytes));
+  if ((size_t)P.n_out != n_out) return fail(c, BMC_EINVAL, "n_out does not match the plan (" + std::to_string(P.n_out) + ")");
+  if (o->first_iter + P.n_iter_max > kMaxIter) return fail(c, BMC_EINVAL, "first_iter + n_iter > 64");
+  rc = upload_plan(c, P);  // also zeroes the bin counts
+  if (rc) return rc;
+  HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, c->stream));
+  rc = enqueue_eval(c, P, *o, P.d_out_C, P.d_out_S);
+  if (rc) return rc;
+  const hipMemcpyKind kind = mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  HIPCHK(c, hipMemcpyAsync(C_out, P.d_out_C, 8 * n_out, kind, c->stream));
+  if (sigma_out) HIPCHK(c, hipMemcpyAsync(sigma_out, P.d_out_S, 8 * n_out, kind, c->stream));
+  return finish_check(c);  // synchronises the stream: the scratch is free for the next call when this returns
 }
 
 int bmc_collision_exact22(bmc_ctx* c, int process, int species, const bmc_run_opts* o, double* C_out,
