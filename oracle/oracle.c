@@ -171,36 +171,36 @@ int orc_fit(const orc_species* s, double a, double t, double fit[4]) {
  * spline is A f_j + B f_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) h_j^2 / 6 with B = (q - q_j) / h_j, A = 1 - B.
  * Conditions: S' continuous at q_1 .. q_{n-2} (rows 1 .. n-2); the third derivative continuous at q_1 (row 0) and
  * at q_{n-2} (row n-1).  The n x n system is solved by Gaussian elimination with partial pivoting. */
-int orc_spline_second_derivatives(int n, const double* q, const double* f, double* M) {
-  if (n < 4) return ORC_EINVAL;
-  double* A = (double*)calloc((size_t)n * (size_t)(n + 1), sizeof(double));  /* augmented rows of n + 1 */
-  if (!A) return ORC_ENOMEM;
-#define AE(r, c) A[(size_t)(r) * (size_t)(n + 1) + (size_t)(c)]
+/* The matrix K of the spline conditions (row stride ld): K M = r(f), where r_j is the jump of the secant slopes at
+ * interior node j and r_0 = r_{n-1} = 0 (the not-a-knot rows). */
+static void spline_matrix(int n, const double* q, double* A, size_t ld) {
+#define KE(r, c) A[(size_t)(r) * ld + (size_t)(c)]
   for (int j = 1; j < n - 1; ++j) {
     const double hl = q[j] - q[j - 1], hr = q[j + 1] - q[j];
-    AE(j, j - 1) = hl / 6.0;
-    AE(j, j) = (hl + hr) / 3.0;
-    AE(j, j + 1) = hr / 6.0;
-    AE(j, n) = (f[j + 1] - f[j]) / hr - (f[j] - f[j - 1]) / hl;
+    KE(j, j - 1) = hl / 6.0;
+    KE(j, j) = (hl + hr) / 3.0;
+    KE(j, j + 1) = hr / 6.0;
   }
-  {
-    const double h0 = q[1] - q[0], h1 = q[2] - q[1];
-    AE(0, 0) = -1.0 / h0;
-    AE(0, 1) = 1.0 / h0 + 1.0 / h1;
-    AE(0, 2) = -1.0 / h1;
-    const double ha = q[n - 2] - q[n - 3], hb = q[n - 1] - q[n - 2];
-    AE(n - 1, n - 3) = -1.0 / ha;
-    AE(n - 1, n - 2) = 1.0 / ha + 1.0 / hb;
-    AE(n - 1, n - 1) = -1.0 / hb;
-  }
+  const double h0 = q[1] - q[0], h1 = q[2] - q[1];
+  KE(0, 0) = -1.0 / h0;
+  KE(0, 1) = 1.0 / h0 + 1.0 / h1;
+  KE(0, 2) = -1.0 / h1;
+  const double ha = q[n - 2] - q[n - 3], hb = q[n - 1] - q[n - 2];
+  KE(n - 1, n - 3) = -1.0 / ha;
+  KE(n - 1, n - 2) = 1.0 / ha + 1.0 / hb;
+  KE(n - 1, n - 1) = -1.0 / hb;
+#undef KE
+}
+
+/* Solves the n x n system whose augmented rows (n + 1 doubles each: the matrix row, then the right-hand side) are in
+ * A, by Gaussian elimination with partial pivoting; A is overwritten. */
+static int dense_solve(int n, double* A, double* x) {
+#define AE(r, c) A[(size_t)(r) * (size_t)(n + 1) + (size_t)(c)]
   for (int col = 0; col < n; ++col) {
     int piv = col;
     for (int r = col + 1; r < n; ++r)
       if (fabs(AE(r, col)) > fabs(AE(piv, col))) piv = r;
-    if (AE(piv, col) == 0.0) {
-      free(A);
-      return ORC_ERANGE;
-    }
+    if (AE(piv, col) == 0.0) return ORC_ERANGE;
     if (piv != col)
       for (int c = 0; c <= n; ++c) {
         double tmp = AE(col, c);
@@ -215,12 +215,56 @@ int orc_spline_second_derivatives(int n, const double* q, const double* f, doubl
   }
   for (int r = n - 1; r >= 0; --r) {
     double acc = AE(r, n);
-    for (int c = r + 1; c < n; ++c) acc -= AE(r, c) * M[c];
-    M[r] = acc / AE(r, r);
+    for (int c = r + 1; c < n; ++c) acc -= AE(r, c) * x[c];
+    x[r] = acc / AE(r, r);
   }
 #undef AE
-  free(A);
   return ORC_OK;
+}
+
+int orc_spline_second_derivatives(int n, const double* q, const double* f, double* M) {
+  if (n < 4) return ORC_EINVAL;
+  double* A = (double*)calloc((size_t)n * (size_t)(n + 1), sizeof(double));  /* augmented rows of n + 1 */
+  if (!A) return ORC_ENOMEM;
+  spline_matrix(n, q, A, (size_t)(n + 1));
+#define AE(r, c) A[(size_t)(r) * (size_t)(n + 1) + (size_t)(c)]
+  for (int j = 1; j < n - 1; ++j) {
+    const double hl = q[j] - q[j - 1], hr = q[j + 1] - q[j];
+    AE(j, n) = (f[j + 1] - f[j]) / hr - (f[j] - f[j - 1]) / hl;
+  }
+#undef AE
+  int rc = dense_solve(n, A, M);
+  free(A);
+  return rc;
+}
+
+/* Adjoint of the spline's second derivatives: given g_j = dL/dM_j, adds dL/df_j = sum_k g_k dM_k/df_j to gf.
+ * M = K^-1 r(f) with r linear in f, so dL/df = r'^T z with K^T z = g; r_j = (f_{j+1} - f_j)/h_j - (f_j - f_{j-1})/h_{j-1}
+ * sends z_j to f_{j+1} (1/h_j), f_j (-1/h_j - 1/h_{j-1}) and f_{j-1} (1/h_{j-1}). */
+int orc_spline_adjoint(int n, const double* q, const double* g, double* gf) {
+  if (n < 4) return ORC_EINVAL;
+  double* K = (double*)calloc((size_t)n * (size_t)n, sizeof(double));
+  double* A = (double*)calloc((size_t)n * (size_t)(n + 1), sizeof(double));
+  double* z = (double*)malloc(sizeof(double) * (size_t)n);
+  if (!K || !A || !z) {
+    free(K); free(A); free(z);
+    return ORC_ENOMEM;
+  }
+  spline_matrix(n, q, K, (size_t)n);
+  for (int r = 0; r < n; ++r) {
+    for (int c = 0; c < n; ++c) A[(size_t)r * (size_t)(n + 1) + (size_t)c] = K[(size_t)c * (size_t)n + (size_t)r];
+    A[(size_t)r * (size_t)(n + 1) + (size_t)n] = g[r];
+  }
+  int rc = dense_solve(n, A, z);
+  if (rc == ORC_OK)
+    for (int j = 1; j < n - 1; ++j) {
+      const double hl = q[j] - q[j - 1], hr = q[j + 1] - q[j];
+      gf[j + 1] += z[j] / hr;
+      gf[j] -= z[j] * (1.0 / hr + 1.0 / hl);
+      gf[j - 1] += z[j] / hl;
+    }
+  free(K); free(A); free(z);
+  return rc;
 }
 
 /* f at comoving momentum q with physical energy E (Sec. III.B):
@@ -1127,11 +1171,13 @@ int orc_collision_all(const orc_world* w, int64_t N, int nitn, uint64_t seed, ui
  * point is sum over its items of mult * sign * I_i.  Given coef_i = v_point * mult * sign, this accumulates
  *   grad_f[s][j] += coef_i/N sum_n dW_n/df_{s,j},   grad_m[s] += coef_i/N sum_n dW_n/dm_s,
  *   grad_lambda[p] += coef_i/N sum_n 2 W_n / lambda_p.
- * f enters W through the statistical factor: the observed leg's table value, linear-in-ln-q interpolation
- * weights of the bracketing nodes, or the extrapolation f = 1/(exp(a + b E) - eta) whose (a, b) are the
- * least-squares line through (E_k, log(1/f_k + eta)) of the end nodes.  m enters through every energy
- * E_i = sqrt(p_i^2 + m^2) of a particle of that species (Gaussian delta, 1/(2 E_i), the extrapolated f of
- * the conserved particle) and through the energies E_k of the fit nodes.
+ * f enters W through the statistical factor: the observed leg's table value, the interpolation rule of the
+ * particle's species between the bracketing nodes (Sec. III.B: linear in ln q; the not-a-knot cubic spline in q,
+ * whose second derivatives depend on every node through the spline conditions; the equilibrium-exact rule, linear
+ * in E for log(1/f + eta)), or the extrapolation f = 1/(exp(a + b E) - eta) whose (a, b) are the least-squares line
+ * through (E_k, log(1/f_k + eta)) of the end nodes.  m enters through every energy E_i = sqrt(p_i^2 + m^2) of a
+ * particle of that species (Gaussian delta, 1/(2 E_i), the extrapolated or equilibrium-exact f) and through the
+ * energies E_k of the fit nodes and of the equilibrium-exact rule's bracketing nodes.
  * ===================================================================================================== */
 
 /* Derivatives of the end-node fit (a, b) of one side: da/dy_k, db/dy_k, da/dE_k, db/dE_k, the node
@@ -1167,8 +1213,8 @@ static void fit_derivatives(const orc_species* s, double a_scale, double m, int 
 
 /* One item: accumulates into grad_f (concatenated species grids, offsets f_off), grad_m, grad_lam. */
 int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int iter, uint64_t seed,
-                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_m,
-                 double* grad_lam) {
+                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_M,
+                 double* grad_m, double* grad_lam) {
   item_ctx c;
   int rc = item_setup(&c, w, it, w->t, fits);
   if (rc) return rc;
@@ -1240,7 +1286,7 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
     double delta = exp(-dE * dE / (2.0 * sig * sig)) / (sig * sqrt(TWO_PI));
     /* f values and where they come from */
     int src[ORC_MAXN], node[ORC_MAXN], eside[ORC_MAXN];
-    double wgt[ORC_MAXN];
+    double wgt[ORC_MAXN], qat[ORC_MAXN];
     for (int i = 0; i < n; ++i) {
       const orc_species* S = c.sp[i];
       double q;
@@ -1252,6 +1298,7 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
       }
       if (i == c.i_cons) q = a * sqrt(px[i] * px[i] + py[i] * py[i] + pz[i] * pz[i]);
       else q = x[3 * kof[i]];
+      qat[i] = q;
       f[i] = orc_f_at(S, c.fit[i], q, E[i]);
       if (q < S->q_min || q > S->q_max) {
         src[i] = 2;
@@ -1309,11 +1356,29 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
       dWdf[i] = Wb * dFdf[i];
       int spc = c.P->sp[i];
       double gsum = cN * dWdf[i];
+      const orc_species* S = c.sp[i];
+      const int j = node[i];
       if (src[i] == 0) {
-        grad_f[f_off[spc] + node[i]] += gsum;
+        grad_f[f_off[spc] + j] += gsum;
+      } else if (src[i] == 1 && S->interp == ORC_INTERP_SPLINE) {
+        /* A f_j + B f_{j+1} + ((A^3 - A) M_j + (B^3 - B) M_{j+1}) h^2/6: the f_j directly, the M_j through grad_M */
+        const double q0 = orc_grid_q(S, j), hq = orc_grid_q(S, j + 1) - q0;
+        const double B = (qat[i] - q0) / hq, A = 1.0 - B;
+        grad_f[f_off[spc] + j] += gsum * A;
+        grad_f[f_off[spc] + j + 1] += gsum * B;
+        grad_M[f_off[spc] + j] += gsum * (A * A * A - A) * hq * hq / 6.0;
+        grad_M[f_off[spc] + j + 1] += gsum * (B * B * B - B) * hq * hq / 6.0;
+      } else if (src[i] == 1 && S->interp == ORC_INTERP_EQEXACT) {
+        /* f = 1/(exp(y) - eta), y = (1 - u) y_j + u y_{j+1}, u = (E - E_j)/(E_{j+1} - E_j), y_k = log(1/f_k + eta):
+         * df/dy = -f (1 + eta f), dy_k/df_k = -1 / (f_k (1 + eta f_k)) */
+        const double u = (E[i] - S->aux[j]) / (S->aux[j + 1] - S->aux[j]);
+        const double dfdy = -f[i] * (1.0 + c.eta[i] * f[i]);
+        const double f0 = S->f[j], f1 = S->f[j + 1];
+        grad_f[f_off[spc] + j] += gsum * dfdy * (1.0 - u) * (-1.0 / (f0 * (1.0 + c.eta[i] * f0)));
+        grad_f[f_off[spc] + j + 1] += gsum * dfdy * u * (-1.0 / (f1 * (1.0 + c.eta[i] * f1)));
       } else if (src[i] == 1) {
-        grad_f[f_off[spc] + node[i]] += gsum * (1.0 - wgt[i]);
-        grad_f[f_off[spc] + node[i] + 1] += gsum * wgt[i];
+        grad_f[f_off[spc] + j] += gsum * (1.0 - wgt[i]);
+        grad_f[f_off[spc] + j + 1] += gsum * wgt[i];
       } else {
         double dfdz = -f[i] * (1.0 + c.eta[i] * f[i]);
         dfit[spc][2 * eside[i]] += gsum * dfdz;
@@ -1328,6 +1393,18 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
       if (src[i] == 2) {
         double b = c.fit[i][2 * eside[i] + 1];
         dWdE += dWdf[i] * (-b * f[i] * (1.0 + c.eta[i] * f[i]));
+      }
+      if (src[i] == 1 && c.sp[i]->interp == ORC_INTERP_EQEXACT) {
+        /* y is linear in E between the node energies E_j = sqrt((q_j/a)^2 + m^2), which move with m too:
+         * du/dE = 1/dE_n, du/dE_j = (u - 1)/dE_n, du/dE_{j+1} = -u/dE_n with dE_n = E_{j+1} - E_j */
+        const orc_species* S = c.sp[i];
+        const int j = node[i];
+        const double Ej = S->aux[j], Ej1 = S->aux[j + 1], dEn = Ej1 - Ej;
+        const double u = (E[i] - Ej) / dEn;
+        const double y0 = log(1.0 / S->f[j] + c.eta[i]), y1 = log(1.0 / S->f[j + 1] + c.eta[i]);
+        const double dfdu = -f[i] * (1.0 + c.eta[i] * f[i]) * (y1 - y0);
+        dWdE += dWdf[i] * dfdu / dEn;
+        grad_m[c.P->sp[i]] += cN * dWdf[i] * dfdu * ((u - 1.0) / dEn * c.m[i] / Ej - u / dEn * c.m[i] / Ej1);
       }
       grad_m[c.P->sp[i]] += cN * dWdE * c.m[i] / E[i];
     }
@@ -1360,9 +1437,7 @@ int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int
 int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
             uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
             int n_threads) {
-  /* the gradient's interpolation chain is written for the linear-in-ln q rule and a constant |M|^2 */
-  for (int s = 0; s < w->n_species; ++s)
-    if (w->species[s].interp != ORC_INTERP_LINLOG) return ORC_EINVAL;
+  /* the gradient's chain is written for a constant |M|^2 */
   for (int p = 0; p < w->n_proc; ++p)
     if (w->procs[p].m2_kind != ORC_M2_CONST) return ORC_EINVAL;
   double fits[4 * ORC_MAXSPECIES];
@@ -1375,6 +1450,8 @@ int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double
     tot += w->species[s].n_grid;
   }
   for (int64_t j = 0; j < tot; ++j) grad_f[j] = 0.0;
+  double* grad_M = (double*)calloc((size_t)(tot > 0 ? tot : 1), sizeof(double));  /* dL/dM_j of spline species */
+  if (!grad_M) return ORC_ENOMEM;
   for (int s = 0; s < w->n_species; ++s) grad_m[s] = 0.0;
   for (int p = 0; p < w->n_proc; ++p) grad_lam[p] = 0.0;
 #ifdef _OPENMP
@@ -1384,6 +1461,7 @@ int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double
 #pragma omp parallel
   {
     double* gf = (double*)calloc((size_t)tot, sizeof(double));
+    double* gM = (double*)calloc((size_t)tot, sizeof(double));
     double gm[ORC_MAXSPECIES] = {0}, gl[256] = {0};
 #pragma omp for schedule(dynamic, 1)
     for (int i = 0; i < n_items; ++i) {
@@ -1392,7 +1470,7 @@ int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double
       double* mp = (double*)malloc(sizeof(double) * stride);
       memcpy(mp, &maps[(size_t)i * stride], sizeof(double) * stride);
       if (isnan(mp[0])) orc_map_uniform(w, &items[i], mp);
-      int r = orc_item_vjp(w, &items[i], fits, N, iter, seed, epoch, mp, coef[i], f_off, gf, gm, gl);
+      int r = orc_item_vjp(w, &items[i], fits, N, iter, seed, epoch, mp, coef[i], f_off, gf, gM, gm, gl);
       free(mp);
       if (r) {
 #pragma omp atomic write
@@ -1402,11 +1480,23 @@ int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double
 #pragma omp critical
     {
       for (int64_t j = 0; j < tot; ++j) grad_f[j] += gf[j];
+      for (int64_t j = 0; j < tot; ++j) grad_M[j] += gM[j];
       for (int s = 0; s < w->n_species; ++s) grad_m[s] += gm[s];
       for (int p = 0; p < w->n_proc && p < 256; ++p) grad_lam[p] += gl[p];
     }
     free(gf);
+    free(gM);
   }
+  /* the spline's second derivatives depend on every node of their species */
+  for (int s = 0; s < w->n_species && !err; ++s) {
+    const orc_species* S = &w->species[s];
+    if (S->interp != ORC_INTERP_SPLINE) continue;
+    double* q = (double*)malloc(sizeof(double) * (size_t)S->n_grid);
+    for (int j = 0; j < S->n_grid; ++j) q[j] = orc_grid_q(S, j);
+    err = orc_spline_adjoint(S->n_grid, q, &grad_M[f_off[s]], &grad_f[f_off[s]]);
+    free(q);
+  }
+  free(grad_M);
   return err;
 }
 

@@ -163,9 +163,14 @@ double orc_m2_factor(const orc_process* P, const double* E, const double* px, co
 /* The width controller: the width after an evaluation whose items of process P had estimates Ibar[i] and Monte
  * Carlo errors sigma[i] (i < n), starting from width w. */
 double orc_width_control(const orc_process* P, int n, const double* Ibar, const double* sigma, double w);
+/* One item's share of the vector-Jacobian product (grad_M: the gradient with respect to the second derivatives
+ * M_j of spline species, on their nodes, taken to f by orc_spline_adjoint). */
 int orc_item_vjp(const orc_world* w, const orc_item* it, const double* fits, int64_t N, int iter, uint64_t seed,
-                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_m,
-                 double* grad_lam);
+                 uint32_t epoch, const double* map, double coef, const int64_t* f_off, double* grad_f, double* grad_M,
+                 double* grad_m, double* grad_lam);
+/* Adds to gf (n nodes) the gradient with respect to f of a loss whose gradient with respect to the not-a-knot
+ * spline's second derivatives M_j on the nodes q is g. */
+int orc_spline_adjoint(int n, const double* q, const double* g, double* gf);
 int orc_vjp(const orc_world* w, int n_items, const orc_item* items, const double* coef, int64_t N, int iter,
             uint64_t seed, uint32_t epoch, const double* maps, double* grad_f, double* grad_m, double* grad_lam,
             int n_threads);
