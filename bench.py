@@ -22,11 +22,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3: one VALU lane-op per lane per cycle on 256 CUs
-# HBM bytes per sample phase (screening + in-shell kernels) of this workload, from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE counters scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernels;
-# None once they change.
-TRAFFIC_BYTES_PER_PHASE = 33.3e6 + 81.8e6
+# Peaks of the VALU in operations per second (one op = one lane's add, mul, fma, compare, logic or integer op):
+# 256 CUs x 4 SIMDs x 2.4 GHz x lanes per cycle, 32 for FP32/INT32 (the published 157.3 TFLOP/s vector FP32, counting
+# an fma as 2 flops) and 16 for FP64 (78.6 TFLOP/s).
+PEAK_FP32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.6
+PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3
+# HBM bytes per launch of the screening kernel on this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
+# scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernel; None once it changes.
+TRAFFIC_BYTES_SCREEN = None
 TIMING_EVERY = 7
 
 
@@ -49,25 +52,44 @@ def ops_weight(n_int: int) -> int:
     return 2 * D + 2 * n_int + 8 * (n_int + 1) + 2 + 3 * (n_int + 2) + 2 * (n_int + 2) + 4 + 5 + 2 * D
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, threads):
-    """The CPU oracle (as it stands) on a bounded sample of the same items."""
+    """The CPU oracle (as it stands) on a bounded sample of the same items, on `threads` threads (OpenMP over items),
+    and its single-thread rate on a smaller sample."""
     from oracle import binding as ob
     ow = ob.OracleWorld(w)
     items, n = ow.items()
-    stride = 2  # half the grid nodes: about 15 s of oracle work on 16 cores
-    nodes = set(range(0, 128, stride))
-    keep = [items[i] for i in range(n) if items[i].eval_idx in nodes]
-    arr = (ob.Item * len(keep))(*keep)
     p = w.processes[0]
-    t0 = time.perf_counter()
-    rc, r = ow.run_items(arr, len(keep), p.n_samples, p.n_iter, seed=0, epoch=0, threads=threads)
-    dt = time.perf_counter() - t0
-    assert rc == 0
-    samples = len(keep) * p.n_samples * p.n_iter
+
+    def run(nodes, nitn, th):
+        keep = [items[i] for i in range(n) if items[i].eval_idx in nodes]
+        arr = (ob.Item * len(keep))(*keep)
+        t0 = time.perf_counter()
+        rc, r = ow.run_items(arr, len(keep), p.n_samples, nitn, seed=0, epoch=0, threads=th)
+        dt = time.perf_counter() - t0
+        assert rc == 0
+        return len(keep), len(keep) * p.n_samples * nitn, dt
+
+    stride = 2  # half the grid nodes: about 15 s of oracle work on 16 threads
+    n_items, samples, dt = run(set(range(0, 128, stride)), p.n_iter, threads)
+    n1, s1, dt1 = run(set(range(0, 128, 32)), 1, 1)  # 4 nodes x 4 items, one iteration, one thread
     return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "%d of 512 items (grid nodes 0,%d,...,%d x 2 sides x 2 terms), %d samples x %d iterations "
-                      "each = %.3g samples in %.1f s" % (len(keep), stride, 128 - stride, p.n_samples, p.n_iter,
-                                                         samples, dt)}
+                      "each = %.3g samples in %.1f s" % (n_items, stride, 128 - stride, p.n_samples, p.n_iter,
+                                                         samples, dt),
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread_value": s1 / dt1,
+            "single_thread_sample": "%d items (grid nodes 0,32,64,96), %d samples x 1 iteration = %.3g samples in "
+                                    "%.1f s" % (n1, p.n_samples, s1, dt1)}
 
 
 def config_line(n, args):
@@ -229,7 +251,7 @@ def main():
         ctx.collision(-1, -1, opts)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    kernel_ms, n_launch = ctx.get_timing(reset=True)
+    screen_ms, second_ms, n_launch = ctx.get_kernel_timing(reset=True)
     n_listed = ctx.get_sample_stats(reset=True)
     ctx.set_timing(False)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -265,12 +287,17 @@ def main():
     ok = (sig32 > 0) & (sig64 > 0)
     sigma_ratio = float(np.median(sig32[ok] / sig64[ok]))
 
-    # ---- roofline of the sample phase (screening + second pass) ----
-    avg_launch_s = kernel_ms / max(1, n_launch) / 1e3
+    # ---- roofline of the dominant kernel (the screening pass) and of the second pass ----
+    # a launch = one sample phase (one Vegas iteration of all 512 items): every sample screened once, the listed
+    # ones (in or near the energy shell) evaluated again by the second pass
+    screen_s = screen_ms / max(1, n_launch) / 1e3
+    second_s = second_ms / max(1, n_launch) / 1e3
     samples_per_launch = samples_per_step / p.n_iter
     listed_per_launch = n_listed / (args.steps * p.n_iter)  # the listed samples of every phase of the timed steps
-    ops_launch = ops_common(n_int) * samples_per_launch + ops_weight(n_int) * listed_per_launch
-    achieved = ops_launch / avg_launch_s / 1e12
+    screen_ops = ops_common(n_int) * samples_per_launch
+    second_ops = ops_weight(n_int) * listed_per_launch
+    achieved = screen_ops / screen_s / 1e12
+    achieved_second = second_ops / second_s / 1e12
 
     line = {
         "metric": "2<->3 collision-integrand samples/s (batched FP32-integrand) + speedup vs plain per-grid-point "
@@ -299,18 +326,27 @@ def main():
             "speedup_fp32i_vs_fp64_batched": value / batched64,
             "sigma_ratio_fp32i_over_plain_fp64": sigma_ratio,
             "sigma_ratio_max_dev": float(np.max(np.abs(sig32[ok] / sig64[ok] - 1.0))),
-            "sample_phase_avg_ms": avg_launch_s * 1e3,
+            "sample_phase_avg_ms": (screen_s + second_s) * 1e3,
+            "screen_avg_ms": screen_s * 1e3,
+            "second_pass_avg_ms": second_s * 1e3,
             "sample_phases_timed": n_launch,
             "timed_every": TIMING_EVERY,
         },
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TOPS, "unit": "TOP/s",
-                     "frac": achieved / PEAK_VALU_TOPS, "traffic": TRAFFIC_BYTES_PER_PHASE,
-                     "ops_per_launch": ops_launch, "ops_per_sample": [ops_common(n_int), ops_weight(n_int)],
-                     "listed_fraction": listed_per_launch / samples_per_launch,
-                     "kernels": "k_screen + k_shell per iteration"},
+        "roofline": {"bound": "alu", "kernel": "k_screen (FP32/INT32 screening pass, every sample)",
+                     "achieved": achieved, "peak": PEAK_FP32_TOPS, "unit": "TOP/s",
+                     "frac": achieved / PEAK_FP32_TOPS, "traffic": TRAFFIC_BYTES_SCREEN,
+                     "ops_per_sample": ops_common(n_int), "samples_per_launch": samples_per_launch,
+                     "ops_per_launch": screen_ops, "avg_launch_ms": screen_s * 1e3,
+                     "second_pass": {"kernel": "k_shell (listed samples: FP64 kinematics, FP32 integrand)",
+                                     "achieved": achieved_second, "peak": PEAK_FP64_TOPS, "unit": "TOP/s",
+                                     "frac": achieved_second / PEAK_FP64_TOPS, "ops_per_sample": ops_weight(n_int),
+                                     "samples_per_launch": listed_per_launch,
+                                     "listed_fraction": listed_per_launch / samples_per_launch,
+                                     "avg_launch_ms": second_s * 1e3}},
     }
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        # the host share of one GPU is 16 threads (OMP_NUM_THREADS on the GPU hosts), whatever nproc reports
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0")) or min(16, os.cpu_count() or 1)
         line["cpu_baseline"] = cpu_baseline(w, threads)
     print(json.dumps(line))
     sys.stdout.flush()

@@ -310,11 +310,16 @@ int bmc_vjp(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, co
 
 /* Timing of the sample phase (screening and second pass of one iteration's launch) with HIP events on the context
  * stream (eager launches only; graph replays are not timed): on = 0 off, on = k >= 1 every k-th sample phase
- * (k = 1: all; each timed phase puts two event records between kernels).  BMC_EINVAL for on < 0. */
+ * (k = 1: all; each timed phase records an event before, between and after its two kernels).  BMC_EINVAL for
+ * on < 0. */
 int bmc_set_timing(bmc_ctx* ctx, int on);
 /* Sum of the timed sample-phase durations (ms) and number of timed phases since the last reset;
  * synchronises the stream.  reset != 0 clears the counters after reading. */
 int bmc_get_timing(bmc_ctx* ctx, int reset, double* sample_ms, int* n_launches);
+/* The same timed sample phases split by kernel: the screening pass (from the event before it to the event between the
+ * two kernels) and the second pass (from there to the event after it), summed in ms; synchronises the stream.  reset
+ * != 0 clears every timing sum (bmc_get_timing's too) after reading. */
+int bmc_get_kernel_timing(bmc_ctx* ctx, int reset, double* screen_ms, double* second_ms, int* n_launches);
 /* Number of samples the second pass evaluated (those the screening pass found able to carry a nonzero W: in
  * the energy shell or near it) since the last reset, over all evaluations on the context, graph replays
  * included; synchronises the stream.  reset != 0 clears the counter after reading. */

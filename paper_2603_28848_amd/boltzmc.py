@@ -94,6 +94,8 @@ _SIGS = {
                 C.c_void_p, C.c_int],
     "bmc_set_timing": [C.c_void_p, C.c_int],
     "bmc_get_timing": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)],
+    "bmc_get_kernel_timing": [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                              C.POINTER(C.c_int)],
     "bmc_get_sample_stats": [C.c_void_p, C.c_int, C.POINTER(C.c_int64)],
     "bmc_state_size": [C.c_void_p, C.POINTER(C.c_size_t)],
     "bmc_state_get": [C.c_void_p, C.c_void_p, C.c_size_t],
@@ -383,6 +385,12 @@ class Context:
         ms, n = C.c_double(), C.c_int()
         self._check(lib().bmc_get_timing(self.h, int(reset), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def get_kernel_timing(self, reset=True):
+        """(screening ms, second-pass ms, phases) summed over the timed sample phases."""
+        a, b, n = C.c_double(), C.c_double(), C.c_int()
+        self._check(lib().bmc_get_kernel_timing(self.h, int(reset), C.byref(a), C.byref(b), C.byref(n)))
+        return a.value, b.value, n.value
 
     def state_get(self) -> bytes:
         """Checkpoint: f of every species, the time and epochs, every process's width and every Vegas map, as one

