@@ -870,28 +870,30 @@ size_t scratch_estimate(bmc_ctx* c, int64_t max_samples, int max_iter) {
        2 * align_up(sizeof(ShellTask) * units);
   for (auto& S : c->sp) outs += S.n;
   (void)max_iter;
-  // adjoint records: per unit n_tab * n_max + 12 doubles (n_tab <= 4 tables of at most the largest grid)
+  // adjoint records: per unit n_tab * n_max (twice that with a spline table) + 12 doubles (n_tab <= 4 tables of at
+  // most the largest grid); the spline adjoint's 3 n_f doubles of scratch
   size_t gmax = 0, vjp_part = 0;
   for (auto& S : c->sp) gmax = std::max(gmax, (size_t)S.n);
   for (auto& Pr : c->pr) {
     const int64_t N = std::max<int64_t>(max_samples > 0 ? max_samples : 0, Pr.prm.n_samples);
     const int U = unit_size_for(N);
     const int64_t nu = (N + U - 1) / U;
-    int ntab = 0;
+    int ntab = 0, spl = 0;
     for (size_t a = 0; a < c->sp.size(); ++a) {
       bool used = false;
       for (int i = 0; i < Pr.n_in + Pr.n_out; ++i) used |= Pr.sp[i] == (int)a;
       ntab += used;
+      spl |= used && c->sp[a].interp == BMC_INTERP_SPLINE ? 1 : 0;
     }
     for (size_t a = 0; a < c->sp.size(); ++a) {
       int sides = 0;
       for (int side = 0; side < 2; ++side) sides += multiplicity(Pr, (int)a, side) > 0;
       const size_t ni = (size_t)c->sp[a].n * sides * (Pr.prm.term_mode == BMC_TERMS_NET ? 1 : 2);
-      vjp_part += ni * nu * (ntab * gmax + 12);
+      vjp_part += ni * nu * (ntab * gmax * (1 + spl) + 12);
     }
   }
-  s += align_up(8 * vjp_part) + align_up((sizeof(ItemRec) + 8 * (4 * gmax + 12) + 24) * items) +
-       align_up(8 * (size_t)c->n_f) + 4 * kAlign + 16 * c->pr.size();
+  s += align_up(8 * vjp_part) + align_up((sizeof(ItemRec) + 8 * (8 * gmax + 12) + 24) * items) +
+       align_up(8 * (size_t)c->n_f) + align_up(24 * (size_t)c->n_f) + 4 * kAlign + 16 * c->pr.size();
   s += align_up(sizeof(ItemRec) * items) + 2 * align_up(sizeof(Task) * tasks) + align_up(8 * items) +
        align_up(4 * part) + 2 * align_up(8 * kMaxIter * items) + 2 * align_up(8 * items) +
        align_up(4 * (slots + 1)) + align_up(4 * items) + 2 * align_up(8 * slots) +
@@ -1962,9 +1964,6 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   if (rc) return rc;
   if (o->precision != BMC_FP64) return fail(c, BMC_EUNSUP, "vector-Jacobian products are FP64 only");
   if (o->eval_q) return fail(c, BMC_EUNSUP, "vector-Jacobian products are on the grids only (eval_q must be NULL)");
-  for (auto& S : c->sp)
-    if (S.interp != BMC_INTERP_LINLOG)
-      return fail(c, BMC_EUNSUP, "vector-Jacobian products need the linear-in-ln q interpolation");
   for (auto& Pr : c->pr)
     if (Pr.prm.m2_kind != BMC_M2_CONST || Pr.prm.vegas_plus)
       return fail(c, BMC_EUNSUP, "vector-Jacobian products need a constant |M|^2 and plain Vegas sampling");
@@ -2003,14 +2002,17 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
     auto f = out_of.find((int64_t)it.obs_species * 1000003 + it.eval_idx);
     if (f == out_of.end()) return fail(c, BMC_EINVAL, "item without an output");
     coef[i] = v[f->second] * (double)it.mult * (double)it.sign;
-    int n_max = 0;
-    for (int t = 0; t < it.n_tab; ++t) n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
+    int n_max = 0, spl = 0;
+    for (int t = 0; t < it.n_tab; ++t) {
+      n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
+      spl |= c->sp[it.tab_species[t]].interp == BMC_INTERP_SPLINE ? 1 : 0;
+    }
     rec_nmax[i] = n_max;
-    rec_len[i] = vjp_record_len(it.n_tab, n_max);
+    rec_len[i] = vjp_record_len(it.n_tab, n_max, spl);
     rec_stride = std::max(rec_stride, rec_len[i]);
     it.part_off = part;
     part += (int64_t)it.n_units * rec_len[i];
-    lds = std::max(lds, vjp_lds_bytes(it.D, it.nb, it.n_tab, n_max));
+    lds = std::max(lds, vjp_lds_bytes(it.D, it.nb, it.n_tab, n_max, spl));
   }
   if (lds > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need of the adjoint above 64 KB");
   // scratch after the plan's own region
@@ -2022,7 +2024,8 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   };
   const size_t o_items = take(sizeof(ItemRec) * nI), o_parts = take(8 * (size_t)part),
                o_rec = take(8 * (size_t)rec_stride * nI), o_coef = take(8 * nI), o_len = take(4 * nI),
-               o_nmax = take(4 * nI), o_gf = take(8 * (size_t)c->n_f), o_gm = take(8 * kMaxSpecies),
+               o_nmax = take(4 * nI), o_gf = take(8 * (size_t)c->n_f), o_work = take(8 * 3 * (size_t)c->n_f),
+               o_gm = take(8 * kMaxSpecies),
                o_gl = take(8 * c->pr.size()), o_cp = take(8 * c->pr.size());
   if (off > c->ws_bytes)
     return fail(c, BMC_ENOMEM, "workspace too small for the adjoint: need " + std::to_string(off) + " bytes");
@@ -2034,6 +2037,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   int* d_len = reinterpret_cast<int*>(b + o_len);
   int* d_nmax = reinterpret_cast<int*>(b + o_nmax);
   double* d_gf = reinterpret_cast<double*>(b + o_gf);
+  double* d_work = reinterpret_cast<double*>(b + o_work);
   double* d_gm = reinterpret_cast<double*>(b + o_gm);
   double* d_gl = reinterpret_cast<double*>(b + o_gl);
   double* d_cp = reinterpret_cast<double*>(b + o_cp);
@@ -2066,7 +2070,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   L.seed_hi = (uint32_t)(o->seed >> 32);
   L.nint_mask = P.nint_mask;
   L.precision = BMC_FP64;
-  L.any_interp = 0;  // the adjoint takes the linear rule only
+  L.any_interp = 0;  // (the adjoint kernel reads each table's rule itself)
   L.lds_bytes = lds;
   L.chunk = 1;
   L.shell_list = P.d_list;
@@ -2089,7 +2093,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
     HIPCHK(c, launch_vjp(L, s));
   }
   HIPCHK(c, launch_vjp_finish(d_items, (int)nI, d_coef, d_parts, d_len, d_nmax, d_rec, rec_stride, c->spec(),
-                              (int)c->sp.size(), c->f64(), c->qnode(), c->st(), d_gf, c->n_f, d_gm, d_gl, d_cp,
+                              (int)c->sp.size(), c->f64(), c->qnode(), c->st(), d_gf, c->n_f, d_work, d_gm, d_gl, d_cp,
                               (int)c->pr.size(), s));
   const hipMemcpyKind kind = mem == BMC_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (grad_f) HIPCHK(c, hipMemcpyAsync(grad_f, d_gf, 8 * (size_t)c->n_f, kind, s));

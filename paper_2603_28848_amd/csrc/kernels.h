@@ -126,13 +126,15 @@ int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
 // Adjoint (FP64, frozen maps): per-unit records of the sample derivatives, then per item (times coef/N),
 // then per species node, fits, masses and couplings.
 hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s);
-int vjp_lds_bytes(int D, int nb, int n_tab, int n_max);
-int vjp_record_len(int n_tab, int n_max);
+// spl: 1 if a table of the item is interpolated by the spline (its record then holds the d/dM slots too)
+int vjp_lds_bytes(int D, int nb, int n_tab, int n_max, int spl);
+int vjp_record_len(int n_tab, int n_max, int spl);
+// work: 3 n_f doubles of scratch (the spline adjoint's right-hand sides and elimination rows)
 hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* coef, const double* parts,
                              const int* rec_len, const int* rec_nmax, double* item_rec, int rec_stride,
                              const SpecDev* spec, int n_species, const double* f64, const double* qnode,
-                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
-                             const double* coupling, int n_proc, hipStream_t s);
+                             const DevState* st, double* grad_f, int64_t n_f, double* work, double* grad_m,
+                             double* grad_lam, const double* coupling, int n_proc, hipStream_t s);
 hipError_t launch_next_epoch(DevState* st, hipStream_t s);
 
 // Sets the next evaluation epoch (and optionally the time) on the device.

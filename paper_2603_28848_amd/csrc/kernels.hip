@@ -1373,12 +1373,25 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
 
 // ------------------------------------------------------------------------------------------------------
 // Adjoint of the frozen-map estimator (FP64).  For each sample, W and its partial derivatives with respect to
-// the f values it reads (scattered to the grid through the interpolation weights, or to the extrapolation
-// line (a, b) of the conserved particle's species), the masses of the species of every particle (through
-// E_i in the Gaussian, in 1/(2 E_i) and in the extrapolated f), and the coupling (2 W / lambda) are summed.
-// Per unit record (doubles): n_tab * n_max table gradients, g_obs, d/d(a_lo, b_lo, a_hi, b_hi), d/dm per
-// role (kMaxN), sum W.
-__host__ __device__ inline int vjp_rec_len(int n_tab, int n_max) { return n_tab * n_max + 1 + 4 + kMaxN + 1; }
+// the f values it reads (scattered to the grid through the interpolation rule of the species, or to the
+// extrapolation line (a, b) of the conserved particle's species), the masses of the species of every particle
+// (through E_i in the Gaussian, in 1/(2 E_i), in the extrapolated or equilibrium-exact f, and the node energies of
+// the equilibrium-exact rule), and the coupling (2 W / lambda) are summed.  Table gradients by rule (Sec. III.B):
+// linear in ln q -- d/df_j with weights 1 - w, w; spline -- d/df_j with weights A, B and d/dM_j with weights
+// (A^3 - A) h^2/6, (B^3 - B) h^2/6 (M, the second derivatives, depend on every node; the finish kernel solves the
+// transposed spline system); equilibrium-exact -- d/dy_j of y_j = log(1/f_j + eta) (the gather converts to f_j).
+// Per unit record (doubles): n_tab * n_max table gradients, as many d/dM slots when a table of the item is a
+// spline, then g_obs, d/d(a_lo, b_lo, a_hi, b_hi), d/dm per role (kMaxN), sum W.
+__host__ __device__ inline int vjp_tab_len(int n_tab, int n_max, int spl) { return n_tab * n_max * (spl ? 2 : 1); }
+__host__ __device__ inline int vjp_rec_len(int n_tab, int n_max, int spl) {
+  return vjp_tab_len(n_tab, n_max, spl) + 1 + 4 + kMaxN + 1;
+}
+// 1 if a table the item reads is interpolated by the spline
+__device__ inline int item_spline(const ItemRec& it, const SpecDev* spec) {
+  int spl = 0;
+  for (int k = 0; k < it.n_tab; ++k) spl |= spec[it.tab_species[k]].interp == 1 ? 1 : 0;
+  return spl;
+}
 
 template <int NI>
 __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem) {
@@ -1392,7 +1405,9 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   const int n_tab = it->n_tab;
   int n_max = 0;
   for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
-  // LDS: e, w, sin/cos table, f tables (q, iq, f), per-wave table gradients, reduction scratch
+  const int spl = item_spline(*it, L.spec);
+  // LDS: e, w, sin/cos table, f tables (q, iq, f by rule, as in the forward pass), per-wave table gradients,
+  // reduction scratch
   int o = 0;
   double* sm_e = reinterpret_cast<double*>(smem + o);
   o = align16(o + DN * 8);
@@ -1403,9 +1418,9 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   const int tab_stride = align16(n_max * 24);
   const int off_tab = o;
   o = align16(o + n_tab * tab_stride);
-  const int TG = n_tab * n_max;
+  const int TG = n_tab * n_max, TG2 = vjp_tab_len(n_tab, n_max, spl);
   double* sm_g = reinterpret_cast<double*>(smem + o);
-  o = align16(o + kWaves * TG * 8);
+  o = align16(o + kWaves * TG2 * 8);
   double* sm_red = reinterpret_cast<double*>(smem + o);
   const double* __restrict__ map = L.maps + it->map_off;
   for (int i = tid; i < DN; i += kBlock) {
@@ -1420,13 +1435,14 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     double* q = reinterpret_cast<double*>(smem + off_tab + k * tab_stride);
     double* iq = q + n_max;
     double* f = iq + n_max;
+    const int md = S.interp;
     for (int j = tid; j < S.n; j += kBlock) {
-      q[j] = L.qnode[S.f_off + j];
-      iq[j] = 1.0 / q[j];
+      q[j] = md == 2 ? S.aux[j] : L.qnode[S.f_off + j];  // node energies (equilibrium-exact) or nodes
+      iq[j] = md == 1 ? S.aux[j] : (md == 2 ? S.tmp[j] : 0.0);  // spline M_j, or log(1/f_j + eta)
       f[j] = L.f64[S.f_off + j];
     }
   }
-  for (int i = tid; i < kWaves * TG; i += kBlock) sm_g[i] = 0.0;
+  for (int i = tid; i < kWaves * TG2; i += kBlock) sm_g[i] = 0.0;
   FTab<double> tr[NI + 1];
   int tslot[NI + 1];
 #pragma unroll
@@ -1437,7 +1453,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     tr[r].iq = tr[r].q + n_max;
     tr[r].f = tr[r].iq + n_max;
     tr[r].n = S.n;
-    tr[r].mode = 0;
+    tr[r].mode = S.interp;
     tr[r].eta = (double)S.stat;
     tr[r].lq0 = S.lq0;
     tr[r].inv_h = S.inv_h;
@@ -1470,7 +1486,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   const double wpar = st->width[it->proc];
   const int rel = it->rel;
   const int wave = tid >> 6;
-  double* my_g = sm_g + wave * TG;
+  double* my_g = sm_g + wave * TG2;
   __syncthreads();
 
   double g_obs = 0.0, dfit[4] = {0.0, 0.0, 0.0, 0.0}, dm[NR], sumW = 0.0;
@@ -1497,7 +1513,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     uint32_t wd[D];
     sample_words<D>(wd, (uint64_t)n, uid, c3, L.seed_lo, L.seed_hi);
     double J = 1.0, jac = 1.0, sx = 0.0, sy = 0.0, sz = esg[NI + 1] * p_obs;
-    double E[NR], f[NR], wt[NR];
+    double E[NR], f[NR], wt[NR], qv[NR];
     int jn[NR], src[NR];  // src: 0 table node, 1 interpolated, 2 extrapolated low, 3 extrapolated high
     E[NI + 1] = E_obs;
     f[NI + 1] = f_obs;
@@ -1531,7 +1547,8 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       jac *= r * r * sc3[0][0];
       E[k] = sqrt(p * p + m[k] * m[k]);
       cut |= E[k] < it->e_cut;
-      f[k] = interp64<false>(tr[k], r, E[k], &jn[k], &wt[k]);
+      f[k] = interp64<true>(tr[k], r, E[k], &jn[k], &wt[k]);
+      qv[k] = r;
       src[k] = 1;
     }
     const double P2 = sx * sx + sy * sy + sz * sz;
@@ -1545,9 +1562,10 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       f[NI] = 1.0 / (exp(fitc[2] + fitc[3] * E[NI]) - eta[NI]);
       src[NI] = 3;
     } else {
-      f[NI] = interp64<false>(tr[NI], qc, E[NI], &jn[NI], &wt[NI]);
+      f[NI] = interp64<true>(tr[NI], qc, E[NI], &jn[NI], &wt[NI]);
       src[NI] = 1;
     }
+    qv[NI] = qc;
     if (cut) continue;
     double dE = 0.0, prod2E = 1.0, sumE = 0.0;
 #pragma unroll
@@ -1597,9 +1615,30 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       if (src[r] == 0) {
         g_obs += dWdf;
       } else if (src[r] == 1) {
-        const int base = (r <= NI ? tslot[r] : 0) * n_max;
-        atomicAdd(&my_g[base + jn[r]], dWdf * (1.0 - wt[r]));
-        atomicAdd(&my_g[base + jn[r] + 1], dWdf * wt[r]);
+        const int rr = r <= NI ? r : 0;  // (the observed role reads its node: src 0)
+        const int base = tslot[rr] * n_max, j = jn[r], mode = tr[rr].mode;
+        if (mode == 1) {
+          const double q0 = tr[rr].q[j], hq = tr[rr].q[j + 1] - q0;
+          const double b = (qv[r] - q0) / hq, a1 = 1.0 - b, h26 = hq * hq / 6.0;
+          atomicAdd(&my_g[base + j], dWdf * a1);
+          atomicAdd(&my_g[base + j + 1], dWdf * b);
+          atomicAdd(&my_g[TG + base + j], dWdf * ((a1 * a1 * a1 - a1) * h26));
+          atomicAdd(&my_g[TG + base + j + 1], dWdf * ((b * b * b - b) * h26));
+        } else if (mode == 2) {
+          // f = 1/(exp(y) - eta), y = (1 - u) y_j + u y_{j+1}, u = (E - E_j)/(E_{j+1} - E_j)
+          const double E0 = tr[rr].q[j], E1 = tr[rr].q[j + 1], dEn = E1 - E0;
+          const double u = (E[r] - E0) / dEn;
+          const double dfdy = -f[r] * (1.0 + eta[r] * f[r]);
+          atomicAdd(&my_g[base + j], dWdf * dfdy * (1.0 - u));
+          atomicAdd(&my_g[base + j + 1], dWdf * dfdy * u);
+          const double dfdu = dfdy * (tr[rr].iq[j + 1] - tr[rr].iq[j]);
+          dWdE += dWdf * dfdu / dEn;
+          // the node energies sqrt((q_j/a)^2 + m^2) move with m: du/dE_j = (u - 1)/dEn, du/dE_{j+1} = -u/dEn
+          dm[r] += dWdf * dfdu * ((u - 1.0) / dEn * (m[r] / E0) - u / dEn * (m[r] / E1));
+        } else {
+          atomicAdd(&my_g[base + j], dWdf * (1.0 - wt[r]));
+          atomicAdd(&my_g[base + j + 1], dWdf * wt[r]);
+        }
       } else {
         const int sd = src[r] - 2;
         const double dfdz = -f[r] * (1.0 + eta[r] * f[r]);
@@ -1619,7 +1658,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
 #pragma unroll
   for (int r = 0; r < NR; ++r) vals[5 + r] = dm[r];
   vals[5 + NR] = sumW;
-  double* rec = L.parts + it->part_off + (int64_t)task.unit * vjp_rec_len(n_tab, n_max);
+  double* rec = L.parts + it->part_off + (int64_t)task.unit * vjp_rec_len(n_tab, n_max, spl);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double v = wave_sum(vals[k]);
@@ -1630,12 +1669,12 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
     double acc = 0.0;
     for (int w = 0; w < kWaves; ++w) acc += sm_red[tid * kWaves + w];
     const int slot = tid < 5 + NR ? tid : 5 + kMaxN;  // g_obs, fit partials, d/dm by role; then sum W
-    rec[TG + slot] = acc;
+    rec[TG2 + slot] = acc;
   }
-  if (tid >= 5 + NR && tid < 5 + kMaxN) rec[TG + tid] = 0.0;  // roles this process does not have
-  for (int i = tid; i < TG; i += kBlock) {
+  if (tid >= 5 + NR && tid < 5 + kMaxN) rec[TG2 + tid] = 0.0;  // roles this process does not have
+  for (int i = tid; i < TG2; i += kBlock) {
     double g = 0.0;
-    for (int w = 0; w < kWaves; ++w) g += sm_g[w * TG + i];
+    for (int w = 0; w < kWaves; ++w) g += sm_g[w * TG2 + i];
     rec[i] = g;
   }
   __syncthreads();
@@ -1670,7 +1709,7 @@ __global__ void k_vjp_reduce(const ItemRec* items, int n_items, const double* co
 }
 
 // Gradients: grad_f of every species node (items in order), then (one thread per species) the chain through
-// the extrapolation fits, the masses, and per process the coupling.
+// the extrapolation fits, the spline's second derivatives, the masses, and per process the coupling.
 __global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
                              int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
                              const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
@@ -1679,35 +1718,108 @@ __global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* it
     int s = 0;
     while (s + 1 < n_species && g >= spec[s + 1].f_off) ++s;
     const int j = (int)(g - spec[s].f_off);
-    double acc = 0.0;
+    double acc = 0.0, obs = 0.0;
     for (int i = 0; i < n_items; ++i) {
       const ItemRec& it = items[i];
       const double* rec = item_rec + (int64_t)i * rec_stride;
       const int nmax = rec_nmax[i];
       for (int k = 0; k < it.n_tab; ++k)
         if (it.tab_species[k] == s && j < spec[s].n) acc += rec[k * nmax + j];
-      if (it.obs_species == s && it.eval_idx == j) acc += rec[it.n_tab * nmax];
+      if (it.obs_species == s && it.eval_idx == j) obs += rec[vjp_tab_len(it.n_tab, nmax, item_spline(it, spec))];
     }
-    grad_f[g] = acc;
+    // equilibrium-exact tables hold d/dy_j, y_j = log(1/f_j + eta): dy_j/df_j = -1 / (f_j (1 + eta f_j))
+    if (spec[s].interp == 2) {
+      const double fj = f64[g];
+      acc *= -1.0 / (fj * (1.0 + (double)spec[s].stat * fj));
+    }
+    grad_f[g] = acc + obs;
+  }
+}
+
+// Adjoint of the spline's second derivatives (spline_second_derivatives: the tridiagonal system T M_int = r(f) in
+// M_1 .. M_{n-2}, then M_0 and M_{n-1} extrapolated from it).  Given g = dL/dM on the n nodes, folds g_0 and g_{n-1}
+// back onto the interior, solves T^T z = g_int (forward elimination and back substitution; T^T is tridiagonal with
+// the sub- and super-diagonals of T swapped), and adds r'^T z to grad_f: z_j reaches f_{j+1} with 1/h_j, f_j with
+// -(1/h_j + 1/h_{j-1}) and f_{j-1} with 1/h_{j-1}.  One thread; g, cp and dp are n-double scratch arrays.
+__device__ void spline_adjoint(int n, const double* qn, double* g, double* cp, double* dp, double* grad_f) {
+  auto hs = [&](int j) { return qn[j + 1] - qn[j]; };
+  // row j (1 <= j <= n-2) of T after the two folds, as the forward elimination builds it
+  auto row = [&](int j, double& lo, double& di, double& up) {
+    const double hl = hs(j - 1), hr = hs(j);
+    lo = hl / 6.0;
+    di = (hl + hr) / 3.0;
+    up = hr / 6.0;
+    if (j == 1) {
+      const double r0 = hl / hr;
+      di += lo * (1.0 + r0);
+      up -= lo * r0;
+      lo = 0.0;
+    }
+    if (j == n - 2) {
+      const double r1 = hr / hl;
+      di += up * (1.0 + r1);
+      lo -= up * r1;
+      up = 0.0;
+    }
+  };
+  const double h0 = hs(0), h1 = hs(1), ha = hs(n - 3), hb = hs(n - 2);
+  // M_0 = (1 + h0/h1) M_1 - (h0/h1) M_2 and M_{n-1} = (1 + hb/ha) M_{n-2} - (hb/ha) M_{n-3}
+  g[1] += (1.0 + h0 / h1) * g[0];
+  g[2] -= (h0 / h1) * g[0];
+  g[n - 2] += (1.0 + hb / ha) * g[n - 1];
+  g[n - 3] -= (hb / ha) * g[n - 1];
+  double lo, di, up, lo_n, di_n, up_n, lo_p, di_p, up_p;
+  for (int j = 1; j <= n - 2; ++j) {
+    row(j, lo, di, up);
+    double sub = 0.0, sup = 0.0;
+    if (j > 1) {
+      row(j - 1, lo_p, di_p, up_p);
+      sub = up_p;
+    }
+    if (j < n - 2) {
+      row(j + 1, lo_n, di_n, up_n);
+      sup = lo_n;
+    }
+    const double den = di - (j > 1 ? sub * cp[j - 1] : 0.0);
+    cp[j] = sup / den;
+    dp[j] = (g[j] - (j > 1 ? sub * dp[j - 1] : 0.0)) / den;
+  }
+  for (int j = n - 3; j >= 1; --j) dp[j] -= cp[j] * dp[j + 1];
+  for (int j = 1; j <= n - 2; ++j) {
+    const double hl = hs(j - 1), hr = hs(j), z = dp[j];
+    grad_f[j + 1] += z / hr;
+    grad_f[j] -= z * (1.0 / hr + 1.0 / hl);
+    grad_f[j - 1] += z / hl;
   }
 }
 
 __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
                              int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
-                             const DevState* st, double* grad_f, double* grad_m, double* grad_lam,
-                             const double* coupling, int n_proc) {
+                             const DevState* st, double* grad_f, int64_t n_f, double* work, double* grad_m,
+                             double* grad_lam, const double* coupling, int n_proc) {
   const int s = threadIdx.x;
   if (s < n_species) {
     const SpecDev& S = spec[s];
     double dfa[4] = {0.0, 0.0, 0.0, 0.0}, gm = 0.0;
+    double* gM = work + S.f_off;  // the species' d/dM_j (spline), then the solve's two scratch rows
+    if (S.interp == 1)
+      for (int j = 0; j < S.n; ++j) gM[j] = 0.0;
     for (int i = 0; i < n_items; ++i) {
       const ItemRec& it = items[i];
-      const double* rec = item_rec + (int64_t)i * rec_stride + it.n_tab * rec_nmax[i];
+      const int nmax = rec_nmax[i], spl = item_spline(it, spec);
+      const double* rec = item_rec + (int64_t)i * rec_stride + vjp_tab_len(it.n_tab, nmax, spl);
       if (it.r_species[it.nint] == s)
         for (int k = 0; k < 4; ++k) dfa[k] += rec[1 + k];
       for (int r = 0; r < it.nint + 2; ++r)
         if (it.r_species[r] == s) gm += rec[5 + r];
+      if (S.interp == 1 && spl) {
+        const double* rM = item_rec + (int64_t)i * rec_stride + it.n_tab * nmax;
+        for (int k = 0; k < it.n_tab; ++k)
+          if (it.tab_species[k] == s)
+            for (int j = 0; j < S.n; ++j) gM[j] += rM[k * nmax + j];
+      }
     }
+    if (S.interp == 1) spline_adjoint(S.n, S.qn, gM, work + n_f + S.f_off, work + 2 * n_f + S.f_off, grad_f + S.f_off);
     // extrapolation fits: (a, b) least-squares line of y_k = log(1/f_k + eta) against E_k, 5 end nodes
     const double a = st->a, m = st->m[s], eta = (double)S.stat;
     const double* f = f64 + S.f_off;
@@ -1746,7 +1858,8 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
     double acc = 0.0;
     for (int i = 0; i < n_items; ++i) {
       if (items[i].proc != p) continue;
-      acc += item_rec[(int64_t)i * rec_stride + items[i].n_tab * rec_nmax[i] + 5 + kMaxN];
+      acc += item_rec[(int64_t)i * rec_stride + vjp_tab_len(items[i].n_tab, rec_nmax[i], item_spline(items[i], spec)) +
+                      5 + kMaxN];
     }
     grad_lam[p] = 2.0 * acc / coupling[p];
   }
@@ -2599,31 +2712,31 @@ hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s) {
   return hipGetLastError();
 }
 
-int vjp_lds_bytes(int D, int nb, int n_tab, int n_max) {
+int vjp_lds_bytes(int D, int nb, int n_tab, int n_max, int spl) {
   int o = 0;
   o = align16(o + D * nb * 8);
   o = align16(o + D * nb * 8);
   o = align16(o + 33 * 16);
   o = align16(o + n_tab * align16(n_max * 24));
-  o = align16(o + kWaves * n_tab * n_max * 8);
+  o = align16(o + kWaves * vjp_tab_len(n_tab, n_max, spl) * 8);
   o = align16(o + (1 + 4 + kMaxN + 1) * kWaves * 8);
   return o;
 }
 
-int vjp_record_len(int n_tab, int n_max) { return vjp_rec_len(n_tab, n_max); }
+int vjp_record_len(int n_tab, int n_max, int spl) { return vjp_rec_len(n_tab, n_max, spl); }
 
 hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* coef, const double* parts,
                              const int* rec_len, const int* rec_nmax, double* item_rec, int rec_stride,
                              const SpecDev* spec, int n_species, const double* f64, const double* qnode,
-                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
-                             const double* coupling, int n_proc, hipStream_t s) {
+                             const DevState* st, double* grad_f, int64_t n_f, double* work, double* grad_m,
+                             double* grad_lam, const double* coupling, int n_proc, hipStream_t s) {
   hipLaunchKernelGGL(k_vjp_reduce, dim3(n_items), dim3(256), 0, s, items, n_items, coef, parts, rec_len, item_rec,
                      rec_stride);
   hipLaunchKernelGGL(k_vjp_gather, dim3((unsigned)((n_f + 255) / 256)), dim3(256), 0, s, items, n_items, item_rec,
                      rec_nmax, rec_stride, spec, n_species, f64, qnode, st, grad_f, n_f, grad_m, grad_lam, coupling,
                      n_proc);
   hipLaunchKernelGGL(k_vjp_finish, dim3(1), dim3(256), 0, s, items, n_items, item_rec, rec_nmax, rec_stride, spec,
-                     n_species, f64, qnode, st, grad_f, grad_m, grad_lam, coupling, n_proc);
+                     n_species, f64, qnode, st, grad_f, n_f, work, grad_m, grad_lam, coupling, n_proc);
   return hipGetLastError();
 }
 

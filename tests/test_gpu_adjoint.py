@@ -21,9 +21,15 @@ def _bm():
     return boltzmc
 
 
-@pytest.mark.parametrize("shape", ["23be", "23be_relwidth", "22mb_tail", "24fd_msin", "multi"])
+@pytest.mark.parametrize("shape", ["23be", "23be_relwidth", "22mb_tail", "24fd_msin", "multi", "23be_spline",
+                                   "23be_eqexact", "22mb_tail_spline", "22mb_tail_eqexact", "24fd_msin_eqexact"])
 def test_vjp_matches_oracle(shape):
+    """The adjoint kernel against the oracle's VJP, through every interpolation rule of Sec. III.B (the spline's
+    transposed system solved on the GPU by elimination, in the oracle by dense pivoted elimination)."""
     bm = _bm()
+    rule = {"spline": wl.INTERP_SPLINE, "eqexact": wl.INTERP_EQEXACT}.get(shape.split("_")[-1])
+    if rule is not None:
+        shape = shape[: shape.rindex("_")]
     if shape == "23be":
         w = wl.w23_be(n_grid=24, q_min=0.05, q_max=8.0, sigma_E=0.05, N=1 << 12, nitn=1)
     elif shape == "23be_relwidth":  # width w (E_in + E_out) / 2: the mass gradient gains the width's energy terms
@@ -37,8 +43,11 @@ def test_vjp_matches_oracle(shape):
         w = wl.w_multi(n_grid=16, N=(1 << 10, 1 << 10, 1 << 10), nitn=1, sigma_E=0.05)
         for p in w.processes:
             p.eval_stride = 1
+    if rule is not None:
+        for s in w.species:
+            s.interp = rule
     N = w.processes[0].n_samples
-    say("vjp %s" % shape)
+    say("vjp %s rule %s" % (shape, rule))
     ctx = bm.from_workload(w)
     opts = bm.default_opts(seed=3, epoch=2, n_iter=1, freeze_maps=1, eval_stride=1, n_samples=N)
     ni, no = ctx.plan_size(-1, -1, opts)
@@ -60,14 +69,17 @@ def test_vjp_matches_oracle(shape):
     np.testing.assert_allclose(gl, ol, rtol=1e-10)
 
 
-def test_heun_rollout_gradient_matches_finite_differences():
+@pytest.mark.parametrize("rule", ["linlog", "spline", "eqexact"])
+def test_heun_rollout_gradient_matches_finite_differences(rule):
     """L = sum (f_T - f_BE)^2 after 3 Heun steps of fixed size, 2<->3 BE: autograd through the adjoint
     kernel vs central differences (h = 1e-6) of the GPU forward on lambda, m0, two f0 coordinates and two
-    random directions, all with frozen maps and the same counters."""
+    random directions, all with frozen maps and the same counters; f between the nodes by each rule of Sec. III.B."""
     import torch
     from paper_2603_28848_amd import adjoint
     bm = _bm()
     w = wl.w23_adjoint(n_grid=32, q_min=0.1, q_max=12.0, sigma_E=0.02, N=1 << 12, nitn=4)
+    for s in w.species:
+        s.interp = {"linlog": wl.INTERP_LINLOG, "spline": wl.INTERP_SPLINE, "eqexact": wl.INTERP_EQEXACT}[rule]
     ctx = bm.from_workload(w)
     ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, n_iter=4, n_samples=1 << 13))  # train the maps
     base = bm.default_opts(seed=0, n_samples=1 << 12)

@@ -95,8 +95,8 @@ def test_interp_points_off_the_grid(interp):
     assert_items_close(res["I_it"], r["I_it"], TOL[0], "I_it", scale=item_scale(items, n, r["Ibar"]))
 
 
-def test_interp_rules_differ_and_vjp_rejects_them():
-    """Negative control: the three rules give different C on the same samples; the adjoint refuses the others."""
+def test_interp_rules_differ():
+    """Negative control: the three rules give different C on the same samples."""
     bm = _bm()
     Cs = []
     for interp in (wl.INTERP_LINLOG, wl.INTERP_SPLINE, wl.INTERP_EQEXACT):
@@ -105,8 +105,3 @@ def test_interp_rules_differ_and_vjp_rejects_them():
         Cs.append(C)
     assert np.max(np.abs(Cs[1] - Cs[0]) / (np.abs(Cs[0]) + 1e-300)) > 1e-6
     assert np.max(np.abs(Cs[2] - Cs[0]) / (np.abs(Cs[0]) + 1e-300)) > 1e-6
-    ctx = bm.from_workload(_with_interp(wl.w22_mb(), wl.INTERP_SPLINE))
-    opts = bm.default_opts(seed=3, epoch=2, n_iter=1, freeze_maps=1, eval_stride=1, n_samples=1000)
-    ni, no = ctx.plan_size(-1, -1, opts)
-    with pytest.raises(bm.BmcError):
-        ctx.vjp(np.ones(no), -1, -1, opts)

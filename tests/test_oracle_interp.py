@@ -95,10 +95,3 @@ def test_eqexact_equilibrium_is_stationary_on_a_coarse_grid():
         assert abs(eq["Ibar"][i]) <= 4 * eq["sigma"][i] + 2e-4 * G[i], (pts[i], eq["Ibar"][i], eq["sigma"][i])
         assert abs(lin["Ibar"][i]) > 5 * lin["sigma"][i], (pts[i], lin["Ibar"][i], lin["sigma"][i])
 
-
-def test_vjp_rejects_other_rules():
-    f_fn = lambda q: 0.8 / np.expm1(np.sqrt(q * q + 1.0) / 1.5)
-    ow, q = _world(wl.INTERP_SPLINE, f_fn)
-    items, n = ow.items()
-    rc, *_ = ow.vjp(items, n, np.ones(n), 256, 0)
-    assert rc == -1  # ORC_EINVAL
