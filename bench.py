@@ -29,7 +29,7 @@ PEAK_FP32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.6
 PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3
 # HBM bytes per launch of the screening kernel on this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
 # scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernel; None once it changes.
-TRAFFIC_BYTES_SCREEN = None
+TRAFFIC_BYTES_SCREEN = 29.22e6
 TIMING_EVERY = 7
 
 
@@ -79,13 +79,15 @@ def cpu_baseline(w, threads):
         assert rc == 0
         return len(keep), len(keep) * p.n_samples * nitn, dt
 
-    stride = 2  # half the grid nodes: about 15 s of oracle work on 16 threads
+    stride = 1  # the whole workload: about 30 s of oracle work on 16 threads
     n_items, samples, dt = run(set(range(0, 128, stride)), p.n_iter, threads)
     n1, s1, dt1 = run(set(range(0, 128, 32)), 1, 1)  # 4 nodes x 4 items, one iteration, one thread
     return {"value": samples / dt, "unit": "samples/s", "cores": threads, "kind": "oracle",
             "sample": "%d of 512 items (grid nodes 0,%d,...,%d x 2 sides x 2 terms), %d samples x %d iterations "
                       "each = %.3g samples in %.1f s" % (n_items, stride, 128 - stride, p.n_samples, p.n_iter,
-                                                         samples, dt),
+                                                         samples, dt) if stride > 1 else
+                      "the whole workload: 512 items, %d samples x %d iterations each = %.3g samples in %.1f s" % (
+                          p.n_samples, p.n_iter, samples, dt),
             "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "single_thread_value": s1 / dt1,
             "single_thread_sample": "%d items (grid nodes 0,32,64,96), %d samples x 1 iteration = %.3g samples in "

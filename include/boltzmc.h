@@ -22,8 +22,13 @@
  *     exception is a static 64 MiB array per GPU that only bmc_collision_noalloc uses for its per-call scratch.
  *   * Results depend only on (inputs, seed, epoch, iteration indices, Vegas maps) and the launch mode; they do not
  *     depend on the launch tuning or on other items in the same call.  The batched and per-grid-point launch modes
- *     group the second pass's sums differently (4 and 32 groups per item), so for the same maps their results
+ *     group the second pass's sums differently (4 and 64 groups per item), so for the same maps their results
  *     agree to rounding; each mode repeats itself bitwise.
+ *   * Accuracy (BMC_FP64): an item's estimate I of one iteration differs from the same samples' estimate in
+ *     correctly rounded arithmetic by at most 1e-12 |I| + 4 eps B1 (eps = 2^-52), B1 = (1/N) sum_n |W_n| s_n with
+ *     s_n = (|dE_n| / sigma_E) (sum_i E_i / sigma_E): the energies carry a few ulps of the library's own sin, cos
+ *     and square root, and the Gaussian energy delta (Eq. 15) amplifies an error in dE by dE / sigma_E^2.  Its
+ *     variance V obeys the same with 1e-12 |V| + 4 eps B2, B2 = 2 / (N (N - 1)) sum_n W_n^2 s_n.
  *   * Work item: (process, observed species, pinned side, term, evaluation grid index).  Its identifier is
  *         uid = process << 24 | species << 20 | side << 19 | term << 18 | eval_index
  *     (side 0 = initial state, 1 = final state; term 0 = gain or net, 1 = loss).  Items of a call are
@@ -86,7 +91,13 @@ extern "C" {
 
 #define BMC_FP64 0        /* everything in IEEE double */
 #define BMC_FP32I 1       /* FP32 integrand (f lookups, statistical factor, exponentials) with FP64
-                             kinematics up to the delta argument and FP64 accumulation */
+                             kinematics up to the delta argument and FP64 accumulation, for samples within
+                             7 sigma_E (+ 1e-3 of the summed energies) of the energy shell.  Samples between that
+                             and the FP64 underflow of the Gaussian factor (|dE| up to sqrt(2 746) sigma_E) are
+                             finished wholly in FP32, conserved momentum and Gaussian argument included: their
+                             factor is below e^-24.5 of the peak and the FP32 dE moves it by at most a few per
+                             cent, so together they move an item's estimate by about 1e-12 of its size at most.
+                             Samples beyond have W = 0 exactly, as in FP64. */
 
 #define BMC_LAUNCH_BATCHED 0  /* all items of a call in one persistent launch per Vegas iteration */
 #define BMC_LAUNCH_PLAIN 1    /* one launch per evaluation grid point per iteration */

@@ -56,10 +56,11 @@ constexpr size_t kStaticListCapBytes = size_t(16) << 20;
 // many items and gives each few groups (every group pays for its barriers, histogram clear and record); a
 // per-grid-point launch has a handful of items and needs many groups to fill the device.  Both depend on the item
 // alone, so an item's results do not depend on the other items of its plan.
+// Measured on the 2<->3 workload: 4 groups per item batched; 64 per grid point (32: 5 % slower, 16: 19 %).
 constexpr int kShellGroupsBatched = 4;
-constexpr int kShellGroupsPlain = 32;
-constexpr int kMaxEvalPoints = BMC_MAXEVAL;
-constexpr int kVplusLdsExtra = 257 * 8 + 256 * 8;  // the VEGAS+ pass's hypercube offsets and chunk of W  // map slots are reserved for this many points off the grid
+constexpr int kShellGroupsPlain = 64;
+constexpr int kMaxEvalPoints = BMC_MAXEVAL;  // map slots are reserved for this many points off the grid
+constexpr int kVplusLdsExtra = 257 * 8 + 256 * 8;  // the VEGAS+ pass's hypercube offsets and chunk of W
 
 // VEGAS+ strata per dimension: the largest k >= 1 with k^D <= N / 2.
 int vplus_strata(int64_t N, int D) {
@@ -140,7 +141,8 @@ struct Plan {
   int64_t n_units = 0;
   int64_t n_parts = 0;   // 32-bit bin counts of all units
   int lds64 = 0, lds32 = 0;      // sample blocks (VEGAS+)
-  int lds_sh64 = 0, lds_sh32 = 0;  // second-pass blocks
+  int lds_sh64 = 0, lds_sh32 = 0;  // second-pass blocks (tables for every rule)
+  int lds_sh64_lin = 0, lds_sh32_lin = 0;  // second-pass blocks of a launch with the linear rule only
   std::vector<int> new_maps;  // item indices whose maps need initialising
   // VEGAS+ items: sample blocks (items with more iterations first), blocks per iteration, the items themselves
   std::vector<VpTask> vp_tasks;
@@ -752,8 +754,10 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
     for (int t = 0; t < it.n_tab; ++t) n_max = std::max(n_max, c->sp[it.tab_species[t]].n);
     Q.lds64 = std::max(Q.lds64, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0));
     Q.lds32 = std::max(Q.lds32, sample_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
-    Q.lds_sh64 = std::max(Q.lds_sh64, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0));
-    Q.lds_sh32 = std::max(Q.lds_sh32, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1));
+    Q.lds_sh64 = std::max(Q.lds_sh64, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0, 1));
+    Q.lds_sh32 = std::max(Q.lds_sh32, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1, 1));
+    Q.lds_sh64_lin = std::max(Q.lds_sh64_lin, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0, 0));
+    Q.lds_sh32_lin = std::max(Q.lds_sh32_lin, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1, 0));
   }
   if (Q.lds64 > 65536 || Q.lds_sh64 > 65536)
     return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
@@ -1002,7 +1006,9 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   for (auto& S : c->sp) L.any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
   for (auto& Pr : c->pr) L.any_interp |= Pr.prm.m2_kind != BMC_M2_CONST ? 1 : 0;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
-  L.shell_lds = o.precision == BMC_FP64 ? P.lds_sh64 : P.lds_sh32;
+  // the second pass's layout follows its kernel instance: tables of f alone when every rule is the linear one
+  L.shell_lds = L.any_interp ? (o.precision == BMC_FP64 ? P.lds_sh64 : P.lds_sh32)
+                             : (o.precision == BMC_FP64 ? P.lds_sh64_lin : P.lds_sh32_lin);
   L.shell_list = P.d_list;
   L.shell_cnt = P.d_cnt;
   L.list_stride = P.list_stride;

@@ -120,8 +120,8 @@ int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
 // LDS bytes of a screening block (the FP32 map only).
 int screen_lds_bytes();
 // LDS bytes of a second-pass block (the sample layout without counts, plus the item's constants and the threads' word
-// slots).
-int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision);
+// slots); alt = 0 for a launch whose tables all use the linear rule and whose |M|^2 is constant (tables of f alone).
+int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision, int alt);
 
 // Adjoint (FP64, frozen maps): per-unit records of the sample derivatives, then per item (times coef/N),
 // then per species node, fits, masses and couplings.

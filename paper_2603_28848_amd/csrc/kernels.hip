@@ -31,7 +31,7 @@ constexpr double kPi = 3.141592653589793238462643383279;
 constexpr double kHistWMin = 0x1p-400;  // |W| below this enters the training histogram as 0
 
 struct Lds {
-  int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, off_h, off_c, off_red, off_q, off_k, off_wd, total;
+  int off_e, off_w, off_m32, off_sc, off_tab, tab_stride, tab_f, off_h, off_c, off_red, off_q, off_k, off_wd, total;
 };
 
 // The three LDS layouts a block can use: the screening pass's, the general sample layout (VEGAS+ blocks and the
@@ -70,6 +70,7 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
   o = align16(o + 33 * 16);
   L.off_tab = o;
   L.tab_stride = align16(n_max * (16 + fbytes));
+  L.tab_f = 16 * n_max;
   o = align16(o + n_tab * L.tab_stride);
   L.off_h = o;
   o = align16(o + kWaves * DN * 8);
@@ -87,10 +88,12 @@ __host__ __device__ inline Lds lds_layout(int D, int nb, int n_tab, int n_max, i
 // Bytes reserved for the per-item constants of a second-pass block (the largest instance).
 constexpr int kItemConstsBytes = 1024;
 
-// LDS of a second-pass block: the map (FP64 edges and widths, and the FP32 map of the FP32 finish), the sin/cos table,
-// the f tables, the per-wave W^2 histograms, reduction and scan scratch, the item's constants (off_k) and, per thread,
-// a slot of the D words of the sample it evaluates (off_wd, word d of thread t at index d kBlock + t).
-__host__ __device__ inline Lds shell_layout(int D, int nb, int n_tab, int n_max, int fbytes) {
+// LDS of a second-pass block: the map (FP64 edges and widths, and the edges and widths of the FP32 map for the FP32
+// finish; no counts), the sin/cos table, the f tables, the per-wave W^2 histograms, reduction and scan scratch, the
+// item's constants (off_k) and, per thread, a slot of the D words of the sample it evaluates (off_wd, word d of thread t
+// at index d kBlock + t).  alt = false (every table of the launch interpolates linearly in ln q): a table holds f_j
+// alone, which keeps the 2<->3 workload's block within 40 KB, four blocks per CU.
+__host__ __device__ inline Lds shell_layout(int D, int nb, int n_tab, int n_max, int fbytes, bool alt) {
   Lds L;
   const int DN = D * nb;
   int o = 0;
@@ -99,11 +102,12 @@ __host__ __device__ inline Lds shell_layout(int D, int nb, int n_tab, int n_max,
   L.off_w = o;
   o = align16(o + DN * 8);
   L.off_m32 = o;
-  o = align16(o + 3 * kMapSlots * 4);
+  o = align16(o + 2 * kMapSlots * 4);
   L.off_sc = o;
   o = align16(o + 33 * 16);
   L.off_tab = o;
-  L.tab_stride = align16(n_max * (16 + fbytes));
+  L.tab_stride = align16(n_max * (alt ? 16 + fbytes : fbytes));
+  L.tab_f = alt ? 16 * n_max : 0;
   o = align16(o + n_tab * L.tab_stride);
   L.off_h = o;
   o = align16(o + kWaves * DN * 8);
@@ -969,7 +973,7 @@ __device__ __forceinline__ void clear_hist(const Lds& lay, unsigned char* smem) 
 // and fills the per-item constants at the current time.  LAY: the block's layout -- kLayScreen (the screening pass:
 // the FP32 map only), kLaySample, or kLayShell (the second pass: K is the block's LDS copy, filled by thread 0).
 // Ends with a block barrier.
-template <int NI, int PREC, int LAY = kLaySample>
+template <int NI, int PREC, int LAY = kLaySample, bool ALT = true>
 __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec* __restrict__ it,
                                            unsigned char* smem, bool stage,
                                            ItemConsts<NI, typename std::conditional<PREC == 0, double, float>::type>& K) {
@@ -985,7 +989,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
   int n_max = 0;
   for (int k = 0; k < n_tab; ++k) n_max = max(n_max, L.spec[it->tab_species[k]].n);
   const Lds lay = SCREEN ? screen_layout()
-                         : (LAY == kLayShell ? shell_layout(D, nb, n_tab, n_max, sizeof(FT))
+                         : (LAY == kLayShell ? shell_layout(D, nb, n_tab, n_max, sizeof(FT), ALT)
                                              : lds_layout(D, nb, n_tab, n_max, sizeof(FT)));
   double* sm_e = reinterpret_cast<double*>(smem + lay.off_e);
   double* sm_w = reinterpret_cast<double*>(smem + lay.off_w);
@@ -1006,7 +1010,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     const double sc = (d % 3 == 0) ? L.st->inv_a : 0.15915494309189535;
     sm_m32[i] = (float)(e0 * sc);
     sm_m32[kMapSlots + i] = (float)((e1 - e0) * sc * 2.3283064365386962890625e-10);
-    reinterpret_cast<uint32_t*>(sm_m32)[2 * kMapSlots + i] = 0u;
+    if constexpr (LAY != kLayShell) reinterpret_cast<uint32_t*>(sm_m32)[2 * kMapSlots + i] = 0u;
   }
   if (!SCREEN && stage && tid < 33) sm_sc[tid] = make_double2(kSinPi16[tid], kCosPi16[tid]);
   for (int k = 0; !SCREEN && stage && k < n_tab; ++k) {
@@ -1014,11 +1018,13 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
     double* q = reinterpret_cast<double*>(base);
     double* iq = q + n_max;
-    FT* f = reinterpret_cast<FT*>(iq + n_max);
+    FT* f = reinterpret_cast<FT*>(base + lay.tab_f);
     const int md = S.interp;
     for (int j = tid; j < S.n; j += kBlock) {
-      q[j] = md == 2 ? S.aux[j] : L.qnode[S.f_off + j];  // node energies (EQEXACT) or nodes
-      iq[j] = md == 1 ? S.aux[j] : (md == 2 ? S.tmp[j] : 0.0);  // spline M_j, or log(1/f_j + eta)
+      if (lay.tab_f != 0) {  // (the compact layout of a linear-rule second pass holds f alone)
+        q[j] = md == 2 ? S.aux[j] : L.qnode[S.f_off + j];  // node energies (EQEXACT) or nodes
+        iq[j] = md == 1 ? S.aux[j] : (md == 2 ? S.tmp[j] : 0.0);  // spline M_j, or log(1/f_j + eta)
+      }
       if constexpr (PREC == 0) f[j] = L.f64[S.f_off + j];
       else f[j] = L.f32[S.f_off + j];
     }
@@ -1038,8 +1044,8 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
       const SpecDev& S = L.spec[it->tab_species[k]];
       const unsigned char* base = smem + lay.off_tab + k * lay.tab_stride;
       K.tr[r].q = to_lds<const double>(reinterpret_cast<const double*>(base));
-      K.tr[r].iq = K.tr[r].q + n_max;
-      K.tr[r].f = to_lds<const FT>(reinterpret_cast<const FT*>(base + 16 * n_max));
+      K.tr[r].iq = K.tr[r].q + n_max;  // (not read by the linear rule)
+      K.tr[r].f = to_lds<const FT>(reinterpret_cast<const FT*>(base + lay.tab_f));
       K.tr[r].n = S.n;
       K.tr[r].mode = S.interp;
       K.tr[r].eta = (double)S.stat;
@@ -1265,8 +1271,8 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
   for (int q = 0; q < it->n_tab; ++q) n_max = max(n_max, L.spec[it->tab_species[q]].n);
   // the item's constants live in LDS (read where needed, so that few stay in registers across a sample)
   ItemConsts<NI, FT>* K =
-      reinterpret_cast<ItemConsts<NI, FT>*>(smem + shell_layout(D, it->nb, it->n_tab, n_max, sizeof(FT)).off_k);
-  const Lds lay = setup_block<NI, PREC, kLayShell>(L, it, smem, stage, *K);
+      reinterpret_cast<ItemConsts<NI, FT>*>(smem + shell_layout(D, it->nb, it->n_tab, n_max, sizeof(FT), ALT).off_k);
+  const Lds lay = setup_block<NI, PREC, kLayShell, ALT>(L, it, smem, stage, *K);
   uint32_t* wl = reinterpret_cast<uint32_t*>(smem + lay.off_wd) + tid;  // this thread's word slot
   const int DN = D * it->nb;
   double* my_h = reinterpret_cast<double*>(smem + lay.off_h) + wave * DN;
@@ -1897,7 +1903,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
 // item are consecutive, so the block re-uses the staged map and tables).  Which block runs a task does not change
 // its result.
 template <int MASK, int PREC, bool ALT>
-__global__ __launch_bounds__(kBlock, 3) void k_shell(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, (PREC == 1 && !ALT && MASK != 15) ? 4 : 3) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = blockIdx.x / L.sh_tiles, tile = blockIdx.x % L.sh_tiles;  // grid = n_sh x sh_tiles
   if (k >= L.n_sh) return;
@@ -2663,8 +2669,8 @@ int sample_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
 }
 
 int screen_lds_bytes() { return screen_layout().total; }
-int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision) {
-  return shell_layout(D, nb, n_tab, n_max, precision == 0 ? 8 : 4).total;
+int shell_lds_bytes(int D, int nb, int n_tab, int n_max, int precision, int alt) {
+  return shell_layout(D, nb, n_tab, n_max, precision == 0 ? 8 : 4, alt != 0).total;
 }
 
 hipError_t launch_sample(const SampleLaunch& L, hipStream_t s) {

@@ -92,7 +92,7 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
         return float(np.max(np.abs(np.log(f[mid] / wl.f_equilibrium(q[mid], m, T, wl.BOSE, mu)))))
 
     hist: Dict[str, List[float]] = {"step": [0], "t": [0.0], "N": [1.0], "E": [1.0], "dt": [0.0],
-                                    "dev": [deviation(f0)]}
+                                    "dev": [deviation(f0)], "width": [ctx.get_width(0)]}
     t0 = time.perf_counter()
     t = 0.0
     stopped = ""
@@ -124,10 +124,13 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
             f = ctx.get_f(0, n_grid)
             Nn, En = moments(q, f, m)
             dev = deviation(f)
-            for k, v in (("step", s), ("t", t), ("N", Nn / N0), ("E", En / E0), ("dt", dt), ("dev", dev)):
+            wd = ctx.get_width(0)
+            for k, v in (("step", s), ("t", t), ("N", Nn / N0), ("E", En / E0), ("dt", dt), ("dev", dev),
+                         ("width", wd)):
                 hist[k].append(v)
             if log:
-                log("step %d t %.4g dt %.3g N/N0 %.5f E/E0 %.5f dev %.4f" % (s, t, dt, Nn / N0, En / E0, dev))
+                log("step %d t %.4g dt %.3g N/N0 %.5f E/E0 %.5f dev %.4f width %.4g" % (
+                    s, t, dt, Nn / N0, En / E0, dev, wd))
         if t >= t_end:
             break
     f = ctx.get_f(0, n_grid)
@@ -139,7 +142,9 @@ def run(process: str = "2to2", n_grid: int = 272, q_min: float = 0.1, q_max: flo
         "n_iter": n_iter,
         "sigma_E": sigma_E, "eps": eps, "steps": hist["step"][-1], "t": t, "wall_s": time.perf_counter() - t0,
         "N_over_N0": Nn / N0, "E_over_E0": En / E0, "T_eq": T_eq, "mu_eq": mu_eq, "T_fit": T_fit, "mu_fit": mu_fit,
-        "max_log_dev_from_eq": deviation(f), "initial_max_log_dev": hist["dev"][0],
+        "max_log_dev_from_eq": deviation(f), "initial_max_log_dev": hist["dev"][0], "width_end": ctx.get_width(0),
+        "max_abs_E_drift": float(np.max(np.abs(np.array(hist["E"]) - 1.0))),
+        "max_abs_N_drift": float(np.max(np.abs(np.array(hist["N"]) - 1.0))),
         "history": hist, "f": f.tolist(), "q": q.tolist(),
     }
 
@@ -160,12 +165,13 @@ def main():
     ap.add_argument("--c3-only", action="store_true", help="2<->3: the final side alone (3 C_3), the incorrect sum")
     ap.add_argument("--rel-width", action="store_true", help="relative width w (E_in + E_out)/2 with its controller")
     ap.add_argument("--precision", type=int, default=1, help="0 FP64, 1 FP32 integrand")
+    ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--record-every", type=int, default=10)
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     res = run(a.process, n_grid=a.n_grid, n_samples=a.samples, n_iter=a.iters, steps=a.steps, eps=a.eps,
               sigma_E=a.sigma_e, side_mask=wl.SIDES_OUT if a.c3_only else wl.SIDES_AUTO,
-              record_every=a.record_every, precision=a.precision, t_end=a.t_end, dt_max=a.dt_max,
+              record_every=a.record_every, precision=a.precision, seed=a.seed, t_end=a.t_end, dt_max=a.dt_max,
               term_mode=wl.TERMS_NET if a.net else wl.TERMS_SPLIT,
               interp={"linlog": wl.INTERP_LINLOG, "spline": wl.INTERP_SPLINE, "eqexact": wl.INTERP_EQEXACT}[a.interp],
               width_mode=wl.WIDTH_REL if a.rel_width else wl.WIDTH_ABS, log=lambda s: print(s, flush=True))
