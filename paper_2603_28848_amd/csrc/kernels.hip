@@ -1259,7 +1259,8 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
 // lists, then the near lists of its units (unit order, waves in order within a unit), each read as one sequence
 // whose entry e is evaluated by thread e mod 256.  FP64 (PREC 0): every listed sample with FP64 kinematics and
 // integrand.  FP32 integrand (PREC 1): in-shell samples with FP64 kinematics, near samples with the FP32 finish.
-// The block's sums go to the task's record.  Units are taken 64 at a time (256 lists).
+// The block's sums go to the task's record (tile t of the task: the t-th record from there).  Units are taken 64 at a
+// time (256 lists).
 template <int NI, int PREC, bool ALT>
 __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
@@ -1899,9 +1900,10 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
   }
 }
 
-// Second pass: block b takes the consecutive in-shell tasks [b c, (b + 1) c), c = ceil(n / G) (the tasks of one
-// item are consecutive, so the block re-uses the staged map and tables).  Which block runs a task does not change
-// its result.
+// Second pass: block b takes tile b mod sh_tiles of second-pass group b / sh_tiles (one group of units of one item;
+// every group of the launch has its own blocks).  Four blocks per CU for the FP32 integrand with the linear rule
+// (its compact LDS layout and at most 128 VGPRs), three otherwise.  Which block runs a group does not change its
+// result.
 template <int MASK, int PREC, bool ALT>
 __global__ __launch_bounds__(kBlock, (PREC == 1 && !ALT && MASK != 15) ? 4 : 3) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
