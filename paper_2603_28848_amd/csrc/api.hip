@@ -2000,7 +2000,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   const size_t nI = P.items.size();
   std::vector<ItemRec> vitems = P.items;
   std::vector<double> coef(nI);
-  std::vector<int> rec_len(nI), rec_nmax(nI);
+  std::vector<int> rec_len(nI), rec_nmax(2 * nI);  // n_max per item, then the offset of each record's tail
   int64_t part = 0;
   int rec_stride = 0, lds = 0;
   for (size_t i = 0; i < nI; ++i) {
@@ -2014,6 +2014,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
       spl |= c->sp[it.tab_species[t]].interp == BMC_INTERP_SPLINE ? 1 : 0;
     }
     rec_nmax[i] = n_max;
+    rec_nmax[nI + i] = it.n_tab * n_max * (spl ? 2 : 1);
     rec_len[i] = vjp_record_len(it.n_tab, n_max, spl);
     rec_stride = std::max(rec_stride, rec_len[i]);
     it.part_off = part;
@@ -2030,7 +2031,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   };
   const size_t o_items = take(sizeof(ItemRec) * nI), o_parts = take(8 * (size_t)part),
                o_rec = take(8 * (size_t)rec_stride * nI), o_coef = take(8 * nI), o_len = take(4 * nI),
-               o_nmax = take(4 * nI), o_gf = take(8 * (size_t)c->n_f), o_work = take(8 * 3 * (size_t)c->n_f),
+               o_nmax = take(8 * nI), o_gf = take(8 * (size_t)c->n_f), o_work = take(8 * 3 * (size_t)c->n_f),
                o_gm = take(8 * kMaxSpecies),
                o_gl = take(8 * c->pr.size()), o_cp = take(8 * c->pr.size());
   if (off > c->ws_bytes)
@@ -2053,7 +2054,7 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   HIPCHK(c, hipMemcpyAsync(d_items, vitems.data(), sizeof(ItemRec) * nI, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(d_coef, coef.data(), 8 * nI, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(d_len, rec_len.data(), 4 * nI, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(d_nmax, rec_nmax.data(), 4 * nI, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(d_nmax, rec_nmax.data(), 8 * nI, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(d_cp, cpl.data(), 8 * cpl.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, launch_set_eval(c->st(), 0.0, o->epoch, 0, s));
   HIPCHK(c, launch_next_epoch(c->st(), s));
@@ -2076,7 +2077,8 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   L.seed_hi = (uint32_t)(o->seed >> 32);
   L.nint_mask = P.nint_mask;
   L.precision = BMC_FP64;
-  L.any_interp = 0;  // (the adjoint kernel reads each table's rule itself)
+  L.any_interp = 0;  // the adjoint kernel's general instance when a species uses the spline or equilibrium-exact rule
+  for (auto& Sp : c->sp) L.any_interp |= Sp.interp != BMC_INTERP_LINLOG ? 1 : 0;
   L.lds_bytes = lds;
   L.chunk = 1;
   L.shell_list = P.d_list;

@@ -1400,7 +1400,8 @@ __device__ inline int item_spline(const ItemRec& it, const SpecDev* spec) {
   return spl;
 }
 
-template <int NI>
+// ALT = false: every table of the launch uses the linear rule (the other rules' code is not compiled in).
+template <int NI, bool ALT>
 __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
@@ -1554,7 +1555,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       jac *= r * r * sc3[0][0];
       E[k] = sqrt(p * p + m[k] * m[k]);
       cut |= E[k] < it->e_cut;
-      f[k] = interp64<true>(tr[k], r, E[k], &jn[k], &wt[k]);
+      f[k] = interp64<ALT>(tr[k], r, E[k], &jn[k], &wt[k]);
       qv[k] = r;
       src[k] = 1;
     }
@@ -1569,7 +1570,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       f[NI] = 1.0 / (exp(fitc[2] + fitc[3] * E[NI]) - eta[NI]);
       src[NI] = 3;
     } else {
-      f[NI] = interp64<true>(tr[NI], qc, E[NI], &jn[NI], &wt[NI]);
+      f[NI] = interp64<ALT>(tr[NI], qc, E[NI], &jn[NI], &wt[NI]);
       src[NI] = 1;
     }
     qv[NI] = qc;
@@ -1623,7 +1624,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
         g_obs += dWdf;
       } else if (src[r] == 1) {
         const int rr = r <= NI ? r : 0;  // (the observed role reads its node: src 0)
-        const int base = tslot[rr] * n_max, j = jn[r], mode = tr[rr].mode;
+        const int base = tslot[rr] * n_max, j = jn[r], mode = ALT ? tr[rr].mode : 0;
         if (mode == 1) {
           const double q0 = tr[rr].q[j], hq = tr[rr].q[j + 1] - q0;
           const double b = (qv[r] - q0) / hq, a1 = 1.0 - b, h26 = hq * hq / 6.0;
@@ -1687,16 +1688,16 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   __syncthreads();
 }
 
-template <int MASK>
+template <int MASK, bool ALT>
 __global__ __launch_bounds__(kBlock, 2) void k_vjp(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
     const Task task = L.tasks[L.task_begin + t];
     const int ni = L.items[task.item].nint;
-    if ((MASK & 1) && ni == 1) vjp_task<1>(L, task, t, smem);
-    if ((MASK & 2) && ni == 2) vjp_task<2>(L, task, t, smem);
-    if ((MASK & 4) && ni == 3) vjp_task<3>(L, task, t, smem);
-    if ((MASK & 8) && ni == 4) vjp_task<4>(L, task, t, smem);
+    if ((MASK & 1) && ni == 1) vjp_task<1, ALT>(L, task, t, smem);
+    if ((MASK & 2) && ni == 2) vjp_task<2, ALT>(L, task, t, smem);
+    if ((MASK & 4) && ni == 3) vjp_task<3, ALT>(L, task, t, smem);
+    if ((MASK & 8) && ni == 4) vjp_task<4, ALT>(L, task, t, smem);
   }
 }
 
@@ -1716,7 +1717,9 @@ __global__ void k_vjp_reduce(const ItemRec* items, int n_items, const double* co
 }
 
 // Gradients: grad_f of every species node (items in order), then (one thread per species) the chain through
-// the extrapolation fits, the spline's second derivatives, the masses, and per process the coupling.
+// the extrapolation fits, the spline's second derivatives, the masses, and per process the coupling.  rec_nmax holds
+// per item the table length n_max of its record, then (at n_items + i) the offset of the record's tail (g_obs, fit
+// partials, masses, sum W) after the table gradients.
 __global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
                              int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
                              const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
@@ -1732,7 +1735,7 @@ __global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* it
       const int nmax = rec_nmax[i];
       for (int k = 0; k < it.n_tab; ++k)
         if (it.tab_species[k] == s && j < spec[s].n) acc += rec[k * nmax + j];
-      if (it.obs_species == s && it.eval_idx == j) obs += rec[vjp_tab_len(it.n_tab, nmax, item_spline(it, spec))];
+      if (it.obs_species == s && it.eval_idx == j) obs += rec[rec_nmax[n_items + i]];
     }
     // equilibrium-exact tables hold d/dy_j, y_j = log(1/f_j + eta): dy_j/df_j = -1 / (f_j (1 + eta f_j))
     if (spec[s].interp == 2) {
@@ -1813,8 +1816,8 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
       for (int j = 0; j < S.n; ++j) gM[j] = 0.0;
     for (int i = 0; i < n_items; ++i) {
       const ItemRec& it = items[i];
-      const int nmax = rec_nmax[i], spl = item_spline(it, spec);
-      const double* rec = item_rec + (int64_t)i * rec_stride + vjp_tab_len(it.n_tab, nmax, spl);
+      const int nmax = rec_nmax[i], tail = rec_nmax[n_items + i], spl = tail > it.n_tab * nmax ? 1 : 0;
+      const double* rec = item_rec + (int64_t)i * rec_stride + tail;
       if (it.r_species[it.nint] == s)
         for (int k = 0; k < 4; ++k) dfa[k] += rec[1 + k];
       for (int r = 0; r < it.nint + 2; ++r)
@@ -1865,8 +1868,7 @@ __global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* it
     double acc = 0.0;
     for (int i = 0; i < n_items; ++i) {
       if (items[i].proc != p) continue;
-      acc += item_rec[(int64_t)i * rec_stride + vjp_tab_len(items[i].n_tab, rec_nmax[i], item_spline(items[i], spec)) +
-                      5 + kMaxN];
+      acc += item_rec[(int64_t)i * rec_stride + rec_nmax[n_items + i] + 5 + kMaxN];
     }
     grad_lam[p] = 2.0 * acc / coupling[p];
   }
@@ -1901,11 +1903,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
 }
 
 // Second pass: block b takes tile b mod sh_tiles of second-pass group b / sh_tiles (one group of units of one item;
-// every group of the launch has its own blocks).  Four blocks per CU for the FP32 integrand with the linear rule
-// (its compact LDS layout and at most 128 VGPRs), three otherwise.  Which block runs a group does not change its
-// result.
+// every group of the launch has its own blocks).  Four blocks per CU with the linear rule (its compact LDS layout and
+// at most 128 VGPRs; the FP64 instance then keeps 2 VGPRs in scratch), three otherwise.  Which block runs a group
+// does not change its result.
 template <int MASK, int PREC, bool ALT>
-__global__ __launch_bounds__(kBlock, (PREC == 1 && !ALT && MASK != 15) ? 4 : 3) void k_shell(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, (!ALT && MASK != 15) ? 4 : 3) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = blockIdx.x / L.sh_tiles, tile = blockIdx.x % L.sh_tiles;  // grid = n_sh x sh_tiles
   if (k >= L.n_sh) return;
@@ -2708,14 +2710,20 @@ hipError_t launch_shell(const SampleLaunch& L, hipStream_t s) {
   }
 }
 
+template <int MASK>
+void launch_vjp_mask(const SampleLaunch& L, hipStream_t s) {
+  if (L.any_interp) hipLaunchKernelGGL((k_vjp<MASK, true>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+  else hipLaunchKernelGGL((k_vjp<MASK, false>), dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L);
+}
+
 hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s) {
   if (L.n_tasks <= 0) return hipSuccess;
   switch (L.nint_mask) {
-    case 1: hipLaunchKernelGGL(k_vjp<1>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
-    case 2: hipLaunchKernelGGL(k_vjp<2>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
-    case 4: hipLaunchKernelGGL(k_vjp<4>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
-    case 8: hipLaunchKernelGGL(k_vjp<8>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
-    default: hipLaunchKernelGGL(k_vjp<15>, dim3(L.grid), dim3(kBlock), L.lds_bytes, s, L); break;
+    case 1: launch_vjp_mask<1>(L, s); break;
+    case 2: launch_vjp_mask<2>(L, s); break;
+    case 4: launch_vjp_mask<4>(L, s); break;
+    case 8: launch_vjp_mask<8>(L, s); break;
+    default: launch_vjp_mask<15>(L, s); break;
   }
   return hipGetLastError();
 }

@@ -3,7 +3,7 @@ import numpy as np
 import pytest
 
 from gpu_util import (TOL, assert_items_close, check_fp64_items, fp64_point_bound, gpu_available, item_scale,
-                      point_scale, say)
+                      oracle_items_matching, point_scale, say)
 from oracle import binding as ob
 from paper_2603_28848_amd import workloads as wl
 
@@ -79,3 +79,36 @@ def test_poly_m2_is_refused_by_the_adjoint_and_the_exact_path():
         ctx.vjp(np.ones(no), -1, -1, opts)
     with pytest.raises(bm.BmcError):
         ctx.collision_exact22(-1, -1, opts)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_unit_polynomial_through_the_general_instance_matches_constant_m2(precision):
+    """A polynomial |M|^2 with P = 1 runs the second pass's general instance (full tables: q_j, M_j or E_j, y_j, and
+    f_j per node, three blocks per CU); the constant |M|^2 runs the linear-rule instance (tables of f_j alone, the
+    compact layout, four blocks per CU for the FP32 integrand).  Both against the oracle on the same frozen maps and
+    samples (FP64: the rounding contract; FP32 integrand: 1e-5), and against each other: the two instances contract
+    the FP64 kinematics into fused multiply-adds differently, so they agree to rounding, not bitwise."""
+    bm = _bm()
+    N, nitn = 1 << 14, 2
+    w = wl.w23_be(n_grid=32, N=N, nitn=nitn)
+    ow = ob.OracleWorld(w)
+    out = []
+    for kind in (wl.M2_CONST, wl.M2_POLY):
+        for p in w.processes:
+            p.m2_kind, p.m2_coef = kind, (1.0, 0.0, 0.0, 0.0, 0.0, 0.0)
+        ctx = bm.from_workload(w)
+        ctx.collision(-1, -1, bm.default_opts(seed=4, epoch=1, precision=precision, freeze_maps=1, n_iter=nitn,
+                                              n_samples=N))
+        out.append(ctx.item_results(nitn))
+    assert np.array_equal(out[0]["uid"], out[1]["uid"])
+    items, n = oracle_items_matching(ow, out[0]["uid"])
+    rc, r = ow.run_items(items, n, N, nitn, seed=4, epoch=1, adapt=False)
+    assert rc == 0
+    for k, res in enumerate(out):
+        say("%s |M|^2, precision %d" % (("constant", "unit polynomial")[k], precision))
+        if precision == 0:
+            check_fp64_items(ow, items, n, res, r, N, nitn, seed=4, epoch=1)
+        else:
+            assert_items_close(res["I_it"], r["I_it"], TOL[1], "I_it", scale=item_scale(items, n, r["Ibar"]))
+    d = np.abs(out[0]["I_it"] - out[1]["I_it"])
+    say("instances differ by max |dI| / |I| %.3e" % float(np.max(d / np.maximum(np.abs(r["I_it"]), 1e-300))))
