@@ -1716,20 +1716,32 @@ __global__ void k_vjp_reduce(const ItemRec* items, int n_items, const double* co
   }
 }
 
-// Gradients: grad_f of every species node (items in order), then (one thread per species) the chain through
-// the extrapolation fits, the spline's second derivatives, the masses, and per process the coupling.  rec_nmax holds
-// per item the table length n_max of its record, then (at n_items + i) the offset of the record's tail (g_obs, fit
-// partials, masses, sum W) after the table gradients.
-__global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
-                             int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
-                             const DevState* st, double* grad_f, int64_t n_f, double* grad_m, double* grad_lam,
-                             const double* coupling, int n_proc) {
-  for (int64_t g = blockIdx.x * blockDim.x + threadIdx.x; g < n_f; g += (int64_t)gridDim.x * blockDim.x) {
+// Sum of one value per thread of a 256-thread block in a fixed order: a butterfly within each wave, then the four
+// waves in order; every thread gets the sum.  red: 4 doubles of LDS.
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double t = ((red[0] + red[1]) + red[2]) + red[3];
+  __syncthreads();
+  return t;
+}
+
+// Gradients: grad_f of every species node (one block per node: its 256 threads take the items i = t, t + 256, ...,
+// then a fixed-order block sum), then (k_vjp_finish, one block per species and one per process) the chain through
+// the extrapolation fits, the spline's second derivatives, the masses, and the couplings.  rec_nmax holds per item the
+// table length n_max of its record, then (at n_items + i) the offset of the record's tail (g_obs, fit partials,
+// masses, sum W) after the table gradients.
+__global__ __launch_bounds__(256) void k_vjp_gather(const ItemRec* items, int n_items, const double* item_rec,
+                                                    const int* rec_nmax, int rec_stride, const SpecDev* spec,
+                                                    int n_species, const double* f64, double* grad_f, int64_t n_f) {
+  __shared__ double red[4];
+  for (int64_t g = blockIdx.x; g < n_f; g += gridDim.x) {
     int s = 0;
     while (s + 1 < n_species && g >= spec[s + 1].f_off) ++s;
     const int j = (int)(g - spec[s].f_off);
     double acc = 0.0, obs = 0.0;
-    for (int i = 0; i < n_items; ++i) {
+    for (int i = threadIdx.x; i < n_items; i += blockDim.x) {
       const ItemRec& it = items[i];
       const double* rec = item_rec + (int64_t)i * rec_stride;
       const int nmax = rec_nmax[i];
@@ -1737,12 +1749,16 @@ __global__ void k_vjp_gather(const ItemRec* items, int n_items, const double* it
         if (it.tab_species[k] == s && j < spec[s].n) acc += rec[k * nmax + j];
       if (it.obs_species == s && it.eval_idx == j) obs += rec[rec_nmax[n_items + i]];
     }
-    // equilibrium-exact tables hold d/dy_j, y_j = log(1/f_j + eta): dy_j/df_j = -1 / (f_j (1 + eta f_j))
-    if (spec[s].interp == 2) {
-      const double fj = f64[g];
-      acc *= -1.0 / (fj * (1.0 + (double)spec[s].stat * fj));
+    acc = block_sum256(acc, red);
+    obs = block_sum256(obs, red);
+    if (threadIdx.x == 0) {
+      // equilibrium-exact tables hold d/dy_j, y_j = log(1/f_j + eta): dy_j/df_j = -1 / (f_j (1 + eta f_j))
+      if (spec[s].interp == 2) {
+        const double fj = f64[g];
+        acc *= -1.0 / (fj * (1.0 + (double)spec[s].stat * fj));
+      }
+      grad_f[g] = acc + obs;
     }
-    grad_f[g] = acc + obs;
   }
 }
 
@@ -1803,75 +1819,88 @@ __device__ void spline_adjoint(int n, const double* qn, double* g, double* cp, d
   }
 }
 
-__global__ void k_vjp_finish(const ItemRec* items, int n_items, const double* item_rec, const int* rec_nmax,
-                             int rec_stride, const SpecDev* spec, int n_species, const double* f64, const double* qnode,
-                             const DevState* st, double* grad_f, int64_t n_f, double* work, double* grad_m,
-                             double* grad_lam, const double* coupling, int n_proc) {
-  const int s = threadIdx.x;
-  if (s < n_species) {
-    const SpecDev& S = spec[s];
-    double dfa[4] = {0.0, 0.0, 0.0, 0.0}, gm = 0.0;
-    double* gM = work + S.f_off;  // the species' d/dM_j (spline), then the solve's two scratch rows
-    if (S.interp == 1)
-      for (int j = 0; j < S.n; ++j) gM[j] = 0.0;
-    for (int i = 0; i < n_items; ++i) {
-      const ItemRec& it = items[i];
-      const int nmax = rec_nmax[i], tail = rec_nmax[n_items + i], spl = tail > it.n_tab * nmax ? 1 : 0;
-      const double* rec = item_rec + (int64_t)i * rec_stride + tail;
-      if (it.r_species[it.nint] == s)
-        for (int k = 0; k < 4; ++k) dfa[k] += rec[1 + k];
-      for (int r = 0; r < it.nint + 2; ++r)
-        if (it.r_species[r] == s) gm += rec[5 + r];
-      if (S.interp == 1 && spl) {
+__global__ __launch_bounds__(256) void k_vjp_finish(const ItemRec* items, int n_items, const double* item_rec,
+                                                    const int* rec_nmax, int rec_stride, const SpecDev* spec,
+                                                    int n_species, const double* f64, const double* qnode,
+                                                    const DevState* st, double* grad_f, int64_t n_f, double* work,
+                                                    double* grad_m, double* grad_lam, const double* coupling,
+                                                    int n_proc) {
+  __shared__ double red[4];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  if (b >= n_species) {  // process b - n_species: dL/dlambda = 2 sum W / lambda over its items
+    const int p = b - n_species;
+    double acc = 0.0;
+    for (int i = tid; i < n_items; i += blockDim.x)
+      if (items[i].proc == p) acc += item_rec[(int64_t)i * rec_stride + rec_nmax[n_items + i] + 5 + kMaxN];
+    acc = block_sum256(acc, red);
+    if (tid == 0) grad_lam[p] = 2.0 * acc / coupling[p];
+    return;
+  }
+  const int s = b;
+  const SpecDev& S = spec[s];
+  // the items' fit partials and mass derivatives of this species (threads over items, fixed-order block sums)
+  double dfa[4] = {0.0, 0.0, 0.0, 0.0}, gm = 0.0;
+  for (int i = tid; i < n_items; i += blockDim.x) {
+    const ItemRec& it = items[i];
+    const double* rec = item_rec + (int64_t)i * rec_stride + rec_nmax[n_items + i];
+    if (it.r_species[it.nint] == s)
+      for (int k = 0; k < 4; ++k) dfa[k] += rec[1 + k];
+    for (int r = 0; r < it.nint + 2; ++r)
+      if (it.r_species[r] == s) gm += rec[5 + r];
+  }
+  for (int k = 0; k < 4; ++k) dfa[k] = block_sum256(dfa[k], red);
+  gm = block_sum256(gm, red);
+  double* gM = work + S.f_off;  // the species' d/dM_j (spline), then the solve's two scratch rows
+  if (S.interp == 1) {  // threads over nodes, each summing the items in order
+    for (int j = tid; j < S.n; j += blockDim.x) {
+      double g = 0.0;
+      for (int i = 0; i < n_items; ++i) {
+        const ItemRec& it = items[i];
+        const int nmax = rec_nmax[i];
+        if (rec_nmax[n_items + i] == it.n_tab * nmax) continue;  // no spline table in this item
         const double* rM = item_rec + (int64_t)i * rec_stride + it.n_tab * nmax;
         for (int k = 0; k < it.n_tab; ++k)
-          if (it.tab_species[k] == s)
-            for (int j = 0; j < S.n; ++j) gM[j] += rM[k * nmax + j];
+          if (it.tab_species[k] == s) g += rM[k * nmax + j];
       }
+      gM[j] = g;
     }
-    if (S.interp == 1) spline_adjoint(S.n, S.qn, gM, work + n_f + S.f_off, work + 2 * n_f + S.f_off, grad_f + S.f_off);
-    // extrapolation fits: (a, b) least-squares line of y_k = log(1/f_k + eta) against E_k, 5 end nodes
-    const double a = st->a, m = st->m[s], eta = (double)S.stat;
-    const double* f = f64 + S.f_off;
-    for (int side = 0; side < 2; ++side) {
-      const double dWa = dfa[2 * side], dWb = dfa[2 * side + 1];
-      if (dWa == 0.0 && dWb == 0.0) continue;
-      const int j0 = side == 0 ? 0 : S.n - 5;
-      double E[5], Y[5], mE = 0.0, mY = 0.0;
-      for (int k = 0; k < 5; ++k) {
-        const double p = qnode[S.f_off + j0 + k] / a;
-        E[k] = sqrt(p * p + m * m);
-        Y[k] = log(1.0 / f[j0 + k] + eta);
-        mE += E[k] / 5.0;
-        mY += Y[k] / 5.0;
-      }
-      double sxx = 0.0, sxy = 0.0;
-      for (int k = 0; k < 5; ++k) {
-        sxx += (E[k] - mE) * (E[k] - mE);
-        sxy += (E[k] - mE) * (Y[k] - mY);
-      }
-      const double b = sxy / sxx;
-      for (int k = 0; k < 5; ++k) {
-        const double db_dy = (E[k] - mE) / sxx;
-        const double da_dy = 1.0 / 5.0 - mE * db_dy;
-        const double db_dE = ((Y[k] - mY) - 2.0 * b * (E[k] - mE)) / sxx;
-        const double da_dE = -db_dE * mE - b / 5.0;
-        const double fk = f[j0 + k];
-        const double dy_df = -1.0 / (fk * (1.0 + eta * fk));
-        grad_f[S.f_off + j0 + k] += (dWa * da_dy + dWb * db_dy) * dy_df;
-        gm += (dWa * da_dE + dWb * db_dE) * m / E[k];
-      }
-    }
-    grad_m[s] = gm;
+    __syncthreads();
   }
-  for (int p = threadIdx.x; p < n_proc; p += blockDim.x) {
-    double acc = 0.0;
-    for (int i = 0; i < n_items; ++i) {
-      if (items[i].proc != p) continue;
-      acc += item_rec[(int64_t)i * rec_stride + rec_nmax[n_items + i] + 5 + kMaxN];
+  if (tid != 0) return;
+  if (S.interp == 1) spline_adjoint(S.n, S.qn, gM, work + n_f + S.f_off, work + 2 * n_f + S.f_off, grad_f + S.f_off);
+  // extrapolation fits: (a, b) least-squares line of y_k = log(1/f_k + eta) against E_k, 5 end nodes
+  const double a = st->a, m = st->m[s], eta = (double)S.stat;
+  const double* f = f64 + S.f_off;
+  for (int side = 0; side < 2; ++side) {
+    const double dWa = dfa[2 * side], dWb = dfa[2 * side + 1];
+    if (dWa == 0.0 && dWb == 0.0) continue;
+    const int j0 = side == 0 ? 0 : S.n - 5;
+    double E[5], Y[5], mE = 0.0, mY = 0.0;
+    for (int k = 0; k < 5; ++k) {
+      const double p = qnode[S.f_off + j0 + k] / a;
+      E[k] = sqrt(p * p + m * m);
+      Y[k] = log(1.0 / f[j0 + k] + eta);
+      mE += E[k] / 5.0;
+      mY += Y[k] / 5.0;
     }
-    grad_lam[p] = 2.0 * acc / coupling[p];
+    double sxx = 0.0, sxy = 0.0;
+    for (int k = 0; k < 5; ++k) {
+      sxx += (E[k] - mE) * (E[k] - mE);
+      sxy += (E[k] - mE) * (Y[k] - mY);
+    }
+    const double bb = sxy / sxx;
+    for (int k = 0; k < 5; ++k) {
+      const double db_dy = (E[k] - mE) / sxx;
+      const double da_dy = 1.0 / 5.0 - mE * db_dy;
+      const double db_dE = ((Y[k] - mY) - 2.0 * bb * (E[k] - mE)) / sxx;
+      const double da_dE = -db_dE * mE - bb / 5.0;
+      const double fk = f[j0 + k];
+      const double dy_df = -1.0 / (fk * (1.0 + eta * fk));
+      grad_f[S.f_off + j0 + k] += (dWa * da_dy + dWb * db_dy) * dy_df;
+      gm += (dWa * da_dE + dWb * db_dE) * m / E[k];
+    }
   }
+  grad_m[s] = gm;
 }
 
 // Persistent screening kernel (both precisions): block b takes the chunks b, b + G, b + 2G, ... of `chunk`
@@ -1904,10 +1933,11 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
 
 // Second pass: block b takes tile b mod sh_tiles of second-pass group b / sh_tiles (one group of units of one item;
 // every group of the launch has its own blocks).  Four blocks per CU with the linear rule (its compact LDS layout and
-// at most 128 VGPRs; the FP64 instance then keeps 2 VGPRs in scratch), three otherwise.  Which block runs a group
-// does not change its result.
+// at most 128 VGPRs; the FP64 instance then keeps 2 VGPRs in scratch) for up to three integrated particles, three
+// otherwise (four integrated particles need more than 40 KB of LDS, so a tighter register cap would buy nothing).
+// Which block runs a group does not change its result.
 template <int MASK, int PREC, bool ALT>
-__global__ __launch_bounds__(kBlock, (!ALT && MASK != 15) ? 4 : 3) void k_shell(SampleLaunch L) {
+__global__ __launch_bounds__(kBlock, (!ALT && MASK != 15 && MASK != 8) ? 4 : 3) void k_shell(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int k = blockIdx.x / L.sh_tiles, tile = blockIdx.x % L.sh_tiles;  // grid = n_sh x sh_tiles
   if (k >= L.n_sh) return;
@@ -2748,11 +2778,11 @@ hipError_t launch_vjp_finish(const ItemRec* items, int n_items, const double* co
                              double* grad_lam, const double* coupling, int n_proc, hipStream_t s) {
   hipLaunchKernelGGL(k_vjp_reduce, dim3(n_items), dim3(256), 0, s, items, n_items, coef, parts, rec_len, item_rec,
                      rec_stride);
-  hipLaunchKernelGGL(k_vjp_gather, dim3((unsigned)((n_f + 255) / 256)), dim3(256), 0, s, items, n_items, item_rec,
-                     rec_nmax, rec_stride, spec, n_species, f64, qnode, st, grad_f, n_f, grad_m, grad_lam, coupling,
+  hipLaunchKernelGGL(k_vjp_gather, dim3((unsigned)std::min<int64_t>(n_f, 65535)), dim3(256), 0, s, items, n_items,
+                     item_rec, rec_nmax, rec_stride, spec, n_species, f64, grad_f, n_f);
+  hipLaunchKernelGGL(k_vjp_finish, dim3(n_species + n_proc), dim3(256), 0, s, items, n_items, item_rec, rec_nmax,
+                     rec_stride, spec, n_species, f64, qnode, st, grad_f, n_f, work, grad_m, grad_lam, coupling,
                      n_proc);
-  hipLaunchKernelGGL(k_vjp_finish, dim3(1), dim3(256), 0, s, items, n_items, item_rec, rec_nmax, rec_stride, spec,
-                     n_species, f64, qnode, st, grad_f, n_f, work, grad_m, grad_lam, coupling, n_proc);
   return hipGetLastError();
 }
 
