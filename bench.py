@@ -207,7 +207,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the collision-integral items shard across GPUs with one small "
-              "all-gather per evaluation, which this build does not implement; run with --gpus 1.",
+              "all-gather per evaluation, which the library does not implement; run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -53,7 +53,7 @@ extern "C" {
 #define BMC_ERANGE (-3)   /* f <= 0, Fermi-Dirac f >= 1, or an invalid extrapolation fit (Sec. III.B) */
 #define BMC_ENOMEM (-4)   /* bound workspace smaller than the call needs (query again) */
 #define BMC_EHIP (-5)     /* a HIP runtime call failed */
-#define BMC_EUNSUP (-6)   /* valid request that this build does not implement */
+#define BMC_EUNSUP (-6)   /* valid request that the library does not implement */
 
 /* ---- enumerations ---- */
 #define BMC_MEM_HOST 0
