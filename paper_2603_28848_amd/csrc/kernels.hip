@@ -314,6 +314,7 @@ struct ItemConsts {
   double p_obs, E_obs, f_obs, g_obs, l_obs, a3M2, e_cut;
   double fit[4], qc_min, qc_max;
   double inv2s2, dnorm, twopi_pow;
+  double a3M2_tp;  // a3M2 / twopi_pow (the FP32 integrand's weight constant)
   int nb, net, term;
   uint32_t uid, c3, seed_lo, seed_hi;
 };
@@ -529,7 +530,7 @@ __device__ __forceinline__ double eval_sample(const ItemConsts<NI, FT>& K, uint6
 // One listed sample of the second pass: the arithmetic of eval_sample, operation for operation (so results are the
 // same bits), with the per-item constants read from the block's LDS copy K and the particle loop not unrolled, so
 // that a thread keeps one particle's values live at a time.  The sample's D words are staged in the thread's LDS
-// slot wl (word d at wl[d kBlock]), where the accumulation reads its bins back.
+// slot wl (word d at wl[d kBlock]); each is replaced by its bin's histogram index d nb + j once used.
 template <int NI, typename FT, bool ALT>
 __device__ __forceinline__ double eval_listed(const ItemConsts<NI, FT>* K, uint64_t n, uint32_t* wl) {
 #pragma clang fp contract(off)
@@ -561,11 +562,13 @@ __device__ __forceinline__ double eval_listed(const ItemConsts<NI, FT>* K, uint6
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int d = 3 * k + c;
-      const double yn = (((double)wl[d * kBlock] + 0.5) * 2.3283064365386962890625e-10) * dnb;
-      int j = (int)yn;
-      j = j > nb - 1 ? nb - 1 : j;
-      const double del = yn - (double)j;
+      // y nb = (word + 1/2) nb 2^-32 in integers: bin j = high word of word nb + floor(nb/2), offset = (low word
+      // + 1/2 for an odd nb) 2^-32 -- the same bits as the FP64 product (which is exact) and its floor
+      const uint64_t t = (uint64_t)wl[d * kBlock] * (uint32_t)nb + (uint64_t)(nb >> 1);
+      const int j = (int)(t >> 32);
+      const double del = ((double)(uint32_t)t + 0.5 * (double)(nb & 1)) * 2.3283064365386962890625e-10;
       const double e0 = K->e[d * nb + j], w = K->w[d * nb + j];
+      wl[d * kBlock] = (uint32_t)(d * nb + j);  // the word is spent: its slot keeps the bin for the accumulation
       x3[c] = e0 + w * del;
       J *= dnb * w;
       if (c != 0) sincos_red(x3[c], K->sc, &sc3[c - 1][0], &sc3[c - 1][1]);
@@ -659,7 +662,7 @@ __device__ __forceinline__ double eval_listed(const ItemConsts<NI, FT>* K, uint6
   } else {
     const float delta = exp_split(-dE * dE * inv2s2) * (float)dnorm;
     const float rcp = __builtin_amdgcn_rcpf((float)prod2E);
-    W = J * jac * (K->a3M2 / K->twopi_pow) * ((double)delta * (double)rcp) * (double)F;
+    W = J * jac * K->a3M2_tp * ((double)delta * (double)rcp) * (double)F;
   }
   if constexpr (ALT) W *= m2f;
   return cut ? 0.0 : W;
@@ -669,7 +672,7 @@ __device__ __forceinline__ double eval_listed(const ItemConsts<NI, FT>* K, uint6
 // screen_sample's FP32 finish, operation for operation, with the constants read from the block's LDS copy K, the
 // sample's words from the thread's LDS slot wl and the particle loop not unrolled.
 template <int NI, bool ALT>
-__device__ __forceinline__ double near_listed(const ItemConsts<NI, float>* K, const uint32_t* wl) {
+__device__ __forceinline__ double near_listed(const ItemConsts<NI, float>* K, uint32_t* wl) {
   const uint32_t nb = (uint32_t)K->nb;
   const uint64_t half_nb = nb >> 1;
   const float a32 = (float)K->a;
@@ -695,6 +698,7 @@ __device__ __forceinline__ double near_listed(const ItemConsts<NI, float>* K, co
       const int d = 3 * k + c;
       const uint64_t t = (uint64_t)wl[d * kBlock] * nb + (half_nb + ((uint64_t)(d * nb) << 32));
       const uint32_t jdu = (uint32_t)(t >> 32);
+      wl[d * kBlock] = jdu;  // the word is spent: its slot keeps the bin (d nb + j) for the accumulation
       const float e0 = m32[jdu], ew = m32[kMapSlots + jdu];
       x3[c] = fmaf(ew, (float)(uint32_t)t, e0);
       J *= (c == 0 ? fnb32r : fnb32rev) * ew;
@@ -784,23 +788,18 @@ __device__ __forceinline__ double near_listed(const ItemConsts<NI, float>* K, co
   return cut ? 0.0 : ldexp((double)m, (int)e) * (double)F;
 }
 
-// The accumulation of one listed sample: S1 += W, S2 += W^2, and W^2 into the wave's histogram at the bins of the
-// sample's words in the thread's LDS slot (the bins eval_listed used), dimension by dimension as accumulate does.
+// The accumulation of one listed sample: S1 += W, S2 += W^2, and W^2 into the wave's histogram at the sample's bins,
+// dimension by dimension as accumulate does.  eval_listed and near_listed leave each dimension's histogram index
+// d nb + j in the thread's LDS slot in place of the word it came from.
 template <int D>
-__device__ __forceinline__ void accumulate_listed(double W, const uint32_t* wl, int nb, double& S1, double& S2,
+__device__ __forceinline__ void accumulate_listed(double W, const uint32_t* wl, double& S1, double& S2,
                                                   double* my_h) {
   S1 += W;
   S2 += W * W;
   if (fabs(W) >= kHistWMin) {
     const double w2 = W * W;
-    const double dnb = (double)nb;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-      const double yn = (((double)wl[d * kBlock] + 0.5) * 2.3283064365386962890625e-10) * dnb;
-      int j = (int)yn;
-      j = j > nb - 1 ? nb - 1 : j;
-      atomicAdd(&my_h[d * nb + j], w2);
-    }
+    for (int d = 0; d < D; ++d) atomicAdd(&my_h[wl[d * kBlock]], w2);
   }
 }
 
@@ -1089,6 +1088,7 @@ __device__ __forceinline__ Lds setup_block(const SampleLaunch& L, const ItemRec*
     K.qc_min = Sc.q_min;
     K.qc_max = Sc.q_max;
     K.twopi_pow = it->twopi_pow;
+    K.a3M2_tp = K.a3M2 / K.twopi_pow;
     {
       // the Gaussian energy delta: an absolute width, or w (E_in + E_out) / 2 at each point
       constexpr double kRs2pi = 0.3989422804014327, kFarK = 38.62641583165593;  // 1/sqrt(2 pi), sqrt(2 746)
@@ -1355,7 +1355,7 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
           for (int e = lo + tid; e < hi; e += kBlock) {
             const uint64_t n = entry(e);
             const double W = eval_listed<NI, FT, ALT>(K, n, wl);
-            accumulate_listed<D>(W, wl, K->nb, S1, S2, my_h);  // the screening pass counted every sample
+            accumulate_listed<D>(W, wl, S1, S2, my_h);  // the screening pass counted every sample
           }
         } else if constexpr (PREC == 1) {
           for (int e = lo + tid; e < hi; e += kBlock) {
@@ -1367,7 +1367,7 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
               for (int d = 0; d < D; ++d) wl[d * kBlock] = wd[d];
             }
             const double W = near_listed<NI, ALT>(K, wl);
-            accumulate_listed<D>(W, wl, K->nb, S1, S2, my_h);
+            accumulate_listed<D>(W, wl, S1, S2, my_h);
           }
         }
         __syncthreads();  // pre is rewritten by the next chunk
