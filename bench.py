@@ -29,7 +29,7 @@ PEAK_FP32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.6
 PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3
 # HBM bytes per launch of the screening kernel on this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
 # scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernel; None once it changes.
-TRAFFIC_BYTES_SCREEN = 42.53e6
+TRAFFIC_BYTES_SCREEN = 33.30e6
 TIMING_EVERY = 7
 
 

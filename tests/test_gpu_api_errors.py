@@ -79,3 +79,23 @@ def test_timing_every_kth_sample_phase():
     assert ctx.get_timing(reset=True)[1] == 0
     with pytest.raises(bm.BmcError):
         ctx.set_timing(True, every=-1)
+
+
+def test_kernel_timing_splits_the_sample_phase():
+    """get_kernel_timing reports the same timed phases as get_timing, split at the event between the screening pass
+    and the second pass: screen + second = the phase total (float event times), both positive; reading either
+    with reset clears both."""
+    bm = _bm()
+    ctx = bm.from_workload(wl.w23_be(n_grid=32, N=1 << 14, nitn=3))
+    o = bm.default_opts(seed=2, n_iter=3)
+    ctx.collision(-1, -1, o)
+    ctx.set_timing(True, every=1)
+    ctx.get_kernel_timing(reset=True)
+    ctx.collision(-1, -1, o)
+    ctx.collision(-1, -1, o)
+    scr, sec, n = ctx.get_kernel_timing(reset=False)
+    ms, n2 = ctx.get_timing(reset=True)
+    assert n == n2 == 6 and scr > 0.0 and sec > 0.0
+    assert abs((scr + sec) - ms) <= 1e-3 * ms + 1e-3, (scr, sec, ms)
+    assert ctx.get_kernel_timing(reset=True) == (0.0, 0.0, 0)
+    ctx.set_timing(False)
