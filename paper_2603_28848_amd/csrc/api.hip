@@ -2017,8 +2017,8 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
     rec_nmax[nI + i] = it.n_tab * n_max * (spl ? 2 : 1);
     rec_len[i] = vjp_record_len(it.n_tab, n_max, spl);
     rec_stride = std::max(rec_stride, rec_len[i]);
-    it.part_off = part;
-    part += (int64_t)it.n_units * rec_len[i];
+    it.part_off = part;  // one record per batched second-pass group of the item
+    part += ((int64_t)it.n_units + it.shell_units - 1) / it.shell_units * rec_len[i];
     lds = std::max(lds, vjp_lds_bytes(it.D, it.nb, it.n_tab, n_max, spl));
   }
   if (lds > 65536) return fail(c, BMC_EUNSUP, "per-block LDS need of the adjoint above 64 KB");
@@ -2092,11 +2092,14 @@ int bmc_vjp(bmc_ctx* c, int process, int species, const bmc_run_opts* o, const d
   S.lds_bytes = P.lds32;
   S.chunk = c->chunk;
   S.n_listed = nullptr;
+  L.sh_tasks = P.d_shb;  // the adjoint takes the batched second pass's groups of units, one block each
   for (const Plan::Slice& sl : P.slices) {
     S.task_begin = L.task_begin = sl.tb;
     S.n_tasks = L.n_tasks = sl.te - sl.tb;
+    L.sh_begin = sl.sb;
+    L.n_sh = sl.se - sl.sb;
     S.grid = std::min((S.n_tasks + S.chunk - 1) / S.chunk, grid_for(c, BMC_FP32I, screen_lds_bytes(), P.nint_mask));
-    L.grid = std::min(L.n_tasks, grid_for(c, BMC_FP64, lds, P.nint_mask));
+    L.grid = std::min(L.n_sh, grid_for(c, BMC_FP64, lds, P.nint_mask));
     HIPCHK(c, launch_sample(S, s));
     HIPCHK(c, launch_vjp(L, s));
   }

@@ -1387,7 +1387,7 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
 // linear in ln q -- d/df_j with weights 1 - w, w; spline -- d/df_j with weights A, B and d/dM_j with weights
 // (A^3 - A) h^2/6, (B^3 - B) h^2/6 (M, the second derivatives, depend on every node; the finish kernel solves the
 // transposed spline system); equilibrium-exact -- d/dy_j of y_j = log(1/f_j + eta) (the gather converts to f_j).
-// Per unit record (doubles): n_tab * n_max table gradients, as many d/dM slots when a table of the item is a
+// Per group record (doubles): n_tab * n_max table gradients, as many d/dM slots when a table of the item is a
 // spline, then g_obs, d/d(a_lo, b_lo, a_hi, b_hi), d/dm per role (kMaxN), sum W.
 __host__ __device__ inline int vjp_tab_len(int n_tab, int n_max, int spl) { return n_tab * n_max * (spl ? 2 : 1); }
 __host__ __device__ inline int vjp_rec_len(int n_tab, int n_max, int spl) {
@@ -1400,13 +1400,16 @@ __device__ inline int item_spline(const ItemRec& it, const SpecDev* spec) {
   return spl;
 }
 
-// ALT = false: every table of the launch uses the linear rule (the other rules' code is not compiled in).
+// One block per group of consecutive units of one item (the batched second pass's groups): the map, tables and
+// constants are staged once, the units' listed samples are taken unit by unit, and the group's sums go to record
+// unit_begin / shell_units of the item.  ALT = false: every table of the launch uses the linear rule (the other
+// rules' code is not compiled in).
 template <int NI, bool ALT>
-__device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsigned char* smem) {
+__device__ void vjp_group(const SampleLaunch& L, const ShellTask sht, unsigned char* smem) {
 #pragma clang fp contract(off)
   constexpr int D = 3 * NI;
   constexpr int NR = NI + 2;
-  const ItemRec* __restrict__ it = &L.items[task.item];
+  const ItemRec* __restrict__ it = &L.items[sht.item];
   const int tid = threadIdx.x;
   const int nb = it->nb;
   const int DN = D * nb;
@@ -1487,9 +1490,6 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
   const double* fitc = st->fit[it->r_species[NI]];
   const uint32_t uid = it->uid;
   const uint32_t c3 = st->epoch * 64u + (uint32_t)L.it;
-  const int64_t N = it->N;
-  const int64_t n0 = (int64_t)task.unit * it->unit_size;
-  const int64_t n1 = min(n0 + (int64_t)it->unit_size, N);
   const double dnb = (double)nb;
   const double wpar = st->width[it->proc];
   const int rel = it->rel;
@@ -1501,14 +1501,17 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
 #pragma unroll
   for (int r = 0; r < NR; ++r) dm[r] = 0.0;
   // Only the samples the screening pass listed (in or near the energy shell): every other sample has W = 0 and
-  // zero derivatives.  The unit's eight lists (in-shell then near, waves in order) form one sequence whose entry
-  // e is taken by thread e mod 256.
+  // zero derivatives.  Per unit of the group, in unit order: the unit's eight lists (in-shell then near, waves in
+  // order) form one sequence whose entry e is taken by thread e mod 256.
+  const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // launch position of unit 0
+  const int64_t wlen = L.list_stride / kWaves;
+  for (int u = sht.unit_begin; u < sht.unit_end; ++u) {
+  const int pos = pos0 + u;
+  const int64_t n0 = (int64_t)u * it->unit_size;
   const uint32_t* cnt = L.shell_cnt + (int64_t)pos * 2 * kWaves;
   const uint16_t* lst = L.shell_list + (int64_t)pos * L.list_stride;
-  const int64_t wlen = L.list_stride / kWaves;
   int M = 0;
   for (int l = 0; l < 2 * kWaves; ++l) M += (int)cnt[l];
-  (void)n1;
   for (int e = tid; e < M; e += kBlock) {
     int l = 0, k = e;
     while (k >= (int)cnt[l]) {
@@ -1657,7 +1660,8 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
       dm[r] += dWdE * m[r] / E[r];
     }
   }
-  // ---- fixed-order reductions into the unit record ----
+  }  // units of the group
+  // ---- fixed-order reductions into the group's record ----
   constexpr int NS = 1 + 4 + NR + 1;
   double vals[NS];
   vals[0] = g_obs;
@@ -1666,7 +1670,7 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
 #pragma unroll
   for (int r = 0; r < NR; ++r) vals[5 + r] = dm[r];
   vals[5 + NR] = sumW;
-  double* rec = L.parts + it->part_off + (int64_t)task.unit * vjp_rec_len(n_tab, n_max, spl);
+  double* rec = L.parts + it->part_off + (int64_t)(sht.unit_begin / it->shell_units) * vjp_rec_len(n_tab, n_max, spl);
 #pragma unroll
   for (int k = 0; k < NS; ++k) {
     const double v = wave_sum(vals[k]);
@@ -1691,27 +1695,28 @@ __device__ void vjp_task(const SampleLaunch& L, const Task task, int pos, unsign
 template <int MASK, bool ALT>
 __global__ __launch_bounds__(kBlock, 2) void k_vjp(SampleLaunch L) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int t = blockIdx.x; t < L.n_tasks; t += gridDim.x) {
-    const Task task = L.tasks[L.task_begin + t];
-    const int ni = L.items[task.item].nint;
-    if ((MASK & 1) && ni == 1) vjp_task<1, ALT>(L, task, t, smem);
-    if ((MASK & 2) && ni == 2) vjp_task<2, ALT>(L, task, t, smem);
-    if ((MASK & 4) && ni == 3) vjp_task<3, ALT>(L, task, t, smem);
-    if ((MASK & 8) && ni == 4) vjp_task<4, ALT>(L, task, t, smem);
+  for (int g = blockIdx.x; g < L.n_sh; g += gridDim.x) {
+    const ShellTask sht = L.sh_tasks[L.sh_begin + g];
+    const int ni = L.items[sht.item].nint;
+    if ((MASK & 1) && ni == 1) vjp_group<1, ALT>(L, sht, smem);
+    if ((MASK & 2) && ni == 2) vjp_group<2, ALT>(L, sht, smem);
+    if ((MASK & 4) && ni == 3) vjp_group<3, ALT>(L, sht, smem);
+    if ((MASK & 8) && ni == 4) vjp_group<4, ALT>(L, sht, smem);
   }
 }
 
-// Per item: sum of its unit records in unit order, times coef_i / N.
+// Per item: sum of its group records in group order, times coef_i / N.
 __global__ void k_vjp_reduce(const ItemRec* items, int n_items, const double* coef, const double* parts,
                              const int* rec_len, double* item_rec, int rec_stride) {
   const int i = blockIdx.x;
   if (i >= n_items) return;
   const ItemRec& it = items[i];
   const int len = rec_len[i];
+  const int n_groups = (it.n_units + it.shell_units - 1) / it.shell_units;
   const double c = coef[i] / (double)it.N;
   for (int k = threadIdx.x; k < len; k += blockDim.x) {
     double acc = 0.0;
-    for (int u = 0; u < it.n_units; ++u) acc += parts[it.part_off + (int64_t)u * len + k];
+    for (int g = 0; g < n_groups; ++g) acc += parts[it.part_off + (int64_t)g * len + k];
     item_rec[(int64_t)i * rec_stride + k] = c * acc;
   }
 }
@@ -2747,13 +2752,18 @@ void launch_vjp_mask(const SampleLaunch& L, hipStream_t s) {
 }
 
 hipError_t launch_vjp(const SampleLaunch& L, hipStream_t s) {
-  if (L.n_tasks <= 0) return hipSuccess;
+  if (L.n_sh <= 0) return hipSuccess;
   switch (L.nint_mask) {
     case 1: launch_vjp_mask<1>(L, s); break;
     case 2: launch_vjp_mask<2>(L, s); break;
     case 4: launch_vjp_mask<4>(L, s); break;
     case 8: launch_vjp_mask<8>(L, s); break;
-    default: launch_vjp_mask<15>(L, s); break;
+    default:  // several particle counts: one launch per count (each skips the other counts' groups)
+      if (L.nint_mask & 1) launch_vjp_mask<1>(L, s);
+      if (L.nint_mask & 2) launch_vjp_mask<2>(L, s);
+      if (L.nint_mask & 4) launch_vjp_mask<4>(L, s);
+      if (L.nint_mask & 8) launch_vjp_mask<8>(L, s);
+      break;
   }
   return hipGetLastError();
 }
