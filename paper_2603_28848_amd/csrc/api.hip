@@ -983,8 +983,10 @@ hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
   return e;
 }
 
-// Enqueues one evaluation of plan P (all iterations, combine, gather) on the context stream.
-int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, double* out_S) {
+// Enqueues one evaluation of plan P (all iterations, combine, gather) on the context stream.  The screening pass
+// counts the samples per bin where the maps adapt, or where count_bins forces it (the autotuner times frozen-map
+// calls of a run that will adapt).
+int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, double* out_S, bool count_bins = false) {
   hipStream_t s = c->stream;
   HIPCHK(c, launch_next_epoch(c->st(), s));
   HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
@@ -996,7 +998,9 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.qnode = c->qnode();
   L.st = c->st();
   L.maps = c->maps();
-  L.counts = P.d_counts;
+  // bin counts only where the maps adapt (frozen maps: the screening pass runs without its count atomics; the
+  // reduction clears the counts either way)
+  L.counts = (o.freeze_maps && !count_bins) ? nullptr : P.d_counts;
   L.unit_base = P.d_unit_base;
   L.seed_lo = (uint32_t)o.seed;
   L.seed_hi = (uint32_t)(o.seed >> 32);
@@ -2223,7 +2227,7 @@ int bmc_autotune(bmc_ctx* c, int process, int species, const bmc_run_opts* o, in
       double ms_sum = 0.0;
       for (int rep = 0; rep < 2; ++rep) {
         HIPCHK(c, hipEventRecord(e0, c->stream));
-        rc = enqueue_eval(c, P, q, P.d_out_C, P.d_out_S);
+        rc = enqueue_eval(c, P, q, P.d_out_C, P.d_out_S, o->freeze_maps == 0);
         if (rc) break;
         HIPCHK(c, hipEventRecord(e1, c->stream));
         HIPCHK(c, hipEventSynchronize(e1));

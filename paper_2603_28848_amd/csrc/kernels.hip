@@ -1202,11 +1202,12 @@ __device__ __forceinline__ void finish_block(double S1, double S2, const Lds& la
 // FP32 integrand, screening pass over the units of tasks t0 .. t1-1 (all of one item; launch positions t).
 // A lane screens the G consecutive samples of one word group (G = 4 / gcd(D, 4): their uniforms fill whole Philox
 // blocks); wave w takes rounds of 64 G samples (round k: samples n0 + 256 G k + 64 G w + G lane + s, s < G), so
-// each wave screens a quarter of a unit.  Every sample adds to the counts of its bins (the unit's counts); far
-// samples (W = 0) do nothing else; the offsets n - n0 of in-shell samples are appended, in screening order (round,
-// s, lane), to the front of the wave's list of the task position (list_stride / 4 entries per wave), those of near
-// samples to its back, for the second pass; the wave's two counts are stored.
-template <int NI>
+// each wave screens a quarter of a unit.  With COUNT every sample adds to the counts of its bins (the unit's counts;
+// a launch whose maps do not adapt passes no counts and runs without them); far samples (W = 0) do nothing else;
+// the offsets n - n0 of in-shell samples are appended, in screening order (round, s, lane), to the front of the
+// wave's list of the task position (list_stride / 4 entries per wave), those of near samples to its back, for the
+// second pass; the wave's two counts are stored.
+template <int NI, bool COUNT>
 __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
   const int item = L.tasks[L.task_begin + t0].item;
@@ -1237,7 +1238,7 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
         if (n < n1) {
           int hj[D];
           double W;
-          cls = screen_sample<NI, false, false, true>(K, wg + s * D, hj, &W);
+          cls = screen_sample<NI, false, false, COUNT>(K, wg + s * D, hj, &W);
         }
         const uint64_t b_in = __ballot(cls == kInShell), b_near = __ballot(cls == kNear);
         if (cls == kInShell) lst[cin + (uint32_t)__popcll(b_in & below)] = (uint16_t)(n - n0);
@@ -1252,7 +1253,11 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
     }
   }
   // the run's bin counts (all its units) into the item's counts
-  finish_counts(slot_cnt, DN, L.counts ? L.counts + it->part_off : nullptr);
+  if constexpr (COUNT) {
+    finish_counts(slot_cnt, DN, L.counts + it->part_off);
+  } else {
+    __syncthreads();  // the next run restages the LDS
+  }
 }
 
 // Second pass over the in-shell tasks k0 .. k1-1 (ranges of units of one item).  Per task: first the in-shell
@@ -1927,10 +1932,17 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
       const int ni = L.items[item].nint;
       const bool stage = item != prev_item;
       prev_item = item;
-      if ((MASK & 1) && ni == 1) screen_run<1>(L, t, t1, smem, stage);
-      if ((MASK & 2) && ni == 2) screen_run<2>(L, t, t1, smem, stage);
-      if ((MASK & 4) && ni == 3) screen_run<3>(L, t, t1, smem, stage);
-      if ((MASK & 8) && ni == 4) screen_run<4>(L, t, t1, smem, stage);
+      if (L.counts) {
+        if ((MASK & 1) && ni == 1) screen_run<1, true>(L, t, t1, smem, stage);
+        if ((MASK & 2) && ni == 2) screen_run<2, true>(L, t, t1, smem, stage);
+        if ((MASK & 4) && ni == 3) screen_run<3, true>(L, t, t1, smem, stage);
+        if ((MASK & 8) && ni == 4) screen_run<4, true>(L, t, t1, smem, stage);
+      } else {
+        if ((MASK & 1) && ni == 1) screen_run<1, false>(L, t, t1, smem, stage);
+        if ((MASK & 2) && ni == 2) screen_run<2, false>(L, t, t1, smem, stage);
+        if ((MASK & 4) && ni == 3) screen_run<3, false>(L, t, t1, smem, stage);
+        if ((MASK & 8) && ni == 4) screen_run<4, false>(L, t, t1, smem, stage);
+      }
       t = t1;
     }
   }
