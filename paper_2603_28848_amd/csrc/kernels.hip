@@ -1260,12 +1260,12 @@ __device__ void screen_run(const SampleLaunch& L, int t0, int t1, unsigned char*
   }
 }
 
-// Second pass over the in-shell tasks k0 .. k1-1 (ranges of units of one item).  Per task: first the in-shell
-// lists, then the near lists of its units (unit order, waves in order within a unit), each read as one sequence
-// whose entry e is evaluated by thread e mod 256.  FP64 (PREC 0): every listed sample with FP64 kinematics and
-// integrand.  FP32 integrand (PREC 1): in-shell samples with FP64 kinematics, near samples with the FP32 finish.
-// The block's sums go to the task's record (tile t of the task: the t-th record from there).  Units are taken 64 at a
-// time (256 lists).
+// Second pass over the in-shell tasks k0 .. k1-1 (ranges of units of one item).  Per task: its in-shell lists, then
+// its near lists (unit order, waves in order within a unit), read as one sequence in chunks of 256 lists; entry e of
+// a chunk is evaluated by thread (e - first entry of the block's tile in the chunk) mod 256.  FP64 (PREC 0): every
+// listed sample with FP64 kinematics and integrand.  FP32 integrand (PREC 1): in-shell samples with FP64
+// kinematics, near samples with the FP32 finish.  The block's sums go to the task's record (tile t of the task: the
+// t-th record from there).
 template <int NI, int PREC, bool ALT>
 __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsigned char* smem, bool stage) {
   constexpr int D = 3 * NI;
@@ -1319,64 +1319,68 @@ __device__ void shell_run(const SampleLaunch& L, int k0, int k1, int tile, unsig
     }
     int base = 0;  // position of the current chunk's first entry in the group's sequence
     double S1 = 0.0, S2 = 0.0;
-    for (int kind = 0; kind < 2; ++kind) {  // 0: in-shell lists, 1: near lists
-      for (int u0 = sht.unit_begin; u0 < sht.unit_end && base < e_hi; u0 += kLists / kWaves) {
-        const int nl = min(kLists, (sht.unit_end - u0) * kWaves);
-        // block-wide inclusive scan of the list lengths: within each wave, then the wave totals in order
-        int v = 0;
-        if (tid < nl) {
-          const int u = u0 + tid / kWaves, w = tid % kWaves;
-          v = (int)L.shell_cnt[(int64_t)(pos0 + u) * 2 * kWaves + kind * kWaves + w];
-        }
-  #pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-          const int t = __shfl_up(v, d, 64);
-          if (lane >= d) v += t;
-        }
-        if (lane == 63) wtot[wave] = v;
-        __syncthreads();
-        for (int w = 0; w < wave; ++w) v += wtot[w];
-        pre[tid + 1] = v;
-        if (tid == 0) pre[0] = 0;
-        __syncthreads();
-        const int M = pre[nl];
-        // this chunk's entries that fall in the tile: [lo, hi) of the chunk (entry e of the chunk is sequence entry
-        // base + e), thread t taking lo + t, lo + t + 256, ...
-        const int lo = max(0, e_lo - base), hi = min(M, e_hi - base);
-        base += M;
-        auto entry = [&](int e) -> uint64_t {
-          int lo = 0, hi = nl;  // pre[lo] <= e < pre[hi]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pre[mid] <= e) lo = mid;
-            else hi = mid;
-          }
-          const int u = u0 + lo / kWaves, w = lo % kWaves, k = e - pre[lo];
-          const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
-          const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
-          return (uint64_t)((int64_t)u * it->unit_size + off);
-        };
-        if (PREC == 0 || kind == 0) {
-          for (int e = lo + tid; e < hi; e += kBlock) {
-            const uint64_t n = entry(e);
-            const double W = eval_listed<NI, FT, ALT>(K, n, wl);
-            accumulate_listed<D>(W, wl, S1, S2, my_h);  // the screening pass counted every sample
-          }
-        } else if constexpr (PREC == 1) {
-          for (int e = lo + tid; e < hi; e += kBlock) {
-            const uint64_t n = entry(e);
-            {
-              uint32_t wd[D];
-              sample_words<D>(wd, n, K->uid, K->c3, K->seed_lo, K->seed_hi);
-#pragma unroll
-              for (int d = 0; d < D; ++d) wl[d * kBlock] = wd[d];
-            }
-            const double W = near_listed<NI, ALT>(K, wl);
-            accumulate_listed<D>(W, wl, S1, S2, my_h);
-          }
-        }
-        __syncthreads();  // pre is rewritten by the next chunk
+    // the group's lists in sequence order: the in-shell lists of its units (unit order, waves in order within a
+    // unit), then their near lists; taken kLists at a time, so that the two kinds share one entry loop (a wave
+    // whose 64 entries straddle the boundary runs both evaluations)
+    const int nu = sht.unit_end - sht.unit_begin, n_half = nu * kWaves;
+    for (int c0 = 0; c0 < 2 * n_half && base < e_hi; c0 += kLists) {
+      const int nl = min(kLists, 2 * n_half - c0);
+      // block-wide inclusive scan of the list lengths: within each wave, then the wave totals in order
+      int v = 0;
+      if (tid < nl) {
+        const int i = c0 + tid, kind = i >= n_half ? 1 : 0, r = i - kind * n_half;
+        v = (int)L.shell_cnt[(int64_t)(pos0 + sht.unit_begin + r / kWaves) * 2 * kWaves + kind * kWaves +
+                             r % kWaves];
       }
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v += t;
+      }
+      if (lane == 63) wtot[wave] = v;
+      __syncthreads();
+      for (int w = 0; w < wave; ++w) v += wtot[w];
+      pre[tid + 1] = v;
+      if (tid == 0) pre[0] = 0;
+      __syncthreads();
+      const int M = pre[nl];
+      // this chunk's entries that fall in the tile: [lo, hi) of the chunk (entry e of the chunk is sequence entry
+      // base + e), thread t taking lo + t, lo + t + 256, ...
+      const int lo = max(0, e_lo - base), hi = min(M, e_hi - base);
+      base += M;
+      // sample index of chunk entry e, and whether it comes from a near list
+      auto entry = [&](int e, bool& near) -> uint64_t {
+        int a = 0, b = nl;  // pre[a] <= e < pre[b]
+        while (b - a > 1) {
+          const int mid = (a + b) >> 1;
+          if (pre[mid] <= e) a = mid;
+          else b = mid;
+        }
+        const int i = c0 + a, kind = i >= n_half ? 1 : 0, r = i - kind * n_half;
+        const int u = sht.unit_begin + r / kWaves, w = r % kWaves, k = e - pre[a];
+        const uint16_t* lst = L.shell_list + (int64_t)(pos0 + u) * L.list_stride + w * wlen;
+        near = kind != 0;
+        const uint32_t off = kind == 0 ? lst[k] : lst[wlen - 1 - k];
+        return (uint64_t)((int64_t)u * it->unit_size + off);
+      };
+      for (int e = lo + tid; e < hi; e += kBlock) {
+        bool near;
+        const uint64_t n = entry(e, near);
+        double W;
+        if constexpr (PREC == 0) {
+          W = eval_listed<NI, FT, ALT>(K, n, wl);
+        } else if (!near) {
+          W = eval_listed<NI, FT, ALT>(K, n, wl);
+        } else {
+          uint32_t wd[D];
+          sample_words<D>(wd, n, K->uid, K->c3, K->seed_lo, K->seed_hi);
+#pragma unroll
+          for (int d = 0; d < D; ++d) wl[d * kBlock] = wd[d];
+          W = near_listed<NI, ALT>(K, wl);
+        }
+        accumulate_listed<D>(W, wl, S1, S2, my_h);  // the screening pass counted every sample
+      }
+      __syncthreads();  // pre is rewritten by the next chunk
     }
     double* rec = L.shell_rec + sht.rec + (int64_t)tile * (2 + DN);
     finish_block<false>(S1, S2, lay, DN, smem, rec, rec + 2);
@@ -1950,7 +1954,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_screen(SampleLaunch L) {
 
 // Second pass: block b takes tile b mod sh_tiles of second-pass group b / sh_tiles (one group of units of one item;
 // every group of the launch has its own blocks).  Four blocks per CU with the linear rule (its compact LDS layout and
-// at most 128 VGPRs; the FP64 instance then keeps 2 VGPRs in scratch) for up to three integrated particles, three
+// at most 128 VGPRs) for up to three integrated particles, three
 // otherwise (four integrated particles need more than 40 KB of LDS, so a tighter register cap would buy nothing).
 // Which block runs a group does not change its result.
 template <int MASK, int PREC, bool ALT>
