@@ -29,16 +29,17 @@ PEAK_FP32_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12  # 78.6
 PEAK_FP64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.3
 # HBM bytes per launch of the screening kernel on this workload, from rocprofv3 FETCH_SIZE and WRITE_SIZE per dispatch
 # scaled by a 256 MiB device copy (fetch x2.0, write x1.0), measured on the current kernel; None once it changes.
-TRAFFIC_BYTES_SCREEN = 33.30e6
+TRAFFIC_BYTES_SCREEN = 37.94e6
 TIMING_EVERY = 7
 
 
 def ops_common(n_int: int) -> int:
     """Arithmetic operations every sample needs (each +, -, *, /, fma, sqrt, exp, log, sin, cos, compare/select and
     each 32x32->64 multiply or 3-way xor of Philox counts one): Philox 40 per block (10 rounds x 2 multiplies + 2
-    xors) x D/4 (the D words of a sample are a quarter block each: consecutive samples share blocks); 7 per dimension (uniform from the word, bin, offset, map edge and width, x, its bin count);
-    13 per integrated particle (momentum components, energy); conserved momentum 3 (n_int + 1) + 5; energy sum,
-    Gaussian argument and its test (n_int + 2) + 5."""
+    xors) x D/4 (the D words of a sample are a quarter block each: consecutive samples share blocks); 7 per
+    dimension (uniform from the word, bin, offset, map edge and width, x, its bin count); 13 per integrated particle
+    (momentum components, energy); conserved momentum 3 (n_int + 1) + 5; energy sum, Gaussian argument and its test
+    (n_int + 2) + 5."""
     D = 3 * n_int
     return 10 * D + 7 * D + 13 * n_int + 3 * (n_int + 1) + 5 + (n_int + 2) + 5
 
