@@ -202,7 +202,7 @@ int bmc_add_species(bmc_ctx* ctx, const char* name, int stat, int grid_kind, int
 int bmc_set_mass(bmc_ctx* ctx, int species, int kind, double m0, double A, double w);
 /* Rule for f between grid nodes of a species (Sec. III.B): BMC_INTERP_LINLOG, _SPLINE or _EQEXACT.  Outside the
  * grid every rule uses the Eq. 17 fit; at the nodes every rule gives the table value.  The spline's second
- * derivatives are recomputed on the device before every evaluation.  bmc_vjp accepts LINLOG only (BMC_EUNSUP). */
+ * derivatives are recomputed on the device before every evaluation.  bmc_vjp differentiates through every rule. */
 int bmc_set_interp(bmc_ctx* ctx, int species, int mode);
 /* Sets f on the species' grid (n values).  Validates f > 0 and, for Fermi-Dirac, f < 1 (BMC_ERANGE). */
 int bmc_set_f(bmc_ctx* ctx, int species, const double* f, int n, int mem);
@@ -239,7 +239,10 @@ int bmc_plan_size(bmc_ctx* ctx, int process, int species, const bmc_run_opts* op
  * Outputs (n_out values each, see bmc_plan_size): with opts->eval_stride >= 1, the values at grid nodes
  * 0, k, 2k, ... of each selected species in species order; with 0, the full grid of each species (the
  * per-process strided values filled).  sigma_out may be NULL.  Vegas maps are taken from and stored back to
- * the context (integrator reuse); maps start uniform. */
+ * the context (integrator reuse); maps start uniform.  BMC_EUNSUP when a block of the second pass would need more
+ * than 64 KB of LDS: it holds the item's map (D N_b entries, twice), four per-wave W^2 histograms of D N_b doubles
+ * and the f tables it reads; at D = 12 with 64 bins that leaves room for one FP64 table of up to 946 nodes with the
+ * linear rule, or 315 when a species uses the spline or equilibrium-exact rule (or |M|^2 is a polynomial). */
 int bmc_collision(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, double* C_out,
                   double* sigma_out, size_t n_out, int mem);
 
@@ -313,7 +316,9 @@ int bmc_graph_status(bmc_ctx* ctx, double* t, double* last_dt);
 /* Vector-Jacobian product of the C of the last-planned items with frozen maps and common random numbers
  * (the same counters as bmc_collision with these opts and one iteration): given the cotangent v on C_out
  * (n_out values, layout as bmc_collision), returns dL/df (every species' grid, concatenated),
- * dL/dcoupling (one per process) and dL/dm0 (one per species). */
+ * dL/dcoupling (one per process) and dL/dm0 (one per species).  BMC_EUNSUP for an FP32-integrand request,
+ * evaluation points off the grid, a polynomial |M|^2, VEGAS+ sampling, a strided fill, or an adjoint block
+ * that would need more than 64 KB of LDS. */
 int bmc_vjp(bmc_ctx* ctx, int process, int species, const bmc_run_opts* opts, const double* v_C,
             size_t n_out, double* grad_f, double* grad_coupling, double* grad_m0, int mem);
 

@@ -759,7 +759,9 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
     Q.lds_sh64_lin = std::max(Q.lds_sh64_lin, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 0, 0));
     Q.lds_sh32_lin = std::max(Q.lds_sh32_lin, shell_lds_bytes(it.D, it.nb, it.n_tab, n_max, 1, 0));
   }
-  if (Q.lds64 > 65536 || Q.lds_sh64 > 65536)
+  // the second pass's compact layout (every launch with the linear rule) is the least any plan needs; a launch with
+  // the spline or equilibrium-exact rule is checked against its own layout when it is enqueued
+  if (Q.lds_sh64_lin > 65536)
     return fail(c, BMC_EUNSUP, "per-block LDS need above 64 KB (grid or bins too large)");
   if (!Q.vp_items.empty() && ((Q.lds64 + 15) & ~15) + kVplusLdsExtra > 65536)
     return fail(c, BMC_EUNSUP, "per-block LDS of the VEGAS+ pass above 64 KB (grid or bins too large)");
@@ -988,6 +990,15 @@ hipError_t sample_phase(bmc_ctx* c, const SampleLaunch& L, hipStream_t s) {
 // calls of a run that will adapt).
 int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, double* out_S, bool count_bins = false) {
   hipStream_t s = c->stream;
+  int any_interp = 0;
+  for (auto& S : c->sp) any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
+  for (auto& Pr : c->pr) any_interp |= Pr.prm.m2_kind != BMC_M2_CONST ? 1 : 0;
+  const int shell_lds = any_interp ? (o.precision == BMC_FP64 ? P.lds_sh64 : P.lds_sh32)
+                                   : (o.precision == BMC_FP64 ? P.lds_sh64_lin : P.lds_sh32_lin);
+  if (shell_lds > 65536)  // checked before anything is enqueued
+    return fail(c, BMC_EUNSUP,
+                "per-block LDS of the second pass above 64 KB with the spline, equilibrium-exact rule or polynomial "
+                "|M|^2 (grid or bins too large)");
   HIPCHK(c, launch_next_epoch(c->st(), s));
   HIPCHK(c, launch_prepare(c->st(), c->spec(), (int)c->sp.size(), c->f64(), c->f32(), c->n_f, s));
   SampleLaunch L{};
@@ -1006,13 +1017,10 @@ int enqueue_eval(bmc_ctx* c, Plan& P, const bmc_run_opts& o, double* out_C, doub
   L.seed_hi = (uint32_t)(o.seed >> 32);
   L.nint_mask = P.nint_mask;
   L.precision = o.precision;
-  L.any_interp = 0;
-  for (auto& S : c->sp) L.any_interp |= S.interp != BMC_INTERP_LINLOG ? 1 : 0;
-  for (auto& Pr : c->pr) L.any_interp |= Pr.prm.m2_kind != BMC_M2_CONST ? 1 : 0;
+  L.any_interp = any_interp;
   L.lds_bytes = o.precision == BMC_FP64 ? P.lds64 : P.lds32;
   // the second pass's layout follows its kernel instance: tables of f alone when every rule is the linear one
-  L.shell_lds = L.any_interp ? (o.precision == BMC_FP64 ? P.lds_sh64 : P.lds_sh32)
-                             : (o.precision == BMC_FP64 ? P.lds_sh64_lin : P.lds_sh32_lin);
+  L.shell_lds = shell_lds;
   L.shell_list = P.d_list;
   L.shell_cnt = P.d_cnt;
   L.list_stride = P.list_stride;

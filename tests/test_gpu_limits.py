@@ -1,0 +1,142 @@
+"""The library's size limits on the GPU: twelve dimensions (2->4, four integrated particles) with 64 Vegas bins per
+dimension, so that every slot of an item's map, of the kernels' LDS map layouts and of the training histograms is in
+use and the adaptation's waves use all 64 lanes, on the 512-node grid of the 2->4 workload (every 64th node
+evaluated).  Both precisions on frozen maps, and adapting iterations step by step, against the oracle; sizes beyond
+the limits are rejected before any launch."""
+import numpy as np
+import pytest
+
+from gpu_util import TOL, assert_items_close, check_fp64_items, gpu_available, item_scale, oracle_items_matching, say
+from oracle import binding as ob
+from paper_2603_28848_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+NB = 64  # the largest number of bins per dimension
+STRIDE = 64
+N = 1 << 14
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not gpu_available():
+        pytest.skip("no GPU")
+
+
+def _bm():
+    from paper_2603_28848_amd import boltzmc
+    return boltzmc
+
+
+def _w(nitn=1, nb=NB):
+    w = wl.w24_fd(n_grid=512, N=N, nitn=nitn)
+    w.processes[0].n_bins = nb
+    w.processes[0].eval_stride = STRIDE
+    return w
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_twelve_dimensions_64_bins_frozen_maps(precision):
+    bm = _bm()
+    w = _w()
+    say("limits: D=12, nb=%d, 512 nodes, stride %d, precision=%d" % (NB, STRIDE, precision))
+    ctx = bm.from_workload(w)
+    ctx.collision(-1, -1, bm.default_opts(seed=3, precision=precision, freeze_maps=1, n_iter=1))
+    res = ctx.item_results(1)
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"])
+    assert n == 4 * (512 // STRIDE)  # both pinned sides, gain and loss, at every evaluated node
+    rc, r = ow.run_items(items, n, N, 1, seed=3, adapt=False)
+    assert rc == 0
+    if precision == 0:
+        check_fp64_items(ow, items, n, res, r, N, 1, seed=3)
+    else:
+        assert_items_close(res["I_it"], r["I_it"], TOL[1], "I_it", scale=item_scale(items, n, r["Ibar"]))
+
+
+def test_twelve_dimensions_64_bins_stepwise_adaptation():
+    """Two iterations, each started on both sides from the oracle's map before it: I_k, V_k to the FP64 contract and
+    the adapted edges to 5e-11 of each dimension's range (the bound of the 2->4 adaptation test at 50 bins: single
+    shell samples carry whole bins of the training histograms at sigma_E = 0.002)."""
+    bm = _bm()
+    w = _w(nitn=2)
+    ow = ob.OracleWorld(w)
+    ctx = bm.from_workload(w)
+    # the GPU's item set (every 64th node), in its order
+    ctx.collision(-1, -1, bm.default_opts(seed=0, precision=0, freeze_maps=1, n_iter=1))
+    uids = [int(u) for u in ctx.item_results(1)["uid"]]
+    items, n = oracle_items_matching(ow, uids)
+    maps = np.stack([ow.map_uniform(items[i], NB) for i in range(n)])
+    rng = np.ones((n, 12 * (NB + 1)))
+    for i in range(n):
+        m = maps[i].reshape(12, NB + 1)
+        for d in range(ow.item_dims(items[i])):
+            rng[i, d * (NB + 1):(d + 1) * (NB + 1)] = m[d, NB] - m[d, 0]
+    for k in range(2):
+        say("limits stepwise iteration %d (%d items, N=%d, nb=%d)" % (k, n, N, NB))
+        rc, r = ow.run_items(items, n, N, 1, maps=maps.copy(), first_iter=k)
+        assert rc == 0
+        ctx.maps_set(uids, maps)
+        ctx.collision(-1, -1, bm.default_opts(seed=0, epoch=0, precision=0, n_iter=1, n_samples=N, first_iter=k))
+        res = ctx.item_results(1)
+        assert [int(u) for u in res["uid"]] == uids
+        check_fp64_items(ow, items, n, res, r, N, 1, maps=maps, first_iter=k)
+        gm = ctx.maps_get(uids, NB)
+        e = float(np.max(np.abs(gm - r["maps"]) / rng))
+        say("limits map %d: max edge err / range %.3e" % (k, e))
+        assert e < 5e-11
+        assert not np.array_equal(r["maps"], maps)  # the map did move
+        # every bin of every dimension is still a bin: strictly increasing edges
+        for i in range(n):
+            m = gm[i].reshape(12, NB + 1)
+            assert np.all(np.diff(m, axis=1) > 0.0)
+        maps = r["maps"]
+
+
+def test_twelve_dimensions_64_bins_vjp():
+    """The adjoint at the same limits (every 64th node, explicit stride: no fill) against the oracle's VJP."""
+    bm = _bm()
+    w = _w()
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=3, epoch=2, n_iter=1, freeze_maps=1, eval_stride=STRIDE, n_samples=N)
+    ni, no = ctx.plan_size(-1, -1, opts)
+    assert no == 512 // STRIDE
+    v = np.random.default_rng(2).normal(size=no)
+    say("limits vjp: %d items, %d outputs" % (ni, no))
+    gf, gl, gm = ctx.vjp(v, -1, -1, opts)
+    ow = ob.OracleWorld(w)
+    items, n = ow.items(stride=STRIDE)
+    assert n == ni
+    coef = np.array([v[items[i].eval_idx // STRIDE] * items[i].mult * (-1 if items[i].term == 1 else 1)
+                     for i in range(n)])
+    rc, of, om, ol = ow.vjp(items, n, coef, N, 0, seed=3, epoch=2)
+    assert rc == 0
+    err_f = np.max(np.abs(gf - of)) / np.max(np.abs(of))
+    say("limits vjp: grad_f max err / max |grad| = %.3e; grad_m %s vs %s" % (err_f, gm, om))
+    assert err_f < 1e-10
+    np.testing.assert_allclose(gm, om, rtol=1e-10, atol=1e-12 * np.max(np.abs(om)))
+    np.testing.assert_allclose(gl, ol, rtol=1e-10)
+
+
+def test_sizes_beyond_the_limits_are_rejected():
+    bm = _bm()
+    w = _w(nb=NB + 1)
+    with pytest.raises(bm.BmcError) as e:
+        bm.from_workload(w)
+    assert e.value.code == bm.EINVAL
+    w = _w()
+    w.processes[0].outs = [0, 0, 0, 0, 0]  # 2 -> 5: fifteen dimensions
+    with pytest.raises(bm.BmcError) as e:
+        bm.from_workload(w)
+    assert e.value.code == bm.EINVAL
+    # the spline's node data make the second pass's tables three times larger: above 64 KB of LDS at these sizes, so
+    # the evaluation is refused before anything is enqueued, and the linear rule then runs on the same context
+    w = _w()
+    w.species[0].interp = wl.INTERP_SPLINE
+    ctx = bm.from_workload(w)
+    with pytest.raises(bm.BmcError) as e:
+        ctx.collision(-1, -1, bm.default_opts(seed=3, precision=0, freeze_maps=1, n_iter=1))
+    assert e.value.code == bm.EUNSUP
+    ctx.set_interp(0, wl.INTERP_LINLOG)
+    C, S = ctx.collision(-1, -1, bm.default_opts(seed=3, precision=0, freeze_maps=1, n_iter=1))
+    assert np.all(np.isfinite(C)) and np.all(np.isfinite(S))
