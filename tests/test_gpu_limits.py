@@ -118,6 +118,36 @@ def test_twelve_dimensions_64_bins_vjp():
     np.testing.assert_allclose(gl, ol, rtol=1e-10)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("which", ["2to2", "2to3"])
+def test_every_sample_in_the_shell(which, precision):
+    """The other extreme of the screening: a Gaussian width far above every energy difference puts every sample in
+    the shell, so each wave's list of a unit fills to its capacity (one entry per sample) and the second pass
+    evaluates every sample.  Ragged sample count (the last unit partly filled)."""
+    bm = _bm()
+    Nr = 3 * 4096 + 777
+    if which == "2to2":
+        w = wl.w22_mb(n_grid=12, sigma_E=50.0, N=Nr, nitn=2)
+    else:
+        w = wl.w23_be(n_grid=12, q_min=0.05, q_max=4.0, sigma_E=50.0, N=Nr, nitn=2)
+    say("all in shell: %s precision=%d N=%d" % (which, precision, Nr))
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=4, precision=precision, freeze_maps=1)
+    ctx.collision(-1, -1, opts)
+    ctx.get_sample_stats(reset=True)
+    ctx.collision(-1, -1, opts)
+    res = ctx.item_results(2)
+    assert ctx.get_sample_stats(reset=True) == len(res["uid"]) * Nr * 2  # the second pass counts what it evaluates
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"])
+    rc, r = ow.run_items(items, n, Nr, 2, seed=4, adapt=False)
+    assert rc == 0
+    if precision == 0:
+        check_fp64_items(ow, items, n, res, r, Nr, 2, seed=4)
+    else:
+        assert_items_close(res["I_it"], r["I_it"], TOL[1], "I_it", scale=item_scale(items, n, r["Ibar"]))
+
+
 def test_sizes_beyond_the_limits_are_rejected():
     bm = _bm()
     w = _w(nb=NB + 1)
