@@ -170,3 +170,24 @@ def test_sizes_beyond_the_limits_are_rejected():
     ctx.set_interp(0, wl.INTERP_LINLOG)
     C, S = ctx.collision(-1, -1, bm.default_opts(seed=3, precision=0, freeze_maps=1, n_iter=1))
     assert np.all(np.isfinite(C)) and np.all(np.isfinite(S))
+
+
+def test_empty_selections_are_rejected():
+    """No evaluation points, and a selection without work items (a species that only appears on the side the side
+    mask leaves out), are refused with BMC_EINVAL; the context stays usable."""
+    bm = _bm()
+    w = wl.w_multi(n_grid=16, N=(1 << 10, 1 << 10, 1 << 10), nitn=1, sigma_E=0.05)
+    w.processes[0].side_mask = wl.SIDES_IN  # AA -> BB pinned on the initial side only: no item observes B
+    ctx = bm.from_workload(w)
+    with pytest.raises(bm.BmcError) as e:
+        ctx.collision(0, 1, bm.default_opts(seed=1, freeze_maps=1))
+    assert e.value.code == bm.EINVAL
+    q = np.array([0.5, 1.0])
+    o = bm.default_opts(seed=1, freeze_maps=1)
+    o.eval_q = q.ctypes.data
+    o.n_eval = 0
+    with pytest.raises(bm.BmcError) as e:
+        ctx.collision(0, 0, o)
+    assert e.value.code == bm.EINVAL
+    C0, S0 = ctx.collision(0, 0, bm.default_opts(seed=1, freeze_maps=1))
+    assert np.all(np.isfinite(C0)) and C0.size == 16
