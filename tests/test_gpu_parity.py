@@ -85,6 +85,33 @@ def test_frozen_maps_2to3_full_size_sampled_items(precision):
         assert_items_close(res["sigma"][pick], r["sigma"], 10 * TOL[1], "sigma", scale=scale)
 
 
+def test_headline_full_size_adaptive_in_the_bench_launch_configuration():
+    """The benchmark's own call: 2<->3 BE, 512 items x 10 adaptive iterations x 2^18 samples, FP32 integrand, the
+    launch shape picked by the autotuner.  Sampled items (first, interior, last nodes; both sides, both terms)
+    against the oracle's free-running run of the same items: iteration 0 (the common uniform map) to the FP32-integrand
+    tolerance, the combined estimate after ten adaptive iterations within 6 sigma (adaptation amplifies rounding
+    differences, so later iterations are two different Monte Carlo histories)."""
+    bm = _bm()
+    w = wl.w23_be()
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=0, epoch=0, precision=bm.FP32I)
+    b, ch, ms = ctx.autotune(-1, -1, opts)
+    say("headline full size, adaptive, autotuned to %d blocks/CU, chunk %d" % (b, ch))
+    C, S = ctx.collision(-1, -1, opts)
+    res = ctx.item_results(10)
+    assert len(res["uid"]) == 512
+    pick = [i for i, u in enumerate(res["uid"]) if (int(u) & 0x3FFFF) in (0, 47, 127)]
+    ow = ob.OracleWorld(w)
+    items, n = oracle_items_matching(ow, res["uid"][pick])
+    rc, r = ow.run_items(items, n, 1 << 18, 10, seed=0, epoch=0)
+    assert rc == 0
+    scale = item_scale(items, n, r["Ibar"])
+    assert_items_close(res["I_it"][pick, 0], r["I_it"][:, 0], TOL[1], "I_it[0]", scale=scale)
+    z = (res["Ibar"][pick] - r["Ibar"]) / np.sqrt(res["sigma"][pick] ** 2 + r["sigma"] ** 2)
+    say("headline adaptive: max |dIbar|/sigma over %d sampled items = %.2f" % (n, float(np.max(np.abs(z)))))
+    assert np.max(np.abs(z)) < 6.0
+
+
 # -------------------------------------------------------------------------------- stepwise adaptation
 def test_stepwise_adaptation_2to2():
     """From the oracle's map before iteration k, one GPU iteration (Philox iteration index k) reproduces the
