@@ -705,8 +705,8 @@ int build_plan(bmc_ctx* c, const PlanKey& k, Plan* P, char* scratch_base = nullp
                                    std::max<int64_t>(pmin, (int64_t)(list_cap / (2 * (size_t)umax))));
     // slices: whole items in batched order, at most list_pos task positions each
     int tb = 0, sb = 0;
-    for (size_t k = 0; k < order.size(); ++k) {
-      const int i = order[k];
+    for (size_t oi = 0; oi < order.size(); ++oi) {
+      const int i = order[oi];
       const int te = first_b[i] + Q.items[i].n_units;
       if (te - tb > Q.list_pos) {
         Q.slices.push_back(Plan::Slice{tb, first_b[i], sb, sh_first[i]});

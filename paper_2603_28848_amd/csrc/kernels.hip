@@ -1514,21 +1514,21 @@ __device__ void vjp_group(const SampleLaunch& L, const ShellTask sht, unsigned c
   // order) form one sequence whose entry e is taken by thread e mod 256.
   const int pos0 = sht.first_task - L.task_begin - sht.unit_begin;  // launch position of unit 0
   const int64_t wlen = L.list_stride / kWaves;
-  for (int u = sht.unit_begin; u < sht.unit_end; ++u) {
-  const int pos = pos0 + u;
-  const int64_t n0 = (int64_t)u * it->unit_size;
+  for (int un = sht.unit_begin; un < sht.unit_end; ++un) {
+  const int pos = pos0 + un;
+  const int64_t n0 = (int64_t)un * it->unit_size;
   const uint32_t* cnt = L.shell_cnt + (int64_t)pos * 2 * kWaves;
   const uint16_t* lst = L.shell_list + (int64_t)pos * L.list_stride;
   int M = 0;
   for (int l = 0; l < 2 * kWaves; ++l) M += (int)cnt[l];
   for (int e = tid; e < M; e += kBlock) {
-    int l = 0, k = e;
-    while (k >= (int)cnt[l]) {
-      k -= (int)cnt[l];
+    int l = 0, ke = e;  // list l of the unit (in-shell lists of waves 0..3, then near lists), entry ke in it
+    while (ke >= (int)cnt[l]) {
+      ke -= (int)cnt[l];
       ++l;
     }
-    const int w = l % kWaves;
-    const uint32_t off = l < kWaves ? lst[w * wlen + k] : lst[w * wlen + wlen - 1 - k];
+    const int lw = l % kWaves;
+    const uint32_t off = l < kWaves ? lst[lw * wlen + ke] : lst[lw * wlen + wlen - 1 - ke];
     const int64_t n = n0 + off;
     uint32_t wd[D];
     sample_words<D>(wd, (uint64_t)n, uid, c3, L.seed_lo, L.seed_hi);
@@ -2566,7 +2566,7 @@ __global__ void k_prepare(DevState* st, const SpecDev* spec, int n_species, cons
   __syncthreads();
   const double a = st->a;
   for (int64_t i = threadIdx.x; i < n_f; i += blockDim.x) f32[i] = (float)f64[i];
-  if (threadIdx.x < n_species) {
+  if ((int)threadIdx.x < n_species) {
     const int s = threadIdx.x;
     const SpecDev& S = spec[s];
     const double m = S.mass_kind == 1 ? S.m0 + S.A * sin(S.w * t) : S.m0;
