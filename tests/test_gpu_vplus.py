@@ -34,14 +34,20 @@ def _oracle_items(ow, uids):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("which", ["2to2", "2to3"])
+@pytest.mark.parametrize("which", ["2to2", "2to3", "multi"])
 def test_vplus_frozen_parity(which, precision):
-    """Frozen runs keep the uniform allocation N / M: every item and iteration against the oracle."""
+    """Frozen runs keep the uniform allocation N / M: every item and iteration against the oracle.  "multi": the
+    two-species set AA->BB, AA->AAA, AA->AABB in one launch (one, two and three integrated particles: the kernel
+    instance for several particle counts)."""
     bm = _bm()
     if which == "2to2":
         w, N, nitn = _vplus(wl.w22_mb()), 10_000, 3
-    else:
+    elif which == "2to3":
         w, N, nitn = _vplus(wl.w23_be(n_grid=24, N=1 << 13)), 1 << 13, 2
+    else:
+        w, N, nitn = _vplus(wl.w_multi(n_grid=16, N=(1 << 12, 1 << 12, 1 << 12), nitn=2, sigma_E=0.05)), 1 << 12, 2
+        for p in w.processes:
+            p.eval_stride = 1
     say("vegas+ frozen %s precision=%d" % (which, precision))
     ctx = bm.from_workload(w)
     opts = bm.default_opts(seed=9, epoch=1, precision=precision, freeze_maps=1, n_iter=nitn, n_samples=N)
@@ -52,8 +58,8 @@ def test_vplus_frozen_parity(which, precision):
     rc, r = ow.run_items(items, n, N, nitn, seed=9, epoch=1, adapt=False)
     assert rc == 0
     tol = TOL[precision]
-    if which == "2to3" and precision == 0:
-        tol = 1e-10  # few in-shell samples per item at 2^13 on the uniform map (the few-sample tolerance)
+    if which != "2to2" and precision == 0:
+        tol = 1e-10  # few in-shell samples per item on the uniform map (the few-sample tolerance)
     sc = item_scale(items, n, r["Ibar"])
     assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=sc)
     assert_items_close(res["V_it"], r["V_it"], 10 * tol, "V_it", scale=sc * sc / N)
