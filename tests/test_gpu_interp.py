@@ -72,6 +72,31 @@ def test_interp_frozen_maps_parity(which, interp, precision):
     assert np.all(np.abs(C - Co) <= tol * scale)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("interp", [wl.INTERP_SPLINE, wl.INTERP_EQEXACT])
+def test_interp_multi_species_every_particle_count(interp, precision):
+    """The two-species set (AA->BB, AA->AAA, AA->AABB: one, two and three integrated particles) in one launch with
+    each rule, so the second pass runs its instance for several particle counts with the rules' tables: every item
+    against the oracle (few samples per item: the few-sample FP64 tolerance)."""
+    bm = _bm()
+    N = 1 << 11
+    w = _with_interp(wl.w_multi(n_grid=16, N=(N, N, N), nitn=2, sigma_E=0.05), interp)
+    for p in w.processes:
+        p.eval_stride = 1
+    say("interp multi rule=%d precision=%d" % (interp, precision))
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=8, epoch=3, precision=precision, freeze_maps=1, n_iter=2, n_samples=N)
+    ctx.collision(-1, -1, opts)
+    res = ctx.item_results(2)
+    ow = ob.OracleWorld(w)
+    items, n = _oracle_items(ow, res["uid"])
+    assert len({int(u) >> 24 for u in res["uid"]}) == 3  # all three processes in the launch
+    rc, r = ow.run_items(items, n, N, 2, seed=8, epoch=3, adapt=False)
+    assert rc == 0
+    tol = 1e-10 if precision == 0 else TOL[1]
+    assert_items_close(res["I_it"], r["I_it"], tol, "I_it", scale=item_scale(items, n, r["Ibar"]))
+
+
 @pytest.mark.parametrize("interp", [wl.INTERP_SPLINE, wl.INTERP_EQEXACT])
 def test_interp_points_off_the_grid(interp):
     """The observed leg between nodes takes its f by the same rule (global-memory path of the observed leg)."""
