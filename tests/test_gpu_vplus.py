@@ -34,9 +34,9 @@ def _oracle_items(ow, uids):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
-@pytest.mark.parametrize("which", ["2to2", "2to3", "multi"])
+@pytest.mark.parametrize("which", ["2to2", "2to3", "multi", "multi_spline"])
 def test_vplus_frozen_parity(which, precision):
-    """Frozen runs keep the uniform allocation N / M: every item and iteration against the oracle.  "multi": the
+    """Frozen runs keep the uniform allocation N / M: every item and iteration against the oracle.  "multi*": the
     two-species set AA->BB, AA->AAA, AA->AABB in one launch (one, two and three integrated particles: the kernel
     instance for several particle counts)."""
     bm = _bm()
@@ -48,6 +48,9 @@ def test_vplus_frozen_parity(which, precision):
         w, N, nitn = _vplus(wl.w_multi(n_grid=16, N=(1 << 12, 1 << 12, 1 << 12), nitn=2, sigma_E=0.05)), 1 << 12, 2
         for p in w.processes:
             p.eval_stride = 1
+        if which == "multi_spline":  # the instance with the alternative rules' tables
+            for sp in w.species:
+                sp.interp = wl.INTERP_SPLINE
     say("vegas+ frozen %s precision=%d" % (which, precision))
     ctx = bm.from_workload(w)
     opts = bm.default_opts(seed=9, epoch=1, precision=precision, freeze_maps=1, n_iter=nitn, n_samples=N)
