@@ -370,7 +370,8 @@ class Context:
         ni, no = self.plan_size(process, species, opts)
         self.ensure_workspace(opts.n_samples, 1)
         v = np.ascontiguousarray(v, dtype=np.float64)
-        assert v.size == no
+        if v.size != no:
+            raise ValueError("the cotangent has %d values, the plan's C has %d" % (v.size, no))
         n_f = n_f if n_f is not None else self._n_f
         gf, gl, gm = np.zeros(n_f), np.zeros(self._n_proc), np.zeros(self._n_species)
         self._check(lib().bmc_vjp(self.h, process, species, C.byref(opts), _ptr(v), no, _ptr(gf), _ptr(gl), _ptr(gm),
