@@ -289,6 +289,13 @@ class Context:
         self.ensure_workspace(opts.n_samples, opts.n_iter)
         self._last_items = ni
         if out is not None:
+            for name, t in (("out", out), ("sigma", sigma)):
+                if t is None:
+                    continue
+                if (not hasattr(t, "data_ptr") or t.dtype != self.torch.float64 or t.device.type != "cuda"
+                        or t.device.index != self.device or not t.is_contiguous() or t.numel() < no):
+                    raise ValueError("%s must be a contiguous float64 tensor of at least %d values on cuda:%d"
+                                     % (name, no, self.device))
             self._check(lib().bmc_collision(self.h, process, species, C.byref(opts), _ptr(out), _ptr(sigma), no,
                                             MEM_DEVICE))
             return out, sigma

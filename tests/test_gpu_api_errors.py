@@ -99,3 +99,24 @@ def test_kernel_timing_splits_the_sample_phase():
     assert abs((scr + sec) - ms) <= 1e-3 * ms + 1e-3, (scr, sec, ms)
     assert ctx.get_kernel_timing(reset=True) == (0.0, 0.0, 0)
     ctx.set_timing(False)
+
+
+def test_device_outputs_equal_host_outputs_and_are_checked():
+    """C and sigma written into device tensors (MEM_DEVICE) equal the host outputs bitwise; a tensor of the wrong
+    dtype, too short or on the host is refused before the call."""
+    import numpy as np
+    import torch
+    bm = _bm()
+    w = wl.w22_mb(n_grid=16, N=4096, nitn=2)
+    ctx = bm.from_workload(w)
+    opts = bm.default_opts(seed=2, freeze_maps=1)
+    C, S = ctx.collision(-1, -1, opts)
+    out = torch.zeros(16, dtype=torch.float64, device="cuda")
+    sig = torch.zeros(16, dtype=torch.float64, device="cuda")
+    ctx.collision(-1, -1, opts, out=out, sigma=sig)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), C) and np.array_equal(sig.cpu().numpy(), S)
+    for bad in (torch.zeros(16, dtype=torch.float32, device="cuda"), torch.zeros(8, dtype=torch.float64, device="cuda"),
+                torch.zeros(16, dtype=torch.float64)):
+        with pytest.raises(ValueError):
+            ctx.collision(-1, -1, opts, out=bad, sigma=sig)
